@@ -1,0 +1,23 @@
+"""Plain FP64 CPU oracle of the directional diffusion splitting method.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link this package: only the tests, the smoke check and the benchmark's CPU
+baseline leg use it.  It shares no code with the HIP library; its inputs come
+from the seeded generators in ``workloads`` and nothing else.
+
+Paper: R. Drebotiy, H. Shynkarenko, "Directional diffusion splitting method
+for advection-diffusion-reaction model" (arXiv 2411.11041).
+
+Modules
+  geometry   Sec. 3 fields b, p; eq. (12) inflow sets; eq. (13)-(14) curve families
+  linefe     eq. (16)-(19): P1 line elements and tridiagonal solves
+  transfer   Sec. 6 grid interpolation: scatter (crossing records) and eq. (21)-(23) gather
+  method     operators A_h, F_h, residual, defect-correction iteration, eq. (10) Lie
+             step, eq. (11) initial guess, implicit-Euler parabolic stepping
+  dense      brute-force dense / sparse direct solves of the method's own system
+  galerkin2d own 2D P1 Galerkin solve of eq. (5)-(6) (independent reference)
+  cnn        FP64 conv-net forward/backward for the learned warm start
+
+Functions whose result has no independent pin are marked "parity unpinned"
+in their docstring (only galerkin2d.compare_data2d).
+"""

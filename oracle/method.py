@@ -1,0 +1,145 @@
+"""The method's sweeps and iterations (FP64).
+
+Test infrastructure: plain FP64 NumPy/SciPy.
+
+Notation: U is a grid field (ny*nx, row-major) holding the unknowns on the
+interior nodes and the Dirichlet value (zero) elsewhere; family 0 (B) are the
+beta-curves, family 1 (G) the gamma-curves; G_F gathers a grid field to the
+interior nodes of family F (eq. (21)-(23)), P_F scatters line values back
+(Sec. 6); M, K, C are the line matrices of eq. (17), (19); S = mu K + C + sigma M;
+L = int f v dl.
+
+One step of eq. (10), as the paper describes it on the curves (eq. (16),
+(18)) with *values* of u_{j+1/2} handed from one family to the other through
+the grid (the paper substitutes "the values from u_{j+1/2}" into the second
+substep):
+    beta substep   u = G_B U                       (values on the beta-curves)
+                   (M + theta dt S) udot = L - S u            eq. (16)-(17)
+                   v = u + dt udot ;   U_half = P_B v
+    gamma substep  u = G_G U_half
+                   (M + theta dt mu K) udot = - mu K u        eq. (18)-(19)
+                   v = u + dt udot ;   U_next = P_G v
+Algebraically v = (M + theta dt S)^{-1} [(M - (1-theta) dt S) u + dt L] on the
+beta-curves and v = (M + theta dt mu K)^{-1} (M - (1-theta) dt mu K) u on the
+gamma-curves; the sweeps below use that form.  Dirichlet ends carry zero.
+
+Stationary problem (Sec. 2: eq. (1) is the t -> infinity limit of eq. (2)):
+the steps are repeated with a fixed pseudo time step until they stop moving
+the solution.  With Phi(U) the step above, the iterate U_{k+1} = Phi(U_k) has
+residual  rel_k = |U_{k+1} - U_k|_2 / |Phi(0)|_2  over the interior nodes, and
+the iteration stops at the first k with rel_k <= tol (returning U_{k+1}).
+Phi is affine, Phi(U) = T U + c with c = Phi(0); its fixed point solves
+(I - T) U = c (see oracle.dense).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import geometry as geo
+from . import linefe as lfe
+from . import transfer as tr
+
+
+class Oracle:
+    """All operators of one problem instance (a workloads.Problem)."""
+
+    def __init__(self, prob, families=None):
+        self.prob = prob
+        self.grid = geo.Grid(prob.box, prob.nx, prob.ny)
+        self.dom = geo.make_domain(prob.domain, prob.dom_params, prob.box)
+        self.flow = geo.Flow(self.grid, prob.beta1, prob.beta2)
+        self.mask = geo.interior_mask(self.grid, self.dom)
+        self.inner_idx = np.nonzero(self.mask.ravel())[0]
+        self.fams = families if families is not None else geo.build_families(
+            self.grid, self.dom, self.flow)
+        self.mu = float(prob.mu)
+        self.sigma = float(prob.sigma)
+        self.G, self.P, self.inner = [], [], []
+        for fam in self.fams:
+            self.G.append(tr.gather_matrix(self.grid, fam))
+            P, _ = tr.scatter_matrix(self.grid, self.dom, fam, self.mask)
+            self.P.append(P)
+            self.inner.append(fam.interior())
+        fb = self.fams[0]
+        b1, b2 = self.flow.beta(fb.x, fb.y)
+        self.bnorm = np.hypot(b1, b2)
+        M, K, C = lfe.line_operators(fb, self.bnorm)
+        self.MB, self.KB, self.CB = M, K, C
+        self.SB = K.scale(self.mu) + C + M.scale(self.sigma)
+        fG = self.fams[1]
+        self.MG, self.KG, _ = lfe.line_operators(fG, None)
+        self.fnode = self.grid.interp(prob.f, fb.x, fb.y)
+        self.L = self.MB.apply(self.fnode)
+        self.L[~self.inner[0]] = 0.0
+
+    # -- pieces ----------------------------------------------------------------
+    def zero_field(self):
+        return np.zeros(self.grid.nx * self.grid.ny)
+
+    def gather(self, fam, U):
+        return self.G[fam] @ U
+
+    def scatter(self, fam, v):
+        return self.P[fam] @ v
+
+    def beta_substep(self, U, theta, dt, source=True):
+        u = self.gather(0, U)
+        A = self.MB + self.SB.scale(theta * dt)
+        rhs = self.MB.apply(u) - (1.0 - theta) * dt * self.SB.apply(u)
+        if source:
+            rhs = rhs + dt * self.L
+        v = lfe.solve_lines(A, rhs, self.inner[0])
+        return self.scatter(0, v), v
+
+    def gamma_substep(self, U, theta, dt):
+        u = self.gather(1, U)
+        A = self.MG + self.KG.scale(theta * dt * self.mu)
+        rhs = self.MG.apply(u) - (1.0 - theta) * dt * self.mu * self.KG.apply(u)
+        v = lfe.solve_lines(A, rhs, self.inner[1])
+        return self.scatter(1, v), v
+
+    def step(self, U, theta, dt, source=True):
+        """One step of eq. (10) with value transfer (see module docstring)."""
+        Uh, _ = self.beta_substep(U, theta, dt, source)
+        Un, _ = self.gamma_substep(Uh, theta, dt)
+        return Un
+
+    def norm(self, U):
+        return float(np.linalg.norm(U[self.inner_idx]))
+
+    # -- stationary iteration --------------------------------------------------
+    def c_norm(self, theta, dt):
+        return self.norm(self.step(self.zero_field(), theta, dt))
+
+    def rel_residual(self, U, theta, dt):
+        return self.norm(self.step(U, theta, dt) - U) / self.c_norm(theta, dt)
+
+    def iterate(self, U0, theta, dt, max_iters, tol, history=False):
+        """U_{k+1} = Phi(U_k) until rel_k <= tol; returns (U, iters, rel, hist)."""
+        cn = self.c_norm(theta, dt)
+        U = np.array(U0, float, copy=True)
+        hist = []
+        rel = np.inf
+        it = 0
+        while it < max_iters:
+            Un = self.step(U, theta, dt)
+            rel = self.norm(Un - U) / cn
+            U = Un
+            it += 1
+            hist.append(rel)
+            if rel <= tol or not np.isfinite(rel):
+                break
+        return U, it, rel, (hist if history else None)
+
+    # -- eq. (11) initial guess --------------------------------------------
+    def s_guess(self):
+        """u0 with s(u0, v) = <l, v> on the beta-curves, scattered to the grid."""
+        v = lfe.solve_lines(self.SB, self.L, self.inner[0])
+        return self.scatter(0, v)
+
+    # -- time marching -------------------------------------------------------
+    def march(self, U0, theta, dt, steps):
+        U = np.array(U0, float, copy=True)
+        for _ in range(steps):
+            U = self.step(U, theta, dt)
+        return U
