@@ -1,0 +1,154 @@
+/*
+ * adr.h -- C ABI of the MI355X (gfx950) directional diffusion splitting solver.
+ *
+ * Method: R. Drebotiy, H. Shynkarenko, "Directional diffusion splitting method
+ * for advection-diffusion-reaction model" (arXiv 2411.11041).
+ *
+ * Problem data follow the paper's problem statement (Sec. 2, eq. (1)-(2)):
+ *   -mu Lap u + beta . grad u + sigma u = f in Omega,  u = 0 on Gamma,
+ *   (parabolic form: u_t + ... = f, u(0) = u0),
+ * mu > 0, sigma > 0 constants, beta divergence free without closed integral
+ * curves in the closure of Omega.  beta and f are given as nodal values on a
+ * rectangular grid covering the bounding box P = [a,b] x [c,d] of Omega
+ * (eq. (20)).  All nodal arrays are row-major, index j*nx + i for the node
+ * (a + i*hx, c + j*hy), hx = (b-a)/(nx-1), hy = (d-c)/(ny-1).
+ *
+ * The solver state u is a grid field with the same layout.  Entries at nodes
+ * that are not strictly inside Omega hold the Dirichlet value, which is zero
+ * (the paper's boundary condition); the caller keeps them at zero.
+ *
+ * One sweep ("step") is eq. (10): the beta substep solves, on every beta-curve
+ * (eq. (13)), the P1 line problem of eq. (16)-(17); the curve values are handed
+ * to the grid by the crossing-record interpolation of Sec. 6 and read by the
+ * gamma-curves (eq. (14)) through the bilinear interpolation of eq. (21)-(23);
+ * the gamma substep solves eq. (18)-(19) and hands its values back to the grid.
+ * The stationary problem is the limit t -> infinity (Sec. 2): sweeps with a
+ * fixed pseudo time step are repeated until they stop changing u.
+ *
+ * Memory and threads.  Problem arrays are host memory owned by the caller and
+ * copied by adr_setup.  u and every other "device" pointer are device memory
+ * (e.g. a torch CUDA/HIP tensor's data_ptr) owned by the caller.  Device
+ * scratch is owned by the context.  Work is queued on options.stream; calls
+ * that return host values synchronise that stream.  A context must not be
+ * used from two threads at once.
+ *
+ * Errors.  Every call returns an adr_status; nothing throws or aborts.  After a
+ * failure adr_last_error(ctx) gives a message (adr_last_error(NULL) gives the
+ * message of the last failed adr_setup in this thread).
+ */
+#ifndef ADR_H
+#define ADR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct adr_ctx adr_ctx;
+typedef int32_t adr_status;
+
+enum {
+    ADR_OK = 0,
+    ADR_EINVAL = -1,      /* bad argument or unsupported size */
+    ADR_ENOMEM = -2,      /* host or device allocation failed */
+    ADR_EDEVICE = -3,     /* HIP runtime error */
+    ADR_EBETA = -4,       /* |beta| vanishes or a curve does not leave Omega (closed streamline) */
+    ADR_ENONFINITE = -5,  /* non-finite input or residual */
+    ADR_ENOTCONV = 1      /* warning: max_iters reached; u holds the last iterate */
+};
+
+enum { ADR_DOM_BOX = 0, ADR_DOM_DISC = 1, ADR_DOM_POLYGON = 2 };
+enum { ADR_PREC_FP64 = 0, ADR_PREC_FP32_LINES = 1 };
+
+typedef struct {
+    int32_t nx, ny;            /* grid nodes over P, each >= 3 */
+    double a, b, c, d;         /* P = [a,b] x [c,d] */
+    int32_t domain;            /* ADR_DOM_*; BOX means Omega = P */
+    int32_t n_dom_params;      /* number of doubles in dom_params */
+    const double *dom_params;  /* DISC: cx, cy, r.  POLYGON: x0,y0,x1,y1,... counter-clockwise */
+    double mu, sigma;          /* > 0 (sigma >= 0 accepted) */
+    const double *beta1;       /* nx*ny nodal beta components (host) */
+    const double *beta2;
+    const double *f;           /* nx*ny nodal source (host) */
+} adr_problem;
+
+typedef struct {
+    int32_t precision;    /* ADR_PREC_FP64: every sweep in FP64.
+                             ADR_PREC_FP32_LINES: one FP64 residual sweep, then
+                             fp32_sweeps FP32 increment sweeps, repeated; state,
+                             residual and convergence test stay FP64 */
+    int32_t fp32_sweeps;  /* FP32 sweeps per FP64 sweep in FP32_LINES mode (>= 0) */
+    double theta;         /* theta of eq. (7)/(10) for the stationary sweeps, (0,1] */
+    double dt;            /* pseudo time step of the stationary sweeps, > 0 */
+    void *stream;         /* hipStream_t; NULL = the default stream */
+    int32_t timing;       /* != 0: time each kernel with HIP events (adr_kernel_times) */
+    int32_t host_only;    /* != 0: build the host geometry only, touch no device; then
+                             only adr_counts, adr_export_lines and adr_destroy are valid */
+} adr_options;
+
+/* Builds the curve families of every instance (host, FP64) and uploads the
+ * line and transfer tables.  probs: n_probs instances solved together (one
+ * launch per kernel covers all of them).  On success *out is a new context;
+ * on failure *out = NULL.  Errors: ADR_EINVAL (sizes, mu <= 0, theta or dt out
+ * of range, a line longer than the solver's LDS capacity), ADR_EBETA (|beta| =
+ * 0 on a curve, a curve longer than four perimeters), ADR_ENONFINITE (NaN/Inf
+ * input), ADR_ENOMEM, ADR_EDEVICE. */
+adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_options *opt,
+                     adr_ctx **out);
+
+/* Packed layout of u over the instances: instance i occupies
+ * offsets[i] .. offsets[i+1]-1 (offsets has n_probs+1 entries, host). */
+adr_status adr_layout(const adr_ctx *ctx, int64_t *offsets);
+
+/* Counts (host out, each may be NULL): interior grid nodes, beta-lines,
+ * gamma-lines, interior (unknown) beta-line nodes and gamma-line nodes, summed
+ * over instances. */
+adr_status adr_counts(const adr_ctx *ctx, int64_t *grid_unknowns, int64_t *lines_b,
+                      int64_t *lines_g, int64_t *line_unknowns_b, int64_t *line_unknowns_g);
+
+/* Stationary solve (Sec. 2 limit, eq. (10) sweeps).  u: device FP64, packed
+ * layout; in: initial iterate, out: last iterate.  Each sweep k maps U_k to
+ * U_{k+1} = Phi(U_k); an instance stops at the first FP64 sweep with
+ *   rel = |U_{k+1} - U_k|_2 / |Phi(0)|_2 <= tol      (interior nodes)
+ * (in FP32_LINES mode rel is measured on the FP64 sweeps only).  iters (host,
+ * n_probs, may be NULL): sweeps applied per instance; rel_res (host, n_probs,
+ * may be NULL): last measured rel.  Returns ADR_ENOTCONV if an instance hit
+ * max_iters, ADR_ENONFINITE if a residual is not finite. */
+adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol,
+                             int32_t *iters, double *rel_res);
+
+/* Parabolic march (eq. (2) discretised by eq. (10)): nsteps sweeps with the
+ * given theta in (0,1] and time step dt > 0, FP64, source f included.  u:
+ * device FP64 packed, in: u_n, out: u_{n+nsteps}.  Asynchronous. */
+adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32_t nsteps);
+
+/* rel_res[i] = |Phi(U) - U|_2 / |Phi(0)|_2 of the stationary sweep for the given
+ * u (device FP64, unchanged), in FP64.  rel_res: host, n_probs. */
+adr_status adr_residual(adr_ctx *ctx, const double *u, double *rel_res);
+
+/* Initial iterate of eq. (11): s(u0, v) = <l, v> solved on every beta-curve,
+ * handed to the grid.  u: device FP64 packed (written).  Asynchronous. */
+adr_status adr_initial_guess(adr_ctx *ctx, double *u);
+
+/* Geometry export for testing: line node coordinates of one instance and
+ * family (0 = beta-curves, 1 = gamma-curves).  Call with NULL arrays to get
+ * *n_lines and *n_nodes, then with offsets (n_lines+1), x, y (n_nodes) host
+ * buffers. */
+adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_lines,
+                            int64_t *n_nodes, int64_t *offsets, double *x, double *y);
+
+/* Kernel timing (options.timing != 0): for kernel class k (0 beta-line solve,
+ * 1 gamma-line solve, 2 beta scatter, 3 gamma scatter/update, 4 norm), total
+ * milliseconds and launch count since setup or the last reset.  reset != 0
+ * clears the counters after reading.  Synchronises the stream. */
+adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out,
+                            int32_t reset);
+
+adr_status adr_destroy(adr_ctx *ctx);
+const char *adr_last_error(const adr_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADR_H */

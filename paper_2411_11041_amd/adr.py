@@ -1,0 +1,196 @@
+"""ctypes binding of libadr.so (include/adr.h): argument marshalling only.
+
+Every step of the solver runs in the HIP library; this module converts problem
+descriptions into the C structs, passes device pointers of torch tensors and
+returns host results.  It fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libadr.so")
+
+ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE, ADR_EBETA, ADR_ENONFINITE, ADR_ENOTCONV = 0, -1, -2, -3, -4, -5, 1
+DOM_BOX, DOM_DISC, DOM_POLYGON = 0, 1, 2
+PREC_FP64, PREC_FP32_LINES = 0, 1
+
+EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_split_iterate", "adr_time_step",
+           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_kernel_times",
+           "adr_destroy", "adr_last_error")
+
+KERNEL_CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma", "norm")
+
+
+class ADRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"adr status {code}: {msg}")
+        self.code = code
+
+
+class Problem(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
+                ("a", C.c_double), ("b", C.c_double), ("c", C.c_double), ("d", C.c_double),
+                ("domain", C.c_int32), ("n_dom_params", C.c_int32),
+                ("dom_params", C.POINTER(C.c_double)),
+                ("mu", C.c_double), ("sigma", C.c_double),
+                ("beta1", C.POINTER(C.c_double)), ("beta2", C.POINTER(C.c_double)),
+                ("f", C.POINTER(C.c_double))]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("fp32_sweeps", C.c_int32),
+                ("theta", C.c_double), ("dt", C.c_double),
+                ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libadr.so (built in-tree); raise if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} not built: run paper_2411_11041_amd/build.py")
+    lib = C.CDLL(LIB_PATH)
+    i32, i64, dbl, vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
+    P = C.POINTER
+    lib.adr_setup.argtypes = [P(Problem), i32, P(Options), P(vp)]
+    lib.adr_layout.argtypes = [vp, P(i64)]
+    lib.adr_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64), P(i64)]
+    lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
+    lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32]
+    lib.adr_residual.argtypes = [vp, vp, P(dbl)]
+    lib.adr_initial_guess.argtypes = [vp, vp]
+    lib.adr_export_lines.argtypes = [vp, i32, i32, P(i64), P(i64), P(i64), P(dbl), P(dbl)]
+    lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), i32]
+    lib.adr_destroy.argtypes = [vp]
+    lib.adr_last_error.argtypes = [vp]
+    lib.adr_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("adr_last_error",):
+            getattr(lib, name).restype = i32
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _device_ptr(t):
+    """Device pointer of a torch float64 CUDA tensor (contiguous)."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError("u must be a contiguous float64 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One context over a batch of problems (workloads.Problem-like objects)."""
+
+    def __init__(self, problems, precision="fp64", theta=1.0, dt=0.05, fp32_sweeps=3,
+                 stream=None, timing=False, host_only=False):
+        self.lib = load()
+        if not isinstance(problems, (list, tuple)):
+            problems = [problems]
+        self._keep = []
+        arr = (Problem * len(problems))()
+        for k, p in enumerate(problems):
+            b1 = np.ascontiguousarray(p.beta1, np.float64).ravel()
+            b2 = np.ascontiguousarray(p.beta2, np.float64).ravel()
+            f = np.ascontiguousarray(p.f, np.float64).ravel()
+            dp = np.ascontiguousarray(np.asarray(p.dom_params, np.float64).ravel())
+            self._keep += [b1, b2, f, dp]
+            a, b, c, d = p.box
+            arr[k] = Problem(p.nx, p.ny, a, b, c, d, int(p.domain), int(dp.size),
+                             _dptr(dp) if dp.size else None, float(p.mu), float(p.sigma),
+                             _dptr(b1), _dptr(b2), _dptr(f))
+        if stream is None and not host_only:
+            import torch
+            stream = torch.cuda.current_stream().cuda_stream
+        prec = {"fp64": PREC_FP64, "fp32": PREC_FP32_LINES}[precision]
+        opt = Options(prec, int(fp32_sweeps), float(theta), float(dt),
+                      C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)))
+        self.n = len(problems)
+        self.ctx = C.c_void_p()
+        st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))
+        if st != ADR_OK:
+            raise ADRError(st, self.lib.adr_last_error(None).decode())
+        self.host_only = host_only
+        self.precision = precision
+
+    def _check(self, st, ok=(ADR_OK,)):
+        if st not in ok:
+            raise ADRError(st, self.lib.adr_last_error(self.ctx).decode())
+        return st
+
+    def layout(self):
+        off = np.zeros(self.n + 1, np.int64)
+        self._check(self.lib.adr_layout(self.ctx, off.ctypes.data_as(C.POINTER(C.c_int64))))
+        return off
+
+    def counts(self):
+        v = [C.c_int64() for _ in range(5)]
+        self._check(self.lib.adr_counts(self.ctx, *[C.byref(x) for x in v]))
+        return dict(grid_unknowns=v[0].value, lines_b=v[1].value, lines_g=v[2].value,
+                    line_unknowns_b=v[3].value, line_unknowns_g=v[4].value)
+
+    def split_iterate(self, u, max_iters, tol):
+        iters = np.zeros(self.n, np.int32)
+        rel = np.zeros(self.n, np.float64)
+        st = self.lib.adr_split_iterate(self.ctx, _device_ptr(u), int(max_iters), float(tol),
+                                        iters.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(rel))
+        self._check(st, ok=(ADR_OK, ADR_ENOTCONV))
+        return iters, rel, st
+
+    def time_step(self, u, theta, dt, nsteps):
+        self._check(self.lib.adr_time_step(self.ctx, _device_ptr(u), float(theta), float(dt), int(nsteps)))
+
+    def residual(self, u):
+        rel = np.zeros(self.n, np.float64)
+        self._check(self.lib.adr_residual(self.ctx, _device_ptr(u), _dptr(rel)))
+        return rel
+
+    def initial_guess(self, u):
+        self._check(self.lib.adr_initial_guess(self.ctx, _device_ptr(u)))
+
+    def export_lines(self, inst, family):
+        nl, nn = C.c_int64(), C.c_int64()
+        self._check(self.lib.adr_export_lines(self.ctx, inst, family, C.byref(nl), C.byref(nn),
+                                              None, None, None))
+        off = np.zeros(nl.value + 1, np.int64)
+        x = np.zeros(nn.value)
+        y = np.zeros(nn.value)
+        self._check(self.lib.adr_export_lines(self.ctx, inst, family, None, None,
+                                              off.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(x), _dptr(y)))
+        return off, x, y
+
+    def kernel_times(self, precision="fp64", reset=True):
+        ms = np.zeros(5)
+        cnt = np.zeros(5, np.int64)
+        self._check(self.lib.adr_kernel_times(self.ctx, {"fp64": 0, "fp32": 1}[precision], _dptr(ms),
+                                              cnt.ctypes.data_as(C.POINTER(C.c_int64)), int(bool(reset))))
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def close(self):
+        if self.ctx:
+            self.lib.adr_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -1,0 +1,625 @@
+// C ABI of the directional diffusion splitting solver: context set-up,
+// device tables, sweep drivers (eq. (10)), stationary iteration, parabolic
+// march, eq. (11) initial guess, residual, geometry export, kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "adr_internal.h"
+#include "adr_kernels.h"
+
+using adr::Error;
+
+namespace {
+
+thread_local std::string g_setup_error;
+
+constexpr int kSlotStep = 0, kSlotLin = 1, kSlotTime = 2, kSlotGuess = 3, kSlots = 4;
+constexpr int kBlock = 256;
+constexpr size_t kLdsLimit = 160 * 1024;
+// line-length buckets (nodes per line): each bucket is one launch with its own LDS size
+constexpr int kBucketEdges[] = {96, 384, 1536, 1 << 30};
+constexpr int kBuckets = 4;
+
+#define HIPCHK(x)                                                                              \
+    do {                                                                                       \
+        hipError_t e_ = (x);                                                                   \
+        if (e_ != hipSuccess) throw Error{ADR_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+template <typename T>
+T *dalloc(size_t n, std::vector<void *> &owned) {
+    if (n == 0) n = 1;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(T));
+    if (e != hipSuccess) throw Error{ADR_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)};
+    owned.push_back(p);
+    return static_cast<T *>(p);
+}
+
+template <typename T>
+T *upload(const std::vector<T> &h, std::vector<void *> &owned, hipStream_t st) {
+    T *d = dalloc<T>(h.size(), owned);
+    (void)st;  // synchronous: the host vector may be a temporary
+    if (!h.empty()) HIPCHK(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return d;
+}
+
+template <typename T>
+std::vector<T> to_type(const std::vector<double> &v) {
+    return std::vector<T>(v.begin(), v.end());
+}
+
+struct Bucket {
+    int first, count, nmax;
+};
+
+struct DevFam {
+    int n_lines = 0;
+    int64_t n_nodes = 0, n_unknowns = 0;
+    Bucket bk[kBuckets];
+    adr::LineArgs<double> a64{};
+    adr::LineArgs<float> a32{};
+    adr::ScatterArgs<double> s64{};
+    adr::ScatterArgs<float> s32{};
+    double *v64 = nullptr;
+    float *v32 = nullptr;
+};
+
+}  // namespace
+
+struct adr_ctx {
+    int n_inst = 0;
+    std::vector<int64_t> goff;
+    int64_t n_grid = 0, n_unknowns = 0;
+    adr_options opt{};
+    hipStream_t st = nullptr;
+    std::vector<void *> owned;
+    DevFam fam[2];
+    int *blk_start = nullptr, *inst_nx = nullptr;
+    int n_blocks = 0;
+    double *par = nullptr;  // [slot][fam][inst][8]
+    std::vector<double> par_h;
+    double *Uh64 = nullptr, *Z64 = nullptr, *partial = nullptr, *cnorm = nullptr, *rel = nullptr;
+    float *d32 = nullptr, *D32 = nullptr;
+    int *done = nullptr, *never = nullptr, *conv_it = nullptr;
+    double last_theta = -1, last_dt = -1;
+    std::vector<double> mu, sg;
+    std::string err;
+    std::vector<adr::Family> geo[2];  // per instance, for export
+    // timing
+    struct Tick {
+        int prec, cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Tick> ticks;
+    double ms[2][5] = {};
+    int64_t cnt[2][5] = {};
+
+    const double *par_ptr(int slot, int f) const { return par + (static_cast<size_t>(slot) * 2 + f) * n_inst * 8; }
+
+    template <typename F>
+    void timed(int prec, int cls, F &&fn) {
+        if (!opt.timing) {
+            HIPCHK(fn());
+            return;
+        }
+        Tick t{prec, cls, nullptr, nullptr};
+        HIPCHK(hipEventCreate(&t.a));
+        HIPCHK(hipEventCreate(&t.b));
+        HIPCHK(hipEventRecord(t.a, st));
+        HIPCHK(fn());
+        HIPCHK(hipEventRecord(t.b, st));
+        ticks.push_back(t);
+    }
+
+    void collect_ticks() {
+        if (ticks.empty()) return;
+        HIPCHK(hipStreamSynchronize(st));
+        for (auto &t : ticks) {
+            float e = 0.f;
+            HIPCHK(hipEventElapsedTime(&e, t.a, t.b));
+            ms[t.prec][t.cls] += e;
+            cnt[t.prec][t.cls] += 1;
+            (void)hipEventDestroy(t.a);
+            (void)hipEventDestroy(t.b);
+        }
+        ticks.clear();
+    }
+
+    void line64(int f, int slot, const double *fin, const int *dn) {
+        DevFam &F = fam[f];
+        for (int b = 0; b < kBuckets; ++b) {
+            const Bucket &k = F.bk[b];
+            if (k.count == 0) continue;
+            adr::LineArgs<double> a = F.a64;
+            a.loff += k.first; a.lcnt += k.first; a.linst += k.first;
+            timed(0, f, [&] { return adr::launch_line<double>(f, a, k.count, fin, F.v64, par_ptr(slot, f), dn, k.nmax, st); });
+        }
+    }
+    void line32(int f, int slot, const float *fin, const int *dn) {
+        DevFam &F = fam[f];
+        for (int b = 0; b < kBuckets; ++b) {
+            const Bucket &k = F.bk[b];
+            if (k.count == 0) continue;
+            adr::LineArgs<float> a = F.a32;
+            a.loff += k.first; a.lcnt += k.first; a.linst += k.first;
+            timed(1, f, [&] { return adr::launch_line<float>(f, a, k.count, fin, F.v32, par_ptr(slot, f), dn, k.nmax, st); });
+        }
+    }
+
+    // One FP64 sweep of eq. (10) from U.  mode of the final scatter: 0 write U,
+    // 1 write U + d32 + partial, 3 partial only (U unchanged).
+    void sweep64(int slot, const double *U_in, double *U_out, int mode, const int *dn) {
+        line64(0, slot, U_in, dn);
+        timed(0, 2, [&] { return adr::launch_scatter<double, double>(0, fam[0].s64, fam[0].v64, Uh64, d32, partial, dn, st); });
+        line64(1, slot, Uh64, dn);
+        timed(0, 3, [&] { return adr::launch_scatter<double, double>(mode, fam[1].s64, fam[1].v64, U_out, d32, partial, dn, st); });
+    }
+    // One FP32 increment sweep: d32 <- T d32, U += d32.
+    void sweep32(double *U, const int *dn) {
+        line32(0, kSlotLin, d32, dn);
+        timed(1, 2, [&] { return adr::launch_scatter<float, float>(0, fam[0].s32, fam[0].v32, D32, nullptr, partial, dn, st); });
+        line32(1, kSlotLin, D32, dn);
+        timed(1, 3, [&] { return adr::launch_scatter<float, double>(2, fam[1].s32, fam[1].v32, U, d32, partial, dn, st); });
+    }
+    void norm(int sweep, double tol, int mode, const int *dn_unused) {
+        (void)dn_unused;
+        timed(0, 4, [&] {
+            return adr::launch_norm(n_inst, partial, blk_start, cnorm, rel, done, conv_it, sweep, tol, mode, st);
+        });
+    }
+
+};
+
+namespace {
+
+void fill_params(std::vector<double> &ph, int n_inst, int slot, const std::vector<double> &mu,
+                 const std::vector<double> &sg, double theta, double dt) {
+    for (int f = 0; f < 2; ++f)
+        for (int i = 0; i < n_inst; ++i) {
+            double *p = ph.data() + ((static_cast<size_t>(slot) * 2 + f) * n_inst + i) * 8;
+            std::fill(p, p + 8, 0.0);
+            if (slot == kSlotGuess) {
+                if (f == 0) { p[0] = sg[i]; p[1] = mu[i]; p[2] = 1.0; p[6] = 1.0; }
+                continue;
+            }
+            const double td = theta * dt, ed = (1.0 - theta) * dt;
+            if (f == 0) {
+                p[0] = 1.0 + td * sg[i]; p[1] = td * mu[i]; p[2] = td;
+                p[3] = 1.0 - ed * sg[i]; p[4] = -ed * mu[i]; p[5] = -ed;
+                p[6] = slot == kSlotLin ? 0.0 : dt;
+            } else {
+                p[0] = 1.0; p[1] = td * mu[i]; p[2] = 0.0;
+                p[3] = 1.0; p[4] = -ed * mu[i]; p[5] = 0.0; p[6] = 0.0;
+            }
+        }
+}
+
+adr_status fail_ctx(adr_ctx *c, const Error &e) {
+    if (c) c->err = e.msg;
+    return e.code;
+}
+
+}  // namespace
+
+extern "C" {
+
+adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_options *opt, adr_ctx **out) {
+    if (!out) return ADR_EINVAL;
+    *out = nullptr;
+    std::unique_ptr<adr_ctx> C(new adr_ctx);
+    try {
+        if (!probs || n_probs <= 0 || !opt) throw Error{ADR_EINVAL, "probs, n_probs > 0 and opt are required"};
+        if (!(opt->theta > 0.0 && opt->theta <= 1.0)) throw Error{ADR_EINVAL, "theta must be in (0, 1]"};
+        if (!(opt->dt > 0.0) || !std::isfinite(opt->dt)) throw Error{ADR_EINVAL, "dt must be > 0"};
+        if (opt->precision != ADR_PREC_FP64 && opt->precision != ADR_PREC_FP32_LINES)
+            throw Error{ADR_EINVAL, "unknown precision"};
+        if (opt->fp32_sweeps < 0) throw Error{ADR_EINVAL, "fp32_sweeps must be >= 0"};
+        C->opt = *opt;
+        C->n_inst = n_probs;
+        C->st = static_cast<hipStream_t>(opt->stream);
+        const int n = n_probs;
+
+        // host geometry, instances in parallel
+        std::vector<adr::InstanceGeo> G(n);
+        std::vector<Error> errs(n, Error{ADR_OK, ""});
+        {
+            unsigned nt = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
+            nt = std::min<unsigned>(nt, static_cast<unsigned>(n));
+            std::atomic<int> next{0};
+            std::vector<std::thread> pool;
+            for (unsigned t = 0; t < nt; ++t)
+                pool.emplace_back([&] {
+                    for (int i = next++; i < n; i = next++) {
+                        try {
+                            adr::build_instance(probs[i], G[i]);
+                        } catch (const Error &e) {
+                            errs[i] = e;
+                        } catch (const std::bad_alloc &) {
+                            errs[i] = Error{ADR_ENOMEM, "host allocation failed"};
+                        }
+                    }
+                });
+            for (auto &th : pool) th.join();
+        }
+        for (int i = 0; i < n; ++i)
+            if (errs[i].code != ADR_OK)
+                throw Error{errs[i].code, "instance " + std::to_string(i) + ": " + errs[i].msg};
+
+        if (opt->host_only) {
+            C->goff.assign(n + 1, 0);
+            for (int i = 0; i < n; ++i) {
+                C->goff[i + 1] = C->goff[i] + static_cast<int64_t>(G[i].g.nx) * G[i].g.ny;
+                C->n_unknowns += static_cast<int64_t>(G[i].inner_list.size());
+                for (int f = 0; f < 2; ++f) {
+                    const adr::Family &fa = G[i].fam[f];
+                    C->fam[f].n_lines += static_cast<int>(fa.off.size()) - 1;
+                    C->fam[f].n_nodes += static_cast<int64_t>(fa.x.size());
+                    C->fam[f].n_unknowns += static_cast<int64_t>(fa.x.size()) - 2 * (static_cast<int64_t>(fa.off.size()) - 1);
+                    C->geo[f].push_back(fa);
+                }
+            }
+            *out = C.release();
+            return ADR_OK;
+        }
+
+        // packing
+        C->goff.assign(n + 1, 0);
+        std::vector<int> inst_nx(n);
+        std::vector<double> mu(n), sg(n);
+        for (int i = 0; i < n; ++i) {
+            C->goff[i + 1] = C->goff[i] + static_cast<int64_t>(G[i].g.nx) * G[i].g.ny;
+            inst_nx[i] = G[i].g.nx;
+            mu[i] = G[i].mu;
+            sg[i] = G[i].sigma;
+        }
+        C->n_grid = C->goff[n];
+        if (C->n_grid > (int64_t(1) << 31) - 1) throw Error{ADR_EINVAL, "packed grid exceeds 2^31 nodes"};
+        hipStream_t st = C->st;
+        auto &own = C->owned;
+        C->inst_nx = upload(inst_nx, own, st);
+
+        // scatter slots, padded per instance to whole blocks
+        std::vector<int> blk_start(n + 1, 0);
+        for (int i = 0; i < n; ++i)
+            blk_start[i + 1] = blk_start[i] + static_cast<int>((G[i].inner_list.size() + kBlock - 1) / kBlock);
+        const int nblk = blk_start[n];
+        const int npad = nblk * kBlock;
+        C->n_blocks = nblk;
+        std::vector<int> gidx(npad, -1), blk_inst(nblk);
+        for (int i = 0; i < n; ++i) {
+            for (int b = blk_start[i]; b < blk_start[i + 1]; ++b) blk_inst[b] = i;
+            for (size_t s = 0; s < G[i].inner_list.size(); ++s)
+                gidx[blk_start[i] * kBlock + s] = static_cast<int>(C->goff[i] + G[i].inner_list[s]);
+            C->n_unknowns += static_cast<int64_t>(G[i].inner_list.size());
+        }
+        int *d_gidx = upload(gidx, own, st);
+        int *d_blk_inst = upload(blk_inst, own, st);
+        C->blk_start = upload(blk_start, own, st);
+
+        for (int f = 0; f < 2; ++f) {
+            DevFam &F = C->fam[f];
+            std::vector<int64_t> noff(n + 1, 0);
+            std::vector<std::pair<int, int>> lines;  // (instance, local line)
+            for (int i = 0; i < n; ++i) {
+                const adr::Family &fa = G[i].fam[f];
+                noff[i + 1] = noff[i] + static_cast<int64_t>(fa.x.size());
+                for (size_t l = 0; l + 1 < fa.off.size(); ++l) lines.emplace_back(i, static_cast<int>(l));
+            }
+            F.n_nodes = noff[n];
+            if (F.n_nodes > (int64_t(1) << 31) - 2) throw Error{ADR_EINVAL, "too many line nodes"};
+            F.n_lines = static_cast<int>(lines.size());
+            // bucket lines by node count (stable within a bucket)
+            std::vector<int> loff, lcnt, linst;
+            loff.reserve(lines.size());
+            int first = 0;
+            for (int b = 0; b < kBuckets; ++b) {
+                const int lo = b == 0 ? 0 : kBucketEdges[b - 1];
+                const int hi = kBucketEdges[b];
+                int nmax = 0, count = 0;
+                for (auto &li : lines) {
+                    const adr::Family &fa = G[li.first].fam[f];
+                    const int cnt = static_cast<int>(fa.off[li.second + 1] - fa.off[li.second]);
+                    if (cnt <= lo || cnt > hi) continue;
+                    loff.push_back(static_cast<int>(noff[li.first] + fa.off[li.second]));
+                    lcnt.push_back(cnt);
+                    linst.push_back(li.first);
+                    nmax = std::max(nmax, cnt);
+                    ++count;
+                    F.n_unknowns += cnt - 2;
+                }
+                F.bk[b] = Bucket{first, count, nmax};
+                first += count;
+                if (count && adr::line_lds_bytes<double>(nmax) > kLdsLimit)
+                    throw Error{ADR_EINVAL, "a curve has " + std::to_string(nmax) +
+                                                " nodes: longer than the LDS-resident line solver holds"};
+            }
+            // per node data
+            std::vector<int> cell(F.n_nodes, -1);
+            std::vector<double> lx(F.n_nodes), ly(F.n_nodes), h(F.n_nodes), w, L;
+            if (f == 0) { w.resize(F.n_nodes); L.resize(F.n_nodes); }
+            for (int i = 0; i < n; ++i) {
+                const adr::Family &fa = G[i].fam[f];
+                for (size_t k = 0; k < fa.x.size(); ++k) {
+                    const int64_t gk = noff[i] + static_cast<int64_t>(k);
+                    const int c = G[i].cellk[f][k];
+                    cell[gk] = c < 0 ? -1 : static_cast<int>(C->goff[i] + c);
+                    lx[gk] = G[i].lxk[f][k];
+                    ly[gk] = G[i].lyk[f][k];
+                    h[gk] = G[i].hk[f][k];
+                    if (f == 0) { w[gk] = G[i].wk[k]; L[gk] = G[i].Lk[k]; }
+                }
+            }
+            const int *d_loff = upload(loff, own, st), *d_lcnt = upload(lcnt, own, st);
+            const int *d_linst = upload(linst, own, st), *d_cell = upload(cell, own, st);
+            F.a64 = adr::LineArgs<double>{d_loff, d_lcnt, d_linst, C->inst_nx, d_cell,
+                                          upload(lx, own, st), upload(ly, own, st), upload(h, own, st),
+                                          f == 0 ? upload(w, own, st) : nullptr,
+                                          f == 0 ? upload(L, own, st) : nullptr};
+            F.a32 = adr::LineArgs<float>{d_loff, d_lcnt, d_linst, C->inst_nx, d_cell,
+                                         upload(to_type<float>(lx), own, st), upload(to_type<float>(ly), own, st),
+                                         upload(to_type<float>(h), own, st),
+                                         f == 0 ? upload(to_type<float>(w), own, st) : nullptr,
+                                         f == 0 ? upload(to_type<float>(L), own, st) : nullptr};
+            // scatter records
+            std::vector<int> rk(4 * static_cast<size_t>(npad), -1);
+            std::vector<double> ra(4 * static_cast<size_t>(npad), 0.0), rb(4 * static_cast<size_t>(npad), 0.0);
+            for (int i = 0; i < n; ++i)
+                for (size_t s = 0; s < G[i].inner_list.size(); ++s) {
+                    const size_t slot = static_cast<size_t>(blk_start[i]) * kBlock + s;
+                    const adr::Rec4 &R = G[i].rec[f][s];
+                    for (int r = 0; r < 4; ++r) {
+                        rk[r * static_cast<size_t>(npad) + slot] = R.k[r] < 0 ? -1 : static_cast<int>(noff[i] + R.k[r]);
+                        ra[r * static_cast<size_t>(npad) + slot] = R.ca[r];
+                        rb[r * static_cast<size_t>(npad) + slot] = R.cb[r];
+                    }
+                }
+            const int *d_rk = upload(rk, own, st);
+            F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, upload(ra, own, st), upload(rb, own, st), npad};
+            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, upload(to_type<float>(ra), own, st),
+                                            upload(to_type<float>(rb), own, st), npad};
+            F.v64 = dalloc<double>(F.n_nodes, own);
+            F.v32 = dalloc<float>(F.n_nodes, own);
+            for (int i = 0; i < n; ++i) C->geo[f].push_back(G[i].fam[f]);
+        }
+
+        // state scratch (zeroed: non-interior nodes must read as zero)
+        C->Uh64 = dalloc<double>(C->n_grid, own);
+        C->Z64 = dalloc<double>(C->n_grid, own);
+        C->d32 = dalloc<float>(C->n_grid, own);
+        C->D32 = dalloc<float>(C->n_grid, own);
+        HIPCHK(hipMemsetAsync(C->Uh64, 0, sizeof(double) * C->n_grid, st));
+        HIPCHK(hipMemsetAsync(C->Z64, 0, sizeof(double) * C->n_grid, st));
+        HIPCHK(hipMemsetAsync(C->d32, 0, sizeof(float) * C->n_grid, st));
+        HIPCHK(hipMemsetAsync(C->D32, 0, sizeof(float) * C->n_grid, st));
+        C->partial = dalloc<double>(std::max(nblk, 1), own);
+        C->cnorm = dalloc<double>(n, own);
+        C->rel = dalloc<double>(n, own);
+        C->done = dalloc<int>(n, own);
+        C->never = dalloc<int>(n, own);
+        C->conv_it = dalloc<int>(n, own);
+        HIPCHK(hipMemsetAsync(C->never, 0, sizeof(int) * n, st));
+        HIPCHK(hipMemsetAsync(C->done, 0, sizeof(int) * n, st));
+
+        C->par_h.assign(static_cast<size_t>(kSlots) * 2 * n * 8, 0.0);
+        fill_params(C->par_h, n, kSlotStep, mu, sg, opt->theta, opt->dt);
+        fill_params(C->par_h, n, kSlotLin, mu, sg, opt->theta, opt->dt);
+        fill_params(C->par_h, n, kSlotGuess, mu, sg, 1.0, 1.0);
+        C->par = upload(C->par_h, own, st);
+        C->mu = mu;
+        C->sg = sg;
+
+        // |Phi(0)| per instance: one FP64 sweep from zero
+        C->sweep64(kSlotStep, C->Z64, C->Z64, 3, C->never);
+        C->norm(0, 0.0, 1, nullptr);
+        HIPCHK(hipStreamSynchronize(st));
+        C->collect_ticks();
+        for (auto &r : C->ms) for (auto &v : r) v = 0.0;
+        for (auto &r : C->cnt) for (auto &v : r) v = 0;
+    } catch (const Error &e) {
+        g_setup_error = e.msg;
+        for (void *p : C->owned) (void)hipFree(p);
+        C->owned.clear();
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        g_setup_error = "host allocation failed";
+        for (void *p : C->owned) (void)hipFree(p);
+        C->owned.clear();
+        return ADR_ENOMEM;
+    }
+    *out = C.release();
+    return ADR_OK;
+}
+
+adr_status adr_layout(const adr_ctx *ctx, int64_t *offsets) {
+    if (!ctx || !offsets) return ADR_EINVAL;
+    for (int i = 0; i <= ctx->n_inst; ++i) offsets[i] = ctx->goff[i];
+    return ADR_OK;
+}
+
+adr_status adr_counts(const adr_ctx *ctx, int64_t *grid_unknowns, int64_t *lines_b, int64_t *lines_g,
+                      int64_t *line_unknowns_b, int64_t *line_unknowns_g) {
+    if (!ctx) return ADR_EINVAL;
+    if (grid_unknowns) *grid_unknowns = ctx->n_unknowns;
+    if (lines_b) *lines_b = ctx->fam[0].n_lines;
+    if (lines_g) *lines_g = ctx->fam[1].n_lines;
+    if (line_unknowns_b) *line_unknowns_b = ctx->fam[0].n_unknowns;
+    if (line_unknowns_g) *line_unknowns_g = ctx->fam[1].n_unknowns;
+    return ADR_OK;
+}
+
+adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol, int32_t *iters,
+                             double *rel_res) {
+    if (!ctx) return ADR_EINVAL;
+    if (!u || max_iters < 0 || !(tol >= 0.0)) {
+        ctx->err = "u, max_iters >= 0 and tol >= 0 are required";
+        return ADR_EINVAL;
+    }
+    try {
+        const int n = ctx->n_inst;
+        hipStream_t st = ctx->st;
+        HIPCHK(adr::launch_fill_int(ctx->done, 0, n, st));
+        HIPCHK(adr::launch_fill_int(ctx->conv_it, 0, n, st));
+        const bool fp32 = ctx->opt.precision == ADR_PREC_FP32_LINES;
+        const int period = fp32 ? ctx->opt.fp32_sweeps + 1 : 1;
+        const int check = std::max(4, 2 * period);
+        std::vector<int> dn(n, 0);
+        int executed = 0;
+        for (int s = 0; s < max_iters; ++s) {
+            if (s % period == 0) {
+                ctx->sweep64(kSlotStep, u, u, 1, ctx->done);
+                ctx->norm(s, tol, 0, nullptr);
+            } else {
+                ctx->sweep32(u, ctx->done);
+            }
+            executed = s + 1;
+            if ((s + 1) % check == 0 || s + 1 == max_iters) {
+                HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                if (std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; })) break;
+            }
+        }
+        std::vector<int> ci(n, 0);
+        std::vector<double> rr(n, 0.0);
+        HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(ci.data(), ctx->conv_it, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(rr.data(), ctx->rel, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        adr_status status = ADR_OK;
+        for (int i = 0; i < n; ++i) {
+            if (iters) iters[i] = dn[i] ? ci[i] : executed;
+            if (rel_res) rel_res[i] = max_iters > 0 ? rr[i] : NAN;
+            if (max_iters > 0 && !std::isfinite(rr[i])) status = ADR_ENONFINITE;
+            else if (!dn[i] && status == ADR_OK) status = ADR_ENOTCONV;
+        }
+        if (status == ADR_ENONFINITE) ctx->err = "non-finite residual";
+        return status;
+    } catch (const Error &e) {
+        return fail_ctx(ctx, e);
+    }
+}
+
+adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32_t nsteps) {
+    if (!ctx) return ADR_EINVAL;
+    if (!u || nsteps < 0 || !(theta > 0.0 && theta <= 1.0) || !(dt > 0.0)) {
+        ctx->err = "u, nsteps >= 0, theta in (0,1] and dt > 0 are required";
+        return ADR_EINVAL;
+    }
+    try {
+        if (theta != ctx->last_theta || dt != ctx->last_dt) {
+            fill_params(ctx->par_h, ctx->n_inst, kSlotTime, ctx->mu, ctx->sg, theta, dt);
+            HIPCHK(hipMemcpy(ctx->par + static_cast<size_t>(kSlotTime) * 2 * ctx->n_inst * 8,
+                             ctx->par_h.data() + static_cast<size_t>(kSlotTime) * 2 * ctx->n_inst * 8,
+                             sizeof(double) * 2 * ctx->n_inst * 8, hipMemcpyHostToDevice));
+            ctx->last_theta = theta;
+            ctx->last_dt = dt;
+        }
+        for (int s = 0; s < nsteps; ++s) ctx->sweep64(kSlotTime, u, u, 0, ctx->never);
+        return ADR_OK;
+    } catch (const Error &e) {
+        return fail_ctx(ctx, e);
+    }
+}
+
+adr_status adr_residual(adr_ctx *ctx, const double *u, double *rel_res) {
+    if (!ctx) return ADR_EINVAL;
+    if (!u || !rel_res) {
+        ctx->err = "u and rel_res are required";
+        return ADR_EINVAL;
+    }
+    try {
+        ctx->sweep64(kSlotStep, u, const_cast<double *>(u), 3, ctx->never);
+        ctx->norm(0, 0.0, 2, nullptr);
+        HIPCHK(hipMemcpyAsync(rel_res, ctx->rel, sizeof(double) * ctx->n_inst, hipMemcpyDeviceToHost, ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        for (int i = 0; i < ctx->n_inst; ++i)
+            if (!std::isfinite(rel_res[i])) {
+                ctx->err = "non-finite residual";
+                return ADR_ENONFINITE;
+            }
+        return ADR_OK;
+    } catch (const Error &e) {
+        return fail_ctx(ctx, e);
+    }
+}
+
+adr_status adr_initial_guess(adr_ctx *ctx, double *u) {
+    if (!ctx) return ADR_EINVAL;
+    if (!u) {
+        ctx->err = "u is required";
+        return ADR_EINVAL;
+    }
+    try {
+        ctx->line64(0, kSlotGuess, ctx->Z64, ctx->never);
+        ctx->timed(0, 2, [&] {
+            return adr::launch_scatter<double, double>(0, ctx->fam[0].s64, ctx->fam[0].v64, u, ctx->d32,
+                                                       ctx->partial, ctx->never, ctx->st);
+        });
+        return ADR_OK;
+    } catch (const Error &e) {
+        return fail_ctx(ctx, e);
+    }
+}
+
+adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_lines, int64_t *n_nodes,
+                            int64_t *offsets, double *x, double *y) {
+    if (!ctx || inst < 0 || inst >= ctx->n_inst || family < 0 || family > 1) return ADR_EINVAL;
+    const adr::Family &F = ctx->geo[family][inst];
+    if (n_lines) *n_lines = static_cast<int64_t>(F.off.size()) - 1;
+    if (n_nodes) *n_nodes = static_cast<int64_t>(F.x.size());
+    if (offsets) std::copy(F.off.begin(), F.off.end(), offsets);
+    if (x) std::copy(F.x.begin(), F.x.end(), x);
+    if (y) std::copy(F.y.begin(), F.y.end(), y);
+    return ADR_OK;
+}
+
+adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out, int32_t reset) {
+    if (!ctx || precision < 0 || precision > 1) return ADR_EINVAL;
+    try {
+        ctx->collect_ticks();
+        for (int k = 0; k < 5; ++k) {
+            if (ms_out) ms_out[k] = ctx->ms[precision][k];
+            if (count_out) count_out[k] = ctx->cnt[precision][k];
+        }
+        if (reset)
+            for (int p = 0; p < 2; ++p)
+                for (int k = 0; k < 5; ++k) {
+                    ctx->ms[p][k] = 0.0;
+                    ctx->cnt[p][k] = 0;
+                }
+        return ADR_OK;
+    } catch (const Error &e) {
+        return fail_ctx(ctx, e);
+    }
+}
+
+adr_status adr_destroy(adr_ctx *ctx) {
+    if (!ctx) return ADR_OK;
+    if (ctx->opt.host_only) {
+        delete ctx;
+        return ADR_OK;
+    }
+    (void)hipStreamSynchronize(ctx->st);
+    for (auto &t : ctx->ticks) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (void *p : ctx->owned) (void)hipFree(p);
+    delete ctx;
+    return ADR_OK;
+}
+
+const char *adr_last_error(const adr_ctx *ctx) {
+    if (!ctx) return g_setup_error.c_str();
+    return ctx->err.c_str();
+}
+
+}  // extern "C"

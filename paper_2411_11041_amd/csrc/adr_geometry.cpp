@@ -1,0 +1,563 @@
+// Host-side geometry of the directional diffusion splitting method (FP64):
+// the bounding-box grid (eq. (20)), the domain, the unit fields b and p
+// (Sec. 3), seeding on the inflow sets (eq. (12)), the curve families
+// (eq. (13)-(14)), the per-node line-element data (eq. (17), (19)), the gather
+// stencils (eq. (21)-(23)) and the crossing-record scatter of Sec. 6.
+//
+// Readings where the paper is silent: curves are integrated in arc length with
+// classical RK4 and step h (the finer grid spacing); a step that leaves the
+// closed domain is shortened by 44 bisections and its end projected onto Gamma;
+// a last element shorter than 0.1 h is merged into the previous one.  Seeds
+// sit at mid-increments h of the measure int |n.b| ds on every connected
+// inflow arc (midpoint rule on sub-segments of length <= h/4).  At a grid node
+// the two estimates of the scatter are combined with weights
+// 1 / (dL*dR + (h/10)^2) (the plain average when the brackets are alike).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <memory>
+
+#include "adr_internal.h"
+
+namespace adr {
+namespace {
+
+constexpr double kCeilTol = 1e-9;
+constexpr int kBisect = 44;
+constexpr double kMerge = 0.1;
+constexpr double kNodeMargin = 1e-9;
+constexpr double kEpsW = 0.1;
+
+[[noreturn]] void fail(adr_status c, const std::string &m) { throw Error{c, m}; }
+
+// ---------------------------------------------------------------- domains
+struct Sub {  // boundary sub-segment
+    double x0, y0, x1, y1, xm, ym, nx, ny, len, t0, t1;
+};
+
+struct Domain {
+    virtual ~Domain() = default;
+    virtual bool inside(double x, double y) const = 0;
+    virtual double dist(double x, double y) const = 0;
+    virtual bool exits(double x0, double y0, double x1, double y1) const = 0;
+    virtual void project(double &x, double &y) const = 0;
+    virtual double first_hit(double x0, double y0, double x1, double y1) const = 0;
+    virtual void subsegments(double h, std::vector<Sub> &out) const = 0;
+    virtual void point(const Sub &s, double frac, double &x, double &y) const = 0;
+    double perimeter = 0.0;
+};
+
+struct Polygon final : Domain {
+    std::vector<double> vx, vy;
+    bool is_box = false, convex = true;
+    int m = 0;
+    Polygon(const std::vector<double> &xy, bool box) : is_box(box) {
+        m = static_cast<int>(xy.size() / 2);
+        for (int q = 0; q < m; ++q) { vx.push_back(xy[2 * q]); vy.push_back(xy[2 * q + 1]); }
+        for (int q = 0; q < m; ++q) {
+            int r = (q + 1) % m, s = (q + 2) % m;
+            double ex = vx[r] - vx[q], ey = vy[r] - vy[q];
+            double fx = vx[s] - vx[r], fy = vy[s] - vy[r];
+            if (ex * fy - ey * fx < 0) convex = false;
+            perimeter += std::hypot(ex, ey);
+        }
+    }
+    bool inside(double x, double y) const override {
+        if (is_box) return x > vx[0] && x < vx[2] && y > vy[0] && y < vy[2];
+        bool in = false;
+        for (int q = 0; q < m; ++q) {
+            int r = (q + 1) % m;
+            bool cond = (vy[q] > y) != (vy[r] > y);
+            if (cond) {
+                double xint = vx[q] + (y - vy[q]) * (vx[r] - vx[q]) / (vy[r] - vy[q]);
+                if (x < xint) in = !in;
+            }
+        }
+        return in;
+    }
+    double dist(double x, double y) const override {
+        double best = std::numeric_limits<double>::infinity();
+        for (int q = 0; q < m; ++q) {
+            int r = (q + 1) % m;
+            double ex = vx[r] - vx[q], ey = vy[r] - vy[q];
+            double t = ((x - vx[q]) * ex + (y - vy[q]) * ey) / (ex * ex + ey * ey);
+            t = std::min(1.0, std::max(0.0, t));
+            best = std::min(best, std::hypot(x - (vx[q] + t * ex), y - (vy[q] + t * ey)));
+        }
+        return best;
+    }
+    bool chord_crosses(double x0, double y0, double x1, double y1) const {
+        double dx = x1 - x0, dy = y1 - y0;
+        for (int q = 0; q < m; ++q) {
+            int r = (q + 1) % m;
+            double ex = vx[r] - vx[q], ey = vy[r] - vy[q];
+            double den = dx * ey - dy * ex;
+            if (den == 0) continue;
+            double t = ((vx[q] - x0) * ey - (vy[q] - y0) * ex) / den;
+            double u = ((vx[q] - x0) * dy - (vy[q] - y0) * dx) / den;
+            if (t > 1e-9 && t <= 1.0 && u >= 0.0 && u <= 1.0) return true;
+        }
+        return false;
+    }
+    bool exits(double x0, double y0, double x1, double y1) const override {
+        if (!inside(x1, y1)) return true;
+        return !convex && chord_crosses(x0, y0, x1, y1);
+    }
+    void project(double &x, double &y) const override {
+        double best = std::numeric_limits<double>::infinity(), px = x, py = y;
+        for (int q = 0; q < m; ++q) {
+            int r = (q + 1) % m;
+            double ex = vx[r] - vx[q], ey = vy[r] - vy[q];
+            double t = ((x - vx[q]) * ex + (y - vy[q]) * ey) / (ex * ex + ey * ey);
+            t = std::min(1.0, std::max(0.0, t));
+            double cx = vx[q] + t * ex, cy = vy[q] + t * ey;
+            double dd = std::hypot(x - cx, y - cy);
+            if (dd < best) { best = dd; px = cx; py = cy; }
+        }
+        x = px; y = py;
+    }
+    double first_hit(double x0, double y0, double x1, double y1) const override {
+        double best = 1.0, dx = x1 - x0, dy = y1 - y0;
+        for (int q = 0; q < m; ++q) {
+            int r = (q + 1) % m;
+            double ex = vx[r] - vx[q], ey = vy[r] - vy[q];
+            double den = dx * ey - dy * ex;
+            if (den == 0) continue;
+            double t = ((vx[q] - x0) * ey - (vy[q] - y0) * ex) / den;
+            double u = ((vx[q] - x0) * dy - (vy[q] - y0) * dx) / den;
+            if (t > 0.0 && t <= 1.0 && u >= 0.0 && u <= 1.0 && t < best) best = t;
+        }
+        return best;
+    }
+    void subsegments(double h, std::vector<Sub> &out) const override {
+        for (int q = 0; q < m; ++q) {
+            int r = (q + 1) % m;
+            double ell = std::hypot(vx[r] - vx[q], vy[r] - vy[q]);
+            int K = std::max(1, static_cast<int>(std::ceil(ell / (0.25 * h) - kCeilTol)));
+            double nxo = (vy[r] - vy[q]) / ell, nyo = -(vx[r] - vx[q]) / ell;
+            for (int k = 0; k < K; ++k) {
+                double s0 = static_cast<double>(k) / K, s1 = static_cast<double>(k + 1) / K;
+                Sub s;
+                s.x0 = vx[q] + s0 * (vx[r] - vx[q]); s.y0 = vy[q] + s0 * (vy[r] - vy[q]);
+                s.x1 = vx[q] + s1 * (vx[r] - vx[q]); s.y1 = vy[q] + s1 * (vy[r] - vy[q]);
+                s.xm = 0.5 * (s.x0 + s.x1); s.ym = 0.5 * (s.y0 + s.y1);
+                s.nx = nxo; s.ny = nyo; s.len = ell / K; s.t0 = s.t1 = 0.0;
+                out.push_back(s);
+            }
+        }
+    }
+    void point(const Sub &s, double frac, double &x, double &y) const override {
+        x = s.x0 + frac * (s.x1 - s.x0);
+        y = s.y0 + frac * (s.y1 - s.y0);
+    }
+};
+
+struct Disc final : Domain {
+    double cx, cy, r;
+    Disc(double a, double b, double c) : cx(a), cy(b), r(c) { perimeter = 2.0 * M_PI * r; }
+    bool inside(double x, double y) const override {
+        return (x - cx) * (x - cx) + (y - cy) * (y - cy) < r * r;
+    }
+    double dist(double x, double y) const override { return std::fabs(r - std::hypot(x - cx, y - cy)); }
+    bool exits(double, double, double x1, double y1) const override { return !inside(x1, y1); }
+    void project(double &x, double &y) const override {
+        double dx = x - cx, dy = y - cy, rho = std::hypot(dx, dy);
+        x = cx + r * dx / rho;
+        y = cy + r * dy / rho;
+    }
+    double first_hit(double x0, double y0, double x1, double y1) const override {
+        double dx = x1 - x0, dy = y1 - y0, px = x0 - cx, py = y0 - cy;
+        double A = dx * dx + dy * dy, B = px * dx + py * dy, C = px * px + py * py - r * r;
+        double disc = std::max(B * B - A * C, 0.0);
+        double t = (-B + std::sqrt(disc)) / A;
+        return std::min(1.0, std::max(0.0, t));
+    }
+    void subsegments(double h, std::vector<Sub> &out) const override {
+        int K = std::max(1, static_cast<int>(std::ceil(perimeter / (0.25 * h) - kCeilTol)));
+        for (int k = 0; k < K; ++k) {
+            Sub s;
+            s.t0 = 2.0 * M_PI * k / K;
+            s.t1 = 2.0 * M_PI * (k + 1) / K;
+            double tm = 0.5 * (s.t0 + s.t1);
+            s.x0 = cx + r * std::cos(s.t0); s.y0 = cy + r * std::sin(s.t0);
+            s.x1 = cx + r * std::cos(s.t1); s.y1 = cy + r * std::sin(s.t1);
+            s.xm = cx + r * std::cos(tm); s.ym = cy + r * std::sin(tm);
+            s.nx = std::cos(tm); s.ny = std::sin(tm);
+            s.len = r * 2.0 * M_PI / K;
+            out.push_back(s);
+        }
+    }
+    void point(const Sub &s, double frac, double &x, double &y) const override {
+        double t = s.t0 + frac * (s.t1 - s.t0);
+        x = cx + r * std::cos(t);
+        y = cy + r * std::sin(t);
+    }
+};
+
+// ---------------------------------------------------------------- flow field
+struct Flow {
+    const Grid *g;
+    const double *B1, *B2;
+    // unit direction b (family 0) or p = (b2, -b1) (family 1)
+    void unit(double x, double y, int fam, double &ux, double &uy) const {
+        double b1 = g->interp(B1, x, y), b2 = g->interp(B2, x, y);
+        double n = std::hypot(b1, b2);
+        if (!(n > 0.0)) fail(ADR_EBETA, "|beta| vanishes on a curve: direction b undefined");
+        b1 /= n; b2 /= n;
+        if (fam == 0) { ux = b1; uy = b2; } else { ux = b2; uy = -b1; }
+    }
+    void rk4(double x, double y, double s, int fam, double &ox, double &oy) const {
+        double k1x, k1y, k2x, k2y, k3x, k3y, k4x, k4y;
+        unit(x, y, fam, k1x, k1y);
+        unit(x + 0.5 * s * k1x, y + 0.5 * s * k1y, fam, k2x, k2y);
+        unit(x + 0.5 * s * k2x, y + 0.5 * s * k2y, fam, k3x, k3y);
+        unit(x + s * k3x, y + s * k3y, fam, k4x, k4y);
+        ox = x + s / 6.0 * (k1x + 2.0 * k2x + 2.0 * k3x + k4x);
+        oy = y + s / 6.0 * (k1y + 2.0 * k2y + 2.0 * k3y + k4y);
+    }
+};
+
+// Seeds on the inflow set of family fam (eq. (12)).
+void make_seeds(const Flow &fl, const Domain &dom, int fam, double hperp, std::vector<double> &sx,
+                std::vector<double> &sy) {
+    std::vector<Sub> sub;
+    dom.subsegments(fl.g->h, sub);
+    const int K = static_cast<int>(sub.size());
+    std::vector<double> w(K);
+    bool any = false, all = true;
+    for (int s = 0; s < K; ++s) {
+        double ux, uy;
+        fl.unit(sub[s].xm, sub[s].ym, fam, ux, uy);
+        double q = std::max(0.0, -(sub[s].nx * ux + sub[s].ny * uy));
+        w[s] = q * sub[s].len;
+        if (w[s] > 0) any = true; else all = false;
+    }
+    if (!any) return;
+    if (all) fail(ADR_EBETA, "the whole boundary is an inflow boundary");
+    int start = 0;
+    while (w[start] > 0) ++start;
+    std::vector<int> run;
+    auto flush = [&]() {
+        if (run.empty()) return;
+        std::vector<double> cum(run.size());
+        double acc = 0.0;
+        for (size_t t = 0; t < run.size(); ++t) { acc += w[run[t]]; cum[t] = acc; }
+        const double lam = acc;
+        const int n = static_cast<int>(std::floor(lam / hperp + 0.5));
+        for (int k = 0; k < n; ++k) {
+            double target = (k + 0.5) * lam / n;
+            size_t r = std::lower_bound(cum.begin(), cum.end(), target) - cum.begin();
+            if (r >= run.size()) r = run.size() - 1;
+            double before = r > 0 ? cum[r - 1] : 0.0;
+            double frac = (target - before) / w[run[r]];
+            double px, py;
+            dom.point(sub[run[r]], frac, px, py);
+            sx.push_back(px);
+            sy.push_back(py);
+        }
+        run.clear();
+    };
+    for (int t = 0; t < K; ++t) {
+        int s = (start + t) % K;
+        if (w[s] > 0) run.push_back(s); else flush();
+    }
+    flush();
+}
+
+// Integral curves from the seeds (eq. (13)-(14)).
+void trace(const Flow &fl, const Domain &dom, const std::vector<double> &sx, const std::vector<double> &sy,
+           int fam, double hl, Family &out) {
+    const int64_t max_steps = static_cast<int64_t>(std::ceil(4.0 * dom.perimeter / hl)) + 2;
+    out.off.assign(1, 0);
+    std::vector<double> lx, ly;
+    for (size_t s = 0; s < sx.size(); ++s) {
+        lx.assign(1, sx[s]);
+        ly.assign(1, sy[s]);
+        double cx = sx[s], cy = sy[s];
+        bool closed = false;
+        for (int64_t step = 0; step < max_steps; ++step) {
+            double nx, ny;
+            fl.rk4(cx, cy, hl, fam, nx, ny);
+            if (!dom.exits(cx, cy, nx, ny)) {
+                lx.push_back(nx); ly.push_back(ny);
+                cx = nx; cy = ny;
+                continue;
+            }
+            double lo = 0.0, hi = hl;
+            for (int it = 0; it < kBisect; ++it) {
+                double mid = 0.5 * (lo + hi), mx, my;
+                fl.rk4(cx, cy, mid, fam, mx, my);
+                if (dom.exits(cx, cy, mx, my)) hi = mid; else lo = mid;
+            }
+            double ex, ey;
+            fl.rk4(cx, cy, hi, fam, ex, ey);
+            dom.project(ex, ey);
+            if (std::hypot(ex - cx, ey - cy) < kMerge * hl && lx.size() >= 2) {
+                lx.back() = ex; ly.back() = ey;
+            } else {
+                lx.push_back(ex); ly.push_back(ey);
+            }
+            closed = true;
+            break;
+        }
+        if (!closed) fail(ADR_EBETA, "a curve did not leave the domain within four perimeters");
+        if (lx.size() < 3) continue;  // no interior node
+        out.x.insert(out.x.end(), lx.begin(), lx.end());
+        out.y.insert(out.y.end(), ly.begin(), ly.end());
+        out.off.push_back(static_cast<int64_t>(out.x.size()));
+    }
+}
+
+// ---------------------------------------------------------------- scatter
+struct Crossing {
+    double coord;  // coordinate along the grid line
+    int64_t k;     // first node of the segment
+    double t;      // (1-t) v[k] + t v[k+1]
+};
+
+struct Bracket {
+    int kind;      // 0 line record, 1 boundary point
+    double coord;
+    int64_t k;
+    double t;
+};
+
+void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> &inner,
+                   const std::vector<int32_t> &inner_list, const Family &F, std::vector<Rec4> &out) {
+    const int nx = g.nx, ny = g.ny;
+    // edges of vertical grid lines: line i, edge j (ny-1 per line); horizontal: line j, edge i
+    const int64_t nvE = static_cast<int64_t>(nx) * (ny - 1), nhE = static_cast<int64_t>(ny) * (nx - 1);
+    std::vector<int64_t> vmin(nvE, -1), vmax(nvE, -1), hmin(nhE, -1), hmax(nhE, -1);
+    std::vector<Crossing> vrec, hrec;
+    const int nl = static_cast<int>(F.off.size()) - 1;
+    for (int axis = 0; axis < 2; ++axis) {
+        std::vector<Crossing> &rec = axis == 0 ? vrec : hrec;
+        std::vector<int64_t> &emin = axis == 0 ? vmin : hmin, &emax = axis == 0 ? vmax : hmax;
+        const double org = axis == 0 ? g.a : g.c, hh = axis == 0 ? g.hx : g.hy;
+        const double qorg = axis == 0 ? g.c : g.a, qh = axis == 0 ? g.hy : g.hx;
+        const int nlines = axis == 0 ? nx : ny, nedges = axis == 0 ? ny - 1 : nx - 1;
+        for (int l = 0; l < nl; ++l) {
+            for (int64_t k = F.off[l]; k + 1 < F.off[l + 1]; ++k) {
+                double p0 = axis == 0 ? F.x[k] : F.y[k], p1 = axis == 0 ? F.x[k + 1] : F.y[k + 1];
+                double q0 = axis == 0 ? F.y[k] : F.x[k], q1 = axis == 0 ? F.y[k + 1] : F.x[k + 1];
+                if (p0 == p1) continue;
+                long lo = static_cast<long>(std::floor((std::min(p0, p1) - org) / hh)) - 1;
+                long hi = static_cast<long>(std::ceil((std::max(p0, p1) - org) / hh)) + 1;
+                lo = std::max(0L, std::min<long>(lo, nlines - 1));
+                hi = std::max(0L, std::min<long>(hi, nlines - 1));
+                for (long c = lo; c <= hi; ++c) {
+                    double gl = org + hh * c;
+                    if ((gl - p0) * (gl - p1) > 0.0) continue;
+                    double t = (gl - p0) / (p1 - p0);
+                    double coord = q0 + t * (q1 - q0);
+                    long e = static_cast<long>(std::floor((coord - qorg) / qh));
+                    e = std::max(0L, std::min<long>(e, nedges - 1));
+                    int64_t eid = c * static_cast<int64_t>(nedges) + e;
+                    int64_t id = static_cast<int64_t>(rec.size());
+                    rec.push_back({coord, k, t});
+                    if (emin[eid] < 0 || coord < rec[emin[eid]].coord) emin[eid] = id;
+                    if (emax[eid] < 0 || coord >= rec[emax[eid]].coord) emax[eid] = id;
+                }
+            }
+        }
+    }
+    const double eps2 = (kEpsW * g.h) * (kEpsW * g.h);
+    out.resize(inner_list.size());
+    auto is_in = [&](int i, int j) { return inner[static_cast<size_t>(j) * nx + i] != 0; };
+    for (size_t n = 0; n < inner_list.size(); ++n) {
+        const int gi = inner_list[n] % nx, gj = inner_list[n] / nx;
+        Bracket br[2][2];  // [direction: 0 horizontal, 1 vertical][side: 0 low, 1 high]
+        for (int dir = 0; dir < 2; ++dir) {
+            // dir 0: along row gj (positions i, edges (e, e+1) on horizontal line gj)
+            // dir 1: along column gi
+            const int pos = dir == 0 ? gi : gj;
+            const int nE = dir == 0 ? nx - 1 : ny - 1;
+            const std::vector<int64_t> &emin = dir == 0 ? hmin : vmin, &emax = dir == 0 ? hmax : vmax;
+            const std::vector<Crossing> &rec = dir == 0 ? hrec : vrec;
+            const int64_t base = static_cast<int64_t>(dir == 0 ? gj : gi) * nE;
+            auto node_in = [&](int p) { return dir == 0 ? is_in(p, gj) : is_in(gi, p); };
+            auto coord_of = [&](int p) { return dir == 0 ? g.x(p) : g.y(p); };
+            auto boundary = [&](int nearp, int farp) {
+                double x0 = dir == 0 ? g.x(nearp) : g.x(gi), y0 = dir == 0 ? g.y(gj) : g.y(nearp);
+                double x1 = dir == 0 ? g.x(farp) : g.x(gi), y1 = dir == 0 ? g.y(gj) : g.y(farp);
+                double t = dom.first_hit(x0, y0, x1, y1);
+                return dir == 0 ? x0 + t * (x1 - x0) : y0 + t * (y1 - y0);
+            };
+            // low side: edges e = pos-1, pos-2, ...
+            bool found = false;
+            for (int e = pos - 1; e >= 0 && !found; --e) {
+                int64_t r = emax[base + e];
+                if (r >= 0) {
+                    br[dir][0] = {0, rec[r].coord, rec[r].k, rec[r].t};
+                    found = true;
+                } else if (!node_in(e)) {
+                    br[dir][0] = {1, boundary(e + 1, e), -1, 0.0};
+                    found = true;
+                }
+            }
+            if (!found) fail(ADR_EINVAL, "interior grid node without a bracketing record");
+            found = false;
+            for (int e = pos; e < nE && !found; ++e) {
+                int64_t r = emin[base + e];
+                if (r >= 0) {
+                    br[dir][1] = {0, rec[r].coord, rec[r].k, rec[r].t};
+                    found = true;
+                } else if (!node_in(e + 1)) {
+                    br[dir][1] = {1, boundary(e, e + 1), -1, 0.0};
+                    found = true;
+                }
+            }
+            if (!found) fail(ADR_EINVAL, "interior grid node without a bracketing record");
+            (void)coord_of;
+        }
+        double W[2], cl[2], cr[2];
+        for (int dir = 0; dir < 2; ++dir) {
+            double p = dir == 0 ? g.x(gi) : g.y(gj);
+            double dL = p - br[dir][0].coord, dR = br[dir][1].coord - p;
+            double span = dL + dR;
+            if (span > 0) { cl[dir] = dR / span; cr[dir] = dL / span; }
+            else { cl[dir] = 0.5; cr[dir] = 0.5; }
+            W[dir] = 1.0 / (dL * dR + eps2);
+        }
+        double Wh = W[0] / (W[0] + W[1]);
+        double Ws[2] = {Wh, 1.0 - Wh};
+        Rec4 &R = out[n];
+        for (int dir = 0; dir < 2; ++dir) {
+            for (int side = 0; side < 2; ++side) {
+                int slot = dir * 2 + side;
+                const Bracket &b = br[dir][side];
+                double coef = Ws[dir] * (side == 0 ? cl[dir] : cr[dir]);
+                if (b.kind == 0) {
+                    R.k[slot] = static_cast<int32_t>(b.k);
+                    R.ca[slot] = coef * (1.0 - b.t);
+                    R.cb[slot] = coef * b.t;
+                } else {  // boundary point: zero Dirichlet value
+                    R.k[slot] = -1;
+                    R.ca[slot] = 0.0;
+                    R.cb[slot] = 0.0;
+                }
+            }
+        }
+    }
+}
+
+bool finite_all(const double *p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+void Grid::cell(double px, double py, int &i, int &j, double &lx, double &ly) const {
+    double X = (px - a) / hx, Y = (py - c) / hy;
+    double fi = std::floor(X), fj = std::floor(Y);
+    fi = std::min(static_cast<double>(nx - 2), std::max(0.0, fi));
+    fj = std::min(static_cast<double>(ny - 2), std::max(0.0, fj));
+    i = static_cast<int>(fi);
+    j = static_cast<int>(fj);
+    lx = X - fi;
+    ly = Y - fj;
+}
+
+double Grid::interp(const double *F, double px, double py) const {
+    int i, j;
+    double lx, ly;
+    cell(px, py, i, j, lx, ly);
+    const double *r0 = F + static_cast<size_t>(j) * nx, *r1 = r0 + nx;
+    return (1 - ly) * (1 - lx) * r0[i] + (1 - ly) * lx * r0[i + 1] + ly * (1 - lx) * r1[i] + ly * lx * r1[i + 1];
+}
+
+void build_instance(const adr_problem &p, InstanceGeo &G) {
+    if (p.nx < 3 || p.ny < 3) fail(ADR_EINVAL, "nx and ny must be >= 3");
+    if (!(p.b > p.a) || !(p.d > p.c)) fail(ADR_EINVAL, "empty bounding box");
+    if (!(p.mu > 0.0)) fail(ADR_EINVAL, "mu must be > 0");
+    if (!(p.sigma >= 0.0)) fail(ADR_EINVAL, "sigma must be >= 0");
+    if (!p.beta1 || !p.beta2 || !p.f) fail(ADR_EINVAL, "beta1, beta2 and f are required");
+    const size_t nn = static_cast<size_t>(p.nx) * p.ny;
+    if (nn > (1u << 30)) fail(ADR_EINVAL, "grid too large");
+    if (!finite_all(p.beta1, nn) || !finite_all(p.beta2, nn) || !finite_all(p.f, nn))
+        fail(ADR_ENONFINITE, "non-finite beta or f");
+    Grid &g = G.g;
+    g.a = p.a; g.b = p.b; g.c = p.c; g.d = p.d; g.nx = p.nx; g.ny = p.ny;
+    g.hx = (p.b - p.a) / (p.nx - 1);
+    g.hy = (p.d - p.c) / (p.ny - 1);
+    g.h = std::min(g.hx, g.hy);
+    G.mu = p.mu;
+    G.sigma = p.sigma;
+
+    std::unique_ptr<Domain> dom;
+    if (p.domain == ADR_DOM_BOX) {
+        dom.reset(new Polygon({p.a, p.c, p.b, p.c, p.b, p.d, p.a, p.d}, true));
+    } else if (p.domain == ADR_DOM_DISC) {
+        if (p.n_dom_params != 3 || !p.dom_params || !(p.dom_params[2] > 0))
+            fail(ADR_EINVAL, "disc needs cx, cy, r > 0");
+        dom.reset(new Disc(p.dom_params[0], p.dom_params[1], p.dom_params[2]));
+    } else if (p.domain == ADR_DOM_POLYGON) {
+        if (p.n_dom_params < 6 || (p.n_dom_params % 2) || !p.dom_params)
+            fail(ADR_EINVAL, "polygon needs >= 3 vertices");
+        dom.reset(new Polygon(std::vector<double>(p.dom_params, p.dom_params + p.n_dom_params), false));
+    } else {
+        fail(ADR_EINVAL, "unknown domain kind");
+    }
+
+    G.inner.assign(nn, 0);
+    G.inner_list.clear();
+    for (int j = 0; j < p.ny; ++j)
+        for (int i = 0; i < p.nx; ++i) {
+            double x = g.x(i), y = g.y(j);
+            if (dom->inside(x, y) && dom->dist(x, y) > kNodeMargin * g.h) {
+                G.inner[static_cast<size_t>(j) * p.nx + i] = 1;
+                G.inner_list.push_back(j * p.nx + i);
+            }
+        }
+
+    Flow fl{&g, p.beta1, p.beta2};
+    for (int fam = 0; fam < 2; ++fam) {
+        std::vector<double> sx, sy;
+        make_seeds(fl, *dom, fam, g.h, sx, sy);
+        trace(fl, *dom, sx, sy, fam, g.h, G.fam[fam]);
+        const Family &F = G.fam[fam];
+        if (F.off.size() < 2)
+            fail(ADR_EBETA, fam == 0 ? "no beta-curve enters the domain (closed streamlines?)"
+                                     : "no gamma-curve enters the domain");
+        const size_t n = F.x.size();
+        G.hk[fam].assign(n, 0.0);
+        G.cellk[fam].assign(n, -1);
+        G.lxk[fam].assign(n, 0.0);
+        G.lyk[fam].assign(n, 0.0);
+        const int nl = static_cast<int>(F.off.size()) - 1;
+        for (int l = 0; l < nl; ++l) {
+            for (int64_t k = F.off[l]; k < F.off[l + 1]; ++k) {
+                if (k > F.off[l]) G.hk[fam][k] = std::hypot(F.x[k] - F.x[k - 1], F.y[k] - F.y[k - 1]);
+                if (k > F.off[l] && k + 1 < F.off[l + 1]) {
+                    int ci, cj;
+                    double lx, ly;
+                    g.cell(F.x[k], F.y[k], ci, cj, lx, ly);
+                    G.cellk[fam][k] = cj * p.nx + ci;
+                    G.lxk[fam][k] = lx;
+                    G.lyk[fam][k] = ly;
+                }
+            }
+        }
+        if (fam == 0) {
+            G.wk.assign(n, 0.0);
+            G.Lk.assign(n, 0.0);
+            std::vector<double> fk(n);
+            for (size_t k = 0; k < n; ++k) {
+                double b1 = g.interp(p.beta1, F.x[k], F.y[k]), b2 = g.interp(p.beta2, F.x[k], F.y[k]);
+                G.wk[k] = std::hypot(b1, b2);
+                fk[k] = g.interp(p.f, F.x[k], F.y[k]);
+            }
+            for (int l = 0; l < nl; ++l)
+                for (int64_t k = F.off[l] + 1; k + 1 < F.off[l + 1]; ++k) {
+                    double hl = G.hk[0][k], hr = G.hk[0][k + 1];
+                    G.Lk[k] = (hl + hr) / 3.0 * fk[k] + hl / 6.0 * fk[k - 1] + hr / 6.0 * fk[k + 1];
+                }
+        }
+        build_scatter(g, *dom, G.inner, G.inner_list, F, G.rec[fam]);
+    }
+}
+
+}  // namespace adr

@@ -1,0 +1,61 @@
+// Internal declarations of the directional diffusion splitting library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/adr.h"
+
+namespace adr {
+
+// Error carrier used inside the library; converted to adr_status at the ABI.
+struct Error {
+    adr_status code;
+    std::string msg;
+};
+
+// Rectangular mesh over the bounding box (eq. (20)).
+struct Grid {
+    double a, b, c, d, hx, hy, h;
+    int nx, ny;
+    double x(int i) const { return a + hx * i; }
+    double y(int j) const { return c + hy * j; }
+    // eq. (21)/(23): 0-based floor clamped to the last cell, y index from y.
+    void cell(double px, double py, int &i, int &j, double &lx, double &ly) const;
+    // eq. (22): bilinear value of a nodal field.
+    double interp(const double *F, double px, double py) const;
+};
+
+// One traced family of curves (polylines).
+struct Family {
+    std::vector<int64_t> off;   // line l: nodes off[l] .. off[l+1]-1
+    std::vector<double> x, y;
+};
+
+// One scatter record: value = ca * v[k] + cb * v[k+1] (k = -1: unused).
+struct Rec4 {
+    int32_t k[4];
+    double ca[4], cb[4];
+};
+
+// Everything the device needs for one instance, in local indices.
+struct InstanceGeo {
+    Grid g;
+    double mu, sigma;
+    std::vector<uint8_t> inner;        // nx*ny interior-node mask
+    std::vector<int32_t> inner_list;   // local grid indices of interior nodes
+    Family fam[2];
+    // per family, per node
+    std::vector<double> hk[2];         // chord to the previous node (0 at a line start)
+    std::vector<int32_t> cellk[2];     // bottom-left corner (local grid index), -1 at line ends
+    std::vector<double> lxk[2], lyk[2];
+    std::vector<double> wk;            // beta family: |beta| at the node
+    std::vector<double> Lk;            // beta family: load int f phi_k (0 at ends)
+    std::vector<Rec4> rec[2];          // per interior node (inner_list order)
+};
+
+// Builds the geometry of one instance; throws Error.
+void build_instance(const adr_problem &p, InstanceGeo &out);
+
+}  // namespace adr

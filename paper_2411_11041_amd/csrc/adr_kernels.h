@@ -1,0 +1,48 @@
+// Device-side argument blocks and kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace adr {
+
+// Line data of one family (all instances concatenated).
+template <typename T>
+struct LineArgs {
+    const int *loff;     // first node of line
+    const int *lcnt;     // nodes of line (including the two Dirichlet ends)
+    const int *linst;    // instance of line
+    const int *inst_nx;  // grid width per instance
+    const int *cell;     // per node: global index of the bottom-left cell corner (-1 at ends)
+    const T *lx, *ly;    // per node: offsets in the cell (eq. (23))
+    const T *h;          // per node: chord to the previous node
+    const T *w;          // per node: |beta| (beta family only)
+    const T *L;          // per node: load int f phi (beta family only)
+};
+
+// Scatter stencils of one family; slot s < npad (padded per instance to 256).
+template <typename T>
+struct ScatterArgs {
+    const int *gidx;      // global grid index of the interior node, -1 for padding
+    const int *blk_inst;  // instance of each 256-slot block
+    const int *rk;        // [4][npad] first node of the record's segment, -1 unused
+    const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1]
+    int npad;
+};
+
+template <typename T>
+size_t line_lds_bytes(int nmax);
+
+template <typename T>
+hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
+                       const int *done, int nmax, hipStream_t st);
+
+template <typename T, typename TO>
+hipError_t launch_scatter(int mode, const ScatterArgs<T> &s, const T *v, TO *out, float *d32, double *partial,
+                          const int *done, hipStream_t st);
+
+hipError_t launch_norm(int n_inst, const double *partial, const int *blk_start, double *cnorm, double *rel, int *done,
+                       int *conv_it, int sweep, double tol, int mode, hipStream_t st);
+
+hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st);
+
+}  // namespace adr

@@ -1,0 +1,357 @@
+// gfx950 kernels of the directional diffusion splitting sweep (eq. (10)).
+//
+//  k_line     one workgroup (256 threads) per curve: gathers the grid field at
+//             the curve's nodes (bilinear, eq. (21)-(23)), assembles the P1
+//             rows of eq. (16)-(19) in LDS and solves the tridiagonal system
+//             by a partitioned elimination: every thread eliminates a
+//             contiguous chunk of rows, the chunk separators form a reduced
+//             tridiagonal system that is solved by parallel cyclic reduction
+//             in LDS, then every thread back-substitutes its chunk.
+//  k_scatter  one thread per interior grid node: the crossing-record
+//             interpolation of Sec. 6, a fixed 4-record stencil per node.
+//  k_norm     per-instance FP64 reduction of the update norm (fixed order).
+//
+// All kernels early-exit for instances whose done flag is set, so a batch
+// of instances shares every launch.
+#include <hip/hip_runtime.h>
+
+#include "adr_kernels.h"
+
+namespace adr {
+
+constexpr int kThreads = 256;
+
+template <typename T>
+__device__ inline T bilinear(const T *__restrict__ F, int cell, int nx, T lx, T ly) {
+    const T p11 = F[cell], p12 = F[cell + 1], p21 = F[cell + nx], p22 = F[cell + nx + 1];
+    return (T(1) - ly) * ((T(1) - lx) * p11 + lx * p12) + ly * ((T(1) - lx) * p21 + lx * p22);
+}
+
+template <typename T, int FAM>
+__global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
+                                                   T *__restrict__ vout, const double *__restrict__ par,
+                                                   const int *__restrict__ done, int nmax) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *U = reinterpret_cast<T *>(smem_raw);
+    T *A = U + nmax;
+    T *B = A + nmax;
+    T *C = B + nmax;
+    T *D = C + nmax;
+    T *RA = D + nmax;
+    T *RB = RA + kThreads;
+    T *RC = RB + kThreads;
+    T *RD = RC + kThreads;
+    T *FY = RD + kThreads;
+    T *FA = FY + kThreads;
+    T *FG = FA + kThreads;
+
+    const int l = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int inst = a.linst[l];
+    if (done[inst]) return;
+    const int o = a.loff[l];
+    const int n = a.lcnt[l];
+    const int N = n - 2;
+    const int nx = a.inst_nx[inst];
+    const double *pp = par + 8 * inst;
+    const T cM = T(pp[0]), cK = T(pp[1]), cC = T(pp[2]);
+    const T eM = T(pp[3]), eK = T(pp[4]), eC = T(pp[5]), eL = T(pp[6]);
+
+    // 1. gather the field at the nodes (ends carry the zero Dirichlet value)
+    for (int j = tid; j < n; j += kThreads) {
+        T u = T(0);
+        if (j > 0 && j < n - 1) {
+            const int k = o + j;
+            u = bilinear(fin, a.cell[k], nx, a.lx[k], a.ly[k]);
+        }
+        U[j] = u;
+    }
+    __syncthreads();
+
+    // 2. rows r = 0..N-1 (node j = r + 1) of  A x = rhs
+    const T sixth = T(1) / T(6), third = T(1) / T(3);
+    for (int r = tid; r < N; r += kThreads) {
+        const int k = o + r + 1;
+        const T hl = a.h[k], hr = a.h[k + 1];
+        const T mlo = hl * sixth, mdi = (hl + hr) * third, mup = hr * sixth;
+        const T il = T(1) / hl, ir = T(1) / hr;
+        const T klo = -il, kdi = il + ir, kup = -ir;
+        const T um = U[r], u0 = U[r + 1], up = U[r + 2];
+        T lo = cM * mlo + cK * klo;
+        T di = cM * mdi + cK * kdi;
+        T hi = cM * mup + cK * kup;
+        T rhs = eM * (mlo * um + mdi * u0 + mup * up) + eK * (klo * um + kdi * u0 + kup * up);
+        if (FAM == 0) {
+            const T wm = a.w[k - 1], w0 = a.w[k], wp = a.w[k + 1];
+            const T clo = -(wm + T(2) * w0) * sixth;
+            const T cdi = (wm - wp) * sixth;
+            const T cup = (T(2) * w0 + wp) * sixth;
+            lo += cC * clo;
+            di += cC * cdi;
+            hi += cC * cup;
+            rhs += eC * (clo * um + cdi * u0 + cup * up) + eL * a.L[k];
+        }
+        A[r] = lo;
+        B[r] = di;
+        C[r] = hi;
+        D[r] = rhs;
+    }
+    __syncthreads();
+
+    // 3. chunked elimination
+    const int m = (N + kThreads - 1) / kThreads;
+    const int Q = (N + m - 1) / m;  // non-empty chunks
+    const int q = tid;
+    int i0 = 0, i1 = -1, sep = -1;
+    T yL = T(0), aL = T(1), gL = T(0);  // last interior row = yL + aL*S_{q-1} + gL*S_q
+    if (q < Q) {
+        const int rs = q * m;
+        const int re = min(rs + m, N) - 1;
+        const bool has_sep = q < Q - 1;
+        i0 = rs;
+        i1 = has_sep ? re - 1 : re;
+        sep = has_sep ? re : -1;
+        T pc = T(0), py = T(0), pa = T(0);
+        for (int r = i0; r <= i1; ++r) {
+            const T ar = A[r];
+            const T inv = T(1) / (B[r] - ar * pc);
+            const T cp = C[r] * inv;
+            const T yp = (D[r] - ar * py) * inv;
+            const T al = (r == i0 ? -ar : -ar * pa) * inv;
+            C[r] = cp;
+            D[r] = yp;
+            A[r] = al;
+            pc = cp;
+            py = yp;
+            pa = al;
+        }
+        T fy = T(0), fa = T(0), fg = T(1);  // empty chunk: its first row is its separator
+        if (i1 >= i0) {
+            T Y = D[i1], Al = A[i1], Ga = -C[i1];
+            yL = Y; aL = Al; gL = Ga;
+            for (int r = i1 - 1; r >= i0; --r) {
+                const T cp = C[r];
+                Y = D[r] - cp * Y;
+                Al = A[r] - cp * Al;
+                Ga = -cp * Ga;
+            }
+            fy = Y; fa = Al; fg = Ga;
+        }
+        FY[q] = fy;
+        FA[q] = fa;
+        FG[q] = fg;
+    }
+    __syncthreads();
+
+    // 4. reduced system on the separators S_0..S_{Q-2}, PCR in LDS
+    const int R = Q - 1;
+    {
+        T ra = T(0), rb = T(1), rc = T(0), rd = T(0);
+        if (q < R) {
+            const T as = A[sep], bs = B[sep], cs = C[sep], ds = D[sep];
+            const T nfy = FY[q + 1], nfa = FA[q + 1], nfg = FG[q + 1];
+            ra = q > 0 ? as * aL : T(0);
+            rb = bs + as * gL + cs * nfa;
+            rc = q + 1 < R ? cs * nfg : T(0);
+            rd = ds - as * yL - cs * nfy;
+        }
+        if (q < kThreads) {
+            RA[q] = ra; RB[q] = rb; RC[q] = rc; RD[q] = rd;
+        }
+        __syncthreads();
+        for (int s = 1; s < R; s <<= 1) {
+            T na = ra, nb = rb, nc = rc, nd = rd;
+            if (q < R) {
+                T la = T(0), lb = T(1), lc = T(0), ld = T(0);
+                T ua = T(0), ub = T(1), uc = T(0), ud = T(0);
+                if (q - s >= 0) { la = RA[q - s]; lb = RB[q - s]; lc = RC[q - s]; ld = RD[q - s]; }
+                if (q + s < R) { ua = RA[q + s]; ub = RB[q + s]; uc = RC[q + s]; ud = RD[q + s]; }
+                const T k1 = ra / lb, k2 = rc / ub;
+                na = -la * k1;
+                nc = -uc * k2;
+                nb = rb - lc * k1 - ua * k2;
+                nd = rd - ld * k1 - ud * k2;
+            }
+            __syncthreads();
+            ra = na; rb = nb; rc = nc; rd = nd;
+            RA[q] = ra; RB[q] = rb; RC[q] = rc; RD[q] = rd;
+            __syncthreads();
+        }
+        if (q < R) RD[q] = rd / rb;  // S_q
+        __syncthreads();
+    }
+
+    // 5. back-substitution of every chunk; results go to U[r + 1]
+    if (q < Q) {
+        const T SL = q > 0 ? RD[q - 1] : T(0);
+        const T SR = q < R ? RD[q] : T(0);
+        if (i1 >= i0) {
+            T x = D[i1] + A[i1] * SL - C[i1] * SR;
+            U[i1 + 1] = x;
+            for (int r = i1 - 1; r >= i0; --r) {
+                x = D[r] + A[r] * SL - C[r] * x;
+                U[r + 1] = x;
+            }
+        }
+        if (sep >= 0) U[sep + 1] = SR;
+    }
+    __syncthreads();
+    for (int j = tid; j < n; j += kThreads) vout[o + j] = (j == 0 || j == n - 1) ? T(0) : U[j];
+}
+
+// Scatter: out = P v on the interior nodes.  MODE 0: write; MODE 1 (FP64 sweep):
+// U <- val, d32 <- val - U_old, partial += (val - U_old)^2; MODE 2 (FP32 sweep):
+// U += val, d32 <- val; MODE 3: partial += (val - U)^2, nothing written.
+template <typename T, typename TO, int MODE>
+__global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T *__restrict__ v,
+                                                      TO *__restrict__ out, float *__restrict__ d32,
+                                                      double *__restrict__ partial,
+                                                      const int *__restrict__ done) {
+    const int blk = blockIdx.x;
+    const int inst = s.blk_inst[blk];
+    if (done[inst]) return;
+    const int slot = blk * kThreads + threadIdx.x;
+    const int g = s.gidx[slot];
+    const int np = s.npad;
+    T val = T(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = s.rk[r * np + slot];
+        if (k >= 0) val += s.ra[r * np + slot] * v[k] + s.rb[r * np + slot] * v[k + 1];
+    }
+    if constexpr (MODE == 0) {
+        if (g >= 0) out[g] = TO(val);
+    } else if constexpr (MODE == 2) {
+        if (g >= 0) {
+            out[g] = out[g] + TO(val);
+            d32[g] = float(val);
+        }
+    } else {
+        double r = 0.0;
+        if (g >= 0) {
+            const double old = double(out[g]);
+            r = double(val) - old;
+            if constexpr (MODE == 1) {
+                out[g] = TO(val);
+                d32[g] = float(r);
+            }
+        }
+        // fixed-order block reduction of r^2
+        __shared__ double red[kThreads];
+        red[threadIdx.x] = r * r;
+        __syncthreads();
+        for (int w = kThreads / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[blk] = red[0];
+    }
+}
+
+// Per-instance norm.  mode 0: rel = sqrt(sum)/cnorm, record, set done at tol.
+// mode 1: cnorm = sqrt(sum).  mode 2: rel only (no flags).
+__global__ __launch_bounds__(kThreads) void k_norm(const double *__restrict__ partial,
+                                                   const int *__restrict__ blk_start, double *__restrict__ cnorm,
+                                                   double *__restrict__ rel, int *__restrict__ done,
+                                                   int *__restrict__ conv_it, int sweep, double tol, int mode) {
+    const int inst = blockIdx.x;
+    if (mode == 0 && done[inst]) return;
+    const int b0 = blk_start[inst], b1 = blk_start[inst + 1];
+    double acc = 0.0;
+    for (int b = b0 + threadIdx.x; b < b1; b += kThreads) acc += partial[b];
+    __shared__ double red[kThreads];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    const double nrm = sqrt(red[0]);
+    if (mode == 1) {
+        cnorm[inst] = nrm;
+        return;
+    }
+    const double cn = cnorm[inst] > 0.0 ? cnorm[inst] : 1.0;
+    const double r = nrm / cn;
+    rel[inst] = r;
+    if (mode == 0) {
+        conv_it[inst] = sweep + 1;
+        if (!(r <= tol)) return;  // NaN never converges
+        done[inst] = 1;
+    }
+}
+
+__global__ void k_fill_int(int *p, int v, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------------ launchers
+template <typename T>
+size_t line_lds_bytes(int nmax) {
+    return sizeof(T) * (5 * static_cast<size_t>(nmax) + 7 * kThreads);
+}
+
+template <typename T>
+hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
+                       const int *done, int nmax, hipStream_t st) {
+    if (n_lines == 0) return hipSuccess;
+    const size_t lds = line_lds_bytes<T>(nmax);
+    if (lds > 64 * 1024) {
+        // allow the large dynamic LDS footprint of long curves (gfx950: 160 KB per CU)
+        if (fam == 0)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 0>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        else
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 1>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    }
+    if (fam == 0)
+        hipLaunchKernelGGL((k_line<T, 0>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
+    else
+        hipLaunchKernelGGL((k_line<T, 1>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
+    return hipGetLastError();
+}
+
+template <typename T, typename TO>
+hipError_t launch_scatter(int mode, const ScatterArgs<T> &s, const T *v, TO *out, float *d32, double *partial,
+                          const int *done, hipStream_t st) {
+    const int nb = s.npad / kThreads;
+    if (nb == 0) return hipSuccess;
+    switch (mode) {
+        case 0: hipLaunchKernelGGL((k_scatter<T, TO, 0>), dim3(nb), dim3(kThreads), 0, st, s, v, out, d32, partial, done); break;
+        case 1: hipLaunchKernelGGL((k_scatter<T, TO, 1>), dim3(nb), dim3(kThreads), 0, st, s, v, out, d32, partial, done); break;
+        case 2: hipLaunchKernelGGL((k_scatter<T, TO, 2>), dim3(nb), dim3(kThreads), 0, st, s, v, out, d32, partial, done); break;
+        default: hipLaunchKernelGGL((k_scatter<T, TO, 3>), dim3(nb), dim3(kThreads), 0, st, s, v, out, d32, partial, done); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_norm(int n_inst, const double *partial, const int *blk_start, double *cnorm, double *rel, int *done,
+                       int *conv_it, int sweep, double tol, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm, dim3(n_inst), dim3(kThreads), 0, st, partial, blk_start, cnorm, rel, done, conv_it,
+                       sweep, tol, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
+    return hipGetLastError();
+}
+
+template size_t line_lds_bytes<double>(int);
+template size_t line_lds_bytes<float>(int);
+template hipError_t launch_line<double>(int, const LineArgs<double> &, int, const double *, double *, const double *,
+                                        const int *, int, hipStream_t);
+template hipError_t launch_line<float>(int, const LineArgs<float> &, int, const float *, float *, const double *,
+                                       const int *, int, hipStream_t);
+template hipError_t launch_scatter<double, double>(int, const ScatterArgs<double> &, const double *, double *,
+                                                   float *, double *, const int *, hipStream_t);
+template hipError_t launch_scatter<float, float>(int, const ScatterArgs<float> &, const float *, float *, float *,
+                                                 double *, const int *, hipStream_t);
+template hipError_t launch_scatter<float, double>(int, const ScatterArgs<float> &, const float *, double *, float *,
+                                                  double *, const int *, hipStream_t);
+
+}  // namespace adr

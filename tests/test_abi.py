@@ -1,0 +1,83 @@
+"""The C-ABI library: it loads, exports every symbol of include/adr.h, and its
+host-side geometry (adr_setup with host_only) reproduces the oracle's curves."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import geometry as geo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "adr.h")).read()
+    return sorted(set(re.findall(r"\b(adr_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_header_symbol():
+    from paper_2411_11041_amd import adr
+    lib = adr.load()
+    syms = header_symbols()
+    assert "adr_setup" in syms and "adr_split_iterate" in syms
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(adr.EXPORTS) == set(syms)
+
+
+@pytest.mark.parametrize("maker", [lambda: W.c1(65), lambda: W.c2(129), lambda: W.data2d(31),
+                                   lambda: W.c4_instance(0, n_max=120), lambda: W.c4_instance(1, n_max=120),
+                                   lambda: W.c5_sample(3, n=65)])
+def test_host_geometry_matches_oracle(maker):
+    from paper_2411_11041_amd.adr import Solver
+    p = maker()
+    s = Solver(p, host_only=True)
+    g = geo.Grid(p.box, p.nx, p.ny)
+    dom = geo.make_domain(p.domain, p.dom_params, p.box)
+    fams = geo.build_families(g, dom, geo.Flow(g, p.beta1, p.beta2))
+    for f in (0, 1):
+        off, x, y = s.export_lines(0, f)
+        assert np.array_equal(off, fams[f].offsets)
+        assert np.max(np.abs(x - fams[f].x)) < 1e-12
+        assert np.max(np.abs(y - fams[f].y)) < 1e-12
+    c = s.counts()
+    assert c["grid_unknowns"] == int(geo.interior_mask(g, dom).sum())
+    assert c["lines_b"] == fams[0].n_lines
+    s.close()
+
+
+def test_setup_errors():
+    from paper_2411_11041_amd.adr import ADRError, Solver, ADR_EINVAL, ADR_ENONFINITE, ADR_EBETA
+    p = W.c1(17)
+    p.mu = 0.0
+    with pytest.raises(ADRError) as e:
+        Solver(p, host_only=True)
+    assert e.value.code == ADR_EINVAL
+    p = W.c1(17)
+    p.f = p.f.copy()
+    p.f[3, 3] = np.nan
+    with pytest.raises(ADRError) as e:
+        Solver(p, host_only=True)
+    assert e.value.code == ADR_ENONFINITE
+    # a stagnation point: beta = 0 on the curves
+    p = W.c1(17)
+    p.beta1 = np.zeros_like(p.beta1)
+    p.beta2 = np.zeros_like(p.beta2)
+    with pytest.raises(ADRError) as e:
+        Solver(p, host_only=True)
+    assert e.value.code == ADR_EBETA
+    # closed streamlines: solid rotation in a disc about its centre has no inflow
+    p = W.c1(17)
+    X, Y = p.coords()
+    p.beta1, p.beta2 = -(Y - 0.5), (X - 0.5)
+    p.domain, p.dom_params = W.DOM_DISC, (0.5, 0.5, 0.45)
+    with pytest.raises(ADRError) as e:
+        Solver(p, host_only=True)
+    assert e.value.code in (ADR_EBETA,)
+    p = W.c1(17)
+    with pytest.raises(ADRError):
+        Solver(p, theta=0.0, host_only=True)
+    with pytest.raises(ADRError):
+        Solver(p, dt=-1.0, host_only=True)

@@ -1,0 +1,168 @@
+"""HIP path vs the FP64 oracle, element by element, through the C ABI.
+
+Tolerances: FP64 mode 1e-11 relative (iterate by iterate: same geometry, same
+sweep sequence); FP32 line solves with the FP64 state and residual: 1e-5
+relative L2 on the converged solution.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.method import Oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, np.float64)).cuda()
+
+
+def rel_l2(a, b, mask=None):
+    if mask is not None:
+        a, b = a[mask], b[mask]
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_11041_amd import adr
+    adr.load()
+
+
+def solver(p, **kw):
+    from paper_2411_11041_amd.adr import Solver
+    return Solver(p, **kw)
+
+
+@pytest.mark.parametrize("sweeps", [1, 3, 12])
+def test_fp64_sweeps_match_oracle_c1(sweeps):
+    print(f"[case] c1 65 fp64 sweeps={sweeps}", flush=True)
+    p = W.c1(65)
+    o = Oracle(p)
+    s = solver(p, precision="fp64", theta=1.0, dt=0.05)
+    u = dev(o.zero_field())
+    iters, rel, st = s.split_iterate(u, sweeps, 0.0)
+    torch.cuda.synchronize()
+    U = o.zero_field()
+    for _ in range(sweeps):
+        U = o.step(U, 1.0, 0.05)
+    assert iters[0] == sweeps
+    assert rel_l2(u.cpu().numpy(), U) < 1e-11
+    s.close()
+
+
+def test_fp64_converged_and_residual_c1():
+    print("[case] c1 65 fp64 converged", flush=True)
+    p = W.c1(65)
+    o = Oracle(p)
+    s = solver(p, precision="fp64", theta=1.0, dt=0.05)
+    u = dev(o.zero_field())
+    iters, rel, st = s.split_iterate(u, 400, 1e-10)
+    Uo, ito, relo, _ = o.iterate(o.zero_field(), 1.0, 0.05, 400, 1e-10)
+    assert st == 0 and rel[0] <= 1e-10
+    assert abs(int(iters[0]) - ito) <= 1
+    assert rel_l2(u.cpu().numpy(), Uo) < 1e-9
+    # adr_residual of the oracle's iterate equals the oracle's own measure
+    r = s.residual(dev(Uo))
+    assert abs(r[0] - o.rel_residual(Uo, 1.0, 0.05)) <= 1e-6 * r[0] + 1e-15
+    s.close()
+
+
+@pytest.mark.parametrize("name,maker", [("c1_65", lambda: W.c1(65)), ("c2_257", lambda: W.c2(257))])
+def test_fp32_lines_converged(name, maker):
+    print(f"[case] {name} fp32 lines converged", flush=True)
+    p = maker()
+    o = Oracle(p)
+    s = solver(p, precision="fp32", fp32_sweeps=3, theta=1.0, dt=0.05)
+    u = dev(o.zero_field())
+    iters, rel, st = s.split_iterate(u, 2000, 1e-10)
+    assert st == 0 and rel[0] <= 1e-10
+    Uo, ito, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 2000, 1e-12)
+    assert rel_l2(u.cpu().numpy(), Uo) < 1e-5
+    s.close()
+
+
+def test_time_march_c3_small():
+    print("[case] c3 129 time march 10 steps fp64", flush=True)
+    p = W.c3(129)
+    o = Oracle(p)
+    s = solver(p, precision="fp64")
+    u0 = p.u0.ravel() * o.mask.ravel()
+    u = dev(u0)
+    s.time_step(u, 1.0, 0.005, 10)
+    torch.cuda.synchronize()
+    U = o.march(u0, 1.0, 0.005, 10)
+    assert rel_l2(u.cpu().numpy(), U) < 1e-11
+    s.close()
+
+
+def test_data2d_paper_experiment():
+    """Sec. 7 set-up: eq. (11) start, theta = 1/2, 50 steps of dt = 0.001."""
+    print("[case] data2d 61 theta=0.5 50 steps", flush=True)
+    p = W.data2d(61)
+    o = Oracle(p)
+    s = solver(p, precision="fp64")
+    u = dev(o.zero_field())
+    s.initial_guess(u)
+    torch.cuda.synchronize()
+    U0 = o.s_guess()
+    assert rel_l2(u.cpu().numpy(), U0) < 1e-12
+    s.time_step(u, 0.5, 0.001, 50)
+    torch.cuda.synchronize()
+    U = o.march(U0, 0.5, 0.001, 50)
+    assert rel_l2(u.cpu().numpy(), U) < 1e-11
+    s.close()
+
+
+def test_batched_instances_match_oracle():
+    """Disc and L-shape instances of uneven sizes in one context (one launch per
+    kernel for all of them): every instance matches its own oracle."""
+    print("[case] batched c4 x4 fp64 8 sweeps", flush=True)
+    probs = [W.c4_instance(i, n_max=140) for i in range(4)]
+    s = solver(probs, precision="fp64", theta=1.0, dt=0.05)
+    off = s.layout()
+    u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    iters, rel, st = s.split_iterate(u, 8, 0.0)
+    torch.cuda.synchronize()
+    U = u.cpu().numpy()
+    for i, p in enumerate(probs):
+        o = Oracle(p)
+        Ui = o.zero_field()
+        for _ in range(8):
+            Ui = o.step(Ui, 1.0, 0.05)
+        assert rel_l2(U[off[i]:off[i + 1]], Ui) < 1e-11, i
+    s.close()
+
+
+def test_batched_early_exit_per_instance():
+    """Instances converge at different sweeps; a converged one stops changing."""
+    print("[case] batched convergence per instance", flush=True)
+    probs = [W.c1(33), W.c2(65)]
+    s = solver(probs, precision="fp64", theta=1.0, dt=0.05)
+    off = s.layout()
+    u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    iters, rel, st = s.split_iterate(u, 500, 1e-9)
+    assert st == 0 and np.all(rel <= 1e-9)
+    for i, p in enumerate(probs):
+        o = Oracle(p)
+        Ui, it, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 500, 1e-9)
+        assert abs(int(iters[i]) - it) <= 1
+        assert rel_l2(u.cpu().numpy()[off[i]:off[i + 1]], Ui) < 1e-8
+    s.close()
+
+
+def test_deterministic_fp64():
+    print("[case] determinism", flush=True)
+    p = W.c2(129)
+    s = solver(p, precision="fp64")
+    a = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+    b = torch.zeros_like(a)
+    s.split_iterate(a, 7, 0.0)
+    s.split_iterate(b, 7, 0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    s.close()
