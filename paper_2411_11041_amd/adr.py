@@ -57,6 +57,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} not built: run paper_2411_11041_amd/build.py")
+    # torch's HIP runtime must be the one in the process: import it first so
+    # that the library binds to the already loaded runtime
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     i32, i64, dbl, vp = C.c_int32, C.c_int64, C.c_double, C.c_void_p
     P = C.POINTER

@@ -10,6 +10,19 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libadr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+CLANG = os.environ.get("ADR_CLANG", "/opt/rocm/lib/llvm/bin/clang++")
+
+
+def runtime_dir() -> str:
+    """Directory of the HIP runtime library used at run time (torch's)."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        return "/opt/rocm/lib"
+    d = os.path.join(os.path.dirname(spec.origin), "lib")
+    return d if os.path.exists(os.path.join(d, "libamdhip64.so")) else "/opt/rocm/lib"
+
+
 SOURCES = ["adr_geometry.cpp", "adr_kernels.hip", "adr_api.cpp"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # packed FP32 instructions stay off (see the design notes)
@@ -39,7 +52,11 @@ def build(verbose: bool = False) -> str:
         if verbose and lines:
             print("\n".join(lines))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"]
+    # Link against the HIP runtime that torch loads, so that one process holds a
+    # single runtime (torch provides the device memory and streams).
+    rt_dir = runtime_dir()
+    cmd = [CLANG, "-shared", "-fPIC", *objs, "-o", tmp, f"-L{rt_dir}", "-l:libamdhip64.so",
+           f"-Wl,-rpath,{rt_dir}", "-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

@@ -66,9 +66,16 @@ def test_fp64_converged_and_residual_c1():
     assert st == 0 and rel[0] <= 1e-10
     assert abs(int(iters[0]) - ito) <= 1
     assert rel_l2(u.cpu().numpy(), Uo) < 1e-9
-    # adr_residual of the oracle's iterate equals the oracle's own measure
+    # adr_residual equals the oracle's measure.  Near convergence the update is a
+    # difference of nearly equal FP64 numbers, so compare in absolute terms there
+    # (units of |Phi(0)|) and relatively on an unconverged iterate.
     r = s.residual(dev(Uo))
-    assert abs(r[0] - o.rel_residual(Uo, 1.0, 0.05)) <= 1e-6 * r[0] + 1e-15
+    assert abs(r[0] - o.rel_residual(Uo, 1.0, 0.05)) <= 1e-13
+    U5 = o.zero_field()
+    for _ in range(5):
+        U5 = o.step(U5, 1.0, 0.05)
+    r5 = s.residual(dev(U5))
+    assert abs(r5[0] - o.rel_residual(U5, 1.0, 0.05)) <= 1e-11 * r5[0]
     s.close()
 
 
