@@ -1,0 +1,178 @@
+"""Benchmark of the directional diffusion splitting hot path on one MI355X.
+
+Step = one stationary solve (eq. (10) sweeps to the fixed point, Sec. 2 limit)
+of the advection-dominated 2049 x 2049 problem from zero to a relative
+fixed-point residual of 1e-8, FP32 line solves with FP64 state, residual and
+convergence test.  value = line unknowns solved per second (every sweep solves
+one tridiagonal system per curve of both families); ms_per_step is the
+time to the 1e-8 residual.  Inputs are resident in device memory before the
+timed region; set-up (curve tracing, tables, upload) is outside it.
+
+Extra fields: the dominant kernel's roofline (HIP-event durations measured in
+the timed region, algorithmic bytes from the line/grid counts) and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "line-unknowns/s + time-to-1e-8 residual: plain vs batched/warm-start, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic (compulsory) bytes per line unknown of one line-solve pass: node
+# geometry read once (cell index 4 B, two cell offsets, chord; beta family also
+# |beta| and the load), the gathered field value (each grid value is read by
+# about one line node) and the written line value.
+LINE_BYTES = {("fp32", 0): 4 + 4 * 2 + 4 + 4 + 4 + 4 + 4, ("fp32", 1): 4 + 4 * 2 + 4 + 4 + 4,
+              ("fp64", 0): 4 + 8 * 2 + 8 + 8 + 8 + 8 + 8, ("fp64", 1): 4 + 8 * 2 + 8 + 8 + 8}
+# Scatter: per interior grid node 4 records (index 4 B + two weights), the 8
+# line values they reference (each line value is referenced by ~2 nodes: 4 per
+# node) and the written grid value (FP64 update: read+write state, write the
+# FP32 increment).
+SCATTER_BYTES = {("fp32", 2): 4 * (4 + 8) + 4 * 4 + 4, ("fp32", 3): 4 * (4 + 8) + 4 * 4 + 8 + 8 + 4,
+                 ("fp64", 2): 4 * (4 + 16) + 4 * 8 + 8, ("fp64", 3): 4 * (4 + 16) + 4 * 8 + 8 + 8 + 4}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=2049, help="grid nodes per side")
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--fp32-sweeps", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    return ap.parse_args()
+
+
+def kernel_roofline(times, counts):
+    """Dominant kernel class over both precisions; achieved = bytes / time."""
+    best = None
+    for prec in ("fp64", "fp32"):
+        for cls, (ms, cnt) in times[prec].items():
+            if cnt == 0 or cls == "norm":
+                continue
+            if best is None or ms > best[2]:
+                best = (prec, cls, ms, cnt)
+    prec, cls, ms, cnt = best
+    fam = 0 if cls.endswith("beta") else 1
+    if cls.startswith("line"):
+        units = counts["line_unknowns_b" if fam == 0 else "line_unknowns_g"]
+        per = LINE_BYTES[(prec, fam)]
+        kname = f"k_line<{'float' if prec == 'fp32' else 'double'}, {fam}>"
+    else:
+        units = counts["grid_unknowns"]
+        per = SCATTER_BYTES[(prec, 2 if fam == 0 else 3)]
+        kname = "k_scatter"
+    # launches of this class per sweep (one per non-empty length bucket)
+    return dict(prec=prec, cls=cls, kernel=kname, total_ms=ms, launches=cnt, bytes_per_unit=per, units=units)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2411_11041_amd.adr import Solver
+
+    p = W.c2(args.n)
+    t0 = time.time()
+    s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, timing=True)
+    setup_s = time.time() - t0
+    counts = s.counts()
+    per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
+    u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+
+    def solve():
+        u.zero_()
+        return s.split_iterate(u, 5000, args.tol)
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    s.kernel_times("fp64", reset=True)
+    s.kernel_times("fp32", reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sweeps = []
+    for _ in range(args.steps):
+        iters, rel, st = solve()
+        sweeps.append(int(iters[0]))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    times = {pr: s.kernel_times(pr, reset=True) for pr in ("fp64", "fp32")}
+    total_unknowns = per_sweep * sum(sweeps)
+    value = total_unknowns / el
+    ms_step = 1e3 * el / args.steps
+
+    rf = kernel_roofline(times, counts)
+    # bytes per launch: the class processes `units` line unknowns (or grid nodes)
+    # once per sweep of its precision, spread over its per-sweep launches
+    n_sw_prec = sum(1 for k in range(sweeps[0]) if (k % (args.fp32_sweeps + 1) == 0) == (rf["prec"] == "fp64"))
+    launches_per_sweep = rf["launches"] / max(1, n_sw_prec * args.steps)
+    bytes_per_launch = rf["bytes_per_unit"] * rf["units"] / launches_per_sweep
+    avg_launch_s = rf["total_ms"] / rf["launches"] / 1e3
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": rf["kernel"], "avg_launch_us": round(avg_launch_s * 1e6, 2),
+                "bytes_per_launch": int(bytes_per_launch)}
+
+    kernels = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()} for pr in times}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(p, args.cpu_sweeps)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "line-unknowns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 line solves, f64 state/residual", "data": "synthetic",
+        "config": {"workload": f"c2: stationary ADR, unit square {args.n}x{args.n}, mu=1e-3, sigma=1, "
+                               "beta=curl psi, psi=x+0.5y+0.1 sin(pi x) sin(pi y), f=8 seeded Gaussians; "
+                               "eq.(10) sweeps theta=1 dt=0.05 to 1e-8",
+                   "time_to_1e-8_ms": ms_step, "sweeps_per_solve": sweeps[0],
+                   "fp32_sweeps_per_fp64": args.fp32_sweeps, "line_unknowns_per_sweep": per_sweep,
+                   "grid_unknowns": counts["grid_unknowns"], "lines": [counts["lines_b"], counts["lines_g"]],
+                   "setup_s": round(setup_s, 2), "final_rel": float(rel[0]), "kernels": kernels},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
+def cpu_baseline(p, sweeps):
+    """FP64 oracle (as it stands) on the same problem: `sweeps` sweeps, timed."""
+    import numpy as np
+    from oracle.method import Oracle
+    t0 = time.time()
+    o = Oracle(p)
+    setup = time.time() - t0
+    per = int(sum(int(f.interior().sum()) for f in o.fams))
+    U = o.zero_field()
+    t0 = time.perf_counter()
+    for _ in range(sweeps):
+        U = o.step(U, 1.0, 0.05)
+    el = time.perf_counter() - t0
+    return {"value": per * sweeps / el, "unit": "line-unknowns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sweeps} FP64 sweeps of the same {p.nx}x{p.ny} problem "
+                      f"(oracle set-up {setup:.0f} s not timed; numpy/scipy, single thread)",
+            "s_per_sweep": el / sweeps}
+
+
+if __name__ == "__main__":
+    main()

@@ -140,8 +140,10 @@ adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, in
 
 /* Kernel timing (options.timing != 0): for kernel class k (0 beta-line solve,
  * 1 gamma-line solve, 2 beta scatter, 3 gamma scatter/update, 4 norm), total
- * milliseconds and launch count since setup or the last reset.  reset != 0
- * clears the counters after reading.  Synchronises the stream. */
+ * milliseconds and launch count of kernels of the given precision (0 FP64,
+ * 1 FP32) since setup or the last reset of that precision.  ms_out and
+ * count_out hold 5 entries.  reset != 0 clears that precision's counters after
+ * reading.  Synchronises the stream. */
 adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out,
                             int32_t reset);
 

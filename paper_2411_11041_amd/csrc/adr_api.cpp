@@ -10,6 +10,7 @@
 #include <memory>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "adr_internal.h"
@@ -23,6 +24,7 @@ thread_local std::string g_setup_error;
 
 constexpr int kSlotStep = 0, kSlotLin = 1, kSlotTime = 2, kSlotGuess = 3, kSlots = 4;
 constexpr int kBlock = 256;
+constexpr int kTile = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
 // line-length buckets (nodes per line): each bucket is one launch with its own LDS size
 constexpr int kBucketEdges[] = {96, 384, 1536, 1 << 30};
@@ -294,11 +296,26 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         const int nblk = blk_start[n];
         const int npad = nblk * kBlock;
         C->n_blocks = nblk;
+        // slot order: 16 x 16 tiles of the grid (row-major inside a tile), so that
+        // a wavefront's nodes are a compact patch whose crossing records come
+        // from few curves (cache-line reuse of the line values)
+        std::vector<std::vector<int>> order(n);
+        for (int i = 0; i < n; ++i) {
+            const int nxi = G[i].g.nx;
+            std::vector<int> &o = order[i];
+            o.resize(G[i].inner_list.size());
+            for (size_t s = 0; s < o.size(); ++s) o[s] = static_cast<int>(s);
+            auto key = [&](int s) {
+                const int g = G[i].inner_list[s], gi = g % nxi, gj = g / nxi;
+                return std::make_tuple(gj / kTile, gi / kTile, gj % kTile, gi % kTile);
+            };
+            std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return key(a) < key(b); });
+        }
         std::vector<int> gidx(npad, -1), blk_inst(nblk);
         for (int i = 0; i < n; ++i) {
             for (int b = blk_start[i]; b < blk_start[i + 1]; ++b) blk_inst[b] = i;
-            for (size_t s = 0; s < G[i].inner_list.size(); ++s)
-                gidx[blk_start[i] * kBlock + s] = static_cast<int>(C->goff[i] + G[i].inner_list[s]);
+            for (size_t s = 0; s < order[i].size(); ++s)
+                gidx[blk_start[i] * kBlock + s] = static_cast<int>(C->goff[i] + G[i].inner_list[order[i][s]]);
             C->n_unknowns += static_cast<int64_t>(G[i].inner_list.size());
         }
         int *d_gidx = upload(gidx, own, st);
@@ -373,9 +390,9 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             std::vector<int> rk(4 * static_cast<size_t>(npad), -1);
             std::vector<double> ra(4 * static_cast<size_t>(npad), 0.0), rb(4 * static_cast<size_t>(npad), 0.0);
             for (int i = 0; i < n; ++i)
-                for (size_t s = 0; s < G[i].inner_list.size(); ++s) {
+                for (size_t s = 0; s < order[i].size(); ++s) {
                     const size_t slot = static_cast<size_t>(blk_start[i]) * kBlock + s;
-                    const adr::Rec4 &R = G[i].rec[f][s];
+                    const adr::Rec4 &R = G[i].rec[f][order[i][s]];
                     for (int r = 0; r < 4; ++r) {
                         rk[r * static_cast<size_t>(npad) + slot] = R.k[r] < 0 ? -1 : static_cast<int>(noff[i] + R.k[r]);
                         ra[r * static_cast<size_t>(npad) + slot] = R.ca[r];
@@ -590,11 +607,10 @@ adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int
             if (count_out) count_out[k] = ctx->cnt[precision][k];
         }
         if (reset)
-            for (int p = 0; p < 2; ++p)
-                for (int k = 0; k < 5; ++k) {
-                    ctx->ms[p][k] = 0.0;
-                    ctx->cnt[p][k] = 0;
-                }
+            for (int k = 0; k < 5; ++k) {
+                ctx->ms[precision][k] = 0.0;
+                ctx->cnt[precision][k] = 0;
+            }
         return ADR_OK;
     } catch (const Error &e) {
         return fail_ctx(ctx, e);

@@ -89,7 +89,8 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
             lo += cC * clo;
             di += cC * cdi;
             hi += cC * cup;
-            rhs += eC * (clo * um + cdi * u0 + cup * up) + eL * a.L[k];
+            rhs += eC * (clo * um + cdi * u0 + cup * up);
+            if (eL != T(0)) rhs += eL * a.L[k];  // source term only in the full step
         }
         A[r] = lo;
         B[r] = di;
