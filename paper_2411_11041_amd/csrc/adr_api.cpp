@@ -27,8 +27,9 @@ constexpr int kBlock = 256;
 constexpr int kTile = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
 // line-length buckets (nodes per line): each bucket is one launch with its own LDS size
-constexpr int kBucketEdges[] = {96, 384, 1536, 1 << 30};
-constexpr int kBuckets = 4;
+constexpr int kBucketEdges[] = {256, 512, 1024, 2048, 3072};
+constexpr int kBuckets = 5;
+constexpr int kMaxNodes = 3072;  // 12 nodes per thread of a 256-thread workgroup
 
 #define HIPCHK(x)                                                                              \
     do {                                                                                       \
@@ -334,6 +335,13 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             F.n_nodes = noff[n];
             if (F.n_nodes > (int64_t(1) << 31) - 2) throw Error{ADR_EINVAL, "too many line nodes"};
             F.n_lines = static_cast<int>(lines.size());
+            for (auto &li : lines) {
+                const adr::Family &fa = G[li.first].fam[f];
+                const int64_t cnt = fa.off[li.second + 1] - fa.off[li.second];
+                if (cnt > kMaxNodes)
+                    throw Error{ADR_EINVAL, "a curve has " + std::to_string(cnt) + " nodes; the line solver holds " +
+                                                std::to_string(kMaxNodes)};
+            }
             // bucket lines by node count (stable within a bucket)
             std::vector<int> loff, lcnt, linst;
             loff.reserve(lines.size());
@@ -355,7 +363,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 }
                 F.bk[b] = Bucket{first, count, nmax};
                 first += count;
-                if (count && adr::line_lds_bytes<double>(nmax) > kLdsLimit)
+                if (count && (nmax > kMaxNodes || adr::line_lds_bytes<double>(nmax) > kLdsLimit))
                     throw Error{ADR_EINVAL, "a curve has " + std::to_string(nmax) +
                                                 " nodes: longer than the LDS-resident line solver holds"};
             }

@@ -27,17 +27,20 @@ __device__ inline T bilinear(const T *__restrict__ F, int cell, int nx, T lx, T 
     return (T(1) - ly) * ((T(1) - lx) * p11 + lx * p12) + ly * ((T(1) - lx) * p21 + lx * p22);
 }
 
-template <typename T, int FAM>
+template <typename T, int FAM, int MAXJ>
 __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
                                                    T *__restrict__ vout, const double *__restrict__ par,
                                                    const int *__restrict__ done, int nmax) {
+    // LDS: four row arrays (the first also holds the gathered values, the
+    // second the solution for the write-out) and the reduced system
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T *U = reinterpret_cast<T *>(smem_raw);
-    T *A = U + nmax;
-    T *B = A + nmax;
-    T *C = B + nmax;
-    T *D = C + nmax;
-    T *RA = D + nmax;
+    const int stride = nmax + kThreads;
+    T *A = reinterpret_cast<T *>(smem_raw);
+    T *B = A + stride;
+    T *C = B + stride;
+    T *D = C + stride;
+    T *U = A;
+    T *RA = D + stride;
     T *RB = RA + kThreads;
     T *RC = RB + kThreads;
     T *RD = RC + kThreads;
@@ -57,52 +60,95 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
     const T cM = T(pp[0]), cK = T(pp[1]), cC = T(pp[2]);
     const T eM = T(pp[3]), eK = T(pp[4]), eC = T(pp[5]), eL = T(pp[6]);
 
-    // 1. gather the field at the nodes (ends carry the zero Dirichlet value)
-    for (int j = tid; j < n; j += kThreads) {
-        T u = T(0);
+    // chunking of the rows: thread q owns rows q*m .. q*m+m-1; in LDS a chunk
+    // starts at q*mp with mp = m | 1 (odd), so a chunk walk is bank-conflict free
+    const int m = (N + kThreads - 1) / kThreads;
+    const int mp = m | 1;
+    const int Q = (N + m - 1) / m;  // non-empty chunks
+
+    // 1. all loads of this thread's nodes (j = tid + 256 q) and rows (r = j)
+    //    issued before any use, then the bilinear gather (eq. (22))
+    T hl[MAXJ], hr[MAXJ], wm[MAXJ], w0[MAXJ], wp[MAXJ], lk[MAXJ], uj[MAXJ];
+    int cj[MAXJ];
+    T lxj[MAXJ], lyj[MAXJ];
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q) {
+        const int j = tid + kThreads * q;
+        cj[q] = -1;
         if (j > 0 && j < n - 1) {
             const int k = o + j;
-            u = bilinear(fin, a.cell[k], nx, a.lx[k], a.ly[k]);
+            cj[q] = a.cell[k];
+            lxj[q] = a.lx[k];
+            lyj[q] = a.ly[k];
         }
-        U[j] = u;
+        if (j < N) {
+            const int k = o + j + 1;
+            hl[q] = a.h[k];
+            hr[q] = a.h[k + 1];
+            if (FAM == 0) {
+                wm[q] = a.w[k - 1];
+                w0[q] = a.w[k];
+                wp[q] = a.w[k + 1];
+                lk[q] = eL != T(0) ? a.L[k] : T(0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q) {
+        const int j = tid + kThreads * q;
+        uj[q] = cj[q] >= 0 ? bilinear(fin, cj[q], nx, lxj[q], lyj[q]) : T(0);
+        if (j < n) U[j] = uj[q];
     }
     __syncthreads();
 
-    // 2. rows r = 0..N-1 (node j = r + 1) of  A x = rhs
+    // 2. rows r = 0..N-1 (node r + 1) of  A x = rhs, kept in registers until
+    //    every thread has read its neighbours' gathered values
     const T sixth = T(1) / T(6), third = T(1) / T(3);
-    for (int r = tid; r < N; r += kThreads) {
-        const int k = o + r + 1;
-        const T hl = a.h[k], hr = a.h[k + 1];
-        const T mlo = hl * sixth, mdi = (hl + hr) * third, mup = hr * sixth;
-        const T il = T(1) / hl, ir = T(1) / hr;
-        const T klo = -il, kdi = il + ir, kup = -ir;
-        const T um = U[r], u0 = U[r + 1], up = U[r + 2];
-        T lo = cM * mlo + cK * klo;
-        T di = cM * mdi + cK * kdi;
-        T hi = cM * mup + cK * kup;
-        T rhs = eM * (mlo * um + mdi * u0 + mup * up) + eK * (klo * um + kdi * u0 + kup * up);
-        if (FAM == 0) {
-            const T wm = a.w[k - 1], w0 = a.w[k], wp = a.w[k + 1];
-            const T clo = -(wm + T(2) * w0) * sixth;
-            const T cdi = (wm - wp) * sixth;
-            const T cup = (T(2) * w0 + wp) * sixth;
-            lo += cC * clo;
-            di += cC * cdi;
-            hi += cC * cup;
-            rhs += eC * (clo * um + cdi * u0 + cup * up);
-            if (eL != T(0)) rhs += eL * a.L[k];  // source term only in the full step
+    T ro_lo[MAXJ], ro_di[MAXJ], ro_hi[MAXJ], ro_d[MAXJ];
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q) {
+        const int r = tid + kThreads * q;
+        if (r < N) {
+            const T mlo = hl[q] * sixth, mdi = (hl[q] + hr[q]) * third, mup = hr[q] * sixth;
+            const T il = T(1) / hl[q], ir = T(1) / hr[q];
+            const T klo = -il, kdi = il + ir, kup = -ir;
+            const T um = U[r], u0 = U[r + 1], up = U[r + 2];
+            T lo = cM * mlo + cK * klo;
+            T di = cM * mdi + cK * kdi;
+            T hi = cM * mup + cK * kup;
+            T rhs = eM * (mlo * um + mdi * u0 + mup * up) + eK * (klo * um + kdi * u0 + kup * up);
+            if (FAM == 0) {
+                const T clo = -(wm[q] + T(2) * w0[q]) * sixth;
+                const T cdi = (wm[q] - wp[q]) * sixth;
+                const T cup = (T(2) * w0[q] + wp[q]) * sixth;
+                lo += cC * clo;
+                di += cC * cdi;
+                hi += cC * cup;
+                rhs += eC * (clo * um + cdi * u0 + cup * up) + eL * lk[q];
+            }
+            ro_lo[q] = lo;
+            ro_di[q] = di;
+            ro_hi[q] = hi;
+            ro_d[q] = rhs;
         }
-        A[r] = lo;
-        B[r] = di;
-        C[r] = hi;
-        D[r] = rhs;
+    }
+    __syncthreads();  // U (aliasing A) fully read
+#pragma unroll
+    for (int q = 0; q < MAXJ; ++q) {
+        const int r = tid + kThreads * q;
+        if (r < N) {
+            const int x = (r / m) * mp + (r % m);
+            A[x] = ro_lo[q];
+            B[x] = ro_di[q];
+            C[x] = ro_hi[q];
+            D[x] = ro_d[q];
+        }
     }
     __syncthreads();
 
-    // 3. chunked elimination
-    const int m = (N + kThreads - 1) / kThreads;
-    const int Q = (N + m - 1) / m;  // non-empty chunks
+    // 3. chunked elimination (row r of chunk q lives at q*mp + (r - q*m))
     const int q = tid;
+    const int cb = q * mp - q * m;  // LDS offset of this thread's chunk minus its first row
     int i0 = 0, i1 = -1, sep = -1;
     T yL = T(0), aL = T(1), gL = T(0);  // last interior row = yL + aL*S_{q-1} + gL*S_q
     if (q < Q) {
@@ -114,26 +160,26 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
         sep = has_sep ? re : -1;
         T pc = T(0), py = T(0), pa = T(0);
         for (int r = i0; r <= i1; ++r) {
-            const T ar = A[r];
-            const T inv = T(1) / (B[r] - ar * pc);
-            const T cp = C[r] * inv;
-            const T yp = (D[r] - ar * py) * inv;
+            const T ar = A[cb + r];
+            const T inv = T(1) / (B[cb + r] - ar * pc);
+            const T cp = C[cb + r] * inv;
+            const T yp = (D[cb + r] - ar * py) * inv;
             const T al = (r == i0 ? -ar : -ar * pa) * inv;
-            C[r] = cp;
-            D[r] = yp;
-            A[r] = al;
+            C[cb + r] = cp;
+            D[cb + r] = yp;
+            A[cb + r] = al;
             pc = cp;
             py = yp;
             pa = al;
         }
         T fy = T(0), fa = T(0), fg = T(1);  // empty chunk: its first row is its separator
         if (i1 >= i0) {
-            T Y = D[i1], Al = A[i1], Ga = -C[i1];
+            T Y = D[cb + i1], Al = A[cb + i1], Ga = -C[cb + i1];
             yL = Y; aL = Al; gL = Ga;
             for (int r = i1 - 1; r >= i0; --r) {
-                const T cp = C[r];
-                Y = D[r] - cp * Y;
-                Al = A[r] - cp * Al;
+                const T cp = C[cb + r];
+                Y = D[cb + r] - cp * Y;
+                Al = A[cb + r] - cp * Al;
                 Ga = -cp * Ga;
             }
             fy = Y; fa = Al; fg = Ga;
@@ -149,7 +195,7 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
     {
         T ra = T(0), rb = T(1), rc = T(0), rd = T(0);
         if (q < R) {
-            const T as = A[sep], bs = B[sep], cs = C[sep], ds = D[sep];
+            const T as = A[cb + sep], bs = B[cb + sep], cs = C[cb + sep], ds = D[cb + sep];
             const T nfy = FY[q + 1], nfa = FA[q + 1], nfg = FG[q + 1];
             ra = q > 0 ? as * aL : T(0);
             rb = bs + as * gL + cs * nfa;
@@ -182,22 +228,31 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
         __syncthreads();
     }
 
-    // 5. back-substitution of every chunk; results go to U[r + 1]
+    // 5. back-substitution of every chunk; x_r goes to X at the padded row
+    //    index (X aliases B, which is no longer read)
+    T *X = B;
     if (q < Q) {
         const T SL = q > 0 ? RD[q - 1] : T(0);
         const T SR = q < R ? RD[q] : T(0);
         if (i1 >= i0) {
-            T x = D[i1] + A[i1] * SL - C[i1] * SR;
-            U[i1 + 1] = x;
+            T x = D[cb + i1] + A[cb + i1] * SL - C[cb + i1] * SR;
+            X[cb + i1] = x;
             for (int r = i1 - 1; r >= i0; --r) {
-                x = D[r] + A[r] * SL - C[r] * x;
-                U[r + 1] = x;
+                x = D[cb + r] + A[cb + r] * SL - C[cb + r] * x;
+                X[cb + r] = x;
             }
         }
-        if (sep >= 0) U[sep + 1] = SR;
+        if (sep >= 0) X[cb + sep] = SR;
     }
     __syncthreads();
-    for (int j = tid; j < n; j += kThreads) vout[o + j] = (j == 0 || j == n - 1) ? T(0) : U[j];
+    for (int j = tid; j < n; j += kThreads) {
+        T v = T(0);
+        if (j > 0 && j < n - 1) {
+            const int r = j - 1;
+            v = X[(r / m) * mp + (r % m)];
+        }
+        vout[o + j] = v;
+    }
 }
 
 // Scatter: out = P v on the interior nodes.  MODE 0: write; MODE 1 (FP64 sweep):
@@ -291,28 +346,39 @@ __global__ void k_fill_int(int *p, int v, int n) {
 // ------------------------------------------------------------------ launchers
 template <typename T>
 size_t line_lds_bytes(int nmax) {
-    return sizeof(T) * (5 * static_cast<size_t>(nmax) + 7 * kThreads);
+    // four row arrays of nmax + 256 (odd chunk stride padding) and the reduced system
+    return sizeof(T) * (4 * static_cast<size_t>(nmax + kThreads) + 7 * kThreads);
+}
+
+template <typename T, int FAM, int MAXJ>
+hipError_t launch_line_j(const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
+                         const int *done, int nmax, hipStream_t st) {
+    const size_t lds = line_lds_bytes<T>(nmax);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, FAM, MAXJ>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    hipLaunchKernelGGL((k_line<T, FAM, MAXJ>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
+    return hipGetLastError();
+}
+
+template <typename T, int FAM>
+hipError_t launch_line_f(const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
+                         const int *done, int nmax, hipStream_t st) {
+    const int per = (nmax + kThreads - 1) / kThreads;  // nodes per thread
+    if (per <= 1) return launch_line_j<T, FAM, 1>(a, n_lines, fin, vout, par, done, nmax, st);
+    if (per <= 2) return launch_line_j<T, FAM, 2>(a, n_lines, fin, vout, par, done, nmax, st);
+    if (per <= 4) return launch_line_j<T, FAM, 4>(a, n_lines, fin, vout, par, done, nmax, st);
+    if (per <= 8) return launch_line_j<T, FAM, 8>(a, n_lines, fin, vout, par, done, nmax, st);
+    if (per <= 12) return launch_line_j<T, FAM, 12>(a, n_lines, fin, vout, par, done, nmax, st);
+    return hipErrorInvalidValue;
 }
 
 template <typename T>
 hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
                        const int *done, int nmax, hipStream_t st) {
     if (n_lines == 0) return hipSuccess;
-    const size_t lds = line_lds_bytes<T>(nmax);
-    if (lds > 64 * 1024) {
-        // allow the large dynamic LDS footprint of long curves (gfx950: 160 KB per CU)
-        if (fam == 0)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 0>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        else
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 1>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    }
-    if (fam == 0)
-        hipLaunchKernelGGL((k_line<T, 0>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
-    else
-        hipLaunchKernelGGL((k_line<T, 1>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
-    return hipGetLastError();
+    if (fam == 0) return launch_line_f<T, 0>(a, n_lines, fin, vout, par, done, nmax, st);
+    return launch_line_f<T, 1>(a, n_lines, fin, vout, par, done, nmax, st);
 }
 
 template <typename T, typename TO>
