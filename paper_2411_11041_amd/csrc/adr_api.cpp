@@ -27,8 +27,9 @@ constexpr int kBlock = 256;
 constexpr int kTile = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
 // line-length buckets (nodes per line): each bucket is one launch with its own LDS size
-constexpr int kBucketEdges[] = {256, 512, 1024, 2048, 3072};
-constexpr int kBuckets = 5;
+// one launch per family: all curves, ordered longest first
+constexpr int kBucketEdges[] = {3072};
+constexpr int kBuckets = 1;
 constexpr int kMaxNodes = 3072;  // 12 nodes per thread of a 256-thread workgroup
 
 #define HIPCHK(x)                                                                              \
@@ -343,6 +344,10 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                                                 std::to_string(kMaxNodes)};
             }
             // bucket lines by node count (stable within a bucket)
+            std::stable_sort(lines.begin(), lines.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
+                const adr::Family &fx = G[x.first].fam[f], &fy = G[y.first].fam[f];
+                return fx.off[x.second + 1] - fx.off[x.second] > fy.off[y.second + 1] - fy.off[y.second];
+            });
             std::vector<int> loff, lcnt, linst;
             loff.reserve(lines.size());
             int first = 0;

@@ -21,6 +21,11 @@ namespace adr {
 
 constexpr int kThreads = 256;
 
+// 1/x: IEEE division in FP64 (parity with the FP64 oracle), the hardware
+// reciprocal (v_rcp_f32, ~1 ulp) in the FP32 increment sweeps
+__device__ inline double recip(double x) { return 1.0 / x; }
+__device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <typename T>
 __device__ inline T bilinear(const T *__restrict__ F, int cell, int nx, T lx, T ly) {
     const T p11 = F[cell], p12 = F[cell + 1], p21 = F[cell + nx], p22 = F[cell + nx + 1];
@@ -28,9 +33,8 @@ __device__ inline T bilinear(const T *__restrict__ F, int cell, int nx, T lx, T 
 }
 
 template <typename T, int FAM, int MAXJ>
-__global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
-                                                   T *__restrict__ vout, const double *__restrict__ par,
-                                                   const int *__restrict__ done, int nmax) {
+__device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restrict__ fin, T *__restrict__ vout,
+                                          const double *__restrict__ par, const int *__restrict__ done, int nmax) {
     // LDS: four row arrays (the first also holds the gathered values, the
     // second the solution for the write-out) and the reduced system
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -60,10 +64,8 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
     const T cM = T(pp[0]), cK = T(pp[1]), cC = T(pp[2]);
     const T eM = T(pp[3]), eK = T(pp[4]), eC = T(pp[5]), eL = T(pp[6]);
 
-    // chunking of the rows: thread q owns rows q*m .. q*m+m-1; in LDS a chunk
-    // starts at q*mp with mp = m | 1 (odd), so a chunk walk is bank-conflict free
+    // chunking of the rows: thread q owns rows q*m .. q*m+m-1 (m <= MAXJ)
     const int m = (N + kThreads - 1) / kThreads;
-    const int mp = m | 1;
     const int Q = (N + m - 1) / m;  // non-empty chunks
 
     // 1. all loads of this thread's nodes (j = tid + 256 q) and rows (r = j)
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
         const int r = tid + kThreads * q;
         if (r < N) {
             const T mlo = hl[q] * sixth, mdi = (hl[q] + hr[q]) * third, mup = hr[q] * sixth;
-            const T il = T(1) / hl[q], ir = T(1) / hr[q];
+            const T il = recip(hl[q]), ir = recip(hr[q]);
             const T klo = -il, kdi = il + ir, kup = -ir;
             const T um = U[r], u0 = U[r + 1], up = U[r + 2];
             T lo = cM * mlo + cK * klo;
@@ -137,53 +139,74 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
     for (int q = 0; q < MAXJ; ++q) {
         const int r = tid + kThreads * q;
         if (r < N) {
-            const int x = (r / m) * mp + (r % m);
-            A[x] = ro_lo[q];
-            B[x] = ro_di[q];
-            C[x] = ro_hi[q];
-            D[x] = ro_d[q];
+            A[r] = ro_lo[q];
+            B[r] = ro_di[q];
+            C[r] = ro_hi[q];
+            D[r] = ro_d[q];
         }
     }
     __syncthreads();
 
-    // 3. chunked elimination (row r of chunk q lives at q*mp + (r - q*m))
+    // 3. chunked elimination in registers.  Chunk q: rows rs..rs+k-1; its last
+    //    row is a separator unless q is the last chunk; the others are interior
+    //    rows, eliminated top-down with their dependence on the separators
+    //    S_{q-1} (left) and S_q (right) carried along.
     const int q = tid;
-    const int cb = q * mp - q * m;  // LDS offset of this thread's chunk minus its first row
-    int i0 = 0, i1 = -1, sep = -1;
-    T yL = T(0), aL = T(1), gL = T(0);  // last interior row = yL + aL*S_{q-1} + gL*S_q
-    if (q < Q) {
-        const int rs = q * m;
-        const int re = min(rs + m, N) - 1;
-        const bool has_sep = q < Q - 1;
-        i0 = rs;
-        i1 = has_sep ? re - 1 : re;
-        sep = has_sep ? re : -1;
-        T pc = T(0), py = T(0), pa = T(0);
-        for (int r = i0; r <= i1; ++r) {
-            const T ar = A[cb + r];
-            const T inv = T(1) / (B[cb + r] - ar * pc);
-            const T cp = C[cb + r] * inv;
-            const T yp = (D[cb + r] - ar * py) * inv;
-            const T al = (r == i0 ? -ar : -ar * pa) * inv;
-            C[cb + r] = cp;
-            D[cb + r] = yp;
-            A[cb + r] = al;
-            pc = cp;
-            py = yp;
-            pa = al;
+    const int rs = q * m;
+    const int k = q < Q ? min(m, N - rs) : 0;
+    const bool has_sep = q < Q - 1;
+    const int kin = has_sep ? k - 1 : k;
+    T ra_[MAXJ], rb_[MAXJ], rc_[MAXJ], rd_[MAXJ];
+#pragma unroll
+    for (int j = 0; j < MAXJ; ++j) {
+        if (j < k) {
+            ra_[j] = A[rs + j];
+            rb_[j] = B[rs + j];
+            rc_[j] = C[rs + j];
+            rd_[j] = D[rs + j];
         }
-        T fy = T(0), fa = T(0), fg = T(1);  // empty chunk: its first row is its separator
-        if (i1 >= i0) {
-            T Y = D[cb + i1], Al = A[cb + i1], Ga = -C[cb + i1];
-            yL = Y; aL = Al; gL = Ga;
-            for (int r = i1 - 1; r >= i0; --r) {
-                const T cp = C[cb + r];
-                Y = D[cb + r] - cp * Y;
-                Al = A[cb + r] - cp * Al;
+    }
+    T sa = T(0), sb = T(1), sc = T(0), sd = T(0);  // separator row
+    {
+        T pc = T(0), py = T(0), pa = T(0);
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j) {
+            if (j < kin) {
+                const T ar = ra_[j];
+                const T inv = recip(rb_[j] - ar * pc);
+                const T cp = rc_[j] * inv;
+                const T yp = (rd_[j] - ar * py) * inv;
+                const T al = (j == 0 ? -ar : -ar * pa) * inv;
+                rc_[j] = cp;
+                rd_[j] = yp;
+                ra_[j] = al;
+                pc = cp;
+                py = yp;
+                pa = al;
+            } else if (has_sep && j == k - 1) {
+                sa = ra_[j]; sb = rb_[j]; sc = rc_[j]; sd = rd_[j];
+            }
+        }
+    }
+    T yL = T(0), aL = T(1), gL = T(0);  // last interior row = yL + aL*S_{q-1} + gL*S_q
+    T fy = T(0), fa = T(0), fg = T(1);  // first row (an empty chunk's first row is S_q)
+    {
+        T Y = T(0), Al = T(0), Ga = T(0);
+#pragma unroll
+        for (int j = MAXJ - 1; j >= 0; --j) {
+            if (j == kin - 1) {
+                Y = rd_[j]; Al = ra_[j]; Ga = -rc_[j];
+                yL = Y; aL = Al; gL = Ga;
+            } else if (j < kin - 1) {
+                const T cp = rc_[j];
+                Y = rd_[j] - cp * Y;
+                Al = ra_[j] - cp * Al;
                 Ga = -cp * Ga;
             }
-            fy = Y; fa = Al; fg = Ga;
         }
+        if (kin > 0) { fy = Y; fa = Al; fg = Ga; }
+    }
+    if (q < Q) {
         FY[q] = fy;
         FA[q] = fa;
         FG[q] = fg;
@@ -195,16 +218,13 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
     {
         T ra = T(0), rb = T(1), rc = T(0), rd = T(0);
         if (q < R) {
-            const T as = A[cb + sep], bs = B[cb + sep], cs = C[cb + sep], ds = D[cb + sep];
             const T nfy = FY[q + 1], nfa = FA[q + 1], nfg = FG[q + 1];
-            ra = q > 0 ? as * aL : T(0);
-            rb = bs + as * gL + cs * nfa;
-            rc = q + 1 < R ? cs * nfg : T(0);
-            rd = ds - as * yL - cs * nfy;
+            ra = q > 0 ? sa * aL : T(0);
+            rb = sb + sa * gL + sc * nfa;
+            rc = q + 1 < R ? sc * nfg : T(0);
+            rd = sd - sa * yL - sc * nfy;
         }
-        if (q < kThreads) {
-            RA[q] = ra; RB[q] = rb; RC[q] = rc; RD[q] = rd;
-        }
+        RA[q] = ra; RB[q] = rb; RC[q] = rc; RD[q] = rd;
         __syncthreads();
         for (int s = 1; s < R; s <<= 1) {
             T na = ra, nb = rb, nc = rc, nd = rd;
@@ -213,7 +233,7 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
                 T ua = T(0), ub = T(1), uc = T(0), ud = T(0);
                 if (q - s >= 0) { la = RA[q - s]; lb = RB[q - s]; lc = RC[q - s]; ld = RD[q - s]; }
                 if (q + s < R) { ua = RA[q + s]; ub = RB[q + s]; uc = RC[q + s]; ud = RD[q + s]; }
-                const T k1 = ra / lb, k2 = rc / ub;
+                const T k1 = ra * recip(lb), k2 = rc * recip(ub);
                 na = -la * k1;
                 nc = -uc * k2;
                 nb = rb - lc * k1 - ua * k2;
@@ -228,31 +248,40 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
         __syncthreads();
     }
 
-    // 5. back-substitution of every chunk; x_r goes to X at the padded row
-    //    index (X aliases B, which is no longer read)
+    // 5. back-substitution of every chunk into X (aliases B, already read)
     T *X = B;
     if (q < Q) {
         const T SL = q > 0 ? RD[q - 1] : T(0);
         const T SR = q < R ? RD[q] : T(0);
-        if (i1 >= i0) {
-            T x = D[cb + i1] + A[cb + i1] * SL - C[cb + i1] * SR;
-            X[cb + i1] = x;
-            for (int r = i1 - 1; r >= i0; --r) {
-                x = D[cb + r] + A[cb + r] * SL - C[cb + r] * x;
-                X[cb + r] = x;
+        T x = T(0);
+#pragma unroll
+        for (int j = MAXJ - 1; j >= 0; --j) {
+            if (j == kin - 1) {
+                x = rd_[j] + ra_[j] * SL - rc_[j] * SR;
+                X[rs + j] = x;
+            } else if (j < kin - 1) {
+                x = rd_[j] + ra_[j] * SL - rc_[j] * x;
+                X[rs + j] = x;
             }
         }
-        if (sep >= 0) X[cb + sep] = SR;
+        if (has_sep) X[rs + k - 1] = SR;
     }
     __syncthreads();
-    for (int j = tid; j < n; j += kThreads) {
-        T v = T(0);
-        if (j > 0 && j < n - 1) {
-            const int r = j - 1;
-            v = X[(r / m) * mp + (r % m)];
-        }
-        vout[o + j] = v;
-    }
+    for (int j = tid; j < n; j += kThreads) vout[o + j] = (j == 0 || j == n - 1) ? T(0) : X[j - 1];
+}
+
+// One launch for every curve of a family: curves are ordered longest first and
+// each workgroup picks the register footprint (nodes per thread) of its curve.
+template <typename T, int FAM>
+__global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
+                                                   T *__restrict__ vout, const double *__restrict__ par,
+                                                   const int *__restrict__ done, int nmax) {
+    const int per = (a.lcnt[blockIdx.x] + kThreads - 1) / kThreads;
+    if (per <= 1) line_body<T, FAM, 1>(a, fin, vout, par, done, nmax);
+    else if (per <= 2) line_body<T, FAM, 2>(a, fin, vout, par, done, nmax);
+    else if (per <= 4) line_body<T, FAM, 4>(a, fin, vout, par, done, nmax);
+    else if (per <= 8) line_body<T, FAM, 8>(a, fin, vout, par, done, nmax);
+    else line_body<T, FAM, 12>(a, fin, vout, par, done, nmax);
 }
 
 // Scatter: out = P v on the interior nodes.  MODE 0: write; MODE 1 (FP64 sweep):
@@ -350,35 +379,24 @@ size_t line_lds_bytes(int nmax) {
     return sizeof(T) * (4 * static_cast<size_t>(nmax + kThreads) + 7 * kThreads);
 }
 
-template <typename T, int FAM, int MAXJ>
-hipError_t launch_line_j(const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
-                         const int *done, int nmax, hipStream_t st) {
-    const size_t lds = line_lds_bytes<T>(nmax);
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, FAM, MAXJ>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    hipLaunchKernelGGL((k_line<T, FAM, MAXJ>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
-    return hipGetLastError();
-}
-
-template <typename T, int FAM>
-hipError_t launch_line_f(const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
-                         const int *done, int nmax, hipStream_t st) {
-    const int per = (nmax + kThreads - 1) / kThreads;  // nodes per thread
-    if (per <= 1) return launch_line_j<T, FAM, 1>(a, n_lines, fin, vout, par, done, nmax, st);
-    if (per <= 2) return launch_line_j<T, FAM, 2>(a, n_lines, fin, vout, par, done, nmax, st);
-    if (per <= 4) return launch_line_j<T, FAM, 4>(a, n_lines, fin, vout, par, done, nmax, st);
-    if (per <= 8) return launch_line_j<T, FAM, 8>(a, n_lines, fin, vout, par, done, nmax, st);
-    if (per <= 12) return launch_line_j<T, FAM, 12>(a, n_lines, fin, vout, par, done, nmax, st);
-    return hipErrorInvalidValue;
-}
-
 template <typename T>
 hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
                        const int *done, int nmax, hipStream_t st) {
     if (n_lines == 0) return hipSuccess;
-    if (fam == 0) return launch_line_f<T, 0>(a, n_lines, fin, vout, par, done, nmax, st);
-    return launch_line_f<T, 1>(a, n_lines, fin, vout, par, done, nmax, st);
+    if (nmax > 12 * kThreads) return hipErrorInvalidValue;
+    const size_t lds = line_lds_bytes<T>(nmax);
+    if (fam == 0) {
+        if (lds > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 0>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        hipLaunchKernelGGL((k_line<T, 0>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
+    } else {
+        if (lds > 64 * 1024)
+            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 1>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        hipLaunchKernelGGL((k_line<T, 1>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
+    }
+    return hipGetLastError();
 }
 
 template <typename T, typename TO>
