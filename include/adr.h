@@ -85,6 +85,9 @@ typedef struct {
     int32_t timing;       /* != 0: time each kernel with HIP events (adr_kernel_times) */
     int32_t host_only;    /* != 0: build the host geometry only, touch no device; then
                              only adr_counts, adr_export_lines and adr_destroy are valid */
+    int32_t graph;        /* != 0: adr_split_iterate replays its sweep blocks from a captured
+                             HIP graph (on a context-owned stream ordered after options.stream);
+                             ignored when timing != 0 */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -110,11 +113,14 @@ adr_status adr_counts(const adr_ctx *ctx, int64_t *grid_unknowns, int64_t *lines
 /* Stationary solve (Sec. 2 limit, eq. (10) sweeps).  u: device FP64, packed
  * layout; in: initial iterate, out: last iterate.  Each sweep k maps U_k to
  * U_{k+1} = Phi(U_k); an instance stops at the first FP64 sweep with
- *   rel = |U_{k+1} - U_k|_2 / |Phi(0)|_2 <= tol      (interior nodes)
- * (in FP32_LINES mode rel is measured on the FP64 sweeps only).  iters (host,
- * n_probs, may be NULL): sweeps applied per instance; rel_res (host, n_probs,
- * may be NULL): last measured rel.  Returns ADR_ENOTCONV if an instance hit
- * max_iters, ADR_ENONFINITE if a residual is not finite. */
+ *   rel = |U_{k+1} - U_k|_2 / |Phi(0)|_2 <= tol      (interior nodes).
+ * Sweep order: one FP64 sweep, then blocks of (fp32_sweeps FP32 sweeps, one
+ * FP64 sweep) in FP32_LINES mode (whole blocks only: at most max_iters
+ * sweeps); every sweep is FP64 in FP64 mode; rel is measured on the FP64
+ * sweeps only.  iters (host, n_probs, may be NULL): sweeps
+ * applied per instance; rel_res (host, n_probs, may be NULL): last measured
+ * rel.  Returns ADR_ENOTCONV if an instance hit max_iters, ADR_ENONFINITE if a
+ * residual is not finite. */
 adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol,
                              int32_t *iters, double *rel_res);
 

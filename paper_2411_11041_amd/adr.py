@@ -44,7 +44,8 @@ class Problem(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("fp32_sweeps", C.c_int32),
                 ("theta", C.c_double), ("dt", C.c_double),
-                ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32)]
+                ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32),
+                ("graph", C.c_int32)]
 
 
 _lib = None
@@ -98,7 +99,7 @@ class Solver:
     """One context over a batch of problems (workloads.Problem-like objects)."""
 
     def __init__(self, problems, precision="fp64", theta=1.0, dt=0.05, fp32_sweeps=3,
-                 stream=None, timing=False, host_only=False):
+                 stream=None, timing=False, host_only=False, graph=False):
         self.lib = load()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -119,7 +120,8 @@ class Solver:
             stream = torch.cuda.current_stream().cuda_stream
         prec = {"fp64": PREC_FP64, "fp32": PREC_FP32_LINES}[precision]
         opt = Options(prec, int(fp32_sweeps), float(theta), float(dt),
-                      C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)))
+                      C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)),
+                      int(bool(graph)))
         self.n = len(problems)
         self.ctx = C.c_void_p()
         st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))

@@ -7,6 +7,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <thread>
@@ -174,11 +175,31 @@ struct adr_ctx {
         line32(1, kSlotLin, D32, dn);
         timed(1, 3, [&] { return adr::launch_scatter<float, double>(2, fam[1].s32, fam[1].v32, U, d32, partial, dn, st); });
     }
-    void norm(int sweep, double tol, int mode, const int *dn_unused) {
-        (void)dn_unused;
+    void norm(int count, double tol, int mode) {
         timed(0, 4, [&] {
-            return adr::launch_norm(n_inst, partial, blk_start, cnorm, rel, done, conv_it, sweep, tol, mode, st);
+            return adr::launch_norm(n_inst, partial, blk_start, cnorm, rel, done, conv_it, count, tol, mode, st);
         });
+    }
+
+    // one block of the stationary iteration: FP32 increment sweeps, then an FP64
+    // sweep with the update norm (the first block has no FP32 sweeps)
+    void block(double *u, int fp32_sweeps, double tol) {
+        for (int k = 0; k < fp32_sweeps; ++k) sweep32(u, done);
+        sweep64(kSlotStep, u, u, 1, done);
+        norm(fp32_sweeps + 1, tol, 0);
+    }
+
+    // captured graph of one block, replayed (keyed by the state pointer and tol)
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    const double *g_u = nullptr;
+    double g_tol = -1.0;
+    hipStream_t cap = nullptr;
+    void drop_graph() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        gexec = nullptr;
+        graph = nullptr;
     }
 
 };
@@ -232,10 +253,26 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         C->st = static_cast<hipStream_t>(opt->stream);
         const int n = n_probs;
 
-        // host geometry, instances in parallel
+        // host geometry, instances in parallel.  Instances that share the grid,
+        // the domain and the beta arrays (same pointers) share their curves:
+        // they are traced once and only the load vector is rebuilt.
         std::vector<adr::InstanceGeo> G(n);
         std::vector<Error> errs(n, Error{ADR_OK, ""});
+        std::vector<int> rep(n);
         {
+            std::map<std::vector<double>, int> first;
+            for (int i = 0; i < n; ++i) {
+                const adr_problem &p = probs[i];
+                std::vector<double> key = {double(p.nx), double(p.ny), p.a, p.b, p.c, p.d, double(p.domain),
+                                           double(reinterpret_cast<uintptr_t>(p.beta1)),
+                                           double(reinterpret_cast<uintptr_t>(p.beta2))};
+                for (int k = 0; k < p.n_dom_params && p.dom_params; ++k) key.push_back(p.dom_params[k]);
+                auto it = first.find(key);
+                if (it == first.end()) { first.emplace(key, i); rep[i] = i; }
+                else rep[i] = it->second;
+            }
+        }
+        auto run_pool = [&](auto &&work) {
             unsigned nt = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
             nt = std::min<unsigned>(nt, static_cast<unsigned>(n));
             std::atomic<int> next{0};
@@ -244,7 +281,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 pool.emplace_back([&] {
                     for (int i = next++; i < n; i = next++) {
                         try {
-                            adr::build_instance(probs[i], G[i]);
+                            work(i);
                         } catch (const Error &e) {
                             errs[i] = e;
                         } catch (const std::bad_alloc &) {
@@ -253,7 +290,13 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     }
                 });
             for (auto &th : pool) th.join();
-        }
+        };
+        run_pool([&](int i) { if (rep[i] == i) adr::build_instance(probs[i], G[i]); });
+        for (int i = 0; i < n; ++i)
+            if (errs[rep[i]].code != ADR_OK && rep[i] != i) errs[i] = errs[rep[i]];
+        run_pool([&](int i) {
+            if (rep[i] != i && errs[rep[i]].code == ADR_OK) adr::rebuild_for_source(G[rep[i]], probs[i], G[i]);
+        });
         for (int i = 0; i < n; ++i)
             if (errs[i].code != ADR_OK)
                 throw Error{errs[i].code, "instance " + std::to_string(i) + ": " + errs[i].msg};
@@ -449,7 +492,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
 
         // |Phi(0)| per instance: one FP64 sweep from zero
         C->sweep64(kSlotStep, C->Z64, C->Z64, 3, C->never);
-        C->norm(0, 0.0, 1, nullptr);
+        C->norm(0, 0.0, 1);
         HIPCHK(hipStreamSynchronize(st));
         C->collect_ticks();
         for (auto &r : C->ms) for (auto &v : r) v = 0.0;
@@ -495,26 +538,50 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
     }
     try {
         const int n = ctx->n_inst;
+        hipStream_t user = ctx->st;
+        const bool use_graph = ctx->opt.graph != 0 && !ctx->opt.timing;
+        if (use_graph) {
+            // run on the context's own stream (capturable), ordered after the caller's work
+            if (!ctx->cap) HIPCHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+            hipEvent_t ev;
+            HIPCHK(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            HIPCHK(hipEventRecord(ev, user));
+            HIPCHK(hipStreamWaitEvent(ctx->cap, ev, 0));
+            HIPCHK(hipEventDestroy(ev));
+            ctx->st = ctx->cap;
+        }
         hipStream_t st = ctx->st;
+        const bool fp32 = ctx->opt.precision == ADR_PREC_FP32_LINES;
+        const int m = fp32 ? ctx->opt.fp32_sweeps : 0;
+        const int period = m + 1;
         HIPCHK(adr::launch_fill_int(ctx->done, 0, n, st));
         HIPCHK(adr::launch_fill_int(ctx->conv_it, 0, n, st));
-        const bool fp32 = ctx->opt.precision == ADR_PREC_FP32_LINES;
-        const int period = fp32 ? ctx->opt.fp32_sweeps + 1 : 1;
-        const int check = std::max(4, 2 * period);
         std::vector<int> dn(n, 0);
+        auto all_done = [&]() {
+            HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            return std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; });
+        };
         int executed = 0;
-        for (int s = 0; s < max_iters; ++s) {
-            if (s % period == 0) {
-                ctx->sweep64(kSlotStep, u, u, 1, ctx->done);
-                ctx->norm(s, tol, 0, nullptr);
-            } else {
-                ctx->sweep32(u, ctx->done);
+        if (max_iters > 0) {
+            ctx->block(u, 0, tol);  // first FP64 sweep
+            executed = 1;
+            const int blocks = (max_iters - 1) / period;
+            const int check = std::max(1, 8 / period);
+            if (use_graph && blocks > 0 && (ctx->g_u != u || ctx->g_tol != tol || !ctx->gexec)) {
+                ctx->drop_graph();
+                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                ctx->block(u, m, tol);
+                HIPCHK(hipStreamEndCapture(st, &ctx->graph));
+                HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+                ctx->g_u = u;
+                ctx->g_tol = tol;
             }
-            executed = s + 1;
-            if ((s + 1) % check == 0 || s + 1 == max_iters) {
-                HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                if (std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; })) break;
+            for (int b = 0; b < blocks; ++b) {
+                if (use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, st));
+                else ctx->block(u, m, tol);
+                executed += period;
+                if ((b + 1) % check == 0 && all_done()) break;
             }
         }
         std::vector<int> ci(n, 0);
@@ -523,9 +590,10 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
         HIPCHK(hipMemcpyAsync(ci.data(), ctx->conv_it, sizeof(int) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(rr.data(), ctx->rel, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        if (use_graph) ctx->st = user;
         adr_status status = ADR_OK;
         for (int i = 0; i < n; ++i) {
-            if (iters) iters[i] = dn[i] ? ci[i] : executed;
+            if (iters) iters[i] = ci[i];
             if (rel_res) rel_res[i] = max_iters > 0 ? rr[i] : NAN;
             if (max_iters > 0 && !std::isfinite(rr[i])) status = ADR_ENONFINITE;
             else if (!dn[i] && status == ADR_OK) status = ADR_ENOTCONV;
@@ -533,6 +601,7 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
         if (status == ADR_ENONFINITE) ctx->err = "non-finite residual";
         return status;
     } catch (const Error &e) {
+        if (ctx->opt.graph) ctx->st = static_cast<hipStream_t>(ctx->opt.stream);
         return fail_ctx(ctx, e);
     }
 }
@@ -567,7 +636,7 @@ adr_status adr_residual(adr_ctx *ctx, const double *u, double *rel_res) {
     }
     try {
         ctx->sweep64(kSlotStep, u, const_cast<double *>(u), 3, ctx->never);
-        ctx->norm(0, 0.0, 2, nullptr);
+        ctx->norm(0, 0.0, 2);
         HIPCHK(hipMemcpyAsync(rel_res, ctx->rel, sizeof(double) * ctx->n_inst, hipMemcpyDeviceToHost, ctx->st));
         HIPCHK(hipStreamSynchronize(ctx->st));
         for (int i = 0; i < ctx->n_inst; ++i)
@@ -641,6 +710,8 @@ adr_status adr_destroy(adr_ctx *ctx) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
     }
+    ctx->drop_graph();
+    if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     for (void *p : ctx->owned) (void)hipFree(p);
     delete ctx;
     return ADR_OK;

@@ -543,21 +543,41 @@ void build_instance(const adr_problem &p, InstanceGeo &G) {
         }
         if (fam == 0) {
             G.wk.assign(n, 0.0);
-            G.Lk.assign(n, 0.0);
-            std::vector<double> fk(n);
             for (size_t k = 0; k < n; ++k) {
                 double b1 = g.interp(p.beta1, F.x[k], F.y[k]), b2 = g.interp(p.beta2, F.x[k], F.y[k]);
                 G.wk[k] = std::hypot(b1, b2);
-                fk[k] = g.interp(p.f, F.x[k], F.y[k]);
             }
-            for (int l = 0; l < nl; ++l)
-                for (int64_t k = F.off[l] + 1; k + 1 < F.off[l + 1]; ++k) {
-                    double hl = G.hk[0][k], hr = G.hk[0][k + 1];
-                    G.Lk[k] = (hl + hr) / 3.0 * fk[k] + hl / 6.0 * fk[k - 1] + hr / 6.0 * fk[k + 1];
-                }
         }
         build_scatter(g, *dom, G.inner, G.inner_list, F, G.rec[fam]);
     }
+    compute_load(p, G);
+}
+
+void compute_load(const adr_problem &p, InstanceGeo &G) {
+    // eq. (17): <l_i, phi_k> with f taken as its P1 interpolant on the beta-curve
+    const Grid &g = G.g;
+    const Family &F = G.fam[0];
+    const size_t n = F.x.size();
+    G.mu = p.mu;
+    G.sigma = p.sigma;
+    G.Lk.assign(n, 0.0);
+    std::vector<double> fk(n);
+    for (size_t k = 0; k < n; ++k) fk[k] = g.interp(p.f, F.x[k], F.y[k]);
+    const int nl = static_cast<int>(F.off.size()) - 1;
+    for (int l = 0; l < nl; ++l)
+        for (int64_t k = F.off[l] + 1; k + 1 < F.off[l + 1]; ++k) {
+            double hl = G.hk[0][k], hr = G.hk[0][k + 1];
+            G.Lk[k] = (hl + hr) / 3.0 * fk[k] + hl / 6.0 * fk[k - 1] + hr / 6.0 * fk[k + 1];
+        }
+}
+
+void rebuild_for_source(const InstanceGeo &base, const adr_problem &p, InstanceGeo &G) {
+    if (!(p.mu > 0.0)) fail(ADR_EINVAL, "mu must be > 0");
+    if (!(p.sigma >= 0.0)) fail(ADR_EINVAL, "sigma must be >= 0");
+    if (!p.f) fail(ADR_EINVAL, "f is required");
+    if (!finite_all(p.f, static_cast<size_t>(p.nx) * p.ny)) fail(ADR_ENONFINITE, "non-finite f");
+    G = base;
+    compute_load(p, G);
 }
 
 }  // namespace adr

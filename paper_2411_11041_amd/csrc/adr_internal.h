@@ -57,5 +57,9 @@ struct InstanceGeo {
 
 // Builds the geometry of one instance; throws Error.
 void build_instance(const adr_problem &p, InstanceGeo &out);
+// Load vector of the beta-curves for the source of p (curves already traced).
+void compute_load(const adr_problem &p, InstanceGeo &G);
+// Copy of base (same grid, domain and beta) with the coefficients and source of p.
+void rebuild_for_source(const InstanceGeo &base, const adr_problem &p, InstanceGeo &out);
 
 }  // namespace adr

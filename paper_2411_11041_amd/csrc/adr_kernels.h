@@ -41,7 +41,7 @@ hipError_t launch_scatter(int mode, const ScatterArgs<T> &s, const T *v, TO *out
                           const int *done, hipStream_t st);
 
 hipError_t launch_norm(int n_inst, const double *partial, const int *blk_start, double *cnorm, double *rel, int *done,
-                       int *conv_it, int sweep, double tol, int mode, hipStream_t st);
+                       int *it_count, int count, double tol, int mode, hipStream_t st);
 
 hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st);
 

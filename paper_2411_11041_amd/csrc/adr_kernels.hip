@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
 __global__ __launch_bounds__(kThreads) void k_norm(const double *__restrict__ partial,
                                                    const int *__restrict__ blk_start, double *__restrict__ cnorm,
                                                    double *__restrict__ rel, int *__restrict__ done,
-                                                   int *__restrict__ conv_it, int sweep, double tol, int mode) {
+                                                   int *__restrict__ it_count, int count, double tol, int mode) {
     const int inst = blockIdx.x;
     if (mode == 0 && done[inst]) return;
     const int b0 = blk_start[inst], b1 = blk_start[inst + 1];
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_norm(const double *__restrict__ pa
     const double r = nrm / cn;
     rel[inst] = r;
     if (mode == 0) {
-        conv_it[inst] = sweep + 1;
+        it_count[inst] += count;  // sweeps applied since the previous measurement
         if (!(r <= tol)) return;  // NaN never converges
         done[inst] = 1;
     }
@@ -414,9 +414,9 @@ hipError_t launch_scatter(int mode, const ScatterArgs<T> &s, const T *v, TO *out
 }
 
 hipError_t launch_norm(int n_inst, const double *partial, const int *blk_start, double *cnorm, double *rel, int *done,
-                       int *conv_it, int sweep, double tol, int mode, hipStream_t st) {
-    hipLaunchKernelGGL(k_norm, dim3(n_inst), dim3(kThreads), 0, st, partial, blk_start, cnorm, rel, done, conv_it,
-                       sweep, tol, mode);
+                       int *it_count, int count, double tol, int mode, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm, dim3(n_inst), dim3(kThreads), 0, st, partial, blk_start, cnorm, rel, done, it_count,
+                       count, tol, mode);
     return hipGetLastError();
 }
 
