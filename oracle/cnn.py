@@ -1,0 +1,137 @@
+"""FP64 reference of the warm-start network (test infrastructure).
+
+Four 3x3 convolutions with "same" zero padding: C_in -> 32 -> 32 -> 32 -> 1,
+ReLU after the first three, biases in FP32/FP64.  Activations are NHWC.  The
+arithmetic is FP64; the values that the device keeps in BF16 are rounded to
+BF16 (round to nearest even) at the same points:
+  * the input tensor x0 and every weight tensor used by a convolution,
+  * the stored activations y1, y2, y3 (after bias and ReLU),
+  * the back-propagated pre-activation gradients g1, g2, g3 (inputs of the
+    matrix-core products).
+The loss gradient g4 and the last layer's products stay in full precision.
+Weight layout: W[l] has shape (C_out, 3, 3, C_in) (tap (dy, dx) in row-major
+order, dy, dx in {-1, 0, 1}); b[l] has shape (C_out,).
+
+Loss: mean squared error over the masked pixels of every sample,
+L = sum_{b, p in mask} (out - target)^2 / (B * |mask|).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CH = 32
+
+
+def bf16(x):
+    """Round to the nearest BF16 value (ties to even), returned as float64."""
+    a = np.asarray(x, np.float32)
+    u = a.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    u = (u + 0x7FFF + lsb) & 0xFFFF0000
+    out = u.astype(np.uint32).view(np.float32).astype(np.float64)
+    nan = np.isnan(a)
+    if nan.any():
+        out[nan] = np.nan
+    return out
+
+
+def init_params(c_in=4, seed=0):
+    """He-normal weights, zero biases (FP32 master values, as float64 arrays)."""
+    rng = np.random.default_rng(seed)
+    shapes = [(CH, 3, 3, c_in), (CH, 3, 3, CH), (CH, 3, 3, CH), (1, 3, 3, CH)]
+    W, b = [], []
+    for s in shapes:
+        fan_in = 9 * s[3]
+        W.append((rng.standard_normal(s) * np.sqrt(2.0 / fan_in)).astype(np.float32).astype(np.float64))
+        b.append(np.zeros(s[0]))
+    return W, b
+
+
+def conv(x, Wt, bias):
+    """z[b,y,x,n] = sum_{dy,dx,c} W[n,dy+1,dx+1,c] x[b,y+dy,x+dx,c] + bias[n] (zero padding)."""
+    B, H, Wd, C = x.shape
+    xp = np.zeros((B, H + 2, Wd + 2, C))
+    xp[:, 1:-1, 1:-1] = x
+    z = np.zeros((B, H, Wd, Wt.shape[0]))
+    for dy in range(3):
+        for dx in range(3):
+            patch = xp[:, dy:dy + H, dx:dx + Wd, :]
+            z += patch @ Wt[:, dy, dx, :].T
+    return z + bias
+
+
+def conv_transpose(g, Wt):
+    """dL/dx for z = conv(x, W): dx[b,y,x,c] = sum_{dy,dx,n} W[n,dy,dx,c] g[b,y-dy+1,x-dx+1,n]."""
+    B, H, Wd, N = g.shape
+    gp = np.zeros((B, H + 2, Wd + 2, N))
+    gp[:, 1:-1, 1:-1] = g
+    dx_ = np.zeros((B, H, Wd, Wt.shape[3]))
+    for dy in range(3):
+        for dx in range(3):
+            # x[p] feeds z[p - (dy-1, dx-1)] through tap (dy, dx)
+            patch = gp[:, 2 - dy:2 - dy + H, 2 - dx:2 - dx + Wd, :]
+            dx_ += patch @ Wt[:, dy, dx, :]
+    return dx_
+
+
+def conv_wgrad(g, x):
+    """dL/dW[n,dy,dx,c] = sum_{b,p} g[b,p,n] x[b,p+(dy-1,dx-1),c]; dL/db[n] = sum g."""
+    B, H, Wd, N = g.shape
+    C = x.shape[3]
+    xp = np.zeros((B, H + 2, Wd + 2, C))
+    xp[:, 1:-1, 1:-1] = x
+    dW = np.zeros((N, 3, 3, C))
+    gf = g.reshape(-1, N)
+    for dy in range(3):
+        for dx in range(3):
+            patch = xp[:, dy:dy + H, dx:dx + Wd, :].reshape(-1, C)
+            dW[:, dy, dx, :] = gf.T @ patch
+    return dW, gf.sum(axis=0)
+
+
+def forward(x0, W, b, rounding=True):
+    """Returns the FP64 output (B,H,W) and the stored activations."""
+    r = bf16 if rounding else (lambda v: np.asarray(v, np.float64))
+    x = r(x0)
+    acts = [x]
+    for l in range(3):
+        z = conv(x, r(W[l]), b[l])
+        x = r(np.maximum(z, 0.0))
+        acts.append(x)
+    out = conv(x, r(W[3]), b[3])[..., 0]
+    return out, acts
+
+
+def loss_and_grads(x0, target, mask, W, b, rounding=True):
+    """MSE loss over masked pixels and its gradients (list dW, list db)."""
+    r = bf16 if rounding else (lambda v: np.asarray(v, np.float64))
+    out, acts = forward(x0, W, b, rounding)
+    B = out.shape[0]
+    m = np.broadcast_to(mask, out.shape).astype(np.float64)
+    cnt = B * mask.sum()
+    diff = (out - target) * m
+    loss = float((diff ** 2).sum() / cnt)
+    g = (2.0 * diff / cnt)[..., None]  # dL/dz4, (B,H,W,1)
+    dW = [None] * 4
+    db = [None] * 4
+    for l in (3, 2, 1, 0):
+        dW[l], db[l] = conv_wgrad(g, acts[l])
+        if l == 0:
+            break
+        dy = conv_transpose(g, r(W[l]))
+        g = r(dy * (acts[l] > 0))
+    return loss, dW, db, out
+
+
+def adam(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step on a list of arrays; state = (m, v, t)."""
+    m, v, t = state
+    t += 1
+    out = []
+    for k, (p, g) in enumerate(zip(params, grads)):
+        m[k] = b1 * m[k] + (1 - b1) * g
+        v[k] = b2 * v[k] + (1 - b2) * g * g
+        mh = m[k] / (1 - b1 ** t)
+        vh = v[k] / (1 - b2 ** t)
+        out.append(p - lr * mh / (np.sqrt(vh) + eps))
+    return out, (m, v, t)
