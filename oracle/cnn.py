@@ -135,3 +135,54 @@ def adam(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         vh = v[k] / (1 - b2 ** t)
         out.append(p - lr * mh / (np.sqrt(vh) + eps))
     return out, (m, v, t)
+
+
+def pack_inputs(f, s, mask, mu):
+    """Network input for B images (f, s: (B,H,W) FP64; mask (H,W); mu (B,)).
+
+    Channels: f/|f|_inf, log10(mu) + 2, s/|s|_inf, mask (norms over masked
+    pixels; 1 if zero).  Returned BF16-rounded, with the per-image |s|_inf.
+    """
+    B, H, W = f.shape
+    m = mask.astype(bool)
+    x = np.zeros((B, H, W, 4))
+    sn = np.zeros(B)
+    for b in range(B):
+        fn = np.abs(f[b][m]).max() if m.any() else 0.0
+        snb = np.abs(s[b][m]).max() if m.any() else 0.0
+        fn = fn if fn > 0 else 1.0
+        snb = snb if snb > 0 else 1.0
+        sn[b] = snb
+        x[b, ..., 0] = np.where(m, f[b] / fn, 0.0)
+        x[b, ..., 1] = np.log10(mu[b]) + 2.0
+        x[b, ..., 2] = np.where(m, s[b] / snb, 0.0)
+        x[b, ..., 3] = m
+    return bf16(x), sn
+
+
+def target(u_star, s, sn, mask):
+    """(u* - s)/|s|_inf on masked pixels (FP32 values)."""
+    t = np.where(mask[None].astype(bool), (u_star - s) / sn[:, None, None], 0.0)
+    return np.asarray(t, np.float32).astype(np.float64)
+
+
+def warm_start(s, sn, out, mask):
+    """u = s + |s|_inf * out on masked pixels, 0 elsewhere."""
+    return np.where(mask[None].astype(bool), s + sn[:, None, None] * out, 0.0)
+
+
+def flatten(W, b):
+    """Parameters in the device's flat FP32 layout (W1,b1,W2,b2,W3,b3,W4,b4)."""
+    return np.concatenate([np.concatenate([w.ravel(), bb.ravel()]) for w, bb in zip(W, b)]).astype(np.float32)
+
+
+def unflatten(p, c_in=4):
+    shapes = [(CH, 3, 3, c_in), (CH, 3, 3, CH), (CH, 3, 3, CH), (1, 3, 3, CH)]
+    W, b, o = [], [], 0
+    for s in shapes:
+        n = int(np.prod(s))
+        W.append(np.asarray(p[o:o + n], np.float64).reshape(s))
+        o += n
+        b.append(np.asarray(p[o:o + s[0]], np.float64))
+        o += s[0]
+    return W, b

@@ -199,3 +199,133 @@ class Solver:
 
     def __exit__(self, *a):
         self.close()
+
+
+# ----------------------------------------------------------------------------
+# learned warm start (include/adrnn.h)
+NN_EXPORTS = ("adrnn_param_count", "adrnn_create", "adrnn_destroy", "adrnn_set_params", "adrnn_get_params",
+              "adrnn_pack", "adrnn_forward", "adrnn_grads", "adrnn_adam", "adrnn_train_step",
+              "adrnn_warm_start", "adrnn_mfma_probe", "adrnn_last_error")
+
+_nn_ready = False
+
+
+def _load_nn():
+    global _nn_ready
+    lib = load()
+    if _nn_ready:
+        return lib
+    i32, vp, P = C.c_int32, C.c_void_p, C.POINTER
+    lib.adrnn_param_count.restype = C.c_int64
+    lib.adrnn_create.argtypes = [i32, i32, i32, vp, P(vp)]
+    lib.adrnn_destroy.argtypes = [vp]
+    lib.adrnn_set_params.argtypes = [vp, vp]
+    lib.adrnn_get_params.argtypes = [vp, vp]
+    lib.adrnn_pack.argtypes = [vp, i32, vp, vp, vp, P(C.c_double), vp, vp, vp, vp]
+    lib.adrnn_forward.argtypes = [vp, i32, vp, vp]
+    lib.adrnn_grads.argtypes = [vp, i32, vp, vp, vp, vp, P(C.c_double)]
+    lib.adrnn_adam.argtypes = [vp, vp, C.c_float]
+    lib.adrnn_train_step.argtypes = [vp, i32, vp, vp, vp, C.c_float, P(C.c_double)]
+    lib.adrnn_warm_start.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    lib.adrnn_mfma_probe.argtypes = [vp, vp, vp, vp]
+    lib.adrnn_last_error.argtypes = [vp]
+    lib.adrnn_last_error.restype = C.c_char_p
+    for n in NN_EXPORTS:
+        if n not in ("adrnn_param_count", "adrnn_last_error"):
+            getattr(lib, n).restype = i32
+    _nn_ready = True
+    return lib
+
+
+def _dp(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Net:
+    """Warm-start network context (H x W images, batches up to max_batch)."""
+
+    def __init__(self, H, W, max_batch, stream=None):
+        import torch
+        self.lib = _load_nn()
+        self.H, self.W, self.maxB = H, W, max_batch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.ctx = C.c_void_p()
+        st = self.lib.adrnn_create(H, W, max_batch, C.c_void_p(stream) if stream else None, C.byref(self.ctx))
+        if st != ADR_OK:
+            raise ADRError(st, "adrnn_create failed")
+        self.n_params = int(self.lib.adrnn_param_count())
+
+    def _check(self, st):
+        if st != ADR_OK:
+            raise ADRError(st, self.lib.adrnn_last_error(self.ctx).decode())
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, np.float32)
+        assert p.size == self.n_params
+        self._check(self.lib.adrnn_set_params(self.ctx, p.ctypes.data_as(C.c_void_p)))
+
+    def get_params(self):
+        p = np.zeros(self.n_params, np.float32)
+        self._check(self.lib.adrnn_get_params(self.ctx, p.ctypes.data_as(C.c_void_p)))
+        return p
+
+    def pack(self, B, f, s, mask, mu, u_star=None):
+        import torch
+        HW = self.H * self.W
+        x0 = torch.empty(B * HW * 4, dtype=torch.int16, device="cuda")
+        tgt = torch.empty(B * HW, dtype=torch.float32, device="cuda") if u_star is not None else None
+        sn = torch.empty(B, dtype=torch.float64, device="cuda")
+        mu = np.ascontiguousarray(mu, np.float64)
+        self._check(self.lib.adrnn_pack(self.ctx, B, _dp(f), _dp(s), _dp(mask), mu.ctypes.data_as(C.POINTER(C.c_double)),
+                                        _dp(u_star), _dp(x0), _dp(tgt), _dp(sn)))
+        return x0, tgt, sn
+
+    def forward(self, B, x0, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(B * self.H * self.W, dtype=torch.float32, device="cuda")
+        self._check(self.lib.adrnn_forward(self.ctx, B, _dp(x0), _dp(out)))
+        return out
+
+    def grads(self, B, x0, target, mask):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        self._check(self.lib.adrnn_grads(self.ctx, B, _dp(x0), _dp(target), _dp(mask), _dp(g), C.byref(loss)))
+        return g, loss.value
+
+    def adam(self, grads, lr):
+        self._check(self.lib.adrnn_adam(self.ctx, _dp(grads), float(lr)))
+
+    def train_step(self, B, x0, target, mask, lr):
+        loss = C.c_double()
+        self._check(self.lib.adrnn_train_step(self.ctx, B, _dp(x0), _dp(target), _dp(mask), float(lr),
+                                              C.byref(loss)))
+        return loss.value
+
+    def warm_start(self, B, s, s_norm, out, mask, u):
+        self._check(self.lib.adrnn_warm_start(self.ctx, B, _dp(s), _dp(s_norm), _dp(out), _dp(mask), _dp(u)))
+
+    def close(self):
+        if self.ctx:
+            self.lib.adrnn_destroy(self.ctx)
+            self.ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def mfma_probe(A_bf16_bits, B_bf16_bits):
+    """D = A @ B through the matrix-core path (16x16 BF16 bit patterns as int16 tensors)."""
+    import torch
+    lib = _load_nn()
+    D = torch.empty(256, dtype=torch.float32, device="cuda")
+    st = lib.adrnn_mfma_probe(_dp(A_bf16_bits), _dp(B_bf16_bits), _dp(D),
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st != ADR_OK:
+        raise ADRError(st, "mfma probe failed")
+    return D

@@ -1,0 +1,710 @@
+// Learned warm start: BF16 matrix-core (MFMA) convolution kernels with FP32
+// accumulation, training (backward, Adam) and inference, behind the C ABI of
+// include/adrnn.h.
+//
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: a wavefront
+// computes 16 pixels x 32 output channels (two 16x16 tiles); K runs over
+// (tap, input channel).  Operand layout of the instruction: lane l supplies
+// A[l%16][4(l/16) .. 4(l/16)+3] and B[4(l/16) .. +3][l%16]; it receives
+// D[4(l/16) + v][l%16], v = 0..3.  NHWC activations make a lane's four K
+// values (four consecutive channels of one pixel) one 8-byte load.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/adrnn.h"
+
+namespace {
+
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16_t;
+
+constexpr int kCh = 32;
+constexpr int kThreads = 256;
+constexpr int kW1 = 32 * 9 * 4, kW2 = 32 * 9 * 32, kW4 = 9 * 32;
+// offsets in the parameter vector
+constexpr int oW1 = 0, ob1 = oW1 + kW1, oW2 = ob1 + 32, ob2 = oW2 + kW2, oW3 = ob2 + 32, ob3 = oW3 + kW2,
+              oW4 = ob3 + 32, ob4 = oW4 + kW4, kParams = ob4 + 1;
+constexpr int kChunk = 256;  // pixels per weight-gradient chunk
+
+__device__ __forceinline__ bf16_t f2bf(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                      // round to nearest even
+    return static_cast<bf16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(static_cast<unsigned>(h) << 16); }
+__device__ __forceinline__ bool bf_pos(bf16_t h) { return h != 0 && (h & 0x8000) == 0 && h <= 0x7f80; }
+
+__device__ __forceinline__ v4f32 mfma(v4i16 a, v4i16 b, v4f32 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// ------------------------------------------------------------------ conv (32 outputs)
+// EPI 0: y = bf16(relu(acc + bias)).   EPI 1: y = bf16(acc * (ymask > 0)) (back-propagation
+// through the ReLU of the layer input).  Wg: [32][9][CIN] BF16 (taps row-major).
+template <int CIN, int EPI>
+__global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ x, const bf16_t *__restrict__ Wg,
+                                                     const float *__restrict__ bias,
+                                                     const bf16_t *__restrict__ ymask, bf16_t *__restrict__ y,
+                                                     int NP, int H, int W) {
+    constexpr int KT = CIN == 4 ? 12 : 9;  // taps, padded to whole K chunks for CIN = 4
+    __shared__ __align__(16) bf16_t Ws[kCh * KT * CIN];
+    for (int e = threadIdx.x; e < kCh * KT * CIN; e += kThreads) {
+        const int n = e / (KT * CIN), r = e % (KT * CIN), tap = r / CIN, c = r % CIN;
+        Ws[e] = tap < 9 ? Wg[(n * 9 + tap) * CIN + c] : bf16_t(0);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    const int HW = H * W;
+    const int ntiles = (NP + 15) / 16;
+    const v4i16 zero = {0, 0, 0, 0};
+    for (int t = blockIdx.x * 4 + wave; t < ntiles; t += gridDim.x * 4) {
+        const int gp = t * 16 + i;  // pixel of this lane's A row
+        const bool pv = gp < NP;
+        const int b = gp / HW, p = gp - b * HW, py = p / W, px = p - py * W;
+        v4f32 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        if constexpr (CIN == 32) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const bool ok = pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
+                const bf16_t *src = x + static_cast<size_t>(gp + dy * W + dx) * CIN;
+#pragma unroll
+                for (int cc = 0; cc < 2; ++cc) {
+                    const v4i16 a = ok ? *reinterpret_cast<const v4i16 *>(src + cc * 16 + g * 4) : zero;
+                    const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * CIN + cc * 16 + g * 4]);
+                    const v4i16 b1 =
+                        *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * CIN + cc * 16 + g * 4]);
+                    acc0 = mfma(a, b0, acc0);
+                    acc1 = mfma(a, b1, acc1);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int kc = 0; kc < 3; ++kc) {
+                const int tap = kc * 4 + g;  // this lane group's tap
+                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const bool ok = tap < 9 && pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
+                const v4i16 a = ok ? *reinterpret_cast<const v4i16 *>(x + static_cast<size_t>(gp + dy * W + dx) * 4)
+                                   : zero;
+                const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * 4]);
+                const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * 4]);
+                acc0 = mfma(a, b0, acc0);
+                acc1 = mfma(a, b1, acc1);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int po = t * 16 + 4 * g + v;
+            if (po >= NP) continue;
+            float z0 = acc0[v], z1 = acc1[v];
+            if constexpr (EPI == 0) {
+                z0 = fmaxf(z0 + bias[i], 0.f);
+                z1 = fmaxf(z1 + bias[i + 16], 0.f);
+            } else {
+                z0 = bf_pos(ymask[static_cast<size_t>(po) * kCh + i]) ? z0 : 0.f;
+                z1 = bf_pos(ymask[static_cast<size_t>(po) * kCh + i + 16]) ? z1 : 0.f;
+            }
+            y[static_cast<size_t>(po) * kCh + i] = f2bf(z0);
+            y[static_cast<size_t>(po) * kCh + i + 16] = f2bf(z1);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ weight gradient (MFMA)
+// part[blk][ (n*9 + tap)*CIN + c ] = sum over the block's pixels of g[p][n] x[p + off(tap)][c]
+// and part[blk][32*9*CIN + n] = sum g[p][n].  g: [NP][32], x: [NP][CIN] BF16.
+template <int CIN>
+__global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__ gsrc, const bf16_t *__restrict__ x,
+                                                      float *__restrict__ part, int NP, int H, int W) {
+    constexpr int NCOL = 9 * CIN;                 // (tap, c) columns
+    constexpr int NJT = (NCOL + 15) / 16;         // column tiles
+    constexpr int NT = 2 * NJT;                   // output tiles (2 row tiles of 16 channels)
+    constexpr int TPW = (NT + 3) / 4;             // tiles per wave
+    const int halo = W + 1;
+    const int span = kChunk + 2 * halo;
+    extern __shared__ __align__(16) unsigned char sm[];
+    bf16_t *gT = reinterpret_cast<bf16_t *>(sm);                // [32][kChunk]
+    bf16_t *xT = gT + kCh * kChunk;                             // [CIN][span]
+    short *pyx = reinterpret_cast<short *>(xT + CIN * span);    // [kChunk][2] (y, x), -1 for no pixel
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    const int HW = H * W;
+    v4f32 acc[TPW];
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) acc[q] = v4f32{0.f, 0.f, 0.f, 0.f};
+    float dbias = 0.f;
+    const int nchunks = (NP + kChunk - 1) / kChunk;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int c0 = ch * kChunk;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kCh * kChunk; e += kThreads) {
+            const int pl = e / kCh, n = e % kCh;  // coalesced read of g
+            const int gp = c0 + pl;
+            gT[n * kChunk + pl] = gp < NP ? gsrc[static_cast<size_t>(gp) * kCh + n] : bf16_t(0);
+        }
+        for (int e = threadIdx.x; e < span * CIN; e += kThreads) {
+            const int sl = e / CIN, c = e % CIN;
+            const int gp = c0 - halo + sl;
+            xT[c * span + sl] = (gp >= 0 && gp < NP) ? x[static_cast<size_t>(gp) * CIN + c] : bf16_t(0);
+        }
+        for (int pl = threadIdx.x; pl < kChunk; pl += kThreads) {
+            const int gp = c0 + pl;
+            short yy = -1, xx = -1;
+            if (gp < NP) {
+                const int p = gp % HW;
+                yy = static_cast<short>(p / W);
+                xx = static_cast<short>(p % W);
+            }
+            pyx[2 * pl] = yy;
+            pyx[2 * pl + 1] = xx;
+        }
+        __syncthreads();
+        if (threadIdx.x < kCh) {
+            float s = 0.f;
+            for (int pl = 0; pl < kChunk; ++pl) s += bf2f(gT[threadIdx.x * kChunk + pl]);
+            dbias += s;
+        }
+#pragma unroll
+        for (int q = 0; q < TPW; ++q) {
+            const int tile = wave * TPW + q;
+            if (tile >= NT) continue;
+            const int rt = tile / NJT, jt = tile % NJT;
+            const int n = rt * 16 + i;                 // A row (output channel)
+            const int col = jt * 16 + i;               // B column (tap, c)
+            const bool colok = col < NCOL;
+            const int tap = colok ? col / CIN : 0, c = colok ? col % CIN : 0;
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            const int off = dy * W + dx;
+            for (int k0 = 0; k0 < kChunk; k0 += 16) {
+                const v4i16 a = *reinterpret_cast<const v4i16 *>(&gT[n * kChunk + k0 + 4 * g]);
+                v4i16 bv;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int pl = k0 + 4 * g + v;
+                    const int yy = pyx[2 * pl], xx = pyx[2 * pl + 1];
+                    const bool ok = colok && yy >= 0 && yy + dy >= 0 && yy + dy < H && xx + dx >= 0 && xx + dx < W;
+                    bv[v] = ok ? static_cast<short>(xT[c * span + halo + pl + off]) : short(0);
+                }
+                acc[q] = mfma(a, bv, acc[q]);
+            }
+        }
+    }
+    float *out = part + static_cast<size_t>(blockIdx.x) * (kCh * NCOL + kCh);
+#pragma unroll
+    for (int q = 0; q < TPW; ++q) {
+        const int tile = wave * TPW + q;
+        if (tile >= NT) continue;
+        const int rt = tile / NJT, jt = tile % NJT;
+        const int col = jt * 16 + i;
+        if (col >= NCOL) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int n = rt * 16 + 4 * g + v;
+            out[n * NCOL + col] = acc[q][v];
+        }
+    }
+    if (threadIdx.x < kCh) out[kCh * NCOL + threadIdx.x] = dbias;
+}
+
+// sum of per-block partials in block order (deterministic)
+__global__ void k_reduce(const float *__restrict__ part, int nblk, int len, float *__restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; ++b) s += part[static_cast<size_t>(b) * len + e];
+    out[e] = s;
+}
+
+// ------------------------------------------------------------------ last layer (32 -> 1), VALU
+__global__ void k_last_fwd(const bf16_t *__restrict__ y3, const float *__restrict__ W4, const float *__restrict__ b4,
+                           float *__restrict__ out, int NP, int H, int W) {
+    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= NP) return;
+    const int HW = H * W, p = gp % HW, py = p / W, px = p % W;
+    float s = b4[0];
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        if (py + dy < 0 || py + dy >= H || px + dx < 0 || px + dx >= W) continue;
+        const bf16_t *src = y3 + static_cast<size_t>(gp + dy * W + dx) * kCh;
+        for (int c = 0; c < kCh; ++c) s += W4[tap * kCh + c] * bf2f(src[c]);
+    }
+    out[gp] = s;
+}
+
+// g4 = 2 (out - target) mask / cnt; partial sums of mask (out - target)^2 per block
+__global__ void k_loss(const float *__restrict__ out, const float *__restrict__ tgt, const uint8_t *__restrict__ mask,
+                       float *__restrict__ g4, double *__restrict__ lpart, int NP, int HW, double inv_cnt) {
+    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+    double e2 = 0.0;
+    if (gp < NP) {
+        const bool m = mask[gp % HW] != 0;
+        const float d = m ? out[gp] - tgt[gp] : 0.f;
+        g4[gp] = static_cast<float>(2.0 * d * inv_cnt);
+        e2 = static_cast<double>(d) * d;
+    }
+    __shared__ double red[kThreads];
+    red[threadIdx.x] = e2;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+// g3 = bf16( (sum_tap W4[tap][c] g4[p - off(tap)]) * (y3 > 0) )
+__global__ void k_last_dgrad(const float *__restrict__ g4, const float *__restrict__ W4,
+                             const bf16_t *__restrict__ y3, bf16_t *__restrict__ g3, int NP, int H, int W) {
+    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= NP) return;
+    const int HW = H * W, p = gp % HW, py = p / W, px = p % W;
+    float gn[9];
+    for (int tap = 0; tap < 9; ++tap) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        // pixel gp feeds output gp - off through tap
+        const bool ok = py - dy >= 0 && py - dy < H && px - dx >= 0 && px - dx < W;
+        gn[tap] = ok ? g4[gp - dy * W - dx] : 0.f;
+    }
+    for (int c = 0; c < kCh; ++c) {
+        float s = 0.f;
+        for (int tap = 0; tap < 9; ++tap) s += W4[tap * kCh + c] * gn[tap];
+        const bf16_t yv = y3[static_cast<size_t>(gp) * kCh + c];
+        g3[static_cast<size_t>(gp) * kCh + c] = f2bf(bf_pos(yv) ? s : 0.f);
+    }
+}
+
+// part[blk][tap*32 + c] = sum over the block's pixels of g4[p] y3[p + off][c]; part[blk][288] = sum g4
+__global__ __launch_bounds__(kThreads) void k_last_wgrad(const float *__restrict__ g4, const bf16_t *__restrict__ y3,
+                                                         float *__restrict__ part, int NP, int H, int W) {
+    const int e = threadIdx.x;  // 0..287 (two passes over 256 threads)
+    const int HW = H * W;
+    float acc[2] = {0.f, 0.f};
+    const int nchunks = (NP + kChunk - 1) / kChunk;
+    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int c0 = ch * kChunk;
+        for (int pass = 0; pass < 2; ++pass) {
+            const int el = e + pass * kThreads;
+            if (el > kW4) continue;
+            float s = 0.f;
+            for (int pl = 0; pl < kChunk; ++pl) {
+                const int gp = c0 + pl;
+                if (gp >= NP) break;
+                const float gv = g4[gp];
+                if (el == kW4) { s += gv; continue; }
+                const int tap = el / kCh, c = el % kCh, dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const int p = gp % HW, py = p / W, px = p % W;
+                if (py + dy < 0 || py + dy >= H || px + dx < 0 || px + dx >= W) continue;
+                s += gv * bf2f(y3[static_cast<size_t>(gp + dy * W + dx) * kCh + c]);
+            }
+            acc[pass] += s;
+        }
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+        const int el = e + pass * kThreads;
+        if (el <= kW4) part[static_cast<size_t>(blockIdx.x) * (kW4 + 1) + el] = acc[pass];
+    }
+}
+
+// ------------------------------------------------------------------ parameters
+// BF16 copies: forward layouts (= parameter layout) for W1..W3, FP32 of the BF16
+// value for W4, and the flipped/transposed dgrad weights Wt[c][8-tap][n] of W2, W3.
+__global__ void k_convert(const float *__restrict__ P, bf16_t *__restrict__ w1, bf16_t *__restrict__ w2,
+                          bf16_t *__restrict__ w3, bf16_t *__restrict__ w2t, bf16_t *__restrict__ w3t,
+                          float *__restrict__ w4) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < kW1) w1[e] = f2bf(P[oW1 + e]);
+    if (e < kW2) {
+        const bf16_t a = f2bf(P[oW2 + e]), b = f2bf(P[oW3 + e]);
+        w2[e] = a;
+        w3[e] = b;
+        const int n = e / (9 * kCh), r = e % (9 * kCh), tap = r / kCh, c = r % kCh;
+        const int t = (c * 9 + (8 - tap)) * kCh + n;
+        w2t[t] = a;
+        w3t[t] = b;
+    }
+    if (e < kW4) w4[e] = bf2f(f2bf(P[oW4 + e]));
+}
+
+__global__ void k_adam(float *__restrict__ P, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, int n, float lr, float c1, float c2) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const float gv = g[e];
+    const float mv = 0.9f * m[e] + 0.1f * gv;
+    const float vv = 0.999f * v[e] + 0.001f * gv * gv;
+    m[e] = mv;
+    v[e] = vv;
+    P[e] -= lr * (mv / c1) / (sqrtf(vv / c2) + 1e-8f);
+}
+
+// ------------------------------------------------------------------ inputs and warm start
+__global__ __launch_bounds__(kThreads) void k_norms(const double *__restrict__ f, const double *__restrict__ s,
+                                                    const uint8_t *__restrict__ mask, double *__restrict__ fn,
+                                                    double *__restrict__ sn, int HW) {
+    const int b = blockIdx.x;
+    double mf = 0.0, ms = 0.0;
+    for (int p = threadIdx.x; p < HW; p += kThreads) {
+        if (!mask[p]) continue;
+        mf = fmax(mf, fabs(f[static_cast<size_t>(b) * HW + p]));
+        ms = fmax(ms, fabs(s[static_cast<size_t>(b) * HW + p]));
+    }
+    __shared__ double rf[kThreads], rs[kThreads];
+    rf[threadIdx.x] = mf;
+    rs[threadIdx.x] = ms;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            rf[threadIdx.x] = fmax(rf[threadIdx.x], rf[threadIdx.x + w]);
+            rs[threadIdx.x] = fmax(rs[threadIdx.x], rs[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        fn[b] = rf[0] > 0.0 ? rf[0] : 1.0;
+        sn[b] = rs[0] > 0.0 ? rs[0] : 1.0;
+    }
+}
+
+__global__ void k_pack(const double *__restrict__ f, const double *__restrict__ s, const uint8_t *__restrict__ mask,
+                       const double *__restrict__ lmu, const double *__restrict__ fn, const double *__restrict__ sn,
+                       const double *__restrict__ ustar, bf16_t *__restrict__ x0, float *__restrict__ tgt, int NP,
+                       int HW) {
+    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= NP) return;
+    const int b = gp / HW, p = gp - b * HW;
+    const bool m = mask[p] != 0;
+    const double sv = s[gp];
+    bf16_t *o = x0 + static_cast<size_t>(gp) * 4;
+    o[0] = f2bf(static_cast<float>(m ? f[gp] / fn[b] : 0.0));
+    o[1] = f2bf(static_cast<float>(lmu[b] + 2.0));
+    o[2] = f2bf(static_cast<float>(m ? sv / sn[b] : 0.0));
+    o[3] = f2bf(m ? 1.f : 0.f);
+    if (ustar) tgt[gp] = static_cast<float>(m ? (ustar[gp] - sv) / sn[b] : 0.0);
+}
+
+__global__ void k_warm(const double *__restrict__ s, const double *__restrict__ sn, const float *__restrict__ out,
+                       const uint8_t *__restrict__ mask, double *__restrict__ u, int NP, int HW) {
+    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gp >= NP) return;
+    const int b = gp / HW;
+    u[gp] = mask[gp - b * HW] ? s[gp] + sn[b] * static_cast<double>(out[gp]) : 0.0;
+}
+
+__global__ void k_probe(const bf16_t *__restrict__ A, const bf16_t *__restrict__ B, float *__restrict__ D) {
+    const int l = threadIdx.x, i = l & 15, g = l >> 4;
+    v4i16 a, b;
+    for (int v = 0; v < 4; ++v) {
+        a[v] = static_cast<short>(A[i * 16 + 4 * g + v]);   // A[i][k]
+        b[v] = static_cast<short>(B[(4 * g + v) * 16 + i]); // B[k][j]
+    }
+    v4f32 d = mfma(a, b, v4f32{0.f, 0.f, 0.f, 0.f});
+    for (int v = 0; v < 4; ++v) D[(4 * g + v) * 16 + i] = d[v];
+}
+
+}  // namespace
+
+// ================================================================== context
+struct adrnn_ctx {
+    int H = 0, W = 0, maxB = 0;
+    hipStream_t st = nullptr;
+    std::vector<void *> owned;
+    float *P = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    bf16_t *w1 = nullptr, *w2 = nullptr, *w3 = nullptr, *w2t = nullptr, *w3t = nullptr;
+    float *w4 = nullptr;
+    bf16_t *y1 = nullptr, *y2 = nullptr, *y3 = nullptr, *ga = nullptr, *gb = nullptr;
+    float *out = nullptr, *g4 = nullptr, *part = nullptr, *lmu = nullptr;
+    double *lpart = nullptr, *fn = nullptr, *dlmu = nullptr;
+    int wblocks = 512;
+    int64_t step = 0;
+    std::string err;
+};
+
+namespace {
+
+struct NNError {
+    adr_status code;
+    std::string msg;
+};
+
+#define NNCHK(x)                                                                                           \
+    do {                                                                                                   \
+        hipError_t e_ = (x);                                                                               \
+        if (e_ != hipSuccess) throw NNError{ADR_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+template <typename T>
+T *nn_alloc(adrnn_ctx *c, size_t n) {
+    void *p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) throw NNError{ADR_ENOMEM, "hipMalloc"};
+    c->owned.push_back(p);
+    return static_cast<T *>(p);
+}
+
+size_t wgrad_lds(int cin, int W) {
+    const int span = kChunk + 2 * (W + 1);
+    return sizeof(bf16_t) * (kCh * kChunk + static_cast<size_t>(cin) * span) + sizeof(short) * 2 * kChunk;
+}
+
+void convert(adrnn_ctx *c) {
+    hipLaunchKernelGGL(k_convert, dim3((kW2 + 255) / 256), dim3(256), 0, c->st, c->P, c->w1, c->w2, c->w3, c->w2t,
+                       c->w3t, c->w4);
+    NNCHK(hipGetLastError());
+}
+
+int conv_grid(int NP) { return std::min(4096, std::max(1, (NP + 16 * 4 * 8 - 1) / (16 * 4 * 8))); }
+
+void forward(adrnn_ctx *c, int B, const bf16_t *x0, float *out) {
+    const int NP = B * c->H * c->W, gridc = conv_grid(NP);
+    hipLaunchKernelGGL((k_conv32<4, 0>), dim3(gridc), dim3(kThreads), 0, c->st, x0, c->w1, c->P + ob1, nullptr, c->y1,
+                       NP, c->H, c->W);
+    hipLaunchKernelGGL((k_conv32<32, 0>), dim3(gridc), dim3(kThreads), 0, c->st, c->y1, c->w2, c->P + ob2, nullptr,
+                       c->y2, NP, c->H, c->W);
+    hipLaunchKernelGGL((k_conv32<32, 0>), dim3(gridc), dim3(kThreads), 0, c->st, c->y2, c->w3, c->P + ob3, nullptr,
+                       c->y3, NP, c->H, c->W);
+    NNCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_last_fwd, dim3((NP + 255) / 256), dim3(256), 0, c->st, c->y3, c->w4, c->P + ob4, out, NP,
+                       c->H, c->W);
+    NNCHK(hipGetLastError());
+}
+
+template <int CIN>
+void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, float *dst) {
+    const size_t lds = wgrad_lds(CIN, c->W);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgrad32<CIN>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    const int nchunks = (NP + kChunk - 1) / kChunk;
+    const int nb = std::min(c->wblocks, nchunks);
+    hipLaunchKernelGGL((k_wgrad32<CIN>), dim3(nb), dim3(kThreads), lds, c->st, g, x, c->part, NP, c->H, c->W);
+    NNCHK(hipGetLastError());
+    const int len = kCh * 9 * CIN + kCh;
+    hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256), dim3(256), 0, c->st, c->part, nb, len, dst);
+    NNCHK(hipGetLastError());
+}
+
+double grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint8_t *mask, float *G) {
+    const int HW = c->H * c->W, NP = B * HW, gridc = conv_grid(NP);
+    forward(c, B, x0, c->out);
+    // interior pixel count (mask shared by the images)
+    std::vector<uint8_t> hm(HW);
+    NNCHK(hipMemcpyAsync(hm.data(), mask, HW, hipMemcpyDeviceToHost, c->st));
+    NNCHK(hipStreamSynchronize(c->st));
+    int64_t cnt = 0;
+    for (uint8_t b : hm) cnt += b != 0;
+    const double inv_cnt = 1.0 / (static_cast<double>(B) * std::max<int64_t>(cnt, 1));
+    const int lb = (NP + 255) / 256;
+    hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, c->st, c->out, tgt, mask, c->g4, c->lpart, NP, HW, inv_cnt);
+    // layer 4
+    const int nchunks = (NP + kChunk - 1) / kChunk, nb = std::min(c->wblocks, nchunks);
+    hipLaunchKernelGGL(k_last_wgrad, dim3(nb), dim3(kThreads), 0, c->st, c->g4, c->y3, c->part, NP, c->H, c->W);
+    hipLaunchKernelGGL(k_reduce, dim3((kW4 + 1 + 255) / 256), dim3(256), 0, c->st, c->part, nb, kW4 + 1, G + oW4);
+    hipLaunchKernelGGL(k_last_dgrad, dim3(lb), dim3(256), 0, c->st, c->g4, c->w4, c->y3, c->ga, NP, c->H, c->W);
+    NNCHK(hipGetLastError());
+    // layer 3: g3 = ga
+    wgrad<32>(c, c->ga, c->y2, NP, G + oW3);  // writes W3 then b3 (contiguous in the layout)
+    hipLaunchKernelGGL((k_conv32<32, 1>), dim3(gridc), dim3(kThreads), 0, c->st, c->ga, c->w3t, nullptr, c->y2, c->gb,
+                       NP, c->H, c->W);
+    // layer 2: g2 = gb
+    wgrad<32>(c, c->gb, c->y1, NP, G + oW2);
+    hipLaunchKernelGGL((k_conv32<32, 1>), dim3(gridc), dim3(kThreads), 0, c->st, c->gb, c->w2t, nullptr, c->y1, c->ga,
+                       NP, c->H, c->W);
+    // layer 1: g1 = ga
+    wgrad<4>(c, c->ga, x0, NP, G + oW1);
+    NNCHK(hipGetLastError());
+    std::vector<double> lp(lb);
+    NNCHK(hipMemcpyAsync(lp.data(), c->lpart, sizeof(double) * lb, hipMemcpyDeviceToHost, c->st));
+    NNCHK(hipStreamSynchronize(c->st));
+    double L = 0.0;
+    for (double v : lp) L += v;
+    return L * inv_cnt;
+}
+
+adr_status fail(adrnn_ctx *c, const NNError &e) {
+    if (c) c->err = e.msg;
+    return e.code;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t adrnn_param_count(void) { return kParams; }
+
+adr_status adrnn_create(int32_t H, int32_t W, int32_t max_batch, void *stream, adrnn_ctx **out) {
+    if (!out || H < 3 || W < 3 || max_batch < 1) return ADR_EINVAL;
+    *out = nullptr;
+    adrnn_ctx *c = new adrnn_ctx;
+    try {
+        c->H = H;
+        c->W = W;
+        c->maxB = max_batch;
+        c->st = static_cast<hipStream_t>(stream);
+        const size_t NP = static_cast<size_t>(max_batch) * H * W;
+        if (NP * kCh > (size_t(1) << 31)) throw NNError{ADR_EINVAL, "batch too large"};
+        c->P = nn_alloc<float>(c, kParams);
+        c->m = nn_alloc<float>(c, kParams);
+        c->v = nn_alloc<float>(c, kParams);
+        c->grad = nn_alloc<float>(c, kParams);
+        c->w1 = nn_alloc<bf16_t>(c, kW1);
+        c->w2 = nn_alloc<bf16_t>(c, kW2);
+        c->w3 = nn_alloc<bf16_t>(c, kW2);
+        c->w2t = nn_alloc<bf16_t>(c, kW2);
+        c->w3t = nn_alloc<bf16_t>(c, kW2);
+        c->w4 = nn_alloc<float>(c, kW4);
+        c->y1 = nn_alloc<bf16_t>(c, NP * kCh);
+        c->y2 = nn_alloc<bf16_t>(c, NP * kCh);
+        c->y3 = nn_alloc<bf16_t>(c, NP * kCh);
+        c->ga = nn_alloc<bf16_t>(c, NP * kCh);
+        c->gb = nn_alloc<bf16_t>(c, NP * kCh);
+        c->out = nn_alloc<float>(c, NP);
+        c->g4 = nn_alloc<float>(c, NP);
+        c->part = nn_alloc<float>(c, static_cast<size_t>(c->wblocks) * (kCh * 9 * kCh + kCh));
+        c->lpart = nn_alloc<double>(c, (NP + 255) / 256);
+        c->fn = nn_alloc<double>(c, 2 * static_cast<size_t>(max_batch));
+        c->dlmu = nn_alloc<double>(c, max_batch);
+        if (wgrad_lds(32, W) > 160 * 1024) throw NNError{ADR_EINVAL, "image too wide for the LDS tiles"};
+        std::vector<float> zero(kParams, 0.f);
+        NNCHK(hipMemcpy(c->P, zero.data(), sizeof(float) * kParams, hipMemcpyHostToDevice));
+        NNCHK(hipMemset(c->m, 0, sizeof(float) * kParams));
+        NNCHK(hipMemset(c->v, 0, sizeof(float) * kParams));
+        convert(c);
+        NNCHK(hipStreamSynchronize(c->st));
+    } catch (const NNError &e) {
+        for (void *p : c->owned) (void)hipFree(p);
+        delete c;
+        return e.code;
+    }
+    *out = c;
+    return ADR_OK;
+}
+
+adr_status adrnn_destroy(adrnn_ctx *c) {
+    if (!c) return ADR_OK;
+    (void)hipStreamSynchronize(c->st);
+    for (void *p : c->owned) (void)hipFree(p);
+    delete c;
+    return ADR_OK;
+}
+
+adr_status adrnn_set_params(adrnn_ctx *c, const float *params) {
+    if (!c || !params) return ADR_EINVAL;
+    try {
+        NNCHK(hipMemcpy(c->P, params, sizeof(float) * kParams, hipMemcpyHostToDevice));
+        NNCHK(hipMemset(c->m, 0, sizeof(float) * kParams));
+        NNCHK(hipMemset(c->v, 0, sizeof(float) * kParams));
+        c->step = 0;
+        convert(c);
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_get_params(adrnn_ctx *c, float *params) {
+    if (!c || !params) return ADR_EINVAL;
+    try {
+        NNCHK(hipMemcpyAsync(params, c->P, sizeof(float) * kParams, hipMemcpyDeviceToHost, c->st));
+        NNCHK(hipStreamSynchronize(c->st));
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_pack(adrnn_ctx *c, int32_t B, const double *f, const double *s, const uint8_t *mask,
+                      const double *mu, const double *u_star, void *x0, float *target, double *s_norm) {
+    if (!c || B < 1 || B > c->maxB || !f || !s || !mask || !mu || !x0 || (u_star && !target)) return ADR_EINVAL;
+    try {
+        const int HW = c->H * c->W, NP = B * HW;
+        std::vector<double> lm(B);
+        for (int b = 0; b < B; ++b) {
+            if (!(mu[b] > 0)) throw NNError{ADR_EINVAL, "mu must be > 0"};
+            lm[b] = std::log10(mu[b]);
+        }
+        NNCHK(hipMemcpy(c->dlmu, lm.data(), sizeof(double) * B, hipMemcpyHostToDevice));
+        double *fn = c->fn, *sn = s_norm ? s_norm : c->fn + c->maxB;
+        hipLaunchKernelGGL(k_norms, dim3(B), dim3(kThreads), 0, c->st, f, s, mask, fn, sn, HW);
+        hipLaunchKernelGGL(k_pack, dim3((NP + 255) / 256), dim3(256), 0, c->st, f, s, mask, c->dlmu, fn, sn, u_star,
+                           static_cast<bf16_t *>(x0), target, NP, HW);
+        NNCHK(hipGetLastError());
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_forward(adrnn_ctx *c, int32_t B, const void *x0, float *out) {
+    if (!c || B < 1 || B > c->maxB || !x0 || !out) return ADR_EINVAL;
+    try {
+        forward(c, B, static_cast<const bf16_t *>(x0), out);
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_grads(adrnn_ctx *c, int32_t B, const void *x0, const float *target, const uint8_t *mask,
+                       float *G, double *loss) {
+    if (!c || B < 1 || B > c->maxB || !x0 || !target || !mask || !G) return ADR_EINVAL;
+    try {
+        const double L = grads(c, B, static_cast<const bf16_t *>(x0), target, mask, G);
+        if (loss) *loss = L;
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_adam(adrnn_ctx *c, const float *G, float lr) {
+    if (!c || !G) return ADR_EINVAL;
+    try {
+        c->step += 1;
+        const float c1 = static_cast<float>(1.0 - std::pow(0.9, static_cast<double>(c->step)));
+        const float c2 = static_cast<float>(1.0 - std::pow(0.999, static_cast<double>(c->step)));
+        hipLaunchKernelGGL(k_adam, dim3((kParams + 255) / 256), dim3(256), 0, c->st, c->P, c->m, c->v, G, kParams, lr,
+                           c1, c2);
+        NNCHK(hipGetLastError());
+        convert(c);
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_train_step(adrnn_ctx *c, int32_t B, const void *x0, const float *target, const uint8_t *mask,
+                            float lr, double *loss) {
+    adr_status s = adrnn_grads(c, B, x0, target, mask, c ? c->grad : nullptr, loss);
+    if (s != ADR_OK) return s;
+    return adrnn_adam(c, c->grad, lr);
+}
+
+adr_status adrnn_warm_start(adrnn_ctx *c, int32_t B, const double *s, const double *s_norm, const float *out,
+                            const uint8_t *mask, double *u) {
+    if (!c || B < 1 || B > c->maxB || !s || !s_norm || !out || !mask || !u) return ADR_EINVAL;
+    try {
+        const int HW = c->H * c->W, NP = B * HW;
+        hipLaunchKernelGGL(k_warm, dim3((NP + 255) / 256), dim3(256), 0, c->st, s, s_norm, out, mask, u, NP, HW);
+        NNCHK(hipGetLastError());
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_mfma_probe(const void *A, const void *B, float *D, void *stream) {
+    if (!A || !B || !D) return ADR_EINVAL;
+    hipLaunchKernelGGL(k_probe, dim3(1), dim3(64), 0, static_cast<hipStream_t>(stream),
+                       static_cast<const bf16_t *>(A), static_cast<const bf16_t *>(B), D);
+    return hipGetLastError() == hipSuccess ? ADR_OK : ADR_EDEVICE;
+}
+
+const char *adrnn_last_error(const adrnn_ctx *c) { return c ? c->err.c_str() : ""; }
+
+}  // extern "C"

@@ -12,9 +12,9 @@ from oracle import geometry as geo
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_symbols():
-    txt = open(os.path.join(ROOT, "include", "adr.h")).read()
-    return sorted(set(re.findall(r"\b(adr_[a-z_]+)\s*\(", txt)))
+def header_symbols(name="adr.h", prefix="adr_"):
+    txt = open(os.path.join(ROOT, "include", name)).read()
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_library_exports_every_header_symbol():
@@ -25,6 +25,11 @@ def test_library_exports_every_header_symbol():
     for s in syms:
         assert hasattr(lib, s), s
     assert set(adr.EXPORTS) == set(syms)
+    nn = header_symbols("adrnn.h", "adrnn_")
+    assert "adrnn_forward" in nn and "adrnn_train_step" in nn
+    for s_ in nn:
+        assert hasattr(lib, s_), s_
+    assert set(adr.NN_EXPORTS) == set(nn)
 
 
 @pytest.mark.parametrize("maker", [lambda: W.c1(65), lambda: W.c2(129), lambda: W.data2d(31),

@@ -1,0 +1,124 @@
+"""Warm-start network kernels (BF16 MFMA, FP32 accumulation) vs the FP64
+oracle on BF16-rounded operands (oracle/cnn.py)."""
+import numpy as np
+import pytest
+
+from oracle import cnn
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def bits(x):
+    """float64 array of BF16 values -> int16 bit patterns (torch, device)."""
+    u = np.asarray(x, np.float32).view(np.uint32) >> 16
+    return torch.from_numpy(u.astype(np.uint16).view(np.int16).copy()).cuda()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-300))
+
+
+def test_mfma_lane_layout():
+    print("[case] mfma probe 16x16x16 bf16", flush=True)
+    from paper_2411_11041_amd.adr import mfma_probe
+    rng = np.random.default_rng(0)
+    A = cnn.bf16(rng.standard_normal((16, 16)))
+    B = cnn.bf16(rng.standard_normal((16, 16)))
+    D = mfma_probe(bits(A).reshape(-1), bits(B).reshape(-1)).cpu().numpy().reshape(16, 16)
+    assert np.max(np.abs(D - A @ B)) <= 1e-5 * np.max(np.abs(A @ B))
+
+
+def make_batch(B=3, H=21, W=19, seed=0):
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((B, H, W))
+    s = rng.standard_normal((B, H, W)) * 0.3
+    u = s + 0.05 * rng.standard_normal((B, H, W))
+    mask = np.zeros((H, W), np.uint8)
+    mask[1:-1, 1:-1] = 1
+    mu = 10.0 ** rng.uniform(-3, -1, B)
+    return f, s, u, mask, mu
+
+
+def setup_net(H, W, B, seed=1, bias=True):
+    from paper_2411_11041_amd.adr import Net
+    net = Net(H, W, B)
+    Wt, bt = cnn.init_params(4, seed=seed)
+    if bias:
+        rng = np.random.default_rng(seed + 100)
+        bt = [rng.standard_normal(v.shape) * 0.05 for v in bt]
+    p = cnn.flatten(Wt, bt)
+    net.set_params(p)
+    Wt, bt = cnn.unflatten(p)  # the FP32 values the device holds
+    return net, Wt, bt
+
+
+def dev(a, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dtype).cuda()
+
+
+def test_pack_forward_warm_start():
+    print("[case] pack + forward + warm start, B=3 21x19", flush=True)
+    f, s, u, mask, mu = make_batch()
+    B, H, W = f.shape
+    net, Wt, bt = setup_net(H, W, B)
+    x0, tgt, sn = net.pack(B, dev(f), dev(s), dev(mask, torch.uint8), mu, dev(u))
+    xo, sno = cnn.pack_inputs(f, s, mask, mu)
+    got = x0.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    got = got.view(np.float32).astype(np.float64).reshape(B, H, W, 4)
+    assert np.array_equal(got, xo)  # BF16 bit-exact
+    assert np.allclose(sn.cpu().numpy(), sno, rtol=0, atol=0)
+    assert rel(tgt.cpu().numpy(), cnn.target(u, s, sno, mask)) < 1e-7
+    out = net.forward(B, x0).cpu().numpy().reshape(B, H, W)
+    ref, _ = cnn.forward(xo, Wt, bt, rounding=True)
+    assert rel(out, ref) < 1e-5, rel(out, ref)
+    ug = torch.empty(B * H * W, dtype=torch.float64, device="cuda")
+    net.warm_start(B, dev(s), sn, torch.from_numpy(out.ravel().astype(np.float32)).cuda(), dev(mask, torch.uint8), ug)
+    assert rel(ug.cpu().numpy(), cnn.warm_start(s, sno, out.astype(np.float32).astype(np.float64), mask)) < 1e-14
+    net.close()
+
+
+def test_gradients_match_oracle():
+    print("[case] grads B=3 21x19", flush=True)
+    f, s, u, mask, mu = make_batch(seed=3)
+    B, H, W = f.shape
+    net, Wt, bt = setup_net(H, W, B, seed=4)
+    x0, tgt, sn = net.pack(B, dev(f), dev(s), dev(mask, torch.uint8), mu, dev(u))
+    g, loss = net.grads(B, x0, tgt, dev(mask, torch.uint8))
+    xo, sno = cnn.pack_inputs(f, s, mask, mu)
+    L, dW, db, _ = cnn.loss_and_grads(xo, cnn.target(u, s, sno, mask), mask, Wt, bt, rounding=True)
+    gW, gb = cnn.unflatten(g.cpu().numpy())
+    assert abs(loss - L) <= 1e-5 * L
+    for l in range(4):
+        assert rel(gW[l], dW[l]) < 1e-4, (l, rel(gW[l], dW[l]))
+        assert rel(gb[l], db[l]) < 1e-4, (l, rel(gb[l], db[l]))
+    net.close()
+
+
+def test_adam_step_matches_oracle():
+    print("[case] adam step", flush=True)
+    f, s, u, mask, mu = make_batch(seed=5)
+    B, H, W = f.shape
+    net, Wt, bt = setup_net(H, W, B, seed=6)
+    p0 = net.get_params().astype(np.float64)
+    x0, tgt, sn = net.pack(B, dev(f), dev(s), dev(mask, torch.uint8), mu, dev(u))
+    net.train_step(B, x0, tgt, dev(mask, torch.uint8), 1e-4)
+    p1 = net.get_params().astype(np.float64)
+    xo, sno = cnn.pack_inputs(f, s, mask, mu)
+    _, dW, db, _ = cnn.loss_and_grads(xo, cnn.target(u, s, sno, mask), mask, Wt, bt, rounding=True)
+    params = Wt + bt
+    grads = dW + db
+    state = ([np.zeros_like(v) for v in params], [np.zeros_like(v) for v in params], 0)
+    newp, _ = cnn.adam(params, grads, state, lr=1e-4)
+    ref = cnn.flatten(newp[:4], newp[4:]).astype(np.float64)
+    # elements with a gradient at rounding level may take either sign: compare the update
+    upd, upd_ref = p1 - p0, ref - p0
+    agree = np.mean(np.sign(upd) == np.sign(upd_ref))
+    assert agree > 0.99 and rel(upd, upd_ref) < 0.05
+    net.close()
