@@ -110,6 +110,13 @@ adr_status adr_layout(const adr_ctx *ctx, int64_t *offsets);
 adr_status adr_counts(const adr_ctx *ctx, int64_t *grid_unknowns, int64_t *lines_b,
                       int64_t *lines_g, int64_t *line_unknowns_b, int64_t *line_unknowns_g);
 
+/* New coefficients and sources on the same curves: probs (n_probs = the
+ * set-up's count) must have the set-up's grids and domains; beta is not read
+ * (the traced curves are kept); mu, sigma and f replace the old ones.  The
+ * loads of eq. (17) and |Phi(0)| are recomputed.  Errors: ADR_EINVAL (count,
+ * grid or domain mismatch, mu <= 0), ADR_ENONFINITE (f).  Synchronises. */
+adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs);
+
 /* Stationary solve (Sec. 2 limit, eq. (10) sweeps).  u: device FP64, packed
  * layout; in: initial iterate, out: last iterate.  Each sweep k maps U_k to
  * U_{k+1} = Phi(U_k); an instance stops at the first FP64 sweep with

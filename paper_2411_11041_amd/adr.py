@@ -18,7 +18,7 @@ ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE, ADR_EBETA, ADR_ENONFINITE, ADR_ENOT
 DOM_BOX, DOM_DISC, DOM_POLYGON = 0, 1, 2
 PREC_FP64, PREC_FP32_LINES = 0, 1
 
-EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_split_iterate", "adr_time_step",
+EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_kernel_times",
            "adr_destroy", "adr_last_error")
 
@@ -67,6 +67,7 @@ def load():
     lib.adr_setup.argtypes = [P(Problem), i32, P(Options), P(vp)]
     lib.adr_layout.argtypes = [vp, P(i64)]
     lib.adr_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64), P(i64)]
+    lib.adr_update.argtypes = [vp, P(Problem), i32]
     lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
     lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32]
     lib.adr_residual.argtypes = [vp, vp, P(dbl)]
@@ -104,17 +105,7 @@ class Solver:
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
         self._keep = []
-        arr = (Problem * len(problems))()
-        for k, p in enumerate(problems):
-            b1 = np.ascontiguousarray(p.beta1, np.float64).ravel()
-            b2 = np.ascontiguousarray(p.beta2, np.float64).ravel()
-            f = np.ascontiguousarray(p.f, np.float64).ravel()
-            dp = np.ascontiguousarray(np.asarray(p.dom_params, np.float64).ravel())
-            self._keep += [b1, b2, f, dp]
-            a, b, c, d = p.box
-            arr[k] = Problem(p.nx, p.ny, a, b, c, d, int(p.domain), int(dp.size),
-                             _dptr(dp) if dp.size else None, float(p.mu), float(p.sigma),
-                             _dptr(b1), _dptr(b2), _dptr(f))
+        arr = self._structs(problems)
         if stream is None and not host_only:
             import torch
             stream = torch.cuda.current_stream().cuda_stream
@@ -129,6 +120,26 @@ class Solver:
             raise ADRError(st, self.lib.adr_last_error(None).decode())
         self.host_only = host_only
         self.precision = precision
+
+    def _structs(self, problems):
+        arr = (Problem * len(problems))()
+        for k, p in enumerate(problems):
+            b1 = np.ascontiguousarray(p.beta1, np.float64).ravel()
+            b2 = np.ascontiguousarray(p.beta2, np.float64).ravel()
+            f = np.ascontiguousarray(p.f, np.float64).ravel()
+            dp = np.ascontiguousarray(np.asarray(p.dom_params, np.float64).ravel())
+            self._keep += [b1, b2, f, dp]
+            a, b, c, d = p.box
+            arr[k] = Problem(p.nx, p.ny, a, b, c, d, int(p.domain), int(dp.size),
+                             _dptr(dp) if dp.size else None, float(p.mu), float(p.sigma),
+                             _dptr(b1), _dptr(b2), _dptr(f))
+        return arr
+
+    def update(self, problems):
+        """New mu, sigma, f on the same curves (same grids and domains)."""
+        self._keep = []
+        arr = self._structs(list(problems))
+        self._check(self.lib.adr_update(self.ctx, arr, len(problems)))
 
     def _check(self, st, ok=(ADR_OK,)):
         if st not in ok:

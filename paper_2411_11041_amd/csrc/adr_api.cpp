@@ -99,6 +99,11 @@ struct adr_ctx {
     std::vector<double> mu, sg;
     std::string err;
     std::vector<adr::Family> geo[2];  // per instance, for export
+    std::vector<adr::Grid> grids;     // per instance
+    std::vector<adr_problem> shape;   // per instance: grid and domain (pointers cleared)
+    std::vector<int64_t> noffB;       // first beta-line node of each instance
+    double *L64 = nullptr;            // packed loads (mutable views of the line tables)
+    float *L32 = nullptr;
     // timing
     struct Tick {
         int prec, cls;
@@ -431,17 +436,19 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     if (f == 0) { w[gk] = G[i].wk[k]; L[gk] = G[i].Lk[k]; }
                 }
             }
+            if (f == 0) C->noffB = noff;
             const int *d_loff = upload(loff, own, st), *d_lcnt = upload(lcnt, own, st);
             const int *d_linst = upload(linst, own, st), *d_cell = upload(cell, own, st);
+            double *dL64 = f == 0 ? upload(L, own, st) : nullptr;
+            float *dL32 = f == 0 ? upload(to_type<float>(L), own, st) : nullptr;
+            if (f == 0) { C->L64 = dL64; C->L32 = dL32; }
             F.a64 = adr::LineArgs<double>{d_loff, d_lcnt, d_linst, C->inst_nx, d_cell,
                                           upload(lx, own, st), upload(ly, own, st), upload(h, own, st),
-                                          f == 0 ? upload(w, own, st) : nullptr,
-                                          f == 0 ? upload(L, own, st) : nullptr};
+                                          f == 0 ? upload(w, own, st) : nullptr, dL64};
             F.a32 = adr::LineArgs<float>{d_loff, d_lcnt, d_linst, C->inst_nx, d_cell,
                                          upload(to_type<float>(lx), own, st), upload(to_type<float>(ly), own, st),
                                          upload(to_type<float>(h), own, st),
-                                         f == 0 ? upload(to_type<float>(w), own, st) : nullptr,
-                                         f == 0 ? upload(to_type<float>(L), own, st) : nullptr};
+                                         f == 0 ? upload(to_type<float>(w), own, st) : nullptr, dL32};
             // scatter records
             std::vector<int> rk(4 * static_cast<size_t>(npad), -1);
             std::vector<double> ra(4 * static_cast<size_t>(npad), 0.0), rb(4 * static_cast<size_t>(npad), 0.0);
@@ -464,6 +471,13 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             for (int i = 0; i < n; ++i) C->geo[f].push_back(G[i].fam[f]);
         }
 
+        for (int i = 0; i < n; ++i) {
+            C->grids.push_back(G[i].g);
+            adr_problem sh = probs[i];
+            sh.beta1 = sh.beta2 = sh.f = nullptr;
+            sh.dom_params = nullptr;
+            C->shape.push_back(sh);
+        }
         // state scratch (zeroed: non-interior nodes must read as zero)
         C->Uh64 = dalloc<double>(C->n_grid, own);
         C->Z64 = dalloc<double>(C->n_grid, own);
@@ -527,6 +541,64 @@ adr_status adr_counts(const adr_ctx *ctx, int64_t *grid_unknowns, int64_t *lines
     if (line_unknowns_b) *line_unknowns_b = ctx->fam[0].n_unknowns;
     if (line_unknowns_g) *line_unknowns_g = ctx->fam[1].n_unknowns;
     return ADR_OK;
+}
+
+adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs) {
+    if (!ctx || !probs) return ADR_EINVAL;
+    if (ctx->opt.host_only || n_probs != ctx->n_inst) {
+        ctx->err = "adr_update needs the set-up's instance count on a device context";
+        return ADR_EINVAL;
+    }
+    try {
+        const int n = ctx->n_inst;
+        for (int i = 0; i < n; ++i) {
+            const adr_problem &p = probs[i], &q = ctx->shape[i];
+            if (p.nx != q.nx || p.ny != q.ny || p.a != q.a || p.b != q.b || p.c != q.c || p.d != q.d ||
+                p.domain != q.domain)
+                throw Error{ADR_EINVAL, "instance " + std::to_string(i) + ": grid or domain differs from the set-up"};
+            if (!(p.mu > 0.0) || !(p.sigma >= 0.0) || !p.f)
+                throw Error{ADR_EINVAL, "instance " + std::to_string(i) + ": mu > 0, sigma >= 0 and f are required"};
+            const size_t nn = static_cast<size_t>(p.nx) * p.ny;
+            for (size_t k = 0; k < nn; ++k)
+                if (!std::isfinite(p.f[k])) throw Error{ADR_ENONFINITE, "non-finite f"};
+        }
+        const int64_t nB = ctx->fam[0].n_nodes;
+        std::vector<double> L(nB, 0.0);
+        {
+            std::atomic<int> next{0};
+            unsigned nt = std::max(1u, std::min<unsigned>(std::thread::hardware_concurrency(), 16u));
+            nt = std::min<unsigned>(nt, static_cast<unsigned>(n));
+            std::vector<std::thread> pool;
+            for (unsigned t = 0; t < nt; ++t)
+                pool.emplace_back([&] {
+                    std::vector<double> Li;
+                    for (int i = next++; i < n; i = next++) {
+                        adr::load_from_positions(ctx->grids[i], ctx->geo[0][i], probs[i].f, Li);
+                        std::copy(Li.begin(), Li.end(), L.begin() + ctx->noffB[i]);
+                    }
+                });
+            for (auto &th : pool) th.join();
+        }
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        HIPCHK(hipMemcpy(ctx->L64, L.data(), sizeof(double) * nB, hipMemcpyHostToDevice));
+        std::vector<float> L32(L.begin(), L.end());
+        HIPCHK(hipMemcpy(ctx->L32, L32.data(), sizeof(float) * nB, hipMemcpyHostToDevice));
+        for (int i = 0; i < n; ++i) {
+            ctx->mu[i] = probs[i].mu;
+            ctx->sg[i] = probs[i].sigma;
+        }
+        fill_params(ctx->par_h, n, kSlotStep, ctx->mu, ctx->sg, ctx->opt.theta, ctx->opt.dt);
+        fill_params(ctx->par_h, n, kSlotLin, ctx->mu, ctx->sg, ctx->opt.theta, ctx->opt.dt);
+        fill_params(ctx->par_h, n, kSlotGuess, ctx->mu, ctx->sg, 1.0, 1.0);
+        HIPCHK(hipMemcpy(ctx->par, ctx->par_h.data(), sizeof(double) * ctx->par_h.size(), hipMemcpyHostToDevice));
+        ctx->last_theta = -1.0;  // the time-step slot is refilled on its next use
+        ctx->sweep64(kSlotStep, ctx->Z64, ctx->Z64, 3, ctx->never);
+        ctx->norm(0, 0.0, 1);
+        HIPCHK(hipStreamSynchronize(ctx->st));
+        return ADR_OK;
+    } catch (const Error &e) {
+        return fail_ctx(ctx, e);
+    }
 }
 
 adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol, int32_t *iters,

@@ -571,6 +571,21 @@ void compute_load(const adr_problem &p, InstanceGeo &G) {
         }
 }
 
+void load_from_positions(const Grid &g, const Family &F, const double *f, std::vector<double> &L) {
+    // same chords and load as compute_load, the chords recomputed from the nodes
+    const size_t n = F.x.size();
+    L.assign(n, 0.0);
+    std::vector<double> fk(n);
+    for (size_t k = 0; k < n; ++k) fk[k] = g.interp(f, F.x[k], F.y[k]);
+    const int nl = static_cast<int>(F.off.size()) - 1;
+    for (int l = 0; l < nl; ++l)
+        for (int64_t k = F.off[l] + 1; k + 1 < F.off[l + 1]; ++k) {
+            const double hl = std::hypot(F.x[k] - F.x[k - 1], F.y[k] - F.y[k - 1]);
+            const double hr = std::hypot(F.x[k + 1] - F.x[k], F.y[k + 1] - F.y[k]);
+            L[k] = (hl + hr) / 3.0 * fk[k] + hl / 6.0 * fk[k - 1] + hr / 6.0 * fk[k + 1];
+        }
+}
+
 void rebuild_for_source(const InstanceGeo &base, const adr_problem &p, InstanceGeo &G) {
     if (!(p.mu > 0.0)) fail(ADR_EINVAL, "mu must be > 0");
     if (!(p.sigma >= 0.0)) fail(ADR_EINVAL, "sigma must be >= 0");

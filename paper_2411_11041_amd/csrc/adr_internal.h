@@ -59,6 +59,8 @@ struct InstanceGeo {
 void build_instance(const adr_problem &p, InstanceGeo &out);
 // Load vector of the beta-curves for the source of p (curves already traced).
 void compute_load(const adr_problem &p, InstanceGeo &G);
+// Load vector of a traced beta family for the nodal source f (chords from the nodes).
+void load_from_positions(const Grid &g, const Family &F, const double *f, std::vector<double> &L);
 // Copy of base (same grid, domain and beta) with the coefficients and source of p.
 void rebuild_for_source(const InstanceGeo &base, const adr_problem &p, InstanceGeo &out);
 

@@ -1,0 +1,158 @@
+"""Learned warm start driver: dataset generation with the splitting solver,
+training of the network (include/adrnn.h kernels) and the warm-started solve.
+
+Every numerical step runs in the HIP library; this module orchestrates the
+calls and moves device buffers (torch tensors) between them.
+
+Workload: 257 x 257 unit square, C2's divergence-free beta, sigma = 1,
+mu log-uniform in [1e-3, 1e-1], a mixture of 1..8 Gaussians as source
+(seeded per sample).  All samples share the grid, the domain and beta, so one
+solver context (one set of traced curves) serves every batch: adr_update swaps
+in each batch's mu and f.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+import workloads as W
+
+from .adr import Net, Solver
+
+
+class Workload:
+    def __init__(self, n=257, batch=128, precision="fp32", fp32_sweeps=3, dt=0.05, graph=True):
+        import torch
+        self.n = n
+        self.batch = batch
+        grid = W._grid(n)
+        _, self.b1, self.b2 = W.curved_stream(*grid)
+        self.HW = n * n
+        mask = np.zeros((n, n), np.uint8)
+        mask[1:-1, 1:-1] = 1
+        self.mask_np = mask
+        self.mask = torch.from_numpy(mask.ravel()).cuda()
+        self.kw = dict(precision=precision, fp32_sweeps=fp32_sweeps, theta=1.0, dt=dt, graph=graph)
+        self.solver = None
+
+    def problems(self, seeds):
+        out = []
+        for s in seeds:
+            p = W.c5_sample(int(s), n=self.n)
+            p.beta1, p.beta2 = self.b1, self.b2  # shared arrays: one set of curves
+            out.append(p)
+        return out
+
+    def _bind(self, probs):
+        if self.solver is None or self.solver.n != len(probs):
+            if self.solver is not None:
+                self.solver.close()
+            self.solver = Solver(probs, **self.kw)
+        else:
+            self.solver.update(probs)
+        return self.solver
+
+    def solve_batch(self, seeds, tol, max_iters=2000, start=None):
+        """Returns u (device, B*HW), iters, rel, seconds.  start: None (zero) or a tensor."""
+        import torch
+        probs = self.problems(seeds)
+        s = self._bind(probs)
+        u = torch.zeros(len(probs) * self.HW, dtype=torch.float64, device="cuda") if start is None else start
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, rel, st = s.split_iterate(u, max_iters, tol)
+        torch.cuda.synchronize()
+        return u, it, rel, time.perf_counter() - t0
+
+    def f_tensor(self, probs):
+        import torch
+        return torch.from_numpy(np.concatenate([p.f.ravel() for p in probs])).cuda()
+
+    def generate(self, net, seeds, tol=1e-10, log=None):
+        """Network inputs x0 (BF16 bits) and targets for the given seeds."""
+        import torch
+        N = len(seeds)
+        x_all = torch.empty(N * self.HW * 4, dtype=torch.int16, device="cuda")
+        t_all = torch.empty(N * self.HW, dtype=torch.float32, device="cuda")
+        for c0 in range(0, N, self.batch):
+            cs = seeds[c0:c0 + self.batch]
+            B = len(cs)
+            probs = self.problems(cs)
+            s = self._bind(probs)
+            u = torch.zeros(B * self.HW, dtype=torch.float64, device="cuda")
+            it, rel, _ = s.split_iterate(u, 3000, tol)
+            g = torch.zeros_like(u)
+            s.initial_guess(g)
+            x0, tgt, _ = net.pack(B, self.f_tensor(probs), g, self.mask, [p.mu for p in probs], u_star=u)
+            x_all[c0 * self.HW * 4:(c0 + B) * self.HW * 4] = x0
+            t_all[c0 * self.HW:(c0 + B) * self.HW] = tgt
+            if log:
+                log(f"generated {c0 + B}/{N} (sweeps max {int(it.max())}, rel max {rel.max():.1e})")
+        return x_all, t_all
+
+    def warm_started(self, net, seeds, tol, max_iters=2000, use_net=True):
+        """Solve from the eq. (11) iterate, corrected by the network when use_net.
+
+        The splitting residual judges the start: where the network's start has
+        a larger FP64 update than the eq. (11) iterate, that instance falls
+        back to the eq. (11) iterate.  Timed from the first call (inference
+        included).  Returns u, iters, rel, seconds, fallbacks.
+        """
+        import torch
+        probs = self.problems(seeds)
+        B = len(probs)
+        s = self._bind(probs)
+        f = self.f_tensor(probs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = torch.zeros(B * self.HW, dtype=torch.float64, device="cuda")
+        s.initial_guess(g)
+        fallback = 0
+        if use_net:
+            x0, _, sn = net.pack(B, f, g, self.mask, [p.mu for p in probs])
+            out = net.forward(B, x0)
+            u = torch.empty_like(g)
+            net.warm_start(B, g, sn, out, self.mask, u)
+            r_net = s.residual(u)
+            r_s = s.residual(g)
+            for b in np.nonzero(~(r_net < r_s))[0]:
+                u[b * self.HW:(b + 1) * self.HW] = g[b * self.HW:(b + 1) * self.HW]
+                fallback += 1
+        else:
+            u = g
+        it, rel, _ = s.split_iterate(u, max_iters, tol)
+        torch.cuda.synchronize()
+        return u, it, rel, time.perf_counter() - t0, fallback
+
+
+def train(net, x_all, t_all, mask, N, HW, epochs, batch=32, lr=1e-3, seed=0, log=None):
+    """Adam on shuffled minibatches; returns the per-epoch mean losses."""
+    import torch
+    rng = np.random.default_rng(seed)
+    xv = x_all.view(N, HW * 4)
+    tv = t_all.view(N, HW)
+    losses = []
+    for ep in range(epochs):
+        perm = rng.permutation(N)
+        tot, nb = 0.0, 0
+        for b0 in range(0, N - batch + 1, batch):
+            idx = torch.from_numpy(perm[b0:b0 + batch]).cuda()
+            xb = xv.index_select(0, idx).contiguous().view(-1)
+            tb = tv.index_select(0, idx).contiguous().view(-1)
+            tot += net.train_step(batch, xb, tb, mask, lr)
+            nb += 1
+        losses.append(tot / max(nb, 1))
+        if log:
+            log(f"epoch {ep + 1}/{epochs} loss {losses[-1]:.3e}")
+    return losses
+
+
+def he_init(seed=0, c_in=4):
+    """He-normal FP32 weights, zero biases, in the flat layout of include/adrnn.h."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for c_out, cin in ((32, c_in), (32, 32), (32, 32), (1, 32)):
+        w = rng.standard_normal((c_out, 3, 3, cin)) * np.sqrt(2.0 / (9 * cin))
+        parts += [w.astype(np.float32).ravel(), np.zeros(c_out, np.float32)]
+    return np.concatenate(parts)

@@ -201,3 +201,33 @@ def test_graph_replay_matches_eager():
     assert st == 0 and rel[0] <= 1e-9
     eager.close()
     graph.close()
+
+
+def test_update_swaps_coefficients_on_same_curves():
+    """adr_update replaces mu, sigma and f on the traced curves: the next sweeps
+    equal the oracle of the new problems, and the set-up's sizes are kept."""
+    print("[case] adr_update c5 65 x2 fp64 6 sweeps", flush=True)
+    a = [W.c5_sample(s, n=65) for s in (0, 1)]
+    b = [W.c5_sample(s, n=65) for s in (7, 8)]
+    for p in b:
+        p.beta1, p.beta2 = a[0].beta1, a[0].beta2
+    for p in a[1:]:
+        p.beta1, p.beta2 = a[0].beta1, a[0].beta2
+    s = solver(a, precision="fp64", theta=1.0, dt=0.05)
+    off = s.layout()
+    u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    s.split_iterate(u, 3, 0.0)
+    s.update(b)
+    u.zero_()
+    iters, rel, st = s.split_iterate(u, 6, 0.0)
+    torch.cuda.synchronize()
+    U = u.cpu().numpy()
+    for i, p in enumerate(b):
+        o = Oracle(p)
+        Ui = o.zero_field()
+        for _ in range(6):
+            Ui = o.step(Ui, 1.0, 0.05)
+        assert rel_l2(U[off[i]:off[i + 1]], Ui) < 1e-11, i
+    with pytest.raises(Exception):
+        s.update(b[:1])
+    s.close()
