@@ -137,7 +137,9 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
 adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32_t nsteps);
 
 /* rel_res[i] = |Phi(U) - U|_2 / |Phi(0)|_2 of the stationary sweep for the given
- * u (device FP64, unchanged), in FP64.  rel_res: host, n_probs. */
+ * u (device FP64, unchanged), in FP64.  rel_res: host, n_probs.  Returns
+ * ADR_ENONFINITE when some entry is not finite; rel_res is written for every
+ * instance all the same. */
 adr_status adr_residual(adr_ctx *ctx, const double *u, double *rel_res);
 
 /* Initial iterate of eq. (11): s(u0, v) = <l, v> solved on every beta-curve,

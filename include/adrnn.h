@@ -8,7 +8,8 @@
  * remains the judge of the result (adr_split_iterate's residual).
  *
  * Network: four 3x3 convolutions with zero padding, 4 -> 32 -> 32 -> 32 -> 1
- * channels, ReLU after the first three.  Tensors are NHWC over B images of
+ * channels, dilations 1, 2, 4, 8 (tap (dy, dx) of layer l reads the pixel
+ * d_l (dy, dx) away; a 31 x 31 receptive field), ReLU after the first three.  Tensors are NHWC over B images of
  * H x W pixels (pixel p = y*W + x, the solver's grid layout).  Stored
  * activations and matrix-core operands are BF16 (round to nearest even);
  * products accumulate in FP32; master weights, Adam moments, biases, the

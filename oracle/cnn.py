@@ -1,7 +1,9 @@
 """FP64 reference of the warm-start network (test infrastructure).
 
 Four 3x3 convolutions with "same" zero padding: C_in -> 32 -> 32 -> 32 -> 1,
-ReLU after the first three, biases in FP32/FP64.  Activations are NHWC.  The
+dilations DIL = (1, 2, 4, 8) (tap (dy, dx) reads the pixel d*(dy, dx) away;
+receptive field 31 pixels), ReLU after the first three, biases in FP32/FP64.
+Activations are NHWC.  The
 arithmetic is FP64; the values that the device keeps in BF16 are rounded to
 BF16 (round to nearest even) at the same points:
   * the input tensor x0 and every weight tensor used by a convolution,
@@ -20,6 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 CH = 32
+DIL = (1, 2, 4, 8)
 
 
 def bf16(x):
@@ -47,45 +50,44 @@ def init_params(c_in=4, seed=0):
     return W, b
 
 
-def conv(x, Wt, bias):
-    """z[b,y,x,n] = sum_{dy,dx,c} W[n,dy+1,dx+1,c] x[b,y+dy,x+dx,c] + bias[n] (zero padding)."""
+def _shift(x, oy, ox):
+    """x shifted so that out[y, x] = x[y + oy, x + ox] (zero outside)."""
     B, H, Wd, C = x.shape
-    xp = np.zeros((B, H + 2, Wd + 2, C))
-    xp[:, 1:-1, 1:-1] = x
-    z = np.zeros((B, H, Wd, Wt.shape[0]))
+    out = np.zeros_like(x)
+    ys, ye = max(0, -oy), min(H, H - oy)
+    xs, xe = max(0, -ox), min(Wd, Wd - ox)
+    if ys < ye and xs < xe:
+        out[:, ys:ye, xs:xe] = x[:, ys + oy:ye + oy, xs + ox:xe + ox]
+    return out
+
+
+def conv(x, Wt, bias, d=1):
+    """z[b,y,x,n] = sum_{dy,dx,c} W[n,dy+1,dx+1,c] x[b,y+d*dy,x+d*dx,c] + bias[n] (zero padding)."""
+    z = np.zeros(x.shape[:3] + (Wt.shape[0],))
     for dy in range(3):
         for dx in range(3):
-            patch = xp[:, dy:dy + H, dx:dx + Wd, :]
-            z += patch @ Wt[:, dy, dx, :].T
+            z += _shift(x, d * (dy - 1), d * (dx - 1)) @ Wt[:, dy, dx, :].T
     return z + bias
 
 
-def conv_transpose(g, Wt):
-    """dL/dx for z = conv(x, W): dx[b,y,x,c] = sum_{dy,dx,n} W[n,dy,dx,c] g[b,y-dy+1,x-dx+1,n]."""
-    B, H, Wd, N = g.shape
-    gp = np.zeros((B, H + 2, Wd + 2, N))
-    gp[:, 1:-1, 1:-1] = g
-    dx_ = np.zeros((B, H, Wd, Wt.shape[3]))
+def conv_transpose(g, Wt, d=1):
+    """dL/dx for z = conv(x, W, d): dx[p] = sum_{tap,n} W[n,tap,c] g[p - d*off(tap), n]."""
+    dx_ = np.zeros(g.shape[:3] + (Wt.shape[3],))
     for dy in range(3):
         for dx in range(3):
-            # x[p] feeds z[p - (dy-1, dx-1)] through tap (dy, dx)
-            patch = gp[:, 2 - dy:2 - dy + H, 2 - dx:2 - dx + Wd, :]
-            dx_ += patch @ Wt[:, dy, dx, :]
+            dx_ += _shift(g, -d * (dy - 1), -d * (dx - 1)) @ Wt[:, dy, dx, :]
     return dx_
 
 
-def conv_wgrad(g, x):
-    """dL/dW[n,dy,dx,c] = sum_{b,p} g[b,p,n] x[b,p+(dy-1,dx-1),c]; dL/db[n] = sum g."""
-    B, H, Wd, N = g.shape
+def conv_wgrad(g, x, d=1):
+    """dL/dW[n,dy,dx,c] = sum_{b,p} g[b,p,n] x[b,p+d*(dy-1,dx-1),c]; dL/db[n] = sum g."""
+    N = g.shape[3]
     C = x.shape[3]
-    xp = np.zeros((B, H + 2, Wd + 2, C))
-    xp[:, 1:-1, 1:-1] = x
     dW = np.zeros((N, 3, 3, C))
     gf = g.reshape(-1, N)
     for dy in range(3):
         for dx in range(3):
-            patch = xp[:, dy:dy + H, dx:dx + Wd, :].reshape(-1, C)
-            dW[:, dy, dx, :] = gf.T @ patch
+            dW[:, dy, dx, :] = gf.T @ _shift(x, d * (dy - 1), d * (dx - 1)).reshape(-1, C)
     return dW, gf.sum(axis=0)
 
 
@@ -95,10 +97,10 @@ def forward(x0, W, b, rounding=True):
     x = r(x0)
     acts = [x]
     for l in range(3):
-        z = conv(x, r(W[l]), b[l])
+        z = conv(x, r(W[l]), b[l], DIL[l])
         x = r(np.maximum(z, 0.0))
         acts.append(x)
-    out = conv(x, r(W[3]), b[3])[..., 0]
+    out = conv(x, r(W[3]), b[3], DIL[3])[..., 0]
     return out, acts
 
 
@@ -115,10 +117,10 @@ def loss_and_grads(x0, target, mask, W, b, rounding=True):
     dW = [None] * 4
     db = [None] * 4
     for l in (3, 2, 1, 0):
-        dW[l], db[l] = conv_wgrad(g, acts[l])
+        dW[l], db[l] = conv_wgrad(g, acts[l], DIL[l])
         if l == 0:
             break
-        dy = conv_transpose(g, r(W[l]))
+        dy = conv_transpose(g, r(W[l]), DIL[l])
         g = r(dy * (acts[l] > 0))
     return loss, dW, db, out
 

@@ -168,9 +168,12 @@ class Solver:
     def time_step(self, u, theta, dt, nsteps):
         self._check(self.lib.adr_time_step(self.ctx, _device_ptr(u), float(theta), float(dt), int(nsteps)))
 
-    def residual(self, u):
+    def residual(self, u, allow_nonfinite=False):
+        """Per-instance relative residual; with allow_nonfinite a non-finite
+        entry is returned (as inf/nan) instead of raised."""
         rel = np.zeros(self.n, np.float64)
-        self._check(self.lib.adr_residual(self.ctx, _device_ptr(u), _dptr(rel)))
+        ok = (ADR_OK, ADR_ENONFINITE) if allow_nonfinite else (ADR_OK,)
+        self._check(self.lib.adr_residual(self.ctx, _device_ptr(u), _dptr(rel)), ok)
         return rel
 
     def initial_guess(self, u):

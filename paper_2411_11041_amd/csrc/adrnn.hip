@@ -8,6 +8,8 @@
 // A[l%16][4(l/16) .. 4(l/16)+3] and B[4(l/16) .. +3][l%16]; it receives
 // D[4(l/16) + v][l%16], v = 0..3.  NHWC activations make a lane's four K
 // values (four consecutive channels of one pixel) one 8-byte load.
+// Layer l's taps are dilated by kDil[l]: tap (dy, dx) reads the pixel
+// (y + d dy, x + d dx), zero outside the image.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,6 +32,7 @@ constexpr int kW1 = 32 * 9 * 4, kW2 = 32 * 9 * 32, kW4 = 9 * 32;
 constexpr int oW1 = 0, ob1 = oW1 + kW1, oW2 = ob1 + 32, ob2 = oW2 + kW2, oW3 = ob2 + 32, ob3 = oW3 + kW2,
               oW4 = ob3 + 32, ob4 = oW4 + kW4, kParams = ob4 + 1;
 constexpr int kChunk = 256;  // pixels per weight-gradient chunk
+constexpr int kDil[4] = {1, 2, 4, 8};
 
 __device__ __forceinline__ bf16_t f2bf(float f) {
     unsigned u = __float_as_uint(f);
@@ -51,7 +54,7 @@ template <int CIN, int EPI>
 __global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ x, const bf16_t *__restrict__ Wg,
                                                      const float *__restrict__ bias,
                                                      const bf16_t *__restrict__ ymask, bf16_t *__restrict__ y,
-                                                     int NP, int H, int W) {
+                                                     int NP, int H, int W, int d) {
     constexpr int KT = CIN == 4 ? 12 : 9;  // taps, padded to whole K chunks for CIN = 4
     __shared__ __align__(16) bf16_t Ws[kCh * KT * CIN];
     for (int e = threadIdx.x; e < kCh * KT * CIN; e += kThreads) {
@@ -72,9 +75,9 @@ __global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ 
         if constexpr (CIN == 32) {
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
-                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
                 const bool ok = pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-                const bf16_t *src = x + static_cast<size_t>(gp + dy * W + dx) * CIN;
+                const bf16_t *src = x + static_cast<ptrdiff_t>(gp + dy * W + dx) * CIN;
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc) {
                     const v4i16 a = ok ? *reinterpret_cast<const v4i16 *>(src + cc * 16 + g * 4) : zero;
@@ -89,9 +92,9 @@ __global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ 
 #pragma unroll
             for (int kc = 0; kc < 3; ++kc) {
                 const int tap = kc * 4 + g;  // this lane group's tap
-                const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
                 const bool ok = tap < 9 && pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-                const v4i16 a = ok ? *reinterpret_cast<const v4i16 *>(x + static_cast<size_t>(gp + dy * W + dx) * 4)
+                const v4i16 a = ok ? *reinterpret_cast<const v4i16 *>(x + static_cast<ptrdiff_t>(gp + dy * W + dx) * 4)
                                    : zero;
                 const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * 4]);
                 const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * 4]);
@@ -118,20 +121,22 @@ __global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ 
 }
 
 // ------------------------------------------------------------------ weight gradient (MFMA)
-// part[blk][ (n*9 + tap)*CIN + c ] = sum over the block's pixels of g[p][n] x[p + off(tap)][c]
+// part[blk][ (n*9 + tap)*CIN + c ] = sum over the block's pixels of g[p][n] x[p + d off(tap)][c]
 // and part[blk][32*9*CIN + n] = sum g[p][n].  g: [NP][32], x: [NP][CIN] BF16.
+// A chunk of kChunk consecutive pixels reads x in three bands (tap rows
+// dy = -1, 0, 1), each kChunk + 2d pixels long, staged channel-major in LDS.
 template <int CIN>
 __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__ gsrc, const bf16_t *__restrict__ x,
-                                                      float *__restrict__ part, int NP, int H, int W) {
+                                                      float *__restrict__ part, int NP, int H, int W, int d) {
     constexpr int NCOL = 9 * CIN;                 // (tap, c) columns
     constexpr int NJT = (NCOL + 15) / 16;         // column tiles
     constexpr int NT = 2 * NJT;                   // output tiles (2 row tiles of 16 channels)
     constexpr int TPW = (NT + 3) / 4;             // tiles per wave
-    const int halo = W + 1;
-    const int span = kChunk + 2 * halo;
+    const int bspan = kChunk + 2 * d;  // one band
+    const int span = 3 * bspan;
     extern __shared__ __align__(16) unsigned char sm[];
     bf16_t *gT = reinterpret_cast<bf16_t *>(sm);                // [32][kChunk]
-    bf16_t *xT = gT + kCh * kChunk;                             // [CIN][span]
+    bf16_t *xT = gT + kCh * kChunk;                             // [CIN][3][bspan]
     short *pyx = reinterpret_cast<short *>(xT + CIN * span);    // [kChunk][2] (y, x), -1 for no pixel
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, g = lane >> 4;
@@ -150,8 +155,9 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__
             gT[n * kChunk + pl] = gp < NP ? gsrc[static_cast<size_t>(gp) * kCh + n] : bf16_t(0);
         }
         for (int e = threadIdx.x; e < span * CIN; e += kThreads) {
-            const int sl = e / CIN, c = e % CIN;
-            const int gp = c0 - halo + sl;
+            const int sl = e / CIN, c = e % CIN;  // coalesced read of x
+            const int band = sl / bspan, bl = sl - band * bspan;
+            const int gp = c0 + (band - 1) * d * W - d + bl;
             xT[c * span + sl] = (gp >= 0 && gp < NP) ? x[static_cast<size_t>(gp) * CIN + c] : bf16_t(0);
         }
         for (int pl = threadIdx.x; pl < kChunk; pl += kThreads) {
@@ -180,8 +186,8 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__
             const int col = jt * 16 + i;               // B column (tap, c)
             const bool colok = col < NCOL;
             const int tap = colok ? col / CIN : 0, c = colok ? col % CIN : 0;
-            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-            const int off = dy * W + dx;
+            const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            const int off = (tap / 3) * bspan + d + dx;  // band of the tap row, then the shift in the band
             for (int k0 = 0; k0 < kChunk; k0 += 16) {
                 const v4i16 a = *reinterpret_cast<const v4i16 *>(&gT[n * kChunk + k0 + 4 * g]);
                 v4i16 bv;
@@ -190,7 +196,7 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__
                     const int pl = k0 + 4 * g + v;
                     const int yy = pyx[2 * pl], xx = pyx[2 * pl + 1];
                     const bool ok = colok && yy >= 0 && yy + dy >= 0 && yy + dy < H && xx + dx >= 0 && xx + dx < W;
-                    bv[v] = ok ? static_cast<short>(xT[c * span + halo + pl + off]) : short(0);
+                    bv[v] = ok ? static_cast<short>(xT[c * span + off + pl]) : short(0);
                 }
                 acc[q] = mfma(a, bv, acc[q]);
             }
@@ -224,13 +230,13 @@ __global__ void k_reduce(const float *__restrict__ part, int nblk, int len, floa
 
 // ------------------------------------------------------------------ last layer (32 -> 1), VALU
 __global__ void k_last_fwd(const bf16_t *__restrict__ y3, const float *__restrict__ W4, const float *__restrict__ b4,
-                           float *__restrict__ out, int NP, int H, int W) {
+                           float *__restrict__ out, int NP, int H, int W, int d) {
     const int gp = blockIdx.x * blockDim.x + threadIdx.x;
     if (gp >= NP) return;
     const int HW = H * W, p = gp % HW, py = p / W, px = p % W;
     float s = b4[0];
     for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
         if (py + dy < 0 || py + dy >= H || px + dx < 0 || px + dx >= W) continue;
         const bf16_t *src = y3 + static_cast<size_t>(gp + dy * W + dx) * kCh;
         for (int c = 0; c < kCh; ++c) s += W4[tap * kCh + c] * bf2f(src[c]);
@@ -259,16 +265,16 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
     if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
 }
 
-// g3 = bf16( (sum_tap W4[tap][c] g4[p - off(tap)]) * (y3 > 0) )
+// g3 = bf16( (sum_tap W4[tap][c] g4[p - d off(tap)]) * (y3 > 0) )
 __global__ void k_last_dgrad(const float *__restrict__ g4, const float *__restrict__ W4,
-                             const bf16_t *__restrict__ y3, bf16_t *__restrict__ g3, int NP, int H, int W) {
+                             const bf16_t *__restrict__ y3, bf16_t *__restrict__ g3, int NP, int H, int W, int d) {
     const int gp = blockIdx.x * blockDim.x + threadIdx.x;
     if (gp >= NP) return;
     const int HW = H * W, p = gp % HW, py = p / W, px = p % W;
     float gn[9];
     for (int tap = 0; tap < 9; ++tap) {
-        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-        // pixel gp feeds output gp - off through tap
+        const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+        // pixel gp feeds output gp - d off through tap
         const bool ok = py - dy >= 0 && py - dy < H && px - dx >= 0 && px - dx < W;
         gn[tap] = ok ? g4[gp - dy * W - dx] : 0.f;
     }
@@ -280,9 +286,9 @@ __global__ void k_last_dgrad(const float *__restrict__ g4, const float *__restri
     }
 }
 
-// part[blk][tap*32 + c] = sum over the block's pixels of g4[p] y3[p + off][c]; part[blk][288] = sum g4
+// part[blk][tap*32 + c] = sum over the block's pixels of g4[p] y3[p + d off][c]; part[blk][288] = sum g4
 __global__ __launch_bounds__(kThreads) void k_last_wgrad(const float *__restrict__ g4, const bf16_t *__restrict__ y3,
-                                                         float *__restrict__ part, int NP, int H, int W) {
+                                                         float *__restrict__ part, int NP, int H, int W, int d) {
     const int e = threadIdx.x;  // 0..287 (two passes over 256 threads)
     const int HW = H * W;
     float acc[2] = {0.f, 0.f};
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_last_wgrad(const float *__restrict
                 if (gp >= NP) break;
                 const float gv = g4[gp];
                 if (el == kW4) { s += gv; continue; }
-                const int tap = el / kCh, c = el % kCh, dy = tap / 3 - 1, dx = tap % 3 - 1;
+                const int tap = el / kCh, c = el % kCh, dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
                 const int p = gp % HW, py = p / W, px = p % W;
                 if (py + dy < 0 || py + dy >= H || px + dx < 0 || px + dx >= W) continue;
                 s += gv * bf2f(y3[static_cast<size_t>(gp + dy * W + dx) * kCh + c]);
@@ -447,8 +453,8 @@ T *nn_alloc(adrnn_ctx *c, size_t n) {
     return static_cast<T *>(p);
 }
 
-size_t wgrad_lds(int cin, int W) {
-    const int span = kChunk + 2 * (W + 1);
+size_t wgrad_lds(int cin, int d) {
+    const int span = 3 * (kChunk + 2 * d);
     return sizeof(bf16_t) * (kCh * kChunk + static_cast<size_t>(cin) * span) + sizeof(short) * 2 * kChunk;
 }
 
@@ -463,26 +469,26 @@ int conv_grid(int NP) { return std::min(4096, std::max(1, (NP + 16 * 4 * 8 - 1) 
 void forward(adrnn_ctx *c, int B, const bf16_t *x0, float *out) {
     const int NP = B * c->H * c->W, gridc = conv_grid(NP);
     hipLaunchKernelGGL((k_conv32<4, 0>), dim3(gridc), dim3(kThreads), 0, c->st, x0, c->w1, c->P + ob1, nullptr, c->y1,
-                       NP, c->H, c->W);
+                       NP, c->H, c->W, kDil[0]);
     hipLaunchKernelGGL((k_conv32<32, 0>), dim3(gridc), dim3(kThreads), 0, c->st, c->y1, c->w2, c->P + ob2, nullptr,
-                       c->y2, NP, c->H, c->W);
+                       c->y2, NP, c->H, c->W, kDil[1]);
     hipLaunchKernelGGL((k_conv32<32, 0>), dim3(gridc), dim3(kThreads), 0, c->st, c->y2, c->w3, c->P + ob3, nullptr,
-                       c->y3, NP, c->H, c->W);
+                       c->y3, NP, c->H, c->W, kDil[2]);
     NNCHK(hipGetLastError());
     hipLaunchKernelGGL(k_last_fwd, dim3((NP + 255) / 256), dim3(256), 0, c->st, c->y3, c->w4, c->P + ob4, out, NP,
-                       c->H, c->W);
+                       c->H, c->W, kDil[3]);
     NNCHK(hipGetLastError());
 }
 
 template <int CIN>
-void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, float *dst) {
-    const size_t lds = wgrad_lds(CIN, c->W);
+void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, int d, float *dst) {
+    const size_t lds = wgrad_lds(CIN, d);
     if (lds > 64 * 1024)
         (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgrad32<CIN>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     const int nchunks = (NP + kChunk - 1) / kChunk;
     const int nb = std::min(c->wblocks, nchunks);
-    hipLaunchKernelGGL((k_wgrad32<CIN>), dim3(nb), dim3(kThreads), lds, c->st, g, x, c->part, NP, c->H, c->W);
+    hipLaunchKernelGGL((k_wgrad32<CIN>), dim3(nb), dim3(kThreads), lds, c->st, g, x, c->part, NP, c->H, c->W, d);
     NNCHK(hipGetLastError());
     const int len = kCh * 9 * CIN + kCh;
     hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256), dim3(256), 0, c->st, c->part, nb, len, dst);
@@ -503,20 +509,23 @@ double grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint
     hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, c->st, c->out, tgt, mask, c->g4, c->lpart, NP, HW, inv_cnt);
     // layer 4
     const int nchunks = (NP + kChunk - 1) / kChunk, nb = std::min(c->wblocks, nchunks);
-    hipLaunchKernelGGL(k_last_wgrad, dim3(nb), dim3(kThreads), 0, c->st, c->g4, c->y3, c->part, NP, c->H, c->W);
+    hipLaunchKernelGGL(k_last_wgrad, dim3(nb), dim3(kThreads), 0, c->st, c->g4, c->y3, c->part, NP, c->H, c->W,
+                       kDil[3]);
     hipLaunchKernelGGL(k_reduce, dim3((kW4 + 1 + 255) / 256), dim3(256), 0, c->st, c->part, nb, kW4 + 1, G + oW4);
-    hipLaunchKernelGGL(k_last_dgrad, dim3(lb), dim3(256), 0, c->st, c->g4, c->w4, c->y3, c->ga, NP, c->H, c->W);
+    hipLaunchKernelGGL(k_last_dgrad, dim3(lb), dim3(256), 0, c->st, c->g4, c->w4, c->y3, c->ga, NP, c->H, c->W,
+                       kDil[3]);
     NNCHK(hipGetLastError());
     // layer 3: g3 = ga
-    wgrad<32>(c, c->ga, c->y2, NP, G + oW3);  // writes W3 then b3 (contiguous in the layout)
+    wgrad<32>(c, c->ga, c->y2, NP, kDil[2], G + oW3);  // writes W3 then b3 (contiguous in the layout)
+    // the transposed convolution is the convolution with flipped taps at the same dilation
     hipLaunchKernelGGL((k_conv32<32, 1>), dim3(gridc), dim3(kThreads), 0, c->st, c->ga, c->w3t, nullptr, c->y2, c->gb,
-                       NP, c->H, c->W);
+                       NP, c->H, c->W, kDil[2]);
     // layer 2: g2 = gb
-    wgrad<32>(c, c->gb, c->y1, NP, G + oW2);
+    wgrad<32>(c, c->gb, c->y1, NP, kDil[1], G + oW2);
     hipLaunchKernelGGL((k_conv32<32, 1>), dim3(gridc), dim3(kThreads), 0, c->st, c->gb, c->w2t, nullptr, c->y1, c->ga,
-                       NP, c->H, c->W);
+                       NP, c->H, c->W, kDil[1]);
     // layer 1: g1 = ga
-    wgrad<4>(c, c->ga, x0, NP, G + oW1);
+    wgrad<4>(c, c->ga, x0, NP, kDil[0], G + oW1);
     NNCHK(hipGetLastError());
     std::vector<double> lp(lb);
     NNCHK(hipMemcpyAsync(lp.data(), c->lpart, sizeof(double) * lb, hipMemcpyDeviceToHost, c->st));
@@ -569,7 +578,6 @@ adr_status adrnn_create(int32_t H, int32_t W, int32_t max_batch, void *stream, a
         c->lpart = nn_alloc<double>(c, (NP + 255) / 256);
         c->fn = nn_alloc<double>(c, 2 * static_cast<size_t>(max_batch));
         c->dlmu = nn_alloc<double>(c, max_batch);
-        if (wgrad_lds(32, W) > 160 * 1024) throw NNError{ADR_EINVAL, "image too wide for the LDS tiles"};
         std::vector<float> zero(kParams, 0.f);
         NNCHK(hipMemcpy(c->P, zero.data(), sizeof(float) * kParams, hipMemcpyHostToDevice));
         NNCHK(hipMemset(c->m, 0, sizeof(float) * kParams));

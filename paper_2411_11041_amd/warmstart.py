@@ -114,8 +114,8 @@ class Workload:
             out = net.forward(B, x0)
             u = torch.empty_like(g)
             net.warm_start(B, g, sn, out, self.mask, u)
-            r_net = s.residual(u)
-            r_s = s.residual(g)
+            r_net = s.residual(u, allow_nonfinite=True)
+            r_s = s.residual(g, allow_nonfinite=True)
             for b in np.nonzero(~(r_net < r_s))[0]:
                 u[b * self.HW:(b + 1) * self.HW] = g[b * self.HW:(b + 1) * self.HW]
                 fallback += 1
@@ -126,13 +126,21 @@ class Workload:
         return u, it, rel, time.perf_counter() - t0, fallback
 
 
-def train(net, x_all, t_all, mask, N, HW, epochs, batch=32, lr=1e-3, seed=0, log=None):
-    """Adam on shuffled minibatches; returns the per-epoch mean losses."""
+def train(net, x_all, t_all, mask, N, HW, epochs, batch=32, lr=1e-3, lr_end=None, seed=0, log=None,
+          on_epoch=None):
+    """Adam on shuffled minibatches, the step size decaying from lr to lr_end
+    (cosine over all steps; constant when lr_end is None).  on_epoch(ep, loss)
+    is called after each epoch.  Returns the per-epoch mean losses."""
+    import math
+
     import torch
     rng = np.random.default_rng(seed)
     xv = x_all.view(N, HW * 4)
     tv = t_all.view(N, HW)
     losses = []
+    per_ep = max(N // batch, 1)
+    total = epochs * per_ep
+    step = 0
     for ep in range(epochs):
         perm = rng.permutation(N)
         tot, nb = 0.0, 0
@@ -140,11 +148,15 @@ def train(net, x_all, t_all, mask, N, HW, epochs, batch=32, lr=1e-3, seed=0, log
             idx = torch.from_numpy(perm[b0:b0 + batch]).cuda()
             xb = xv.index_select(0, idx).contiguous().view(-1)
             tb = tv.index_select(0, idx).contiguous().view(-1)
-            tot += net.train_step(batch, xb, tb, mask, lr)
+            a = lr if lr_end is None else lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * step / total))
+            tot += net.train_step(batch, xb, tb, mask, a)
+            step += 1
             nb += 1
         losses.append(tot / max(nb, 1))
         if log:
             log(f"epoch {ep + 1}/{epochs} loss {losses[-1]:.3e}")
+        if on_epoch:
+            on_epoch(ep, losses[-1])
     return losses
 
 

@@ -84,9 +84,10 @@ def test_pack_forward_warm_start():
     net.close()
 
 
-def test_gradients_match_oracle():
-    print("[case] grads B=3 21x19", flush=True)
-    f, s, u, mask, mu = make_batch(seed=3)
+@pytest.mark.parametrize("B,H,W", [(3, 21, 19), (2, 67, 45)])
+def test_gradients_match_oracle(B, H, W):
+    print(f"[case] grads B={B} {H}x{W}", flush=True)
+    f, s, u, mask, mu = make_batch(B, H, W, seed=3)
     B, H, W = f.shape
     net, Wt, bt = setup_net(H, W, B, seed=4)
     x0, tgt, sn = net.pack(B, dev(f), dev(s), dev(mask, torch.uint8), mu, dev(u))
@@ -94,10 +95,22 @@ def test_gradients_match_oracle():
     xo, sno = cnn.pack_inputs(f, s, mask, mu)
     L, dW, db, _ = cnn.loss_and_grads(xo, cnn.target(u, s, sno, mask), mask, Wt, bt, rounding=True)
     gW, gb = cnn.unflatten(g.cpu().numpy())
-    assert abs(loss - L) <= 1e-5 * L
+    # The device accumulates in FP32, the oracle in FP64; both round the stored
+    # activations and gradients to BF16 at the same points, but a value within
+    # ~1e-7 of a BF16 rounding boundary may round the other way (probability
+    # ~2^-24/2^-9 per value).  Each such flip moves one value by a BF16 ulp and,
+    # through the dilated taps, up to 9^3 outputs.  On the small image no flip
+    # reaches the outputs beyond 1e-4; on the larger one the bar is that the
+    # device stays well inside the effect of the BF16 rounding itself (oracle
+    # rounded vs unrounded, ~4e-3 here).
+    _, dWx, dbx, _ = cnn.loss_and_grads(xo, cnn.target(u, s, sno, mask), mask, Wt, bt, rounding=False)
+    small = B * H * W <= 1200
+    assert abs(loss - L) <= (1e-5 if small else 1e-4) * L
     for l in range(4):
-        assert rel(gW[l], dW[l]) < 1e-4, (l, rel(gW[l], dW[l]))
-        assert rel(gb[l], db[l]) < 1e-4, (l, rel(gb[l], db[l]))
+        env = rel(dWx[l], dW[l])
+        bar = 1e-4 if small else min(2e-3, 0.25 * env)
+        assert rel(gW[l], dW[l]) < bar, (l, rel(gW[l], dW[l]), env)
+        assert rel(gb[l], db[l]) < (1e-4 if small else 2e-3), (l, rel(gb[l], db[l]))
     net.close()
 
 

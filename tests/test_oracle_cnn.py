@@ -14,12 +14,13 @@ def test_bf16_rounding_matches_torch():
     assert np.array_equal(cnn.bf16(x), ref)
 
 
-def test_conv_brute_force():
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_conv_brute_force(d):
     rng = np.random.default_rng(1)
     x = rng.standard_normal((2, 5, 6, 3))
     W = rng.standard_normal((4, 3, 3, 3))
     b = rng.standard_normal(4)
-    z = cnn.conv(x, W, b)
+    z = cnn.conv(x, W, b, d)
     ref = np.zeros_like(z)
     for bb in range(2):
         for y in range(5):
@@ -28,27 +29,28 @@ def test_conv_brute_force():
                     s = b[n]
                     for dy in (-1, 0, 1):
                         for dx in (-1, 0, 1):
-                            yy, x2 = y + dy, xx + dx
+                            yy, x2 = y + d * dy, xx + d * dx
                             if 0 <= yy < 5 and 0 <= x2 < 6:
                                 s += W[n, dy + 1, dx + 1] @ x[bb, yy, x2]
                     ref[bb, y, xx, n] = s
     assert np.max(np.abs(z - ref)) < 1e-12
 
 
-def test_conv_transpose_is_adjoint():
+@pytest.mark.parametrize("d", [1, 2, 4])
+def test_conv_transpose_is_adjoint(d):
     rng = np.random.default_rng(2)
-    x = rng.standard_normal((2, 7, 5, 3))
-    g = rng.standard_normal((2, 7, 5, 4))
+    x = rng.standard_normal((2, 9, 7, 3))
+    g = rng.standard_normal((2, 9, 7, 4))
     W = rng.standard_normal((4, 3, 3, 3))
-    lhs = np.sum(cnn.conv(x, W, np.zeros(4)) * g)
-    rhs = np.sum(x * cnn.conv_transpose(g, W))
+    lhs = np.sum(cnn.conv(x, W, np.zeros(4), d) * g)
+    rhs = np.sum(x * cnn.conv_transpose(g, W, d))
     assert abs(lhs - rhs) < 1e-10 * abs(lhs)
-    dW, db = cnn.conv_wgrad(g, x)
+    dW, db = cnn.conv_wgrad(g, x, d)
     # d/dW <conv(x, W), g> = conv_wgrad(g, x)
     eps = 1e-6
     for idx in [(0, 0, 0, 0), (3, 2, 1, 2), (1, 1, 1, 1)]:
         Wp = W.copy(); Wp[idx] += eps
-        num = (np.sum(cnn.conv(x, Wp, np.zeros(4)) * g) - lhs) / eps
+        num = (np.sum(cnn.conv(x, Wp, np.zeros(4), d) * g) - lhs) / eps
         assert abs(num - dW[idx]) < 1e-5 * max(1, abs(dW[idx]))
     assert np.allclose(db, g.reshape(-1, 4).sum(0))
 
@@ -56,9 +58,9 @@ def test_conv_transpose_is_adjoint():
 def test_gradients_by_finite_differences():
     """Backward of the full network (FP64, no rounding) vs central differences."""
     rng = np.random.default_rng(3)
-    x0 = rng.standard_normal((2, 6, 7, 4))
-    target = rng.standard_normal((2, 6, 7))
-    mask = np.zeros((6, 7), bool)
+    x0 = rng.standard_normal((2, 12, 11, 4))
+    target = rng.standard_normal((2, 12, 11))
+    mask = np.zeros((12, 11), bool)
     mask[1:-1, 1:-1] = True
     W, b = cnn.init_params(4, seed=5)
     b = [rng.standard_normal(v.shape) * 0.1 for v in b]
