@@ -32,12 +32,12 @@ HBM_PEAK_GBS = 8000.0
 # about one line node) and the written line value.
 LINE_BYTES = {("fp32", 0): 4 + 4 * 2 + 4 + 4 + 4 + 4 + 4, ("fp32", 1): 4 + 4 * 2 + 4 + 4 + 4,
               ("fp64", 0): 4 + 8 * 2 + 8 + 8 + 8 + 8 + 8, ("fp64", 1): 4 + 8 * 2 + 8 + 8 + 8}
-# Scatter: per interior grid node 4 records (index 4 B + two weights), the 8
-# line values they reference (each line value is referenced by ~2 nodes: 4 per
+# Scatter: per interior grid node its grid index (4 B), 4 records (index 4 B +
+# two weights), the 8 line values they reference (each line value is referenced by ~2 nodes: 4 per
 # node) and the written grid value (FP64 update: read+write state, write the
 # FP32 increment).
-SCATTER_BYTES = {("fp32", 2): 4 * (4 + 8) + 4 * 4 + 4, ("fp32", 3): 4 * (4 + 8) + 4 * 4 + 8 + 8 + 4,
-                 ("fp64", 2): 4 * (4 + 16) + 4 * 8 + 8, ("fp64", 3): 4 * (4 + 16) + 4 * 8 + 8 + 8 + 4}
+SCATTER_BYTES = {("fp32", 2): 4 + 4 * (4 + 8) + 4 * 4 + 4, ("fp32", 3): 4 + 4 * (4 + 8) + 4 * 4 + 8 + 8 + 4,
+                 ("fp64", 2): 4 + 4 * (4 + 16) + 4 * 8 + 8, ("fp64", 3): 4 + 4 * (4 + 16) + 4 * 8 + 8 + 8 + 4}
 
 
 def parse():
@@ -57,6 +57,9 @@ def parse():
     ap.add_argument("--epochs", type=int, default=40, help="c5: training epochs")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--graph", action="store_true", help="replay sweep blocks from a HIP graph")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="before the timed region, run one plain elementwise copy of 256 MiB in / 256 MiB out, "
+                         "the reference dispatch for scaling hardware byte counters")
     return ap.parse_args()
 
 
@@ -215,6 +218,28 @@ def bench_c5(args):
     wl.solver.close()
 
 
+def measured_traffic(kernel, profile="c2_2049_fp32lines.md"):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the
+    summary is missing or was taken on other kernel sources."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", profile)
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in ("adr_kernels.hip", "adr_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2411_11041_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    text = open(path).read()
+    if f"Kernel source sha256[:16] = {h.hexdigest()[:16]}" not in text:
+        return None
+    for line in text.splitlines():
+        cells = [c.strip() for c in line.strip().strip("|").split("|")]
+        if len(cells) == 4 and cells[0] == "adr::" + kernel:
+            return float(cells[3])
+    return None
+
+
 def kernel_roofline(times, counts):
     """Dominant kernel class over both precisions; achieved = bytes / time."""
     best = None
@@ -233,7 +258,9 @@ def kernel_roofline(times, counts):
     else:
         units = counts["grid_unknowns"]
         per = SCATTER_BYTES[(prec, 2 if fam == 0 else 3)]
-        kname = "k_scatter"
+        # beta half-sweep writes the grid field; gamma half-sweep updates the state
+        kname = {("fp32", 0): "k_scatter<float, float, 0>", ("fp32", 1): "k_scatter<float, double, 2>",
+                 ("fp64", 0): "k_scatter<double, double, 0>", ("fp64", 1): "k_scatter<double, double, 1>"}[(prec, fam)]
     # launches of this class per sweep (one per non-empty length bucket)
     return dict(prec=prec, cls=cls, kernel=kname, total_ms=ms, launches=cnt, bytes_per_unit=per, units=units)
 
@@ -255,6 +282,12 @@ def main():
     import workloads as W
     from paper_2411_11041_amd.adr import Solver
 
+    if args.calibrate_copy:
+        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
     p = W.c2(args.n)
     t0 = time.time()
     s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, timing=True)
@@ -286,17 +319,20 @@ def main():
     ms_step = 1e3 * el / args.steps
 
     rf = kernel_roofline(times, counts)
-    # bytes per launch: the class processes `units` line unknowns (or grid nodes)
-    # once per sweep of its precision, spread over its per-sweep launches
+    # one launch per sweep of its precision processes `units` line unknowns (or
+    # grid nodes).  Launches made after the convergence flag was set exit at
+    # once and carry no work: the average is taken over the work-carrying
+    # launches (their total time includes the empty ones, a conservative bound).
     n_sw_prec = sum(1 for k in range(sweeps[0]) if (k % (args.fp32_sweeps + 1) == 0) == (rf["prec"] == "fp64"))
-    launches_per_sweep = rf["launches"] / max(1, n_sw_prec * args.steps)
-    bytes_per_launch = rf["bytes_per_unit"] * rf["units"] / launches_per_sweep
-    avg_launch_s = rf["total_ms"] / rf["launches"] / 1e3
+    work_launches = max(1, n_sw_prec * args.steps)
+    bytes_per_launch = rf["bytes_per_unit"] * rf["units"]
+    avg_launch_s = rf["total_ms"] / work_launches / 1e3
     achieved = bytes_per_launch / avg_launch_s / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(rf["kernel"]),
                 "kernel": rf["kernel"], "avg_launch_us": round(avg_launch_s * 1e6, 2),
-                "bytes_per_launch": int(bytes_per_launch)}
+                "bytes_per_launch": int(bytes_per_launch), "launches": rf["launches"],
+                "work_launches": work_launches}
 
     kernels = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()} for pr in times}
 
