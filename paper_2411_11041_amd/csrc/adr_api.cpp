@@ -416,7 +416,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 }
                 F.bk[b] = Bucket{first, count, nmax};
                 first += count;
-                if (count && (nmax > kMaxNodes || adr::line_lds_bytes<double>(nmax) > kLdsLimit))
+                if (count && (nmax > kMaxNodes || adr::line_lds_bytes<double>(f, nmax) > kLdsLimit))
                     throw Error{ADR_EINVAL, "a curve has " + std::to_string(nmax) +
                                                 " nodes: longer than the LDS-resident line solver holds"};
             }

@@ -29,8 +29,9 @@ struct ScatterArgs {
     int npad;
 };
 
+// dynamic LDS of the line solve of family fam (0 beta, 1 gamma) whose longest curve has nmax nodes
 template <typename T>
-size_t line_lds_bytes(int nmax);
+size_t line_lds_bytes(int fam, int nmax);
 
 template <typename T>
 hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,

@@ -21,6 +21,11 @@ namespace adr {
 
 constexpr int kThreads = 256;
 
+// LDS of a line-solve workgroup: arrays of `stride` elements (the longest curve
+// of the launch, at least the 7 x 256 entries of the reduced system)
+__host__ __device__ inline int line_lds_stride(int nmax) { return ((nmax > 7 * kThreads ? nmax : 7 * kThreads) + 3) & ~3; }
+__host__ __device__ inline int line_lds_arrays(int fam) { return fam == 0 ? 3 : 2; }
+
 // 1/x: IEEE division in FP64 (parity with the FP64 oracle), the hardware
 // reciprocal (v_rcp_f32, ~1 ulp) in the FP32 increment sweeps
 __device__ inline double recip(double x) { return 1.0 / x; }
@@ -35,16 +40,21 @@ __device__ inline T bilinear(const T *__restrict__ F, int cell, int nx, T lx, T 
 template <typename T, int FAM, int MAXJ>
 __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restrict__ fin, T *__restrict__ vout,
                                           const double *__restrict__ par, const int *__restrict__ done, int nmax) {
-    // LDS: four row arrays (the first also holds the gathered values, the
-    // second the solution for the write-out) and the reduced system
+    // LDS: line_lds_arrays(FAM) arrays of line_lds_stride(nmax) elements
+    //   P0  gathered values U, then the right-hand sides D, then the solution X
+    //   P1  chords h; after every thread has read its chunk, the reduced system
+    //   P2  |beta| (beta family)
+    // The matrix rows are rebuilt in registers from h and |beta| in chunk
+    // order, so no row array is staged (a small footprint: more resident
+    // workgroups per CU to hide the latency of the serial elimination).
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int stride = nmax + kThreads;
-    T *A = reinterpret_cast<T *>(smem_raw);
-    T *B = A + stride;
-    T *C = B + stride;
-    T *D = C + stride;
-    T *U = A;
-    T *RA = D + stride;
+    const int S = line_lds_stride(nmax);
+    T *P0 = reinterpret_cast<T *>(smem_raw);
+    T *P1 = P0 + S;
+    T *P2 = P1 + S;
+    T *U = P0, *D = P0, *X = P0;
+    T *Hs = P1, *Ws = P2;
+    T *RA = P1;
     T *RB = RA + kThreads;
     T *RC = RB + kThreads;
     T *RD = RC + kThreads;
@@ -68,9 +78,9 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     const int m = (N + kThreads - 1) / kThreads;
     const int Q = (N + m - 1) / m;  // non-empty chunks
 
-    // 1. all loads of this thread's nodes (j = tid + 256 q) and rows (r = j)
-    //    issued before any use, then the bilinear gather (eq. (22))
-    T hl[MAXJ], hr[MAXJ], wm[MAXJ], w0[MAXJ], wp[MAXJ], lk[MAXJ], uj[MAXJ];
+    // 1. all loads of this thread's nodes j = tid + 256 q (coalesced) issued
+    //    before any use, then the bilinear gather (eq. (22)); node values to LDS
+    T hj[MAXJ], wj[MAXJ], lk[MAXJ];
     int cj[MAXJ];
     T lxj[MAXJ], lyj[MAXJ];
 #pragma unroll
@@ -83,67 +93,53 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
             lxj[q] = a.lx[k];
             lyj[q] = a.ly[k];
         }
-        if (j < N) {
-            const int k = o + j + 1;
-            hl[q] = a.h[k];
-            hr[q] = a.h[k + 1];
-            if (FAM == 0) {
-                wm[q] = a.w[k - 1];
-                w0[q] = a.w[k];
-                wp[q] = a.w[k + 1];
-                lk[q] = eL != T(0) ? a.L[k] : T(0);
-            }
+        if (j > 0 && j < n) hj[q] = a.h[o + j];
+        if (FAM == 0) {
+            if (j < n) wj[q] = a.w[o + j];
+            // load of row j (node j + 1)
+            lk[q] = (j < N && eL != T(0)) ? a.L[o + j + 1] : T(0);
         }
     }
 #pragma unroll
     for (int q = 0; q < MAXJ; ++q) {
         const int j = tid + kThreads * q;
-        uj[q] = cj[q] >= 0 ? bilinear(fin, cj[q], nx, lxj[q], lyj[q]) : T(0);
-        if (j < n) U[j] = uj[q];
+        const T uj = cj[q] >= 0 ? bilinear(fin, cj[q], nx, lxj[q], lyj[q]) : T(0);
+        if (j < n) {
+            U[j] = uj;
+            if (j > 0) Hs[j] = hj[q];
+            if (FAM == 0) Ws[j] = wj[q];
+        }
     }
     __syncthreads();
 
-    // 2. rows r = 0..N-1 (node r + 1) of  A x = rhs, kept in registers until
-    //    every thread has read its neighbours' gathered values
+    // 2. right-hand sides of the rows r = tid + 256 q (node r + 1) of A x = rhs
     const T sixth = T(1) / T(6), third = T(1) / T(3);
-    T ro_lo[MAXJ], ro_di[MAXJ], ro_hi[MAXJ], ro_d[MAXJ];
+    T rh[MAXJ];
 #pragma unroll
     for (int q = 0; q < MAXJ; ++q) {
         const int r = tid + kThreads * q;
         if (r < N) {
-            const T mlo = hl[q] * sixth, mdi = (hl[q] + hr[q]) * third, mup = hr[q] * sixth;
-            const T il = recip(hl[q]), ir = recip(hr[q]);
+            const T hl = Hs[r + 1], hr = Hs[r + 2];
+            const T mlo = hl * sixth, mdi = (hl + hr) * third, mup = hr * sixth;
+            const T il = recip(hl), ir = recip(hr);
             const T klo = -il, kdi = il + ir, kup = -ir;
             const T um = U[r], u0 = U[r + 1], up = U[r + 2];
-            T lo = cM * mlo + cK * klo;
-            T di = cM * mdi + cK * kdi;
-            T hi = cM * mup + cK * kup;
             T rhs = eM * (mlo * um + mdi * u0 + mup * up) + eK * (klo * um + kdi * u0 + kup * up);
             if (FAM == 0) {
-                const T clo = -(wm[q] + T(2) * w0[q]) * sixth;
-                const T cdi = (wm[q] - wp[q]) * sixth;
-                const T cup = (T(2) * w0[q] + wp[q]) * sixth;
-                lo += cC * clo;
-                di += cC * cdi;
-                hi += cC * cup;
+                const T wm = Ws[r], w0 = Ws[r + 1], wp = Ws[r + 2];
+                const T clo = -(wm + T(2) * w0) * sixth;
+                const T cdi = (wm - wp) * sixth;
+                const T cup = (T(2) * w0 + wp) * sixth;
                 rhs += eC * (clo * um + cdi * u0 + cup * up) + eL * lk[q];
             }
-            ro_lo[q] = lo;
-            ro_di[q] = di;
-            ro_hi[q] = hi;
-            ro_d[q] = rhs;
+            rh[q] = rhs;
         }
     }
-    __syncthreads();  // U (aliasing A) fully read
+    __syncthreads();  // U fully read: P0 now takes the right-hand sides
 #pragma unroll
     for (int q = 0; q < MAXJ; ++q) {
         const int r = tid + kThreads * q;
-        if (r < N) {
-            A[r] = ro_lo[q];
-            B[r] = ro_di[q];
-            C[r] = ro_hi[q];
-            D[r] = ro_d[q];
-        }
+        if (r < N) D[r] = rh[q];
     }
     __syncthreads();
 
@@ -160,12 +156,25 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
 #pragma unroll
     for (int j = 0; j < MAXJ; ++j) {
         if (j < k) {
-            ra_[j] = A[rs + j];
-            rb_[j] = B[rs + j];
-            rc_[j] = C[rs + j];
-            rd_[j] = D[rs + j];
+            const int r = rs + j;
+            const T hl = Hs[r + 1], hr = Hs[r + 2];
+            const T il = recip(hl), ir = recip(hr);
+            T lo = cM * (hl * sixth) - cK * il;
+            T di = cM * ((hl + hr) * third) + cK * (il + ir);
+            T hi = cM * (hr * sixth) - cK * ir;
+            if (FAM == 0) {
+                const T wm = Ws[r], w0 = Ws[r + 1], wp = Ws[r + 2];
+                lo += cC * (-(wm + T(2) * w0) * sixth);
+                di += cC * ((wm - wp) * sixth);
+                hi += cC * ((T(2) * w0 + wp) * sixth);
+            }
+            ra_[j] = lo;
+            rb_[j] = di;
+            rc_[j] = hi;
+            rd_[j] = D[r];
         }
     }
+    __syncthreads();  // h, |beta| and D read: P1 takes the reduced system, P0 the solution
     T sa = T(0), sb = T(1), sc = T(0), sd = T(0);  // separator row
     {
         T pc = T(0), py = T(0), pa = T(0);
@@ -248,8 +257,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         __syncthreads();
     }
 
-    // 5. back-substitution of every chunk into X (aliases B, already read)
-    T *X = B;
+    // 5. back-substitution of every chunk into X (P0)
     if (q < Q) {
         const T SL = q > 0 ? RD[q - 1] : T(0);
         const T SR = q < R ? RD[q] : T(0);
@@ -374,9 +382,8 @@ __global__ void k_fill_int(int *p, int v, int n) {
 
 // ------------------------------------------------------------------ launchers
 template <typename T>
-size_t line_lds_bytes(int nmax) {
-    // four row arrays of nmax + 256 (odd chunk stride padding) and the reduced system
-    return sizeof(T) * (4 * static_cast<size_t>(nmax + kThreads) + 7 * kThreads);
+size_t line_lds_bytes(int fam, int nmax) {
+    return sizeof(T) * static_cast<size_t>(line_lds_arrays(fam)) * line_lds_stride(nmax);
 }
 
 template <typename T>
@@ -384,7 +391,7 @@ hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin,
                        const int *done, int nmax, hipStream_t st) {
     if (n_lines == 0) return hipSuccess;
     if (nmax > 12 * kThreads) return hipErrorInvalidValue;
-    const size_t lds = line_lds_bytes<T>(nmax);
+    const size_t lds = line_lds_bytes<T>(fam, nmax);
     if (fam == 0) {
         if (lds > 64 * 1024)
             (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 0>),
@@ -426,8 +433,8 @@ hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
-template size_t line_lds_bytes<double>(int);
-template size_t line_lds_bytes<float>(int);
+template size_t line_lds_bytes<double>(int, int);
+template size_t line_lds_bytes<float>(int, int);
 template hipError_t launch_line<double>(int, const LineArgs<double> &, int, const double *, double *, const double *,
                                         const int *, int, hipStream_t);
 template hipError_t launch_line<float>(int, const LineArgs<float> &, int, const float *, float *, const double *,
