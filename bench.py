@@ -33,10 +33,12 @@ HBM_PEAK_GBS = 8000.0
 LINE_BYTES = {("fp32", 0): 4 + 4 * 2 + 4 + 4 + 4 + 4 + 4, ("fp32", 1): 4 + 4 * 2 + 4 + 4 + 4,
               ("fp64", 0): 4 + 8 * 2 + 8 + 8 + 8 + 8 + 8, ("fp64", 1): 4 + 8 * 2 + 8 + 8 + 8}
 # Scatter: per interior grid node its grid index (4 B), 4 records (index 4 B +
-# two weights), the 8 line values they reference (each line value is referenced by ~2 nodes: 4 per
-# node) and the written grid value (FP64 update: read+write state, write the
-# FP32 increment).
-SCATTER_BYTES = {("fp32", 2): 4 + 4 * (4 + 8) + 4 * 4 + 4, ("fp32", 3): 4 + 4 * (4 + 8) + 4 * 4 + 8 + 8 + 4,
+# two weights: FP16 pair in the FP32 sweeps, 2 x FP64 in the FP64 sweeps), the
+# 8 line values they reference (each line value is referenced by ~2 nodes: 4
+# per node) and the written grid value (FP64 update: read+write state, write
+# the FP32 increment).  Keys: (precision, 2) beta half sweep, (precision, 3)
+# gamma half sweep.
+SCATTER_BYTES = {("fp32", 2): 4 + 4 * (4 + 4) + 4 * 4 + 4, ("fp32", 3): 4 + 4 * (4 + 4) + 4 * 4 + 8 + 8 + 4,
                  ("fp64", 2): 4 + 4 * (4 + 16) + 4 * 8 + 8, ("fp64", 3): 4 + 4 * (4 + 16) + 4 * 8 + 8 + 8 + 4}
 
 
@@ -50,13 +52,16 @@ def parse():
     ap.add_argument("--fp32-sweeps", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
-                    help="c2: one 2049^2 problem (default); c4: the 512-instance batch; "
+    ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
+                    help="c2: one 2049^2 problem (default); c3: the 2049^2 parabolic march (200 steps); "
+                         "c4: the 512-instance batch; "
                          "c5: learned warm start (train, then zero / eq. (11) / network starts)")
     ap.add_argument("--train", type=int, default=2048, help="c5: training samples")
     ap.add_argument("--epochs", type=int, default=40, help="c5: training epochs")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--graph", action="store_true", help="replay sweep blocks from a HIP graph")
+    ap.add_argument("--autotune", action="store_true",
+                    help="c2/c4: choose the FP32 sweeps per FP64 sweep with adr_autotune before the timed region")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before the timed region, run one plain elementwise copy of 256 MiB in / 256 MiB out, "
                          "the reference dispatch for scaling hardware byte counters")
@@ -93,6 +98,9 @@ def bench_c4(args):
     per_inst = np.array(per_inst, np.int64)
     off = s.layout()
     u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    tuned = None
+    if args.autotune:
+        tuned = s.autotune(u, 3000, args.tol)
 
     def solve():
         u.zero_()
@@ -122,7 +130,9 @@ def bench_c4(args):
                       "line_unknowns_per_sweep": int(per_inst.sum()), "lines": [counts["lines_b"], counts["lines_g"]],
                       "sweeps_min_median_max": [int(its.min()), int(np.median(its)), int(its.max())],
                       "converged": int((rel <= args.tol).sum()), "gen_s": round(gen_s, 1), "setup_s": round(setup_s, 1),
-                      "graph": bool(args.graph)}}
+                      "graph": bool(args.graph),
+                      "fp32_sweeps_per_fp64": tuned[0] if tuned else args.fp32_sweeps,
+                      "autotune_ms": round(tuned[1], 2) if tuned else None}}
     if not args.graph:
         times = {pr: s.kernel_times(pr, reset=True) for pr in ("fp64", "fp32")}
         out["config"]["kernels"] = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()}
@@ -240,6 +250,57 @@ def measured_traffic(kernel, profile="c2_2049_fp32lines.md"):
     return None
 
 
+def bench_c3(args):
+    """Parabolic march: 200 implicit-Euler steps of eq. (10) (one splitting
+    step per time step, FP64) on 2049^2 from the Gaussian bump."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2411_11041_amd.adr import Solver
+    p = W.c3(args.n)
+    th, dt, nst = p.extra["theta"], p.extra["dt"], p.extra["steps"]
+    t0 = time.time()
+    s = Solver(p, precision="fp64", theta=th, dt=dt, timing=True)
+    setup_s = time.time() - t0
+    c = s.counts()
+    per_step = c["line_unknowns_b"] + c["line_unknowns_g"]
+    u0 = torch.from_numpy(np.ascontiguousarray(p.u0, np.float64).ravel()).cuda()
+    u = torch.empty_like(u0)
+    for _ in range(args.warmup):
+        u.copy_(u0)
+        s.time_step(u, th, dt, nst)
+    torch.cuda.synchronize()
+    s.kernel_times("fp64", reset=True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        u.copy_(u0)
+        s.time_step(u, th, dt, nst)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    times = {"fp64": s.kernel_times("fp64", reset=True), "fp32": {}}
+    rf = kernel_roofline(times, c)
+    if rf["cls"].startswith("scatter"):  # the march writes both half steps (no update/norm mode)
+        rf["bytes_per_unit"], rf["kernel"] = SCATTER_BYTES[("fp64", 2)], "k_scatter<double, double, 0>"
+    work_launches = nst * args.steps
+    bytes_per_launch = rf["bytes_per_unit"] * rf["units"]
+    avg_launch_s = rf["total_ms"] / work_launches / 1e3
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    out = {"metric": METRIC, "value": per_step * nst * args.steps / el, "unit": "line-unknowns/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"c3: parabolic ADR, unit square {args.n}x{args.n}, mu=1e-2, sigma=0.5, C2's beta, "
+                                  f"f=0, Gaussian bump u0; implicit Euler theta={th}, dt={dt}, {nst} steps "
+                                  "(one eq.(10) splitting step per time step); a step of the bench = the whole march",
+                      "time_steps_per_s": nst * args.steps / el, "ms_per_time_step": 1e3 * el / (nst * args.steps),
+                      "line_unknowns_per_time_step": per_step, "setup_s": round(setup_s, 2),
+                      "kernels": {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times["fp64"].items()}},
+           "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": rf["kernel"],
+                        "avg_launch_us": round(avg_launch_s * 1e6, 2), "bytes_per_launch": int(bytes_per_launch)}}
+    print(json.dumps(out), flush=True)
+    s.close()
+
+
 def kernel_roofline(times, counts):
     """Dominant kernel class over both precisions; achieved = bytes / time."""
     best = None
@@ -277,6 +338,9 @@ def main():
     if args.workload == "c5":
         bench_c5(args)
         return
+    if args.workload == "c3":
+        bench_c3(args)
+        return
     import numpy as np
     import torch
     import workloads as W
@@ -295,6 +359,10 @@ def main():
     counts = s.counts()
     per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
     u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+    if args.autotune:
+        args.fp32_sweeps = s.autotune(u, 5000, args.tol)[0]
+        s.kernel_times("fp64", reset=True)
+        s.kernel_times("fp32", reset=True)
 
     def solve():
         u.zero_()

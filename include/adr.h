@@ -131,6 +131,16 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs);
 adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol,
                              int32_t *iters, double *rel_res);
 
+/* Autotuner of the batched stationary solve (FP32_LINES precision only): for
+ * each candidate count of FP32 sweeps per FP64 sweep (2, 3, 4, 6) it runs the
+ * stationary solve from zero twice (the first run captures the graph in graph
+ * mode) on `work` (device FP64, packed layout, overwritten), times the second
+ * on the host clock, and keeps the fastest count in the context's options.
+ * best_fp32_sweeps, best_ms (host, may be NULL): the choice and its time.
+ * Kernel timers (timing mode) are reset afterwards.  Synchronises. */
+adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
+                        double *best_ms);
+
 /* Parabolic march (eq. (2) discretised by eq. (10)): nsteps sweeps with the
  * given theta in (0,1] and time step dt > 0, FP64, source f included.  u:
  * device FP64 packed, in: u_n, out: u_{n+nsteps}.  Asynchronous. */

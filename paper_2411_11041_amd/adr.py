@@ -18,7 +18,7 @@ ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE, ADR_EBETA, ADR_ENONFINITE, ADR_ENOT
 DOM_BOX, DOM_DISC, DOM_POLYGON = 0, 1, 2
 PREC_FP64, PREC_FP32_LINES = 0, 1
 
-EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_time_step",
+EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_autotune", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_kernel_times",
            "adr_destroy", "adr_last_error")
 
@@ -69,6 +69,7 @@ def load():
     lib.adr_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64), P(i64)]
     lib.adr_update.argtypes = [vp, P(Problem), i32]
     lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
+    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
     lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32]
     lib.adr_residual.argtypes = [vp, vp, P(dbl)]
     lib.adr_initial_guess.argtypes = [vp, vp]
@@ -156,6 +157,15 @@ class Solver:
         self._check(self.lib.adr_counts(self.ctx, *[C.byref(x) for x in v]))
         return dict(grid_unknowns=v[0].value, lines_b=v[1].value, lines_g=v[2].value,
                     line_unknowns_b=v[3].value, line_unknowns_g=v[4].value)
+
+    def autotune(self, work, max_iters, tol):
+        """Times the solve for each candidate FP32-sweep count on `work`
+        (overwritten) and keeps the fastest; returns (count, ms)."""
+        best = C.c_int32()
+        ms = C.c_double()
+        self._check(self.lib.adr_autotune(self.ctx, _device_ptr(work), int(max_iters), float(tol),
+                                          C.byref(best), C.byref(ms)))
+        return best.value, ms.value
 
     def split_iterate(self, u, max_iters, tol):
         iters = np.zeros(self.n, np.int32)

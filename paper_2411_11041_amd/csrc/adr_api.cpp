@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -199,6 +200,7 @@ struct adr_ctx {
     hipGraph_t graph = nullptr;
     const double *g_u = nullptr;
     double g_tol = -1.0;
+    int g_m = -1;  // FP32 sweeps per block of the captured graph
     hipStream_t cap = nullptr;
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -463,9 +465,16 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     }
                 }
             const int *d_rk = upload(rk, own, st);
-            F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, upload(ra, own, st), upload(rb, own, st), npad};
-            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, upload(to_type<float>(ra), own, st),
-                                            upload(to_type<float>(rb), own, st), npad};
+            std::vector<unsigned> rw(ra.size());
+            for (size_t e = 0; e < ra.size(); ++e) {
+                const _Float16 a16 = static_cast<_Float16>(static_cast<float>(ra[e]));
+                const _Float16 b16 = static_cast<_Float16>(static_cast<float>(rb[e]));
+                rw[e] = static_cast<unsigned>(__builtin_bit_cast(unsigned short, a16)) |
+                        (static_cast<unsigned>(__builtin_bit_cast(unsigned short, b16)) << 16);
+            }
+            F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, upload(ra, own, st), upload(rb, own, st),
+                                             nullptr, npad};
+            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, nullptr, nullptr, upload(rw, own, st), npad};
             F.v64 = dalloc<double>(F.n_nodes, own);
             F.v32 = dalloc<float>(F.n_nodes, own);
             for (int i = 0; i < n; ++i) C->geo[f].push_back(G[i].fam[f]);
@@ -640,7 +649,7 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
             executed = 1;
             const int blocks = (max_iters - 1) / period;
             const int check = std::max(1, 8 / period);
-            if (use_graph && blocks > 0 && (ctx->g_u != u || ctx->g_tol != tol || !ctx->gexec)) {
+            if (use_graph && blocks > 0 && (ctx->g_u != u || ctx->g_tol != tol || ctx->g_m != m || !ctx->gexec)) {
                 ctx->drop_graph();
                 HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 ctx->block(u, m, tol);
@@ -648,6 +657,7 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
                 HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
                 ctx->g_u = u;
                 ctx->g_tol = tol;
+                ctx->g_m = m;
             }
             for (int b = 0; b < blocks; ++b) {
                 if (use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, st));
@@ -676,6 +686,49 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
         if (ctx->opt.graph) ctx->st = static_cast<hipStream_t>(ctx->opt.stream);
         return fail_ctx(ctx, e);
     }
+}
+
+adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
+                        double *best_ms) {
+    if (!ctx) return ADR_EINVAL;
+    if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES) {
+        ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0 and FP32_LINES precision";
+        return ADR_EINVAL;
+    }
+    static const int kCand[] = {2, 3, 4, 6};
+    const int32_t saved = ctx->opt.fp32_sweeps;
+    int best = saved;
+    double best_t = INFINITY;
+    const size_t nbytes = sizeof(double) * static_cast<size_t>(ctx->goff.back());
+    for (int c : kCand) {
+        ctx->opt.fp32_sweeps = c;
+        double t = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {  // the first run also captures the graph (graph mode)
+            if (hipMemsetAsync(work, 0, nbytes, ctx->st) != hipSuccess || hipStreamSynchronize(ctx->st) != hipSuccess) {
+                ctx->opt.fp32_sweeps = saved;
+                ctx->err = "adr_autotune: device error";
+                return ADR_EDEVICE;
+            }
+            const auto t0 = std::chrono::steady_clock::now();
+            const adr_status st = adr_split_iterate(ctx, work, max_iters, tol, nullptr, nullptr);
+            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (st != ADR_OK && st != ADR_ENOTCONV) {
+                ctx->opt.fp32_sweeps = saved;
+                return st;
+            }
+            t = ms;
+        }
+        if (t < best_t) {
+            best_t = t;
+            best = c;
+        }
+    }
+    ctx->opt.fp32_sweeps = best;
+    if (ctx->opt.timing)
+        for (int prec = 0; prec < 2; ++prec) (void)adr_kernel_times(ctx, prec, nullptr, nullptr, 1);
+    if (best_fp32_sweeps) *best_fp32_sweeps = best;
+    if (best_ms) *best_ms = best_t;
+    return ADR_OK;
 }
 
 adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32_t nsteps) {

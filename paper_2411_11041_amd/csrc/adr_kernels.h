@@ -25,7 +25,8 @@ struct ScatterArgs {
     const int *gidx;      // global grid index of the interior node, -1 for padding
     const int *blk_inst;  // instance of each 256-slot block
     const int *rk;        // [4][npad] first node of the record's segment, -1 unused
-    const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1]
+    const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1] (FP64 tables)
+    const unsigned *rw;   // [4][npad] the same weights as two FP16 halves (low: v[k]); FP32 tables
     int npad;
 };
 

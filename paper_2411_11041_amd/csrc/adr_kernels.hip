@@ -310,7 +310,18 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         const int k = s.rk[r * np + slot];
-        if (k >= 0) val += s.ra[r * np + slot] * v[k] + s.rb[r * np + slot] * v[k + 1];
+        if (k >= 0) {
+            if constexpr (sizeof(T) == 4) {
+                // increment sweeps: FP16 weights (relative error 2^-11; the FP64
+                // sweeps, with FP64 weights, fix the iterate and its residual)
+                const unsigned w = s.rw[r * np + slot];
+                const float wa = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w & 0xffffu)));
+                const float wb = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w >> 16)));
+                val += wa * v[k] + wb * v[k + 1];
+            } else {
+                val += s.ra[r * np + slot] * v[k] + s.rb[r * np + slot] * v[k + 1];
+            }
+        }
     }
     if constexpr (MODE == 0) {
         if (g >= 0) out[g] = TO(val);

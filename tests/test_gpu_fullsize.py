@@ -62,3 +62,33 @@ def test_c2_full_fp32_lines_bench_configuration(golden, problem):
     full = float(torch.linalg.norm(u))
     assert abs(full - golden["fixed_point_norm"]) <= 1e-5 * golden["fixed_point_norm"]
     s.close()
+
+
+GOLDEN_C3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_2049_samples.json")
+
+
+def test_c3_full_parabolic_march():
+    """The parabolic benchmark configuration: 200 implicit-Euler steps of
+    eq. (10) at 2049^2 from the Gaussian bump, FP64, vs stored oracle samples
+    after 10 and 200 steps."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("[case] c3 2049 fp64 march 200 steps vs stored oracle samples", flush=True)
+    from paper_2411_11041_amd.adr import Solver
+    with open(GOLDEN_C3) as fh:
+        g = json.load(fh)
+    p = W.c3(2049)
+    th, dt = p.extra["theta"], p.extra["dt"]
+    s = Solver(p, precision="fp64", theta=th, dt=dt)
+    u = torch.from_numpy(np.ascontiguousarray(p.u0, np.float64).ravel()).cuda()
+    idx = np.array(g["nodes"])
+    s.time_step(u, th, dt, 10)
+    torch.cuda.synchronize()
+    e10 = np.abs(u.cpu().numpy()[idx] - np.array(g["after10"])).max()
+    s.time_step(u, th, dt, 190)
+    torch.cuda.synchronize()
+    e200 = np.abs(u.cpu().numpy()[idx] - np.array(g["after200"])).max()
+    print(f"[case] max abs error: 10 steps {e10:.2e} (max {g['max10']:.3e}), 200 steps {e200:.2e}", flush=True)
+    assert e10 <= 1e-11 * g["max10"]
+    assert e200 <= 1e-11 * g["max10"]
+    s.close()

@@ -231,3 +231,21 @@ def test_update_swaps_coefficients_on_same_curves():
     with pytest.raises(Exception):
         s.update(b[:1])
     s.close()
+
+
+def test_autotune_keeps_a_candidate_and_the_fixed_point():
+    """The autotuner picks one of its candidate FP32-sweep counts; the solve
+    with the chosen count reaches the oracle's fixed point (FP32-lines bar)."""
+    print("[case] autotune c2 129 fp32 lines", flush=True)
+    p = W.c2(129)
+    s = solver(p, precision="fp32", fp32_sweeps=3)
+    work = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+    best, ms = s.autotune(work, 2000, 1e-10)
+    assert best in (2, 3, 4, 6) and ms > 0
+    u = torch.zeros_like(work)
+    iters, rel, st = s.split_iterate(u, 2000, 1e-10)
+    assert st == 0 and rel[0] <= 1e-10
+    o = Oracle(p)
+    Uo, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-12)
+    assert rel_l2(u.cpu().numpy(), Uo) < 1e-5
+    s.close()
