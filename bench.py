@@ -60,8 +60,8 @@ def parse():
     ap.add_argument("--epochs", type=int, default=40, help="c5: training epochs")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--graph", action="store_true", help="replay sweep blocks from a HIP graph")
-    ap.add_argument("--autotune", action="store_true",
-                    help="c2/c4: choose the FP32 sweeps per FP64 sweep with adr_autotune before the timed region")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="c2/c4: keep --fp32-sweeps instead of choosing it with adr_autotune (before the timed region)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before the timed region, run one plain elementwise copy of 256 MiB in / 256 MiB out, "
                          "the reference dispatch for scaling hardware byte counters")
@@ -84,8 +84,7 @@ def bench_c4(args):
     probs = gen_c4(args.instances)
     gen_s = time.time() - t0
     t0 = time.time()
-    s = Solver(probs, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05,
-               timing=not args.graph, graph=args.graph)
+    s = Solver(probs, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, graph=args.graph)
     setup_s = time.time() - t0
     counts = s.counts()
     per_inst = []
@@ -99,7 +98,7 @@ def bench_c4(args):
     off = s.layout()
     u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     tuned = None
-    if args.autotune:
+    if not args.no_autotune:
         tuned = s.autotune(u, 3000, args.tol)
 
     def solve():
@@ -109,15 +108,13 @@ def bench_c4(args):
     for _ in range(args.warmup):
         solve()
     torch.cuda.synchronize()
-    if not args.graph:
-        s.kernel_times("fp64", reset=True)
-        s.kernel_times("fp32", reset=True)
     t0 = time.perf_counter()
     its = None
     for _ in range(args.steps):
         its, rel, st = solve()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    el_ev, times = events_pass(s, solve, args.steps)  # eager launches with events
     solved = int((its.astype(np.int64) * per_inst).sum()) * args.steps
     out = {"metric": METRIC, "value": solved / el, "unit": "line-unknowns/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps,
@@ -133,8 +130,7 @@ def bench_c4(args):
                       "graph": bool(args.graph),
                       "fp32_sweeps_per_fp64": tuned[0] if tuned else args.fp32_sweeps,
                       "autotune_ms": round(tuned[1], 2) if tuned else None}}
-    if not args.graph:
-        times = {pr: s.kernel_times(pr, reset=True) for pr in ("fp64", "fp32")}
+    if True:
         out["config"]["kernels"] = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()}
                                     for pr in times}
         rf = kernel_roofline(times, counts)
@@ -148,7 +144,8 @@ def bench_c4(args):
         out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": rf["kernel"],
                            "avg_launch_us": round(avg_launch_s * 1e6, 2), "bytes_per_launch": int(bytes_per_launch),
-                           "note": "bytes scaled by the fraction of instance-sweeps still active"}
+                           "note": "bytes scaled by the fraction of instance-sweeps still active",
+                           "events_pass_ms_per_step": round(1e3 * el_ev / args.steps, 2)}
     print(json.dumps(out), flush=True)
     s.close()
 
@@ -228,6 +225,25 @@ def bench_c5(args):
     wl.solver.close()
 
 
+def events_pass(s, solve, steps):
+    """A second timed region over the same steps with per-launch HIP events on
+    the library's stream (a few us between launches, so it is kept apart from
+    the region that gives value); returns its seconds and the kernel times."""
+    import torch
+    s.kernel_times("fp64", reset=True)
+    s.kernel_times("fp32", reset=True)
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        solve()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    s.set_timing(False)
+    times = {pr: s.kernel_times(pr, reset=True) for pr in ("fp64", "fp32")}
+    return el, times
+
+
 def measured_traffic(kernel, profile="c2_2049_fp32lines.md"):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the
@@ -260,7 +276,7 @@ def bench_c3(args):
     p = W.c3(args.n)
     th, dt, nst = p.extra["theta"], p.extra["dt"], p.extra["steps"]
     t0 = time.time()
-    s = Solver(p, precision="fp64", theta=th, dt=dt, timing=True)
+    s = Solver(p, precision="fp64", theta=th, dt=dt)
     setup_s = time.time() - t0
     c = s.counts()
     per_step = c["line_unknowns_b"] + c["line_unknowns_g"]
@@ -269,15 +285,18 @@ def bench_c3(args):
     for _ in range(args.warmup):
         u.copy_(u0)
         s.time_step(u, th, dt, nst)
-    torch.cuda.synchronize()
-    s.kernel_times("fp64", reset=True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    def march():
         u.copy_(u0)
         s.time_step(u, th, dt, nst)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        march()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    times = {"fp64": s.kernel_times("fp64", reset=True), "fp32": {}}
+    el_ev, times = events_pass(s, march, args.steps)
+    times["fp32"] = {}
     rf = kernel_roofline(times, c)
     if rf["cls"].startswith("scatter"):  # the march writes both half steps (no update/norm mode)
         rf["bytes_per_unit"], rf["kernel"] = SCATTER_BYTES[("fp64", 2)], "k_scatter<double, double, 0>"
@@ -354,15 +373,15 @@ def main():
         del a, b
     p = W.c2(args.n)
     t0 = time.time()
-    s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, timing=True)
+    s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05)
     setup_s = time.time() - t0
     counts = s.counts()
     per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
     u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
-    if args.autotune:
-        args.fp32_sweeps = s.autotune(u, 5000, args.tol)[0]
-        s.kernel_times("fp64", reset=True)
-        s.kernel_times("fp32", reset=True)
+    tuned = None
+    if not args.no_autotune:
+        tuned = s.autotune(u, 5000, args.tol)
+        args.fp32_sweeps = tuned[0]
 
     def solve():
         u.zero_()
@@ -370,9 +389,7 @@ def main():
 
     for _ in range(args.warmup):
         solve()
-    torch.cuda.synchronize()
-    s.kernel_times("fp64", reset=True)
-    s.kernel_times("fp32", reset=True)
+    # timed region 1 (value, ms_per_step): no per-launch events
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sweeps = []
@@ -381,7 +398,8 @@ def main():
         sweeps.append(int(iters[0]))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    times = {pr: s.kernel_times(pr, reset=True) for pr in ("fp64", "fp32")}
+    # timed region 2 (roofline): the same steps with HIP events around every launch
+    el_ev, times = events_pass(s, solve, args.steps)
     total_unknowns = per_sweep * sum(sweeps)
     value = total_unknowns / el
     ms_step = 1e3 * el / args.steps
@@ -400,7 +418,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(rf["kernel"]),
                 "kernel": rf["kernel"], "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "bytes_per_launch": int(bytes_per_launch), "launches": rf["launches"],
-                "work_launches": work_launches}
+                "work_launches": work_launches, "events_pass_ms_per_step": round(1e3 * el_ev / args.steps, 3)}
 
     kernels = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()} for pr in times}
 
@@ -417,7 +435,8 @@ def main():
                                "beta=curl psi, psi=x+0.5y+0.1 sin(pi x) sin(pi y), f=8 seeded Gaussians; "
                                "eq.(10) sweeps theta=1 dt=0.05 to 1e-8",
                    "time_to_1e-8_ms": ms_step, "sweeps_per_solve": sweeps[0],
-                   "fp32_sweeps_per_fp64": args.fp32_sweeps, "line_unknowns_per_sweep": per_sweep,
+                   "fp32_sweeps_per_fp64": args.fp32_sweeps, "autotuned": tuned is not None,
+                   "line_unknowns_per_sweep": per_sweep,
                    "grid_unknowns": counts["grid_unknowns"], "lines": [counts["lines_b"], counts["lines_g"]],
                    "setup_s": round(setup_s, 2), "final_rel": float(rel[0]), "kernels": kernels},
         "roofline": roofline,

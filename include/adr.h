@@ -163,6 +163,13 @@ adr_status adr_initial_guess(adr_ctx *ctx, double *u);
 adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_lines,
                             int64_t *n_nodes, int64_t *offsets, double *x, double *y);
 
+/* Per-launch HIP-event timing on (1) or off (0) from now on (the set-up
+ * option's initial value).  Each timed launch records two events on the
+ * context's stream, which adds a few microseconds between launches.  Pending
+ * records are folded into the totals of adr_kernel_times first.  Errors:
+ * ADR_EINVAL (host-only context). */
+adr_status adr_set_timing(adr_ctx *ctx, int32_t on);
+
 /* Kernel timing (options.timing != 0): for kernel class k (0 beta-line solve,
  * 1 gamma-line solve, 2 beta scatter, 3 gamma scatter/update, 4 norm), total
  * milliseconds and launch count of kernels of the given precision (0 FP64,

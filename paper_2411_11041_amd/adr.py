@@ -19,7 +19,7 @@ DOM_BOX, DOM_DISC, DOM_POLYGON = 0, 1, 2
 PREC_FP64, PREC_FP32_LINES = 0, 1
 
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_autotune", "adr_time_step",
-           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_kernel_times",
+           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_set_timing", "adr_kernel_times",
            "adr_destroy", "adr_last_error")
 
 KERNEL_CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma", "norm")
@@ -70,6 +70,7 @@ def load():
     lib.adr_update.argtypes = [vp, P(Problem), i32]
     lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
     lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
+    lib.adr_set_timing.argtypes = [vp, i32]
     lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32]
     lib.adr_residual.argtypes = [vp, vp, P(dbl)]
     lib.adr_initial_guess.argtypes = [vp, vp]
@@ -157,6 +158,9 @@ class Solver:
         self._check(self.lib.adr_counts(self.ctx, *[C.byref(x) for x in v]))
         return dict(grid_unknowns=v[0].value, lines_b=v[1].value, lines_g=v[2].value,
                     line_unknowns_b=v[3].value, line_unknowns_g=v[4].value)
+
+    def set_timing(self, on):
+        self._check(self.lib.adr_set_timing(self.ctx, int(bool(on))))
 
     def autotune(self, work, max_iters, tol):
         """Times the solve for each candidate FP32-sweep count on `work`

@@ -111,6 +111,7 @@ struct adr_ctx {
         hipEvent_t a, b;
     };
     std::vector<Tick> ticks;
+    std::vector<hipEvent_t> ev_pool;
     double ms[2][5] = {};
     int64_t cnt[2][5] = {};
 
@@ -122,13 +123,19 @@ struct adr_ctx {
             HIPCHK(fn());
             return;
         }
-        Tick t{prec, cls, nullptr, nullptr};
-        HIPCHK(hipEventCreate(&t.a));
-        HIPCHK(hipEventCreate(&t.b));
+        // events come from a pool (created once, reused after each collection)
+        while (ev_pool.size() < 2 * (ticks.size() + 1)) {
+            hipEvent_t e = nullptr;
+            HIPCHK(hipEventCreate(&e));
+            ev_pool.push_back(e);
+        }
+        Tick t{prec, cls, ev_pool[2 * ticks.size()], ev_pool[2 * ticks.size() + 1]};
         HIPCHK(hipEventRecord(t.a, st));
         HIPCHK(fn());
         HIPCHK(hipEventRecord(t.b, st));
         ticks.push_back(t);
+        // bound the outstanding records: fold them in every 4096 launches
+        if (ticks.size() >= 4096) collect_ticks();
     }
 
     void collect_ticks() {
@@ -139,8 +146,6 @@ struct adr_ctx {
             HIPCHK(hipEventElapsedTime(&e, t.a, t.b));
             ms[t.prec][t.cls] += e;
             cnt[t.prec][t.cls] += 1;
-            (void)hipEventDestroy(t.a);
-            (void)hipEventDestroy(t.b);
         }
         ticks.clear();
     }
@@ -805,6 +810,17 @@ adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, in
     return ADR_OK;
 }
 
+adr_status adr_set_timing(adr_ctx *ctx, int32_t on) {
+    if (!ctx || ctx->opt.host_only) return ADR_EINVAL;
+    try {
+        ctx->collect_ticks();
+        ctx->opt.timing = on ? 1 : 0;
+        return ADR_OK;
+    } catch (const Error &e) {
+        return fail_ctx(ctx, e);
+    }
+}
+
 adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out, int32_t reset) {
     if (!ctx || precision < 0 || precision > 1) return ADR_EINVAL;
     try {
@@ -831,10 +847,7 @@ adr_status adr_destroy(adr_ctx *ctx) {
         return ADR_OK;
     }
     (void)hipStreamSynchronize(ctx->st);
-    for (auto &t : ctx->ticks) {
-        (void)hipEventDestroy(t.a);
-        (void)hipEventDestroy(t.b);
-    }
+    for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     ctx->drop_graph();
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
     for (void *p : ctx->owned) (void)hipFree(p);
