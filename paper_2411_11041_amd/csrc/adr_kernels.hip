@@ -87,6 +87,8 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     for (int q = 0; q < MAXJ; ++q) {
         const int j = tid + kThreads * q;
         cj[q] = -1;
+        lxj[q] = T(0);
+        lyj[q] = T(0);
         if (j > 0 && j < n - 1) {
             const int k = o + j;
             cj[q] = a.cell[k];
@@ -100,14 +102,33 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
             lk[q] = (j < N && eL != T(0)) ? a.L[o + j + 1] : T(0);
         }
     }
+    // gathers in groups of (up to) 4 slots: the 16 corner loads of a group are
+    // issued together (cell 0 stands in for the end nodes, whose value is
+    // dropped), then the group's values go to LDS
+    constexpr int G = MAXJ < 4 ? MAXJ : 4;
 #pragma unroll
-    for (int q = 0; q < MAXJ; ++q) {
-        const int j = tid + kThreads * q;
-        const T uj = cj[q] >= 0 ? bilinear(fin, cj[q], nx, lxj[q], lyj[q]) : T(0);
-        if (j < n) {
-            U[j] = uj;
-            if (j > 0) Hs[j] = hj[q];
-            if (FAM == 0) Ws[j] = wj[q];
+    for (int q0 = 0; q0 < MAXJ; q0 += G) {
+        T p11[G], p12[G], p21[G], p22[G];
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            const int c = cj[q0 + t] >= 0 ? cj[q0 + t] : 0;
+            p11[t] = fin[c];
+            p12[t] = fin[c + 1];
+            p21[t] = fin[c + nx];
+            p22[t] = fin[c + nx + 1];
+        }
+#pragma unroll
+        for (int t = 0; t < G; ++t) {
+            const int q = q0 + t;
+            const int j = tid + kThreads * q;
+            const T lx = lxj[q], ly = lyj[q];
+            const T ub = (T(1) - ly) * ((T(1) - lx) * p11[t] + lx * p12[t]) + ly * ((T(1) - lx) * p21[t] + lx * p22[t]);
+            const T uj = cj[q] >= 0 ? ub : T(0);
+            if (j < n) {
+                U[j] = uj;
+                if (j > 0) Hs[j] = hj[q];
+                if (FAM == 0) Ws[j] = wj[q];
+            }
         }
     }
     __syncthreads();
@@ -306,35 +327,50 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
     const int slot = blk * kThreads + threadIdx.x;
     const int g = s.gidx[slot];
     const int np = s.npad;
-    T val = T(0);
+    // every load is issued before any is used (no branch between them): the
+    // records, then the line values (a missing record reads v[0], v[1] with
+    // its contribution dropped), and the old grid value, which depends only
+    // on g
+    int kk[4];
+    T wa[4], wb[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        const int k = s.rk[r * np + slot];
-        if (k >= 0) {
-            if constexpr (sizeof(T) == 4) {
-                // increment sweeps: FP16 weights (relative error 2^-11; the FP64
-                // sweeps, with FP64 weights, fix the iterate and its residual)
-                const unsigned w = s.rw[r * np + slot];
-                const float wa = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w & 0xffffu)));
-                const float wb = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w >> 16)));
-                val += wa * v[k] + wb * v[k + 1];
-            } else {
-                val += s.ra[r * np + slot] * v[k] + s.rb[r * np + slot] * v[k + 1];
-            }
+        kk[r] = s.rk[r * np + slot];
+        if constexpr (sizeof(T) == 4) {
+            // increment sweeps: FP16 weights (relative error 2^-11; the FP64
+            // sweeps, with FP64 weights, fix the iterate and its residual)
+            const unsigned w = s.rw[r * np + slot];
+            wa[r] = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w & 0xffffu)));
+            wb[r] = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w >> 16)));
+        } else {
+            wa[r] = s.ra[r * np + slot];
+            wb[r] = s.rb[r * np + slot];
         }
     }
+    TO old = TO(0);
+    if constexpr (MODE != 0) old = out[g >= 0 ? g : 0];
+    T va[4], vb[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int k = kk[r] >= 0 ? kk[r] : 0;
+        va[r] = v[k];
+        vb[r] = v[k + 1];
+    }
+    T val = T(0);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (kk[r] >= 0) val += wa[r] * va[r] + wb[r] * vb[r];
     if constexpr (MODE == 0) {
         if (g >= 0) out[g] = TO(val);
     } else if constexpr (MODE == 2) {
         if (g >= 0) {
-            out[g] = out[g] + TO(val);
+            out[g] = old + TO(val);
             d32[g] = float(val);
         }
     } else {
         double r = 0.0;
         if (g >= 0) {
-            const double old = double(out[g]);
-            r = double(val) - old;
+            r = double(val) - double(old);
             if constexpr (MODE == 1) {
                 out[g] = TO(val);
                 d32[g] = float(r);
@@ -361,8 +397,18 @@ __global__ __launch_bounds__(kThreads) void k_norm(const double *__restrict__ pa
     const int inst = blockIdx.x;
     if (mode == 0 && done[inst]) return;
     const int b0 = blk_start[inst], b1 = blk_start[inst + 1];
-    double acc = 0.0;
-    for (int b = b0 + threadIdx.x; b < b1; b += kThreads) acc += partial[b];
+    // eight loads in flight per thread (independent accumulators, fixed order)
+    double a8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    int b = b0 + threadIdx.x;
+    for (; b + 7 * kThreads < b1; b += 8 * kThreads) {
+        double p8[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) p8[q] = partial[b + q * kThreads];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a8[q] += p8[q];
+    }
+    for (; b < b1; b += kThreads) a8[0] += partial[b];
+    const double acc = ((a8[0] + a8[1]) + (a8[2] + a8[3])) + ((a8[4] + a8[5]) + (a8[6] + a8[7]));
     __shared__ double red[kThreads];
     red[threadIdx.x] = acc;
     __syncthreads();

@@ -32,9 +32,24 @@ def test_library_exports_every_header_symbol():
     assert set(adr.NN_EXPORTS) == set(nn)
 
 
+def _axis_beta(n=33):
+    p = W.c1(n)
+    p.beta1, p.beta2 = np.ones_like(p.beta1), np.zeros_like(p.beta2)
+    return p
+
+
+def _diag_beta(n=33):
+    p = W.c1(n)
+    p.beta1, p.beta2 = np.ones_like(p.beta1), np.ones_like(p.beta2)
+    return p
+
+
+# the degenerate cases: one interior node (3x3), curves along grid lines and
+# through grid nodes (constant beta along an axis or a diagonal)
 @pytest.mark.parametrize("maker", [lambda: W.c1(65), lambda: W.c2(129), lambda: W.data2d(31),
                                    lambda: W.c4_instance(0, n_max=120), lambda: W.c4_instance(1, n_max=120),
-                                   lambda: W.c5_sample(3, n=65)])
+                                   lambda: W.c5_sample(3, n=65), lambda: W.c1(3), lambda: W.c1(4),
+                                   _axis_beta, _diag_beta])
 def test_host_geometry_matches_oracle(maker):
     from paper_2411_11041_amd.adr import Solver
     p = maker()
@@ -86,3 +101,13 @@ def test_setup_errors():
         Solver(p, theta=0.0, host_only=True)
     with pytest.raises(ADRError):
         Solver(p, dt=-1.0, host_only=True)
+
+
+def test_empty_and_undersized_inputs_rejected():
+    from paper_2411_11041_amd.adr import ADRError, Solver, ADR_EINVAL
+    with pytest.raises(ADRError) as e:
+        Solver([], host_only=True)
+    assert e.value.code == ADR_EINVAL
+    with pytest.raises(ADRError) as e:
+        Solver(W.c1(2), host_only=True)  # no interior node
+    assert e.value.code == ADR_EINVAL

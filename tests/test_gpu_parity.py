@@ -249,3 +249,40 @@ def test_autotune_keeps_a_candidate_and_the_fixed_point():
     Uo, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-12)
     assert rel_l2(u.cpu().numpy(), Uo) < 1e-5
     s.close()
+
+
+def _const_beta(n, b1, b2):
+    p = W.c1(n)
+    p.beta1, p.beta2 = np.full_like(p.beta1, b1), np.full_like(p.beta2, b2)
+    return p
+
+
+@pytest.mark.parametrize("name,maker", [("c1_3", lambda: W.c1(3)), ("c1_4", lambda: W.c1(4)),
+                                        ("c1_5", lambda: W.c1(5)),
+                                        ("axis_33", lambda: _const_beta(33, 1.0, 0.0)),
+                                        ("diag_33", lambda: _const_beta(33, 1.0, 1.0))])
+def test_degenerate_cases_match_oracle(name, maker):
+    """One interior node; curves on grid lines; curves through grid nodes."""
+    print(f"[case] degenerate {name} fp64 6 sweeps", flush=True)
+    p = maker()
+    o = Oracle(p)
+    s = solver(p, precision="fp64", theta=1.0, dt=0.05)
+    u = dev(o.zero_field())
+    s.split_iterate(u, 6, 0.0)
+    torch.cuda.synchronize()
+    U = o.zero_field()
+    for _ in range(6):
+        U = o.step(U, 1.0, 0.05)
+    assert rel_l2(u.cpu().numpy(), U) < 1e-11
+    s.close()
+
+
+def test_curve_beyond_the_line_solver_is_rejected():
+    """The longest curve the LDS line solver holds is 3072 nodes: C2's flow on
+    2700^2 has gamma-curves of up to 3216 nodes, which set-up rejects (2049^2,
+    the benchmark size, has at most 2440)."""
+    print("[case] c2 2700 set-up (a curve over 3072 nodes)", flush=True)
+    from paper_2411_11041_amd.adr import ADRError, ADR_EINVAL
+    with pytest.raises(ADRError) as e:
+        solver(W.c2(2700), precision="fp32")
+    assert e.value.code == ADR_EINVAL and "3072" in str(e.value)
