@@ -41,7 +41,7 @@ template <typename T, int FAM, int MAXJ>
 __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restrict__ fin, T *__restrict__ vout,
                                           const double *__restrict__ par, const int *__restrict__ done, int nmax) {
     // LDS: line_lds_arrays(FAM) arrays of line_lds_stride(nmax) elements
-    //   P0  gathered values U, then the right-hand sides D, then the solution X
+    //   P0  gathered values U, then the solution X
     //   P1  chords h; after every thread has read its chunk, the reduced system
     //   P2  |beta| (beta family)
     // The matrix rows are rebuilt in registers from h and |beta| in chunk
@@ -52,7 +52,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T *P0 = reinterpret_cast<T *>(smem_raw);
     T *P1 = P0 + S;
     T *P2 = P1 + S;
-    T *U = P0, *D = P0, *X = P0;
+    T *U = P0, *X = P0;
     T *Hs = P1, *Ws = P2;
     T *RA = P1;
     T *RB = RA + kThreads;
@@ -74,9 +74,12 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     const T cM = T(pp[0]), cK = T(pp[1]), cC = T(pp[2]);
     const T eM = T(pp[3]), eK = T(pp[4]), eC = T(pp[5]), eL = T(pp[6]);
 
-    // chunking of the rows: thread q owns rows q*m .. q*m+m-1 (m <= MAXJ)
+    // chunking of the rows: thread q owns rows rs .. rs+k-1, rs = q*m (m <= MAXJ)
     const int m = (N + kThreads - 1) / kThreads;
     const int Q = (N + m - 1) / m;  // non-empty chunks
+    const int q = tid;
+    const int rs = q * m;
+    const int k = q < Q ? min(m, N - rs) : 0;
 
     // 1. all loads of this thread's nodes j = tid + 256 q (coalesced) issued
     //    before any use, then the bilinear gather (eq. (22)); node values to LDS
@@ -84,23 +87,19 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     int cj[MAXJ];
     T lxj[MAXJ], lyj[MAXJ];
 #pragma unroll
-    for (int q = 0; q < MAXJ; ++q) {
-        const int j = tid + kThreads * q;
-        cj[q] = -1;
-        lxj[q] = T(0);
-        lyj[q] = T(0);
+    for (int sl = 0; sl < MAXJ; ++sl) {
+        const int j = tid + kThreads * sl;
+        cj[sl] = -1;
+        lxj[sl] = T(0);
+        lyj[sl] = T(0);
         if (j > 0 && j < n - 1) {
-            const int k = o + j;
-            cj[q] = a.cell[k];
-            lxj[q] = a.lx[k];
-            lyj[q] = a.ly[k];
+            const int kn = o + j;
+            cj[sl] = a.cell[kn];
+            lxj[sl] = a.lx[kn];
+            lyj[sl] = a.ly[kn];
         }
-        if (j > 0 && j < n) hj[q] = a.h[o + j];
-        if (FAM == 0) {
-            if (j < n) wj[q] = a.w[o + j];
-            // load of row j (node j + 1)
-            lk[q] = (j < N && eL != T(0)) ? a.L[o + j + 1] : T(0);
-        }
+        if (j > 0 && j < n) hj[sl] = a.h[o + j];
+        if (FAM == 0 && j < n) wj[sl] = a.w[o + j];
     }
     // gathers in groups of (up to) 4 slots: the 16 corner loads of a group are
     // issued together (cell 0 stands in for the end nodes, whose value is
@@ -119,83 +118,85 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         }
 #pragma unroll
         for (int t = 0; t < G; ++t) {
-            const int q = q0 + t;
-            const int j = tid + kThreads * q;
-            const T lx = lxj[q], ly = lyj[q];
+            const int sl = q0 + t;
+            const int j = tid + kThreads * sl;
+            const T lx = lxj[sl], ly = lyj[sl];
             const T ub = (T(1) - ly) * ((T(1) - lx) * p11[t] + lx * p12[t]) + ly * ((T(1) - lx) * p21[t] + lx * p22[t]);
-            const T uj = cj[q] >= 0 ? ub : T(0);
+            const T uj = cj[sl] >= 0 ? ub : T(0);
             if (j < n) {
                 U[j] = uj;
-                if (j > 0) Hs[j] = hj[q];
-                if (FAM == 0) Ws[j] = wj[q];
+                if (j > 0) Hs[j] = hj[sl];
+                if (FAM == 0) Ws[j] = wj[sl];
             }
         }
     }
-    __syncthreads();
-
-    // 2. right-hand sides of the rows r = tid + 256 q (node r + 1) of A x = rhs
-    const T sixth = T(1) / T(6), third = T(1) / T(3);
-    T rh[MAXJ];
+    // loads of this thread's own rows (node rs + j + 1), in chunk order, in
+    // flight across the barrier
+    if (FAM == 0) {
 #pragma unroll
-    for (int q = 0; q < MAXJ; ++q) {
-        const int r = tid + kThreads * q;
-        if (r < N) {
-            const T hl = Hs[r + 1], hr = Hs[r + 2];
-            const T mlo = hl * sixth, mdi = (hl + hr) * third, mup = hr * sixth;
-            const T il = recip(hl), ir = recip(hr);
-            const T klo = -il, kdi = il + ir, kup = -ir;
-            const T um = U[r], u0 = U[r + 1], up = U[r + 2];
-            T rhs = eM * (mlo * um + mdi * u0 + mup * up) + eK * (klo * um + kdi * u0 + kup * up);
-            if (FAM == 0) {
-                const T wm = Ws[r], w0 = Ws[r + 1], wp = Ws[r + 2];
-                const T clo = -(wm + T(2) * w0) * sixth;
-                const T cdi = (wm - wp) * sixth;
-                const T cup = (T(2) * w0 + wp) * sixth;
-                rhs += eC * (clo * um + cdi * u0 + cup * up) + eL * lk[q];
-            }
-            rh[q] = rhs;
-        }
-    }
-    __syncthreads();  // U fully read: P0 now takes the right-hand sides
-#pragma unroll
-    for (int q = 0; q < MAXJ; ++q) {
-        const int r = tid + kThreads * q;
-        if (r < N) D[r] = rh[q];
+        for (int j = 0; j < MAXJ; ++j) lk[j] = (j < k && eL != T(0)) ? a.L[o + rs + j + 1] : T(0);
     }
     __syncthreads();
 
-    // 3. chunked elimination in registers.  Chunk q: rows rs..rs+k-1; its last
+    // 2. chunked elimination in registers.  Chunk q: rows rs..rs+k-1; its last
     //    row is a separator unless q is the last chunk; the others are interior
     //    rows, eliminated top-down with their dependence on the separators
     //    S_{q-1} (left) and S_q (right) carried along.
-    const int q = tid;
-    const int rs = q * m;
-    const int k = q < Q ? min(m, N - rs) : 0;
     const bool has_sep = q < Q - 1;
     const int kin = has_sep ? k - 1 : k;
+    // rows and right-hand sides of the chunk, P1 rows of eq. (16)-(19):
+    // M, K and C entries from the chords and |beta| (a sliding window over the
+    // chunk's nodes), A = cM M + cK K + cC C, rhs = (eM M + eK K + eC C) u + eL L
+    const T sixth = T(1) / T(6), third = T(1) / T(3);
     T ra_[MAXJ], rb_[MAXJ], rc_[MAXJ], rd_[MAXJ];
-#pragma unroll
-    for (int j = 0; j < MAXJ; ++j) {
-        if (j < k) {
-            const int r = rs + j;
-            const T hl = Hs[r + 1], hr = Hs[r + 2];
-            const T il = recip(hl), ir = recip(hr);
-            T lo = cM * (hl * sixth) - cK * il;
-            T di = cM * ((hl + hr) * third) + cK * (il + ir);
-            T hi = cM * (hr * sixth) - cK * ir;
+    {
+        T um = T(0), u0 = T(0), hl = T(1), il = T(1), wm = T(0), w0 = T(0);
+        if (k > 0) {
+            um = U[rs];
+            u0 = U[rs + 1];
+            hl = Hs[rs + 1];
+            il = recip(hl);
             if (FAM == 0) {
-                const T wm = Ws[r], w0 = Ws[r + 1], wp = Ws[r + 2];
-                lo += cC * (-(wm + T(2) * w0) * sixth);
-                di += cC * ((wm - wp) * sixth);
-                hi += cC * ((T(2) * w0 + wp) * sixth);
+                wm = Ws[rs];
+                w0 = Ws[rs + 1];
             }
-            ra_[j] = lo;
-            rb_[j] = di;
-            rc_[j] = hi;
-            rd_[j] = D[r];
+        }
+#pragma unroll
+        for (int j = 0; j < MAXJ; ++j) {
+            if (j < k) {
+                const int r = rs + j;
+                const T up = U[r + 2], hr = Hs[r + 2];
+                const T ir = recip(hr);
+                const T mlo = hl * sixth, mdi = (hl + hr) * third, mup = hr * sixth;
+                const T klo = -il, kdi = il + ir, kup = -ir;
+                T lo = cM * mlo + cK * klo;
+                T di = cM * mdi + cK * kdi;
+                T hi = cM * mup + cK * kup;
+                T rhs = eM * (mlo * um + mdi * u0 + mup * up) + eK * (klo * um + kdi * u0 + kup * up);
+                if (FAM == 0) {
+                    const T wp = Ws[r + 2];
+                    const T clo = -(wm + T(2) * w0) * sixth;
+                    const T cdi = (wm - wp) * sixth;
+                    const T cup = (T(2) * w0 + wp) * sixth;
+                    lo += cC * clo;
+                    di += cC * cdi;
+                    hi += cC * cup;
+                    rhs += eC * (clo * um + cdi * u0 + cup * up) + eL * lk[j];
+                    wm = w0;
+                    w0 = wp;
+                }
+                ra_[j] = lo;
+                rb_[j] = di;
+                rc_[j] = hi;
+                rd_[j] = rhs;
+                um = u0;
+                u0 = up;
+                hl = hr;
+                il = ir;
+            }
         }
     }
-    __syncthreads();  // h, |beta| and D read: P1 takes the reduced system, P0 the solution
+    __syncthreads();  // U, h and |beta| read: P1 takes the reduced system, P0 the solution
     T sa = T(0), sb = T(1), sc = T(0), sd = T(0);  // separator row
     {
         T pc = T(0), py = T(0), pa = T(0);
@@ -243,7 +244,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     }
     __syncthreads();
 
-    // 4. reduced system on the separators S_0..S_{Q-2}, PCR in LDS
+    // 3. reduced system on the separators S_0..S_{Q-2}, PCR in LDS
     const int R = Q - 1;
     {
         T ra = T(0), rb = T(1), rc = T(0), rd = T(0);
@@ -278,7 +279,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         __syncthreads();
     }
 
-    // 5. back-substitution of every chunk into X (P0)
+    // 4. back-substitution of every chunk into X (P0)
     if (q < Q) {
         const T SL = q > 0 ? RD[q - 1] : T(0);
         const T SR = q < R ? RD[q] : T(0);
