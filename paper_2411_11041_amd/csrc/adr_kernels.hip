@@ -22,8 +22,8 @@ namespace adr {
 constexpr int kThreads = 256;
 
 // LDS of a line-solve workgroup: arrays of `stride` elements (the longest curve
-// of the launch, at least the 7 x 256 entries of the reduced system)
-__host__ __device__ inline int line_lds_stride(int nmax) { return ((nmax > 7 * kThreads ? nmax : 7 * kThreads) + 3) & ~3; }
+// of the launch, at least the 6 x 256 entries of the reduced system)
+__host__ __device__ inline int line_lds_stride(int nmax) { return ((nmax > 6 * kThreads ? nmax : 6 * kThreads) + 3) & ~3; }
 __host__ __device__ inline int line_lds_arrays(int fam) { return fam == 0 ? 3 : 2; }
 
 // 1/x: IEEE division in FP64 (parity with the FP64 oracle), the hardware
@@ -54,13 +54,11 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T *P2 = P1 + S;
     T *U = P0, *X = P0;
     T *Hs = P1, *Ws = P2;
-    T *RA = P1;
-    T *RB = RA + kThreads;
-    T *RC = RB + kThreads;
-    T *RD = RC + kThreads;
-    T *FY = RD + kThreads;
-    T *FA = FY + kThreads;
-    T *FG = FA + kThreads;
+    // reduced system: two buffers of normalised rows (a, c, d); the chunks'
+    // first rows FY, FA, FG occupy the second buffer until the first PCR step
+    T *A0 = P1, *C0 = A0 + kThreads, *D0 = C0 + kThreads;
+    T *A1 = D0 + kThreads, *C1 = A1 + kThreads, *D1 = C1 + kThreads;
+    T *FY = A1, *FA = C1, *FG = D1;
 
     const int l = blockIdx.x;
     const int tid = threadIdx.x;
@@ -244,45 +242,53 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     }
     __syncthreads();
 
-    // 3. reduced system on the separators S_0..S_{Q-2}, PCR in LDS
+    // 3. reduced system on the separators S_0..S_{Q-2}: parallel cyclic
+    //    reduction on rows normalised to a unit diagonal,
+    //    a x_{q-s} + x_q + c x_{q+s} = d, ping-ponging between two LDS buffers
+    //    (one reciprocal and one barrier per step).  Finally d = S_q.
     const int R = Q - 1;
+    const T *Sv = D0;
     {
-        T ra = T(0), rb = T(1), rc = T(0), rd = T(0);
+        T ra = T(0), rc = T(0), rd = T(0);
         if (q < R) {
             const T nfy = FY[q + 1], nfa = FA[q + 1], nfg = FG[q + 1];
-            ra = q > 0 ? sa * aL : T(0);
-            rb = sb + sa * gL + sc * nfa;
-            rc = q + 1 < R ? sc * nfg : T(0);
-            rd = sd - sa * yL - sc * nfy;
+            const T a = q > 0 ? sa * aL : T(0);
+            const T b = sb + sa * gL + sc * nfa;
+            const T c = q + 1 < R ? sc * nfg : T(0);
+            const T d = sd - sa * yL - sc * nfy;
+            const T ib = recip(b);
+            ra = a * ib;
+            rc = c * ib;
+            rd = d * ib;
         }
-        RA[q] = ra; RB[q] = rb; RC[q] = rc; RD[q] = rd;
+        A0[q] = ra; C0[q] = rc; D0[q] = rd;
         __syncthreads();
-        for (int s = 1; s < R; s <<= 1) {
-            T na = ra, nb = rb, nc = rc, nd = rd;
+        T *Ai = A0, *Ci = C0, *Di = D0, *Ao = A1, *Co = C1, *Do = D1;
+        for (int st = 1; st < R; st <<= 1) {
             if (q < R) {
-                T la = T(0), lb = T(1), lc = T(0), ld = T(0);
-                T ua = T(0), ub = T(1), uc = T(0), ud = T(0);
-                if (q - s >= 0) { la = RA[q - s]; lb = RB[q - s]; lc = RC[q - s]; ld = RD[q - s]; }
-                if (q + s < R) { ua = RA[q + s]; ub = RB[q + s]; uc = RC[q + s]; ud = RD[q + s]; }
-                const T k1 = ra * recip(lb), k2 = rc * recip(ub);
-                na = -la * k1;
-                nc = -uc * k2;
-                nb = rb - lc * k1 - ua * k2;
-                nd = rd - ld * k1 - ud * k2;
+                T la = T(0), lc = T(0), ld = T(0), ua = T(0), uc = T(0), ud = T(0);
+                if (q - st >= 0) { la = Ai[q - st]; lc = Ci[q - st]; ld = Di[q - st]; }
+                if (q + st < R) { ua = Ai[q + st]; uc = Ci[q + st]; ud = Di[q + st]; }
+                const T ib = recip(T(1) - ra * lc - rc * ua);
+                const T na = -(ra * la) * ib;
+                const T nc = -(rc * uc) * ib;
+                const T nd = (rd - ra * ld - rc * ud) * ib;
+                ra = na; rc = nc; rd = nd;
             }
+            Ao[q] = ra; Co[q] = rc; Do[q] = rd;
             __syncthreads();
-            ra = na; rb = nb; rc = nc; rd = nd;
-            RA[q] = ra; RB[q] = rb; RC[q] = rc; RD[q] = rd;
-            __syncthreads();
+            T *t;
+            t = Ai; Ai = Ao; Ao = t;
+            t = Ci; Ci = Co; Co = t;
+            t = Di; Di = Do; Do = t;
         }
-        if (q < R) RD[q] = rd / rb;  // S_q
-        __syncthreads();
+        Sv = Di;
     }
 
     // 4. back-substitution of every chunk into X (P0)
     if (q < Q) {
-        const T SL = q > 0 ? RD[q - 1] : T(0);
-        const T SR = q < R ? RD[q] : T(0);
+        const T SL = q > 0 ? Sv[q - 1] : T(0);
+        const T SR = q < R ? Sv[q] : T(0);
         T x = T(0);
 #pragma unroll
         for (int j = MAXJ - 1; j >= 0; --j) {
