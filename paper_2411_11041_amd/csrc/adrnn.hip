@@ -67,39 +67,67 @@ __global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ 
     const int HW = H * W;
     const int ntiles = (NP + 15) / 16;
     const v4i16 zero = {0, 0, 0, 0};
+    const float bias0 = EPI == 0 ? bias[i] : 0.f, bias1 = EPI == 0 ? bias[i + 16] : 0.f;
     for (int t = blockIdx.x * 4 + wave; t < ntiles; t += gridDim.x * 4) {
         const int gp = t * 16 + i;  // pixel of this lane's A row
         const bool pv = gp < NP;
         const int b = gp / HW, p = gp - b * HW, py = p / W, px = p - py * W;
         v4f32 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
+        // back-propagation: the ReLU mask of the outputs, loaded with the operands
+        bf16_t ym0[4], ym1[4];
+        if constexpr (EPI == 1) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int po = t * 16 + 4 * g + v;
+                const size_t pq = static_cast<size_t>(po < NP ? po : 0) * kCh;
+                ym0[v] = ymask[pq + i];
+                ym1[v] = ymask[pq + i + 16];
+            }
+        }
+        // every A fragment of the tile is loaded before the first product: a
+        // tap outside the image reads a valid pixel (the tile's own, or pixel 0
+        // past the end) and is replaced by zeros, so no load sits behind a branch
+        const ptrdiff_t self = pv ? gp : 0;
         if constexpr (CIN == 32) {
+            v4i16 av[18];
 #pragma unroll
             for (int tap = 0; tap < 9; ++tap) {
                 const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
                 const bool ok = pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-                const bf16_t *src = x + static_cast<ptrdiff_t>(gp + dy * W + dx) * CIN;
+                const bf16_t *src = x + (ok ? static_cast<ptrdiff_t>(gp + dy * W + dx) : self) * CIN;
 #pragma unroll
                 for (int cc = 0; cc < 2; ++cc) {
-                    const v4i16 a = ok ? *reinterpret_cast<const v4i16 *>(src + cc * 16 + g * 4) : zero;
-                    const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * CIN + cc * 16 + g * 4]);
-                    const v4i16 b1 =
-                        *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * CIN + cc * 16 + g * 4]);
-                    acc0 = mfma(a, b0, acc0);
-                    acc1 = mfma(a, b1, acc1);
+                    const v4i16 v = *reinterpret_cast<const v4i16 *>(src + cc * 16 + g * 4);
+                    av[tap * 2 + cc] = ok ? v : zero;
                 }
             }
+#pragma unroll
+            for (int t = 0; t < 18; ++t) {
+                const int tap = t / 2, cc = t % 2;
+                const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * CIN + cc * 16 + g * 4]);
+                const v4i16 b1 =
+                    *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * CIN + cc * 16 + g * 4]);
+                acc0 = mfma(av[t], b0, acc0);
+                acc1 = mfma(av[t], b1, acc1);
+            }
         } else {
+            v4i16 av[3];
 #pragma unroll
             for (int kc = 0; kc < 3; ++kc) {
                 const int tap = kc * 4 + g;  // this lane group's tap
                 const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
                 const bool ok = tap < 9 && pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-                const v4i16 a = ok ? *reinterpret_cast<const v4i16 *>(x + static_cast<ptrdiff_t>(gp + dy * W + dx) * 4)
-                                   : zero;
+                const v4i16 v = *reinterpret_cast<const v4i16 *>(
+                    x + (ok ? static_cast<ptrdiff_t>(gp + dy * W + dx) : self) * 4);
+                av[kc] = ok ? v : zero;
+            }
+#pragma unroll
+            for (int kc = 0; kc < 3; ++kc) {
+                const int tap = kc * 4 + g;
                 const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * 4]);
                 const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * 4]);
-                acc0 = mfma(a, b0, acc0);
-                acc1 = mfma(a, b1, acc1);
+                acc0 = mfma(av[kc], b0, acc0);
+                acc1 = mfma(av[kc], b1, acc1);
             }
         }
 #pragma unroll
@@ -108,11 +136,11 @@ __global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ 
             if (po >= NP) continue;
             float z0 = acc0[v], z1 = acc1[v];
             if constexpr (EPI == 0) {
-                z0 = fmaxf(z0 + bias[i], 0.f);
-                z1 = fmaxf(z1 + bias[i + 16], 0.f);
+                z0 = fmaxf(z0 + bias0, 0.f);
+                z1 = fmaxf(z1 + bias1, 0.f);
             } else {
-                z0 = bf_pos(ymask[static_cast<size_t>(po) * kCh + i]) ? z0 : 0.f;
-                z1 = bf_pos(ymask[static_cast<size_t>(po) * kCh + i + 16]) ? z1 : 0.f;
+                z0 = bf_pos(ym0[v]) ? z0 : 0.f;
+                z1 = bf_pos(ym1[v]) ? z1 : 0.f;
             }
             y[static_cast<size_t>(po) * kCh + i] = f2bf(z0);
             y[static_cast<size_t>(po) * kCh + i + 16] = f2bf(z1);
@@ -132,12 +160,13 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__
     constexpr int NJT = (NCOL + 15) / 16;         // column tiles
     constexpr int NT = 2 * NJT;                   // output tiles (2 row tiles of 16 channels)
     constexpr int TPW = (NT + 3) / 4;             // tiles per wave
-    const int bspan = kChunk + 2 * d;  // one band
+    const int bspan = (kChunk + 2 * d + 3) & ~3;  // one band (a multiple of 4: aligned fragments)
     const int span = 3 * bspan;
     extern __shared__ __align__(16) unsigned char sm[];
-    bf16_t *gT = reinterpret_cast<bf16_t *>(sm);                // [32][kChunk]
-    bf16_t *xT = gT + kCh * kChunk;                             // [CIN][3][bspan]
-    short *pyx = reinterpret_cast<short *>(xT + CIN * span);    // [kChunk][2] (y, x), -1 for no pixel
+    constexpr int GS = kChunk + 4;                              // gT row stride (8-byte aligned, 2-way banks)
+    bf16_t *gT = reinterpret_cast<bf16_t *>(sm);                // [32][GS]
+    bf16_t *xT = gT + kCh * GS;                                 // [CIN][3][bspan]
+    unsigned short *vm = reinterpret_cast<unsigned short *>(xT + CIN * span);  // [kChunk] valid taps (bit tap)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, g = lane >> 4;
     const int HW = H * W;
@@ -152,7 +181,9 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__
         for (int e = threadIdx.x; e < kCh * kChunk; e += kThreads) {
             const int pl = e / kCh, n = e % kCh;  // coalesced read of g
             const int gp = c0 + pl;
-            gT[n * kChunk + pl] = gp < NP ? gsrc[static_cast<size_t>(gp) * kCh + n] : bf16_t(0);
+            const bf16_t gv = gp < NP ? gsrc[static_cast<size_t>(gp) * kCh + n] : bf16_t(0);
+            gT[n * GS + pl] = gv;
+            dbias += bf2f(gv);  // this thread always stages channel n = threadIdx.x % 32
         }
         for (int e = threadIdx.x; e < span * CIN; e += kThreads) {
             const int sl = e / CIN, c = e % CIN;  // coalesced read of x
@@ -162,21 +193,18 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__
         }
         for (int pl = threadIdx.x; pl < kChunk; pl += kThreads) {
             const int gp = c0 + pl;
-            short yy = -1, xx = -1;
+            unsigned mask = 0;
             if (gp < NP) {
-                const int p = gp % HW;
-                yy = static_cast<short>(p / W);
-                xx = static_cast<short>(p % W);
+                const int p = gp % HW, yy = p / W, xx = p % W;
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) {
+                    const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+                    if (yy + dy >= 0 && yy + dy < H && xx + dx >= 0 && xx + dx < W) mask |= 1u << tap;
+                }
             }
-            pyx[2 * pl] = yy;
-            pyx[2 * pl + 1] = xx;
+            vm[pl] = static_cast<unsigned short>(mask);
         }
         __syncthreads();
-        if (threadIdx.x < kCh) {
-            float s = 0.f;
-            for (int pl = 0; pl < kChunk; ++pl) s += bf2f(gT[threadIdx.x * kChunk + pl]);
-            dbias += s;
-        }
 #pragma unroll
         for (int q = 0; q < TPW; ++q) {
             const int tile = wave * TPW + q;
@@ -186,18 +214,36 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__
             const int col = jt * 16 + i;               // B column (tap, c)
             const bool colok = col < NCOL;
             const int tap = colok ? col / CIN : 0, c = colok ? col % CIN : 0;
-            const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            const int dx = d * (tap % 3 - 1);
             const int off = (tap / 3) * bspan + d + dx;  // band of the tap row, then the shift in the band
+            const unsigned tbit = colok ? 1u << tap : 0u;
+            const int base = c * span + off;
             for (int k0 = 0; k0 < kChunk; k0 += 16) {
-                const v4i16 a = *reinterpret_cast<const v4i16 *>(&gT[n * kChunk + k0 + 4 * g]);
+                const v4i16 a = *reinterpret_cast<const v4i16 *>(&gT[n * GS + k0 + 4 * g]);
+                const int pl0 = k0 + 4 * g;
+                // the valid-tap masks of the 4 pixels, one 8-byte read
+                const uint2 mw = *reinterpret_cast<const uint2 *>(&vm[pl0]);
+                const unsigned m4[4] = {mw.x & 0xffffu, mw.x >> 16, mw.y & 0xffffu, mw.y >> 16};
+                // 4 consecutive pixels of channel c shifted by the tap: with 32 input
+                // channels all lanes of a column tile share the tap, so the alignment
+                // (and the read width) is uniform across the wavefront
+                v4i16 raw;
+                if (CIN == 32 && (off & 3) == 0) {
+                    raw = *reinterpret_cast<const v4i16 *>(&xT[base + pl0]);
+                } else if (CIN == 32 && (off & 1) == 0) {
+                    const unsigned lo = *reinterpret_cast<const unsigned *>(&xT[base + pl0]);
+                    const unsigned hi = *reinterpret_cast<const unsigned *>(&xT[base + pl0 + 2]);
+                    raw[0] = static_cast<short>(lo & 0xffffu);
+                    raw[1] = static_cast<short>(lo >> 16);
+                    raw[2] = static_cast<short>(hi & 0xffffu);
+                    raw[3] = static_cast<short>(hi >> 16);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) raw[v] = static_cast<short>(xT[base + pl0 + v]);
+                }
                 v4i16 bv;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int pl = k0 + 4 * g + v;
-                    const int yy = pyx[2 * pl], xx = pyx[2 * pl + 1];
-                    const bool ok = colok && yy >= 0 && yy + dy >= 0 && yy + dy < H && xx + dx >= 0 && xx + dx < W;
-                    bv[v] = ok ? static_cast<short>(xT[c * span + off + pl]) : short(0);
-                }
+                for (int v = 0; v < 4; ++v) bv[v] = (m4[v] & tbit) ? raw[v] : short(0);
                 acc[q] = mfma(a, bv, acc[q]);
             }
         }
@@ -216,30 +262,86 @@ __global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__
             out[n * NCOL + col] = acc[q][v];
         }
     }
-    if (threadIdx.x < kCh) out[kCh * NCOL + threadIdx.x] = dbias;
+    // bias gradient: the 8 threads of each channel, in thread order
+    __syncthreads();
+    float *bred = reinterpret_cast<float *>(sm);
+    bred[threadIdx.x] = dbias;
+    __syncthreads();
+    if (threadIdx.x < kCh) {
+        float sb = 0.f;
+        for (int r = 0; r < kThreads / kCh; ++r) sb += bred[threadIdx.x + r * kCh];
+        out[kCh * NCOL + threadIdx.x] = sb;
+    }
 }
 
-// sum of per-block partials in block order (deterministic)
-__global__ void k_reduce(const float *__restrict__ part, int nblk, int len, float *__restrict__ out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= len) return;
-    float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[static_cast<size_t>(b) * len + e];
-    out[e] = s;
+// sum of per-block partials (deterministic): a 256-thread block covers 32
+// elements; thread group r (8 groups) sums the partials of blocks r, r+8, ...
+// with four loads in flight, then the 8 group sums are added in group order
+__global__ __launch_bounds__(kThreads) void k_reduce(const float *__restrict__ part, int nblk, int len,
+                                                     float *__restrict__ out) {
+    const int el = blockIdx.x * 32 + (threadIdx.x & 31), r = threadIdx.x >> 5;
+    float a4[4] = {0.f, 0.f, 0.f, 0.f};
+    if (el < len) {
+        int b = r;
+        for (; b + 24 < nblk; b += 32) {
+            float p4[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p4[u] = part[static_cast<size_t>(b + 8 * u) * len + el];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a4[u] += p4[u];
+        }
+        for (; b < nblk; b += 8) a4[0] += part[static_cast<size_t>(b) * len + el];
+    }
+    __shared__ float red[8][32];
+    red[r][threadIdx.x & 31] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
+    __syncthreads();
+    if (r == 0 && el < len) {
+        float sum = 0.f;
+        for (int q = 0; q < 8; ++q) sum += red[q][threadIdx.x];
+        out[el] = sum;
+    }
 }
 
 // ------------------------------------------------------------------ last layer (32 -> 1), VALU
-__global__ void k_last_fwd(const bf16_t *__restrict__ y3, const float *__restrict__ W4, const float *__restrict__ b4,
-                           float *__restrict__ out, int NP, int H, int W, int d) {
+__global__ __launch_bounds__(kThreads) void k_last_fwd(const bf16_t *__restrict__ y3, const float *__restrict__ W4,
+                                                       const float *__restrict__ b4, float *__restrict__ out, int NP,
+                                                       int H, int W, int d) {
+    __shared__ float w4s[kW4];
+    for (int e = threadIdx.x; e < kW4; e += blockDim.x) w4s[e] = W4[e];
+    __syncthreads();
     const int gp = blockIdx.x * blockDim.x + threadIdx.x;
     if (gp >= NP) return;
     const int HW = H * W, p = gp % HW, py = p / W, px = p % W;
     float s = b4[0];
-    for (int tap = 0; tap < 9; ++tap) {
-        const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-        if (py + dy < 0 || py + dy >= H || px + dx < 0 || px + dx >= W) continue;
-        const bf16_t *src = y3 + static_cast<size_t>(gp + dy * W + dx) * kCh;
-        for (int c = 0; c < kCh; ++c) s += W4[tap * kCh + c] * bf2f(src[c]);
+    // taps in groups of 3: each tap's 32 channels are four 16-byte loads, all
+    // issued before use; a tap outside the image reads the pixel itself and is
+    // dropped
+#pragma unroll
+    for (int t0 = 0; t0 < 9; t0 += 3) {
+        uint4 v[3][4];
+        bool ok[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int tap = t0 + u, dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            ok[u] = py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
+            const uint4 *src = reinterpret_cast<const uint4 *>(y3 + static_cast<size_t>(ok[u] ? gp + dy * W + dx : gp) * kCh);
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) v[u][c4] = src[c4];
+        }
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            if (!ok[u]) continue;
+            const float *w = w4s + (t0 + u) * kCh;
+#pragma unroll
+            for (int c4 = 0; c4 < 4; ++c4) {
+                const unsigned q[4] = {v[u][c4].x, v[u][c4].y, v[u][c4].z, v[u][c4].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = c4 * 8 + 2 * e;
+                    s += w[c] * __uint_as_float(q[e] << 16) + w[c + 1] * __uint_as_float(q[e] & 0xffff0000u);
+                }
+            }
+        }
     }
     out[gp] = s;
 }
@@ -266,55 +368,99 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
 }
 
 // g3 = bf16( (sum_tap W4[tap][c] g4[p - d off(tap)]) * (y3 > 0) )
-__global__ void k_last_dgrad(const float *__restrict__ g4, const float *__restrict__ W4,
-                             const bf16_t *__restrict__ y3, bf16_t *__restrict__ g3, int NP, int H, int W, int d) {
+__global__ __launch_bounds__(kThreads) void k_last_dgrad(const float *__restrict__ g4, const float *__restrict__ W4,
+                                                         const bf16_t *__restrict__ y3, bf16_t *__restrict__ g3,
+                                                         int NP, int H, int W, int d) {
+    __shared__ float w4s[kW4];
+    for (int e = threadIdx.x; e < kW4; e += blockDim.x) w4s[e] = W4[e];
+    __syncthreads();
     const int gp = blockIdx.x * blockDim.x + threadIdx.x;
     if (gp >= NP) return;
     const int HW = H * W, p = gp % HW, py = p / W, px = p % W;
     float gn[9];
+#pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
         const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
         // pixel gp feeds output gp - d off through tap
         const bool ok = py - dy >= 0 && py - dy < H && px - dx >= 0 && px - dx < W;
-        gn[tap] = ok ? g4[gp - dy * W - dx] : 0.f;
+        const float gvl = g4[ok ? gp - dy * W - dx : gp];
+        gn[tap] = ok ? gvl : 0.f;
     }
-    for (int c = 0; c < kCh; ++c) {
-        float s = 0.f;
-        for (int tap = 0; tap < 9; ++tap) s += W4[tap * kCh + c] * gn[tap];
-        const bf16_t yv = y3[static_cast<size_t>(gp) * kCh + c];
-        g3[static_cast<size_t>(gp) * kCh + c] = f2bf(bf_pos(yv) ? s : 0.f);
+    // the pixel's 32 stored activations (ReLU mask) and gradients as four 16-byte words
+    const uint4 *ysrc = reinterpret_cast<const uint4 *>(y3 + static_cast<size_t>(gp) * kCh);
+    uint4 *gdst = reinterpret_cast<uint4 *>(g3 + static_cast<size_t>(gp) * kCh);
+#pragma unroll
+    for (int c4 = 0; c4 < 4; ++c4) {
+        const uint4 yv = ysrc[c4];
+        const unsigned yq[4] = {yv.x, yv.y, yv.z, yv.w};
+        unsigned oq[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            unsigned packed = 0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int c = c4 * 8 + 2 * e + h;
+                float s_ = 0.f;
+#pragma unroll
+                for (int tap = 0; tap < 9; ++tap) s_ += w4s[tap * kCh + c] * gn[tap];
+                const bf16_t yb = static_cast<bf16_t>(h == 0 ? (yq[e] & 0xffffu) : (yq[e] >> 16));
+                packed |= static_cast<unsigned>(f2bf(bf_pos(yb) ? s_ : 0.f)) << (16 * h);
+            }
+            oq[e] = packed;
+        }
+        gdst[c4] = make_uint4(oq[0], oq[1], oq[2], oq[3]);
     }
 }
 
-// part[blk][tap*32 + c] = sum over the block's pixels of g4[p] y3[p + d off][c]; part[blk][288] = sum g4
+// part[blk][tap*32 + c] = sum over the block's pixels of g4[p] y3[p + d off][c]; part[blk][288] = sum g4.
+// Thread t: channel pair cp = t % 16 (channels 2cp, 2cp+1) of the pixels p = t / 16 (mod 16) of
+// every chunk: 18 accumulators (9 taps x 2 channels); the 16 pixel groups are summed in LDS
+// at the end (fixed order).  A pixel row of y3 is read by 16 consecutive threads (64 bytes).
 __global__ __launch_bounds__(kThreads) void k_last_wgrad(const float *__restrict__ g4, const bf16_t *__restrict__ y3,
                                                          float *__restrict__ part, int NP, int H, int W, int d) {
-    const int e = threadIdx.x;  // 0..287 (two passes over 256 threads)
+    const int cp = threadIdx.x & 15, pg = threadIdx.x >> 4;
     const int HW = H * W;
-    float acc[2] = {0.f, 0.f};
+    float acc[9][2];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) acc[tap][0] = acc[tap][1] = 0.f;
+    float gsum = 0.f;
     const int nchunks = (NP + kChunk - 1) / kChunk;
     for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int c0 = ch * kChunk;
-        for (int pass = 0; pass < 2; ++pass) {
-            const int el = e + pass * kThreads;
-            if (el > kW4) continue;
-            float s = 0.f;
-            for (int pl = 0; pl < kChunk; ++pl) {
-                const int gp = c0 + pl;
-                if (gp >= NP) break;
-                const float gv = g4[gp];
-                if (el == kW4) { s += gv; continue; }
-                const int tap = el / kCh, c = el % kCh, dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-                const int p = gp % HW, py = p / W, px = p % W;
-                if (py + dy < 0 || py + dy >= H || px + dx < 0 || px + dx >= W) continue;
-                s += gv * bf2f(y3[static_cast<size_t>(gp + dy * W + dx) * kCh + c]);
+        for (int pl = pg; pl < kChunk; pl += 16) {
+            const int gp = c0 + pl;
+            if (gp >= NP) break;
+            const float gv = g4[gp];
+            if (cp == 0) gsum += gv;
+            const int p = gp % HW, py = p / W, px = p % W;
+            unsigned v[9];
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+                const bool ok = py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
+                const unsigned w = *reinterpret_cast<const unsigned *>(
+                    y3 + static_cast<size_t>(ok ? gp + dy * W + dx : gp) * kCh + 2 * cp);
+                v[tap] = ok ? w : 0u;
             }
-            acc[pass] += s;
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                acc[tap][0] += gv * __uint_as_float(v[tap] << 16);
+                acc[tap][1] += gv * __uint_as_float(v[tap] & 0xffff0000u);
+            }
         }
     }
-    for (int pass = 0; pass < 2; ++pass) {
-        const int el = e + pass * kThreads;
-        if (el <= kW4) part[static_cast<size_t>(blockIdx.x) * (kW4 + 1) + el] = acc[pass];
+    __shared__ float red[16][kW4 + 1];
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        red[pg][tap * kCh + 2 * cp] = acc[tap][0];
+        red[pg][tap * kCh + 2 * cp + 1] = acc[tap][1];
+    }
+    if (cp == 0) red[pg][kW4] = gsum;
+    __syncthreads();
+    for (int el = threadIdx.x; el <= kW4; el += kThreads) {
+        float sum = 0.f;
+        for (int q = 0; q < 16; ++q) sum += red[q][el];
+        part[static_cast<size_t>(blockIdx.x) * (kW4 + 1) + el] = sum;
     }
 }
 
@@ -454,8 +600,8 @@ T *nn_alloc(adrnn_ctx *c, size_t n) {
 }
 
 size_t wgrad_lds(int cin, int d) {
-    const int span = 3 * (kChunk + 2 * d);
-    return sizeof(bf16_t) * (kCh * kChunk + static_cast<size_t>(cin) * span) + sizeof(short) * 2 * kChunk;
+    const int span = 3 * ((kChunk + 2 * d + 3) & ~3);
+    return sizeof(bf16_t) * (kCh * (kChunk + 4) + static_cast<size_t>(cin) * span) + sizeof(short) * 2 * kChunk;
 }
 
 void convert(adrnn_ctx *c) {
@@ -491,7 +637,7 @@ void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, int d, float 
     hipLaunchKernelGGL((k_wgrad32<CIN>), dim3(nb), dim3(kThreads), lds, c->st, g, x, c->part, NP, c->H, c->W, d);
     NNCHK(hipGetLastError());
     const int len = kCh * 9 * CIN + kCh;
-    hipLaunchKernelGGL(k_reduce, dim3((len + 255) / 256), dim3(256), 0, c->st, c->part, nb, len, dst);
+    hipLaunchKernelGGL(k_reduce, dim3((len + 31) / 32), dim3(kThreads), 0, c->st, c->part, nb, len, dst);
     NNCHK(hipGetLastError());
 }
 
@@ -511,7 +657,7 @@ double grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint
     const int nchunks = (NP + kChunk - 1) / kChunk, nb = std::min(c->wblocks, nchunks);
     hipLaunchKernelGGL(k_last_wgrad, dim3(nb), dim3(kThreads), 0, c->st, c->g4, c->y3, c->part, NP, c->H, c->W,
                        kDil[3]);
-    hipLaunchKernelGGL(k_reduce, dim3((kW4 + 1 + 255) / 256), dim3(256), 0, c->st, c->part, nb, kW4 + 1, G + oW4);
+    hipLaunchKernelGGL(k_reduce, dim3((kW4 + 1 + 31) / 32), dim3(kThreads), 0, c->st, c->part, nb, kW4 + 1, G + oW4);
     hipLaunchKernelGGL(k_last_dgrad, dim3(lb), dim3(256), 0, c->st, c->g4, c->w4, c->y3, c->ga, NP, c->H, c->W,
                        kDil[3]);
     NNCHK(hipGetLastError());
