@@ -2,9 +2,11 @@
 // accumulation, training (backward, Adam) and inference, behind the C ABI of
 // include/adrnn.h.
 //
-// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: a wavefront
-// computes 16 pixels x 32 output channels (two 16x16 tiles); K runs over
-// (tap, input channel).  Operand layout of the instruction: lane l supplies
+// Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: M = pixels,
+// N = 32 output channels (two 16x16 tiles), K = (tap, input channel).  The
+// 32 -> 32 layers run tiled (k_conv32t: a 16 x 16-pixel tile and its dilated
+// halo staged in LDS), the 4 -> 32 first layer directly from global memory
+// (k_conv_in), the 32 -> 1 last layer on the vector ALUs.  Operand layout of the instruction: lane l supplies
 // A[l%16][4(l/16) .. 4(l/16)+3] and B[4(l/16) .. +3][l%16]; it receives
 // D[4(l/16) + v][l%16], v = 0..3.  NHWC activations make a lane's four K
 // values (four consecutive channels of one pixel) one 8-byte load.
@@ -47,15 +49,14 @@ __device__ __forceinline__ v4f32 mfma(v4i16 a, v4i16 b, v4f32 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// ------------------------------------------------------------------ conv (32 outputs)
-// EPI 0: y = bf16(relu(acc + bias)).   EPI 1: y = bf16(acc * (ymask > 0)) (back-propagation
-// through the ReLU of the layer input).  Wg: [32][9][CIN] BF16 (taps row-major).
-template <int CIN, int EPI>
-__global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ x, const bf16_t *__restrict__ Wg,
-                                                     const float *__restrict__ bias,
-                                                     const bf16_t *__restrict__ ymask, bf16_t *__restrict__ y,
-                                                     int NP, int H, int W, int d) {
-    constexpr int KT = CIN == 4 ? 12 : 9;  // taps, padded to whole K chunks for CIN = 4
+// ------------------------------------------------------------------ conv, 4 -> 32 (first layer)
+// y = bf16(relu(conv(x0) + bias)); x0: [NP][4] BF16, Wg: [32][9][4].  A wavefront
+// computes 16 pixels x 32 channels; K = 12 taps (9, padded) x 4 channels, one
+// tap per lane group, so a lane's 4 K values are one pixel's 4 channels.
+__global__ __launch_bounds__(kThreads) void k_conv_in(const bf16_t *__restrict__ x, const bf16_t *__restrict__ Wg,
+                                                      const float *__restrict__ bias, bf16_t *__restrict__ y,
+                                                      int NP, int H, int W, int d) {
+    constexpr int CIN = 4, KT = 12;
     __shared__ __align__(16) bf16_t Ws[kCh * KT * CIN];
     for (int e = threadIdx.x; e < kCh * KT * CIN; e += kThreads) {
         const int n = e / (KT * CIN), r = e % (KT * CIN), tap = r / CIN, c = r % CIN;
@@ -67,83 +68,167 @@ __global__ __launch_bounds__(kThreads) void k_conv32(const bf16_t *__restrict__ 
     const int HW = H * W;
     const int ntiles = (NP + 15) / 16;
     const v4i16 zero = {0, 0, 0, 0};
-    const float bias0 = EPI == 0 ? bias[i] : 0.f, bias1 = EPI == 0 ? bias[i + 16] : 0.f;
+    const float bias0 = bias[i], bias1 = bias[i + 16];
     for (int t = blockIdx.x * 4 + wave; t < ntiles; t += gridDim.x * 4) {
         const int gp = t * 16 + i;  // pixel of this lane's A row
         const bool pv = gp < NP;
         const int b = gp / HW, p = gp - b * HW, py = p / W, px = p - py * W;
         v4f32 acc0 = {0.f, 0.f, 0.f, 0.f}, acc1 = {0.f, 0.f, 0.f, 0.f};
-        // back-propagation: the ReLU mask of the outputs, loaded with the operands
-        bf16_t ym0[4], ym1[4];
-        if constexpr (EPI == 1) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int po = t * 16 + 4 * g + v;
-                const size_t pq = static_cast<size_t>(po < NP ? po : 0) * kCh;
-                ym0[v] = ymask[pq + i];
-                ym1[v] = ymask[pq + i + 16];
-            }
-        }
-        // every A fragment of the tile is loaded before the first product: a
-        // tap outside the image reads a valid pixel (the tile's own, or pixel 0
-        // past the end) and is replaced by zeros, so no load sits behind a branch
+        // every A fragment is loaded before the first product: a tap outside
+        // the image reads a valid pixel (the tile's own, or pixel 0 past the
+        // end) and is replaced by zeros, so no load sits behind a branch
         const ptrdiff_t self = pv ? gp : 0;
-        if constexpr (CIN == 32) {
-            v4i16 av[18];
+        v4i16 av[3];
 #pragma unroll
-            for (int tap = 0; tap < 9; ++tap) {
-                const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-                const bool ok = pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-                const bf16_t *src = x + (ok ? static_cast<ptrdiff_t>(gp + dy * W + dx) : self) * CIN;
+        for (int kc = 0; kc < 3; ++kc) {
+            const int tap = kc * 4 + g;  // this lane group's tap
+            const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            const bool ok = tap < 9 && pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
+            const v4i16 v = *reinterpret_cast<const v4i16 *>(
+                x + (ok ? static_cast<ptrdiff_t>(gp + dy * W + dx) : self) * CIN);
+            av[kc] = ok ? v : zero;
+        }
 #pragma unroll
-                for (int cc = 0; cc < 2; ++cc) {
-                    const v4i16 v = *reinterpret_cast<const v4i16 *>(src + cc * 16 + g * 4);
-                    av[tap * 2 + cc] = ok ? v : zero;
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < 18; ++t) {
-                const int tap = t / 2, cc = t % 2;
-                const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * CIN + cc * 16 + g * 4]);
-                const v4i16 b1 =
-                    *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * CIN + cc * 16 + g * 4]);
-                acc0 = mfma(av[t], b0, acc0);
-                acc1 = mfma(av[t], b1, acc1);
-            }
-        } else {
-            v4i16 av[3];
-#pragma unroll
-            for (int kc = 0; kc < 3; ++kc) {
-                const int tap = kc * 4 + g;  // this lane group's tap
-                const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-                const bool ok = tap < 9 && pv && py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-                const v4i16 v = *reinterpret_cast<const v4i16 *>(
-                    x + (ok ? static_cast<ptrdiff_t>(gp + dy * W + dx) : self) * 4);
-                av[kc] = ok ? v : zero;
-            }
-#pragma unroll
-            for (int kc = 0; kc < 3; ++kc) {
-                const int tap = kc * 4 + g;
-                const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * 4]);
-                const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * 4]);
-                acc0 = mfma(av[kc], b0, acc0);
-                acc1 = mfma(av[kc], b1, acc1);
-            }
+        for (int kc = 0; kc < 3; ++kc) {
+            const int tap = kc * 4 + g;
+            const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * CIN]);
+            const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * CIN]);
+            acc0 = mfma(av[kc], b0, acc0);
+            acc1 = mfma(av[kc], b1, acc1);
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int po = t * 16 + 4 * g + v;
             if (po >= NP) continue;
-            float z0 = acc0[v], z1 = acc1[v];
+            y[static_cast<size_t>(po) * kCh + i] = f2bf(fmaxf(acc0[v] + bias0, 0.f));
+            y[static_cast<size_t>(po) * kCh + i + 16] = f2bf(fmaxf(acc1[v] + bias1, 0.f));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ conv, 32 -> 32, tiled
+// A workgroup computes a 16 x 16-pixel output tile of one image for all 32
+// output channels.  The input patch ((16 + 2d)^2 pixels x 32 channels, zeros
+// outside the image) and the weights are staged in LDS once; pixel rows are
+// padded to kCP channels and weight rows to kWS entries so that the fragment
+// reads of a wavefront spread over the LDS banks.  Wavefront w computes tile
+// rows 4w .. 4w+3 (4 M-tiles of 16 pixels) x 32 channels (2 N-tiles).
+// EPI 0: y = bf16(relu(acc + bias)).  EPI 1: y = bf16(acc * (ymask > 0)) (back-
+// propagation through the ReLU of the layer input, with flipped taps).
+constexpr int kTile = 16;
+constexpr int kCP = 36;            // staged channels per pixel (32 + pad)
+constexpr int kWS = 9 * kCh + 4;   // staged weight row (one output channel: 9 taps x 32 inputs + pad)
+constexpr int kMaxDilT = 4;        // largest dilation the tiled kernel stages (patch (16 + 2*4)^2)
+constexpr int kWStage = (kCh * 36 + kThreads - 1) / kThreads;
+constexpr int kXStage = ((kTile + 2 * kMaxDilT) * (kTile + 2 * kMaxDilT) * 4 + kThreads - 1) / kThreads;
+
+__host__ __device__ inline int conv_tiles(int H, int W) { return ((H + kTile - 1) / kTile) * ((W + kTile - 1) / kTile); }
+__host__ __device__ inline size_t conv_tiled_lds(int d) {
+    const int P = kTile + 2 * d;
+    return sizeof(bf16_t) * (static_cast<size_t>(kCh) * kWS + static_cast<size_t>(P) * P * kCP);
+}
+
+template <int EPI>
+__global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__ x, const bf16_t *__restrict__ Wg,
+                                                      const float *__restrict__ bias,
+                                                      const bf16_t *__restrict__ ymask, bf16_t *__restrict__ y,
+                                                      int H, int W, int d) {
+    extern __shared__ __align__(16) unsigned char sm[];
+    bf16_t *Ws = reinterpret_cast<bf16_t *>(sm);  // [32][kWS]
+    bf16_t *Xs = Ws + kCh * kWS;                  // [P*P][kCP]
+    const int P = kTile + 2 * d;
+    const int tw = (W + kTile - 1) / kTile, tpi = conv_tiles(H, W);
+    const int b = blockIdx.x / tpi, t = blockIdx.x - b * tpi;
+    const int ty = t / tw, tx = t - ty * tw;
+    const int y0 = ty * kTile, x0 = tx * kTile;
+    // staging, 16 bytes (8 channels) per load, every load issued before the
+    // first LDS store: the weights (32 rows of 288 entries), then the input
+    // patch (a pixel outside the image reads the tile's first in-image pixel
+    // and stores zeros)
+    const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
+    uint4 wv[kWStage];
+#pragma unroll
+    for (int u = 0; u < kWStage; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        wv[u] = reinterpret_cast<const uint4 *>(Wg)[e < kCh * 36 ? e : 0];
+    }
+    const bf16_t *xb = x + static_cast<size_t>(b) * H * W * kCh;
+    const uint4 *x00 = reinterpret_cast<const uint4 *>(xb + (static_cast<size_t>(y0) * W + x0) * kCh);
+    uint4 xv[kXStage];
+    bool in[kXStage];
+#pragma unroll
+    for (int u = 0; u < kXStage; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        const int pix = e >> 2, q = e & 3;
+        const int py = pix / P, px = pix - py * P;
+        const int gy = y0 - d + py, gx = x0 - d + px;
+        in[u] = e < P * P * 4 && gy >= 0 && gy < H && gx >= 0 && gx < W;
+        const uint4 *src = in[u] ? reinterpret_cast<const uint4 *>(xb + (static_cast<size_t>(gy) * W + gx) * kCh) + q
+                                 : x00;
+        xv[u] = *src;
+    }
+#pragma unroll
+    for (int u = 0; u < kWStage; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        if (e < kCh * 36) {
+            const int n = e / 36, q = e - n * 36;
+            uint2 *dst = reinterpret_cast<uint2 *>(Ws + n * kWS + q * 8);
+            dst[0] = make_uint2(wv[u].x, wv[u].y);
+            dst[1] = make_uint2(wv[u].z, wv[u].w);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kXStage; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        if (e < P * P * 4) {
+            const uint4 v = in[u] ? xv[u] : z4;
+            uint2 *dst = reinterpret_cast<uint2 *>(Xs + (e >> 2) * kCP + (e & 3) * 8);
+            dst[0] = make_uint2(v.x, v.y);
+            dst[1] = make_uint2(v.z, v.w);
+        }
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    v4f32 acc[4][2];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc[mt][0] = acc[mt][1] = v4f32{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        const int oy = d + d * (tap / 3 - 1), ox = d + d * (tap % 3 - 1);
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[i * kWS + tap * kCh + cc * 16 + g * 4]);
+            const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[(i + 16) * kWS + tap * kCh + cc * 16 + g * 4]);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const int r = wave * 4 + mt;
+                const v4i16 a =
+                    *reinterpret_cast<const v4i16 *>(&Xs[((r + oy) * P + i + ox) * kCP + cc * 16 + g * 4]);
+                acc[mt][0] = mfma(a, b0, acc[mt][0]);
+                acc[mt][1] = mfma(a, b1, acc[mt][1]);
+            }
+        }
+    }
+    const float bias0 = EPI == 0 ? bias[i] : 0.f, bias1 = EPI == 0 ? bias[i + 16] : 0.f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const int gy = y0 + wave * 4 + mt;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int gx = x0 + 4 * g + v;
+            if (gy >= H || gx >= W) continue;
+            const size_t po = (static_cast<size_t>(b) * H + gy) * W + gx;
+            float z0 = acc[mt][0][v], z1 = acc[mt][1][v];
             if constexpr (EPI == 0) {
                 z0 = fmaxf(z0 + bias0, 0.f);
                 z1 = fmaxf(z1 + bias1, 0.f);
             } else {
-                z0 = bf_pos(ym0[v]) ? z0 : 0.f;
-                z1 = bf_pos(ym1[v]) ? z1 : 0.f;
+                z0 = bf_pos(ymask[po * kCh + i]) ? z0 : 0.f;
+                z1 = bf_pos(ymask[po * kCh + i + 16]) ? z1 : 0.f;
             }
-            y[static_cast<size_t>(po) * kCh + i] = f2bf(z0);
-            y[static_cast<size_t>(po) * kCh + i + 16] = f2bf(z1);
+            y[po * kCh + i] = f2bf(z0);
+            y[po * kCh + i + 16] = f2bf(z1);
         }
     }
 }
@@ -612,14 +697,26 @@ void convert(adrnn_ctx *c) {
 
 int conv_grid(int NP) { return std::min(4096, std::max(1, (NP + 16 * 4 * 8 - 1) / (16 * 4 * 8))); }
 
+// 32 -> 32 convolution of B images (tiled kernel)
+template <int EPI>
+void conv32t(adrnn_ctx *c, int B, const bf16_t *x, const bf16_t *w, const float *bias, const bf16_t *ymask, bf16_t *y,
+             int d) {
+    if (d < 1 || d > kMaxDilT) throw NNError{ADR_EINVAL, "tiled convolution: dilation out of range"};
+    const size_t lds = conv_tiled_lds(d);
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv32t<EPI>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    hipLaunchKernelGGL((k_conv32t<EPI>), dim3(B * conv_tiles(c->H, c->W)), dim3(kThreads), lds, c->st, x, w, bias,
+                       ymask, y, c->H, c->W, d);
+    NNCHK(hipGetLastError());
+}
+
 void forward(adrnn_ctx *c, int B, const bf16_t *x0, float *out) {
     const int NP = B * c->H * c->W, gridc = conv_grid(NP);
-    hipLaunchKernelGGL((k_conv32<4, 0>), dim3(gridc), dim3(kThreads), 0, c->st, x0, c->w1, c->P + ob1, nullptr, c->y1,
-                       NP, c->H, c->W, kDil[0]);
-    hipLaunchKernelGGL((k_conv32<32, 0>), dim3(gridc), dim3(kThreads), 0, c->st, c->y1, c->w2, c->P + ob2, nullptr,
-                       c->y2, NP, c->H, c->W, kDil[1]);
-    hipLaunchKernelGGL((k_conv32<32, 0>), dim3(gridc), dim3(kThreads), 0, c->st, c->y2, c->w3, c->P + ob3, nullptr,
-                       c->y3, NP, c->H, c->W, kDil[2]);
+    hipLaunchKernelGGL(k_conv_in, dim3(gridc), dim3(kThreads), 0, c->st, x0, c->w1, c->P + ob1, c->y1, NP, c->H,
+                       c->W, kDil[0]);
+    conv32t<0>(c, B, c->y1, c->w2, c->P + ob2, nullptr, c->y2, kDil[1]);
+    conv32t<0>(c, B, c->y2, c->w3, c->P + ob3, nullptr, c->y3, kDil[2]);
     NNCHK(hipGetLastError());
     hipLaunchKernelGGL(k_last_fwd, dim3((NP + 255) / 256), dim3(256), 0, c->st, c->y3, c->w4, c->P + ob4, out, NP,
                        c->H, c->W, kDil[3]);
@@ -642,7 +739,7 @@ void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, int d, float 
 }
 
 double grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint8_t *mask, float *G) {
-    const int HW = c->H * c->W, NP = B * HW, gridc = conv_grid(NP);
+    const int HW = c->H * c->W, NP = B * HW;
     forward(c, B, x0, c->out);
     // interior pixel count (mask shared by the images)
     std::vector<uint8_t> hm(HW);
@@ -664,12 +761,10 @@ double grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint
     // layer 3: g3 = ga
     wgrad<32>(c, c->ga, c->y2, NP, kDil[2], G + oW3);  // writes W3 then b3 (contiguous in the layout)
     // the transposed convolution is the convolution with flipped taps at the same dilation
-    hipLaunchKernelGGL((k_conv32<32, 1>), dim3(gridc), dim3(kThreads), 0, c->st, c->ga, c->w3t, nullptr, c->y2, c->gb,
-                       NP, c->H, c->W, kDil[2]);
+    conv32t<1>(c, B, c->ga, c->w3t, nullptr, c->y2, c->gb, kDil[2]);
     // layer 2: g2 = gb
     wgrad<32>(c, c->gb, c->y1, NP, kDil[1], G + oW2);
-    hipLaunchKernelGGL((k_conv32<32, 1>), dim3(gridc), dim3(kThreads), 0, c->st, c->gb, c->w2t, nullptr, c->y1, c->ga,
-                       NP, c->H, c->W, kDil[1]);
+    conv32t<1>(c, B, c->gb, c->w2t, nullptr, c->y1, c->ga, kDil[1]);
     // layer 1: g1 = ga
     wgrad<4>(c, c->ga, x0, NP, kDil[0], G + oW1);
     NNCHK(hipGetLastError());
