@@ -28,10 +28,7 @@ constexpr int kSlotStep = 0, kSlotLin = 1, kSlotTime = 2, kSlotGuess = 3, kSlots
 constexpr int kBlock = 256;
 constexpr int kTile = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
-// line-length buckets (nodes per line): each bucket is one launch with its own LDS size
-// one launch per family: all curves, ordered longest first
-constexpr int kBucketEdges[] = {3072};
-constexpr int kBuckets = 1;
+// one line-solve launch per family: all curves of all instances, longest first
 constexpr int kMaxNodes = 3072;  // 12 nodes per thread of a 256-thread workgroup
 
 #define HIPCHK(x)                                                                              \
@@ -63,14 +60,10 @@ std::vector<T> to_type(const std::vector<double> &v) {
     return std::vector<T>(v.begin(), v.end());
 }
 
-struct Bucket {
-    int first, count, nmax;
-};
-
 struct DevFam {
     int n_lines = 0;
+    int nmax = 0;  // nodes of the longest curve (sizes the launch's LDS)
     int64_t n_nodes = 0, n_unknowns = 0;
-    Bucket bk[kBuckets];
     adr::LineArgs<double> a64{};
     adr::LineArgs<float> a32{};
     adr::ScatterArgs<double> s64{};
@@ -152,23 +145,15 @@ struct adr_ctx {
 
     void line64(int f, int slot, const double *fin, const int *dn) {
         DevFam &F = fam[f];
-        for (int b = 0; b < kBuckets; ++b) {
-            const Bucket &k = F.bk[b];
-            if (k.count == 0) continue;
-            adr::LineArgs<double> a = F.a64;
-            a.loff += k.first; a.lcnt += k.first; a.linst += k.first;
-            timed(0, f, [&] { return adr::launch_line<double>(f, a, k.count, fin, F.v64, par_ptr(slot, f), dn, k.nmax, st); });
-        }
+        timed(0, f, [&] {
+            return adr::launch_line<double>(f, F.a64, F.n_lines, fin, F.v64, par_ptr(slot, f), dn, F.nmax, st);
+        });
     }
     void line32(int f, int slot, const float *fin, const int *dn) {
         DevFam &F = fam[f];
-        for (int b = 0; b < kBuckets; ++b) {
-            const Bucket &k = F.bk[b];
-            if (k.count == 0) continue;
-            adr::LineArgs<float> a = F.a32;
-            a.loff += k.first; a.lcnt += k.first; a.linst += k.first;
-            timed(1, f, [&] { return adr::launch_line<float>(f, a, k.count, fin, F.v32, par_ptr(slot, f), dn, k.nmax, st); });
-        }
+        timed(1, f, [&] {
+            return adr::launch_line<float>(f, F.a32, F.n_lines, fin, F.v32, par_ptr(slot, f), dn, F.nmax, st);
+        });
     }
 
     // One FP64 sweep of eq. (10) from U.  mode of the final scatter: 0 write U,
@@ -398,35 +383,26 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     throw Error{ADR_EINVAL, "a curve has " + std::to_string(cnt) + " nodes; the line solver holds " +
                                                 std::to_string(kMaxNodes)};
             }
-            // bucket lines by node count (stable within a bucket)
+            // workgroup order: longest curve first (stable), so that no long curve
+            // is left for the end of the launch
             std::stable_sort(lines.begin(), lines.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
                 const adr::Family &fx = G[x.first].fam[f], &fy = G[y.first].fam[f];
                 return fx.off[x.second + 1] - fx.off[x.second] > fy.off[y.second + 1] - fy.off[y.second];
             });
             std::vector<int> loff, lcnt, linst;
             loff.reserve(lines.size());
-            int first = 0;
-            for (int b = 0; b < kBuckets; ++b) {
-                const int lo = b == 0 ? 0 : kBucketEdges[b - 1];
-                const int hi = kBucketEdges[b];
-                int nmax = 0, count = 0;
-                for (auto &li : lines) {
-                    const adr::Family &fa = G[li.first].fam[f];
-                    const int cnt = static_cast<int>(fa.off[li.second + 1] - fa.off[li.second]);
-                    if (cnt <= lo || cnt > hi) continue;
-                    loff.push_back(static_cast<int>(noff[li.first] + fa.off[li.second]));
-                    lcnt.push_back(cnt);
-                    linst.push_back(li.first);
-                    nmax = std::max(nmax, cnt);
-                    ++count;
-                    F.n_unknowns += cnt - 2;
-                }
-                F.bk[b] = Bucket{first, count, nmax};
-                first += count;
-                if (count && (nmax > kMaxNodes || adr::line_lds_bytes<double>(f, nmax) > kLdsLimit))
-                    throw Error{ADR_EINVAL, "a curve has " + std::to_string(nmax) +
-                                                " nodes: longer than the LDS-resident line solver holds"};
+            for (auto &li : lines) {
+                const adr::Family &fa = G[li.first].fam[f];
+                const int cnt = static_cast<int>(fa.off[li.second + 1] - fa.off[li.second]);
+                loff.push_back(static_cast<int>(noff[li.first] + fa.off[li.second]));
+                lcnt.push_back(cnt);
+                linst.push_back(li.first);
+                F.nmax = std::max(F.nmax, cnt);
+                F.n_unknowns += cnt - 2;
             }
+            if (F.nmax > kMaxNodes || adr::line_lds_bytes<double>(f, F.nmax) > kLdsLimit)
+                throw Error{ADR_EINVAL, "a curve has " + std::to_string(F.nmax) +
+                                            " nodes: longer than the LDS-resident line solver holds"};
             // per node data
             std::vector<int> cell(F.n_nodes, -1);
             std::vector<double> lx(F.n_nodes), ly(F.n_nodes), h(F.n_nodes), w, L;
@@ -648,10 +624,8 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
             HIPCHK(hipStreamSynchronize(st));
             return std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; });
         };
-        int executed = 0;
         if (max_iters > 0) {
             ctx->block(u, 0, tol);  // first FP64 sweep
-            executed = 1;
             const int blocks = (max_iters - 1) / period;
             const int check = std::max(1, 8 / period);
             if (use_graph && blocks > 0 && (ctx->g_u != u || ctx->g_tol != tol || ctx->g_m != m || !ctx->gexec)) {
@@ -667,7 +641,6 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
             for (int b = 0; b < blocks; ++b) {
                 if (use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, st));
                 else ctx->block(u, m, tol);
-                executed += period;
                 if ((b + 1) % check == 0 && all_done()) break;
             }
         }

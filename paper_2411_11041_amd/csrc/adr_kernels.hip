@@ -388,7 +388,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
         red[threadIdx.x] = r * r;
         __syncthreads();
         for (int w = kThreads / 2; w > 0; w >>= 1) {
-            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
             __syncthreads();
         }
         if (threadIdx.x == 0) partial[blk] = red[0];
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void k_norm(const double *__restrict__ pa
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x != 0) return;

@@ -446,7 +446,7 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
     red[threadIdx.x] = e2;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(kThreads) void k_norms(const double *__restrict__ f
     rs[threadIdx.x] = ms;
     __syncthreads();
     for (int w = kThreads / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
+        if (static_cast<int>(threadIdx.x) < w) {
             rf[threadIdx.x] = fmax(rf[threadIdx.x], rf[threadIdx.x + w]);
             rs[threadIdx.x] = fmax(rs[threadIdx.x], rs[threadIdx.x + w]);
         }
