@@ -78,11 +78,13 @@ struct adr_ctx {
     int n_inst = 0;
     std::vector<int64_t> goff;
     int64_t n_grid = 0, n_unknowns = 0;
+    int64_t n_blocked = 0;  // size of the blocked (8 x 4) FP32 increment fields
     adr_options opt{};
     hipStream_t st = nullptr;
     std::vector<void *> owned;
     DevFam fam[2];
-    int *blk_start = nullptr, *inst_nx = nullptr;
+    int *blk_start = nullptr, *inst_nx = nullptr, *inst_bstride = nullptr;
+    int4 *inst_blk = nullptr;
     int n_blocks = 0;
     double *par = nullptr;  // [slot][fam][inst][8]
     std::vector<double> par_h;
@@ -327,9 +329,24 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         }
         C->n_grid = C->goff[n];
         if (C->n_grid > (int64_t(1) << 31) - 1) throw Error{ADR_EINVAL, "packed grid exceeds 2^31 nodes"};
+        // blocked layout of the FP32 increment fields: 8 x 4-node blocks per instance
+        std::vector<int64_t> boff(n + 1, 0);
+        std::vector<int> inst_bstride(n);
+        std::vector<int4> inst_blk(n);
+        for (int i = 0; i < n; ++i) {
+            const int nx8 = (G[i].g.nx + 7) / 8, ny4 = (G[i].g.ny + 3) / 4;
+            boff[i + 1] = boff[i] + int64_t(32) * nx8 * ny4;
+            inst_bstride[i] = 32 * nx8;
+        }
+        C->n_blocked = boff[n];
+        if (C->n_blocked > (int64_t(1) << 31) - 1) throw Error{ADR_EINVAL, "packed grid exceeds 2^31 nodes"};
+        for (int i = 0; i < n; ++i)
+            inst_blk[i] = make_int4(static_cast<int>(C->goff[i]), G[i].g.nx, static_cast<int>(boff[i]), inst_bstride[i]);
         hipStream_t st = C->st;
         auto &own = C->owned;
         C->inst_nx = upload(inst_nx, own, st);
+        C->inst_bstride = upload(inst_bstride, own, st);
+        C->inst_blk = upload(inst_blk, own, st);
 
         // scatter slots, padded per instance to whole blocks
         std::vector<int> blk_start(n + 1, 0);
@@ -403,8 +420,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             if (F.nmax > kMaxNodes || adr::line_lds_bytes<double>(f, F.nmax) > kLdsLimit)
                 throw Error{ADR_EINVAL, "a curve has " + std::to_string(F.nmax) +
                                             " nodes: longer than the LDS-resident line solver holds"};
-            // per node data
-            std::vector<int> cell(F.n_nodes, -1);
+            // per node data (cellb: the corner in the blocked FP32 fields)
+            std::vector<int> cell(F.n_nodes, -1), cellb(F.n_nodes, -1);
             std::vector<double> lx(F.n_nodes), ly(F.n_nodes), h(F.n_nodes), w, L;
             if (f == 0) { w.resize(F.n_nodes); L.resize(F.n_nodes); }
             for (int i = 0; i < n; ++i) {
@@ -413,6 +430,10 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     const int64_t gk = noff[i] + static_cast<int64_t>(k);
                     const int c = G[i].cellk[f][k];
                     cell[gk] = c < 0 ? -1 : static_cast<int>(C->goff[i] + c);
+                    if (c >= 0) {
+                        const int nx = G[i].g.nx;
+                        cellb[gk] = adr::blocked_index(c % nx, c / nx, static_cast<int>(boff[i]), inst_bstride[i]);
+                    }
                     lx[gk] = G[i].lxk[f][k];
                     ly[gk] = G[i].lyk[f][k];
                     h[gk] = G[i].hk[f][k];
@@ -428,7 +449,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             F.a64 = adr::LineArgs<double>{d_loff, d_lcnt, d_linst, C->inst_nx, d_cell,
                                           upload(lx, own, st), upload(ly, own, st), upload(h, own, st),
                                           f == 0 ? upload(w, own, st) : nullptr, dL64};
-            F.a32 = adr::LineArgs<float>{d_loff, d_lcnt, d_linst, C->inst_nx, d_cell,
+            F.a32 = adr::LineArgs<float>{d_loff, d_lcnt, d_linst, C->inst_bstride, upload(cellb, own, st),
                                          upload(to_type<float>(lx), own, st), upload(to_type<float>(ly), own, st),
                                          upload(to_type<float>(h), own, st),
                                          f == 0 ? upload(to_type<float>(w), own, st) : nullptr, dL32};
@@ -454,8 +475,9 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                         (static_cast<unsigned>(__builtin_bit_cast(unsigned short, b16)) << 16);
             }
             F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, upload(ra, own, st), upload(rb, own, st),
-                                             nullptr, npad};
-            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, nullptr, nullptr, upload(rw, own, st), npad};
+                                             nullptr, C->inst_blk, npad};
+            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, nullptr, nullptr, upload(rw, own, st),
+                                            C->inst_blk, npad};
             F.v64 = dalloc<double>(F.n_nodes, own);
             F.v32 = dalloc<float>(F.n_nodes, own);
             for (int i = 0; i < n; ++i) C->geo[f].push_back(G[i].fam[f]);
@@ -471,12 +493,12 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         // state scratch (zeroed: non-interior nodes must read as zero)
         C->Uh64 = dalloc<double>(C->n_grid, own);
         C->Z64 = dalloc<double>(C->n_grid, own);
-        C->d32 = dalloc<float>(C->n_grid, own);
-        C->D32 = dalloc<float>(C->n_grid, own);
+        C->d32 = dalloc<float>(C->n_blocked, own);
+        C->D32 = dalloc<float>(C->n_blocked, own);
         HIPCHK(hipMemsetAsync(C->Uh64, 0, sizeof(double) * C->n_grid, st));
         HIPCHK(hipMemsetAsync(C->Z64, 0, sizeof(double) * C->n_grid, st));
-        HIPCHK(hipMemsetAsync(C->d32, 0, sizeof(float) * C->n_grid, st));
-        HIPCHK(hipMemsetAsync(C->D32, 0, sizeof(float) * C->n_grid, st));
+        HIPCHK(hipMemsetAsync(C->d32, 0, sizeof(float) * C->n_blocked, st));
+        HIPCHK(hipMemsetAsync(C->D32, 0, sizeof(float) * C->n_blocked, st));
         C->partial = dalloc<double>(std::max(nblk, 1), own);
         C->cnorm = dalloc<double>(n, own);
         C->rel = dalloc<double>(n, own);

@@ -11,8 +11,9 @@ struct LineArgs {
     const int *loff;     // first node of line
     const int *lcnt;     // nodes of line (including the two Dirichlet ends)
     const int *linst;    // instance of line
-    const int *inst_nx;  // grid width per instance
-    const int *cell;     // per node: global index of the bottom-left cell corner (-1 at ends)
+    const int *inst_nx;  // grid width per instance (FP32 tables: the blocked row stride, 32 ceil(nx / 8))
+    const int *cell;     // per node: global index of the bottom-left cell corner (-1 at ends); row-major
+                         // in the FP64 tables, blocked (8 x 4) in the FP32 tables
     const T *lx, *ly;    // per node: offsets in the cell (eq. (23))
     const T *h;          // per node: chord to the previous node
     const T *w;          // per node: |beta| (beta family only)
@@ -27,8 +28,17 @@ struct ScatterArgs {
     const int *rk;        // [4][npad] first node of the record's segment, -1 unused
     const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1] (FP64 tables)
     const unsigned *rw;   // [4][npad] the same weights as two FP16 halves (low: v[k]); FP32 tables
+    const int4 *inst_blk; // per instance {row-major offset, nx, blocked offset, blocked row stride}
     int npad;
 };
+
+// The FP32 increment fields are stored in blocks of 8 x 4 nodes (one 128-byte
+// line): node (x, y) of an instance sits at
+//   boff + ((y / 4) * (nx8) + x / 8) * 32 + (y % 4) * 8 + x % 8,   nx8 = ceil(nx / 8),
+// with boff a multiple of 32; the row-major index g of the node maps there.
+__host__ __device__ inline int blocked_index(int x, int y, int boff, int bstride) {
+    return boff + (y >> 2) * bstride + ((x >> 3) << 5) + ((y & 3) << 3) + (x & 7);
+}
 
 // dynamic LDS of the line solve of family fam (0 beta, 1 gamma) whose longest curve has nmax nodes
 template <typename T>

@@ -109,10 +109,21 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
 #pragma unroll
         for (int t = 0; t < G; ++t) {
             const int c = cj[q0 + t] >= 0 ? cj[q0 + t] : 0;
-            p11[t] = fin[c];
-            p12[t] = fin[c + 1];
-            p21[t] = fin[c + nx];
-            p22[t] = fin[c + nx + 1];
+            if constexpr (sizeof(T) == 4) {
+                // blocked field (8 x 4 nodes per block): the corner's position in
+                // its block is in the low bits of c; nx is the block-row stride
+                const int sx = (c & 7) == 7 ? 25 : 1;
+                const int cu = c + (((c >> 3) & 3) == 3 ? nx - 24 : 8);
+                p11[t] = fin[c];
+                p12[t] = fin[c + sx];
+                p21[t] = fin[cu];
+                p22[t] = fin[cu + sx];
+            } else {
+                p11[t] = fin[c];
+                p12[t] = fin[c + 1];
+                p21[t] = fin[c + nx];
+                p22[t] = fin[c + nx + 1];
+            }
         }
 #pragma unroll
         for (int t = 0; t < G; ++t) {
@@ -334,6 +345,13 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
     const int slot = blk * kThreads + threadIdx.x;
     const int g = s.gidx[slot];
     const int np = s.npad;
+    // index of the node in the blocked FP32 fields (d32; out when it is FP32)
+    int gb = 0;
+    if constexpr (MODE == 1 || MODE == 2 || sizeof(TO) == 4) {
+        const int4 ib = s.inst_blk[inst];
+        const int gl = (g >= 0 ? g : ib.x) - ib.x, y = gl / ib.y, x = gl - y * ib.y;
+        gb = blocked_index(x, y, ib.z, ib.w);
+    }
     // every load is issued before any is used (no branch between them): the
     // records, then the line values (a missing record reads v[0], v[1] with
     // its contribution dropped), and the old grid value, which depends only
@@ -368,11 +386,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
     for (int r = 0; r < 4; ++r)
         if (kk[r] >= 0) val += wa[r] * va[r] + wb[r] * vb[r];
     if constexpr (MODE == 0) {
-        if (g >= 0) out[g] = TO(val);
+        if (g >= 0) out[sizeof(TO) == 4 ? gb : g] = TO(val);
     } else if constexpr (MODE == 2) {
         if (g >= 0) {
             out[g] = old + TO(val);
-            d32[g] = float(val);
+            d32[gb] = float(val);
         }
     } else {
         double r = 0.0;
@@ -380,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
             r = double(val) - double(old);
             if constexpr (MODE == 1) {
                 out[g] = TO(val);
-                d32[g] = float(r);
+                d32[gb] = float(r);
             }
         }
         // fixed-order block reduction of r^2
