@@ -101,7 +101,11 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                      adr_ctx **out);
 
 /* Packed layout of u over the instances: instance i occupies
- * offsets[i] .. offsets[i+1]-1 (offsets has n_probs+1 entries, host). */
+ * offsets[i] .. offsets[i+1]-1 (offsets has n_probs+1 entries, host), row-major
+ * (node (x, y) at offsets[i] + y nx + x).  The calls below read and write the
+ * interior nodes of u only (nodes strictly inside the domain); the others are
+ * the zero Dirichlet data: they are read as 0 and left unchanged.  Inside a
+ * call the library keeps its own copy of the state in a blocked layout. */
 adr_status adr_layout(const adr_ctx *ctx, int64_t *offsets);
 
 /* Counts (host out, each may be NULL): interior grid nodes, beta-lines,

@@ -83,8 +83,10 @@ struct adr_ctx {
     hipStream_t st = nullptr;
     std::vector<void *> owned;
     DevFam fam[2];
-    int *blk_start = nullptr, *inst_nx = nullptr, *inst_bstride = nullptr;
-    int4 *inst_blk = nullptr;
+    int *blk_start = nullptr, *inst_bstride = nullptr;
+    int *slot_rm = nullptr, *slot_b = nullptr;  // interior node of each scatter slot: row-major / blocked
+    int npad = 0;
+    double *Ub = nullptr;  // the state in the blocked layout during a call
     int n_blocks = 0;
     double *par = nullptr;  // [slot][fam][inst][8]
     std::vector<double> par_h;
@@ -178,6 +180,10 @@ struct adr_ctx {
             return adr::launch_norm(n_inst, partial, blk_start, cnorm, rel, done, conv_it, count, tol, mode, st);
         });
     }
+
+    // the caller's row-major state in and out of the blocked state Ub (interior nodes)
+    void to_blocked(const double *u) { HIPCHK(adr::launch_layout(slot_rm, slot_b, npad, u, Ub, true, st)); }
+    void from_blocked(double *u) { HIPCHK(adr::launch_layout(slot_rm, slot_b, npad, Ub, u, false, st)); }
 
     // one block of the stationary iteration: FP32 increment sweeps, then an FP64
     // sweep with the update norm (the first block has no FP32 sweeps)
@@ -319,20 +325,17 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
 
         // packing
         C->goff.assign(n + 1, 0);
-        std::vector<int> inst_nx(n);
         std::vector<double> mu(n), sg(n);
         for (int i = 0; i < n; ++i) {
             C->goff[i + 1] = C->goff[i] + static_cast<int64_t>(G[i].g.nx) * G[i].g.ny;
-            inst_nx[i] = G[i].g.nx;
             mu[i] = G[i].mu;
             sg[i] = G[i].sigma;
         }
         C->n_grid = C->goff[n];
         if (C->n_grid > (int64_t(1) << 31) - 1) throw Error{ADR_EINVAL, "packed grid exceeds 2^31 nodes"};
-        // blocked layout of the FP32 increment fields: 8 x 4-node blocks per instance
+        // blocked layout of the sweep fields: 8 x 4-node blocks per instance
         std::vector<int64_t> boff(n + 1, 0);
         std::vector<int> inst_bstride(n);
-        std::vector<int4> inst_blk(n);
         for (int i = 0; i < n; ++i) {
             const int nx8 = (G[i].g.nx + 7) / 8, ny4 = (G[i].g.ny + 3) / 4;
             boff[i + 1] = boff[i] + int64_t(32) * nx8 * ny4;
@@ -340,13 +343,9 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         }
         C->n_blocked = boff[n];
         if (C->n_blocked > (int64_t(1) << 31) - 1) throw Error{ADR_EINVAL, "packed grid exceeds 2^31 nodes"};
-        for (int i = 0; i < n; ++i)
-            inst_blk[i] = make_int4(static_cast<int>(C->goff[i]), G[i].g.nx, static_cast<int>(boff[i]), inst_bstride[i]);
         hipStream_t st = C->st;
         auto &own = C->owned;
-        C->inst_nx = upload(inst_nx, own, st);
         C->inst_bstride = upload(inst_bstride, own, st);
-        C->inst_blk = upload(inst_blk, own, st);
 
         // scatter slots, padded per instance to whole blocks
         std::vector<int> blk_start(n + 1, 0);
@@ -370,14 +369,22 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             };
             std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return key(a) < key(b); });
         }
-        std::vector<int> gidx(npad, -1), blk_inst(nblk);
+        std::vector<int> gidx(npad, -1), gidx_b(npad, -1), blk_inst(nblk);
         for (int i = 0; i < n; ++i) {
+            const int nxi = G[i].g.nx;
             for (int b = blk_start[i]; b < blk_start[i + 1]; ++b) blk_inst[b] = i;
-            for (size_t s = 0; s < order[i].size(); ++s)
-                gidx[blk_start[i] * kBlock + s] = static_cast<int>(C->goff[i] + G[i].inner_list[order[i][s]]);
+            for (size_t s = 0; s < order[i].size(); ++s) {
+                const int g = G[i].inner_list[order[i][s]];
+                gidx[blk_start[i] * kBlock + s] = static_cast<int>(C->goff[i] + g);
+                gidx_b[blk_start[i] * kBlock + s] =
+                    adr::blocked_index(g % nxi, g / nxi, static_cast<int>(boff[i]), inst_bstride[i]);
+            }
             C->n_unknowns += static_cast<int64_t>(G[i].inner_list.size());
         }
-        int *d_gidx = upload(gidx, own, st);
+        C->slot_rm = upload(gidx, own, st);
+        int *d_gidx = upload(gidx_b, own, st);
+        C->slot_b = d_gidx;
+        C->npad = npad;
         int *d_blk_inst = upload(blk_inst, own, st);
         C->blk_start = upload(blk_start, own, st);
 
@@ -420,8 +427,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             if (F.nmax > kMaxNodes || adr::line_lds_bytes<double>(f, F.nmax) > kLdsLimit)
                 throw Error{ADR_EINVAL, "a curve has " + std::to_string(F.nmax) +
                                             " nodes: longer than the LDS-resident line solver holds"};
-            // per node data (cellb: the corner in the blocked FP32 fields)
-            std::vector<int> cell(F.n_nodes, -1), cellb(F.n_nodes, -1);
+            // per node data (cellb: the cell's corner in the blocked fields)
+            std::vector<int> cellb(F.n_nodes, -1);
             std::vector<double> lx(F.n_nodes), ly(F.n_nodes), h(F.n_nodes), w, L;
             if (f == 0) { w.resize(F.n_nodes); L.resize(F.n_nodes); }
             for (int i = 0; i < n; ++i) {
@@ -429,7 +436,6 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 for (size_t k = 0; k < fa.x.size(); ++k) {
                     const int64_t gk = noff[i] + static_cast<int64_t>(k);
                     const int c = G[i].cellk[f][k];
-                    cell[gk] = c < 0 ? -1 : static_cast<int>(C->goff[i] + c);
                     if (c >= 0) {
                         const int nx = G[i].g.nx;
                         cellb[gk] = adr::blocked_index(c % nx, c / nx, static_cast<int>(boff[i]), inst_bstride[i]);
@@ -442,14 +448,14 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             }
             if (f == 0) C->noffB = noff;
             const int *d_loff = upload(loff, own, st), *d_lcnt = upload(lcnt, own, st);
-            const int *d_linst = upload(linst, own, st), *d_cell = upload(cell, own, st);
+            const int *d_linst = upload(linst, own, st), *d_cellb = upload(cellb, own, st);
             double *dL64 = f == 0 ? upload(L, own, st) : nullptr;
             float *dL32 = f == 0 ? upload(to_type<float>(L), own, st) : nullptr;
             if (f == 0) { C->L64 = dL64; C->L32 = dL32; }
-            F.a64 = adr::LineArgs<double>{d_loff, d_lcnt, d_linst, C->inst_nx, d_cell,
+            F.a64 = adr::LineArgs<double>{d_loff, d_lcnt, d_linst, C->inst_bstride, d_cellb,
                                           upload(lx, own, st), upload(ly, own, st), upload(h, own, st),
                                           f == 0 ? upload(w, own, st) : nullptr, dL64};
-            F.a32 = adr::LineArgs<float>{d_loff, d_lcnt, d_linst, C->inst_bstride, upload(cellb, own, st),
+            F.a32 = adr::LineArgs<float>{d_loff, d_lcnt, d_linst, C->inst_bstride, d_cellb,
                                          upload(to_type<float>(lx), own, st), upload(to_type<float>(ly), own, st),
                                          upload(to_type<float>(h), own, st),
                                          f == 0 ? upload(to_type<float>(w), own, st) : nullptr, dL32};
@@ -475,9 +481,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                         (static_cast<unsigned>(__builtin_bit_cast(unsigned short, b16)) << 16);
             }
             F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, upload(ra, own, st), upload(rb, own, st),
-                                             nullptr, C->inst_blk, npad};
-            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, nullptr, nullptr, upload(rw, own, st),
-                                            C->inst_blk, npad};
+                                             nullptr, npad};
+            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, nullptr, nullptr, upload(rw, own, st), npad};
             F.v64 = dalloc<double>(F.n_nodes, own);
             F.v32 = dalloc<float>(F.n_nodes, own);
             for (int i = 0; i < n; ++i) C->geo[f].push_back(G[i].fam[f]);
@@ -491,12 +496,14 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             C->shape.push_back(sh);
         }
         // state scratch (zeroed: non-interior nodes must read as zero)
-        C->Uh64 = dalloc<double>(C->n_grid, own);
-        C->Z64 = dalloc<double>(C->n_grid, own);
+        C->Ub = dalloc<double>(C->n_blocked, own);
+        C->Uh64 = dalloc<double>(C->n_blocked, own);
+        C->Z64 = dalloc<double>(C->n_blocked, own);
         C->d32 = dalloc<float>(C->n_blocked, own);
         C->D32 = dalloc<float>(C->n_blocked, own);
-        HIPCHK(hipMemsetAsync(C->Uh64, 0, sizeof(double) * C->n_grid, st));
-        HIPCHK(hipMemsetAsync(C->Z64, 0, sizeof(double) * C->n_grid, st));
+        HIPCHK(hipMemsetAsync(C->Ub, 0, sizeof(double) * C->n_blocked, st));
+        HIPCHK(hipMemsetAsync(C->Uh64, 0, sizeof(double) * C->n_blocked, st));
+        HIPCHK(hipMemsetAsync(C->Z64, 0, sizeof(double) * C->n_blocked, st));
         HIPCHK(hipMemsetAsync(C->d32, 0, sizeof(float) * C->n_blocked, st));
         HIPCHK(hipMemsetAsync(C->D32, 0, sizeof(float) * C->n_blocked, st));
         C->partial = dalloc<double>(std::max(nblk, 1), own);
@@ -646,26 +653,29 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
             HIPCHK(hipStreamSynchronize(st));
             return std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; });
         };
+        double *const ub = ctx->Ub;
+        ctx->to_blocked(u);
         if (max_iters > 0) {
-            ctx->block(u, 0, tol);  // first FP64 sweep
+            ctx->block(ub, 0, tol);  // first FP64 sweep
             const int blocks = (max_iters - 1) / period;
             const int check = std::max(1, 8 / period);
-            if (use_graph && blocks > 0 && (ctx->g_u != u || ctx->g_tol != tol || ctx->g_m != m || !ctx->gexec)) {
+            if (use_graph && blocks > 0 && (ctx->g_u != ub || ctx->g_tol != tol || ctx->g_m != m || !ctx->gexec)) {
                 ctx->drop_graph();
                 HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                ctx->block(u, m, tol);
+                ctx->block(ub, m, tol);
                 HIPCHK(hipStreamEndCapture(st, &ctx->graph));
                 HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
-                ctx->g_u = u;
+                ctx->g_u = ub;
                 ctx->g_tol = tol;
                 ctx->g_m = m;
             }
             for (int b = 0; b < blocks; ++b) {
                 if (use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, st));
-                else ctx->block(u, m, tol);
+                else ctx->block(ub, m, tol);
                 if ((b + 1) % check == 0 && all_done()) break;
             }
         }
+        ctx->from_blocked(u);
         std::vector<int> ci(n, 0);
         std::vector<double> rr(n, 0.0);
         HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
@@ -746,7 +756,9 @@ adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32
             ctx->last_theta = theta;
             ctx->last_dt = dt;
         }
-        for (int s = 0; s < nsteps; ++s) ctx->sweep64(kSlotTime, u, u, 0, ctx->never);
+        ctx->to_blocked(u);
+        for (int s = 0; s < nsteps; ++s) ctx->sweep64(kSlotTime, ctx->Ub, ctx->Ub, 0, ctx->never);
+        ctx->from_blocked(u);
         return ADR_OK;
     } catch (const Error &e) {
         return fail_ctx(ctx, e);
@@ -760,7 +772,8 @@ adr_status adr_residual(adr_ctx *ctx, const double *u, double *rel_res) {
         return ADR_EINVAL;
     }
     try {
-        ctx->sweep64(kSlotStep, u, const_cast<double *>(u), 3, ctx->never);
+        ctx->to_blocked(u);
+        ctx->sweep64(kSlotStep, ctx->Ub, ctx->Ub, 3, ctx->never);
         ctx->norm(0, 0.0, 2);
         HIPCHK(hipMemcpyAsync(rel_res, ctx->rel, sizeof(double) * ctx->n_inst, hipMemcpyDeviceToHost, ctx->st));
         HIPCHK(hipStreamSynchronize(ctx->st));
@@ -784,9 +797,10 @@ adr_status adr_initial_guess(adr_ctx *ctx, double *u) {
     try {
         ctx->line64(0, kSlotGuess, ctx->Z64, ctx->never);
         ctx->timed(0, 2, [&] {
-            return adr::launch_scatter<double, double>(0, ctx->fam[0].s64, ctx->fam[0].v64, u, ctx->d32,
+            return adr::launch_scatter<double, double>(0, ctx->fam[0].s64, ctx->fam[0].v64, ctx->Ub, ctx->d32,
                                                        ctx->partial, ctx->never, ctx->st);
         });
+        ctx->from_blocked(u);
         return ADR_OK;
     } catch (const Error &e) {
         return fail_ctx(ctx, e);

@@ -11,9 +11,8 @@ struct LineArgs {
     const int *loff;     // first node of line
     const int *lcnt;     // nodes of line (including the two Dirichlet ends)
     const int *linst;    // instance of line
-    const int *inst_nx;  // grid width per instance (FP32 tables: the blocked row stride, 32 ceil(nx / 8))
-    const int *cell;     // per node: global index of the bottom-left cell corner (-1 at ends); row-major
-                         // in the FP64 tables, blocked (8 x 4) in the FP32 tables
+    const int *inst_nx;  // blocked row stride per instance, 32 ceil(nx / 8)
+    const int *cell;     // per node: blocked index of the bottom-left cell corner (-1 at ends)
     const T *lx, *ly;    // per node: offsets in the cell (eq. (23))
     const T *h;          // per node: chord to the previous node
     const T *w;          // per node: |beta| (beta family only)
@@ -23,19 +22,20 @@ struct LineArgs {
 // Scatter stencils of one family; slot s < npad (padded per instance to 256).
 template <typename T>
 struct ScatterArgs {
-    const int *gidx;      // global grid index of the interior node, -1 for padding
+    const int *gidx;      // blocked index of the interior node, -1 for padding
     const int *blk_inst;  // instance of each 256-slot block
     const int *rk;        // [4][npad] first node of the record's segment, -1 unused
     const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1] (FP64 tables)
     const unsigned *rw;   // [4][npad] the same weights as two FP16 halves (low: v[k]); FP32 tables
-    const int4 *inst_blk; // per instance {row-major offset, nx, blocked offset, blocked row stride}
     int npad;
 };
 
-// The FP32 increment fields are stored in blocks of 8 x 4 nodes (one 128-byte
-// line): node (x, y) of an instance sits at
-//   boff + ((y / 4) * (nx8) + x / 8) * 32 + (y % 4) * 8 + x % 8,   nx8 = ceil(nx / 8),
-// with boff a multiple of 32; the row-major index g of the node maps there.
+// The grid fields the sweeps use (state, half step, increments) are stored in
+// blocks of 8 x 4 nodes (one 128-byte line in FP32): node (x, y) of an
+// instance sits at
+//   boff + ((y / 4) * nx8 + x / 8) * 32 + (y % 4) * 8 + x % 8,   nx8 = ceil(nx / 8),
+// with boff a multiple of 32, so that the corner gathers of a curve touch few
+// cache lines whatever its direction.  The caller's arrays stay row-major.
 __host__ __device__ inline int blocked_index(int x, int y, int boff, int bstride) {
     return boff + (y >> 2) * bstride + ((x >> 3) << 5) + ((y & 3) << 3) + (x & 7);
 }
@@ -47,6 +47,11 @@ size_t line_lds_bytes(int fam, int nmax);
 template <typename T>
 hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
                        const int *done, int nmax, hipStream_t st);
+
+// interior nodes between the caller's row-major array and the blocked layout:
+// to_blocked: blk[gb[s]] = rm[gr[s]]; otherwise rm[gr[s]] = blk[gb[s]] (slots s < npad, gr < 0: padding)
+hipError_t launch_layout(const int *gr, const int *gb, int npad, const double *src, double *dst, bool to_blocked,
+                         hipStream_t st);
 
 template <typename T, typename TO>
 hipError_t launch_scatter(int mode, const ScatterArgs<T> &s, const T *v, TO *out, float *d32, double *partial,

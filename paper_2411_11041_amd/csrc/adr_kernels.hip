@@ -31,12 +31,6 @@ __host__ __device__ inline int line_lds_arrays(int fam) { return fam == 0 ? 3 : 
 __device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <typename T>
-__device__ inline T bilinear(const T *__restrict__ F, int cell, int nx, T lx, T ly) {
-    const T p11 = F[cell], p12 = F[cell + 1], p21 = F[cell + nx], p22 = F[cell + nx + 1];
-    return (T(1) - ly) * ((T(1) - lx) * p11 + lx * p12) + ly * ((T(1) - lx) * p21 + lx * p22);
-}
-
 template <typename T, int FAM, int MAXJ>
 __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restrict__ fin, T *__restrict__ vout,
                                           const double *__restrict__ par, const int *__restrict__ done, int nmax) {
@@ -108,22 +102,15 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         T p11[G], p12[G], p21[G], p22[G];
 #pragma unroll
         for (int t = 0; t < G; ++t) {
+            // blocked field (8 x 4 nodes per block): the corner's position in its
+            // block is in the low bits of c; nx is the block-row stride
             const int c = cj[q0 + t] >= 0 ? cj[q0 + t] : 0;
-            if constexpr (sizeof(T) == 4) {
-                // blocked field (8 x 4 nodes per block): the corner's position in
-                // its block is in the low bits of c; nx is the block-row stride
-                const int sx = (c & 7) == 7 ? 25 : 1;
-                const int cu = c + (((c >> 3) & 3) == 3 ? nx - 24 : 8);
-                p11[t] = fin[c];
-                p12[t] = fin[c + sx];
-                p21[t] = fin[cu];
-                p22[t] = fin[cu + sx];
-            } else {
-                p11[t] = fin[c];
-                p12[t] = fin[c + 1];
-                p21[t] = fin[c + nx];
-                p22[t] = fin[c + nx + 1];
-            }
+            const int sx = (c & 7) == 7 ? 25 : 1;
+            const int cu = c + (((c >> 3) & 3) == 3 ? nx - 24 : 8);
+            p11[t] = fin[c];
+            p12[t] = fin[c + sx];
+            p21[t] = fin[cu];
+            p22[t] = fin[cu + sx];
         }
 #pragma unroll
         for (int t = 0; t < G; ++t) {
@@ -345,13 +332,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
     const int slot = blk * kThreads + threadIdx.x;
     const int g = s.gidx[slot];
     const int np = s.npad;
-    // index of the node in the blocked FP32 fields (d32; out when it is FP32)
-    int gb = 0;
-    if constexpr (MODE == 1 || MODE == 2 || sizeof(TO) == 4) {
-        const int4 ib = s.inst_blk[inst];
-        const int gl = (g >= 0 ? g : ib.x) - ib.x, y = gl / ib.y, x = gl - y * ib.y;
-        gb = blocked_index(x, y, ib.z, ib.w);
-    }
+
     // every load is issued before any is used (no branch between them): the
     // records, then the line values (a missing record reads v[0], v[1] with
     // its contribution dropped), and the old grid value, which depends only
@@ -386,11 +367,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
     for (int r = 0; r < 4; ++r)
         if (kk[r] >= 0) val += wa[r] * va[r] + wb[r] * vb[r];
     if constexpr (MODE == 0) {
-        if (g >= 0) out[sizeof(TO) == 4 ? gb : g] = TO(val);
+        if (g >= 0) out[g] = TO(val);
     } else if constexpr (MODE == 2) {
         if (g >= 0) {
             out[g] = old + TO(val);
-            d32[gb] = float(val);
+            d32[g] = float(val);
         }
     } else {
         double r = 0.0;
@@ -398,7 +379,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
             r = double(val) - double(old);
             if constexpr (MODE == 1) {
                 out[g] = TO(val);
-                d32[gb] = float(r);
+                d32[g] = float(r);
             }
         }
         // fixed-order block reduction of r^2
@@ -457,6 +438,16 @@ __global__ __launch_bounds__(kThreads) void k_norm(const double *__restrict__ pa
     }
 }
 
+__global__ void k_layout(const int *__restrict__ gr, const int *__restrict__ gb, int npad,
+                         const double *__restrict__ src, double *__restrict__ dst, int to_blocked) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= npad) return;
+    const int r = gr[s];
+    if (r < 0) return;
+    if (to_blocked) dst[gb[s]] = src[r];
+    else dst[r] = src[gb[s]];
+}
+
 __global__ void k_fill_int(int *p, int v, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -506,6 +497,14 @@ hipError_t launch_norm(int n_inst, const double *partial, const int *blk_start, 
                        int *it_count, int count, double tol, int mode, hipStream_t st) {
     hipLaunchKernelGGL(k_norm, dim3(n_inst), dim3(kThreads), 0, st, partial, blk_start, cnorm, rel, done, it_count,
                        count, tol, mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_layout(const int *gr, const int *gb, int npad, const double *src, double *dst, bool to_blocked,
+                         hipStream_t st) {
+    if (npad <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_layout, dim3((npad + kThreads - 1) / kThreads), dim3(kThreads), 0, st, gr, gb, npad, src, dst,
+                       to_blocked ? 1 : 0);
     return hipGetLastError();
 }
 
