@@ -70,6 +70,10 @@ struct DevFam {
     adr::ScatterArgs<float> s32{};
     double *v64 = nullptr;
     float *v32 = nullptr;
+    // launch-list compaction (batched stationary solves): lines of unfinished instances
+    std::vector<int> inst_lines, inst_nmax;  // per instance: curves, longest curve
+    int *lidx = nullptr;                      // compacted line list (device)
+    int act = -1, act_nmax = 0;               // its length and longest curve; -1: full list
 };
 
 }  // namespace
@@ -85,9 +89,13 @@ struct adr_ctx {
     DevFam fam[2];
     int *blk_start = nullptr, *inst_bstride = nullptr;
     int *slot_rm = nullptr, *slot_b = nullptr;  // interior node of each scatter slot: row-major / blocked
+    const int *blk_inst_d = nullptr;            // instance of each scatter block (device)
     int npad = 0;
     double *Ub = nullptr;  // the state in the blocked layout during a call
     int n_blocks = 0;
+    std::vector<int> inst_blocks;                      // per instance: 256-slot scatter blocks
+    int *blist = nullptr, *cscan = nullptr, *ccount = nullptr;  // compacted block list, scan scratch, count
+    int act_blocks = -1;                               // length of blist; -1: full list
     double *par = nullptr;  // [slot][fam][inst][8]
     std::vector<double> par_h;
     double *Uh64 = nullptr, *Z64 = nullptr, *partial = nullptr, *cnorm = nullptr, *rel = nullptr;
@@ -147,16 +155,34 @@ struct adr_ctx {
         ticks.clear();
     }
 
+    // line and scatter arguments with the compacted lists when they are active
+    template <typename T>
+    adr::LineArgs<T> largs(const DevFam &F, const adr::LineArgs<T> &a) const {
+        adr::LineArgs<T> r = a;
+        if (F.act >= 0) r.lidx = F.lidx;
+        return r;
+    }
+    template <typename T>
+    adr::ScatterArgs<T> sargs(const adr::ScatterArgs<T> &a) const {
+        adr::ScatterArgs<T> r = a;
+        if (act_blocks >= 0) {
+            r.blist = blist;
+            r.nblist = act_blocks;
+        }
+        return r;
+    }
     void line64(int f, int slot, const double *fin, const int *dn) {
         DevFam &F = fam[f];
+        const int nl = F.act >= 0 ? F.act : F.n_lines, nm = F.act >= 0 ? F.act_nmax : F.nmax;
         timed(0, f, [&] {
-            return adr::launch_line<double>(f, F.a64, F.n_lines, fin, F.v64, par_ptr(slot, f), dn, F.nmax, st);
+            return adr::launch_line<double>(f, largs(F, F.a64), nl, fin, F.v64, par_ptr(slot, f), dn, nm, st);
         });
     }
     void line32(int f, int slot, const float *fin, const int *dn) {
         DevFam &F = fam[f];
+        const int nl = F.act >= 0 ? F.act : F.n_lines, nm = F.act >= 0 ? F.act_nmax : F.nmax;
         timed(1, f, [&] {
-            return adr::launch_line<float>(f, F.a32, F.n_lines, fin, F.v32, par_ptr(slot, f), dn, F.nmax, st);
+            return adr::launch_line<float>(f, largs(F, F.a32), nl, fin, F.v32, par_ptr(slot, f), dn, nm, st);
         });
     }
 
@@ -164,16 +190,46 @@ struct adr_ctx {
     // 1 write U + d32 + partial, 3 partial only (U unchanged).
     void sweep64(int slot, const double *U_in, double *U_out, int mode, const int *dn) {
         line64(0, slot, U_in, dn);
-        timed(0, 2, [&] { return adr::launch_scatter<double, double>(0, fam[0].s64, fam[0].v64, Uh64, d32, partial, dn, st); });
+        timed(0, 2, [&] { return adr::launch_scatter<double, double>(0, sargs(fam[0].s64), fam[0].v64, Uh64, d32, partial, dn, st); });
         line64(1, slot, Uh64, dn);
-        timed(0, 3, [&] { return adr::launch_scatter<double, double>(mode, fam[1].s64, fam[1].v64, U_out, d32, partial, dn, st); });
+        timed(0, 3, [&] { return adr::launch_scatter<double, double>(mode, sargs(fam[1].s64), fam[1].v64, U_out, d32, partial, dn, st); });
     }
     // One FP32 increment sweep: d32 <- T d32, U += d32.
     void sweep32(double *U, const int *dn) {
         line32(0, kSlotLin, d32, dn);
-        timed(1, 2, [&] { return adr::launch_scatter<float, float>(0, fam[0].s32, fam[0].v32, D32, nullptr, partial, dn, st); });
+        timed(1, 2, [&] { return adr::launch_scatter<float, float>(0, sargs(fam[0].s32), fam[0].v32, D32, nullptr, partial, dn, st); });
         line32(1, kSlotLin, D32, dn);
-        timed(1, 3, [&] { return adr::launch_scatter<float, double>(2, fam[1].s32, fam[1].v32, U, d32, partial, dn, st); });
+        timed(1, 3, [&] { return adr::launch_scatter<float, double>(2, sargs(fam[1].s32), fam[1].v32, U, d32, partial, dn, st); });
+    }
+
+    // Restricts the line and scatter launches to the instances not done (dn,
+    // read from the device after the stream was synchronised): the lists are
+    // compacted on the device from the same flags, their lengths counted here.
+    // The kernels still test the flags, so instances that finish later are
+    // skipped as before.  A launch's workgroups then all carry work.
+    void compact(const std::vector<int> &dn) {
+        int nb = 0;
+        for (int i = 0; i < n_inst; ++i)
+            if (!dn[i]) nb += inst_blocks[i];
+        if (nb == (act_blocks >= 0 ? act_blocks : n_blocks)) return;  // unchanged set
+        HIPCHK(adr::launch_compact(blk_inst_d, n_blocks, done, cscan, blist, ccount, st));
+        act_blocks = nb;
+        for (int f = 0; f < 2; ++f) {
+            DevFam &F = fam[f];
+            int nl = 0, nm = 0;
+            for (int i = 0; i < n_inst; ++i)
+                if (!dn[i]) {
+                    nl += F.inst_lines[i];
+                    nm = std::max(nm, F.inst_nmax[i]);
+                }
+            HIPCHK(adr::launch_compact(F.a64.linst, F.n_lines, done, cscan, F.lidx, ccount, st));
+            F.act = nl;
+            F.act_nmax = nm;
+        }
+    }
+    void uncompact() {
+        act_blocks = -1;
+        fam[0].act = fam[1].act = -1;
     }
     void norm(int count, double tol, int mode) {
         timed(0, 4, [&] {
@@ -387,6 +443,11 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         C->npad = npad;
         int *d_blk_inst = upload(blk_inst, own, st);
         C->blk_start = upload(blk_start, own, st);
+        C->blk_inst_d = d_blk_inst;
+        C->inst_blocks.resize(n);
+        for (int i = 0; i < n; ++i) C->inst_blocks[i] = blk_start[i + 1] - blk_start[i];
+        C->blist = dalloc<int>(std::max(nblk, 1), own);
+        HIPCHK(hipMemsetAsync(C->blist, 0, sizeof(int) * std::max(nblk, 1), st));  // valid indices from the start
 
         for (int f = 0; f < 2; ++f) {
             DevFam &F = C->fam[f];
@@ -415,6 +476,10 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             });
             std::vector<int> loff, lcnt, linst;
             loff.reserve(lines.size());
+            F.inst_lines.assign(n, 0);
+            F.inst_nmax.assign(n, 0);
+            F.lidx = dalloc<int>(std::max(F.n_lines, 1), own);
+            HIPCHK(hipMemsetAsync(F.lidx, 0, sizeof(int) * std::max(F.n_lines, 1), st));
             for (auto &li : lines) {
                 const adr::Family &fa = G[li.first].fam[f];
                 const int cnt = static_cast<int>(fa.off[li.second + 1] - fa.off[li.second]);
@@ -422,6 +487,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 lcnt.push_back(cnt);
                 linst.push_back(li.first);
                 F.nmax = std::max(F.nmax, cnt);
+                F.inst_lines[li.first] += 1;
+                F.inst_nmax[li.first] = std::max(F.inst_nmax[li.first], cnt);
                 F.n_unknowns += cnt - 2;
             }
             if (F.nmax > kMaxNodes || adr::line_lds_bytes<double>(f, F.nmax) > kLdsLimit)
@@ -507,6 +574,11 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         HIPCHK(hipMemsetAsync(C->d32, 0, sizeof(float) * C->n_blocked, st));
         HIPCHK(hipMemsetAsync(C->D32, 0, sizeof(float) * C->n_blocked, st));
         C->partial = dalloc<double>(std::max(nblk, 1), own);
+        {
+            const int most = std::max({nblk, C->fam[0].n_lines, C->fam[1].n_lines});
+            C->cscan = dalloc<int>((most + 255) / 256 + 1, own);
+            C->ccount = dalloc<int>(1, own);
+        }
         C->cnorm = dalloc<double>(n, own);
         C->rel = dalloc<double>(n, own);
         C->done = dalloc<int>(n, own);
@@ -672,9 +744,14 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
             for (int b = 0; b < blocks; ++b) {
                 if (use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, st));
                 else ctx->block(ub, m, tol);
-                if ((b + 1) % check == 0 && all_done()) break;
+                if ((b + 1) % check == 0) {
+                    if (all_done()) break;
+                    // the graph's launches are fixed; eager launches follow the active set
+                    if (!use_graph && n > 1) ctx->compact(dn);
+                }
             }
         }
+        ctx->uncompact();
         ctx->from_blocked(u);
         std::vector<int> ci(n, 0);
         std::vector<double> rr(n, 0.0);
@@ -693,6 +770,7 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
         if (status == ADR_ENONFINITE) ctx->err = "non-finite residual";
         return status;
     } catch (const Error &e) {
+        ctx->uncompact();
         if (ctx->opt.graph) ctx->st = static_cast<hipStream_t>(ctx->opt.stream);
         return fail_ctx(ctx, e);
     }

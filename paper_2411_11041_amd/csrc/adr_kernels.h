@@ -17,6 +17,7 @@ struct LineArgs {
     const T *h;          // per node: chord to the previous node
     const T *w;          // per node: |beta| (beta family only)
     const T *L;          // per node: load int f phi (beta family only)
+    const int *lidx;     // optional: the line of each workgroup (active lines only), else line = workgroup
 };
 
 // Scatter stencils of one family; slot s < npad (padded per instance to 256).
@@ -28,6 +29,8 @@ struct ScatterArgs {
     const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1] (FP64 tables)
     const unsigned *rw;   // [4][npad] the same weights as two FP16 halves (low: v[k]); FP32 tables
     int npad;
+    const int *blist;     // optional: the slot block of each workgroup (active blocks only)
+    int nblist;           // workgroups when blist is set
 };
 
 // The grid fields the sweeps use (state, half step, increments) are stored in
@@ -61,5 +64,10 @@ hipError_t launch_norm(int n_inst, const double *partial, const int *blk_start, 
                        int *it_count, int count, double tol, int mode, hipStream_t st);
 
 hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st);
+
+// Order-preserving compaction of the items (lines or slot blocks) whose
+// instance inst_of[i] is not done: idx receives their indices, *count (device)
+// their number.  bcnt: scratch of ceil(n / 256) + 1 ints.
+hipError_t launch_compact(const int *inst_of, int n, const int *done, int *bcnt, int *idx, int *count, hipStream_t st);
 
 }  // namespace adr

@@ -54,7 +54,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T *A1 = D0 + kThreads, *C1 = A1 + kThreads, *D1 = C1 + kThreads;
     T *FY = A1, *FA = C1, *FG = D1;
 
-    const int l = blockIdx.x;
+    const int l = a.lidx ? a.lidx[blockIdx.x] : static_cast<int>(blockIdx.x);
     const int tid = threadIdx.x;
     const int inst = a.linst[l];
     if (done[inst]) return;
@@ -310,7 +310,7 @@ template <typename T, int FAM>
 __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
                                                    T *__restrict__ vout, const double *__restrict__ par,
                                                    const int *__restrict__ done, int nmax) {
-    const int per = (a.lcnt[blockIdx.x] + kThreads - 1) / kThreads;
+    const int per = (a.lcnt[a.lidx ? a.lidx[blockIdx.x] : static_cast<int>(blockIdx.x)] + kThreads - 1) / kThreads;
     if (per <= 1) line_body<T, FAM, 1>(a, fin, vout, par, done, nmax);
     else if (per <= 2) line_body<T, FAM, 2>(a, fin, vout, par, done, nmax);
     else if (per <= 4) line_body<T, FAM, 4>(a, fin, vout, par, done, nmax);
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
                                                       TO *__restrict__ out, float *__restrict__ d32,
                                                       double *__restrict__ partial,
                                                       const int *__restrict__ done) {
-    const int blk = blockIdx.x;
+    const int blk = s.blist ? s.blist[blockIdx.x] : static_cast<int>(blockIdx.x);
     const int inst = s.blk_inst[blk];
     if (done[inst]) return;
     const int slot = blk * kThreads + threadIdx.x;
@@ -438,6 +438,65 @@ __global__ __launch_bounds__(kThreads) void k_norm(const double *__restrict__ pa
     }
 }
 
+// ------------------------------------------------------------------ compaction
+// active items (instance not done), order preserved: per-block counts, one
+// workgroup scans them, then every block writes its items' indices
+__global__ __launch_bounds__(kThreads) void k_count_active(const int *__restrict__ inst_of, int n,
+                                                           const int *__restrict__ done, int *__restrict__ bcnt) {
+    __shared__ int red[kThreads];
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    red[threadIdx.x] = (i < n && !done[inst_of[i]]) ? 1 : 0;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bcnt[blockIdx.x] = red[0];
+}
+
+// in-place exclusive scan of nb counts by one workgroup; *total = their sum
+__global__ __launch_bounds__(kThreads) void k_scan_counts(int *__restrict__ bcnt, int nb, int *__restrict__ total) {
+    __shared__ int sc[kThreads];
+    __shared__ int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < nb; b0 += kThreads) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < nb ? bcnt[b] : 0;
+        sc[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = 1; w < kThreads; w <<= 1) {  // inclusive Hillis-Steele scan
+            const int add = static_cast<int>(threadIdx.x) >= w ? sc[threadIdx.x - w] : 0;
+            __syncthreads();
+            sc[threadIdx.x] += add;
+            __syncthreads();
+        }
+        const int base = carry;
+        if (b < nb) bcnt[b] = base + sc[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == kThreads - 1) carry = base + sc[threadIdx.x];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kThreads) void k_write_active(const int *__restrict__ inst_of, int n,
+                                                           const int *__restrict__ done,
+                                                           const int *__restrict__ bstart, int *__restrict__ idx) {
+    __shared__ int sc[kThreads];
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int f = (i < n && !done[inst_of[i]]) ? 1 : 0;
+    sc[threadIdx.x] = f;
+    __syncthreads();
+    for (int w = 1; w < kThreads; w <<= 1) {
+        const int add = static_cast<int>(threadIdx.x) >= w ? sc[threadIdx.x - w] : 0;
+        __syncthreads();
+        sc[threadIdx.x] += add;
+        __syncthreads();
+    }
+    if (f) idx[bstart[blockIdx.x] + sc[threadIdx.x] - 1] = i;
+}
+
 __global__ void k_layout(const int *__restrict__ gr, const int *__restrict__ gb, int npad,
                          const double *__restrict__ src, double *__restrict__ dst, int to_blocked) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
@@ -482,7 +541,7 @@ hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin,
 template <typename T, typename TO>
 hipError_t launch_scatter(int mode, const ScatterArgs<T> &s, const T *v, TO *out, float *d32, double *partial,
                           const int *done, hipStream_t st) {
-    const int nb = s.npad / kThreads;
+    const int nb = s.blist ? s.nblist : s.npad / kThreads;
     if (nb == 0) return hipSuccess;
     switch (mode) {
         case 0: hipLaunchKernelGGL((k_scatter<T, TO, 0>), dim3(nb), dim3(kThreads), 0, st, s, v, out, d32, partial, done); break;
@@ -505,6 +564,15 @@ hipError_t launch_layout(const int *gr, const int *gb, int npad, const double *s
     if (npad <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_layout, dim3((npad + kThreads - 1) / kThreads), dim3(kThreads), 0, st, gr, gb, npad, src, dst,
                        to_blocked ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const int *inst_of, int n, const int *done, int *bcnt, int *idx, int *count, hipStream_t st) {
+    const int nb = (n + kThreads - 1) / kThreads;
+    if (nb == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_active, dim3(nb), dim3(kThreads), 0, st, inst_of, n, done, bcnt);
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kThreads), 0, st, bcnt, nb, count);
+    hipLaunchKernelGGL(k_write_active, dim3(nb), dim3(kThreads), 0, st, inst_of, n, done, bcnt, idx);
     return hipGetLastError();
 }
 
