@@ -33,7 +33,6 @@ constexpr int kW1 = 32 * 9 * 4, kW2 = 32 * 9 * 32, kW4 = 9 * 32;
 // offsets in the parameter vector
 constexpr int oW1 = 0, ob1 = oW1 + kW1, oW2 = ob1 + 32, ob2 = oW2 + kW2, oW3 = ob2 + 32, ob3 = oW3 + kW2,
               oW4 = ob3 + 32, ob4 = oW4 + kW4, kParams = ob4 + 1;
-constexpr int kChunk = 256;  // pixels per weight-gradient chunk
 constexpr int kDil[4] = {1, 2, 4, 8};
 
 __device__ __forceinline__ bf16_t f2bf(float f) {
@@ -52,7 +51,9 @@ __device__ __forceinline__ v4f32 mfma(v4i16 a, v4i16 b, v4f32 c) {
 // ------------------------------------------------------------------ conv, 4 -> 32 (first layer)
 // y = bf16(relu(conv(x0) + bias)); x0: [NP][4] BF16, Wg: [32][9][4].  A wavefront
 // computes 16 pixels x 32 channels; K = 12 taps (9, padded) x 4 channels, one
-// tap per lane group, so a lane's 4 K values are one pixel's 4 channels.
+// tap per lane group, so a lane's 4 K values are one pixel's 4 channels.  N-tile
+// 0 holds the even output channels and N-tile 1 the odd ones: a lane stores its
+// two results of a pixel as one 4-byte pair.
 __global__ __launch_bounds__(kThreads) void k_conv_in(const bf16_t *__restrict__ x, const bf16_t *__restrict__ Wg,
                                                       const float *__restrict__ bias, bf16_t *__restrict__ y,
                                                       int NP, int H, int W, int d) {
@@ -68,7 +69,8 @@ __global__ __launch_bounds__(kThreads) void k_conv_in(const bf16_t *__restrict__
     const int HW = H * W;
     const int ntiles = (NP + 15) / 16;
     const v4i16 zero = {0, 0, 0, 0};
-    const float bias0 = bias[i], bias1 = bias[i + 16];
+    const float bias0 = bias[2 * i], bias1 = bias[2 * i + 1];
+    unsigned *yw = reinterpret_cast<unsigned *>(y);
     for (int t = blockIdx.x * 4 + wave; t < ntiles; t += gridDim.x * 4) {
         const int gp = t * 16 + i;  // pixel of this lane's A row
         const bool pv = gp < NP;
@@ -91,8 +93,8 @@ __global__ __launch_bounds__(kThreads) void k_conv_in(const bf16_t *__restrict__
 #pragma unroll
         for (int kc = 0; kc < 3; ++kc) {
             const int tap = kc * 4 + g;
-            const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(i * KT + tap) * CIN]);
-            const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[((i + 16) * KT + tap) * CIN]);
+            const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[((2 * i) * KT + tap) * CIN]);
+            const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[((2 * i + 1) * KT + tap) * CIN]);
             acc0 = mfma(av[kc], b0, acc0);
             acc1 = mfma(av[kc], b1, acc1);
         }
@@ -100,25 +102,28 @@ __global__ __launch_bounds__(kThreads) void k_conv_in(const bf16_t *__restrict__
         for (int v = 0; v < 4; ++v) {
             const int po = t * 16 + 4 * g + v;
             if (po >= NP) continue;
-            y[static_cast<size_t>(po) * kCh + i] = f2bf(fmaxf(acc0[v] + bias0, 0.f));
-            y[static_cast<size_t>(po) * kCh + i + 16] = f2bf(fmaxf(acc1[v] + bias1, 0.f));
+            yw[static_cast<unsigned>(po) * (kCh / 2) + i] = static_cast<unsigned>(f2bf(fmaxf(acc0[v] + bias0, 0.f))) |
+                                                           (static_cast<unsigned>(f2bf(fmaxf(acc1[v] + bias1, 0.f))) << 16);
         }
     }
 }
 
 // ------------------------------------------------------------------ conv, 32 -> 32, tiled
-// A workgroup computes a 16 x 16-pixel output tile of one image for all 32
-// output channels.  The input patch ((16 + 2d)^2 pixels x 32 channels, zeros
-// outside the image) and the weights are staged in LDS once; pixel rows are
-// padded to kCP channels and weight rows to kWS entries so that the fragment
-// reads of a wavefront spread over the LDS banks.  Wavefront w computes tile
-// rows 4w .. 4w+3 (4 M-tiles of 16 pixels) x 32 channels (2 N-tiles).
+// A workgroup computes 16 x 16-pixel output tiles (all 32 output channels) in
+// turn.  The weights are staged in LDS once; per tile the input patch
+// ((16 + 2d)^2 pixels x 32 channels, zeros outside the image) is staged, and
+// the next tile's patch loads are issued before the current tile's products.
+// Pixel rows are padded to kCP channels and weight rows to kWS entries so that
+// the fragment reads of a wavefront spread over the LDS banks.  Wavefront w
+// computes tile rows 4w .. 4w+3 (4 M-tiles of 16 pixels) x 32 channels: N-tile
+// 0 holds the even output channels and N-tile 1 the odd ones, so that a lane's
+// two results of a pixel are adjacent channels (one 4-byte store).
 // EPI 0: y = bf16(relu(acc + bias)).  EPI 1: y = bf16(acc * (ymask > 0)) (back-
 // propagation through the ReLU of the layer input, with flipped taps).
 constexpr int kTile = 16;
 constexpr int kCP = 36;            // staged channels per pixel (32 + pad)
 constexpr int kWS = 9 * kCh + 4;   // staged weight row (one output channel: 9 taps x 32 inputs + pad)
-constexpr int kMaxDilT = 4;        // largest dilation the tiled kernel stages (patch (16 + 2*4)^2)
+constexpr int kMaxDilT = 4;        // largest dilation the tiled kernels stage (patch (16 + 2*4)^2)
 constexpr int kWStage = (kCh * 36 + kThreads - 1) / kThreads;
 constexpr int kXStage = ((kTile + 2 * kMaxDilT) * (kTile + 2 * kMaxDilT) * 4 + kThreads - 1) / kThreads;
 
@@ -128,234 +133,385 @@ __host__ __device__ inline size_t conv_tiled_lds(int d) {
     return sizeof(bf16_t) * (static_cast<size_t>(kCh) * kWS + static_cast<size_t>(P) * P * kCP);
 }
 
-template <int EPI>
+// the patch loads of tile t (16 bytes each, issued without waiting): a pixel
+// outside the image reads the image's first pixel; bit u of *inm marks load u
+// as inside (the LDS store writes zeros for the others)
+template <int XS>
+__device__ __forceinline__ void conv_patch_load(const bf16_t *__restrict__ x, int t, int tpi, int tw, int H, int W,
+                                                int d, int P, uint4 (&xv)[XS], unsigned &inm) {
+    const int b = t / tpi, tt = t - b * tpi;
+    const int ty = tt / tw, tx = tt - ty * tw;
+    const int y0 = ty * kTile, x0 = tx * kTile;
+    const unsigned ib = static_cast<unsigned>(b) * static_cast<unsigned>(H * W);
+    const uint4 *xq = reinterpret_cast<const uint4 *>(x);
+    unsigned m = 0;
+#pragma unroll
+    for (int u = 0; u < XS; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        const int pix = e >> 2, q = e & 3;
+        const int py = pix / P, px = pix - py * P;
+        const int gy = y0 - d + py, gx = x0 - d + px;
+        const bool ok = e < P * P * 4 && gy >= 0 && gy < H && gx >= 0 && gx < W;
+        const unsigned gp = ib + (ok ? static_cast<unsigned>(gy * W + gx) : 0u);
+        xv[u] = xq[gp * (kCh / 8) + q];
+        m |= ok ? 1u << u : 0u;
+    }
+    inm = m;
+}
+
+// XS: patch loads per thread, ceil((16 + 2d)^2 * 4 / 256) (the prefetch registers)
+template <int EPI, int XS>
 __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__ x, const bf16_t *__restrict__ Wg,
                                                       const float *__restrict__ bias,
                                                       const bf16_t *__restrict__ ymask, bf16_t *__restrict__ y,
-                                                      int H, int W, int d) {
+                                                      int H, int W, int d, int ntiles) {
     extern __shared__ __align__(16) unsigned char sm[];
     bf16_t *Ws = reinterpret_cast<bf16_t *>(sm);  // [32][kWS]
     bf16_t *Xs = Ws + kCh * kWS;                  // [P*P][kCP]
     const int P = kTile + 2 * d;
     const int tw = (W + kTile - 1) / kTile, tpi = conv_tiles(H, W);
-    const int b = blockIdx.x / tpi, t = blockIdx.x - b * tpi;
-    const int ty = t / tw, tx = t - ty * tw;
-    const int y0 = ty * kTile, x0 = tx * kTile;
-    // staging, 16 bytes (8 channels) per load, every load issued before the
-    // first LDS store: the weights (32 rows of 288 entries), then the input
-    // patch (a pixel outside the image reads the tile's first in-image pixel
-    // and stores zeros)
     const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
-    uint4 wv[kWStage];
+    // weights, once (32 rows of 288 entries, 16 bytes per load)
+    {
+        uint4 wv[kWStage];
 #pragma unroll
-    for (int u = 0; u < kWStage; ++u) {
-        const int e = threadIdx.x + u * kThreads;
-        wv[u] = reinterpret_cast<const uint4 *>(Wg)[e < kCh * 36 ? e : 0];
-    }
-    const bf16_t *xb = x + static_cast<size_t>(b) * H * W * kCh;
-    const uint4 *x00 = reinterpret_cast<const uint4 *>(xb + (static_cast<size_t>(y0) * W + x0) * kCh);
-    uint4 xv[kXStage];
-    bool in[kXStage];
+        for (int u = 0; u < kWStage; ++u) {
+            const int e = threadIdx.x + u * kThreads;
+            wv[u] = reinterpret_cast<const uint4 *>(Wg)[e < kCh * 36 ? e : 0];
+        }
 #pragma unroll
-    for (int u = 0; u < kXStage; ++u) {
-        const int e = threadIdx.x + u * kThreads;
-        const int pix = e >> 2, q = e & 3;
-        const int py = pix / P, px = pix - py * P;
-        const int gy = y0 - d + py, gx = x0 - d + px;
-        in[u] = e < P * P * 4 && gy >= 0 && gy < H && gx >= 0 && gx < W;
-        const uint4 *src = in[u] ? reinterpret_cast<const uint4 *>(xb + (static_cast<size_t>(gy) * W + gx) * kCh) + q
-                                 : x00;
-        xv[u] = *src;
-    }
-#pragma unroll
-    for (int u = 0; u < kWStage; ++u) {
-        const int e = threadIdx.x + u * kThreads;
-        if (e < kCh * 36) {
-            const int n = e / 36, q = e - n * 36;
-            uint2 *dst = reinterpret_cast<uint2 *>(Ws + n * kWS + q * 8);
-            dst[0] = make_uint2(wv[u].x, wv[u].y);
-            dst[1] = make_uint2(wv[u].z, wv[u].w);
+        for (int u = 0; u < kWStage; ++u) {
+            const int e = threadIdx.x + u * kThreads;
+            if (e < kCh * 36) {
+                const int n = e / 36, q = e - n * 36;
+                uint2 *dst = reinterpret_cast<uint2 *>(Ws + n * kWS + q * 8);
+                dst[0] = make_uint2(wv[u].x, wv[u].y);
+                dst[1] = make_uint2(wv[u].z, wv[u].w);
+            }
         }
     }
-#pragma unroll
-    for (int u = 0; u < kXStage; ++u) {
-        const int e = threadIdx.x + u * kThreads;
-        if (e < P * P * 4) {
-            const uint4 v = in[u] ? xv[u] : z4;
-            uint2 *dst = reinterpret_cast<uint2 *>(Xs + (e >> 2) * kCP + (e & 3) * 8);
-            dst[0] = make_uint2(v.x, v.y);
-            dst[1] = make_uint2(v.z, v.w);
-        }
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, g = lane >> 4;
-    v4f32 acc[4][2];
+    const float bias0 = EPI == 0 ? bias[2 * i] : 0.f, bias1 = EPI == 0 ? bias[2 * i + 1] : 0.f;
+    uint4 xv[XS];
+    unsigned inm = 0;
+    int t = blockIdx.x;
+    if (t < ntiles) conv_patch_load<XS>(x, t, tpi, tw, H, W, d, P, xv, inm);
+    for (; t < ntiles; t += gridDim.x) {
+        __syncthreads();  // the previous tile's products are done with Xs
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt][0] = acc[mt][1] = v4f32{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        const int oy = d + d * (tap / 3 - 1), ox = d + d * (tap % 3 - 1);
-#pragma unroll
-        for (int cc = 0; cc < 2; ++cc) {
-            const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[i * kWS + tap * kCh + cc * 16 + g * 4]);
-            const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[(i + 16) * kWS + tap * kCh + cc * 16 + g * 4]);
-#pragma unroll
-            for (int mt = 0; mt < 4; ++mt) {
-                const int r = wave * 4 + mt;
-                const v4i16 a =
-                    *reinterpret_cast<const v4i16 *>(&Xs[((r + oy) * P + i + ox) * kCP + cc * 16 + g * 4]);
-                acc[mt][0] = mfma(a, b0, acc[mt][0]);
-                acc[mt][1] = mfma(a, b1, acc[mt][1]);
+        for (int u = 0; u < XS; ++u) {
+            const int e = threadIdx.x + u * kThreads;
+            if (e < P * P * 4) {
+                const uint4 v = (inm >> u) & 1u ? xv[u] : z4;
+                uint2 *dst = reinterpret_cast<uint2 *>(Xs + (e >> 2) * kCP + (e & 3) * 8);
+                dst[0] = make_uint2(v.x, v.y);
+                dst[1] = make_uint2(v.z, v.w);
             }
         }
-    }
-    const float bias0 = EPI == 0 ? bias[i] : 0.f, bias1 = EPI == 0 ? bias[i + 16] : 0.f;
+        __syncthreads();
+        if (t + static_cast<int>(gridDim.x) < ntiles)  // in flight during the products
+            conv_patch_load<XS>(x, t + gridDim.x, tpi, tw, H, W, d, P, xv, inm);
+        v4f32 acc[4][2];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
-        const int gy = y0 + wave * 4 + mt;
+        for (int mt = 0; mt < 4; ++mt) acc[mt][0] = acc[mt][1] = v4f32{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int tap = 0; tap < 9; ++tap) {
+            const int oy = d + d * (tap / 3 - 1), ox = d + d * (tap % 3 - 1);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int gx = x0 + 4 * g + v;
-            if (gy >= H || gx >= W) continue;
-            const size_t po = (static_cast<size_t>(b) * H + gy) * W + gx;
-            float z0 = acc[mt][0][v], z1 = acc[mt][1][v];
-            if constexpr (EPI == 0) {
-                z0 = fmaxf(z0 + bias0, 0.f);
-                z1 = fmaxf(z1 + bias1, 0.f);
-            } else {
-                z0 = bf_pos(ymask[po * kCh + i]) ? z0 : 0.f;
-                z1 = bf_pos(ymask[po * kCh + i + 16]) ? z1 : 0.f;
+            for (int cc = 0; cc < 2; ++cc) {
+                const v4i16 b0 = *reinterpret_cast<const v4i16 *>(&Ws[(2 * i) * kWS + tap * kCh + cc * 16 + g * 4]);
+                const v4i16 b1 = *reinterpret_cast<const v4i16 *>(&Ws[(2 * i + 1) * kWS + tap * kCh + cc * 16 + g * 4]);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const int r = wave * 4 + mt;
+                    const v4i16 a =
+                        *reinterpret_cast<const v4i16 *>(&Xs[((r + oy) * P + i + ox) * kCP + cc * 16 + g * 4]);
+                    acc[mt][0] = mfma(a, b0, acc[mt][0]);
+                    acc[mt][1] = mfma(a, b1, acc[mt][1]);
+                }
             }
-            y[po * kCh + i] = f2bf(z0);
-            y[po * kCh + i + 16] = f2bf(z1);
+        }
+        const int b = t / tpi, tt = t - b * tpi;
+        const int ty = tt / tw, tx = tt - ty * tw;
+        const int y0 = ty * kTile, x0 = tx * kTile;
+        unsigned *yw = reinterpret_cast<unsigned *>(y);
+        const unsigned *mw = reinterpret_cast<const unsigned *>(ymask);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int gy = y0 + wave * 4 + mt;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int gx = x0 + 4 * g + v;
+                if (gy >= H || gx >= W) continue;
+                const unsigned po = (static_cast<unsigned>(b) * H + gy) * W + gx;
+                float z0 = acc[mt][0][v], z1 = acc[mt][1][v];
+                if constexpr (EPI == 0) {
+                    z0 = fmaxf(z0 + bias0, 0.f);
+                    z1 = fmaxf(z1 + bias1, 0.f);
+                } else {
+                    const unsigned mk = mw[po * (kCh / 2) + i];
+                    z0 = bf_pos(static_cast<bf16_t>(mk & 0xffffu)) ? z0 : 0.f;
+                    z1 = bf_pos(static_cast<bf16_t>(mk >> 16)) ? z1 : 0.f;
+                }
+                yw[po * (kCh / 2) + i] = static_cast<unsigned>(f2bf(z0)) | (static_cast<unsigned>(f2bf(z1)) << 16);
+            }
         }
     }
 }
 
-// ------------------------------------------------------------------ weight gradient (MFMA)
-// part[blk][ (n*9 + tap)*CIN + c ] = sum over the block's pixels of g[p][n] x[p + d off(tap)][c]
-// and part[blk][32*9*CIN + n] = sum g[p][n].  g: [NP][32], x: [NP][CIN] BF16.
-// A chunk of kChunk consecutive pixels reads x in three bands (tap rows
-// dy = -1, 0, 1), each kChunk + 2d pixels long, staged channel-major in LDS.
+// ------------------------------------------------------------------ weight gradient (MFMA), tiled
+// part[blk][(n*9 + tap)*CIN + c] = sum over the block's pixels p of g[p][n] x[p + d off(tap)][c]
+// and part[blk][32*9*CIN + n] = sum g[p][n]; g: [NP][32], x: [NP][CIN] BF16.
+// A workgroup takes 16 x 16-pixel tiles of the images in turn.  Per tile it
+// stages g (the tile's 256 pixels) and the input patch ((16 + 2d)^2 pixels,
+// zeros outside the image) channel-major in LDS; a lane's MFMA operand is then
+// 4 consecutive pixels of one channel, one 8-byte read.  The pixel quads are
+// transposed in registers (4 pixels x 8 channels -> 8 channels x 4 pixels), and
+// the next tile's loads are issued before the current tile's products.
+// GEMM view: M = 32 output channels (2 row tiles), N = 9 CIN (tap, c)
+// columns, K = the tile's pixels, one tile row (16 pixels) per MFMA.
+constexpr int kGS = kTile * kTile + 4;  // gT row stride: 16 rows of one fragment read fall on distinct bank pairs
+__host__ __device__ inline int wg_pw(int d) { return (kTile + 2 * d + 3) & ~3; }  // patch row (multiple of 4)
+__host__ __device__ inline int wg_cs(int d) {  // patch channel stride, = 4 (mod 64) like kGS
+    const int raw = (kTile + 2 * d) * wg_pw(d);
+    return raw + (((4 - raw) % 64) + 64) % 64;
+}
+__host__ __device__ inline size_t wgrad_lds(int cin, int d) {
+    return sizeof(bf16_t) * (static_cast<size_t>(kCh) * kGS + static_cast<size_t>(cin) * wg_cs(d));
+}
+// patch items per thread: CIN 32: (row, pixel quad, channel octet); CIN 4: (row, pixel quad)
 template <int CIN>
-__global__ __launch_bounds__(kThreads) void k_wgrad32(const bf16_t *__restrict__ gsrc, const bf16_t *__restrict__ x,
-                                                      float *__restrict__ part, int NP, int H, int W, int d) {
-    constexpr int NCOL = 9 * CIN;                 // (tap, c) columns
-    constexpr int NJT = (NCOL + 15) / 16;         // column tiles
-    constexpr int NT = 2 * NJT;                   // output tiles (2 row tiles of 16 channels)
-    constexpr int TPW = (NT + 3) / 4;             // tiles per wave
-    const int bspan = (kChunk + 2 * d + 3) & ~3;  // one band (a multiple of 4: aligned fragments)
-    const int span = 3 * bspan;
+constexpr int wg_xitems() {
+    return CIN == 32 ? ((kTile + 2 * kMaxDilT) * ((kTile + 2 * kMaxDilT + 3) / 4) * 4 + kThreads - 1) / kThreads
+                     : ((kTile + 2 * kMaxDilT) * ((kTile + 2 * kMaxDilT + 3) / 4) + kThreads - 1) / kThreads;
+}
+
+__device__ __forceinline__ unsigned word_of(const uint4 &v, int w) {
+    return w == 0 ? v.x : w == 1 ? v.y : w == 2 ? v.z : v.w;
+}
+
+// 4 pixels' words w of a channel octet -> the two 4-pixel rows of channels 2w, 2w+1
+__device__ __forceinline__ void tr_pair(unsigned p0, unsigned p1, unsigned p2, unsigned p3, uint2 &ev, uint2 &od) {
+    ev.x = (p0 & 0xffffu) | (p1 << 16);
+    ev.y = (p2 & 0xffffu) | (p3 << 16);
+    od.x = (p0 >> 16) | (p1 & 0xffff0000u);
+    od.y = (p2 >> 16) | (p3 & 0xffff0000u);
+}
+
+// Loads of one tile (g quad and patch items of this thread), issued without
+// waiting: out-of-image pixels read the image's first pixel and are marked in
+// *okm (bit v: g pixel v; bit 4 + 4u + v: patch item u, pixel v), zeroed at
+// the LDS store.  Offsets are 32-bit (an activation buffer holds < 2^31 entries).
+template <int CIN, int XI, int XU>
+__device__ __forceinline__ void wg_load(const bf16_t *__restrict__ gsrc, const bf16_t *__restrict__ x, int t,
+                                        int tpi, int tw, int H, int W, int d, int P, int QW, int nxi, int tid,
+                                        uint4 (&gv)[4], uint4 (&xv)[XI][XU], unsigned &okm) {
+    const int b = t / tpi, tt = t - b * tpi;
+    const int ty = tt / tw, tx = tt - ty * tw;
+    const int y0 = ty * kTile, x0 = tx * kTile;
+    const unsigned ib = static_cast<unsigned>(b) * static_cast<unsigned>(H * W);
+    unsigned m = 0;
+    {
+        const int gq = tid >> 2, go = tid & 3;
+        const int gy = y0 + (gq >> 2), gx0 = x0 + 4 * (gq & 3);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const bool ok = gy < H && gx0 + v < W;
+            const unsigned pix = ib + (ok ? static_cast<unsigned>(gy * W + gx0 + v) : 0u);
+            gv[v] = reinterpret_cast<const uint4 *>(gsrc)[pix * (kCh / 8) + go];
+            m |= ok ? 1u << v : 0u;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < XI; ++u) {
+        const int e = tid + u * kThreads;
+        const int it = CIN == 32 ? e >> 2 : e;
+        const int py = it / QW, qx = it - py * QW;
+        const int gy = y0 - d + py;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int px = 4 * qx + v, gx = x0 - d + px;
+            const bool ok = e < nxi && px < P && gy >= 0 && gy < H && gx >= 0 && gx < W;
+            const unsigned pix = ib + (ok ? static_cast<unsigned>(gy * W + gx) : 0u);
+            if (CIN == 32) {
+                xv[u][v] = reinterpret_cast<const uint4 *>(x)[pix * (kCh / 8) + (e & 3)];
+            } else {
+                const uint2 w2 = reinterpret_cast<const uint2 *>(x)[pix];
+                // two pixels per uint4: v even -> .x .y, v odd -> .z .w
+                if (v & 1) { xv[u][v >> 1].z = w2.x; xv[u][v >> 1].w = w2.y; }
+                else { xv[u][v >> 1].x = w2.x; xv[u][v >> 1].y = w2.y; }
+            }
+            m |= ok ? 1u << (4 + 4 * u + v) : 0u;
+        }
+    }
+    okm = m;
+}
+
+template <int CIN>
+__global__ __launch_bounds__(kThreads) void k_wgradt(const bf16_t *__restrict__ gsrc, const bf16_t *__restrict__ x,
+                                                     float *__restrict__ part, int ntiles, int H, int W, int d) {
+    constexpr int NCOL = 9 * CIN;          // (tap, c) columns
+    constexpr int NJT = (NCOL + 15) / 16;  // column tiles
+    constexpr int CPW = (NJT + 3) / 4;     // column tiles per wave
+    constexpr int XI = wg_xitems<CIN>();
+    constexpr int XU = CIN == 32 ? 4 : 2;  // 16-byte loads per patch item
     extern __shared__ __align__(16) unsigned char sm[];
-    constexpr int GS = kChunk + 4;                              // gT row stride (8-byte aligned, 2-way banks)
-    bf16_t *gT = reinterpret_cast<bf16_t *>(sm);                // [32][GS]
-    bf16_t *xT = gT + kCh * GS;                                 // [CIN][3][bspan]
-    unsigned short *vm = reinterpret_cast<unsigned short *>(xT + CIN * span);  // [kChunk] valid taps (bit tap)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bf16_t *gT = reinterpret_cast<bf16_t *>(sm);  // [32][kGS]
+    bf16_t *xT = gT + kCh * kGS;                  // [CIN][CS]: row py at py * PW
+    const int P = kTile + 2 * d, PW = wg_pw(d), CS = wg_cs(d);
+    const int QW = PW / 4;                        // pixel quads per patch row
+    const int nxi = CIN == 32 ? P * QW * 4 : P * QW;
+    const int tw = (W + kTile - 1) / kTile, tpi = conv_tiles(H, W);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, g = lane >> 4;
-    const int HW = H * W;
-    v4f32 acc[TPW];
+    // this thread's g item: pixel quad gq (tile row gq / 4, pixels 4 (gq % 4) ..), channel octet go
+    const int gq = tid >> 2, go = tid & 3;
+
+    uint4 gv[4], xv[XI][XU];
+    unsigned okm = 0;
+    v4f32 acc[CPW][2];
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) acc[q] = v4f32{0.f, 0.f, 0.f, 0.f};
-    float dbias = 0.f;
-    const int nchunks = (NP + kChunk - 1) / kChunk;
-    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int c0 = ch * kChunk;
-        __syncthreads();
-        for (int e = threadIdx.x; e < kCh * kChunk; e += kThreads) {
-            const int pl = e / kCh, n = e % kCh;  // coalesced read of g
-            const int gp = c0 + pl;
-            const bf16_t gv = gp < NP ? gsrc[static_cast<size_t>(gp) * kCh + n] : bf16_t(0);
-            gT[n * GS + pl] = gv;
-            dbias += bf2f(gv);  // this thread always stages channel n = threadIdx.x % 32
-        }
-        for (int e = threadIdx.x; e < span * CIN; e += kThreads) {
-            const int sl = e / CIN, c = e % CIN;  // coalesced read of x
-            const int band = sl / bspan, bl = sl - band * bspan;
-            const int gp = c0 + (band - 1) * d * W - d + bl;
-            xT[c * span + sl] = (gp >= 0 && gp < NP) ? x[static_cast<size_t>(gp) * CIN + c] : bf16_t(0);
-        }
-        for (int pl = threadIdx.x; pl < kChunk; pl += kThreads) {
-            const int gp = c0 + pl;
-            unsigned mask = 0;
-            if (gp < NP) {
-                const int p = gp % HW, yy = p / W, xx = p % W;
+    for (int q = 0; q < CPW; ++q) acc[q][0] = acc[q][1] = v4f32{0.f, 0.f, 0.f, 0.f};
+    float db[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+
+    // column tiles of this wave: jt = wave + 4 cq (cq < CPW, jt < NJT), each with
+    // both row tiles, so that a B fragment feeds two products.  CIN 32: a column
+    // tile is 16 channels of one tap, so its tap and offset are uniform over the
+    // wavefront (scalar); the lane adds c * CS + 4 g.
+    const int wv = __builtin_amdgcn_readfirstlane(wave);
+    int bofs[CPW];
+    bool jok[CPW], colok_q[CPW];
 #pragma unroll
-                for (int tap = 0; tap < 9; ++tap) {
-                    const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-                    if (yy + dy >= 0 && yy + dy < H && xx + dx >= 0 && xx + dx < W) mask |= 1u << tap;
+    for (int cq = 0; cq < CPW; ++cq) {
+        const int jt = wv + 4 * cq;
+        jok[cq] = jt < NJT;
+        if (CIN == 32) {
+            const int tap = jok[cq] ? jt >> 1 : 4, dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            bofs[cq] = (jt & 1) * 16 * CS + (d + dy) * PW + d + dx;  // uniform
+            colok_q[cq] = jok[cq];
+        } else {
+            const int col = jt * 16 + i;
+            const bool ok = jok[cq] && col < NCOL;
+            const int tap = ok ? col / CIN : 4, c = ok ? col % CIN : 0;
+            const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            bofs[cq] = c * CS + (d + dy) * PW + d + dx;  // per lane
+            colok_q[cq] = ok;
+        }
+    }
+    const int lbase = (CIN == 32 ? i * CS : 0) + 4 * g;
+
+    int t = blockIdx.x;
+    if (t < ntiles) wg_load<CIN, XI, XU>(gsrc, x, t, tpi, tw, H, W, d, P, QW, nxi, tid, gv, xv, okm);
+    for (; t < ntiles; t += gridDim.x) {
+        __syncthreads();  // the previous tile's products are done with the LDS
+        // g: 8 channels x 4 pixels -> 8 rows of gT (and the bias gradient)
+        {
+            const int pl = (gq >> 2) * kTile + 4 * (gq & 3);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const unsigned p0 = (okm & 1u) ? word_of(gv[0], w) : 0u, p1 = (okm & 2u) ? word_of(gv[1], w) : 0u;
+                const unsigned p2 = (okm & 4u) ? word_of(gv[2], w) : 0u, p3 = (okm & 8u) ? word_of(gv[3], w) : 0u;
+                uint2 ev, od;
+                tr_pair(p0, p1, p2, p3, ev, od);
+                *reinterpret_cast<uint2 *>(&gT[(8 * go + 2 * w) * kGS + pl]) = ev;
+                *reinterpret_cast<uint2 *>(&gT[(8 * go + 2 * w + 1) * kGS + pl]) = od;
+                db[2 * w] += bf2f(static_cast<bf16_t>(p0 & 0xffffu)) + bf2f(static_cast<bf16_t>(p1 & 0xffffu)) +
+                             bf2f(static_cast<bf16_t>(p2 & 0xffffu)) + bf2f(static_cast<bf16_t>(p3 & 0xffffu));
+                db[2 * w + 1] += bf2f(static_cast<bf16_t>(p0 >> 16)) + bf2f(static_cast<bf16_t>(p1 >> 16)) +
+                                 bf2f(static_cast<bf16_t>(p2 >> 16)) + bf2f(static_cast<bf16_t>(p3 >> 16));
+            }
+        }
+        // patch: channel-major rows
+#pragma unroll
+        for (int u = 0; u < XI; ++u) {
+            const int e = tid + u * kThreads;
+            if (e >= nxi) continue;
+            const int it = CIN == 32 ? e >> 2 : e;
+            const int py = it / QW, qx = it - py * QW;
+            const int off = py * PW + 4 * qx;
+            if (CIN == 32) {
+                const int c0 = 8 * (e & 3);
+#pragma unroll
+                for (int w = 0; w < 4; ++w) {
+                    uint2 ev, od;
+                    const unsigned mu = okm >> (4 + 4 * u);
+                    tr_pair((mu & 1u) ? word_of(xv[u][0], w) : 0u, (mu & 2u) ? word_of(xv[u][1], w) : 0u,
+                            (mu & 4u) ? word_of(xv[u][2], w) : 0u, (mu & 8u) ? word_of(xv[u][3], w) : 0u, ev, od);
+                    *reinterpret_cast<uint2 *>(&xT[(c0 + 2 * w) * CS + off]) = ev;
+                    *reinterpret_cast<uint2 *>(&xT[(c0 + 2 * w + 1) * CS + off]) = od;
+                }
+            } else {
+                // pixels v = 0..3 hold words (c0 c1), (c2 c3): xv[u][v / 2] .x .y (even v) or .z .w (odd v)
+#pragma unroll
+                for (int w = 0; w < 2; ++w) {
+                    const unsigned mu = okm >> (4 + 4 * u);
+                    const unsigned p0 = (mu & 1u) ? word_of(xv[u][0], w) : 0u;
+                    const unsigned p1 = (mu & 2u) ? word_of(xv[u][0], 2 + w) : 0u;
+                    const unsigned p2 = (mu & 4u) ? word_of(xv[u][1], w) : 0u;
+                    const unsigned p3 = (mu & 8u) ? word_of(xv[u][1], 2 + w) : 0u;
+                    uint2 ev, od;
+                    tr_pair(p0, p1, p2, p3, ev, od);
+                    *reinterpret_cast<uint2 *>(&xT[(2 * w) * CS + off]) = ev;
+                    *reinterpret_cast<uint2 *>(&xT[(2 * w + 1) * CS + off]) = od;
                 }
             }
-            vm[pl] = static_cast<unsigned short>(mask);
         }
         __syncthreads();
+        if (t + static_cast<int>(gridDim.x) < ntiles)  // in flight during the products
+            wg_load<CIN, XI, XU>(gsrc, x, t + gridDim.x, tpi, tw, H, W, d, P, QW, nxi, tid, gv, xv, okm);
+        // all fragment reads of a tile row are issued before its products: the
+        // read form is the same for every tile (CIN 32: two 4-byte halves, the
+        // tap shift d + dx being even; CIN 4: four 2-byte reads)
+#pragma unroll 1
+        for (int r = 0; r < kTile; ++r) {
+            const v4i16 a0 = *reinterpret_cast<const v4i16 *>(&gT[i * kGS + r * kTile + 4 * g]);
+            const v4i16 a1 = *reinterpret_cast<const v4i16 *>(&gT[(16 + i) * kGS + r * kTile + 4 * g]);
+            v4i16 bv[CPW];
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            const int tile = wave * TPW + q;
-            if (tile >= NT) continue;
-            const int rt = tile / NJT, jt = tile % NJT;
-            const int n = rt * 16 + i;                 // A row (output channel)
-            const int col = jt * 16 + i;               // B column (tap, c)
-            const bool colok = col < NCOL;
-            const int tap = colok ? col / CIN : 0, c = colok ? col % CIN : 0;
-            const int dx = d * (tap % 3 - 1);
-            const int off = (tap / 3) * bspan + d + dx;  // band of the tap row, then the shift in the band
-            const unsigned tbit = colok ? 1u << tap : 0u;
-            const int base = c * span + off;
-            for (int k0 = 0; k0 < kChunk; k0 += 16) {
-                const v4i16 a = *reinterpret_cast<const v4i16 *>(&gT[n * GS + k0 + 4 * g]);
-                const int pl0 = k0 + 4 * g;
-                // the valid-tap masks of the 4 pixels, one 8-byte read
-                const uint2 mw = *reinterpret_cast<const uint2 *>(&vm[pl0]);
-                const unsigned m4[4] = {mw.x & 0xffffu, mw.x >> 16, mw.y & 0xffffu, mw.y >> 16};
-                // 4 consecutive pixels of channel c shifted by the tap: with 32 input
-                // channels all lanes of a column tile share the tap, so the alignment
-                // (and the read width) is uniform across the wavefront
-                v4i16 raw;
-                if (CIN == 32 && (off & 3) == 0) {
-                    raw = *reinterpret_cast<const v4i16 *>(&xT[base + pl0]);
-                } else if (CIN == 32 && (off & 1) == 0) {
-                    const unsigned lo = *reinterpret_cast<const unsigned *>(&xT[base + pl0]);
-                    const unsigned hi = *reinterpret_cast<const unsigned *>(&xT[base + pl0 + 2]);
-                    raw[0] = static_cast<short>(lo & 0xffffu);
-                    raw[1] = static_cast<short>(lo >> 16);
-                    raw[2] = static_cast<short>(hi & 0xffffu);
-                    raw[3] = static_cast<short>(hi >> 16);
+            for (int cq = 0; cq < CPW; ++cq) {
+                const bf16_t *src = &xT[lbase + bofs[cq] + r * PW];
+                if (CIN == 32) {
+                    const unsigned lo = *reinterpret_cast<const unsigned *>(src);
+                    const unsigned hi = *reinterpret_cast<const unsigned *>(src + 2);
+                    bv[cq][0] = static_cast<short>(lo & 0xffffu);
+                    bv[cq][1] = static_cast<short>(lo >> 16);
+                    bv[cq][2] = static_cast<short>(hi & 0xffffu);
+                    bv[cq][3] = static_cast<short>(hi >> 16);
                 } else {
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) raw[v] = static_cast<short>(xT[base + pl0 + v]);
+                    for (int v = 0; v < 4; ++v) bv[cq][v] = colok_q[cq] ? static_cast<short>(src[v]) : short(0);
                 }
-                v4i16 bv;
+            }
 #pragma unroll
-                for (int v = 0; v < 4; ++v) bv[v] = (m4[v] & tbit) ? raw[v] : short(0);
-                acc[q] = mfma(a, bv, acc[q]);
+            for (int cq = 0; cq < CPW; ++cq) {
+                if (!jok[cq]) continue;  // uniform
+                acc[cq][0] = mfma(a0, bv[cq], acc[cq][0]);
+                acc[cq][1] = mfma(a1, bv[cq], acc[cq][1]);
             }
         }
     }
     float *out = part + static_cast<size_t>(blockIdx.x) * (kCh * NCOL + kCh);
 #pragma unroll
-    for (int q = 0; q < TPW; ++q) {
-        const int tile = wave * TPW + q;
-        if (tile >= NT) continue;
-        const int rt = tile / NJT, jt = tile % NJT;
-        const int col = jt * 16 + i;
-        if (col >= NCOL) continue;
+    for (int cq = 0; cq < CPW; ++cq) {
+        const int col = (wv + 4 * cq) * 16 + i;
+        if (!jok[cq] || col >= NCOL) continue;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int n = rt * 16 + 4 * g + v;
-            out[n * NCOL + col] = acc[q][v];
-        }
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) out[(rt * 16 + 4 * g + v) * NCOL + col] = acc[cq][rt][v];
     }
-    // bias gradient: the 8 threads of each channel, in thread order
+    // bias gradient: channel 8 o + k is summed by the 64 threads with tid % 4 = o, in thread order
     __syncthreads();
-    float *bred = reinterpret_cast<float *>(sm);
-    bred[threadIdx.x] = dbias;
+    float *bred = reinterpret_cast<float *>(sm);  // [8][256]
+#pragma unroll
+    for (int k = 0; k < 8; ++k) bred[k * kThreads + tid] = db[k];
     __syncthreads();
-    if (threadIdx.x < kCh) {
+    if (tid < kCh) {
+        const int o = tid >> 3, k = tid & 7;
         float sb = 0.f;
-        for (int r = 0; r < kThreads / kCh; ++r) sb += bred[threadIdx.x + r * kCh];
-        out[kCh * NCOL + threadIdx.x] = sb;
+        for (int q = 0; q < kThreads / 4; ++q) sb += bred[k * kThreads + 4 * q + o];
+        out[kCh * NCOL + tid] = sb;
     }
 }
 
@@ -388,47 +544,55 @@ __global__ __launch_bounds__(kThreads) void k_reduce(const float *__restrict__ p
 }
 
 // ------------------------------------------------------------------ last layer (32 -> 1), VALU
+// 32 -> 1 last layer (no activation): out[p] = b + sum_tap sum_c W4[tap][c] y3[p + d off(tap)][c].
+// Four lanes per pixel, lane o holding channels 8o .. 8o+7 (one 16-byte load per
+// tap; a wavefront's load covers 16 whole pixels), the four partial sums added
+// across the lanes; a workgroup walks pixel groups of 64 with the weights in
+// registers.
 __global__ __launch_bounds__(kThreads) void k_last_fwd(const bf16_t *__restrict__ y3, const float *__restrict__ W4,
                                                        const float *__restrict__ b4, float *__restrict__ out, int NP,
                                                        int H, int W, int d) {
-    __shared__ float w4s[kW4];
+    __shared__ __align__(16) float w4s[kW4];
     for (int e = threadIdx.x; e < kW4; e += blockDim.x) w4s[e] = W4[e];
     __syncthreads();
-    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gp >= NP) return;
-    const int HW = H * W, p = gp % HW, py = p / W, px = p % W;
-    float s = b4[0];
-    // taps in groups of 3: each tap's 32 channels are four 16-byte loads, all
-    // issued before use; a tap outside the image reads the pixel itself and is
-    // dropped
+    const int ps = threadIdx.x >> 2, o = threadIdx.x & 3;
+    float wr[9][8];
 #pragma unroll
-    for (int t0 = 0; t0 < 9; t0 += 3) {
-        uint4 v[3][4];
-        bool ok[3];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            const int tap = t0 + u, dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-            ok[u] = py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-            const uint4 *src = reinterpret_cast<const uint4 *>(y3 + static_cast<size_t>(ok[u] ? gp + dy * W + dx : gp) * kCh);
-#pragma unroll
-            for (int c4 = 0; c4 < 4; ++c4) v[u][c4] = src[c4];
-        }
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            if (!ok[u]) continue;
-            const float *w = w4s + (t0 + u) * kCh;
-#pragma unroll
-            for (int c4 = 0; c4 < 4; ++c4) {
-                const unsigned q[4] = {v[u][c4].x, v[u][c4].y, v[u][c4].z, v[u][c4].w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int c = c4 * 8 + 2 * e;
-                    s += w[c] * __uint_as_float(q[e] << 16) + w[c + 1] * __uint_as_float(q[e] & 0xffff0000u);
-                }
-            }
-        }
+    for (int tap = 0; tap < 9; ++tap) {
+        const float4 lo = *reinterpret_cast<const float4 *>(&w4s[tap * kCh + 8 * o]);
+        const float4 hi = *reinterpret_cast<const float4 *>(&w4s[tap * kCh + 8 * o + 4]);
+        wr[tap][0] = lo.x; wr[tap][1] = lo.y; wr[tap][2] = lo.z; wr[tap][3] = lo.w;
+        wr[tap][4] = hi.x; wr[tap][5] = hi.y; wr[tap][6] = hi.z; wr[tap][7] = hi.w;
     }
-    out[gp] = s;
+    const float bias = b4[0];
+    const int HW = H * W;
+    const uint4 *yv = reinterpret_cast<const uint4 *>(y3);
+    for (int gp0 = blockIdx.x * 64; gp0 < NP; gp0 += gridDim.x * 64) {
+        const int gp = gp0 + ps;
+        if (gp >= NP) break;
+        const int p = gp % HW, py = p / W, px = p - py * W;
+        uint4 v[9];
+        bool ok[9];
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            ok[tap] = py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
+            v[tap] = yv[static_cast<unsigned>(ok[tap] ? gp + dy * W + dx : gp) * (kCh / 8) + o];
+        }
+        float s = 0.f;
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const unsigned q[4] = {v[tap].x, v[tap].y, v[tap].z, v[tap].w};
+            float t = 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                t += wr[tap][2 * e] * __uint_as_float(q[e] << 16) + wr[tap][2 * e + 1] * __uint_as_float(q[e] & 0xffff0000u);
+            s += ok[tap] ? t : 0.f;
+        }
+        s += __shfl_xor(s, 1, 4);
+        s += __shfl_xor(s, 2, 4);
+        if (o == 0) out[gp] = s + bias;
+    }
 }
 
 // g4 = 2 (out - target) mask / cnt; partial sums of mask (out - target)^2 per block
@@ -452,31 +616,41 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
     if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
 }
 
-// g3 = bf16( (sum_tap W4[tap][c] g4[p - d off(tap)]) * (y3 > 0) )
+// g3 = bf16( (sum_tap W4[tap][c] g4[p - d off(tap)]) * (y3 > 0) ).  Four lanes per
+// pixel (lane o: channels 8o .. 8o+7, one 16-byte mask load and one 16-byte store),
+// weights in registers, a workgroup walks pixel groups of 64.
 __global__ __launch_bounds__(kThreads) void k_last_dgrad(const float *__restrict__ g4, const float *__restrict__ W4,
                                                          const bf16_t *__restrict__ y3, bf16_t *__restrict__ g3,
                                                          int NP, int H, int W, int d) {
-    __shared__ float w4s[kW4];
+    __shared__ __align__(16) float w4s[kW4];
     for (int e = threadIdx.x; e < kW4; e += blockDim.x) w4s[e] = W4[e];
     __syncthreads();
-    const int gp = blockIdx.x * blockDim.x + threadIdx.x;
-    if (gp >= NP) return;
-    const int HW = H * W, p = gp % HW, py = p / W, px = p % W;
-    float gn[9];
+    const int ps = threadIdx.x >> 2, o = threadIdx.x & 3;
+    float wr[9][8];
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
-        const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-        // pixel gp feeds output gp - d off through tap
-        const bool ok = py - dy >= 0 && py - dy < H && px - dx >= 0 && px - dx < W;
-        const float gvl = g4[ok ? gp - dy * W - dx : gp];
-        gn[tap] = ok ? gvl : 0.f;
+        const float4 lo = *reinterpret_cast<const float4 *>(&w4s[tap * kCh + 8 * o]);
+        const float4 hi = *reinterpret_cast<const float4 *>(&w4s[tap * kCh + 8 * o + 4]);
+        wr[tap][0] = lo.x; wr[tap][1] = lo.y; wr[tap][2] = lo.z; wr[tap][3] = lo.w;
+        wr[tap][4] = hi.x; wr[tap][5] = hi.y; wr[tap][6] = hi.z; wr[tap][7] = hi.w;
     }
-    // the pixel's 32 stored activations (ReLU mask) and gradients as four 16-byte words
-    const uint4 *ysrc = reinterpret_cast<const uint4 *>(y3 + static_cast<size_t>(gp) * kCh);
-    uint4 *gdst = reinterpret_cast<uint4 *>(g3 + static_cast<size_t>(gp) * kCh);
+    const int HW = H * W;
+    const uint4 *ysrc = reinterpret_cast<const uint4 *>(y3);
+    uint4 *gdst = reinterpret_cast<uint4 *>(g3);
+    for (int gp0 = blockIdx.x * 64; gp0 < NP; gp0 += gridDim.x * 64) {
+        const int gp = gp0 + ps;
+        if (gp >= NP) break;
+        const int p = gp % HW, py = p / W, px = p - py * W;
+        float gn[9];
 #pragma unroll
-    for (int c4 = 0; c4 < 4; ++c4) {
-        const uint4 yv = ysrc[c4];
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            // pixel gp feeds output gp - d off through tap
+            const bool ok = py - dy >= 0 && py - dy < H && px - dx >= 0 && px - dx < W;
+            const float gvl = g4[ok ? gp - dy * W - dx : gp];
+            gn[tap] = ok ? gvl : 0.f;
+        }
+        const uint4 yv = ysrc[static_cast<unsigned>(gp) * (kCh / 8) + o];
         const unsigned yq[4] = {yv.x, yv.y, yv.z, yv.w};
         unsigned oq[4];
 #pragma unroll
@@ -484,69 +658,87 @@ __global__ __launch_bounds__(kThreads) void k_last_dgrad(const float *__restrict
             unsigned packed = 0;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                const int c = c4 * 8 + 2 * e + h;
                 float s_ = 0.f;
 #pragma unroll
-                for (int tap = 0; tap < 9; ++tap) s_ += w4s[tap * kCh + c] * gn[tap];
+                for (int tap = 0; tap < 9; ++tap) s_ += wr[tap][2 * e + h] * gn[tap];
                 const bf16_t yb = static_cast<bf16_t>(h == 0 ? (yq[e] & 0xffffu) : (yq[e] >> 16));
                 packed |= static_cast<unsigned>(f2bf(bf_pos(yb) ? s_ : 0.f)) << (16 * h);
             }
             oq[e] = packed;
         }
-        gdst[c4] = make_uint4(oq[0], oq[1], oq[2], oq[3]);
+        gdst[static_cast<unsigned>(gp) * (kCh / 8) + o] = make_uint4(oq[0], oq[1], oq[2], oq[3]);
     }
 }
 
 // part[blk][tap*32 + c] = sum over the block's pixels of g4[p] y3[p + d off][c]; part[blk][288] = sum g4.
-// Thread t: channel pair cp = t % 16 (channels 2cp, 2cp+1) of the pixels p = t / 16 (mod 16) of
-// every chunk: 18 accumulators (9 taps x 2 channels); the 16 pixel groups are summed in LDS
-// at the end (fixed order).  A pixel row of y3 is read by 16 consecutive threads (64 bytes).
+// Four lanes per pixel (lane o: channels 8o .. 8o+7, one 16-byte load per tap),
+// 72 accumulators per lane; a workgroup walks pixel groups of 64.  At the end
+// the 16 pixel lanes of a wavefront are summed by a butterfly, then the four
+// wavefronts in LDS (fixed order).
 __global__ __launch_bounds__(kThreads) void k_last_wgrad(const float *__restrict__ g4, const bf16_t *__restrict__ y3,
                                                          float *__restrict__ part, int NP, int H, int W, int d) {
-    const int cp = threadIdx.x & 15, pg = threadIdx.x >> 4;
+    const int ps = threadIdx.x >> 2, o = threadIdx.x & 3;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int HW = H * W;
-    float acc[9][2];
+    const uint4 *yv = reinterpret_cast<const uint4 *>(y3);
+    float acc[9][8];
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) acc[tap][0] = acc[tap][1] = 0.f;
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[tap][k] = 0.f;
     float gsum = 0.f;
-    const int nchunks = (NP + kChunk - 1) / kChunk;
-    for (int ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
-        const int c0 = ch * kChunk;
-        for (int pl = pg; pl < kChunk; pl += 16) {
-            const int gp = c0 + pl;
-            if (gp >= NP) break;
-            const float gv = g4[gp];
-            if (cp == 0) gsum += gv;
-            const int p = gp % HW, py = p / W, px = p % W;
-            unsigned v[9];
+    for (int gp0 = blockIdx.x * 64; gp0 < NP; gp0 += gridDim.x * 64) {
+        const int gp = gp0 + ps;
+        if (gp >= NP) break;
+        const float gv = g4[gp];
+        gsum += gv;
+        const int p = gp % HW, py = p / W, px = p - py * W;
+        uint4 v[9];
+        bool ok[9];
 #pragma unroll
-            for (int tap = 0; tap < 9; ++tap) {
-                const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-                const bool ok = py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-                const unsigned w = *reinterpret_cast<const unsigned *>(
-                    y3 + static_cast<size_t>(ok ? gp + dy * W + dx : gp) * kCh + 2 * cp);
-                v[tap] = ok ? w : 0u;
-            }
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
+            ok[tap] = py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
+            v[tap] = yv[static_cast<unsigned>(ok[tap] ? gp + dy * W + dx : gp) * (kCh / 8) + o];
+        }
 #pragma unroll
-            for (int tap = 0; tap < 9; ++tap) {
-                acc[tap][0] += gv * __uint_as_float(v[tap] << 16);
-                acc[tap][1] += gv * __uint_as_float(v[tap] & 0xffff0000u);
+        for (int tap = 0; tap < 9; ++tap) {
+            const float gt = ok[tap] ? gv : 0.f;
+            const unsigned q[4] = {v[tap].x, v[tap].y, v[tap].z, v[tap].w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                acc[tap][2 * e] += gt * __uint_as_float(q[e] << 16);
+                acc[tap][2 * e + 1] += gt * __uint_as_float(q[e] & 0xffff0000u);
             }
         }
     }
-    __shared__ float red[16][kW4 + 1];
+    // butterfly over the 16 pixel lanes of each octet (lane bits 2..5)
 #pragma unroll
-    for (int tap = 0; tap < 9; ++tap) {
-        red[pg][tap * kCh + 2 * cp] = acc[tap][0];
-        red[pg][tap * kCh + 2 * cp + 1] = acc[tap][1];
+    for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            float a = acc[tap][k];
+            a += __shfl_xor(a, 4);
+            a += __shfl_xor(a, 8);
+            a += __shfl_xor(a, 16);
+            a += __shfl_xor(a, 32);
+            acc[tap][k] = a;
+        }
+    gsum += __shfl_xor(gsum, 4);
+    gsum += __shfl_xor(gsum, 8);
+    gsum += __shfl_xor(gsum, 16);
+    gsum += __shfl_xor(gsum, 32);
+    __shared__ float red[4][kW4 + 1];
+    if (lane < 4) {
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) red[wave][tap * kCh + 8 * lane + k] = acc[tap][k];
+        if (lane == 0) red[wave][kW4] = gsum;
     }
-    if (cp == 0) red[pg][kW4] = gsum;
     __syncthreads();
-    for (int el = threadIdx.x; el <= kW4; el += kThreads) {
-        float sum = 0.f;
-        for (int q = 0; q < 16; ++q) sum += red[q][el];
-        part[static_cast<size_t>(blockIdx.x) * (kW4 + 1) + el] = sum;
-    }
+    for (int el = threadIdx.x; el <= kW4; el += kThreads)
+        part[static_cast<size_t>(blockIdx.x) * (kW4 + 1) + el] = ((red[0][el] + red[1][el]) + red[2][el]) + red[3][el];
 }
 
 // ------------------------------------------------------------------ parameters
@@ -659,6 +851,7 @@ struct adrnn_ctx {
     float *out = nullptr, *g4 = nullptr, *part = nullptr, *lmu = nullptr;
     double *lpart = nullptr, *fn = nullptr, *dlmu = nullptr;
     int wblocks = 512;
+    int n_cu = 256;  // compute units of the device (set at creation)
     int64_t step = 0;
     std::string err;
 };
@@ -684,10 +877,6 @@ T *nn_alloc(adrnn_ctx *c, size_t n) {
     return static_cast<T *>(p);
 }
 
-size_t wgrad_lds(int cin, int d) {
-    const int span = 3 * ((kChunk + 2 * d + 3) & ~3);
-    return sizeof(bf16_t) * (kCh * (kChunk + 4) + static_cast<size_t>(cin) * span) + sizeof(short) * 2 * kChunk;
-}
 
 void convert(adrnn_ctx *c) {
     hipLaunchKernelGGL(k_convert, dim3((kW2 + 255) / 256), dim3(256), 0, c->st, c->P, c->w1, c->w2, c->w3, c->w2t,
@@ -695,20 +884,40 @@ void convert(adrnn_ctx *c) {
     NNCHK(hipGetLastError());
 }
 
+// last-layer kernels: 64 pixels per workgroup step, at most 1024 workgroups
+int last_grid(int NP) { return std::min(1024, std::max(1, (NP + 63) / 64)); }
+static_assert(1024 * (kW4 + 1) <= 512 * (kCh * 9 * kCh + kCh), "last-layer partials exceed the partial buffer");
+
 int conv_grid(int NP) { return std::min(4096, std::max(1, (NP + 16 * 4 * 8 - 1) / (16 * 4 * 8))); }
+
+// 32 -> 32 convolution of B images (tiled kernel)
+template <int EPI, int XS>
+void conv32t_launch(adrnn_ctx *c, int B, const bf16_t *x, const bf16_t *w, const float *bias, const bf16_t *ymask,
+                    bf16_t *y, int d) {
+    const size_t lds = conv_tiled_lds(d);
+    const void *fn = reinterpret_cast<const void *>(&k_conv32t<EPI, XS>);
+    if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    // one workgroup per resident slot (each walks its tiles)
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
+    const int ntiles = B * conv_tiles(c->H, c->W);
+    const int nb = std::min(ntiles, per_cu * c->n_cu);
+    hipLaunchKernelGGL((k_conv32t<EPI, XS>), dim3(nb), dim3(kThreads), lds, c->st, x, w, bias, ymask, y, c->H, c->W,
+                       d, ntiles);
+    NNCHK(hipGetLastError());
+}
 
 // 32 -> 32 convolution of B images (tiled kernel)
 template <int EPI>
 void conv32t(adrnn_ctx *c, int B, const bf16_t *x, const bf16_t *w, const float *bias, const bf16_t *ymask, bf16_t *y,
              int d) {
     if (d < 1 || d > kMaxDilT) throw NNError{ADR_EINVAL, "tiled convolution: dilation out of range"};
-    const size_t lds = conv_tiled_lds(d);
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_conv32t<EPI>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    hipLaunchKernelGGL((k_conv32t<EPI>), dim3(B * conv_tiles(c->H, c->W)), dim3(kThreads), lds, c->st, x, w, bias,
-                       ymask, y, c->H, c->W, d);
-    NNCHK(hipGetLastError());
+    switch (d) {  // patch loads per thread: ceil((16 + 2d)^2 * 4 / 256)
+        case 1: conv32t_launch<EPI, 6>(c, B, x, w, bias, ymask, y, d); break;
+        case 2: conv32t_launch<EPI, 7>(c, B, x, w, bias, ymask, y, d); break;
+        case 3: conv32t_launch<EPI, 8>(c, B, x, w, bias, ymask, y, d); break;
+        default: conv32t_launch<EPI, kXStage>(c, B, x, w, bias, ymask, y, d); break;
+    }
 }
 
 void forward(adrnn_ctx *c, int B, const bf16_t *x0, float *out) {
@@ -718,20 +927,22 @@ void forward(adrnn_ctx *c, int B, const bf16_t *x0, float *out) {
     conv32t<0>(c, B, c->y1, c->w2, c->P + ob2, nullptr, c->y2, kDil[1]);
     conv32t<0>(c, B, c->y2, c->w3, c->P + ob3, nullptr, c->y3, kDil[2]);
     NNCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_last_fwd, dim3((NP + 255) / 256), dim3(256), 0, c->st, c->y3, c->w4, c->P + ob4, out, NP,
+    hipLaunchKernelGGL(k_last_fwd, dim3(last_grid(NP)), dim3(kThreads), 0, c->st, c->y3, c->w4, c->P + ob4, out, NP,
                        c->H, c->W, kDil[3]);
     NNCHK(hipGetLastError());
 }
 
 template <int CIN>
 void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, int d, float *dst) {
+    if (d < 1 || d > kMaxDilT || (CIN == 32 && d % 2 != 0))
+        throw NNError{ADR_EINVAL, "weight gradient: dilation out of range (32 input channels: even, <= 4)"};
     const size_t lds = wgrad_lds(CIN, d);
     if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgrad32<CIN>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgradt<CIN>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-    const int nchunks = (NP + kChunk - 1) / kChunk;
-    const int nb = std::min(c->wblocks, nchunks);
-    hipLaunchKernelGGL((k_wgrad32<CIN>), dim3(nb), dim3(kThreads), lds, c->st, g, x, c->part, NP, c->H, c->W, d);
+    const int ntiles = (NP / (c->H * c->W)) * conv_tiles(c->H, c->W);
+    const int nb = std::min(c->wblocks, ntiles);
+    hipLaunchKernelGGL((k_wgradt<CIN>), dim3(nb), dim3(kThreads), lds, c->st, g, x, c->part, ntiles, c->H, c->W, d);
     NNCHK(hipGetLastError());
     const int len = kCh * 9 * CIN + kCh;
     hipLaunchKernelGGL(k_reduce, dim3((len + 31) / 32), dim3(kThreads), 0, c->st, c->part, nb, len, dst);
@@ -751,11 +962,12 @@ double grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint
     const int lb = (NP + 255) / 256;
     hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, c->st, c->out, tgt, mask, c->g4, c->lpart, NP, HW, inv_cnt);
     // layer 4
-    const int nchunks = (NP + kChunk - 1) / kChunk, nb = std::min(c->wblocks, nchunks);
+    // partials of up to 1024 workgroups (289 floats each) fit in the 32 -> 32 layers' buffer
+    const int nb = last_grid(NP);
     hipLaunchKernelGGL(k_last_wgrad, dim3(nb), dim3(kThreads), 0, c->st, c->g4, c->y3, c->part, NP, c->H, c->W,
                        kDil[3]);
     hipLaunchKernelGGL(k_reduce, dim3((kW4 + 1 + 31) / 32), dim3(kThreads), 0, c->st, c->part, nb, kW4 + 1, G + oW4);
-    hipLaunchKernelGGL(k_last_dgrad, dim3(lb), dim3(256), 0, c->st, c->g4, c->w4, c->y3, c->ga, NP, c->H, c->W,
+    hipLaunchKernelGGL(k_last_dgrad, dim3(last_grid(NP)), dim3(kThreads), 0, c->st, c->g4, c->w4, c->y3, c->ga, NP, c->H, c->W,
                        kDil[3]);
     NNCHK(hipGetLastError());
     // layer 3: g3 = ga
@@ -796,6 +1008,12 @@ adr_status adrnn_create(int32_t H, int32_t W, int32_t max_batch, void *stream, a
         c->W = W;
         c->maxB = max_batch;
         c->st = static_cast<hipStream_t>(stream);
+        {
+            int dev = 0, ncu = 0;
+            if (hipGetDevice(&dev) == hipSuccess &&
+                hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+                c->n_cu = ncu;
+        }
         const size_t NP = static_cast<size_t>(max_batch) * H * W;
         if (NP * kCh > (size_t(1) << 31)) throw NNError{ADR_EINVAL, "batch too large"};
         c->P = nn_alloc<float>(c, kParams);
