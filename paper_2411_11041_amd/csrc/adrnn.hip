@@ -125,7 +125,6 @@ constexpr int kCP = 36;            // staged channels per pixel (32 + pad)
 constexpr int kWS = 9 * kCh + 4;   // staged weight row (one output channel: 9 taps x 32 inputs + pad)
 constexpr int kMaxDilT = 4;        // largest dilation the tiled kernels stage (patch (16 + 2*4)^2)
 constexpr int kWStage = (kCh * 36 + kThreads - 1) / kThreads;
-constexpr int kXStage = ((kTile + 2 * kMaxDilT) * (kTile + 2 * kMaxDilT) * 4 + kThreads - 1) / kThreads;
 
 __host__ __device__ inline int conv_tiles(int H, int W) { return ((H + kTile - 1) / kTile) * ((W + kTile - 1) / kTile); }
 __host__ __device__ inline size_t conv_tiled_lds(int d) {
@@ -136,9 +135,10 @@ __host__ __device__ inline size_t conv_tiled_lds(int d) {
 // the patch loads of tile t (16 bytes each, issued without waiting): a pixel
 // outside the image reads the image's first pixel; bit u of *inm marks load u
 // as inside (the LDS store writes zeros for the others)
-template <int XS>
+template <int D, int XS>
 __device__ __forceinline__ void conv_patch_load(const bf16_t *__restrict__ x, int t, int tpi, int tw, int H, int W,
-                                                int d, int P, uint4 (&xv)[XS], unsigned &inm) {
+                                                uint4 (&xv)[XS], unsigned &inm) {
+    constexpr int d = D, P = kTile + 2 * D;
     const int b = t / tpi, tt = t - b * tpi;
     const int ty = tt / tw, tx = tt - ty * tw;
     const int y0 = ty * kTile, x0 = tx * kTile;
@@ -159,16 +159,18 @@ __device__ __forceinline__ void conv_patch_load(const bf16_t *__restrict__ x, in
     inm = m;
 }
 
-// XS: patch loads per thread, ceil((16 + 2d)^2 * 4 / 256) (the prefetch registers)
-template <int EPI, int XS>
+// patch loads per thread at dilation d: ceil((16 + 2d)^2 * 4 / 256) (the prefetch registers)
+__host__ __device__ constexpr int conv_xs(int d) { return ((kTile + 2 * d) * (kTile + 2 * d) * 4 + kThreads - 1) / kThreads; }
+
+template <int EPI, int D>
 __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__ x, const bf16_t *__restrict__ Wg,
                                                       const float *__restrict__ bias,
                                                       const bf16_t *__restrict__ ymask, bf16_t *__restrict__ y,
-                                                      int H, int W, int d, int ntiles) {
+                                                      int H, int W, int ntiles) {
+    constexpr int d = D, P = kTile + 2 * D, XS = conv_xs(D);
     extern __shared__ __align__(16) unsigned char sm[];
     bf16_t *Ws = reinterpret_cast<bf16_t *>(sm);  // [32][kWS]
     bf16_t *Xs = Ws + kCh * kWS;                  // [P*P][kCP]
-    const int P = kTile + 2 * d;
     const int tw = (W + kTile - 1) / kTile, tpi = conv_tiles(H, W);
     const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
     // weights, once (32 rows of 288 entries, 16 bytes per load)
@@ -196,7 +198,7 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
     uint4 xv[XS];
     unsigned inm = 0;
     int t = blockIdx.x;
-    if (t < ntiles) conv_patch_load<XS>(x, t, tpi, tw, H, W, d, P, xv, inm);
+    if (t < ntiles) conv_patch_load<D, XS>(x, t, tpi, tw, H, W, xv, inm);
     for (; t < ntiles; t += gridDim.x) {
         __syncthreads();  // the previous tile's products are done with Xs
 #pragma unroll
@@ -211,11 +213,11 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
         }
         __syncthreads();
         if (t + static_cast<int>(gridDim.x) < ntiles)  // in flight during the products
-            conv_patch_load<XS>(x, t + gridDim.x, tpi, tw, H, W, d, P, xv, inm);
+            conv_patch_load<D, XS>(x, t + gridDim.x, tpi, tw, H, W, xv, inm);
         v4f32 acc[4][2];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc[mt][0] = acc[mt][1] = v4f32{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
+#pragma unroll 3
         for (int tap = 0; tap < 9; ++tap) {
             const int oy = d + d * (tap / 3 - 1), ox = d + d * (tap % 3 - 1);
 #pragma unroll
@@ -272,19 +274,17 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
 // GEMM view: M = 32 output channels (2 row tiles), N = 9 CIN (tap, c)
 // columns, K = the tile's pixels, one tile row (16 pixels) per MFMA.
 constexpr int kGS = kTile * kTile + 4;  // gT row stride: 16 rows of one fragment read fall on distinct bank pairs
-__host__ __device__ inline int wg_pw(int d) { return (kTile + 2 * d + 3) & ~3; }  // patch row (multiple of 4)
-__host__ __device__ inline int wg_cs(int d) {  // patch channel stride, = 4 (mod 64) like kGS
+__host__ __device__ constexpr int wg_pw(int d) { return (kTile + 2 * d + 3) & ~3; }  // patch row (multiple of 4)
+__host__ __device__ constexpr int wg_cs(int d) {  // patch channel stride, = 4 (mod 64) like kGS
     const int raw = (kTile + 2 * d) * wg_pw(d);
     return raw + (((4 - raw) % 64) + 64) % 64;
 }
 __host__ __device__ inline size_t wgrad_lds(int cin, int d) {
     return sizeof(bf16_t) * (static_cast<size_t>(kCh) * kGS + static_cast<size_t>(cin) * wg_cs(d));
 }
-// patch items per thread: CIN 32: (row, pixel quad, channel octet); CIN 4: (row, pixel quad)
-template <int CIN>
-constexpr int wg_xitems() {
-    return CIN == 32 ? ((kTile + 2 * kMaxDilT) * ((kTile + 2 * kMaxDilT + 3) / 4) * 4 + kThreads - 1) / kThreads
-                     : ((kTile + 2 * kMaxDilT) * ((kTile + 2 * kMaxDilT + 3) / 4) + kThreads - 1) / kThreads;
+// patch items at dilation d: CIN 32: (row, pixel quad, channel octet); CIN 4: (row, pixel quad)
+__host__ __device__ constexpr int wg_nxi(int cin, int d) {
+    return (kTile + 2 * d) * (wg_pw(d) / 4) * (cin == 32 ? 4 : 1);
 }
 
 __device__ __forceinline__ unsigned word_of(const uint4 &v, int w) {
@@ -303,10 +303,11 @@ __device__ __forceinline__ void tr_pair(unsigned p0, unsigned p1, unsigned p2, u
 // waiting: out-of-image pixels read the image's first pixel and are marked in
 // *okm (bit v: g pixel v; bit 4 + 4u + v: patch item u, pixel v), zeroed at
 // the LDS store.  Offsets are 32-bit (an activation buffer holds < 2^31 entries).
-template <int CIN, int XI, int XU>
+template <int CIN, int D, int XI, int XU>
 __device__ __forceinline__ void wg_load(const bf16_t *__restrict__ gsrc, const bf16_t *__restrict__ x, int t,
-                                        int tpi, int tw, int H, int W, int d, int P, int QW, int nxi, int tid,
-                                        uint4 (&gv)[4], uint4 (&xv)[XI][XU], unsigned &okm) {
+                                        int tpi, int tw, int H, int W, int tid, uint4 (&gv)[4], uint4 (&xv)[XI][XU],
+                                        unsigned &okm) {
+    constexpr int d = D, P = kTile + 2 * D, QW = wg_pw(D) / 4, nxi = wg_nxi(CIN, D);
     const int b = t / tpi, tt = t - b * tpi;
     const int ty = tt / tw, tx = tt - ty * tw;
     const int y0 = ty * kTile, x0 = tx * kTile;
@@ -348,20 +349,21 @@ __device__ __forceinline__ void wg_load(const bf16_t *__restrict__ gsrc, const b
     okm = m;
 }
 
-template <int CIN>
+template <int CIN, int D>
 __global__ __launch_bounds__(kThreads) void k_wgradt(const bf16_t *__restrict__ gsrc, const bf16_t *__restrict__ x,
-                                                     float *__restrict__ part, int ntiles, int H, int W, int d) {
+                                                     float *__restrict__ part, int ntiles, int H, int W) {
     constexpr int NCOL = 9 * CIN;          // (tap, c) columns
     constexpr int NJT = (NCOL + 15) / 16;  // column tiles
     constexpr int CPW = (NJT + 3) / 4;     // column tiles per wave
-    constexpr int XI = wg_xitems<CIN>();
+    constexpr int d = D;
+    constexpr int XI = (wg_nxi(CIN, D) + kThreads - 1) / kThreads;
     constexpr int XU = CIN == 32 ? 4 : 2;  // 16-byte loads per patch item
     extern __shared__ __align__(16) unsigned char sm[];
     bf16_t *gT = reinterpret_cast<bf16_t *>(sm);  // [32][kGS]
     bf16_t *xT = gT + kCh * kGS;                  // [CIN][CS]: row py at py * PW
-    const int P = kTile + 2 * d, PW = wg_pw(d), CS = wg_cs(d);
-    const int QW = PW / 4;                        // pixel quads per patch row
-    const int nxi = CIN == 32 ? P * QW * 4 : P * QW;
+    constexpr int PW = wg_pw(D), CS = wg_cs(D);
+    constexpr int QW = PW / 4;                    // pixel quads per patch row
+    constexpr int nxi = wg_nxi(CIN, D);
     const int tw = (W + kTile - 1) / kTile, tpi = conv_tiles(H, W);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int i = lane & 15, g = lane >> 4;
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(kThreads) void k_wgradt(const bf16_t *__restrict__ 
     const int lbase = (CIN == 32 ? i * CS : 0) + 4 * g;
 
     int t = blockIdx.x;
-    if (t < ntiles) wg_load<CIN, XI, XU>(gsrc, x, t, tpi, tw, H, W, d, P, QW, nxi, tid, gv, xv, okm);
+    if (t < ntiles) wg_load<CIN, D, XI, XU>(gsrc, x, t, tpi, tw, H, W, tid, gv, xv, okm);
     for (; t < ntiles; t += gridDim.x) {
         __syncthreads();  // the previous tile's products are done with the LDS
         // g: 8 channels x 4 pixels -> 8 rows of gT (and the bias gradient)
@@ -459,7 +461,7 @@ __global__ __launch_bounds__(kThreads) void k_wgradt(const bf16_t *__restrict__ 
         }
         __syncthreads();
         if (t + static_cast<int>(gridDim.x) < ntiles)  // in flight during the products
-            wg_load<CIN, XI, XU>(gsrc, x, t + gridDim.x, tpi, tw, H, W, d, P, QW, nxi, tid, gv, xv, okm);
+            wg_load<CIN, D, XI, XU>(gsrc, x, t + gridDim.x, tpi, tw, H, W, tid, gv, xv, okm);
         // all fragment reads of a tile row are issued before its products: the
         // read form is the same for every tile (CIN 32: two 4-byte halves, the
         // tap shift d + dx being even; CIN 4: four 2-byte reads)
@@ -891,19 +893,19 @@ static_assert(1024 * (kW4 + 1) <= 512 * (kCh * 9 * kCh + kCh), "last-layer parti
 int conv_grid(int NP) { return std::min(4096, std::max(1, (NP + 16 * 4 * 8 - 1) / (16 * 4 * 8))); }
 
 // 32 -> 32 convolution of B images (tiled kernel)
-template <int EPI, int XS>
+template <int EPI, int D>
 void conv32t_launch(adrnn_ctx *c, int B, const bf16_t *x, const bf16_t *w, const float *bias, const bf16_t *ymask,
-                    bf16_t *y, int d) {
-    const size_t lds = conv_tiled_lds(d);
-    const void *fn = reinterpret_cast<const void *>(&k_conv32t<EPI, XS>);
+                    bf16_t *y) {
+    const size_t lds = conv_tiled_lds(D);
+    const void *fn = reinterpret_cast<const void *>(&k_conv32t<EPI, D>);
     if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     // one workgroup per resident slot (each walks its tiles)
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, lds) != hipSuccess || per_cu < 1) per_cu = 1;
     const int ntiles = B * conv_tiles(c->H, c->W);
     const int nb = std::min(ntiles, per_cu * c->n_cu);
-    hipLaunchKernelGGL((k_conv32t<EPI, XS>), dim3(nb), dim3(kThreads), lds, c->st, x, w, bias, ymask, y, c->H, c->W,
-                       d, ntiles);
+    hipLaunchKernelGGL((k_conv32t<EPI, D>), dim3(nb), dim3(kThreads), lds, c->st, x, w, bias, ymask, y, c->H, c->W,
+                       ntiles);
     NNCHK(hipGetLastError());
 }
 
@@ -912,11 +914,11 @@ template <int EPI>
 void conv32t(adrnn_ctx *c, int B, const bf16_t *x, const bf16_t *w, const float *bias, const bf16_t *ymask, bf16_t *y,
              int d) {
     if (d < 1 || d > kMaxDilT) throw NNError{ADR_EINVAL, "tiled convolution: dilation out of range"};
-    switch (d) {  // patch loads per thread: ceil((16 + 2d)^2 * 4 / 256)
-        case 1: conv32t_launch<EPI, 6>(c, B, x, w, bias, ymask, y, d); break;
-        case 2: conv32t_launch<EPI, 7>(c, B, x, w, bias, ymask, y, d); break;
-        case 3: conv32t_launch<EPI, 8>(c, B, x, w, bias, ymask, y, d); break;
-        default: conv32t_launch<EPI, kXStage>(c, B, x, w, bias, ymask, y, d); break;
+    switch (d) {
+        case 1: conv32t_launch<EPI, 1>(c, B, x, w, bias, ymask, y); break;
+        case 2: conv32t_launch<EPI, 2>(c, B, x, w, bias, ymask, y); break;
+        case 3: conv32t_launch<EPI, 3>(c, B, x, w, bias, ymask, y); break;
+        default: conv32t_launch<EPI, 4>(c, B, x, w, bias, ymask, y); break;
     }
 }
 
@@ -932,18 +934,36 @@ void forward(adrnn_ctx *c, int B, const bf16_t *x0, float *out) {
     NNCHK(hipGetLastError());
 }
 
-template <int CIN>
-void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, int d, float *dst) {
-    if (d < 1 || d > kMaxDilT || (CIN == 32 && d % 2 != 0))
-        throw NNError{ADR_EINVAL, "weight gradient: dilation out of range (32 input channels: even, <= 4)"};
-    const size_t lds = wgrad_lds(CIN, d);
+template <int CIN, int D>
+int wgrad_launch(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP) {
+    const size_t lds = wgrad_lds(CIN, D);
     if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgradt<CIN>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_wgradt<CIN, D>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     const int ntiles = (NP / (c->H * c->W)) * conv_tiles(c->H, c->W);
     const int nb = std::min(c->wblocks, ntiles);
-    hipLaunchKernelGGL((k_wgradt<CIN>), dim3(nb), dim3(kThreads), lds, c->st, g, x, c->part, ntiles, c->H, c->W, d);
+    hipLaunchKernelGGL((k_wgradt<CIN, D>), dim3(nb), dim3(kThreads), lds, c->st, g, x, c->part, ntiles, c->H, c->W);
     NNCHK(hipGetLastError());
+    return nb;
+}
+
+template <int CIN>
+void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, int d, float *dst) {
+    int nb = 0;
+    if constexpr (CIN == 32) {
+        if (d == 2) nb = wgrad_launch<CIN, 2>(c, g, x, NP);
+        else if (d == 4) nb = wgrad_launch<CIN, 4>(c, g, x, NP);
+    } else {
+        switch (d) {
+            case 1: nb = wgrad_launch<CIN, 1>(c, g, x, NP); break;
+            case 2: nb = wgrad_launch<CIN, 2>(c, g, x, NP); break;
+            case 3: nb = wgrad_launch<CIN, 3>(c, g, x, NP); break;
+            case 4: nb = wgrad_launch<CIN, 4>(c, g, x, NP); break;
+            default: break;
+        }
+    }
+    if (nb == 0)
+        throw NNError{ADR_EINVAL, "weight gradient: dilation out of range (32 input channels: 2 or 4; 4 channels: 1..4)"};
     const int len = kCh * 9 * CIN + kCh;
     hipLaunchKernelGGL(k_reduce, dim3((len + 31) / 32), dim3(kThreads), 0, c->st, c->part, nb, len, dst);
     NNCHK(hipGetLastError());
