@@ -214,6 +214,23 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
         __syncthreads();
         if (t + static_cast<int>(gridDim.x) < ntiles)  // in flight during the products
             conv_patch_load<D, XS>(x, t + gridDim.x, tpi, tw, H, W, xv, inm);
+        const int b = t / tpi, tt = t - b * tpi;
+        const int ty = tt / tw, tx = tt - ty * tw;
+        const int y0 = ty * kTile, x0 = tx * kTile;
+        // EPI 1: the ReLU mask pairs of this lane's outputs, loaded before the products
+        unsigned mk[4][4];
+        if constexpr (EPI == 1) {
+            const unsigned *mw = reinterpret_cast<const unsigned *>(ymask);
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int gy = y0 + wave * 4 + mt, gx = x0 + 4 * g + v;
+                    const bool in = gy < H && gx < W;
+                    const unsigned po = (static_cast<unsigned>(b) * H + (in ? gy : 0)) * W + (in ? gx : 0);
+                    mk[mt][v] = mw[po * (kCh / 2) + i];
+                }
+        }
         v4f32 acc[4][2];
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) acc[mt][0] = acc[mt][1] = v4f32{0.f, 0.f, 0.f, 0.f};
@@ -234,11 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
                 }
             }
         }
-        const int b = t / tpi, tt = t - b * tpi;
-        const int ty = tt / tw, tx = tt - ty * tw;
-        const int y0 = ty * kTile, x0 = tx * kTile;
         unsigned *yw = reinterpret_cast<unsigned *>(y);
-        const unsigned *mw = reinterpret_cast<const unsigned *>(ymask);
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const int gy = y0 + wave * 4 + mt;
@@ -252,9 +265,8 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
                     z0 = fmaxf(z0 + bias0, 0.f);
                     z1 = fmaxf(z1 + bias1, 0.f);
                 } else {
-                    const unsigned mk = mw[po * (kCh / 2) + i];
-                    z0 = bf_pos(static_cast<bf16_t>(mk & 0xffffu)) ? z0 : 0.f;
-                    z1 = bf_pos(static_cast<bf16_t>(mk >> 16)) ? z1 : 0.f;
+                    z0 = bf_pos(static_cast<bf16_t>(mk[mt][v] & 0xffffu)) ? z0 : 0.f;
+                    z1 = bf_pos(static_cast<bf16_t>(mk[mt][v] >> 16)) ? z1 : 0.f;
                 }
                 yw[po * (kCh / 2) + i] = static_cast<unsigned>(f2bf(z0)) | (static_cast<unsigned>(f2bf(z1)) << 16);
             }
