@@ -306,3 +306,41 @@ def test_batched_fp32_lines_match_oracle_fixed_points():
         Ui, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-12)
         assert rel_l2(U[off[i]:off[i + 1]], Ui) < 1e-5, i
     s.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_compaction_matches_single_solves(precision):
+    """Instances of a batch converge at different sweeps, so the eager solve
+    shrinks its launches to the unfinished instances after each check.  Every
+    instance's arithmetic is its own, so each must equal, bitwise and in sweep
+    count, the same instance solved alone (no compaction) and the batch replayed
+    from a captured graph (full launches)."""
+    print(f"[case] batch compaction vs single solves ({precision})", flush=True)
+    probs = [W.c1(33), W.c2(65), W.c4_instance(2, n_max=100), W.c4_instance(5, n_max=140)]
+    kw = dict(precision=precision, theta=1.0, dt=0.05)
+    if precision == "fp32":
+        kw["fp32_sweeps"] = 3
+    tol = 1e-9
+    batch = solver(probs, **kw)
+    off = batch.layout()
+    ub = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    it_b, rel_b, st = batch.split_iterate(ub, 2000, tol)
+    torch.cuda.synchronize()
+    assert st == 0 and np.all(rel_b <= tol)
+    assert len(set(int(v) for v in it_b)) > 1  # the instances stop at different sweeps
+    graph = solver(probs, graph=True, **kw)
+    ug = torch.zeros_like(ub)
+    it_g, _, _ = graph.split_iterate(ug, 2000, tol)
+    torch.cuda.synchronize()
+    assert np.array_equal(it_g, it_b)
+    assert torch.equal(ug, ub)
+    for i, p in enumerate(probs):
+        one = solver(p, **kw)
+        u1 = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+        it1, _, _ = one.split_iterate(u1, 2000, tol)
+        torch.cuda.synchronize()
+        assert int(it1[0]) == int(it_b[i]), i
+        assert torch.equal(u1, ub[int(off[i]):int(off[i + 1])]), i
+        one.close()
+    batch.close()
+    graph.close()
