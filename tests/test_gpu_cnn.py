@@ -135,3 +135,53 @@ def test_adam_step_matches_oracle():
     agree = np.mean(np.sign(upd) == np.sign(upd_ref))
     assert agree > 0.99 and rel(upd, upd_ref) < 0.05
     net.close()
+
+
+def test_multi_tile_forward_equals_single_images():
+    """16 images of 129^2 are 1296 tiles of 16 x 16 pixels, more than the
+    resident workgroups, so a workgroup computes several tiles (the next tile's
+    patch loaded during the current one's products).  Each output tile's
+    arithmetic is the same as when the image is run alone (81 tiles, one per
+    workgroup): the outputs must be bitwise equal."""
+    print("[case] multi-tile forward B=16 129x129 vs single images", flush=True)
+    B, H, W = 16, 129, 129
+    f, s, u, mask, mu = make_batch(B, H, W, seed=7)
+    net, _, _ = setup_net(H, W, B, seed=8)
+    x0, _, _ = net.pack(B, dev(f), dev(s), dev(mask, torch.uint8), mu, dev(u))
+    out = net.forward(B, x0).clone()
+    HW = H * W
+    for i in range(B):
+        xi = x0[i * HW * 4:(i + 1) * HW * 4].clone()
+        oi = net.forward(1, xi)
+        assert torch.equal(oi[:HW], out[i * HW:(i + 1) * HW]), i
+    net.close()
+
+
+def test_multi_tile_gradients_equal_mean_of_single_images():
+    """8 images of 129^2 (648 tiles) spread the weight gradient over more tiles
+    than workgroups and the last layer over several pixel sweeps; the batch
+    gradient is the mean of the single-image gradients (same mask, so the same
+    pixel count per image), up to the FP32 summation order."""
+    print("[case] multi-tile gradients B=8 129x129 vs single images", flush=True)
+    B, H, W = 8, 129, 129
+    f, s, u, mask, mu = make_batch(B, H, W, seed=9)
+    net, _, _ = setup_net(H, W, B, seed=10)
+    m = dev(mask, torch.uint8)
+    x0, tgt, _ = net.pack(B, dev(f), dev(s), m, mu, dev(u))
+    g, loss = net.grads(B, x0, tgt, m)
+    g = g.cpu().numpy().astype(np.float64)
+    HW = H * W
+    acc = np.zeros_like(g)
+    losses = []
+    for i in range(B):
+        gi, li = net.grads(1, x0[i * HW * 4:(i + 1) * HW * 4].clone(), tgt[i * HW:(i + 1) * HW].clone(), m)
+        acc += gi.cpu().numpy().astype(np.float64)
+        losses.append(li)
+    acc /= B
+    assert abs(loss - np.mean(losses)) <= 1e-6 * loss
+    gW, gb = cnn.unflatten(g)
+    aW, ab = cnn.unflatten(acc)
+    for l in range(4):
+        assert rel(gW[l], aW[l]) < 1e-5, (l, rel(gW[l], aW[l]))
+        assert rel(gb[l], ab[l]) < 1e-5, (l, rel(gb[l], ab[l]))
+    net.close()
