@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--n", type=int, default=2049, help="grid nodes per side")
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--fp32-sweeps", type=int, default=3)
+    ap.add_argument("--adaptive", action="store_true",
+                    help="c2/c4 with --no-autotune: adaptive schedule with at most --fp32-sweeps FP32 sweeps per FP64 sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
@@ -84,7 +86,8 @@ def bench_c4(args):
     probs = gen_c4(args.instances)
     gen_s = time.time() - t0
     t0 = time.time()
-    s = Solver(probs, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, graph=args.graph)
+    s = Solver(probs, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, graph=args.graph,
+               adaptive=args.adaptive)
     setup_s = time.time() - t0
     counts = s.counts()
     per_inst = []
@@ -129,7 +132,8 @@ def bench_c4(args):
                       "converged": int((rel <= args.tol).sum()), "gen_s": round(gen_s, 1), "setup_s": round(setup_s, 1),
                       "graph": bool(args.graph),
                       "fp32_sweeps_per_fp64": tuned[0] if tuned else args.fp32_sweeps,
-                      "autotune_ms": round(tuned[1], 2) if tuned else None}}
+                      "adaptive_schedule": tuned[1] if tuned else False,
+                      "autotune_ms": round(tuned[2], 2) if tuned else None}}
     if True:
         out["config"]["kernels"] = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()}
                                     for pr in times}
@@ -373,7 +377,7 @@ def main():
         del a, b
     p = W.c2(args.n)
     t0 = time.time()
-    s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05)
+    s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, adaptive=args.adaptive)
     setup_s = time.time() - t0
     counts = s.counts()
     per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
@@ -381,7 +385,7 @@ def main():
     tuned = None
     if not args.no_autotune:
         tuned = s.autotune(u, 5000, args.tol)
-        args.fp32_sweeps = tuned[0]
+        args.fp32_sweeps, args.adaptive = tuned[0], tuned[1]
 
     def solve():
         u.zero_()
@@ -409,8 +413,11 @@ def main():
     # grid nodes).  Launches made after the convergence flag was set exit at
     # once and carry no work: the average is taken over the work-carrying
     # launches (their total time includes the empty ones, a conservative bound).
-    n_sw_prec = sum(1 for k in range(sweeps[0]) if (k % (args.fp32_sweeps + 1) == 0) == (rf["prec"] == "fp64"))
-    work_launches = max(1, n_sw_prec * args.steps)
+    if args.adaptive:  # the host stops at the converging sweep: every launch carries work
+        work_launches = max(1, rf["launches"])
+    else:
+        n_sw_prec = sum(1 for k in range(sweeps[0]) if (k % (args.fp32_sweeps + 1) == 0) == (rf["prec"] == "fp64"))
+        work_launches = max(1, n_sw_prec * args.steps)
     bytes_per_launch = rf["bytes_per_unit"] * rf["units"]
     avg_launch_s = rf["total_ms"] / work_launches / 1e3
     achieved = bytes_per_launch / avg_launch_s / 1e9
@@ -435,7 +442,8 @@ def main():
                                "beta=curl psi, psi=x+0.5y+0.1 sin(pi x) sin(pi y), f=8 seeded Gaussians; "
                                "eq.(10) sweeps theta=1 dt=0.05 to 1e-8",
                    "time_to_1e-8_ms": ms_step, "sweeps_per_solve": sweeps[0],
-                   "fp32_sweeps_per_fp64": args.fp32_sweeps, "autotuned": tuned is not None,
+                   "fp32_sweeps_per_fp64": args.fp32_sweeps, "adaptive_schedule": bool(args.adaptive),
+                   "autotuned": tuned is not None,
                    "line_unknowns_per_sweep": per_sweep,
                    "grid_unknowns": counts["grid_unknowns"], "lines": [counts["lines_b"], counts["lines_g"]],
                    "setup_s": round(setup_s, 2), "final_rel": float(rel[0]), "kernels": kernels},

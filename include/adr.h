@@ -88,6 +88,12 @@ typedef struct {
     int32_t graph;        /* != 0: adr_split_iterate replays its sweep blocks from a captured
                              HIP graph (on a context-owned stream ordered after options.stream);
                              ignored when timing != 0 */
+    int32_t adaptive;     /* != 0 (FP32_LINES, eager mode only: graph == 0 or timing != 0): the
+                             number of FP32 sweeps before each FP64 sweep varies from 0 to
+                             fp32_sweeps; it is chosen after each FP64 sweep so that the next
+                             one falls on the sweep where the first unfinished instance is
+                             expected to reach tol, from the geometric decay of its measured
+                             rel (at least fp32_sweeps / 2 while several instances run) */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -127,8 +133,8 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs);
  *   rel = |U_{k+1} - U_k|_2 / |Phi(0)|_2 <= tol      (interior nodes).
  * Sweep order: one FP64 sweep, then blocks of (fp32_sweeps FP32 sweeps, one
  * FP64 sweep) in FP32_LINES mode (whole blocks only: at most max_iters
- * sweeps); every sweep is FP64 in FP64 mode; rel is measured on the FP64
- * sweeps only.  iters (host, n_probs, may be NULL): sweeps
+ * sweeps; the block length varies with options.adaptive); every sweep is FP64
+ * in FP64 mode; rel is measured on the FP64 sweeps only.  iters (host, n_probs, may be NULL): sweeps
  * applied per instance; rel_res (host, n_probs, may be NULL): last measured
  * rel.  Returns ADR_ENOTCONV if an instance hit max_iters, ADR_ENONFINITE if a
  * residual is not finite. */
@@ -136,14 +142,16 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
                              int32_t *iters, double *rel_res);
 
 /* Autotuner of the batched stationary solve (FP32_LINES precision only): for
- * each candidate count of FP32 sweeps per FP64 sweep (2, 3, 4, 6) it runs the
- * stationary solve from zero twice (the first run captures the graph in graph
- * mode) on `work` (device FP64, packed layout, overwritten), times the second
- * on the host clock, and keeps the fastest count in the context's options.
- * best_fp32_sweeps, best_ms (host, may be NULL): the choice and its time.
- * Kernel timers (timing mode) are reset afterwards.  Synchronises. */
+ * each candidate schedule -- a fixed count of FP32 sweeps per FP64 sweep (2, 3,
+ * 4, 6) and, in eager mode, the adaptive schedule with at most 6, 8 or 12 --
+ * it runs the stationary solve from zero twice (the first run captures the
+ * graph in graph mode) on `work` (device FP64, packed layout, overwritten),
+ * times the second on the host clock, and keeps the fastest schedule in the
+ * context's options.  best_fp32_sweeps, best_adaptive, best_ms (host, may be
+ * NULL): the choice (count or maximum, adaptive flag) and its time.  Kernel
+ * timers (timing mode) are reset afterwards.  Synchronises. */
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
-                        double *best_ms);
+                        int32_t *best_adaptive, double *best_ms);
 
 /* Parabolic march (eq. (2) discretised by eq. (10)): nsteps sweeps with the
  * given theta in (0,1] and time step dt > 0, FP64, source f included.  u:

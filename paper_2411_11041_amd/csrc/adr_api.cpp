@@ -249,6 +249,51 @@ struct adr_ctx {
         norm(fp32_sweeps + 1, tol, 0);
     }
 
+    // Adaptive schedule (eager): after each FP64 sweep the per-instance rel is
+    // read with the done flags; an unfinished instance whose rel fell from r0
+    // (sweep k0) to r (sweep k) is expected to reach tol after
+    // ceil(log(tol / r) / log(rho)) more sweeps, rho = (r / r0)^(1 / (k - k0)).
+    // The next block ends on the earliest such sweep (at most fp32_sweeps FP32
+    // sweeps; at least half of that while several instances run, so that one
+    // instance about to finish does not cut every block short).
+    template <typename AllDone>
+    void adaptive_blocks(double *ub, int max_iters, double tol, std::vector<int> &dn, AllDone &&all_done) {
+        const int mmax = opt.fp32_sweeps;
+        std::vector<double> rel_h(n_inst, 0.0), r0(n_inst, -1.0);
+        std::vector<int> k0(n_inst, 0);
+        auto read_rel = [&]() {
+            HIPCHK(hipMemcpyAsync(rel_h.data(), rel, sizeof(double) * n_inst, hipMemcpyDeviceToHost, st));
+        };
+        int k = 1;  // the first FP64 sweep has run
+        read_rel();
+        if (all_done()) return;  // synchronises (rel_h is valid too)
+        for (int i = 0; i < n_inst; ++i) { r0[i] = rel_h[i]; k0[i] = k; }
+        int m = std::min(mmax, max_iters - k - 1);
+        while (m >= 0 && k + m + 1 <= max_iters) {
+            block(ub, m, tol);
+            k += m + 1;
+            read_rel();
+            if (all_done()) return;
+            if (n_inst > 1) compact(dn);
+            int target = k + mmax + 1, active = 0;
+            for (int i = 0; i < n_inst; ++i) {
+                if (dn[i]) continue;
+                ++active;
+                const double r = rel_h[i];
+                if (tol > 0.0 && r > 0.0 && r0[i] > r && std::isfinite(r)) {
+                    const double rho = std::pow(r / r0[i], 1.0 / (k - k0[i]));
+                    const double more = std::ceil(std::log(tol / r) / std::log(rho));
+                    if (rho > 0.0 && rho < 1.0 && more >= 0.0 && more < 1e6)
+                        target = std::min(target, k + static_cast<int>(more));
+                }
+                r0[i] = r;
+                k0[i] = k;
+            }
+            const int lo = active > 1 ? mmax / 2 : 0;
+            m = std::min(std::max(lo, std::min(mmax, target - k - 1)), max_iters - k - 1);
+        }
+    }
+
     // captured graph of one block, replayed (keyed by the state pointer and tol)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -702,7 +747,8 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
     try {
         const int n = ctx->n_inst;
         hipStream_t user = ctx->st;
-        const bool use_graph = ctx->opt.graph != 0 && !ctx->opt.timing;
+        const bool use_graph = ctx->opt.graph != 0 && !ctx->opt.timing &&
+                               !(ctx->opt.adaptive && ctx->opt.precision == ADR_PREC_FP32_LINES);
         if (use_graph) {
             // run on the context's own stream (capturable), ordered after the caller's work
             if (!ctx->cap) HIPCHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
@@ -741,13 +787,17 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
                 ctx->g_tol = tol;
                 ctx->g_m = m;
             }
-            for (int b = 0; b < blocks; ++b) {
-                if (use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, st));
-                else ctx->block(ub, m, tol);
-                if ((b + 1) % check == 0) {
-                    if (all_done()) break;
-                    // the graph's launches are fixed; eager launches follow the active set
-                    if (!use_graph && n > 1) ctx->compact(dn);
+            if (fp32 && ctx->opt.adaptive) {
+                ctx->adaptive_blocks(ub, max_iters, tol, dn, all_done);
+            } else {
+                for (int b = 0; b < blocks; ++b) {
+                    if (use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, st));
+                    else ctx->block(ub, m, tol);
+                    if ((b + 1) % check == 0) {
+                        if (all_done()) break;
+                        // the graph's launches are fixed; eager launches follow the active set
+                        if (!use_graph && n > 1) ctx->compact(dn);
+                    }
                 }
             }
         }
@@ -777,23 +827,29 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
 }
 
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
-                        double *best_ms) {
+                        int32_t *best_adaptive, double *best_ms) {
     if (!ctx) return ADR_EINVAL;
     if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES) {
         ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0 and FP32_LINES precision";
         return ADR_EINVAL;
     }
-    static const int kCand[] = {2, 3, 4, 6};
-    const int32_t saved = ctx->opt.fp32_sweeps;
-    int best = saved;
+    // (FP32 sweeps per FP64 sweep or their maximum, adaptive)
+    static const int kCand[][2] = {{2, 0}, {3, 0}, {4, 0}, {6, 0}, {6, 1}, {8, 1}, {12, 1}};
+    const int32_t saved = ctx->opt.fp32_sweeps, saved_ad = ctx->opt.adaptive;
+    const bool eager = !ctx->opt.graph || ctx->opt.timing;
+    int best = saved, best_ad = saved_ad;
     double best_t = INFINITY;
     const size_t nbytes = sizeof(double) * static_cast<size_t>(ctx->goff.back());
-    for (int c : kCand) {
+    for (const auto &cand : kCand) {
+        const int c = cand[0];
+        if (cand[1] && !eager) continue;  // the adaptive schedule runs eager launches only
         ctx->opt.fp32_sweeps = c;
+        ctx->opt.adaptive = cand[1];
         double t = INFINITY;
         for (int rep = 0; rep < 2; ++rep) {  // the first run also captures the graph (graph mode)
             if (hipMemsetAsync(work, 0, nbytes, ctx->st) != hipSuccess || hipStreamSynchronize(ctx->st) != hipSuccess) {
                 ctx->opt.fp32_sweeps = saved;
+                ctx->opt.adaptive = saved_ad;
                 ctx->err = "adr_autotune: device error";
                 return ADR_EDEVICE;
             }
@@ -802,6 +858,7 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
             const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
             if (st != ADR_OK && st != ADR_ENOTCONV) {
                 ctx->opt.fp32_sweeps = saved;
+                ctx->opt.adaptive = saved_ad;
                 return st;
             }
             t = ms;
@@ -809,12 +866,15 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
         if (t < best_t) {
             best_t = t;
             best = c;
+            best_ad = cand[1];
         }
     }
     ctx->opt.fp32_sweeps = best;
+    ctx->opt.adaptive = best_ad;
     if (ctx->opt.timing)
         for (int prec = 0; prec < 2; ++prec) (void)adr_kernel_times(ctx, prec, nullptr, nullptr, 1);
     if (best_fp32_sweeps) *best_fp32_sweeps = best;
+    if (best_adaptive) *best_adaptive = best_ad;
     if (best_ms) *best_ms = best_t;
     return ADR_OK;
 }

@@ -240,8 +240,8 @@ def test_autotune_keeps_a_candidate_and_the_fixed_point():
     p = W.c2(129)
     s = solver(p, precision="fp32", fp32_sweeps=3)
     work = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
-    best, ms = s.autotune(work, 2000, 1e-10)
-    assert best in (2, 3, 4, 6) and ms > 0
+    best, adaptive, ms = s.autotune(work, 2000, 1e-10)
+    assert ((best in (2, 3, 4, 6) and not adaptive) or (best in (6, 8, 12) and adaptive)) and ms > 0
     u = torch.zeros_like(work)
     iters, rel, st = s.split_iterate(u, 2000, 1e-10)
     assert st == 0 and rel[0] <= 1e-10
@@ -344,3 +344,31 @@ def test_batch_compaction_matches_single_solves(precision):
         one.close()
     batch.close()
     graph.close()
+
+
+@pytest.mark.parametrize("name,maker,tol", [("c2_257", lambda: [W.c2(257)], 1e-10),
+                                            ("batch", lambda: [W.c1(33), W.c2(65), W.c4_instance(2, n_max=100)], 1e-9)])
+def test_adaptive_schedule_reaches_the_fixed_point(name, maker, tol):
+    """The adaptive schedule (FP64 sweeps placed where rel is predicted to reach
+    tol) stops every instance at rel <= tol on an FP64 sweep and reaches the
+    oracle's fixed point (FP32-lines bar); a single instance needs at most one
+    sweep more than the fixed schedule (4 FP32 sweeps per FP64 sweep)."""
+    print(f"[case] adaptive schedule {name}", flush=True)
+    probs = maker()
+    fixed = solver(probs, precision="fp32", fp32_sweeps=4)
+    ada = solver(probs, precision="fp32", fp32_sweeps=8, adaptive=True)
+    off = fixed.layout()
+    uf = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    ua = torch.zeros_like(uf)
+    it_f, rel_f, st_f = fixed.split_iterate(uf, 3000, tol)
+    it_a, rel_a, st_a = ada.split_iterate(ua, 3000, tol)
+    assert st_f == 0 and st_a == 0 and np.all(rel_a <= tol)
+    if len(probs) == 1:
+        assert int(it_a[0]) <= int(it_f[0]) + 1
+    U = ua.cpu().numpy()
+    for i, p in enumerate(probs):
+        o = Oracle(p)
+        Ui, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-12)
+        assert rel_l2(U[off[i]:off[i + 1]], Ui) < 1e-5, i
+    fixed.close()
+    ada.close()
