@@ -132,7 +132,7 @@ def bench_c4(args):
                       "converged": int((rel <= args.tol).sum()), "gen_s": round(gen_s, 1), "setup_s": round(setup_s, 1),
                       "graph": bool(args.graph),
                       "fp32_sweeps_per_fp64": tuned[0] if tuned else args.fp32_sweeps,
-                      "adaptive_schedule": tuned[1] if tuned else False,
+                      "adaptive_schedule": tuned[1] if tuned else bool(args.adaptive),
                       "autotune_ms": round(tuned[2], 2) if tuned else None}}
     if True:
         out["config"]["kernels"] = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()}

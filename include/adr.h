@@ -143,7 +143,7 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
 
 /* Autotuner of the batched stationary solve (FP32_LINES precision only): for
  * each candidate schedule -- a fixed count of FP32 sweeps per FP64 sweep (2, 3,
- * 4, 6) and, in eager mode, the adaptive schedule with at most 6, 8 or 12 --
+ * 4, 6) and, in eager mode, the adaptive schedule with at most 6, 8, 12, 16 or 24 --
  * it runs the stationary solve from zero twice (the first run captures the
  * graph in graph mode) on `work` (device FP64, packed layout, overwritten),
  * times the second on the host clock, and keeps the fastest schedule in the

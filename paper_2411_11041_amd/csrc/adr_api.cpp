@@ -834,7 +834,7 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
         return ADR_EINVAL;
     }
     // (FP32 sweeps per FP64 sweep or their maximum, adaptive)
-    static const int kCand[][2] = {{2, 0}, {3, 0}, {4, 0}, {6, 0}, {6, 1}, {8, 1}, {12, 1}};
+    static const int kCand[][2] = {{2, 0}, {3, 0}, {4, 0}, {6, 0}, {6, 1}, {8, 1}, {12, 1}, {16, 1}, {24, 1}};
     const int32_t saved = ctx->opt.fp32_sweeps, saved_ad = ctx->opt.adaptive;
     const bool eager = !ctx->opt.graph || ctx->opt.timing;
     int best = saved, best_ad = saved_ad;
