@@ -35,11 +35,13 @@ constexpr int oW1 = 0, ob1 = oW1 + kW1, oW2 = ob1 + 32, ob2 = oW2 + kW2, oW3 = o
               oW4 = ob3 + 32, ob4 = oW4 + kW4, kParams = ob4 + 1;
 constexpr int kDil[4] = {1, 2, 4, 8};
 
-__device__ __forceinline__ bf16_t f2bf(float f) {
-    unsigned u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
-    u += 0x7fffu + ((u >> 16) & 1u);                      // round to nearest even
-    return static_cast<bf16_t>(u >> 16);
+// FP32 -> BF16, round to nearest even: the gfx950 conversion instruction
+// (v_cvt_pk_bf16_f32), one value or a packed pair (low half: a)
+typedef __bf16 v2bf16 __attribute__((ext_vector_type(2)));
+typedef float v2f32 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ bf16_t f2bf(float f) { return __builtin_bit_cast(bf16_t, static_cast<__bf16>(f)); }
+__device__ __forceinline__ unsigned f2bf2(float a, float b) {
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v2f32{a, b}, v2bf16));
 }
 __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(static_cast<unsigned>(h) << 16); }
 __device__ __forceinline__ bool bf_pos(bf16_t h) { return h != 0 && (h & 0x8000) == 0 && h <= 0x7f80; }
@@ -102,8 +104,7 @@ __global__ __launch_bounds__(kThreads) void k_conv_in(const bf16_t *__restrict__
         for (int v = 0; v < 4; ++v) {
             const int po = t * 16 + 4 * g + v;
             if (po >= NP) continue;
-            yw[static_cast<unsigned>(po) * (kCh / 2) + i] = static_cast<unsigned>(f2bf(fmaxf(acc0[v] + bias0, 0.f))) |
-                                                           (static_cast<unsigned>(f2bf(fmaxf(acc1[v] + bias1, 0.f))) << 16);
+            yw[static_cast<unsigned>(po) * (kCh / 2) + i] = f2bf2(fmaxf(acc0[v] + bias0, 0.f), fmaxf(acc1[v] + bias1, 0.f));
         }
     }
 }
@@ -268,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
                     z0 = bf_pos(static_cast<bf16_t>(mk[mt][v] & 0xffffu)) ? z0 : 0.f;
                     z1 = bf_pos(static_cast<bf16_t>(mk[mt][v] >> 16)) ? z1 : 0.f;
                 }
-                yw[po * (kCh / 2) + i] = static_cast<unsigned>(f2bf(z0)) | (static_cast<unsigned>(f2bf(z1)) << 16);
+                yw[po * (kCh / 2) + i] = f2bf2(z0, z1);
             }
         }
     }
@@ -633,7 +634,9 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
 // g3 = bf16( (sum_tap W4[tap][c] g4[p - d off(tap)]) * (y3 > 0) ).  Four lanes per
 // pixel (lane o: channels 8o .. 8o+7, one 16-byte mask load and one 16-byte store),
 // weights in registers, a workgroup walks pixel groups of 64.
-__global__ __launch_bounds__(kThreads) void k_last_dgrad(const float *__restrict__ g4, const float *__restrict__ W4,
+// (at most 4 waves per SIMD: with the 72 weights in registers, a tighter
+// register budget makes the compiler wait for each tap's load in turn)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))) void k_last_dgrad(const float *__restrict__ g4, const float *__restrict__ W4,
                                                          const bf16_t *__restrict__ y3, bf16_t *__restrict__ g3,
                                                          int NP, int H, int W, int d) {
     __shared__ __align__(16) float w4s[kW4];
@@ -665,6 +668,7 @@ __global__ __launch_bounds__(kThreads) void k_last_dgrad(const float *__restrict
             gn[tap] = ok ? gvl : 0.f;
         }
         const uint4 yv = ysrc[static_cast<unsigned>(gp) * (kCh / 8) + o];
+
         const unsigned yq[4] = {yv.x, yv.y, yv.z, yv.w};
         unsigned oq[4];
 #pragma unroll
