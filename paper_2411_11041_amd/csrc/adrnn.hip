@@ -160,6 +160,26 @@ __device__ __forceinline__ void conv_patch_load(const bf16_t *__restrict__ x, in
     inm = m;
 }
 
+// the ReLU mask pairs (channels 2i, 2i+1) of a lane's 16 outputs in tile t of
+// the transposed pass: rows 4 wave + mt, columns 4 g + v (outside the image:
+// the image's first pixel, not used)
+__device__ __forceinline__ void conv_mask_load(const bf16_t *__restrict__ ymask, int t, int tpi, int tw, int H, int W,
+                                               int wave, int g, int i, unsigned (&mk)[4][4]) {
+    const int b = t / tpi, tt = t - b * tpi;
+    const int ty = tt / tw, tx = tt - ty * tw;
+    const int y0 = ty * kTile, x0 = tx * kTile;
+    const unsigned *mw = reinterpret_cast<const unsigned *>(ymask);
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int gy = y0 + wave * 4 + mt, gx = x0 + 4 * g + v;
+            const bool in = gy < H && gx < W;
+            const unsigned po = (static_cast<unsigned>(b) * H + (in ? gy : 0)) * W + (in ? gx : 0);
+            mk[mt][v] = mw[po * (kCh / 2) + i];
+        }
+}
+
 // patch loads per thread at dilation d: ceil((16 + 2d)^2 * 4 / 256) (the prefetch registers)
 __host__ __device__ constexpr int conv_xs(int d) { return ((kTile + 2 * d) * (kTile + 2 * d) * 4 + kThreads - 1) / kThreads; }
 
@@ -195,11 +215,20 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i = lane & 15, g = lane >> 4;
-    const float bias0 = EPI == 0 ? bias[2 * i] : 0.f, bias1 = EPI == 0 ? bias[2 * i + 1] : 0.f;
+    // the bias through LDS: a global load pending at the epilogue would make the
+    // epilogue wait for the next tile's patch loads as well (one counter for all)
+    __shared__ float bs[kCh];
+    if (threadIdx.x < kCh) bs[threadIdx.x] = EPI == 0 ? bias[threadIdx.x] : 0.f;
     uint4 xv[XS];
     unsigned inm = 0;
+    // EPI 1: the ReLU mask pairs of this lane's outputs, double-buffered: the
+    // next tile's are loaded with its patch, so the epilogue never waits
+    unsigned mk[4][4], mkn[4][4];
     int t = blockIdx.x;
-    if (t < ntiles) conv_patch_load<D, XS>(x, t, tpi, tw, H, W, xv, inm);
+    if (t < ntiles) {
+        if constexpr (EPI == 1) conv_mask_load(ymask, t, tpi, tw, H, W, wave, g, i, mkn);
+        conv_patch_load<D, XS>(x, t, tpi, tw, H, W, xv, inm);
+    }
     for (; t < ntiles; t += gridDim.x) {
         __syncthreads();  // the previous tile's products are done with Xs
 #pragma unroll
@@ -213,24 +242,19 @@ __global__ __launch_bounds__(kThreads) void k_conv32t(const bf16_t *__restrict__
             }
         }
         __syncthreads();
-        if (t + static_cast<int>(gridDim.x) < ntiles)  // in flight during the products
-            conv_patch_load<D, XS>(x, t + gridDim.x, tpi, tw, H, W, xv, inm);
+        const float bias0 = bs[2 * i], bias1 = bs[2 * i + 1];
         const int b = t / tpi, tt = t - b * tpi;
         const int ty = tt / tw, tx = tt - ty * tw;
         const int y0 = ty * kTile, x0 = tx * kTile;
-        // EPI 1: the ReLU mask pairs of this lane's outputs, loaded before the products
-        unsigned mk[4][4];
         if constexpr (EPI == 1) {
-            const unsigned *mw = reinterpret_cast<const unsigned *>(ymask);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int gy = y0 + wave * 4 + mt, gx = x0 + 4 * g + v;
-                    const bool in = gy < H && gx < W;
-                    const unsigned po = (static_cast<unsigned>(b) * H + (in ? gy : 0)) * W + (in ? gx : 0);
-                    mk[mt][v] = mw[po * (kCh / 2) + i];
-                }
+                for (int v = 0; v < 4; ++v) mk[mt][v] = mkn[mt][v];
+        }
+        if (t + static_cast<int>(gridDim.x) < ntiles) {  // in flight during the products
+            if constexpr (EPI == 1) conv_mask_load(ymask, t + gridDim.x, tpi, tw, H, W, wave, g, i, mkn);
+            conv_patch_load<D, XS>(x, t + gridDim.x, tpi, tw, H, W, xv, inm);
         }
         v4f32 acc[4][2];
 #pragma unroll
