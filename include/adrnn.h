@@ -64,13 +64,21 @@ adr_status adrnn_pack(adrnn_ctx *ctx, int32_t B, const double *f, const double *
 /* out (FP32, B*H*W) = network(x0). */
 adr_status adrnn_forward(adrnn_ctx *ctx, int32_t B, const void *x0, float *out);
 
-/* Loss (host, may be NULL) and its gradient (FP32, parameter layout) for a
- * batch: forward, loss, backward.  grads: device, adrnn_param_count() floats. */
+/* Loss and its gradient (FP32, parameter layout) for a batch: forward, loss,
+ * backward.  grads: device, adrnn_param_count() floats.  The loss is also
+ * added to the context's device-side sum (adrnn_loss_sum).  loss (host, may be
+ * NULL): this batch's loss; non-NULL synchronises the stream, NULL leaves the
+ * call asynchronous. */
 adr_status adrnn_grads(adrnn_ctx *ctx, int32_t B, const void *x0, const float *target, const uint8_t *mask,
                        float *grads, double *loss);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the device master weights. */
 adr_status adrnn_adam(adrnn_ctx *ctx, const float *grads, float lr);
+
+/* Sum (host, may be NULL) and count (host, may be NULL) of the losses of the
+ * adrnn_grads / adrnn_train_step calls since the context was created or last
+ * reset; reset != 0 clears both afterwards.  Synchronises the stream. */
+adr_status adrnn_loss_sum(adrnn_ctx *ctx, double *sum, int64_t *steps, int32_t reset);
 
 /* adrnn_grads followed by adrnn_adam with the context's gradient buffer. */
 adr_status adrnn_train_step(adrnn_ctx *ctx, int32_t B, const void *x0, const float *target, const uint8_t *mask,

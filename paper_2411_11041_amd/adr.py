@@ -234,7 +234,7 @@ class Solver:
 # ----------------------------------------------------------------------------
 # learned warm start (include/adrnn.h)
 NN_EXPORTS = ("adrnn_param_count", "adrnn_create", "adrnn_destroy", "adrnn_set_params", "adrnn_get_params",
-              "adrnn_pack", "adrnn_forward", "adrnn_grads", "adrnn_adam", "adrnn_train_step",
+              "adrnn_pack", "adrnn_forward", "adrnn_grads", "adrnn_adam", "adrnn_train_step", "adrnn_loss_sum",
               "adrnn_warm_start", "adrnn_mfma_probe", "adrnn_last_error")
 
 _nn_ready = False
@@ -256,6 +256,7 @@ def _load_nn():
     lib.adrnn_grads.argtypes = [vp, i32, vp, vp, vp, vp, P(C.c_double)]
     lib.adrnn_adam.argtypes = [vp, vp, C.c_float]
     lib.adrnn_train_step.argtypes = [vp, i32, vp, vp, vp, C.c_float, P(C.c_double)]
+    lib.adrnn_loss_sum.argtypes = [vp, P(C.c_double), P(C.c_int64), i32]
     lib.adrnn_warm_start.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     lib.adrnn_mfma_probe.argtypes = [vp, vp, vp, vp]
     lib.adrnn_last_error.argtypes = [vp]
@@ -328,11 +329,20 @@ class Net:
     def adam(self, grads, lr):
         self._check(self.lib.adrnn_adam(self.ctx, _dp(grads), float(lr)))
 
-    def train_step(self, B, x0, target, mask, lr):
+    def train_step(self, B, x0, target, mask, lr, want_loss=True):
+        """One Adam step; returns the batch loss (a stream synchronisation), or
+        None with want_loss=False (asynchronous; see loss_sum)."""
         loss = C.c_double()
         self._check(self.lib.adrnn_train_step(self.ctx, B, _dp(x0), _dp(target), _dp(mask), float(lr),
-                                              C.byref(loss)))
-        return loss.value
+                                              C.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def loss_sum(self, reset=True):
+        """(sum, count) of the losses since the last reset (synchronises)."""
+        sm = C.c_double()
+        n = C.c_int64()
+        self._check(self.lib.adrnn_loss_sum(self.ctx, C.byref(sm), C.byref(n), int(bool(reset))))
+        return sm.value, n.value
 
     def warm_start(self, B, s, s_norm, out, mask, u):
         self._check(self.lib.adrnn_warm_start(self.ctx, B, _dp(s), _dp(s_norm), _dp(out), _dp(mask), _dp(u)))

@@ -634,10 +634,26 @@ __global__ __launch_bounds__(kThreads) void k_last_fwd(const bf16_t *__restrict_
     }
 }
 
-// g4 = 2 (out - target) mask / cnt; partial sums of mask (out - target)^2 per block
+// interior pixels of the mask (one workgroup, fixed order): cnt[0]
+__global__ __launch_bounds__(kThreads) void k_mask_count(const uint8_t *__restrict__ mask, int HW, int *__restrict__ cnt) {
+    int c = 0;
+    for (int p = threadIdx.x; p < HW; p += kThreads) c += mask[p] != 0;
+    __shared__ int red[kThreads];
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) cnt[0] = red[0];
+}
+
+// g4 = 2 (out - target) mask / (B cnt); partial sums of mask (out - target)^2 per block
 __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ tgt, const uint8_t *__restrict__ mask,
-                       float *__restrict__ g4, double *__restrict__ lpart, int NP, int HW, double inv_cnt) {
+                       float *__restrict__ g4, double *__restrict__ lpart, int NP, int HW, int B,
+                       const int *__restrict__ cnt) {
     const int gp = blockIdx.x * blockDim.x + threadIdx.x;
+    const double inv_cnt = 1.0 / (static_cast<double>(B) * (cnt[0] > 0 ? cnt[0] : 1));
     double e2 = 0.0;
     if (gp < NP) {
         const bool m = mask[gp % HW] != 0;
@@ -653,6 +669,27 @@ __global__ void k_loss(const float *__restrict__ out, const float *__restrict__ 
         __syncthreads();
     }
     if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+// loss of the step = sum of the block partials (fixed order) / (B cnt): acc[2]
+// = this step's loss, acc[0] += it, acc[1] += 1 (one workgroup)
+__global__ __launch_bounds__(kThreads) void k_loss_sum(const double *__restrict__ lpart, int nb, int B,
+                                                       const int *__restrict__ cnt, double *__restrict__ acc) {
+    double sum = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kThreads) sum += lpart[b];
+    __shared__ double red[kThreads];
+    red[threadIdx.x] = sum;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double L = red[0] / (static_cast<double>(B) * (cnt[0] > 0 ? cnt[0] : 1));
+        acc[2] = L;
+        acc[0] += L;
+        acc[1] += 1.0;
+    }
 }
 
 // g3 = bf16( (sum_tap W4[tap][c] g4[p - d off(tap)]) * (y3 > 0) ).  Four lanes per
@@ -892,6 +929,8 @@ struct adrnn_ctx {
     bf16_t *y1 = nullptr, *y2 = nullptr, *y3 = nullptr, *ga = nullptr, *gb = nullptr;
     float *out = nullptr, *g4 = nullptr, *part = nullptr, *lmu = nullptr;
     double *lpart = nullptr, *fn = nullptr, *dlmu = nullptr;
+    double *lacc = nullptr;  // device: loss sum, step count, last loss
+    int *cnt = nullptr;      // device: interior pixels of the last mask
     int wblocks = 512;
     int n_cu = 256;  // compute units of the device (set at creation)
     int64_t step = 0;
@@ -1009,18 +1048,15 @@ void wgrad(adrnn_ctx *c, const bf16_t *g, const bf16_t *x, int NP, int d, float 
     NNCHK(hipGetLastError());
 }
 
-double grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint8_t *mask, float *G) {
+// forward, loss (accumulated on the device), backward: no host synchronisation
+void grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint8_t *mask, float *G) {
     const int HW = c->H * c->W, NP = B * HW;
     forward(c, B, x0, c->out);
-    // interior pixel count (mask shared by the images)
-    std::vector<uint8_t> hm(HW);
-    NNCHK(hipMemcpyAsync(hm.data(), mask, HW, hipMemcpyDeviceToHost, c->st));
-    NNCHK(hipStreamSynchronize(c->st));
-    int64_t cnt = 0;
-    for (uint8_t b : hm) cnt += b != 0;
-    const double inv_cnt = 1.0 / (static_cast<double>(B) * std::max<int64_t>(cnt, 1));
+    // interior pixel count (mask shared by the images), on the device
+    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(kThreads), 0, c->st, mask, HW, c->cnt);
     const int lb = (NP + 255) / 256;
-    hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, c->st, c->out, tgt, mask, c->g4, c->lpart, NP, HW, inv_cnt);
+    hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, c->st, c->out, tgt, mask, c->g4, c->lpart, NP, HW, B, c->cnt);
+    hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(kThreads), 0, c->st, c->lpart, lb, B, c->cnt, c->lacc);
     // layer 4
     // partials of up to 1024 workgroups (289 floats each) fit in the 32 -> 32 layers' buffer
     const int nb = last_grid(NP);
@@ -1040,12 +1076,6 @@ double grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint
     // layer 1: g1 = ga
     wgrad<4>(c, c->ga, x0, NP, kDil[0], G + oW1);
     NNCHK(hipGetLastError());
-    std::vector<double> lp(lb);
-    NNCHK(hipMemcpyAsync(lp.data(), c->lpart, sizeof(double) * lb, hipMemcpyDeviceToHost, c->st));
-    NNCHK(hipStreamSynchronize(c->st));
-    double L = 0.0;
-    for (double v : lp) L += v;
-    return L * inv_cnt;
 }
 
 adr_status fail(adrnn_ctx *c, const NNError &e) {
@@ -1095,6 +1125,9 @@ adr_status adrnn_create(int32_t H, int32_t W, int32_t max_batch, void *stream, a
         c->g4 = nn_alloc<float>(c, NP);
         c->part = nn_alloc<float>(c, static_cast<size_t>(c->wblocks) * (kCh * 9 * kCh + kCh));
         c->lpart = nn_alloc<double>(c, (NP + 255) / 256);
+        c->lacc = nn_alloc<double>(c, 3);
+        c->cnt = nn_alloc<int>(c, 1);
+        NNCHK(hipMemsetAsync(c->lacc, 0, 3 * sizeof(double), c->st));
         c->fn = nn_alloc<double>(c, 2 * static_cast<size_t>(max_batch));
         c->dlmu = nn_alloc<double>(c, max_batch);
         std::vector<float> zero(kParams, 0.f);
@@ -1181,8 +1214,11 @@ adr_status adrnn_grads(adrnn_ctx *c, int32_t B, const void *x0, const float *tar
                        float *G, double *loss) {
     if (!c || B < 1 || B > c->maxB || !x0 || !target || !mask || !G) return ADR_EINVAL;
     try {
-        const double L = grads(c, B, static_cast<const bf16_t *>(x0), target, mask, G);
-        if (loss) *loss = L;
+        grads(c, B, static_cast<const bf16_t *>(x0), target, mask, G);
+        if (loss) {
+            NNCHK(hipMemcpyAsync(loss, c->lacc + 2, sizeof(double), hipMemcpyDeviceToHost, c->st));
+            NNCHK(hipStreamSynchronize(c->st));
+        }
         return ADR_OK;
     } catch (const NNError &e) {
         return fail(c, e);
@@ -1210,6 +1246,21 @@ adr_status adrnn_train_step(adrnn_ctx *c, int32_t B, const void *x0, const float
     adr_status s = adrnn_grads(c, B, x0, target, mask, c ? c->grad : nullptr, loss);
     if (s != ADR_OK) return s;
     return adrnn_adam(c, c->grad, lr);
+}
+
+adr_status adrnn_loss_sum(adrnn_ctx *c, double *sum, int64_t *steps, int32_t reset) {
+    if (!c) return ADR_EINVAL;
+    try {
+        double h[3] = {0.0, 0.0, 0.0};
+        NNCHK(hipMemcpyAsync(h, c->lacc, sizeof(h), hipMemcpyDeviceToHost, c->st));
+        NNCHK(hipStreamSynchronize(c->st));
+        if (sum) *sum = h[0];
+        if (steps) *steps = static_cast<int64_t>(h[1]);
+        if (reset) NNCHK(hipMemsetAsync(c->lacc, 0, 2 * sizeof(double), c->st));
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
 }
 
 adr_status adrnn_warm_start(adrnn_ctx *c, int32_t B, const double *s, const double *s_norm, const float *out,

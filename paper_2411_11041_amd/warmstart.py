@@ -141,17 +141,20 @@ def train(net, x_all, t_all, mask, N, HW, epochs, batch=32, lr=1e-3, lr_end=None
     per_ep = max(N // batch, 1)
     total = epochs * per_ep
     step = 0
+    net.loss_sum(reset=True)
     for ep in range(epochs):
-        perm = rng.permutation(N)
-        tot, nb = 0.0, 0
+        # the epoch's permutation goes to the device once (a copy from pageable
+        # host memory waits for the stream); the steps then queue without a
+        # host synchronisation, and the loss is summed on the device
+        perm = torch.from_numpy(rng.permutation(N)).cuda()
         for b0 in range(0, N - batch + 1, batch):
-            idx = torch.from_numpy(perm[b0:b0 + batch]).cuda()
+            idx = perm[b0:b0 + batch]
             xb = xv.index_select(0, idx).contiguous().view(-1)
             tb = tv.index_select(0, idx).contiguous().view(-1)
             a = lr if lr_end is None else lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * step / total))
-            tot += net.train_step(batch, xb, tb, mask, a)
+            net.train_step(batch, xb, tb, mask, a, want_loss=False)
             step += 1
-            nb += 1
+        tot, nb = net.loss_sum(reset=True)
         losses.append(tot / max(nb, 1))
         if log:
             log(f"epoch {ep + 1}/{epochs} loss {losses[-1]:.3e}")
