@@ -4,12 +4,15 @@
 //
 // Convolutions are implicit GEMMs on v_mfma_f32_16x16x16_bf16: M = pixels,
 // N = 32 output channels (two 16x16 tiles), K = (tap, input channel).  The
-// 32 -> 32 layers run tiled (k_conv32t: a 16 x 16-pixel tile and its dilated
-// halo staged in LDS), the 4 -> 32 first layer directly from global memory
-// (k_conv_in), the 32 -> 1 last layer on the vector ALUs.  Operand layout of the instruction: lane l supplies
-// A[l%16][4(l/16) .. 4(l/16)+3] and B[4(l/16) .. +3][l%16]; it receives
-// D[4(l/16) + v][l%16], v = 0..3.  NHWC activations make a lane's four K
-// values (four consecutive channels of one pixel) one 8-byte load.
+// 32 -> 32 layers run tiled and persistent (k_conv32t: 16 x 16-pixel tiles
+// with their dilated halo staged in LDS, the next tile prefetched), the
+// 4 -> 32 first layer directly from global memory (k_conv_in), the 32 -> 1
+// last layer on the vector ALUs.  Weight gradients are GEMMs with K = pixels
+// (k_wgradt: tiles transposed to channel-major LDS).  Operand layout of the
+// instruction: lane l supplies A[l%16][4(l/16) .. 4(l/16)+3] and
+// B[4(l/16) .. +3][l%16]; it receives D[4(l/16) + v][l%16], v = 0..3.  NHWC
+// activations make a lane's four K values (four consecutive channels of one
+// pixel) one 8-byte load.
 // Layer l's taps are dilated by kDil[l]: tap (dy, dx) reads the pixel
 // (y + d dy, x + d dx), zero outside the image.
 #include <hip/hip_runtime.h>
