@@ -637,10 +637,28 @@ __global__ __launch_bounds__(kThreads) void k_last_fwd(const bf16_t *__restrict_
     }
 }
 
-// interior pixels of the mask (one workgroup, fixed order): cnt[0]
+// interior pixels of the mask: cnt[0] += the nonzero bytes (zeroed before).
+// A thread counts 16 bytes (one 16-byte load from the first 16-byte boundary
+// on); the bytes before that boundary and after the last full word are
+// counted one by one by one thread.  A workgroup adds its count once (integer:
+// any order gives the same sum).
 __global__ __launch_bounds__(kThreads) void k_mask_count(const uint8_t *__restrict__ mask, int HW, int *__restrict__ cnt) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int head = static_cast<int>((16u - (reinterpret_cast<uintptr_t>(mask) & 15u)) & 15u);
+    const int h = head < HW ? head : HW;
+    const int n16 = (HW - h) / 16;
     int c = 0;
-    for (int p = threadIdx.x; p < HW; p += kThreads) c += mask[p] != 0;
+    if (i < n16) {
+        const uint4 v = reinterpret_cast<const uint4 *>(mask + h)[i];
+        const unsigned w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int bt = 0; bt < 4; ++bt) c += ((w[k] >> (8 * bt)) & 0xffu) != 0u;
+    } else if (i == n16) {
+        for (int p = 0; p < h; ++p) c += mask[p] != 0;
+        for (int p = h + 16 * n16; p < HW; ++p) c += mask[p] != 0;
+    }
     __shared__ int red[kThreads];
     red[threadIdx.x] = c;
     __syncthreads();
@@ -648,7 +666,7 @@ __global__ __launch_bounds__(kThreads) void k_mask_count(const uint8_t *__restri
         if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) cnt[0] = red[0];
+    if (threadIdx.x == 0 && red[0] != 0) atomicAdd(cnt, red[0]);
 }
 
 // g4 = 2 (out - target) mask / (B cnt); partial sums of mask (out - target)^2 per block
@@ -753,8 +771,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(1, 4))
 }
 
 // part[blk][tap*32 + c] = sum over the block's pixels of g4[p] y3[p + d off][c]; part[blk][288] = sum g4.
-// Four lanes per pixel (lane o: channels 8o .. 8o+7, one 16-byte load per tap),
-// 72 accumulators per lane; a workgroup walks pixel groups of 64.  At the end
+// Four lanes per activation pixel (lane o: channels 8o .. 8o+7, one 16-byte
+// load), 72 accumulators per lane; a workgroup walks pixel groups of 64.  At the end
 // the 16 pixel lanes of a wavefront are summed by a butterfly, then the four
 // wavefronts in LDS (fixed order).
 __global__ __launch_bounds__(kThreads) void k_last_wgrad(const float *__restrict__ g4, const bf16_t *__restrict__ y3,
@@ -769,30 +787,35 @@ __global__ __launch_bounds__(kThreads) void k_last_wgrad(const float *__restrict
 #pragma unroll
         for (int k = 0; k < 8; ++k) acc[tap][k] = 0.f;
     float gsum = 0.f;
-    for (int gp0 = blockIdx.x * 64; gp0 < NP; gp0 += gridDim.x * 64) {
-        const int gp = gp0 + ps;
-        if (gp >= NP) break;
-        const float gv = g4[gp];
-        gsum += gv;
-        const int p = gp % HW, py = p / W, px = p - py * W;
-        uint4 v[9];
-        bool ok[9];
+    // summed over the activation pixel q = p + d off(tap): each activation is
+    // loaded and converted once, and the nine taps take the output gradient at
+    // q - d off(tap) (a scalar shared by the pixel's four lanes); the pairs
+    // (p, q) are those with both pixels in the image, as in the definition
+    for (int q0 = blockIdx.x * 64; q0 < NP; q0 += gridDim.x * 64) {
+        const int gq = q0 + ps;
+        if (gq >= NP) break;
+        const int pq = gq % HW, qy = pq / W, qx = pq - qy * W;
+        const uint4 yv4 = yv[static_cast<unsigned>(gq) * (kCh / 8) + o];
+        float gt[9];
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = d * (tap / 3 - 1), dx = d * (tap % 3 - 1);
-            ok[tap] = py + dy >= 0 && py + dy < H && px + dx >= 0 && px + dx < W;
-            v[tap] = yv[static_cast<unsigned>(ok[tap] ? gp + dy * W + dx : gp) * (kCh / 8) + o];
+            const bool ok = qy - dy >= 0 && qy - dy < H && qx - dx >= 0 && qx - dx < W;
+            const float gvl = g4[ok ? gq - dy * W - dx : gq];
+            gt[tap] = ok ? gvl : 0.f;
+        }
+        gsum += gt[4];  // the centre tap: every pixel's own gradient once
+        const unsigned w4[4] = {yv4.x, yv4.y, yv4.z, yv4.w};
+        float yf[8];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            yf[2 * e] = __uint_as_float(w4[e] << 16);
+            yf[2 * e + 1] = __uint_as_float(w4[e] & 0xffff0000u);
         }
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const float gt = ok[tap] ? gv : 0.f;
-            const unsigned q[4] = {v[tap].x, v[tap].y, v[tap].z, v[tap].w};
+        for (int tap = 0; tap < 9; ++tap)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                acc[tap][2 * e] += gt * __uint_as_float(q[e] << 16);
-                acc[tap][2 * e + 1] += gt * __uint_as_float(q[e] & 0xffff0000u);
-            }
-        }
+            for (int k = 0; k < 8; ++k) acc[tap][k] += gt[tap] * yf[k];
     }
     // butterfly over the 16 pixel lanes of each octet (lane bits 2..5)
 #pragma unroll
@@ -856,15 +879,25 @@ __global__ void k_adam(float *__restrict__ P, float *__restrict__ m, float *__re
 }
 
 // ------------------------------------------------------------------ inputs and warm start
+// per-image max |f| and max |s| over the interior pixels: workgroup (b, sl)
+// takes slice sl of image b (loads issued unconditionally, the mask applied by
+// a select) and folds its maxima into bits[2b], bits[2b+1] (zeroed before) by
+// an integer max of the FP64 bit patterns, whose order is that of the values
+// for non-negative numbers (exact, and the same in any order)
+constexpr int kNormSlices = 16;
 __global__ __launch_bounds__(kThreads) void k_norms(const double *__restrict__ f, const double *__restrict__ s,
-                                                    const uint8_t *__restrict__ mask, double *__restrict__ fn,
-                                                    double *__restrict__ sn, int HW) {
-    const int b = blockIdx.x;
+                                                    const uint8_t *__restrict__ mask,
+                                                    unsigned long long *__restrict__ bits, int HW) {
+    const int b = blockIdx.x / kNormSlices, sl = blockIdx.x - b * kNormSlices;
+    const int p0 = static_cast<int>(static_cast<long long>(HW) * sl / kNormSlices);
+    const int p1 = static_cast<int>(static_cast<long long>(HW) * (sl + 1) / kNormSlices);
+    const size_t ib = static_cast<size_t>(b) * HW;
     double mf = 0.0, ms = 0.0;
-    for (int p = threadIdx.x; p < HW; p += kThreads) {
-        if (!mask[p]) continue;
-        mf = fmax(mf, fabs(f[static_cast<size_t>(b) * HW + p]));
-        ms = fmax(ms, fabs(s[static_cast<size_t>(b) * HW + p]));
+    for (int p = p0 + static_cast<int>(threadIdx.x); p < p1; p += kThreads) {
+        const bool m = mask[p] != 0;
+        const double fv = fabs(f[ib + p]), sv = fabs(s[ib + p]);
+        mf = fmax(mf, m ? fv : 0.0);
+        ms = fmax(ms, m ? sv : 0.0);
     }
     __shared__ double rf[kThreads], rs[kThreads];
     rf[threadIdx.x] = mf;
@@ -878,9 +911,21 @@ __global__ __launch_bounds__(kThreads) void k_norms(const double *__restrict__ f
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        fn[b] = rf[0] > 0.0 ? rf[0] : 1.0;
-        sn[b] = rs[0] > 0.0 ? rs[0] : 1.0;
+        atomicMax(bits + 2 * b, static_cast<unsigned long long>(__double_as_longlong(rf[0])));
+        atomicMax(bits + 2 * b + 1, static_cast<unsigned long long>(__double_as_longlong(rs[0])));
     }
+}
+
+// fn[b], sn[b] from the folded maxima (1 where the maximum is 0; fmax has
+// dropped NaN values, as it does in the maxima above)
+__global__ void k_norms_fin(const unsigned long long *__restrict__ bits, double *__restrict__ fn,
+                            double *__restrict__ sn, int B) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    const double vf = __longlong_as_double(static_cast<long long>(bits[2 * b]));
+    const double vs = __longlong_as_double(static_cast<long long>(bits[2 * b + 1]));
+    fn[b] = vf > 0.0 ? vf : 1.0;
+    sn[b] = vs > 0.0 ? vs : 1.0;
 }
 
 __global__ void k_pack(const double *__restrict__ f, const double *__restrict__ s, const uint8_t *__restrict__ mask,
@@ -934,6 +979,7 @@ struct adrnn_ctx {
     double *lpart = nullptr, *fn = nullptr, *dlmu = nullptr;
     double *lacc = nullptr;  // device: loss sum, step count, last loss
     int *cnt = nullptr;      // device: interior pixels of the last mask
+    unsigned long long *nbits = nullptr;  // device: per-image maxima of |f|, |s| (FP64 bits)
     int wblocks = 512;
     int n_cu = 256;  // compute units of the device (set at creation)
     int64_t step = 0;
@@ -1056,7 +1102,8 @@ void grads(adrnn_ctx *c, int B, const bf16_t *x0, const float *tgt, const uint8_
     const int HW = c->H * c->W, NP = B * HW;
     forward(c, B, x0, c->out);
     // interior pixel count (mask shared by the images), on the device
-    hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(kThreads), 0, c->st, mask, HW, c->cnt);
+    NNCHK(hipMemsetAsync(c->cnt, 0, sizeof(int), c->st));
+    hipLaunchKernelGGL(k_mask_count, dim3(HW / 16 / kThreads + 1), dim3(kThreads), 0, c->st, mask, HW, c->cnt);
     const int lb = (NP + 255) / 256;
     hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, c->st, c->out, tgt, mask, c->g4, c->lpart, NP, HW, B, c->cnt);
     hipLaunchKernelGGL(k_loss_sum, dim3(1), dim3(kThreads), 0, c->st, c->lpart, lb, B, c->cnt, c->lacc);
@@ -1130,6 +1177,7 @@ adr_status adrnn_create(int32_t H, int32_t W, int32_t max_batch, void *stream, a
         c->lpart = nn_alloc<double>(c, (NP + 255) / 256);
         c->lacc = nn_alloc<double>(c, 3);
         c->cnt = nn_alloc<int>(c, 1);
+        c->nbits = nn_alloc<unsigned long long>(c, 2 * static_cast<size_t>(max_batch));
         NNCHK(hipMemsetAsync(c->lacc, 0, 3 * sizeof(double), c->st));
         c->fn = nn_alloc<double>(c, 2 * static_cast<size_t>(max_batch));
         c->dlmu = nn_alloc<double>(c, max_batch);
@@ -1193,7 +1241,9 @@ adr_status adrnn_pack(adrnn_ctx *c, int32_t B, const double *f, const double *s,
         }
         NNCHK(hipMemcpy(c->dlmu, lm.data(), sizeof(double) * B, hipMemcpyHostToDevice));
         double *fn = c->fn, *sn = s_norm ? s_norm : c->fn + c->maxB;
-        hipLaunchKernelGGL(k_norms, dim3(B), dim3(kThreads), 0, c->st, f, s, mask, fn, sn, HW);
+        NNCHK(hipMemsetAsync(c->nbits, 0, sizeof(unsigned long long) * 2 * B, c->st));
+        hipLaunchKernelGGL(k_norms, dim3(B * kNormSlices), dim3(kThreads), 0, c->st, f, s, mask, c->nbits, HW);
+        hipLaunchKernelGGL(k_norms_fin, dim3((B + 255) / 256), dim3(256), 0, c->st, c->nbits, fn, sn, B);
         hipLaunchKernelGGL(k_pack, dim3((NP + 255) / 256), dim3(256), 0, c->st, f, s, mask, c->dlmu, fn, sn, u_star,
                            static_cast<bf16_t *>(x0), target, NP, HW);
         NNCHK(hipGetLastError());
