@@ -248,6 +248,28 @@ def events_pass(s, solve, steps):
     return el, times
 
 
+def copy_bandwidth_gbs(nbytes=1 << 30, reps=10):
+    """HBM bandwidth of a plain device copy (the library's copy kernel, nbytes
+    in and nbytes out, on torch's current stream), timed with events: the
+    measured counterpart of the vendor peak."""
+    import torch
+    from paper_2411_11041_amd.adr import copy_probe
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    copy_probe(a, b)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        copy_probe(a, b)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
 def measured_traffic(kernel, profile="c2_2049_fp32lines.md"):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the
@@ -421,8 +443,10 @@ def main():
     bytes_per_launch = rf["bytes_per_unit"] * rf["units"]
     avg_launch_s = rf["total_ms"] / work_launches / 1e3
     achieved = bytes_per_launch / avg_launch_s / 1e9
+    copy_gbs = copy_bandwidth_gbs()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(rf["kernel"]),
+                "copy_measured": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4),
                 "kernel": rf["kernel"], "avg_launch_us": round(avg_launch_s * 1e6, 2),
                 "bytes_per_launch": int(bytes_per_launch), "launches": rf["launches"],
                 "work_launches": work_launches, "events_pass_ms_per_step": round(1e3 * el_ev / args.steps, 3)}

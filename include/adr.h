@@ -191,6 +191,13 @@ adr_status adr_set_timing(adr_ctx *ctx, int32_t on);
 adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out,
                             int32_t reset);
 
+/* Measurement export (not part of the method): dst = src, `bytes` bytes of
+ * device memory (a multiple of 16; both pointers 16-byte aligned), a plain
+ * copy kernel queued on `stream` (hipStream_t, NULL = default): the measured
+ * HBM bandwidth against which the kernels' rooflines are also quoted.
+ * Errors: ADR_EINVAL (size or alignment), ADR_EDEVICE.  Asynchronous. */
+adr_status adr_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
+
 adr_status adr_destroy(adr_ctx *ctx);
 const char *adr_last_error(const adr_ctx *ctx);
 

@@ -20,7 +20,7 @@ PREC_FP64, PREC_FP32_LINES = 0, 1
 
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_autotune", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_set_timing", "adr_kernel_times",
-           "adr_destroy", "adr_last_error")
+           "adr_destroy", "adr_last_error", "adr_copy_probe")
 
 KERNEL_CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma", "norm")
 
@@ -77,6 +77,7 @@ def load():
     lib.adr_export_lines.argtypes = [vp, i32, i32, P(i64), P(i64), P(i64), P(dbl), P(dbl)]
     lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), i32]
     lib.adr_destroy.argtypes = [vp]
+    lib.adr_copy_probe.argtypes = [vp, vp, i64, vp]
     lib.adr_last_error.argtypes = [vp]
     lib.adr_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -96,6 +97,20 @@ def _device_ptr(t):
     if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
         raise TypeError("u must be a contiguous float64 device tensor")
     return C.c_void_p(t.data_ptr())
+
+
+def copy_probe(src, dst, stream=None):
+    """dst = src (device tensors of equal byte size) by the library's plain copy
+    kernel, queued on torch's current stream (measurement export)."""
+    import torch
+    lib = load()
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes or not (src.is_cuda and dst.is_cuda):
+        raise ValueError("copy_probe: two device tensors of equal size")
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    code = lib.adr_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, C.c_void_p(st))
+    if code != ADR_OK:
+        raise ADRError(code, "adr_copy_probe failed")
 
 
 class Solver:

@@ -372,3 +372,18 @@ def test_adaptive_schedule_reaches_the_fixed_point(name, maker, tol):
         assert rel_l2(U[off[i]:off[i + 1]], Ui) < 1e-5, i
     fixed.close()
     ada.close()
+
+
+def test_copy_probe_copies():
+    """The measurement copy (the bench's measured HBM bandwidth) copies exactly,
+    including a size that is not a multiple of the workgroup; bad sizes are
+    rejected."""
+    print("[case] copy probe", flush=True)
+    from paper_2411_11041_amd.adr import copy_probe, ADRError
+    a = torch.randn(1000003 * 4, dtype=torch.float32, device="cuda")
+    b = torch.zeros_like(a)
+    copy_probe(a, b)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+    with pytest.raises(ADRError):
+        copy_probe(a[:5], torch.zeros(5, dtype=torch.float32, device="cuda"))  # 20 bytes: not a multiple of 16
