@@ -58,8 +58,10 @@ def parse():
                     help="c2: one 2049^2 problem (default); c3: the 2049^2 parabolic march (200 steps); "
                          "c4: the 512-instance batch; "
                          "c5: learned warm start (train, then zero / eq. (11) / network starts)")
-    ap.add_argument("--train", type=int, default=2048, help="c5: training samples")
-    ap.add_argument("--epochs", type=int, default=40, help="c5: training epochs")
+    ap.add_argument("--train", type=int, default=8192, help="c5: training samples")
+    ap.add_argument("--epochs", type=int, default=400, help="c5: training epochs")
+    ap.add_argument("--coarsen", type=int, default=8,
+                    help="c5: the network runs on every coarsen-th node (1: on the 257x257 grid itself)")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--graph", action="store_true", help="replay sweep blocks from a HIP graph")
     ap.add_argument("--no-autotune", action="store_true",
@@ -168,15 +170,16 @@ def bench_c5(args):
     from paper_2411_11041_amd import warmstart as WS
     from paper_2411_11041_amd.adr import Net
     n, B = 257, 64
-    wl = WS.Workload(n=n, batch=128)
-    net = Net(n, n, 128)
+    wl = WS.Workload(n=n, batch=128, coarsen=args.coarsen)
+    Hc, Wc = wl.coarse_shape()
+    net = Net(Hc, Wc, 128)
     net.set_params(WS.he_init(0))
     t0 = time.time()
     x, t = wl.generate(net, list(range(args.train)), tol=1e-10)
     torch.cuda.synchronize()
     gen_s = time.time() - t0
     t0 = time.time()
-    losses = WS.train(net, x, t, wl.mask, args.train, wl.HW, args.epochs, batch=32, lr=2e-3, lr_end=2e-5)
+    losses = WS.train(net, x, t, wl.mask_c, args.train, wl.HWc, args.epochs, batch=32, lr=2e-3, lr_end=2e-5)
     torch.cuda.synchronize()
     train_s = time.time() - t0
     del x, t
@@ -196,7 +199,7 @@ def bench_c5(args):
     s = wl._bind(probs)
     g = torch.zeros(B * wl.HW, dtype=torch.float64, device="cuda")
     s.initial_guess(g)
-    x0, _, _ = net.pack(B, wl.f_tensor(probs), g, wl.mask, [p.mu for p in probs])
+    x0, _, _ = wl._net_inputs(net, B, wl.f_tensor(probs), g, [p.mu for p in probs])
     out = net.forward(B, x0)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     reps = 10
@@ -206,7 +209,7 @@ def bench_c5(args):
     e1.record()
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1) / reps
-    tflops = CNN_FLOP_PER_PIXEL * B * wl.HW / (fwd_ms * 1e-3) / 1e12
+    tflops = CNN_FLOP_PER_PIXEL * B * wl.HWc / (fwd_ms * 1e-3) / 1e12
     c = s.counts()
     per_sweep = (c["line_unknowns_b"] + c["line_unknowns_g"])
     value = per_sweep * res["network"]["sweeps_mean"] * 1.0 / (res["network"]["ms"] * 1e-3)
@@ -217,7 +220,8 @@ def bench_c5(args):
             "data": "synthetic",
             "config": {"workload": f"c5: {B} test seeds, unit square {n}x{n}, sigma=1, curved stream, "
                                    "mu logU[1e-3,1e-1], 1..8 Gaussians; solved to the tolerance from three starts",
-                       "tol": args.tol, "starts": res, "train_samples": args.train, "epochs": args.epochs,
+                       "tol": args.tol, "starts": res, "network_grid": f"{Hc}x{Wc} (every {args.coarsen}th node)",
+                       "train_samples": args.train, "epochs": args.epochs,
                        "final_train_loss": losses[-1], "gen_s": round(gen_s, 1), "train_s": round(train_s, 1),
                        "train_samples_per_s": round(args.train * args.epochs / train_s, 1),
                        "forward_ms_batch64": round(fwd_ms, 3)},

@@ -89,6 +89,32 @@ adr_status adrnn_train_step(adrnn_ctx *ctx, int32_t B, const void *x0, const flo
 adr_status adrnn_warm_start(adrnn_ctx *ctx, int32_t B, const double *s, const double *s_norm, const float *out,
                             const uint8_t *mask, double *u);
 
+/* Coarse-grid use of the network.  The context's H x W pixels are then the
+ * nodes of a coarse grid inside a fine grid of Hf = r (H - 1) + 1 by
+ * Wf = r (W - 1) + 1 nodes (integer factor r >= 1), coarse node (i, j) lying
+ * on fine node (r i, r j); the network sees the problem on the coarse grid,
+ * where its 31 x 31 receptive field spans 31 r fine nodes.  Not in the paper:
+ * the grid transfers of the multigrid literature (full weighting, bilinear
+ * interpolation).
+ *
+ * adrnn_restrict: coarse (FP64, B*H*W) = R fine (FP64, B*Hf*Wf).  At interior
+ * coarse nodes R is the tent-weighted mean of the (2r - 1)^2 fine nodes
+ * around the coincident fine node, weight (r - |dy|)(r - |dx|) / r^4; boundary
+ * coarse nodes take the coincident fine value.  r = 1 copies.  EINVAL when
+ * Wf > 8192 or B*Hf*Wf > 2^31. */
+adr_status adrnn_restrict(adrnn_ctx *ctx, int32_t B, int32_t r, const double *fine, double *coarse);
+
+/* adrnn_warm_start for a network run on the coarse grid: u (FP64, B*Hf*Wf) =
+ * s + |s|_inf * (P out) on the fine pixels where mask (uint8, Hf*Wf) is set,
+ * 0 elsewhere, P the bilinear interpolation of out (FP32, B*H*W, coarse) at
+ * the fine nodes, evaluated in FP64:
+ *   (P out)(r i + a, r j + c) = [(r-a)(r-c) o(i,j) + (r-a) c o(i,j+1)
+ *                                + a (r-c) o(i+1,j) + a c o(i+1,j+1)] / r^2.
+ * s, s_norm as in adrnn_warm_start (s_norm from adrnn_pack on the restricted
+ * s).  r = 1 gives adrnn_warm_start.  EINVAL when B*Hf*Wf > 2^31. */
+adr_status adrnn_warm_start_prolong(adrnn_ctx *ctx, int32_t B, int32_t r, const double *s, const double *s_norm,
+                                    const float *out, const uint8_t *mask, double *u);
+
 /* Test export: D (16x16 FP32, row-major) = A (16x16 BF16, row-major) * B
  * (16x16 BF16, row-major) on one wavefront through the same matrix-core
  * instruction and operand layout the convolutions use. */

@@ -250,7 +250,8 @@ class Solver:
 # learned warm start (include/adrnn.h)
 NN_EXPORTS = ("adrnn_param_count", "adrnn_create", "adrnn_destroy", "adrnn_set_params", "adrnn_get_params",
               "adrnn_pack", "adrnn_forward", "adrnn_grads", "adrnn_adam", "adrnn_train_step", "adrnn_loss_sum",
-              "adrnn_warm_start", "adrnn_mfma_probe", "adrnn_last_error")
+              "adrnn_warm_start", "adrnn_restrict", "adrnn_warm_start_prolong", "adrnn_mfma_probe",
+              "adrnn_last_error")
 
 _nn_ready = False
 
@@ -273,6 +274,8 @@ def _load_nn():
     lib.adrnn_train_step.argtypes = [vp, i32, vp, vp, vp, C.c_float, P(C.c_double)]
     lib.adrnn_loss_sum.argtypes = [vp, P(C.c_double), P(C.c_int64), i32]
     lib.adrnn_warm_start.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    lib.adrnn_restrict.argtypes = [vp, i32, i32, vp, vp]
+    lib.adrnn_warm_start_prolong.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
     lib.adrnn_mfma_probe.argtypes = [vp, vp, vp, vp]
     lib.adrnn_last_error.argtypes = [vp]
     lib.adrnn_last_error.restype = C.c_char_p
@@ -361,6 +364,23 @@ class Net:
 
     def warm_start(self, B, s, s_norm, out, mask, u):
         self._check(self.lib.adrnn_warm_start(self.ctx, B, _dp(s), _dp(s_norm), _dp(out), _dp(mask), _dp(u)))
+
+    def fine_shape(self, r):
+        """Fine grid (rows, columns) whose every r-th node is this context's grid."""
+        return r * (self.H - 1) + 1, r * (self.W - 1) + 1
+
+    def restrict(self, B, r, fine, coarse=None):
+        """Coarse FP64 grids (B*H*W) from fine FP64 grids (B*Hf*Wf); include/adrnn.h."""
+        import torch
+        if coarse is None:
+            coarse = torch.empty(B * self.H * self.W, dtype=torch.float64, device="cuda")
+        self._check(self.lib.adrnn_restrict(self.ctx, B, r, _dp(fine), _dp(coarse)))
+        return coarse
+
+    def warm_start_prolong(self, B, r, s, s_norm, out, mask, u):
+        """u (fine) = s + |s|_inf * bilinear(out) on the fine mask; include/adrnn.h."""
+        self._check(self.lib.adrnn_warm_start_prolong(self.ctx, B, r, _dp(s), _dp(s_norm), _dp(out), _dp(mask),
+                                                      _dp(u)))
 
     def close(self):
         if self.ctx:

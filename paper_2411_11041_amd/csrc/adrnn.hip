@@ -37,6 +37,8 @@ constexpr int kW1 = 32 * 9 * 4, kW2 = 32 * 9 * 32, kW4 = 9 * 32;
 constexpr int oW1 = 0, ob1 = oW1 + kW1, oW2 = ob1 + 32, ob2 = oW2 + kW2, oW3 = ob2 + 32, ob3 = oW3 + kW2,
               oW4 = ob3 + 32, ob4 = oW4 + kW4, kParams = ob4 + 1;
 constexpr int kDil[4] = {1, 2, 4, 8};
+// widest fine grid of adrnn_restrict (one FP64 row of column sums in 64 KB of LDS)
+constexpr int kMaxRestrictWidth = 8192;
 
 // FP32 -> BF16, round to nearest even: the gfx950 conversion instruction
 // (v_cvt_pk_bf16_f32), one value or a packed pair (low half: a)
@@ -953,6 +955,72 @@ __global__ void k_warm(const double *__restrict__ s, const double *__restrict__ 
     u[gp] = mask[gp - b * HW] ? s[gp] + sn[b] * static_cast<double>(out[gp]) : 0.0;
 }
 
+// Coarse grid of H x W nodes inside a fine grid of Hf = r (H - 1) + 1 by
+// Wf = r (W - 1) + 1 nodes, coarse node (i, j) on fine node (r i, r j).
+// Restriction: interior coarse nodes take the tent-weighted mean over the
+// (2r - 1)^2 fine nodes around their fine node, weights (r - |dy|)(r - |dx|) / r^4
+// (separable, each factor summing to one); boundary coarse nodes take their
+// fine node's value.  One workgroup per (coarse row, image): the column
+// sums of the row's fine band go to LDS with coalesced row reads, then the
+// row sums are formed from LDS.
+__global__ void k_restrict(const double *__restrict__ fine, double *__restrict__ coarse, int H, int W, int r) {
+    extern __shared__ double colsum[];  // Wf
+    const int i = blockIdx.x, b = blockIdx.y;
+    const int Hf = r * (H - 1) + 1, Wf = r * (W - 1) + 1;
+    const double *fb = fine + static_cast<size_t>(b) * Hf * Wf;
+    double *cb = coarse + (static_cast<size_t>(b) * H + i) * W;
+    const double inv = 1.0 / (static_cast<double>(r) * r);
+    const bool edge = i == 0 || i == H - 1;
+    if (!edge) {
+        for (int x = threadIdx.x; x < Wf; x += blockDim.x) {
+            const double *p = fb + static_cast<size_t>(r * i) * Wf + x;
+            double acc = r * p[0];
+            for (int d = 1; d < r; ++d) acc += (r - d) * (p[-static_cast<ptrdiff_t>(d) * Wf] + p[static_cast<ptrdiff_t>(d) * Wf]);
+            colsum[x] = acc * inv;
+        }
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < W; j += blockDim.x) {
+        double v;
+        if (edge || j == 0 || j == W - 1) {
+            v = fb[static_cast<size_t>(r * i) * Wf + r * j];
+        } else {
+            const double *q = colsum + r * j;
+            v = r * q[0];
+            for (int d = 1; d < r; ++d) v += (r - d) * (q[-d] + q[d]);
+            v *= inv;
+        }
+        cb[j] = v;
+    }
+}
+
+// u = s + |s|_inf * (P out) on interior fine nodes, 0 elsewhere; P the
+// bilinear interpolation of the coarse output at the fine nodes.
+__global__ void k_warm_prolong(const double *__restrict__ s, const double *__restrict__ sn,
+                               const float *__restrict__ out, const uint8_t *__restrict__ mask, double *__restrict__ u,
+                               int H, int W, int r, int B) {
+    const int Hf = r * (H - 1) + 1, Wf = r * (W - 1) + 1;
+    const size_t HWf = static_cast<size_t>(Hf) * Wf;
+    const size_t gp = static_cast<size_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gp >= HWf * B) return;
+    const int b = static_cast<int>(gp / HWf);
+    const int p = static_cast<int>(gp - b * HWf);
+    if (!mask[p]) {
+        u[gp] = 0.0;
+        return;
+    }
+    const int y = p / Wf, x = p - y * Wf;
+    const int i0 = y / r, j0 = x / r, fy = y - i0 * r, fx = x - j0 * r;
+    const int i1 = min(i0 + 1, H - 1), j1 = min(j0 + 1, W - 1);  // weight 0 when clamped
+    const float *o = out + static_cast<size_t>(b) * H * W;
+    const double v = (static_cast<double>((r - fy) * (r - fx)) * o[i0 * W + j0] +
+                      static_cast<double>((r - fy) * fx) * o[i0 * W + j1] +
+                      static_cast<double>(fy * (r - fx)) * o[i1 * W + j0] +
+                      static_cast<double>(fy * fx) * o[i1 * W + j1]) /
+                     (static_cast<double>(r) * r);
+    u[gp] = s[gp] + sn[b] * v;
+}
+
 __global__ void k_probe(const bf16_t *__restrict__ A, const bf16_t *__restrict__ B, float *__restrict__ D) {
     const int l = threadIdx.x, i = l & 15, g = l >> 4;
     v4i16 a, b;
@@ -1322,6 +1390,36 @@ adr_status adrnn_warm_start(adrnn_ctx *c, int32_t B, const double *s, const doub
     try {
         const int HW = c->H * c->W, NP = B * HW;
         hipLaunchKernelGGL(k_warm, dim3((NP + 255) / 256), dim3(256), 0, c->st, s, s_norm, out, mask, u, NP, HW);
+        NNCHK(hipGetLastError());
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_restrict(adrnn_ctx *c, int32_t B, int32_t r, const double *fine, double *coarse) {
+    if (!c || B < 1 || B > c->maxB || r < 1 || !fine || !coarse) return ADR_EINVAL;
+    try {
+        const int64_t Wf = static_cast<int64_t>(r) * (c->W - 1) + 1, Hf = static_cast<int64_t>(r) * (c->H - 1) + 1;
+        if (Wf > kMaxRestrictWidth || Hf * Wf * B > (int64_t(1) << 31))
+            throw NNError{ADR_EINVAL, "fine grid too large for adrnn_restrict"};
+        hipLaunchKernelGGL(k_restrict, dim3(c->H, B), dim3(256), sizeof(double) * Wf, c->st, fine, coarse, c->H, c->W,
+                           static_cast<int>(r));
+        NNCHK(hipGetLastError());
+        return ADR_OK;
+    } catch (const NNError &e) {
+        return fail(c, e);
+    }
+}
+
+adr_status adrnn_warm_start_prolong(adrnn_ctx *c, int32_t B, int32_t r, const double *s, const double *s_norm,
+                                    const float *out, const uint8_t *mask, double *u) {
+    if (!c || B < 1 || B > c->maxB || r < 1 || !s || !s_norm || !out || !mask || !u) return ADR_EINVAL;
+    try {
+        const int64_t NPf = (static_cast<int64_t>(r) * (c->H - 1) + 1) * (static_cast<int64_t>(r) * (c->W - 1) + 1) * B;
+        if (NPf > (int64_t(1) << 31)) throw NNError{ADR_EINVAL, "fine grid too large for adrnn_warm_start_prolong"};
+        hipLaunchKernelGGL(k_warm_prolong, dim3(static_cast<unsigned>((NPf + 255) / 256)), dim3(256), 0, c->st, s,
+                           s_norm, out, mask, u, c->H, c->W, static_cast<int>(r), static_cast<int>(B));
         NNCHK(hipGetLastError());
         return ADR_OK;
     } catch (const NNError &e) {

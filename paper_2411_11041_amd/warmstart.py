@@ -9,6 +9,13 @@ mu log-uniform in [1e-3, 1e-1], a mixture of 1..8 Gaussians as source
 (seeded per sample).  All samples share the grid, the domain and beta, so one
 solver context (one set of traced curves) serves every batch: adr_update swaps
 in each batch's mu and f.
+
+With coarsen = r > 1 the network sees every sample on the grid of every r-th
+node: f, the eq. (11) iterate s and the converged solution are restricted by
+full weighting (adrnn_restrict), the network runs on that coarse grid, and
+its output is interpolated bilinearly back to the fine nodes inside the warm
+start (adrnn_warm_start_prolong).  The network's context is then created for
+the coarse grid (coarse_shape()).
 """
 from __future__ import annotations
 
@@ -22,8 +29,10 @@ from .adr import Net, Solver
 
 
 class Workload:
-    def __init__(self, n=257, batch=128, precision="fp32", fp32_sweeps=3, dt=0.05, graph=True):
+    def __init__(self, n=257, batch=128, precision="fp32", fp32_sweeps=3, dt=0.05, graph=True, coarsen=1):
         import torch
+        if coarsen < 1 or (n - 1) % coarsen:
+            raise ValueError(f"coarsening factor {coarsen} does not divide {n - 1}")
         self.n = n
         self.batch = batch
         grid = W._grid(n)
@@ -33,6 +42,13 @@ class Workload:
         mask[1:-1, 1:-1] = 1
         self.mask_np = mask
         self.mask = torch.from_numpy(mask.ravel()).cuda()
+        # the network's grid: every coarsen-th node (the fine grid when 1)
+        self.r = coarsen
+        self.nc = (n - 1) // coarsen + 1
+        self.HWc = self.nc * self.nc
+        mc = np.zeros((self.nc, self.nc), np.uint8)
+        mc[1:-1, 1:-1] = 1
+        self.mask_c = torch.from_numpy(mc.ravel()).cuda()
         self.kw = dict(precision=precision, fp32_sweeps=fp32_sweeps, theta=1.0, dt=dt, graph=graph)
         self.solver = None
 
@@ -65,16 +81,30 @@ class Workload:
         torch.cuda.synchronize()
         return u, it, rel, time.perf_counter() - t0
 
+    def coarse_shape(self):
+        """(H, W) of the network's context."""
+        return self.nc, self.nc
+
+    def _net_inputs(self, net, B, f, g, mu, u_star=None):
+        """pack() on the network's grid (restricted fields when coarsened)."""
+        if self.r > 1:
+            f, g = net.restrict(B, self.r, f), net.restrict(B, self.r, g)
+            if u_star is not None:
+                u_star = net.restrict(B, self.r, u_star)
+        return net.pack(B, f, g, self.mask_c, mu, u_star=u_star)
+
     def f_tensor(self, probs):
         import torch
         return torch.from_numpy(np.concatenate([p.f.ravel() for p in probs])).cuda()
 
     def generate(self, net, seeds, tol=1e-10, log=None):
-        """Network inputs x0 (BF16 bits) and targets for the given seeds."""
+        """Network inputs x0 (BF16 bits) and targets for the given seeds, on
+        the network's grid."""
         import torch
         N = len(seeds)
-        x_all = torch.empty(N * self.HW * 4, dtype=torch.int16, device="cuda")
-        t_all = torch.empty(N * self.HW, dtype=torch.float32, device="cuda")
+        HWc = self.HWc
+        x_all = torch.empty(N * HWc * 4, dtype=torch.int16, device="cuda")
+        t_all = torch.empty(N * HWc, dtype=torch.float32, device="cuda")
         for c0 in range(0, N, self.batch):
             cs = seeds[c0:c0 + self.batch]
             B = len(cs)
@@ -84,9 +114,9 @@ class Workload:
             it, rel, _ = s.split_iterate(u, 3000, tol)
             g = torch.zeros_like(u)
             s.initial_guess(g)
-            x0, tgt, _ = net.pack(B, self.f_tensor(probs), g, self.mask, [p.mu for p in probs], u_star=u)
-            x_all[c0 * self.HW * 4:(c0 + B) * self.HW * 4] = x0
-            t_all[c0 * self.HW:(c0 + B) * self.HW] = tgt
+            x0, tgt, _ = self._net_inputs(net, B, self.f_tensor(probs), g, [p.mu for p in probs], u_star=u)
+            x_all[c0 * HWc * 4:(c0 + B) * HWc * 4] = x0
+            t_all[c0 * HWc:(c0 + B) * HWc] = tgt
             if log:
                 log(f"generated {c0 + B}/{N} (sweeps max {int(it.max())}, rel max {rel.max():.1e})")
         return x_all, t_all
@@ -110,10 +140,13 @@ class Workload:
         s.initial_guess(g)
         fallback = 0
         if use_net:
-            x0, _, sn = net.pack(B, f, g, self.mask, [p.mu for p in probs])
+            x0, _, sn = self._net_inputs(net, B, f, g, [p.mu for p in probs])
             out = net.forward(B, x0)
             u = torch.empty_like(g)
-            net.warm_start(B, g, sn, out, self.mask, u)
+            if self.r > 1:
+                net.warm_start_prolong(B, self.r, g, sn, out, self.mask, u)
+            else:
+                net.warm_start(B, g, sn, out, self.mask, u)
             r_net = s.residual(u, allow_nonfinite=True)
             r_s = s.residual(g, allow_nonfinite=True)
             for b in np.nonzero(~(r_net < r_s))[0]:

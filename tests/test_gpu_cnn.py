@@ -185,3 +185,54 @@ def test_multi_tile_gradients_equal_mean_of_single_images():
         assert rel(gW[l], aW[l]) < 1e-5, (l, rel(gW[l], aW[l]))
         assert rel(gb[l], ab[l]) < 1e-5, (l, rel(gb[l], ab[l]))
     net.close()
+
+
+@pytest.mark.parametrize("r,H,W,B", [(1, 9, 7, 2), (2, 11, 6, 3), (4, 17, 13, 2), (8, 33, 33, 5), (3, 4, 3, 1)])
+def test_restrict_matches_oracle(r, H, W, B):
+    print(f"[case] restrict r={r} coarse {H}x{W} B={B}", flush=True)
+    from paper_2411_11041_amd.adr import Net
+    from oracle import coarse
+    rng = np.random.default_rng(10 + r)
+    Hf, Wf = r * (H - 1) + 1, r * (W - 1) + 1
+    x = rng.standard_normal((B, Hf, Wf))
+    net = Net(H, W, B)
+    got = net.restrict(B, r, dev(x.ravel())).cpu().numpy().reshape(B, H, W)
+    want = coarse.restrict(x, r)
+    # boundary nodes are copies; interior nodes differ from the oracle only in summation order
+    assert np.array_equal(got[:, [0, -1], :], want[:, [0, -1], :])
+    assert np.array_equal(got[:, :, [0, -1]], want[:, :, [0, -1]])
+    assert np.max(np.abs(got - want)) <= 1e-14 * max(1.0, np.max(np.abs(x)))
+
+
+@pytest.mark.parametrize("r,H,W,B", [(1, 9, 7, 2), (2, 11, 6, 3), (8, 33, 33, 4), (5, 3, 4, 1)])
+def test_warm_start_prolong_matches_oracle(r, H, W, B):
+    print(f"[case] warm_start_prolong r={r} coarse {H}x{W} B={B}", flush=True)
+    from paper_2411_11041_amd.adr import Net
+    from oracle import coarse
+    rng = np.random.default_rng(20 + r)
+    Hf, Wf = r * (H - 1) + 1, r * (W - 1) + 1
+    s = rng.standard_normal((B, Hf, Wf))
+    sn = np.abs(rng.standard_normal(B)) + 0.5
+    out = rng.standard_normal((B, H, W)).astype(np.float32)
+    mask = (rng.random((Hf, Wf)) < 0.8).astype(np.uint8)
+    net = Net(H, W, B)
+    u = torch.full((B * Hf * Wf,), np.nan, dtype=torch.float64, device="cuda")
+    net.warm_start_prolong(B, r, dev(s.ravel()), dev(sn), dev(out.ravel(), torch.float32), dev(mask, torch.uint8), u)
+    got = u.cpu().numpy().reshape(B, Hf, Wf)
+    want = coarse.warm_start_prolong(s, sn, out, mask, r)
+    assert np.all(got[:, mask == 0] == 0)
+    assert np.max(np.abs(got - want)) <= 1e-14 * max(1.0, np.max(np.abs(want)))
+
+
+def test_coarse_transfers_reject_bad_arguments():
+    print("[case] coarse transfers: argument checks", flush=True)
+    from paper_2411_11041_amd.adr import ADRError, Net
+    net = Net(5, 5, 2)
+    x = torch.zeros(2 * 17 * 17, dtype=torch.float64, device="cuda")
+    with pytest.raises(ADRError):
+        net.restrict(2, 0, x)
+    with pytest.raises(ADRError):
+        net.restrict(3, 4, x)   # batch above the context's maximum
+    big = Net(3, 3, 1)
+    with pytest.raises(ADRError):
+        big.restrict(1, 5000, x)  # fine width 10001 > 8192

@@ -19,18 +19,21 @@ TRAIN = list(range(0, 256))
 TEST = list(range(20000, 20016))
 
 
-@pytest.fixture(scope="module")
-def trained():
+@pytest.fixture(scope="module", params=[1, 4], ids=["fine", "coarse4"])
+def trained(request):
+    """The network on the 129^2 grid itself, and on every 4th node (33^2)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2411_11041_amd import warmstart as WS
     from paper_2411_11041_amd.adr import Net
-    print("[case] warm start: generate 256 samples 129^2, train 12 epochs", flush=True)
-    wl = WS.Workload(n=N_GRID, batch=64)
-    net = Net(N_GRID, N_GRID, 64)
+    r = request.param
+    print(f"[case] warm start: generate 256 samples 129^2, network grid every {r} nodes, train 12 epochs",
+          flush=True)
+    wl = WS.Workload(n=N_GRID, batch=64, coarsen=r)
+    net = Net(*wl.coarse_shape(), 64)
     net.set_params(WS.he_init(0))
     x, t = wl.generate(net, TRAIN, tol=1e-10)
-    losses = WS.train(net, x, t, wl.mask, len(TRAIN), wl.HW, 12, batch=32, lr=2e-3, lr_end=1e-4)
+    losses = WS.train(net, x, t, wl.mask_c, len(TRAIN), wl.HWc, 12, batch=32, lr=2e-3, lr_end=1e-4)
     yield wl, net, losses
     net.close()
     wl.solver.close()
@@ -72,10 +75,13 @@ def test_network_start_is_closer_than_zero(trained):
     B = len(TEST)
     g = torch.zeros(B * wl.HW, dtype=torch.float64, device="cuda")
     s.initial_guess(g)
-    x0, _, sn = net.pack(B, wl.f_tensor(probs), g, wl.mask, [p.mu for p in probs])
+    x0, _, sn = wl._net_inputs(net, B, wl.f_tensor(probs), g, [p.mu for p in probs])
     out = net.forward(B, x0)
     u = torch.empty_like(g)
-    net.warm_start(B, g, sn, out, wl.mask, u)
+    if wl.r > 1:
+        net.warm_start_prolong(B, wl.r, g, sn, out, wl.mask, u)
+    else:
+        net.warm_start(B, g, sn, out, wl.mask, u)
     e_net = float(torch.linalg.norm(u - u_ref) / torch.linalg.norm(u_ref))
     e_s = float(torch.linalg.norm(g - u_ref) / torch.linalg.norm(u_ref))
     print(f"[case] relative L2 error of the start: eq. (11) {e_s:.3e}, network {e_net:.3e}", flush=True)
