@@ -141,6 +141,22 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs);
 adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol,
                              int32_t *iters, double *rel_res);
 
+/* adr_split_iterate from the start u, judged by the method's own residual
+ * against a fallback start (a predicted start judged against the eq. (11)
+ * iterate, say).  The FP64 residual of fallback (as adr_residual) is computed
+ * first.  The first sweep from u then yields u's residual.  Every instance
+ * whose residual is not below the fallback's, or is not finite, restarts from
+ * its fallback values.  The restart costs one more FP64 sweep, which the other
+ * unfinished instances take as a sweep of their own.  Each instance then
+ * iterates as in adr_split_iterate to the same fixed point.
+ *   fallback: device FP64, packed layout (read only).
+ *   used_fallback: host, n_probs (may be NULL); 1 where the instance restarted.
+ *   iters: counts every sweep, the restart's included.
+ * Otherwise as adr_split_iterate; max_iters >= 1.  Synchronises once more
+ * than adr_split_iterate (after the first sweep). */
+adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallback, int32_t max_iters,
+                                    double tol, int32_t *iters, double *rel_res, int32_t *used_fallback);
+
 /* Autotuner of the batched stationary solve (FP32_LINES precision only): for
  * each candidate schedule -- a fixed count of FP32 sweeps per FP64 sweep (2, 3,
  * 4, 6) and, in eager mode, the adaptive schedule with at most 6, 8, 12, 16 or 24 --

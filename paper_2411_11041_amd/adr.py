@@ -18,7 +18,8 @@ ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE, ADR_EBETA, ADR_ENONFINITE, ADR_ENOT
 DOM_BOX, DOM_DISC, DOM_POLYGON = 0, 1, 2
 PREC_FP64, PREC_FP32_LINES = 0, 1
 
-EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_autotune", "adr_time_step",
+EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
+           "adr_autotune", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_set_timing", "adr_kernel_times",
            "adr_destroy", "adr_last_error", "adr_copy_probe")
 
@@ -69,6 +70,7 @@ def load():
     lib.adr_counts.argtypes = [vp, P(i64), P(i64), P(i64), P(i64), P(i64)]
     lib.adr_update.argtypes = [vp, P(Problem), i32]
     lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
+    lib.adr_split_iterate_judged.argtypes = [vp, vp, vp, i32, dbl, P(i32), P(dbl), P(i32)]
     lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl)]
     lib.adr_set_timing.argtypes = [vp, i32]
     lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32]
@@ -195,6 +197,19 @@ class Solver:
                                         iters.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(rel))
         self._check(st, ok=(ADR_OK, ADR_ENOTCONV))
         return iters, rel, st
+
+    def split_iterate_judged(self, u, fallback, max_iters, tol):
+        """split_iterate from u; instances whose start has a residual not below
+        the fallback's restart from the fallback (include/adr.h).  Returns
+        iters, rel, status, used_fallback."""
+        iters = np.zeros(self.n, np.int32)
+        rel = np.zeros(self.n, np.float64)
+        used = np.zeros(self.n, np.int32)
+        st = self.lib.adr_split_iterate_judged(self.ctx, _device_ptr(u), _device_ptr(fallback), int(max_iters),
+                                               float(tol), iters.ctypes.data_as(C.POINTER(C.c_int32)), _dptr(rel),
+                                               used.ctypes.data_as(C.POINTER(C.c_int32)))
+        self._check(st, ok=(ADR_OK, ADR_ENOTCONV))
+        return iters, rel, st, used
 
     def time_step(self, u, theta, dt, nsteps):
         self._check(self.lib.adr_time_step(self.ctx, _device_ptr(u), float(theta), float(dt), int(nsteps)))

@@ -99,6 +99,7 @@ struct adr_ctx {
     double *par = nullptr;  // [slot][fam][inst][8]
     std::vector<double> par_h;
     double *Uh64 = nullptr, *Z64 = nullptr, *partial = nullptr, *cnorm = nullptr, *rel = nullptr;
+    double *rel_fb = nullptr;  // residual of a fallback start (adr_split_iterate_judged)
     float *d32 = nullptr, *D32 = nullptr;
     int *done = nullptr, *never = nullptr, *conv_it = nullptr;
     double last_theta = -1, last_dt = -1;
@@ -626,6 +627,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         }
         C->cnorm = dalloc<double>(n, own);
         C->rel = dalloc<double>(n, own);
+        C->rel_fb = dalloc<double>(n, own);
         C->done = dalloc<int>(n, own);
         C->never = dalloc<int>(n, own);
         C->conv_it = dalloc<int>(n, own);
@@ -737,13 +739,10 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs) {
     }
 }
 
-adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol, int32_t *iters,
-                             double *rel_res) {
-    if (!ctx) return ADR_EINVAL;
-    if (!u || max_iters < 0 || !(tol >= 0.0)) {
-        ctx->err = "u, max_iters >= 0 and tol >= 0 are required";
-        return ADR_EINVAL;
-    }
+// The stationary iteration; with a fallback start, the start u is judged by
+// the first sweep (see adr_split_iterate_judged).
+static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback, int32_t max_iters, double tol,
+                                int32_t *iters, double *rel_res, int32_t *used_fallback) {
     try {
         const int n = ctx->n_inst;
         hipStream_t user = ctx->st;
@@ -772,9 +771,47 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
             return std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; });
         };
         double *const ub = ctx->Ub;
+        if (fallback) {
+            // the fallback's residual, kept aside: an FP64 sweep that leaves the state alone
+            ctx->to_blocked(fallback);
+            ctx->sweep64(kSlotStep, ub, ub, 3, ctx->never);
+            ctx->norm(0, 0.0, 2);
+            HIPCHK(hipMemcpyAsync(ctx->rel_fb, ctx->rel, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        }
         ctx->to_blocked(u);
         if (max_iters > 0) {
             ctx->block(ub, 0, tol);  // first FP64 sweep
+            if (fallback) {
+                // its update is the start's residual: an instance whose residual is
+                // not below the fallback's (or not finite) restarts from the fallback
+                std::vector<double> rn(n), rf(n);
+                HIPCHK(hipMemcpyAsync(rn.data(), ctx->rel, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(rf.data(), ctx->rel_fb, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                bool any = false;
+                for (int i = 0; i < n; ++i) {
+                    const bool back = !(rn[i] < rf[i]);
+                    if (used_fallback) used_fallback[i] = back ? 1 : 0;
+                    if (back) {
+                        any = true;
+                        dn[i] = 0;
+                    }
+                }
+                if (any) {
+                    ctx->from_blocked(u);  // u = Phi(start) on every instance
+                    for (int i = 0; i < n; ++i)
+                        if (used_fallback ? used_fallback[i] : !(rn[i] < rf[i]))
+                            HIPCHK(hipMemcpyAsync(u + ctx->goff[i], fallback + ctx->goff[i],
+                                                  sizeof(double) * (ctx->goff[i + 1] - ctx->goff[i]),
+                                                  hipMemcpyDeviceToDevice, st));
+                    ctx->to_blocked(u);
+                    HIPCHK(hipMemcpyAsync(ctx->done, dn.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+                    // one more first sweep: from the fallback where restarted, a second
+                    // sweep for the other unfinished instances
+                    ctx->block(ub, 0, tol);
+                }
+            }
             const int blocks = (max_iters - 1) / period;
             const int check = std::max(1, 8 / period);
             if (use_graph && blocks > 0 && (ctx->g_u != ub || ctx->g_tol != tol || ctx->g_m != m || !ctx->gexec)) {
@@ -824,6 +861,26 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
         if (ctx->opt.graph) ctx->st = static_cast<hipStream_t>(ctx->opt.stream);
         return fail_ctx(ctx, e);
     }
+}
+
+adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol, int32_t *iters,
+                             double *rel_res) {
+    if (!ctx) return ADR_EINVAL;
+    if (!u || max_iters < 0 || !(tol >= 0.0)) {
+        ctx->err = "u, max_iters >= 0 and tol >= 0 are required";
+        return ADR_EINVAL;
+    }
+    return split_iterate(ctx, u, nullptr, max_iters, tol, iters, rel_res, nullptr);
+}
+
+adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallback, int32_t max_iters, double tol,
+                                    int32_t *iters, double *rel_res, int32_t *used_fallback) {
+    if (!ctx) return ADR_EINVAL;
+    if (!u || !fallback || max_iters < 1 || !(tol >= 0.0) || ctx->opt.host_only) {
+        ctx->err = "u, fallback, max_iters >= 1, tol >= 0 and a device context are required";
+        return ADR_EINVAL;
+    }
+    return split_iterate(ctx, u, fallback, max_iters, tol, iters, rel_res, used_fallback);
 }
 
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,

@@ -124,10 +124,11 @@ class Workload:
     def warm_started(self, net, seeds, tol, max_iters=2000, use_net=True):
         """Solve from the eq. (11) iterate, corrected by the network when use_net.
 
-        The splitting residual judges the start: where the network's start has
-        a larger FP64 update than the eq. (11) iterate, that instance falls
-        back to the eq. (11) iterate.  Timed from the first call (inference
-        included).  Returns u, iters, rel, seconds, fallbacks.
+        The splitting residual judges the start (adr_split_iterate_judged):
+        an instance whose network start has an FP64 update not below the
+        eq. (11) iterate's restarts from the eq. (11) iterate.  Timed from the
+        first call (inference included).  Returns u, iters, rel, seconds,
+        fallbacks.
         """
         import torch
         probs = self.problems(seeds)
@@ -147,14 +148,11 @@ class Workload:
                 net.warm_start_prolong(B, self.r, g, sn, out, self.mask, u)
             else:
                 net.warm_start(B, g, sn, out, self.mask, u)
-            r_net = s.residual(u, allow_nonfinite=True)
-            r_s = s.residual(g, allow_nonfinite=True)
-            for b in np.nonzero(~(r_net < r_s))[0]:
-                u[b * self.HW:(b + 1) * self.HW] = g[b * self.HW:(b + 1) * self.HW]
-                fallback += 1
+            it, rel, _, used = s.split_iterate_judged(u, g, max_iters, tol)
+            fallback = int(used.sum())
         else:
             u = g
-        it, rel, _ = s.split_iterate(u, max_iters, tol)
+            it, rel, _ = s.split_iterate(u, max_iters, tol)
         torch.cuda.synchronize()
         return u, it, rel, time.perf_counter() - t0, fallback
 

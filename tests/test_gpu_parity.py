@@ -374,6 +374,64 @@ def test_adaptive_schedule_reaches_the_fixed_point(name, maker, tol):
     ada.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_judged_iterate_keeps_a_better_start_bitwise(precision):
+    """A start whose residual is below the fallback's is kept: the judged solve
+    then equals the plain solve from that start, bitwise and in sweep count
+    (the fallback's residual sweep leaves the state alone)."""
+    print(f"[case] judged iterate, better start kept ({precision})", flush=True)
+    probs = [W.c1(33), W.c2(65), W.c4_instance(2, n_max=100)]
+    kw = dict(precision=precision, theta=1.0, dt=0.05)
+    if precision == "fp32":
+        kw["fp32_sweeps"] = 3
+    tol = 1e-9
+    s = solver(probs, **kw)
+    off = s.layout()
+    start = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    s.split_iterate(start, 6, 0.0)  # six sweeps from zero: residual below zero's (1)
+    zero = torch.zeros_like(start)
+    u_p = start.clone()
+    it_p, rel_p, st_p = s.split_iterate(u_p, 2000, tol)
+    u_j = start.clone()
+    it_j, rel_j, st_j, used = s.split_iterate_judged(u_j, zero, 2000, tol)
+    torch.cuda.synchronize()
+    assert st_p == 0 and st_j == 0
+    assert not used.any()
+    assert np.array_equal(it_j, it_p)
+    assert torch.equal(u_j, u_p)
+    s.close()
+
+
+def test_judged_iterate_restarts_worse_starts():
+    """Instances whose start is worse than the fallback (a NaN start, a start
+    far from the solution) restart from the fallback (the eq. (11) iterate);
+    the others keep theirs.  Every instance converges to the plain solve's
+    fixed point."""
+    print("[case] judged iterate, worse starts restart", flush=True)
+    probs = [W.c1(33), W.c2(65), W.c4_instance(2, n_max=100), W.c4_instance(5, n_max=140)]
+    s = solver(probs, precision="fp64", theta=1.0, dt=0.05)
+    off = [int(v) for v in s.layout()]
+    g = torch.zeros(off[-1], dtype=torch.float64, device="cuda")
+    s.initial_guess(g)
+    ref = g.clone()
+    s.split_iterate(ref, 3000, 1e-13)
+    u = g + 0.9 * (ref - g)  # closer than the eq. (11) iterate on every instance
+    u[off[0]:off[1]] = float("nan")
+    rng = np.random.default_rng(0)
+    u[off[2]:off[3]] += torch.from_numpy(10.0 * rng.standard_normal(off[3] - off[2])).cuda()
+    tol = 1e-10
+    it, rel, st, used = s.split_iterate_judged(u, g, 3000, tol)
+    torch.cuda.synchronize()
+    assert list(used) == [1, 0, 1, 0]
+    assert st == 0 and np.all(rel <= tol)
+    assert torch.isfinite(u).all()
+    a, b = u.cpu().numpy(), ref.cpu().numpy()
+    for i in range(len(probs)):
+        e = np.linalg.norm(a[off[i]:off[i + 1]] - b[off[i]:off[i + 1]]) / np.linalg.norm(b[off[i]:off[i + 1]])
+        assert e < 100 * tol, (i, e)
+    s.close()
+
+
 def test_copy_probe_copies():
     """The measurement copy (the bench's measured HBM bandwidth) copies exactly,
     including a size that is not a multiple of the workgroup; bad sizes are
