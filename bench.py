@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--fp32-sweeps", type=int, default=3)
     ap.add_argument("--adaptive", action="store_true",
                     help="c2/c4 with --no-autotune: adaptive schedule with at most --fp32-sweeps FP32 sweeps per FP64 sweep")
+    ap.add_argument("--split-lines", action="store_true",
+                    help="c2/c4 with --no-autotune: one line-solve launch per length bucket")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
@@ -89,7 +91,7 @@ def bench_c4(args):
     gen_s = time.time() - t0
     t0 = time.time()
     s = Solver(probs, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, graph=args.graph,
-               adaptive=args.adaptive)
+               adaptive=args.adaptive, split_lines=args.split_lines)
     setup_s = time.time() - t0
     counts = s.counts()
     per_inst = []
@@ -135,11 +137,12 @@ def bench_c4(args):
                       "graph": bool(args.graph),
                       "fp32_sweeps_per_fp64": tuned[0] if tuned else args.fp32_sweeps,
                       "adaptive_schedule": tuned[1] if tuned else bool(args.adaptive),
+                      "line_launches": "one per length bucket" if (tuned[3] if tuned else args.split_lines) else "one",
                       "autotune_ms": round(tuned[2], 2) if tuned else None}}
     if True:
         out["config"]["kernels"] = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()}
                                     for pr in times}
-        rf = kernel_roofline(times, counts)
+        rf = kernel_roofline(times, counts, tuned[3] if tuned else args.split_lines)
         per_sweep_units = rf["units"]
         # every instance converges at its own sweep: the measured launches cover
         # sum_i iters_i sweeps of instance i; use the mean per launch
@@ -306,7 +309,7 @@ def bench_c3(args):
     p = W.c3(args.n)
     th, dt, nst = p.extra["theta"], p.extra["dt"], p.extra["steps"]
     t0 = time.time()
-    s = Solver(p, precision="fp64", theta=th, dt=dt)
+    s = Solver(p, precision="fp64", theta=th, dt=dt, split_lines=args.split_lines)
     setup_s = time.time() - t0
     c = s.counts()
     per_step = c["line_unknowns_b"] + c["line_unknowns_g"]
@@ -327,7 +330,7 @@ def bench_c3(args):
     el = time.perf_counter() - t0
     el_ev, times = events_pass(s, march, args.steps)
     times["fp32"] = {}
-    rf = kernel_roofline(times, c)
+    rf = kernel_roofline(times, c, args.split_lines)
     if rf["cls"].startswith("scatter"):  # the march writes both half steps (no update/norm mode)
         rf["bytes_per_unit"], rf["kernel"] = SCATTER_BYTES[("fp64", 2)], "k_scatter<double, double, 0>"
     work_launches = nst * args.steps
@@ -350,7 +353,7 @@ def bench_c3(args):
     s.close()
 
 
-def kernel_roofline(times, counts):
+def kernel_roofline(times, counts, split_lines=False):
     """Dominant kernel class over both precisions; achieved = bytes / time."""
     best = None
     for prec in ("fp64", "fp32"):
@@ -364,7 +367,9 @@ def kernel_roofline(times, counts):
     if cls.startswith("line"):
         units = counts["line_unknowns_b" if fam == 0 else "line_unknowns_g"]
         per = LINE_BYTES[(prec, fam)]
-        kname = f"k_line<{'float' if prec == 'fp32' else 'double'}, {fam}>"
+        tn = 'float' if prec == 'fp32' else 'double'
+        kname = f"k_line_b<{tn}, {fam}, 12|8|4|2|1> (one launch per length bucket)" if split_lines else \
+            f"k_line<{tn}, {fam}>"
     else:
         units = counts["grid_unknowns"]
         per = SCATTER_BYTES[(prec, 2 if fam == 0 else 3)]
@@ -403,7 +408,8 @@ def main():
         del a, b
     p = W.c2(args.n)
     t0 = time.time()
-    s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, adaptive=args.adaptive)
+    s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, adaptive=args.adaptive,
+               split_lines=args.split_lines)
     setup_s = time.time() - t0
     counts = s.counts()
     per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
@@ -411,7 +417,7 @@ def main():
     tuned = None
     if not args.no_autotune:
         tuned = s.autotune(u, 5000, args.tol)
-        args.fp32_sweeps, args.adaptive = tuned[0], tuned[1]
+        args.fp32_sweeps, args.adaptive, args.split_lines = tuned[0], tuned[1], tuned[3]
 
     def solve():
         u.zero_()
@@ -434,7 +440,7 @@ def main():
     value = total_unknowns / el
     ms_step = 1e3 * el / args.steps
 
-    rf = kernel_roofline(times, counts)
+    rf = kernel_roofline(times, counts, args.split_lines)
     # one launch per sweep of its precision processes `units` line unknowns (or
     # grid nodes).  Launches made after the convergence flag was set exit at
     # once and carry no work: the average is taken over the work-carrying
@@ -471,6 +477,7 @@ def main():
                                "eq.(10) sweeps theta=1 dt=0.05 to 1e-8",
                    "time_to_1e-8_ms": ms_step, "sweeps_per_solve": sweeps[0],
                    "fp32_sweeps_per_fp64": args.fp32_sweeps, "adaptive_schedule": bool(args.adaptive),
+                   "line_launches": "one per length bucket" if args.split_lines else "one",
                    "autotuned": tuned is not None,
                    "line_unknowns_per_sweep": per_sweep,
                    "grid_unknowns": counts["grid_unknowns"], "lines": [counts["lines_b"], counts["lines_g"]],

@@ -94,6 +94,10 @@ typedef struct {
                              one falls on the sweep where the first unfinished instance is
                              expected to reach tol, from the geometric decay of its measured
                              rel (at least fp32_sweeps / 2 while several instances run) */
+    int32_t split_lines;  /* != 0: the line solves of a family run as one launch per length
+                             bucket (curves of at most 12, 8, 4, 2, 1 nodes per thread), each
+                             kernel with its bucket's register footprint and LDS; 0: one
+                             launch whose workgroups pick their footprint */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -157,17 +161,21 @@ adr_status adr_split_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double 
 adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallback, int32_t max_iters,
                                     double tol, int32_t *iters, double *rel_res, int32_t *used_fallback);
 
-/* Autotuner of the batched stationary solve (FP32_LINES precision only): for
- * each candidate schedule -- a fixed count of FP32 sweeps per FP64 sweep (2, 3,
- * 4, 6) and, in eager mode, the adaptive schedule with at most 6, 8, 12, 16 or 24 --
- * it runs the stationary solve from zero twice (the first run captures the
- * graph in graph mode) on `work` (device FP64, packed layout, overwritten),
- * times the second on the host clock, and keeps the fastest schedule in the
- * context's options.  best_fp32_sweeps, best_adaptive, best_ms (host, may be
- * NULL): the choice (count or maximum, adaptive flag) and its time.  Kernel
+/* Autotuner of the batched stationary solve (FP32_LINES precision only).  Each
+ * trial runs the stationary solve from zero twice on `work` (device FP64,
+ * packed layout, overwritten) and times the second run on the host clock (the
+ * first also captures the graph in graph mode).  It tunes in two steps:
+ *   1. the line launches (options.split_lines 0 and 1), under the context's
+ *      current schedule;
+ *   2. with the faster of those, each candidate schedule: a fixed count of
+ *      FP32 sweeps per FP64 sweep (2, 3, 4, 6) and, in eager mode, the
+ *      adaptive schedule with at most 6, 8, 12, 16 or 24.
+ * The fastest choice stays in the context's options.  Outputs (host, each may
+ * be NULL): best_fp32_sweeps and best_adaptive (the count or maximum, and the
+ * adaptive flag), best_ms (its time), best_split (the launch choice).  Kernel
  * timers (timing mode) are reset afterwards.  Synchronises. */
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
-                        int32_t *best_adaptive, double *best_ms);
+                        int32_t *best_adaptive, double *best_ms, int32_t *best_split);
 
 /* Parabolic march (eq. (2) discretised by eq. (10)): nsteps sweeps with the
  * given theta in (0,1] and time step dt > 0, FP64, source f included.  u:

@@ -46,7 +46,7 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("fp32_sweeps", C.c_int32),
                 ("theta", C.c_double), ("dt", C.c_double),
                 ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32),
-                ("graph", C.c_int32), ("adaptive", C.c_int32)]
+                ("graph", C.c_int32), ("adaptive", C.c_int32), ("split_lines", C.c_int32)]
 
 
 _lib = None
@@ -71,7 +71,7 @@ def load():
     lib.adr_update.argtypes = [vp, P(Problem), i32]
     lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
     lib.adr_split_iterate_judged.argtypes = [vp, vp, vp, i32, dbl, P(i32), P(dbl), P(i32)]
-    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl)]
+    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32)]
     lib.adr_set_timing.argtypes = [vp, i32]
     lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32]
     lib.adr_residual.argtypes = [vp, vp, P(dbl)]
@@ -119,7 +119,7 @@ class Solver:
     """One context over a batch of problems (workloads.Problem-like objects)."""
 
     def __init__(self, problems, precision="fp64", theta=1.0, dt=0.05, fp32_sweeps=3,
-                 stream=None, timing=False, host_only=False, graph=False, adaptive=False):
+                 stream=None, timing=False, host_only=False, graph=False, adaptive=False, split_lines=False):
         self.lib = load()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -131,7 +131,7 @@ class Solver:
         prec = {"fp64": PREC_FP64, "fp32": PREC_FP32_LINES}[precision]
         opt = Options(prec, int(fp32_sweeps), float(theta), float(dt),
                       C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)),
-                      int(bool(graph)), int(bool(adaptive)))
+                      int(bool(graph)), int(bool(adaptive)), int(bool(split_lines)))
         self.n = len(problems)
         self.ctx = C.c_void_p()
         st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))
@@ -180,15 +180,17 @@ class Solver:
         self._check(self.lib.adr_set_timing(self.ctx, int(bool(on))))
 
     def autotune(self, work, max_iters, tol):
-        """Times the solve for each candidate schedule (fixed FP32-sweep counts,
-        adaptive maxima) on `work` (overwritten) and keeps the fastest; returns
-        (count or maximum, adaptive, ms)."""
+        """Times the solve with one line launch and with one per length bucket,
+        then each candidate schedule (fixed FP32-sweep counts, adaptive maxima)
+        on `work` (overwritten), and keeps the fastest; returns (count or
+        maximum, adaptive, ms, split_lines)."""
         best = C.c_int32()
         ad = C.c_int32()
         ms = C.c_double()
+        sp = C.c_int32()
         self._check(self.lib.adr_autotune(self.ctx, _device_ptr(work), int(max_iters), float(tol),
-                                          C.byref(best), C.byref(ad), C.byref(ms)))
-        return best.value, bool(ad.value), ms.value
+                                          C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp)))
+        return best.value, bool(ad.value), ms.value, bool(sp.value)
 
     def split_iterate(self, u, max_iters, tol):
         iters = np.zeros(self.n, np.int32)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <atomic>
 #include <cmath>
@@ -74,6 +75,12 @@ struct DevFam {
     std::vector<int> inst_lines, inst_nmax;  // per instance: curves, longest curve
     int *lidx = nullptr;                      // compacted line list (device)
     int act = -1, act_nmax = 0;               // its length and longest curve; -1: full list
+    // length buckets: the list is ordered longest first, so bucket b is the
+    // range bstart[b] .. bstart[b+1]-1 of the full list (abstart: of the
+    // compacted list); bnmax: its longest curve
+    int bstart[adr::kLineBuckets + 1] = {}, bnmax[adr::kLineBuckets] = {};
+    int abstart[adr::kLineBuckets + 1] = {}, abnmax[adr::kLineBuckets] = {};
+    std::vector<std::array<int, adr::kLineBuckets>> inst_bl, inst_bnmax;  // per instance and bucket
 };
 
 }  // namespace
@@ -172,19 +179,31 @@ struct adr_ctx {
         }
         return r;
     }
+    // the line solves of family f: one launch, or one per non-empty length bucket
+    template <typename T>
+    hipError_t lines(int f, const adr::LineArgs<T> &base, const T *fin, T *vout, const double *par, const int *dn) {
+        const DevFam &F = fam[f];
+        adr::LineArgs<T> a = largs(F, base);
+        a.lbase = 0;
+        if (!opt.split_lines) {
+            const int nl = F.act >= 0 ? F.act : F.n_lines, nm = F.act >= 0 ? F.act_nmax : F.nmax;
+            return adr::launch_line<T>(f, -1, a, nl, fin, vout, par, dn, nm, st);
+        }
+        const int *bs = F.act >= 0 ? F.abstart : F.bstart;
+        const int *bn = F.act >= 0 ? F.abnmax : F.bnmax;
+        for (int b = 0; b < adr::kLineBuckets; ++b) {
+            if (bs[b + 1] == bs[b]) continue;
+            a.lbase = bs[b];
+            const hipError_t e = adr::launch_line<T>(f, b, a, bs[b + 1] - bs[b], fin, vout, par, dn, bn[b], st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     void line64(int f, int slot, const double *fin, const int *dn) {
-        DevFam &F = fam[f];
-        const int nl = F.act >= 0 ? F.act : F.n_lines, nm = F.act >= 0 ? F.act_nmax : F.nmax;
-        timed(0, f, [&] {
-            return adr::launch_line<double>(f, largs(F, F.a64), nl, fin, F.v64, par_ptr(slot, f), dn, nm, st);
-        });
+        timed(0, f, [&] { return lines<double>(f, fam[f].a64, fin, fam[f].v64, par_ptr(slot, f), dn); });
     }
     void line32(int f, int slot, const float *fin, const int *dn) {
-        DevFam &F = fam[f];
-        const int nl = F.act >= 0 ? F.act : F.n_lines, nm = F.act >= 0 ? F.act_nmax : F.nmax;
-        timed(1, f, [&] {
-            return adr::launch_line<float>(f, largs(F, F.a32), nl, fin, F.v32, par_ptr(slot, f), dn, nm, st);
-        });
+        timed(1, f, [&] { return lines<float>(f, fam[f].a32, fin, fam[f].v32, par_ptr(slot, f), dn); });
     }
 
     // One FP64 sweep of eq. (10) from U.  mode of the final scatter: 0 write U,
@@ -218,14 +237,23 @@ struct adr_ctx {
         for (int f = 0; f < 2; ++f) {
             DevFam &F = fam[f];
             int nl = 0, nm = 0;
+            int bl[adr::kLineBuckets] = {};
+            for (int b = 0; b < adr::kLineBuckets; ++b) F.abnmax[b] = 0;
             for (int i = 0; i < n_inst; ++i)
                 if (!dn[i]) {
                     nl += F.inst_lines[i];
                     nm = std::max(nm, F.inst_nmax[i]);
+                    for (int b = 0; b < adr::kLineBuckets; ++b) {
+                        bl[b] += F.inst_bl[i][b];
+                        F.abnmax[b] = std::max(F.abnmax[b], F.inst_bnmax[i][b]);
+                    }
                 }
             HIPCHK(adr::launch_compact(F.a64.linst, F.n_lines, done, cscan, F.lidx, ccount, st));
             F.act = nl;
             F.act_nmax = nm;
+            // the compaction keeps the list order, so the buckets stay contiguous ranges
+            F.abstart[0] = 0;
+            for (int b = 0; b < adr::kLineBuckets; ++b) F.abstart[b + 1] = F.abstart[b] + bl[b];
         }
     }
     void uncompact() {
@@ -300,7 +328,8 @@ struct adr_ctx {
     hipGraph_t graph = nullptr;
     const double *g_u = nullptr;
     double g_tol = -1.0;
-    int g_m = -1;  // FP32 sweeps per block of the captured graph
+    int g_m = -1;      // FP32 sweeps per block of the captured graph
+    int g_split = -1;  // its line launches (options.split_lines)
     hipStream_t cap = nullptr;
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
@@ -524,6 +553,9 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             loff.reserve(lines.size());
             F.inst_lines.assign(n, 0);
             F.inst_nmax.assign(n, 0);
+            F.inst_bl.assign(n, {});
+            F.inst_bnmax.assign(n, {});
+            int bcount[adr::kLineBuckets] = {};
             F.lidx = dalloc<int>(std::max(F.n_lines, 1), own);
             HIPCHK(hipMemsetAsync(F.lidx, 0, sizeof(int) * std::max(F.n_lines, 1), st));
             for (auto &li : lines) {
@@ -536,7 +568,14 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 F.inst_lines[li.first] += 1;
                 F.inst_nmax[li.first] = std::max(F.inst_nmax[li.first], cnt);
                 F.n_unknowns += cnt - 2;
+                const int b = adr::line_bucket(cnt);
+                bcount[b] += 1;
+                F.bnmax[b] = std::max(F.bnmax[b], cnt);
+                F.inst_bl[li.first][b] += 1;
+                F.inst_bnmax[li.first][b] = std::max(F.inst_bnmax[li.first][b], cnt);
             }
+            F.bstart[0] = 0;
+            for (int b = 0; b < adr::kLineBuckets; ++b) F.bstart[b + 1] = F.bstart[b] + bcount[b];
             if (F.nmax > kMaxNodes || adr::line_lds_bytes<double>(f, F.nmax) > kLdsLimit)
                 throw Error{ADR_EINVAL, "a curve has " + std::to_string(F.nmax) +
                                             " nodes: longer than the LDS-resident line solver holds"};
@@ -814,7 +853,9 @@ static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback,
             }
             const int blocks = (max_iters - 1) / period;
             const int check = std::max(1, 8 / period);
-            if (use_graph && blocks > 0 && (ctx->g_u != ub || ctx->g_tol != tol || ctx->g_m != m || !ctx->gexec)) {
+            if (use_graph && blocks > 0 &&
+                (ctx->g_u != ub || ctx->g_tol != tol || ctx->g_m != m || ctx->g_split != ctx->opt.split_lines ||
+                 !ctx->gexec)) {
                 ctx->drop_graph();
                 HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
                 ctx->block(ub, m, tol);
@@ -823,6 +864,7 @@ static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback,
                 ctx->g_u = ub;
                 ctx->g_tol = tol;
                 ctx->g_m = m;
+                ctx->g_split = ctx->opt.split_lines;
             }
             if (fp32 && ctx->opt.adaptive) {
                 ctx->adaptive_blocks(ub, max_iters, tol, dn, all_done);
@@ -884,7 +926,7 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
 }
 
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
-                        int32_t *best_adaptive, double *best_ms) {
+                        int32_t *best_adaptive, double *best_ms, int32_t *best_split) {
     if (!ctx) return ADR_EINVAL;
     if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES) {
         ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0 and FP32_LINES precision";
@@ -892,33 +934,62 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     }
     // (FP32 sweeps per FP64 sweep or their maximum, adaptive)
     static const int kCand[][2] = {{2, 0}, {3, 0}, {4, 0}, {6, 0}, {6, 1}, {8, 1}, {12, 1}, {16, 1}, {24, 1}};
-    const int32_t saved = ctx->opt.fp32_sweeps, saved_ad = ctx->opt.adaptive;
+    const int32_t saved = ctx->opt.fp32_sweeps, saved_ad = ctx->opt.adaptive, saved_split = ctx->opt.split_lines;
     const bool eager = !ctx->opt.graph || ctx->opt.timing;
-    int best = saved, best_ad = saved_ad;
-    double best_t = INFINITY;
     const size_t nbytes = sizeof(double) * static_cast<size_t>(ctx->goff.back());
-    for (const auto &cand : kCand) {
-        const int c = cand[0];
-        if (cand[1] && !eager) continue;  // the adaptive schedule runs eager launches only
-        ctx->opt.fp32_sweeps = c;
-        ctx->opt.adaptive = cand[1];
-        double t = INFINITY;
-        for (int rep = 0; rep < 2; ++rep) {  // the first run also captures the graph (graph mode)
+    auto restore = [&]() {
+        ctx->opt.fp32_sweeps = saved;
+        ctx->opt.adaptive = saved_ad;
+        ctx->opt.split_lines = saved_split;
+    };
+    // one timed solve from zero (the second of two runs: the first also
+    // captures the graph in graph mode); ms < 0 on a device error
+    auto time_solve = [&](double &ms) -> adr_status {
+        ms = INFINITY;
+        for (int rep = 0; rep < 2; ++rep) {
             if (hipMemsetAsync(work, 0, nbytes, ctx->st) != hipSuccess || hipStreamSynchronize(ctx->st) != hipSuccess) {
-                ctx->opt.fp32_sweeps = saved;
-                ctx->opt.adaptive = saved_ad;
                 ctx->err = "adr_autotune: device error";
                 return ADR_EDEVICE;
             }
             const auto t0 = std::chrono::steady_clock::now();
             const adr_status st = adr_split_iterate(ctx, work, max_iters, tol, nullptr, nullptr);
-            const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            if (st != ADR_OK && st != ADR_ENOTCONV) {
-                ctx->opt.fp32_sweeps = saved;
-                ctx->opt.adaptive = saved_ad;
+            ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (st != ADR_OK && st != ADR_ENOTCONV) return st;
+        }
+        return ADR_OK;
+    };
+    // 1. the line launches (one, or one per length bucket) under the current schedule
+    int split = saved_split;
+    {
+        double best_t = INFINITY;
+        for (int sp = 0; sp < 2; ++sp) {
+            ctx->opt.split_lines = sp;
+            double t;
+            const adr_status st = time_solve(t);
+            if (st != ADR_OK) {
+                restore();
                 return st;
             }
-            t = ms;
+            if (t < best_t) {
+                best_t = t;
+                split = sp;
+            }
+        }
+        ctx->opt.split_lines = split;
+    }
+    // 2. the FP32/FP64 sweep schedule with those launches
+    int best = saved, best_ad = saved_ad;
+    double best_t = INFINITY;
+    for (const auto &cand : kCand) {
+        const int c = cand[0];
+        if (cand[1] && !eager) continue;  // the adaptive schedule runs eager launches only
+        ctx->opt.fp32_sweeps = c;
+        ctx->opt.adaptive = cand[1];
+        double t;
+        const adr_status st = time_solve(t);
+        if (st != ADR_OK) {
+            restore();
+            return st;
         }
         if (t < best_t) {
             best_t = t;
@@ -933,6 +1004,7 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     if (best_fp32_sweeps) *best_fp32_sweeps = best;
     if (best_adaptive) *best_adaptive = best_ad;
     if (best_ms) *best_ms = best_t;
+    if (best_split) *best_split = split;
     return ADR_OK;
 }
 

@@ -17,7 +17,8 @@ struct LineArgs {
     const T *h;          // per node: chord to the previous node
     const T *w;          // per node: |beta| (beta family only)
     const T *L;          // per node: load int f phi (beta family only)
-    const int *lidx;     // optional: the line of each workgroup (active lines only), else line = workgroup
+    const int *lidx;     // optional: the line at each list position (active lines only), else line = position
+    int lbase;           // list position of the launch's first workgroup (length buckets)
 };
 
 // Scatter stencils of one family; slot s < npad (padded per instance to 256).
@@ -47,9 +48,17 @@ __host__ __device__ inline int blocked_index(int x, int y, int boff, int bstride
 template <typename T>
 size_t line_lds_bytes(int fam, int nmax);
 
+// Length buckets of the line solve: curves of at most 12, 8, 4, 2, 1 nodes per
+// thread (bucket 0..4); a curve of `nodes` nodes belongs to line_bucket(nodes).
+constexpr int kLineBuckets = 5;
+int line_bucket(int nodes);
+
+// bucket -1: one launch for curves of any length (a register footprint per
+// workgroup inside the kernel); bucket b: every curve of the launch lies in b.
+// n_lines workgroups take the list positions a.lbase .. a.lbase + n_lines - 1.
 template <typename T>
-hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
-                       const int *done, int nmax, hipStream_t st);
+hipError_t launch_line(int fam, int bucket, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
+                       const double *par, const int *done, int nmax, hipStream_t st);
 
 // interior nodes between the caller's row-major array and the blocked layout:
 // to_blocked: blk[gb[s]] = rm[gr[s]]; otherwise rm[gr[s]] = blk[gb[s]] (slots s < npad, gr < 0: padding)

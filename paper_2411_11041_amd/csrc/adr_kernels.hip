@@ -54,7 +54,8 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T *A1 = D0 + kThreads, *C1 = A1 + kThreads, *D1 = C1 + kThreads;
     T *FY = A1, *FA = C1, *FG = D1;
 
-    const int l = a.lidx ? a.lidx[blockIdx.x] : static_cast<int>(blockIdx.x);
+    const int pos = a.lbase + static_cast<int>(blockIdx.x);
+    const int l = a.lidx ? a.lidx[pos] : pos;
     const int tid = threadIdx.x;
     const int inst = a.linst[l];
     if (done[inst]) return;
@@ -305,17 +306,30 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
 }
 
 // One launch for every curve of a family: curves are ordered longest first and
-// each workgroup picks the register footprint (nodes per thread) of its curve.
+// each workgroup picks the register footprint (nodes per thread) of its curve;
+// the kernel's registers are those of the largest footprint.
 template <typename T, int FAM>
 __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
                                                    T *__restrict__ vout, const double *__restrict__ par,
                                                    const int *__restrict__ done, int nmax) {
-    const int per = (a.lcnt[a.lidx ? a.lidx[blockIdx.x] : static_cast<int>(blockIdx.x)] + kThreads - 1) / kThreads;
+    const int pos = a.lbase + static_cast<int>(blockIdx.x);
+    const int per = (a.lcnt[a.lidx ? a.lidx[pos] : pos] + kThreads - 1) / kThreads;
     if (per <= 1) line_body<T, FAM, 1>(a, fin, vout, par, done, nmax);
     else if (per <= 2) line_body<T, FAM, 2>(a, fin, vout, par, done, nmax);
     else if (per <= 4) line_body<T, FAM, 4>(a, fin, vout, par, done, nmax);
     else if (per <= 8) line_body<T, FAM, 8>(a, fin, vout, par, done, nmax);
     else line_body<T, FAM, 12>(a, fin, vout, par, done, nmax);
+}
+
+// One launch per length bucket: every curve of the launch has at most MAXJ
+// nodes per thread, and the kernel has that footprint's registers (more
+// resident workgroups for the short curves), its LDS sized by the bucket's
+// longest curve.
+template <typename T, int FAM, int MAXJ>
+__global__ __launch_bounds__(kThreads) void k_line_b(LineArgs<T> a, const T *__restrict__ fin,
+                                                     T *__restrict__ vout, const double *__restrict__ par,
+                                                     const int *__restrict__ done, int nmax) {
+    line_body<T, FAM, MAXJ>(a, fin, vout, par, done, nmax);
 }
 
 // Scatter: out = P v on the interior nodes.  MODE 0: write; MODE 1 (FP64 sweep):
@@ -518,23 +532,43 @@ size_t line_lds_bytes(int fam, int nmax) {
     return sizeof(T) * static_cast<size_t>(line_lds_arrays(fam)) * line_lds_stride(nmax);
 }
 
-template <typename T>
-hipError_t launch_line(int fam, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
-                       const int *done, int nmax, hipStream_t st) {
-    if (n_lines == 0) return hipSuccess;
-    if (nmax > 12 * kThreads) return hipErrorInvalidValue;
-    const size_t lds = line_lds_bytes<T>(fam, nmax);
-    if (fam == 0) {
-        if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 0>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        hipLaunchKernelGGL((k_line<T, 0>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
-    } else {
-        if (lds > 64 * 1024)
-            (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_line<T, 1>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
-        hipLaunchKernelGGL((k_line<T, 1>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
+namespace {
+template <typename K>
+void set_lds(K *kernel, size_t lds) {
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(lds));
+}
+
+template <typename T, int FAM>
+void launch_line_fam(int bucket, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
+                     const int *done, int nmax, size_t lds, hipStream_t st) {
+    const dim3 g(n_lines), b(kThreads);
+    switch (bucket) {
+        case 0: set_lds(&k_line_b<T, FAM, 12>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 12>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
+        case 1: set_lds(&k_line_b<T, FAM, 8>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 8>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
+        case 2: set_lds(&k_line_b<T, FAM, 4>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 4>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
+        case 3: set_lds(&k_line_b<T, FAM, 2>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 2>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
+        case 4: set_lds(&k_line_b<T, FAM, 1>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 1>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
+        default: set_lds(&k_line<T, FAM>, lds); hipLaunchKernelGGL((k_line<T, FAM>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
     }
+}
+}  // namespace
+
+int line_bucket(int nodes) {
+    const int per = (nodes + kThreads - 1) / kThreads;
+    return per <= 1 ? 4 : per <= 2 ? 3 : per <= 4 ? 2 : per <= 8 ? 1 : 0;
+}
+
+template <typename T>
+hipError_t launch_line(int fam, int bucket, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
+                       const double *par, const int *done, int nmax, hipStream_t st) {
+    if (n_lines == 0) return hipSuccess;
+    if (nmax > 12 * kThreads || bucket > 4) return hipErrorInvalidValue;
+    if (bucket >= 0 && line_bucket(nmax) < bucket) return hipErrorInvalidValue;  // curves too long for the bucket
+    const size_t lds = line_lds_bytes<T>(fam, nmax);
+    if (fam == 0) launch_line_fam<T, 0>(bucket, a, n_lines, fin, vout, par, done, nmax, lds, st);
+    else launch_line_fam<T, 1>(bucket, a, n_lines, fin, vout, par, done, nmax, lds, st);
     return hipGetLastError();
 }
 
@@ -584,9 +618,9 @@ hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st) {
 
 template size_t line_lds_bytes<double>(int, int);
 template size_t line_lds_bytes<float>(int, int);
-template hipError_t launch_line<double>(int, const LineArgs<double> &, int, const double *, double *, const double *,
-                                        const int *, int, hipStream_t);
-template hipError_t launch_line<float>(int, const LineArgs<float> &, int, const float *, float *, const double *,
+template hipError_t launch_line<double>(int, int, const LineArgs<double> &, int, const double *, double *,
+                                        const double *, const int *, int, hipStream_t);
+template hipError_t launch_line<float>(int, int, const LineArgs<float> &, int, const float *, float *, const double *,
                                        const int *, int, hipStream_t);
 template hipError_t launch_scatter<double, double>(int, const ScatterArgs<double> &, const double *, double *,
                                                    float *, double *, const int *, hipStream_t);

@@ -240,8 +240,9 @@ def test_autotune_keeps_a_candidate_and_the_fixed_point():
     p = W.c2(129)
     s = solver(p, precision="fp32", fp32_sweeps=3)
     work = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
-    best, adaptive, ms = s.autotune(work, 2000, 1e-10)
+    best, adaptive, ms, split = s.autotune(work, 2000, 1e-10)
     assert ((best in (2, 3, 4, 6) and not adaptive) or (best in (6, 8, 12, 16, 24) and adaptive)) and ms > 0
+    assert split in (True, False)
     u = torch.zeros_like(work)
     iters, rel, st = s.split_iterate(u, 2000, 1e-10)
     assert st == 0 and rel[0] <= 1e-10
@@ -430,6 +431,54 @@ def test_judged_iterate_restarts_worse_starts():
         e = np.linalg.norm(a[off[i]:off[i + 1]] - b[off[i]:off[i + 1]]) / np.linalg.norm(b[off[i]:off[i + 1]])
         assert e < 100 * tol, (i, e)
     s.close()
+
+
+def _bucket(nodes):
+    per = (nodes + 255) // 256
+    return 4 if per <= 1 else 3 if per <= 2 else 2 if per <= 4 else 1 if per <= 8 else 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_split_line_launches_equal_the_single_launch(precision):
+    """One launch per length bucket runs every curve through the same
+    per-curve code as the single launch.  A batch whose curves fill all five
+    buckets (up to 12 nodes per thread) gives, with launch lists compacted as
+    instances finish, the single launch's sweep counts and iterates, and the
+    graph replay (full lists) gives the eager result bitwise."""
+    print(f"[case] split line launches vs one launch ({precision})", flush=True)
+    probs = [W.c2(2049), W.c4_instance(2, n_max=100), W.c1(33), W.c4_instance(7, n_max=600)]
+    kw = dict(precision=precision, theta=1.0, dt=0.05)
+    if precision == "fp32":
+        kw["fp32_sweeps"] = 3
+    one = solver(probs, **kw)
+    buckets = set()
+    for i in range(len(probs)):
+        for fam in (0, 1):
+            off, _, _ = one.export_lines(i, fam)
+            buckets |= {_bucket(int(c)) for c in np.diff(off)}
+    assert buckets == {0, 1, 2, 3, 4}, buckets
+    spl = solver(probs, split_lines=True, **kw)
+    off = spl.layout()
+    tol = 1e-9
+    u1 = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    u2 = torch.zeros_like(u1)
+    it1, rel1, st1 = one.split_iterate(u1, 3000, tol)
+    it2, rel2, st2 = spl.split_iterate(u2, 3000, tol)
+    torch.cuda.synchronize()
+    assert st1 == 0 and st2 == 0
+    assert len(set(int(v) for v in it2)) > 1  # compaction took place
+    assert np.array_equal(it1, it2)
+    d = float(torch.max(torch.abs(u1 - u2)) / torch.max(torch.abs(u1)))
+    print(f"[case] max relative difference {d:.2e} (bitwise: {bool(torch.equal(u1, u2))})", flush=True)
+    assert d <= 1e-13
+    spl_g = solver(probs, split_lines=True, graph=True, **kw)
+    u3 = torch.zeros_like(u1)
+    it3, _, st3 = spl_g.split_iterate(u3, 3000, tol)
+    torch.cuda.synchronize()
+    assert st3 == 0 and np.array_equal(it3, it2)
+    assert torch.equal(u3, u2)
+    for s in (one, spl, spl_g):
+        s.close()
 
 
 def test_copy_probe_copies():
