@@ -52,8 +52,9 @@ def parse():
     ap.add_argument("--fp32-sweeps", type=int, default=3)
     ap.add_argument("--adaptive", action="store_true",
                     help="c2/c4 with --no-autotune: adaptive schedule with at most --fp32-sweeps FP32 sweeps per FP64 sweep")
-    ap.add_argument("--split-lines", action="store_true",
-                    help="c2/c4 with --no-autotune: one line-solve launch per length bucket")
+    ap.add_argument("--split-lines", type=int, choices=[0, 1, 2], default=0,
+                    help="c2/c4 with --no-autotune (and c3): line-solve launches, 0 one per family, 1 one per "
+                         "length bucket, 2 one per length bucket on concurrent streams")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=12)
     ap.add_argument("--workload", choices=["c2", "c3", "c4", "c5"], default="c2",
@@ -137,7 +138,7 @@ def bench_c4(args):
                       "graph": bool(args.graph),
                       "fp32_sweeps_per_fp64": tuned[0] if tuned else args.fp32_sweeps,
                       "adaptive_schedule": tuned[1] if tuned else bool(args.adaptive),
-                      "line_launches": "one per length bucket" if (tuned[3] if tuned else args.split_lines) else "one",
+                      "line_launches": LINE_LAUNCHES[tuned[3] if tuned else args.split_lines],
                       "autotune_ms": round(tuned[2], 2) if tuned else None}}
     if True:
         out["config"]["kernels"] = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()}
@@ -353,7 +354,10 @@ def bench_c3(args):
     s.close()
 
 
-def kernel_roofline(times, counts, split_lines=False):
+LINE_LAUNCHES = {0: "one per family", 1: "one per length bucket", 2: "one per length bucket, concurrent streams"}
+
+
+def kernel_roofline(times, counts, split_lines=0):
     """Dominant kernel class over both precisions; achieved = bytes / time."""
     best = None
     for prec in ("fp64", "fp32"):
@@ -368,7 +372,7 @@ def kernel_roofline(times, counts, split_lines=False):
         units = counts["line_unknowns_b" if fam == 0 else "line_unknowns_g"]
         per = LINE_BYTES[(prec, fam)]
         tn = 'float' if prec == 'fp32' else 'double'
-        kname = f"k_line_b<{tn}, {fam}, 12|8|4|2|1> (one launch per length bucket)" if split_lines else \
+        kname = f"k_line_b<{tn}, {fam}, 12|8|4|2|1> ({LINE_LAUNCHES[split_lines]})" if split_lines else \
             f"k_line<{tn}, {fam}>"
     else:
         units = counts["grid_unknowns"]
@@ -477,7 +481,7 @@ def main():
                                "eq.(10) sweeps theta=1 dt=0.05 to 1e-8",
                    "time_to_1e-8_ms": ms_step, "sweeps_per_solve": sweeps[0],
                    "fp32_sweeps_per_fp64": args.fp32_sweeps, "adaptive_schedule": bool(args.adaptive),
-                   "line_launches": "one per length bucket" if args.split_lines else "one",
+                   "line_launches": LINE_LAUNCHES[args.split_lines],
                    "autotuned": tuned is not None,
                    "line_unknowns_per_sweep": per_sweep,
                    "grid_unknowns": counts["grid_unknowns"], "lines": [counts["lines_b"], counts["lines_g"]],

@@ -94,10 +94,13 @@ typedef struct {
                              one falls on the sweep where the first unfinished instance is
                              expected to reach tol, from the geometric decay of its measured
                              rel (at least fp32_sweeps / 2 while several instances run) */
-    int32_t split_lines;  /* != 0: the line solves of a family run as one launch per length
-                             bucket (curves of at most 12, 8, 4, 2, 1 nodes per thread), each
-                             kernel with its bucket's register footprint and LDS; 0: one
-                             launch whose workgroups pick their footprint */
+    int32_t split_lines;  /* line solves of a family: 0 one launch whose workgroups pick their
+                             register footprint; 1 one launch per length bucket (curves of at
+                             most 12, 8, 4, 2, 1 nodes per thread), each kernel with its
+                             bucket's footprint and LDS, in turn on the stream; 2 the same
+                             launches on three streams at once (the longest bucket on the
+                             context's stream, the next and the rest on two streams of its
+                             own, joined back by events; in turn inside a graph capture) */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -165,7 +168,7 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
  * trial runs the stationary solve from zero twice on `work` (device FP64,
  * packed layout, overwritten) and times the second run on the host clock (the
  * first also captures the graph in graph mode).  It tunes in two steps:
- *   1. the line launches (options.split_lines 0 and 1), under the context's
+ *   1. the line launches (options.split_lines 0, 1 and 2), under the context's
  *      current schedule;
  *   2. with the faster of those, each candidate schedule: a fixed count of
  *      FP32 sweeps per FP64 sweep (2, 3, 4, 6) and, in eager mode, the

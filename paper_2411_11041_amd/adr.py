@@ -131,7 +131,7 @@ class Solver:
         prec = {"fp64": PREC_FP64, "fp32": PREC_FP32_LINES}[precision]
         opt = Options(prec, int(fp32_sweeps), float(theta), float(dt),
                       C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)),
-                      int(bool(graph)), int(bool(adaptive)), int(bool(split_lines)))
+                      int(bool(graph)), int(bool(adaptive)), int(split_lines))
         self.n = len(problems)
         self.ctx = C.c_void_p()
         st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))
@@ -180,17 +180,18 @@ class Solver:
         self._check(self.lib.adr_set_timing(self.ctx, int(bool(on))))
 
     def autotune(self, work, max_iters, tol):
-        """Times the solve with one line launch and with one per length bucket,
-        then each candidate schedule (fixed FP32-sweep counts, adaptive maxima)
+        """Times the solve with one line launch and with one per length bucket
+        (in turn, and on concurrent streams), then each candidate schedule (fixed FP32-sweep counts, adaptive maxima)
         on `work` (overwritten), and keeps the fastest; returns (count or
-        maximum, adaptive, ms, split_lines)."""
+        maximum, adaptive, ms, split_lines: 0 one launch, 1 per bucket, 2 per
+        bucket on concurrent streams)."""
         best = C.c_int32()
         ad = C.c_int32()
         ms = C.c_double()
         sp = C.c_int32()
         self._check(self.lib.adr_autotune(self.ctx, _device_ptr(work), int(max_iters), float(tol),
                                           C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp)))
-        return best.value, bool(ad.value), ms.value, bool(sp.value)
+        return best.value, bool(ad.value), ms.value, int(sp.value)
 
     def split_iterate(self, u, max_iters, tol):
         iters = np.zeros(self.n, np.int32)

@@ -191,12 +191,34 @@ struct adr_ctx {
         }
         const int *bs = F.act >= 0 ? F.abstart : F.bstart;
         const int *bn = F.act >= 0 ? F.abnmax : F.bnmax;
+        // concurrent: the longest bucket on st, the next on side[0], the short ones
+        // in turn on side[1] (not inside a graph capture, which runs on cap)
+        const bool conc = opt.split_lines == 2 && st != cap;
+        hipError_t e = hipSuccess;
+        if (conc) {
+            if (!side[0]) {
+                for (int k = 0; k < 2; ++k) {
+                    if ((e = hipStreamCreateWithFlags(&side[k], hipStreamNonBlocking)) != hipSuccess) return e;
+                    if ((e = hipEventCreateWithFlags(&join_ev[k], hipEventDisableTiming)) != hipSuccess) return e;
+                }
+                if ((e = hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming)) != hipSuccess) return e;
+            }
+            if ((e = hipEventRecord(fork_ev, st)) != hipSuccess) return e;
+            for (int k = 0; k < 2; ++k)
+                if ((e = hipStreamWaitEvent(side[k], fork_ev, 0)) != hipSuccess) return e;
+        }
         for (int b = 0; b < adr::kLineBuckets; ++b) {
             if (bs[b + 1] == bs[b]) continue;
             a.lbase = bs[b];
-            const hipError_t e = adr::launch_line<T>(f, b, a, bs[b + 1] - bs[b], fin, vout, par, dn, bn[b], st);
-            if (e != hipSuccess) return e;
+            hipStream_t sb = !conc || b == 0 ? st : side[b == 1 ? 0 : 1];
+            if ((e = adr::launch_line<T>(f, b, a, bs[b + 1] - bs[b], fin, vout, par, dn, bn[b], sb)) != hipSuccess)
+                return e;
         }
+        if (conc)
+            for (int k = 0; k < 2; ++k) {
+                if ((e = hipEventRecord(join_ev[k], side[k])) != hipSuccess) return e;
+                if ((e = hipStreamWaitEvent(st, join_ev[k], 0)) != hipSuccess) return e;
+            }
         return hipSuccess;
     }
     void line64(int f, int slot, const double *fin, const int *dn) {
@@ -331,6 +353,10 @@ struct adr_ctx {
     int g_m = -1;      // FP32 sweeps per block of the captured graph
     int g_split = -1;  // its line launches (options.split_lines)
     hipStream_t cap = nullptr;
+    // concurrent bucket launches (options.split_lines == 2): two more streams of
+    // the default priority, forked from and joined back into st by events
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
     void drop_graph() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
@@ -962,7 +988,7 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     int split = saved_split;
     {
         double best_t = INFINITY;
-        for (int sp = 0; sp < 2; ++sp) {
+        for (int sp = 0; sp < 3; ++sp) {
             ctx->opt.split_lines = sp;
             double t;
             const adr_status st = time_solve(t);
@@ -1126,6 +1152,12 @@ adr_status adr_destroy(adr_ctx *ctx) {
     for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
     ctx->drop_graph();
     if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+    for (int k = 0; k < 2; ++k) {
+        if (ctx->side[k]) (void)hipStreamSynchronize(ctx->side[k]);
+        if (ctx->side[k]) (void)hipStreamDestroy(ctx->side[k]);
+        if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
+    }
+    if (ctx->fork_ev) (void)hipEventDestroy(ctx->fork_ev);
     for (void *p : ctx->owned) (void)hipFree(p);
     delete ctx;
     return ADR_OK;

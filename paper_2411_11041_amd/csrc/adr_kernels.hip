@@ -21,9 +21,11 @@ namespace adr {
 
 constexpr int kThreads = 256;
 
-// LDS of a line-solve workgroup: arrays of `stride` elements (the longest curve
-// of the launch, at least the 6 x 256 entries of the reduced system)
-__host__ __device__ inline int line_lds_stride(int nmax) { return ((nmax > 6 * kThreads ? nmax : 6 * kThreads) + 3) & ~3; }
+// LDS of a line-solve workgroup of nt threads: arrays of `stride` elements (the
+// longest curve of the launch, at least the 6 nt entries of the reduced system)
+__host__ __device__ inline int line_lds_stride(int nmax, int nt = kThreads) {
+    return ((nmax > 6 * nt ? nmax : 6 * nt) + 3) & ~3;
+}
 __host__ __device__ inline int line_lds_arrays(int fam) { return fam == 0 ? 3 : 2; }
 
 // 1/x: IEEE division in FP64 (parity with the FP64 oracle), the hardware
@@ -31,7 +33,8 @@ __host__ __device__ inline int line_lds_arrays(int fam) { return fam == 0 ? 3 : 
 __device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-template <typename T, int FAM, int MAXJ>
+// NT threads per curve (the workgroup); a curve of n nodes needs n <= NT * MAXJ.
+template <typename T, int FAM, int MAXJ, int NT>
 __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restrict__ fin, T *__restrict__ vout,
                                           const double *__restrict__ par, const int *__restrict__ done, int nmax) {
     // LDS: line_lds_arrays(FAM) arrays of line_lds_stride(nmax) elements
@@ -42,7 +45,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     // order, so no row array is staged (a small footprint: more resident
     // workgroups per CU to hide the latency of the serial elimination).
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int S = line_lds_stride(nmax);
+    const int S = line_lds_stride(nmax, NT);
     T *P0 = reinterpret_cast<T *>(smem_raw);
     T *P1 = P0 + S;
     T *P2 = P1 + S;
@@ -50,8 +53,8 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T *Hs = P1, *Ws = P2;
     // reduced system: two buffers of normalised rows (a, c, d); the chunks'
     // first rows FY, FA, FG occupy the second buffer until the first PCR step
-    T *A0 = P1, *C0 = A0 + kThreads, *D0 = C0 + kThreads;
-    T *A1 = D0 + kThreads, *C1 = A1 + kThreads, *D1 = C1 + kThreads;
+    T *A0 = P1, *C0 = A0 + NT, *D0 = C0 + NT;
+    T *A1 = D0 + NT, *C1 = A1 + NT, *D1 = C1 + NT;
     T *FY = A1, *FA = C1, *FG = D1;
 
     const int pos = a.lbase + static_cast<int>(blockIdx.x);
@@ -68,7 +71,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     const T eM = T(pp[3]), eK = T(pp[4]), eC = T(pp[5]), eL = T(pp[6]);
 
     // chunking of the rows: thread q owns rows rs .. rs+k-1, rs = q*m (m <= MAXJ)
-    const int m = (N + kThreads - 1) / kThreads;
+    const int m = (N + NT - 1) / NT;
     const int Q = (N + m - 1) / m;  // non-empty chunks
     const int q = tid;
     const int rs = q * m;
@@ -81,7 +84,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T lxj[MAXJ], lyj[MAXJ];
 #pragma unroll
     for (int sl = 0; sl < MAXJ; ++sl) {
-        const int j = tid + kThreads * sl;
+        const int j = tid + NT * sl;
         cj[sl] = -1;
         lxj[sl] = T(0);
         lyj[sl] = T(0);
@@ -116,7 +119,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
 #pragma unroll
         for (int t = 0; t < G; ++t) {
             const int sl = q0 + t;
-            const int j = tid + kThreads * sl;
+            const int j = tid + NT * sl;
             const T lx = lxj[sl], ly = lyj[sl];
             const T ub = (T(1) - ly) * ((T(1) - lx) * p11[t] + lx * p12[t]) + ly * ((T(1) - lx) * p21[t] + lx * p22[t]);
             const T uj = cj[sl] >= 0 ? ub : T(0);
@@ -302,7 +305,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         if (has_sep) X[rs + k - 1] = SR;
     }
     __syncthreads();
-    for (int j = tid; j < n; j += kThreads) vout[o + j] = (j == 0 || j == n - 1) ? T(0) : X[j - 1];
+    for (int j = tid; j < n; j += NT) vout[o + j] = (j == 0 || j == n - 1) ? T(0) : X[j - 1];
 }
 
 // One launch for every curve of a family: curves are ordered longest first and
@@ -314,22 +317,23 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
                                                    const int *__restrict__ done, int nmax) {
     const int pos = a.lbase + static_cast<int>(blockIdx.x);
     const int per = (a.lcnt[a.lidx ? a.lidx[pos] : pos] + kThreads - 1) / kThreads;
-    if (per <= 1) line_body<T, FAM, 1>(a, fin, vout, par, done, nmax);
-    else if (per <= 2) line_body<T, FAM, 2>(a, fin, vout, par, done, nmax);
-    else if (per <= 4) line_body<T, FAM, 4>(a, fin, vout, par, done, nmax);
-    else if (per <= 8) line_body<T, FAM, 8>(a, fin, vout, par, done, nmax);
-    else line_body<T, FAM, 12>(a, fin, vout, par, done, nmax);
+    if (per <= 1) line_body<T, FAM, 1, kThreads>(a, fin, vout, par, done, nmax);
+    else if (per <= 2) line_body<T, FAM, 2, kThreads>(a, fin, vout, par, done, nmax);
+    else if (per <= 4) line_body<T, FAM, 4, kThreads>(a, fin, vout, par, done, nmax);
+    else if (per <= 8) line_body<T, FAM, 8, kThreads>(a, fin, vout, par, done, nmax);
+    else line_body<T, FAM, 12, kThreads>(a, fin, vout, par, done, nmax);
 }
 
-// One launch per length bucket: every curve of the launch has at most MAXJ
-// nodes per thread, and the kernel has that footprint's registers (more
+// One launch per length bucket: every curve of the launch has at most
+// NT * MAXJ nodes, and the kernel has that footprint's registers (more
 // resident workgroups for the short curves), its LDS sized by the bucket's
-// longest curve.
-template <typename T, int FAM, int MAXJ>
-__global__ __launch_bounds__(kThreads) void k_line_b(LineArgs<T> a, const T *__restrict__ fin,
-                                                     T *__restrict__ vout, const double *__restrict__ par,
-                                                     const int *__restrict__ done, int nmax) {
-    line_body<T, FAM, MAXJ>(a, fin, vout, par, done, nmax);
+// longest curve.  Short curves take smaller workgroups (128 or 64 threads,
+// 4 rows each): fewer idle lanes and a shorter reduced system.
+template <typename T, int FAM, int MAXJ, int NT>
+__global__ __launch_bounds__(NT) void k_line_b(LineArgs<T> a, const T *__restrict__ fin,
+                                               T *__restrict__ vout, const double *__restrict__ par,
+                                               const int *__restrict__ done, int nmax) {
+    line_body<T, FAM, MAXJ, NT>(a, fin, vout, par, done, nmax);
 }
 
 // Scatter: out = P v on the interior nodes.  MODE 0: write; MODE 1 (FP64 sweep):
@@ -540,17 +544,30 @@ void set_lds(K *kernel, size_t lds) {
                                   static_cast<int>(lds));
 }
 
+template <typename T, int FAM, int MAXJ, int NT>
+void launch_b(const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par, const int *done, int nmax,
+              hipStream_t st) {
+    const size_t lds = sizeof(T) * static_cast<size_t>(line_lds_arrays(FAM)) * line_lds_stride(nmax, NT);
+    set_lds(&k_line_b<T, FAM, MAXJ, NT>, lds);
+    hipLaunchKernelGGL((k_line_b<T, FAM, MAXJ, NT>), dim3(n_lines), dim3(NT), lds, st, a, fin, vout, par, done, nmax);
+}
+
+// buckets 0..4: curves of at most 3072, 2048, 1024, 512, 256 nodes
 template <typename T, int FAM>
 void launch_line_fam(int bucket, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
-                     const int *done, int nmax, size_t lds, hipStream_t st) {
-    const dim3 g(n_lines), b(kThreads);
+                     const int *done, int nmax, hipStream_t st) {
     switch (bucket) {
-        case 0: set_lds(&k_line_b<T, FAM, 12>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 12>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
-        case 1: set_lds(&k_line_b<T, FAM, 8>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 8>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
-        case 2: set_lds(&k_line_b<T, FAM, 4>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 4>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
-        case 3: set_lds(&k_line_b<T, FAM, 2>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 2>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
-        case 4: set_lds(&k_line_b<T, FAM, 1>, lds); hipLaunchKernelGGL((k_line_b<T, FAM, 1>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
-        default: set_lds(&k_line<T, FAM>, lds); hipLaunchKernelGGL((k_line<T, FAM>), g, b, lds, st, a, fin, vout, par, done, nmax); break;
+        case 0: launch_b<T, FAM, 12, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 1: launch_b<T, FAM, 8, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 2: launch_b<T, FAM, 4, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 3: launch_b<T, FAM, 4, 128>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 4: launch_b<T, FAM, 4, 64>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        default: {
+            const size_t lds = line_lds_bytes<T>(FAM, nmax);
+            set_lds(&k_line<T, FAM>, lds);
+            hipLaunchKernelGGL((k_line<T, FAM>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
+            break;
+        }
     }
 }
 }  // namespace
@@ -566,9 +583,8 @@ hipError_t launch_line(int fam, int bucket, const LineArgs<T> &a, int n_lines, c
     if (n_lines == 0) return hipSuccess;
     if (nmax > 12 * kThreads || bucket > 4) return hipErrorInvalidValue;
     if (bucket >= 0 && line_bucket(nmax) < bucket) return hipErrorInvalidValue;  // curves too long for the bucket
-    const size_t lds = line_lds_bytes<T>(fam, nmax);
-    if (fam == 0) launch_line_fam<T, 0>(bucket, a, n_lines, fin, vout, par, done, nmax, lds, st);
-    else launch_line_fam<T, 1>(bucket, a, n_lines, fin, vout, par, done, nmax, lds, st);
+    if (fam == 0) launch_line_fam<T, 0>(bucket, a, n_lines, fin, vout, par, done, nmax, st);
+    else launch_line_fam<T, 1>(bucket, a, n_lines, fin, vout, par, done, nmax, st);
     return hipGetLastError();
 }
 

@@ -125,12 +125,15 @@ def test_data2d_paper_experiment():
     s.close()
 
 
-def test_batched_instances_match_oracle():
+@pytest.mark.parametrize("split", [0, 1, 2])
+def test_batched_instances_match_oracle(split):
     """Disc and L-shape instances of uneven sizes in one context (one launch per
-    kernel for all of them): every instance matches its own oracle."""
-    print("[case] batched c4 x4 fp64 8 sweeps", flush=True)
-    probs = [W.c4_instance(i, n_max=140) for i in range(4)]
-    s = solver(probs, precision="fp64", theta=1.0, dt=0.05)
+    kernel for all of them, or one per length bucket: curves of up to 256
+    nodes on 64-thread workgroups, up to 512 on 128): every instance matches
+    its own oracle."""
+    print(f"[case] batched c4 x4 fp64 8 sweeps, line launches {split}", flush=True)
+    probs = [W.c4_instance(i, n_max=140) for i in range(3)] + [W.c4_instance(7, n_max=600)]
+    s = solver(probs, precision="fp64", theta=1.0, dt=0.05, split_lines=split)
     off = s.layout()
     u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     iters, rel, st = s.split_iterate(u, 8, 0.0)
@@ -242,7 +245,7 @@ def test_autotune_keeps_a_candidate_and_the_fixed_point():
     work = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
     best, adaptive, ms, split = s.autotune(work, 2000, 1e-10)
     assert ((best in (2, 3, 4, 6) and not adaptive) or (best in (6, 8, 12, 16, 24) and adaptive)) and ms > 0
-    assert split in (True, False)
+    assert split in (0, 1, 2)
     u = torch.zeros_like(work)
     iters, rel, st = s.split_iterate(u, 2000, 1e-10)
     assert st == 0 and rel[0] <= 1e-10
@@ -258,16 +261,17 @@ def _const_beta(n, b1, b2):
     return p
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("name,maker", [("c1_3", lambda: W.c1(3)), ("c1_4", lambda: W.c1(4)),
                                         ("c1_5", lambda: W.c1(5)),
                                         ("axis_33", lambda: _const_beta(33, 1.0, 0.0)),
                                         ("diag_33", lambda: _const_beta(33, 1.0, 1.0))])
-def test_degenerate_cases_match_oracle(name, maker):
+def test_degenerate_cases_match_oracle(name, maker, split):
     """One interior node; curves on grid lines; curves through grid nodes."""
-    print(f"[case] degenerate {name} fp64 6 sweeps", flush=True)
+    print(f"[case] degenerate {name} fp64 6 sweeps, line launches {split}", flush=True)
     p = maker()
     o = Oracle(p)
-    s = solver(p, precision="fp64", theta=1.0, dt=0.05)
+    s = solver(p, precision="fp64", theta=1.0, dt=0.05, split_lines=split)
     u = dev(o.zero_field())
     s.split_iterate(u, 6, 0.0)
     torch.cuda.synchronize()
@@ -440,11 +444,13 @@ def _bucket(nodes):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_split_line_launches_equal_the_single_launch(precision):
-    """One launch per length bucket runs every curve through the same
-    per-curve code as the single launch.  A batch whose curves fill all five
-    buckets (up to 12 nodes per thread) gives, with launch lists compacted as
-    instances finish, the single launch's sweep counts and iterates, and the
-    graph replay (full lists) gives the eager result bitwise."""
+    """One launch per length bucket (the short curves on 64- and 128-thread
+    workgroups, so partitioned differently) against the single launch: a
+    batch whose curves fill all five buckets reaches, with launch lists
+    compacted as instances finish, the same fixed point (to rounding in FP64,
+    to the FP32-lines bar with FP32 lines) in the same sweeps (+-1).  The
+    graph replay (full lists) and the concurrent launches give the eager
+    bucketed result bitwise."""
     print(f"[case] split line launches vs one launch ({precision})", flush=True)
     probs = [W.c2(2049), W.c4_instance(2, n_max=100), W.c1(33), W.c4_instance(7, n_max=600)]
     kw = dict(precision=precision, theta=1.0, dt=0.05)
@@ -467,17 +473,25 @@ def test_split_line_launches_equal_the_single_launch(precision):
     torch.cuda.synchronize()
     assert st1 == 0 and st2 == 0
     assert len(set(int(v) for v in it2)) > 1  # compaction took place
-    assert np.array_equal(it1, it2)
+    assert np.all(np.abs(it1.astype(int) - it2.astype(int)) <= 1)
     d = float(torch.max(torch.abs(u1 - u2)) / torch.max(torch.abs(u1)))
     print(f"[case] max relative difference {d:.2e} (bitwise: {bool(torch.equal(u1, u2))})", flush=True)
-    assert d <= 1e-13
+    assert d <= (1e-11 if precision == "fp64" else 1e-6)
     spl_g = solver(probs, split_lines=True, graph=True, **kw)
     u3 = torch.zeros_like(u1)
     it3, _, st3 = spl_g.split_iterate(u3, 3000, tol)
     torch.cuda.synchronize()
     assert st3 == 0 and np.array_equal(it3, it2)
     assert torch.equal(u3, u2)
-    for s in (one, spl, spl_g):
+    # the same launches on three streams at once (forked and joined by events)
+    conc = solver(probs, split_lines=2, **kw)
+    for rep in range(2):
+        u4 = torch.zeros_like(u1)
+        it4, _, st4 = conc.split_iterate(u4, 3000, tol)
+        torch.cuda.synchronize()
+        assert st4 == 0 and np.array_equal(it4, it2)
+        assert torch.equal(u4, u2), rep
+    for s in (one, spl, spl_g, conc):
         s.close()
 
 
