@@ -139,6 +139,7 @@ def bench_c4(args):
                       "fp32_sweeps_per_fp64": tuned[0] if tuned else args.fp32_sweeps,
                       "adaptive_schedule": tuned[1] if tuned else bool(args.adaptive),
                       "line_launches": LINE_LAUNCHES[tuned[3] if tuned else args.split_lines],
+                      "line_shapes": tuned[4] if tuned else [0] * 5,
                       "autotune_ms": round(tuned[2], 2) if tuned else None}}
     if True:
         out["config"]["kernels"] = {pr: {k: {"ms": round(v[0], 3), "launches": v[1]} for k, v in times[pr].items()}
@@ -422,6 +423,7 @@ def main():
     if not args.no_autotune:
         tuned = s.autotune(u, 5000, args.tol)
         args.fp32_sweeps, args.adaptive, args.split_lines = tuned[0], tuned[1], tuned[3]
+    shapes = tuned[4] if tuned else [0] * 5
 
     def solve():
         u.zero_()
@@ -481,7 +483,7 @@ def main():
                                "eq.(10) sweeps theta=1 dt=0.05 to 1e-8",
                    "time_to_1e-8_ms": ms_step, "sweeps_per_solve": sweeps[0],
                    "fp32_sweeps_per_fp64": args.fp32_sweeps, "adaptive_schedule": bool(args.adaptive),
-                   "line_launches": LINE_LAUNCHES[args.split_lines],
+                   "line_launches": LINE_LAUNCHES[args.split_lines], "line_shapes": shapes,
                    "autotuned": tuned is not None,
                    "line_unknowns_per_sweep": per_sweep,
                    "grid_unknowns": counts["grid_unknowns"], "lines": [counts["lines_b"], counts["lines_g"]],

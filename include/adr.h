@@ -173,12 +173,27 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
  *   2. with the faster of those, each candidate schedule: a fixed count of
  *      FP32 sweeps per FP64 sweep (2, 3, 4, 6) and, in eager mode, the
  *      adaptive schedule with at most 6, 8, 12, 16 or 24.
- * The fastest choice stays in the context's options.  Outputs (host, each may
- * be NULL): best_fp32_sweeps and best_adaptive (the count or maximum, and the
- * adaptive flag), best_ms (its time), best_split (the launch choice).  Kernel
- * timers (timing mode) are reset afterwards.  Synchronises. */
+ * With bucketed launches, between the two steps, each length bucket's
+ * workgroup shape (adr_set_line_shapes) is chosen from its FP32 line solves
+ * timed alone.  The fastest choices stay in the context.  Outputs (host, each
+ * may be NULL): best_fp32_sweeps and best_adaptive (the count or maximum, and
+ * the adaptive flag), best_ms (its time), best_split (the launch choice),
+ * best_shapes (5 entries, the shape of each bucket).  Kernel timers (timing
+ * mode) are reset afterwards.  Synchronises. */
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
-                        int32_t *best_adaptive, double *best_ms, int32_t *best_split);
+                        int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes);
+
+/* Workgroup shapes of the bucketed line launches (options.split_lines != 0):
+ * shapes[b] for bucket b = 0..4 (curves of at most 3072, 2048, 1024, 512, 256
+ * nodes) selects rows per thread x threads per curve:
+ *   bucket 0: 0 = 12 x 256            bucket 1: 0 = 8 x 256
+ *   bucket 2: 0 = 4 x 256, 1 = 8 x 128
+ *   bucket 3: 0 = 4 x 128, 1 = 2 x 256, 2 = 8 x 64
+ *   bucket 4: 0 = 4 x 64,  1 = 2 x 128, 2 = 1 x 256
+ * Every shape solves the same systems (the partition of a curve's rows among
+ * the threads, and so the rounding, differs).  shapes: host, 5 entries.  Set-up
+ * gives 0 everywhere.  Errors: ADR_EINVAL (a shape out of range). */
+adr_status adr_set_line_shapes(adr_ctx *ctx, const int32_t *shapes);
 
 /* Parabolic march (eq. (2) discretised by eq. (10)): nsteps sweeps with the
  * given theta in (0,1] and time step dt > 0, FP64, source f included.  u:

@@ -19,7 +19,7 @@ DOM_BOX, DOM_DISC, DOM_POLYGON = 0, 1, 2
 PREC_FP64, PREC_FP32_LINES = 0, 1
 
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
-           "adr_autotune", "adr_time_step",
+           "adr_autotune", "adr_set_line_shapes", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_set_timing", "adr_kernel_times",
            "adr_destroy", "adr_last_error", "adr_copy_probe")
 
@@ -71,7 +71,8 @@ def load():
     lib.adr_update.argtypes = [vp, P(Problem), i32]
     lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
     lib.adr_split_iterate_judged.argtypes = [vp, vp, vp, i32, dbl, P(i32), P(dbl), P(i32)]
-    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32)]
+    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32), P(i32)]
+    lib.adr_set_line_shapes.argtypes = [vp, P(i32)]
     lib.adr_set_timing.argtypes = [vp, i32]
     lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32]
     lib.adr_residual.argtypes = [vp, vp, P(dbl)]
@@ -184,14 +185,21 @@ class Solver:
         (in turn, and on concurrent streams), then each candidate schedule (fixed FP32-sweep counts, adaptive maxima)
         on `work` (overwritten), and keeps the fastest; returns (count or
         maximum, adaptive, ms, split_lines: 0 one launch, 1 per bucket, 2 per
-        bucket on concurrent streams)."""
+        bucket on concurrent streams, shapes: the workgroup shape of each length
+        bucket)."""
         best = C.c_int32()
         ad = C.c_int32()
         ms = C.c_double()
         sp = C.c_int32()
+        sh = (C.c_int32 * 5)()
         self._check(self.lib.adr_autotune(self.ctx, _device_ptr(work), int(max_iters), float(tol),
-                                          C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp)))
-        return best.value, bool(ad.value), ms.value, int(sp.value)
+                                          C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp), sh))
+        return best.value, bool(ad.value), ms.value, int(sp.value), list(sh)
+
+    def set_line_shapes(self, shapes):
+        """Workgroup shape of each of the 5 length buckets (include/adr.h)."""
+        arr = (C.c_int32 * 5)(*[int(v) for v in shapes])
+        self._check(self.lib.adr_set_line_shapes(self.ctx, arr))
 
     def split_iterate(self, u, max_iters, tol):
         iters = np.zeros(self.n, np.int32)

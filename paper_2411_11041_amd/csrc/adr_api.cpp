@@ -79,6 +79,7 @@ struct DevFam {
     // range bstart[b] .. bstart[b+1]-1 of the full list (abstart: of the
     // compacted list); bnmax: its longest curve
     int bstart[adr::kLineBuckets + 1] = {}, bnmax[adr::kLineBuckets] = {};
+    int bshape[adr::kLineBuckets] = {};  // workgroup shape of each bucket's launch (adr_autotune)
     int abstart[adr::kLineBuckets + 1] = {}, abnmax[adr::kLineBuckets] = {};
     std::vector<std::array<int, adr::kLineBuckets>> inst_bl, inst_bnmax;  // per instance and bucket
 };
@@ -187,7 +188,7 @@ struct adr_ctx {
         a.lbase = 0;
         if (!opt.split_lines) {
             const int nl = F.act >= 0 ? F.act : F.n_lines, nm = F.act >= 0 ? F.act_nmax : F.nmax;
-            return adr::launch_line<T>(f, -1, a, nl, fin, vout, par, dn, nm, st);
+            return adr::launch_line<T>(f, -1, 0, a, nl, fin, vout, par, dn, nm, st);
         }
         const int *bs = F.act >= 0 ? F.abstart : F.bstart;
         const int *bn = F.act >= 0 ? F.abnmax : F.bnmax;
@@ -211,7 +212,8 @@ struct adr_ctx {
             if (bs[b + 1] == bs[b]) continue;
             a.lbase = bs[b];
             hipStream_t sb = !conc || b == 0 ? st : side[b == 1 ? 0 : 1];
-            if ((e = adr::launch_line<T>(f, b, a, bs[b + 1] - bs[b], fin, vout, par, dn, bn[b], sb)) != hipSuccess)
+            if ((e = adr::launch_line<T>(f, b, F.bshape[b], a, bs[b + 1] - bs[b], fin, vout, par, dn, bn[b], sb)) !=
+                hipSuccess)
                 return e;
         }
         if (conc)
@@ -220,6 +222,33 @@ struct adr_ctx {
                 if ((e = hipStreamWaitEvent(st, join_ev[k], 0)) != hipSuccess) return e;
             }
         return hipSuccess;
+    }
+    // milliseconds of `reps` FP32 line solves of bucket b (both families, full
+    // lists) with workgroup shape `shape`, after one untimed run
+    double time_bucket(int b, int shape, int reps) {
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        auto run = [&]() {
+            for (int f = 0; f < 2; ++f) {
+                const DevFam &F = fam[f];
+                adr::LineArgs<float> a = F.a32;
+                a.lidx = nullptr;
+                a.lbase = F.bstart[b];
+                HIPCHK(adr::launch_line<float>(f, b, shape, a, F.bstart[b + 1] - F.bstart[b], d32, F.v32,
+                                               par_ptr(kSlotLin, f), never, F.bnmax[b], st));
+            }
+        };
+        run();
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r) run();
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return ms;
     }
     void line64(int f, int slot, const double *fin, const int *dn) {
         timed(0, f, [&] { return lines<double>(f, fam[f].a64, fin, fam[f].v64, par_ptr(slot, f), dn); });
@@ -952,7 +981,7 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
 }
 
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
-                        int32_t *best_adaptive, double *best_ms, int32_t *best_split) {
+                        int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes) {
     if (!ctx) return ADR_EINVAL;
     if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES) {
         ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0 and FP32_LINES precision";
@@ -1003,6 +1032,31 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
         }
         ctx->opt.split_lines = split;
     }
+    // 1b. with bucketed launches: each bucket's workgroup shape, from its FP32
+    //     line solves timed alone (both families, the bucket's curves of every instance)
+    if (split) {
+        try {
+            for (int b = 0; b < adr::kLineBuckets; ++b) {
+                const int ns = adr::line_shapes(b);
+                if (ns < 2 || (ctx->fam[0].bstart[b + 1] == ctx->fam[0].bstart[b] &&
+                               ctx->fam[1].bstart[b + 1] == ctx->fam[1].bstart[b]))
+                    continue;
+                int bs = 0;
+                double bt = INFINITY;
+                for (int sh = 0; sh < ns; ++sh) {
+                    const double t = ctx->time_bucket(b, sh, 3);
+                    if (t < bt) {
+                        bt = t;
+                        bs = sh;
+                    }
+                }
+                ctx->fam[0].bshape[b] = ctx->fam[1].bshape[b] = bs;
+            }
+        } catch (const Error &e) {
+            restore();
+            return fail_ctx(ctx, e);
+        }
+    }
     // 2. the FP32/FP64 sweep schedule with those launches
     int best = saved, best_ad = saved_ad;
     double best_t = INFINITY;
@@ -1031,6 +1085,24 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     if (best_adaptive) *best_adaptive = best_ad;
     if (best_ms) *best_ms = best_t;
     if (best_split) *best_split = split;
+    if (best_shapes)
+        for (int b = 0; b < adr::kLineBuckets; ++b) best_shapes[b] = ctx->fam[0].bshape[b];
+    return ADR_OK;
+}
+
+adr_status adr_set_line_shapes(adr_ctx *ctx, const int32_t *shapes) {
+    if (!ctx) return ADR_EINVAL;
+    if (!shapes || ctx->opt.host_only) {
+        ctx->err = "shapes and a device context are required";
+        return ADR_EINVAL;
+    }
+    for (int b = 0; b < adr::kLineBuckets; ++b)
+        if (shapes[b] < 0 || shapes[b] >= adr::line_shapes(b)) {
+            ctx->err = "bucket " + std::to_string(b) + " has " + std::to_string(adr::line_shapes(b)) + " shapes";
+            return ADR_EINVAL;
+        }
+    for (int b = 0; b < adr::kLineBuckets; ++b) ctx->fam[0].bshape[b] = ctx->fam[1].bshape[b] = shapes[b];
+    ctx->drop_graph();  // a captured block holds the old launches
     return ADR_OK;
 }
 

@@ -53,11 +53,16 @@ size_t line_lds_bytes(int fam, int nmax);
 constexpr int kLineBuckets = 5;
 int line_bucket(int nodes);
 
+// Workgroup shapes of bucket b (rows per thread x threads per curve): shape
+// 0 .. line_shapes(b) - 1, shape 0 the default.
+int line_shapes(int bucket);
+
 // bucket -1: one launch for curves of any length (a register footprint per
-// workgroup inside the kernel); bucket b: every curve of the launch lies in b.
-// n_lines workgroups take the list positions a.lbase .. a.lbase + n_lines - 1.
+// workgroup inside the kernel; shape ignored); bucket b: every curve of the
+// launch lies in b and is solved with the given shape.  n_lines workgroups
+// take the list positions a.lbase .. a.lbase + n_lines - 1.
 template <typename T>
-hipError_t launch_line(int fam, int bucket, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
+hipError_t launch_line(int fam, int bucket, int shape, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
                        const double *par, const int *done, int nmax, hipStream_t st);
 
 // interior nodes between the caller's row-major array and the blocked layout:

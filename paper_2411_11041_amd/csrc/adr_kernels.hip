@@ -552,16 +552,23 @@ void launch_b(const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const do
     hipLaunchKernelGGL((k_line_b<T, FAM, MAXJ, NT>), dim3(n_lines), dim3(NT), lds, st, a, fin, vout, par, done, nmax);
 }
 
-// buckets 0..4: curves of at most 3072, 2048, 1024, 512, 256 nodes
+// buckets 0..4: curves of at most 3072, 2048, 1024, 512, 256 nodes; each
+// bucket's workgroup shapes (rows per thread x threads) cover its longest
+// curve, shape 0 first
 template <typename T, int FAM>
-void launch_line_fam(int bucket, const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par,
-                     const int *done, int nmax, hipStream_t st) {
-    switch (bucket) {
+void launch_line_fam(int bucket, int shape, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
+                     const double *par, const int *done, int nmax, hipStream_t st) {
+    switch (bucket * 4 + shape) {
         case 0: launch_b<T, FAM, 12, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 1: launch_b<T, FAM, 8, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 2: launch_b<T, FAM, 4, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 3: launch_b<T, FAM, 4, 128>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 4: launch_b<T, FAM, 4, 64>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 4: launch_b<T, FAM, 8, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 8: launch_b<T, FAM, 4, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 9: launch_b<T, FAM, 8, 128>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 12: launch_b<T, FAM, 4, 128>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 13: launch_b<T, FAM, 2, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 14: launch_b<T, FAM, 8, 64>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 16: launch_b<T, FAM, 4, 64>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 17: launch_b<T, FAM, 2, 128>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 18: launch_b<T, FAM, 1, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
         default: {
             const size_t lds = line_lds_bytes<T>(FAM, nmax);
             set_lds(&k_line<T, FAM>, lds);
@@ -577,14 +584,20 @@ int line_bucket(int nodes) {
     return per <= 1 ? 4 : per <= 2 ? 3 : per <= 4 ? 2 : per <= 8 ? 1 : 0;
 }
 
+int line_shapes(int bucket) {
+    static const int kShapes[kLineBuckets] = {1, 1, 2, 3, 3};
+    return bucket >= 0 && bucket < kLineBuckets ? kShapes[bucket] : 1;
+}
+
 template <typename T>
-hipError_t launch_line(int fam, int bucket, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
+hipError_t launch_line(int fam, int bucket, int shape, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
                        const double *par, const int *done, int nmax, hipStream_t st) {
     if (n_lines == 0) return hipSuccess;
     if (nmax > 12 * kThreads || bucket > 4) return hipErrorInvalidValue;
     if (bucket >= 0 && line_bucket(nmax) < bucket) return hipErrorInvalidValue;  // curves too long for the bucket
-    if (fam == 0) launch_line_fam<T, 0>(bucket, a, n_lines, fin, vout, par, done, nmax, st);
-    else launch_line_fam<T, 1>(bucket, a, n_lines, fin, vout, par, done, nmax, st);
+    if (bucket >= 0 && (shape < 0 || shape >= line_shapes(bucket))) return hipErrorInvalidValue;
+    if (fam == 0) launch_line_fam<T, 0>(bucket, bucket < 0 ? 0 : shape, a, n_lines, fin, vout, par, done, nmax, st);
+    else launch_line_fam<T, 1>(bucket, bucket < 0 ? 0 : shape, a, n_lines, fin, vout, par, done, nmax, st);
     return hipGetLastError();
 }
 
@@ -634,10 +647,10 @@ hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st) {
 
 template size_t line_lds_bytes<double>(int, int);
 template size_t line_lds_bytes<float>(int, int);
-template hipError_t launch_line<double>(int, int, const LineArgs<double> &, int, const double *, double *,
+template hipError_t launch_line<double>(int, int, int, const LineArgs<double> &, int, const double *, double *,
                                         const double *, const int *, int, hipStream_t);
-template hipError_t launch_line<float>(int, int, const LineArgs<float> &, int, const float *, float *, const double *,
-                                       const int *, int, hipStream_t);
+template hipError_t launch_line<float>(int, int, int, const LineArgs<float> &, int, const float *, float *,
+                                       const double *, const int *, int, hipStream_t);
 template hipError_t launch_scatter<double, double>(int, const ScatterArgs<double> &, const double *, double *,
                                                    float *, double *, const int *, hipStream_t);
 template hipError_t launch_scatter<float, float>(int, const ScatterArgs<float> &, const float *, float *, float *,

@@ -125,15 +125,18 @@ def test_data2d_paper_experiment():
     s.close()
 
 
-@pytest.mark.parametrize("split", [0, 1, 2])
-def test_batched_instances_match_oracle(split):
+@pytest.mark.parametrize("split,shapes", [(0, None), (1, None), (2, None), (1, (0, 0, 1, 1, 1)),
+                                          (1, (0, 0, 0, 2, 2))])
+def test_batched_instances_match_oracle(split, shapes):
     """Disc and L-shape instances of uneven sizes in one context (one launch per
     kernel for all of them, or one per length bucket: curves of up to 256
     nodes on 64-thread workgroups, up to 512 on 128): every instance matches
     its own oracle."""
-    print(f"[case] batched c4 x4 fp64 8 sweeps, line launches {split}", flush=True)
+    print(f"[case] batched c4 x4 fp64 8 sweeps, line launches {split}, shapes {shapes}", flush=True)
     probs = [W.c4_instance(i, n_max=140) for i in range(3)] + [W.c4_instance(7, n_max=600)]
     s = solver(probs, precision="fp64", theta=1.0, dt=0.05, split_lines=split)
+    if shapes is not None:
+        s.set_line_shapes(shapes)
     off = s.layout()
     u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     iters, rel, st = s.split_iterate(u, 8, 0.0)
@@ -243,9 +246,10 @@ def test_autotune_keeps_a_candidate_and_the_fixed_point():
     p = W.c2(129)
     s = solver(p, precision="fp32", fp32_sweeps=3)
     work = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
-    best, adaptive, ms, split = s.autotune(work, 2000, 1e-10)
+    best, adaptive, ms, split, shapes = s.autotune(work, 2000, 1e-10)
     assert ((best in (2, 3, 4, 6) and not adaptive) or (best in (6, 8, 12, 16, 24) and adaptive)) and ms > 0
     assert split in (0, 1, 2)
+    assert all(0 <= v < n for v, n in zip(shapes, (1, 1, 2, 3, 3)))
     u = torch.zeros_like(work)
     iters, rel, st = s.split_iterate(u, 2000, 1e-10)
     assert st == 0 and rel[0] <= 1e-10
