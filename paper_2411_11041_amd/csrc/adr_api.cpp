@@ -598,11 +598,19 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     throw Error{ADR_EINVAL, "a curve has " + std::to_string(cnt) + " nodes; the line solver holds " +
                                                 std::to_string(kMaxNodes)};
             }
-            // workgroup order: longest curve first (stable), so that no long curve
-            // is left for the end of the launch
+            // list order: length bucket (longest first), then instance, then curve
+            // length (longest first).  With one instance this is longest first, so
+            // that no long curve is left for the end of a launch; in a batch each
+            // bucket holds the instances one after another, so that the workgroups
+            // of one XCD gather from one instance's grid at a time (see k_line_b)
             std::stable_sort(lines.begin(), lines.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
                 const adr::Family &fx = G[x.first].fam[f], &fy = G[y.first].fam[f];
-                return fx.off[x.second + 1] - fx.off[x.second] > fy.off[y.second + 1] - fy.off[y.second];
+                const int nx = static_cast<int>(fx.off[x.second + 1] - fx.off[x.second]);
+                const int ny = static_cast<int>(fy.off[y.second + 1] - fy.off[y.second]);
+                const int bx = adr::line_bucket(nx), by = adr::line_bucket(ny);
+                if (bx != by) return bx < by;
+                if (x.first != y.first) return x.first < y.first;
+                return nx > ny;
             });
             std::vector<int> loff, lcnt, linst;
             loff.reserve(lines.size());

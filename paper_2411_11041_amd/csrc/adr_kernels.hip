@@ -33,10 +33,22 @@ __host__ __device__ inline int line_lds_arrays(int fam) { return fam == 0 ? 3 : 
 __device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// List position of workgroup w of G when each XCD is to take a contiguous
+// part of the list: workgroups are dispatched to the 8 XCDs in turn (w mod 8),
+// so XCD x receives positions x*floor(G/8) + min(x, G mod 8) onwards, in order
+// (a bijection of 0..G-1).  Neighbouring curves of one instance then share
+// one XCD's L2 for their bilinear gathers.
+__device__ inline int xcd_position(int w, int G) {
+    const int x = w & 7, i = w >> 3, base = G >> 3, rem = G & 7;
+    return x * base + (x < rem ? x : rem) + i;
+}
+
 // NT threads per curve (the workgroup); a curve of n nodes needs n <= NT * MAXJ.
+// pos: the workgroup's position in the launch's part of the line list.
 template <typename T, int FAM, int MAXJ, int NT>
 __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restrict__ fin, T *__restrict__ vout,
-                                          const double *__restrict__ par, const int *__restrict__ done, int nmax) {
+                                          const double *__restrict__ par, const int *__restrict__ done, int nmax,
+                                          int pos) {
     // LDS: line_lds_arrays(FAM) arrays of line_lds_stride(nmax) elements
     //   P0  gathered values U, then the solution X
     //   P1  chords h; after every thread has read its chunk, the reduced system
@@ -57,8 +69,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T *A1 = D0 + NT, *C1 = A1 + NT, *D1 = C1 + NT;
     T *FY = A1, *FA = C1, *FG = D1;
 
-    const int pos = a.lbase + static_cast<int>(blockIdx.x);
-    const int l = a.lidx ? a.lidx[pos] : pos;
+    const int l = a.lidx ? a.lidx[a.lbase + pos] : a.lbase + pos;
     const int tid = threadIdx.x;
     const int inst = a.linst[l];
     if (done[inst]) return;
@@ -315,13 +326,14 @@ template <typename T, int FAM>
 __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
                                                    T *__restrict__ vout, const double *__restrict__ par,
                                                    const int *__restrict__ done, int nmax) {
-    const int pos = a.lbase + static_cast<int>(blockIdx.x);
-    const int per = (a.lcnt[a.lidx ? a.lidx[pos] : pos] + kThreads - 1) / kThreads;
-    if (per <= 1) line_body<T, FAM, 1, kThreads>(a, fin, vout, par, done, nmax);
-    else if (per <= 2) line_body<T, FAM, 2, kThreads>(a, fin, vout, par, done, nmax);
-    else if (per <= 4) line_body<T, FAM, 4, kThreads>(a, fin, vout, par, done, nmax);
-    else if (per <= 8) line_body<T, FAM, 8, kThreads>(a, fin, vout, par, done, nmax);
-    else line_body<T, FAM, 12, kThreads>(a, fin, vout, par, done, nmax);
+    // the list order (longest first) is the dispatch order
+    const int pos = static_cast<int>(blockIdx.x);
+    const int per = (a.lcnt[a.lidx ? a.lidx[a.lbase + pos] : a.lbase + pos] + kThreads - 1) / kThreads;
+    if (per <= 1) line_body<T, FAM, 1, kThreads>(a, fin, vout, par, done, nmax, pos);
+    else if (per <= 2) line_body<T, FAM, 2, kThreads>(a, fin, vout, par, done, nmax, pos);
+    else if (per <= 4) line_body<T, FAM, 4, kThreads>(a, fin, vout, par, done, nmax, pos);
+    else if (per <= 8) line_body<T, FAM, 8, kThreads>(a, fin, vout, par, done, nmax, pos);
+    else line_body<T, FAM, 12, kThreads>(a, fin, vout, par, done, nmax, pos);
 }
 
 // One launch per length bucket: every curve of the launch has at most
@@ -333,7 +345,10 @@ template <typename T, int FAM, int MAXJ, int NT>
 __global__ __launch_bounds__(NT) void k_line_b(LineArgs<T> a, const T *__restrict__ fin,
                                                T *__restrict__ vout, const double *__restrict__ par,
                                                const int *__restrict__ done, int nmax) {
-    line_body<T, FAM, MAXJ, NT>(a, fin, vout, par, done, nmax);
+    // the curves of one bucket have similar lengths: each XCD takes a contiguous
+    // part of the list (one instance's neighbouring curves)
+    line_body<T, FAM, MAXJ, NT>(a, fin, vout, par, done, nmax,
+                                xcd_position(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)));
 }
 
 // Scatter: out = P v on the interior nodes.  MODE 0: write; MODE 1 (FP64 sweep):
