@@ -32,14 +32,15 @@ HBM_PEAK_GBS = 8000.0
 # about one line node) and the written line value.
 LINE_BYTES = {("fp32", 0): 4 + 4 * 2 + 4 + 4 + 4 + 4 + 4, ("fp32", 1): 4 + 4 * 2 + 4 + 4 + 4,
               ("fp64", 0): 4 + 8 * 2 + 8 + 8 + 8 + 8 + 8, ("fp64", 1): 4 + 8 * 2 + 8 + 8 + 8}
-# Scatter: per interior grid node its grid index (4 B), 4 records (index 4 B +
-# two weights: FP16 pair in the FP32 sweeps, 2 x FP64 in the FP64 sweeps), the
-# 8 line values they reference (each line value is referenced by ~2 nodes: 4
-# per node) and the written grid value (FP64 update: read+write state, write
-# the FP32 increment).  Keys: (precision, 2) beta half sweep, (precision, 3)
-# gamma half sweep.
-SCATTER_BYTES = {("fp32", 2): 4 + 4 * (4 + 4) + 4 * 4 + 4, ("fp32", 3): 4 + 4 * (4 + 4) + 4 * 4 + 8 + 8 + 4,
-                 ("fp64", 2): 4 + 4 * (4 + 16) + 4 * 8 + 8, ("fp64", 3): 4 + 4 * (4 + 16) + 4 * 8 + 8 + 8 + 4}
+# Scatter: per interior grid node its grid index (4 B), its 4 records (the
+# first record's line node 4 B and three 16-bit offsets 6 B; two weights per
+# record: FP16 pair in the FP32 sweeps, 2 x FP64 in the FP64 sweeps), the 8
+# line values they reference (each line value is referenced by ~2 nodes: 4 per
+# node) and the written grid value (FP64 update: read+write state, write the
+# FP32 increment).  Keys: (precision, 2) beta half sweep, (precision, 3) gamma
+# half sweep.
+SCATTER_BYTES = {("fp32", 2): 4 + 10 + 4 * 4 + 4 * 4 + 4, ("fp32", 3): 4 + 10 + 4 * 4 + 4 * 4 + 8 + 8 + 4,
+                 ("fp64", 2): 4 + 10 + 4 * 16 + 4 * 8 + 8, ("fp64", 3): 4 + 10 + 4 * 16 + 4 * 8 + 8 + 8 + 4}
 
 
 def parse():

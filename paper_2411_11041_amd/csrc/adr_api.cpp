@@ -688,6 +688,23 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     }
                 }
             const int *d_rk = upload(rk, own, st);
+            // compact form: the first record's node and 16-bit offsets of the others
+            std::vector<int> rk0(npad, -1);
+            std::vector<short> rd(3 * static_cast<size_t>(npad), adr::kRecMissing);
+            for (size_t slot = 0; slot < static_cast<size_t>(npad); ++slot) {
+                const int k0 = rk[slot];
+                rk0[slot] = k0;
+                for (int r = 1; r < 4; ++r) {
+                    const int kr = rk[r * static_cast<size_t>(npad) + slot];
+                    short &d = rd[(r - 1) * static_cast<size_t>(npad) + slot];
+                    if (kr < 0) d = adr::kRecMissing;
+                    else if (k0 >= 0 && std::abs(static_cast<int64_t>(kr) - k0) <= adr::kRecMaxDelta)
+                        d = static_cast<short>(kr - k0);
+                    else d = adr::kRecEscape;
+                }
+            }
+            const int *d_rk0 = upload(rk0, own, st);
+            const short *d_rd = upload(rd, own, st);
             std::vector<unsigned> rw(ra.size());
             for (size_t e = 0; e < ra.size(); ++e) {
                 const _Float16 a16 = static_cast<_Float16>(static_cast<float>(ra[e]));
@@ -695,9 +712,10 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 rw[e] = static_cast<unsigned>(__builtin_bit_cast(unsigned short, a16)) |
                         (static_cast<unsigned>(__builtin_bit_cast(unsigned short, b16)) << 16);
             }
-            F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, upload(ra, own, st), upload(rb, own, st),
-                                             nullptr, npad};
-            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, nullptr, nullptr, upload(rw, own, st), npad};
+            F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, upload(ra, own, st),
+                                             upload(rb, own, st), nullptr, npad};
+            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, nullptr, nullptr,
+                                            upload(rw, own, st), npad};
             F.v64 = dalloc<double>(F.n_nodes, own);
             F.v32 = dalloc<float>(F.n_nodes, own);
             for (int i = 0; i < n; ++i) C->geo[f].push_back(G[i].fam[f]);

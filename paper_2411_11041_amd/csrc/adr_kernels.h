@@ -21,12 +21,23 @@ struct LineArgs {
     int lbase;           // list position of the launch's first workgroup (length buckets)
 };
 
+// Record indices relative to the slot's first record (ScatterArgs::rd)
+constexpr short kRecMissing = -32768;  // no record
+constexpr short kRecEscape = -32767;   // too far from the first: read rk
+constexpr int kRecMaxDelta = 32766;
+
 // Scatter stencils of one family; slot s < npad (padded per instance to 256).
+// The 4 records of a slot reference nearby line nodes, so they are stored as
+// the first record's node (rk0) and three 16-bit offsets from it (rd); a
+// record too far away (or whose first record is missing) is marked
+// kRecEscape and read from the full table rk.
 template <typename T>
 struct ScatterArgs {
     const int *gidx;      // blocked index of the interior node, -1 for padding
     const int *blk_inst;  // instance of each 256-slot block
-    const int *rk;        // [4][npad] first node of the record's segment, -1 unused
+    const int *rk;        // [4][npad] first node of the record's segment, -1 unused (escapes only)
+    const int *rk0;       // [npad] rk[0]
+    const short *rd;      // [3][npad] rk[r] - rk0 for r = 1..3, or kRecMissing / kRecEscape
     const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1] (FP64 tables)
     const unsigned *rw;   // [4][npad] the same weights as two FP16 halves (low: v[k]); FP32 tables
     int npad;

@@ -372,9 +372,12 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
     // on g
     int kk[4];
     T wa[4], wb[4];
+    short dk[3];
+    kk[0] = s.rk0[slot];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) dk[r] = s.rd[r * np + slot];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        kk[r] = s.rk[r * np + slot];
         if constexpr (sizeof(T) == 4) {
             // increment sweeps: FP16 weights (relative error 2^-11; the FP64
             // sweeps, with FP64 weights, fix the iterate and its residual)
@@ -385,6 +388,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
             wa[r] = s.ra[r * np + slot];
             wb[r] = s.rb[r * np + slot];
         }
+    }
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const short d = dk[r - 1];
+        kk[r] = d == kRecMissing ? -1 : d == kRecEscape ? s.rk[r * np + slot] : kk[0] + d;
     }
     TO old = TO(0);
     if constexpr (MODE != 0) old = out[g >= 0 ? g : 0];
