@@ -111,3 +111,22 @@ def test_empty_and_undersized_inputs_rejected():
     with pytest.raises(ADRError) as e:
         Solver(W.c1(2), host_only=True)  # no interior node
     assert e.value.code == ADR_EINVAL
+
+
+def test_device_only_calls_reject_host_contexts():
+    """Calls that launch work refuse a host-only context with ADR_EINVAL (no
+    device touched); argument checks come before any launch."""
+    import ctypes as C
+    from paper_2411_11041_amd.adr import ADR_EINVAL, Solver, load
+    lib = load()
+    s = Solver(W.c1(9), host_only=True)
+    shapes = (C.c_int32 * 5)(0, 0, 0, 0, 0)
+    assert lib.adr_set_line_shapes(s.ctx, shapes) == ADR_EINVAL
+    assert lib.adr_set_line_shapes(None, shapes) == ADR_EINVAL
+    fake = C.c_void_p(1)  # never dereferenced: the context check comes first
+    it = (C.c_int32 * 1)()
+    rel = (C.c_double * 1)()
+    used = (C.c_int32 * 1)()
+    assert lib.adr_split_iterate_judged(s.ctx, fake, fake, 10, 1e-8, it, rel, used) == ADR_EINVAL
+    assert lib.adr_split_iterate_judged(None, fake, fake, 10, 1e-8, it, rel, used) == ADR_EINVAL
+    s.close()
