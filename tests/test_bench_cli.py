@@ -1,5 +1,5 @@
 """bench.py's command line on the CPU: more than one GPU is refused with a
-message (this build measures one GPU), and the byte model the roofline divides
+message (the benchmark measures one GPU), and the byte model the roofline divides
 by matches the per-unit bytes stated for the kernels."""
 import os
 import subprocess
