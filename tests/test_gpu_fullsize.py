@@ -92,3 +92,40 @@ def test_c3_full_parabolic_march():
     assert e10 <= 1e-11 * g["max10"]
     assert e200 <= 1e-11 * g["max10"]
     s.close()
+
+
+def test_c4_full_batch_bench_configuration():
+    """The 512-instance batch in the benchmark's configuration (launch shape,
+    bucket shapes and sweep schedule chosen by adr_autotune): every instance
+    stops at rel <= 1e-8, and sampled instances (the four smallest grids, discs
+    and L-shapes) match their own oracle fixed points to the FP32-lines bar."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("[case] c4 512 instances, autotuned, to 1e-8; sampled instances vs oracle", flush=True)
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle.method import Oracle
+    from paper_2411_11041_amd.adr import Solver
+    with ThreadPoolExecutor(max_workers=8) as ex:
+        probs = list(ex.map(W.c4_instance, range(512)))
+    s = Solver(probs, precision="fp32", fp32_sweeps=3, theta=1.0, dt=0.05)
+    off = s.layout()
+    u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    tuned = s.autotune(u, 3000, 1e-8)
+    print(f"[case] autotuned: {tuned}", flush=True)
+    u.zero_()
+    iters, rel, st = s.split_iterate(u, 3000, 1e-8)
+    torch.cuda.synchronize()
+    assert st == 0 and np.all(rel <= 1e-8), (st, rel.max())
+    U = u.cpu().numpy()
+    sizes = np.array([p.nx for p in probs])
+    picks = list(np.argsort(sizes, kind="stable")[:4])
+    assert {int(i) % 2 for i in picks} == {0, 1}  # discs and L-shapes
+    for i in picks:
+        p = probs[i]
+        o = Oracle(p)
+        Ui, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 4000, 1e-12)
+        e = np.linalg.norm(U[off[i]:off[i + 1]] - Ui) / np.linalg.norm(Ui)
+        print(f"[case] instance {i} ({p.nx}^2): rel L2 vs oracle {e:.2e}, sweeps {int(iters[i])}", flush=True)
+        assert e < 1e-5, (i, e)
+    s.close()
