@@ -129,3 +129,35 @@ def test_c4_full_batch_bench_configuration():
         print(f"[case] instance {i} ({p.nx}^2): rel L2 vs oracle {e:.2e}, sweeps {int(iters[i])}", flush=True)
         assert e < 1e-5, (i, e)
     s.close()
+
+
+def test_c5_full_size_warm_start():
+    """The warm-start configuration at its full size: 257^2 samples, the
+    network on every 8th node (33^2), a short training (512 samples, 20
+    epochs), then the judged warm-started solve of 16 test seeds to 1e-8.
+    Every instance converges to the fixed point of the plain solve (within the
+    bound the stopping test implies), and inference plus the judge leave the
+    iteration unchanged otherwise."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    print("[case] c5 257^2, network on 33^2: train 512 x 20, judged solve of 16 seeds", flush=True)
+    from paper_2411_11041_amd import warmstart as WS
+    from paper_2411_11041_amd.adr import Net
+    wl = WS.Workload(n=257, batch=128, coarsen=8)
+    net = Net(*wl.coarse_shape(), 128)
+    net.set_params(WS.he_init(0))
+    x, t = wl.generate(net, list(range(512)), tol=1e-10)
+    losses = WS.train(net, x, t, wl.mask_c, 512, wl.HWc, 20, batch=32, lr=2e-3, lr_end=2e-5)
+    assert losses[-1] < losses[0]
+    test = list(range(20000, 20016))
+    tol = 1e-8
+    u0, it0, rel0, _ = wl.solve_batch(test, tol)
+    un, itn, reln, _, fb = wl.warm_started(net, test, tol, use_net=True)
+    print(f"[case] sweeps: zero {it0.mean():.1f}, network {itn.mean():.1f} (fallbacks {fb})", flush=True)
+    assert np.all(rel0 <= tol) and np.all(reln <= tol)
+    a = u0.view(len(test), wl.HW).cpu().numpy()
+    b = un.view(len(test), wl.HW).cpu().numpy()
+    err = np.linalg.norm(a - b, axis=1) / np.linalg.norm(a, axis=1)
+    assert np.all(err < 100 * tol), err.max()
+    net.close()
+    wl.solver.close()
