@@ -193,8 +193,9 @@ struct adr_ctx {
         const int *bs = F.act >= 0 ? F.abstart : F.bstart;
         const int *bn = F.act >= 0 ? F.abnmax : F.bnmax;
         // concurrent: the longest bucket on st, the next on side[0], the short ones
-        // in turn on side[1] (not inside a graph capture, which runs on cap)
-        const bool conc = opt.split_lines == 2 && st != cap;
+        // in turn on side[1] (not inside a graph capture, which runs on cap; st may
+        // be the null stream, so the test is on cap being in use)
+        const bool conc = opt.split_lines == 2 && !(cap != nullptr && st == cap);
         hipError_t e = hipSuccess;
         if (conc) {
             if (!side[0]) {
