@@ -84,7 +84,8 @@ typedef struct {
     void *stream;         /* hipStream_t; NULL = the default stream */
     int32_t timing;       /* != 0: time each kernel with HIP events (adr_kernel_times) */
     int32_t host_only;    /* != 0: build the host geometry only, touch no device; then
-                             only adr_counts, adr_export_lines and adr_destroy are valid */
+                             only adr_counts, adr_export_lines, adr_export_scatter and
+                             adr_destroy are valid */
     int32_t graph;        /* != 0: adr_split_iterate replays its sweep blocks from a captured
                              HIP graph (on a context-owned stream ordered after options.stream);
                              ignored when timing != 0 */
@@ -216,6 +217,19 @@ adr_status adr_initial_guess(adr_ctx *ctx, double *u);
  * buffers. */
 adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_lines,
                             int64_t *n_nodes, int64_t *offsets, double *x, double *y);
+
+/* Test export (host-only contexts): the scatter stencil of Sec. 6 that the
+ * set-up built for one instance and family, one row per interior grid node in
+ * row-major order.  Row r is grid node node[r] (row-major index in the
+ * instance's grid); its value is sum over the 4 slots s (horizontal low,
+ * horizontal high, vertical low, vertical high) of ca[4r+s] v[k] + cb[4r+s]
+ * v[k+1], k = k[4r+s] a node index of the family local to the instance
+ * (offsets of adr_export_lines); k = -1 marks a boundary point of Gamma (Dirichlet
+ * value, weights 0).  Call with NULL arrays to get *n_rows, then with node
+ * (n_rows) and k, ca, cb (4 n_rows) host buffers.  Errors: ADR_EINVAL (a
+ * device context, an index out of range). */
+adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
+                              int32_t *node, int32_t *k, double *ca, double *cb);
 
 /* Per-launch HIP-event timing on (1) or off (0) from now on (the set-up
  * option's initial value).  Each timed launch records two events on the

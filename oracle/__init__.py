@@ -12,9 +12,13 @@ Modules
   geometry   Sec. 3 fields b, p; eq. (12) inflow sets; eq. (13)-(14) curve families
   linefe     eq. (16)-(19): P1 line elements and tridiagonal solves
   transfer   Sec. 6 grid interpolation: scatter (crossing records) and eq. (21)-(23) gather
-  method     operators A_h, F_h, residual, defect-correction iteration, eq. (10) Lie
-             step, eq. (11) initial guess, implicit-Euler parabolic stepping
-  dense      brute-force dense / sparse direct solves of the method's own system
+  method     one step Phi of eq. (10) (beta and gamma substeps, values handed on
+             through the grid), the stationary fixed-point iteration and its
+             relative update, eq. (11) initial guess, theta-scheme time marching
+  dense      the affine map Phi(U) = T U + c assembled column by column, and the
+             dense LU solve of (I - T) U = c (the iteration's limit)
+  coarse     full-weighting restriction and bilinear interpolation between the
+             solver grid and the warm-start network's coarse grid
   galerkin2d own 2D P1 Galerkin solve of eq. (5)-(6) (independent reference)
   cnn        FP64 conv-net forward/backward for the learned warm start
 

@@ -19,21 +19,24 @@ advection-reaction paper):
      grid line (the max record of the edge to the left, the min record of the
      edge to the right) gives a linear interpolant; the same along the
      vertical grid line;
-  4. the node value combines the two estimates.
+  4. the node value is the average of the two estimates.
 Readings: an edge with no crossing passes the search on to the next edge
 outward; where the grid line leaves Omega first, the boundary point acts as a
-crossing carrying the Dirichlet value (zero for increments).  Step 4's
-"average" is taken as a weighted mean with weights 1/(dL*dR + (h/10)^2), dL,
-dR the distances from the node to its two bracketing crossings; when the two
-brackets are alike this is the plain average, and it stays continuous when a
-crossing passes through a node.
+crossing carrying the Dirichlet value (zero for increments).  Step 4 is the
+plain average wherever both estimates are local: an estimate is local when
+each of its two brackets lies on one of the LOCAL_EDGES grid edges nearest
+the node on that side (within 4 grid spacings).  Where only one estimate is
+local, that estimate alone is the node value; this is the case where the
+curves run along (or nearly along) a grid line, so that the line carries no
+crossing for many edges and its estimate would interpolate across a large
+part of the domain.  Where neither is local the plain average is kept.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.sparse as sp
 
-EPS_W = 0.1  # regulariser of the direction weights, in units of h
+LOCAL_EDGES = 4  # a bracket found further out than this many edges is not local
 
 
 def gather_matrix(grid, fam):
@@ -110,7 +113,8 @@ def _bracket(emin, emax, inner_line, rec, gl, pos_of_line, dom, along_x, fixed):
     closest record at-or-before and at-or-after along the line.
 
     inner_line: (n_lines, n_nodes) interior-node mask along each grid line.
-    Returns for each side dict(kind: 0 line record / 1 boundary, idx, coord).
+    Returns for each side (kind: 0 line record / 1 boundary, idx, coord, depth),
+    depth the number of edges from the node to the edge holding the bracket.
     """
     nL, nE = emin.shape
     nN = nE + 1
@@ -128,6 +132,7 @@ def _bracket(emin, emax, inner_line, rec, gl, pos_of_line, dom, along_x, fixed):
         kind = np.full((nL, nN), -1, np.int64)
         idx = np.full((nL, nN), -1, np.int64)
         coord = np.full((nL, nN), np.nan)
+        depth = np.zeros((nL, nN), np.int64)  # 1 = the node's own edge on that side
         for p in range(nN):
             if side == "L":
                 if p == 0:
@@ -137,6 +142,7 @@ def _bracket(emin, emax, inner_line, rec, gl, pos_of_line, dom, along_x, fixed):
                 rid = np.where(valid, emax[np.arange(nL), np.maximum(e, 0)], -1)
                 far = np.maximum(e, 0)           # node on the far side of the edge
                 near = far + 1
+                depth[:, p] = p - e
             else:
                 if p == nN - 1:
                     continue
@@ -145,6 +151,7 @@ def _bracket(emin, emax, inner_line, rec, gl, pos_of_line, dom, along_x, fixed):
                 rid = np.where(valid, emin[np.arange(nL), np.minimum(e, nE - 1)], -1)
                 far = np.minimum(e, nE - 1) + 1
                 near = far - 1
+                depth[:, p] = e - p + 1
             has = valid & (rid >= 0)
             kind[has, p] = 0
             idx[has, p] = rid[has]
@@ -163,14 +170,16 @@ def _bracket(emin, emax, inner_line, rec, gl, pos_of_line, dom, along_x, fixed):
                     t = dom.first_hit(xs0, ys0, xs1, ys1)
                     coord[L, p] = ys0 + t * (ys1 - ys0)
                 kind[L, p] = 1
-        res[side] = (kind, idx, coord)
+        res[side] = (kind, idx, coord, depth)
     return res
 
 
-def scatter_matrix(grid, dom, fam, node_mask):
+def scatter_matrix(grid, dom, fam, node_mask, literal=False):
     """Sparse P: (nx*ny, n_line_nodes) and the boundary-record list.
 
     node_mask: (ny, nx) interior grid nodes (rows of P exist only for these).
+    literal: average the two estimates at every node, local or not (the rule
+    of Sec. 6 with no fallback; used only to compare the readings).
     Returns P and (rows, coefs, xb, yb): the weight each boundary crossing point
     (xb, yb) carries in row `rows` (used when the scattered field has non-zero
     values on Gamma).
@@ -183,26 +192,29 @@ def scatter_matrix(grid, dom, fam, node_mask):
     # horizontal estimate: along rows j (grid line y = y_j), positions i
     H = _bracket(hmin, hmax, node_mask, recs[1], grid.x, None, dom, True, grid.y)
     V = _bracket(vmin, vmax, node_mask.T, recs[0], grid.y, None, dom, False, grid.x)
-    eps2 = (EPS_W * grid.h) ** 2
     J, I = np.nonzero(node_mask)
     rows_all, cols_all, vals_all = [], [], []
     b_rows, b_coef, b_x, b_y = [], [], [], []
 
     def side_info(D, a_, b_, rec):
-        kind, idx, coord = D
-        return kind[a_, b_], idx[a_, b_], coord[a_, b_]
+        kind, idx, coord, depth = D
+        return kind[a_, b_], idx[a_, b_], coord[a_, b_], depth[a_, b_]
 
     # horizontal: grid line j, position i ; vertical: grid line i, position j
-    kLh, iLh, cLh = side_info(H["L"], J, I, recs[1])
-    kRh, iRh, cRh = side_info(H["R"], J, I, recs[1])
-    kLv, iLv, cLv = side_info(V["L"], I, J, recs[0])
-    kRv, iRv, cRv = side_info(V["R"], I, J, recs[0])
+    kLh, iLh, cLh, eLh = side_info(H["L"], J, I, recs[1])
+    kRh, iRh, cRh, eRh = side_info(H["R"], J, I, recs[1])
+    kLv, iLv, cLv, eLv = side_info(V["L"], I, J, recs[0])
+    kRv, iRv, cRv, eRv = side_info(V["R"], I, J, recs[0])
     xi, yj = grid.x[I], grid.y[J]
     dL_h, dR_h = xi - cLh, cRh - xi
     dL_v, dR_v = yj - cLv, cRv - yj
-    w_h = 1.0 / (dL_h * dR_h + eps2)
-    w_v = 1.0 / (dL_v * dR_v + eps2)
-    W_h = w_h / (w_h + w_v)
+    # share of the horizontal estimate: 1/2 (the average), or 1 / 0 where only
+    # the horizontal / only the vertical estimate is local
+    loc_h = (eLh <= LOCAL_EDGES) & (eRh <= LOCAL_EDGES)
+    loc_v = (eLv <= LOCAL_EDGES) & (eRv <= LOCAL_EDGES)
+    if literal:
+        loc_h = loc_v = np.ones(len(J), bool)
+    W_h = np.where(loc_h == loc_v, 0.5, np.where(loc_h, 1.0, 0.0))
     W_v = 1.0 - W_h
 
     def lerp_coefs(dL, dR):

@@ -20,7 +20,7 @@ PREC_FP64, PREC_FP32_LINES = 0, 1
 
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
            "adr_autotune", "adr_set_line_shapes", "adr_time_step",
-           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_set_timing", "adr_kernel_times",
+           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_set_timing", "adr_kernel_times",
            "adr_destroy", "adr_last_error", "adr_copy_probe")
 
 KERNEL_CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma", "norm")
@@ -78,6 +78,7 @@ def load():
     lib.adr_residual.argtypes = [vp, vp, P(dbl)]
     lib.adr_initial_guess.argtypes = [vp, vp]
     lib.adr_export_lines.argtypes = [vp, i32, i32, P(i64), P(i64), P(i64), P(dbl), P(dbl)]
+    lib.adr_export_scatter.argtypes = [vp, i32, i32, P(i64), P(i32), P(i32), P(dbl), P(dbl)]
     lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), i32]
     lib.adr_destroy.argtypes = [vp]
     lib.adr_copy_probe.argtypes = [vp, vp, i64, vp]
@@ -246,6 +247,20 @@ class Solver:
         self._check(self.lib.adr_export_lines(self.ctx, inst, family, None, None,
                                               off.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(x), _dptr(y)))
         return off, x, y
+
+    def export_scatter(self, inst, family):
+        """Scatter stencil rows (host-only contexts): node, k, ca, cb."""
+        nr = C.c_int64()
+        self._check(self.lib.adr_export_scatter(self.ctx, inst, family, C.byref(nr), None, None, None, None))
+        n = nr.value
+        node = np.zeros(n, np.int32)
+        k = np.zeros(4 * n, np.int32)
+        ca = np.zeros(4 * n)
+        cb = np.zeros(4 * n)
+        i32p = C.POINTER(C.c_int32)
+        self._check(self.lib.adr_export_scatter(self.ctx, inst, family, None, node.ctypes.data_as(i32p),
+                                                k.ctypes.data_as(i32p), _dptr(ca), _dptr(cb)))
+        return node, k.reshape(n, 4), ca.reshape(n, 4), cb.reshape(n, 4)
 
     def kernel_times(self, precision="fp64", reset=True):
         ms = np.zeros(5)

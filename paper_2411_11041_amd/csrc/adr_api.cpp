@@ -114,6 +114,7 @@ struct adr_ctx {
     std::vector<double> mu, sg;
     std::string err;
     std::vector<adr::Family> geo[2];  // per instance, for export
+    std::vector<adr::InstanceGeo> host_geo;  // host-only contexts: the whole set-up, for export
     std::vector<adr::Grid> grids;     // per instance
     std::vector<adr_problem> shape;   // per instance: grid and domain (pointers cleared)
     std::vector<int64_t> noffB;       // first beta-line node of each instance
@@ -506,6 +507,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     C->geo[f].push_back(fa);
                 }
             }
+            C->host_geo = std::move(G);
             *out = C.release();
             return ADR_OK;
         }
@@ -1208,6 +1210,24 @@ adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, in
     if (offsets) std::copy(F.off.begin(), F.off.end(), offsets);
     if (x) std::copy(F.x.begin(), F.x.end(), x);
     if (y) std::copy(F.y.begin(), F.y.end(), y);
+    return ADR_OK;
+}
+
+adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
+                              int32_t *node, int32_t *k, double *ca, double *cb) {
+    if (!ctx || !ctx->opt.host_only || inst < 0 || inst >= ctx->n_inst || family < 0 || family > 1)
+        return ADR_EINVAL;
+    const adr::InstanceGeo &G = ctx->host_geo[inst];
+    const std::vector<adr::Rec4> &R = G.rec[family];
+    if (n_rows) *n_rows = static_cast<int64_t>(R.size());
+    for (size_t r = 0; r < R.size(); ++r) {
+        if (node) node[r] = G.inner_list[r];
+        for (int q = 0; q < 4; ++q) {
+            if (k) k[4 * r + q] = R[r].k[q];
+            if (ca) ca[4 * r + q] = R[r].ca[q];
+            if (cb) cb[4 * r + q] = R[r].cb[q];
+        }
+    }
     return ADR_OK;
 }
 

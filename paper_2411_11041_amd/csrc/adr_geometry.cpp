@@ -27,7 +27,7 @@ constexpr double kCeilTol = 1e-9;
 constexpr int kBisect = 44;
 constexpr double kMerge = 0.1;
 constexpr double kNodeMargin = 1e-9;
-constexpr double kEpsW = 0.1;
+constexpr int kLocalEdges = 4;  // a scatter bracket further out is not local
 
 [[noreturn]] void fail(adr_status c, const std::string &m) { throw Error{c, m}; }
 
@@ -321,6 +321,7 @@ struct Bracket {
     double coord;
     int64_t k;
     double t;
+    int depth;     // edges from the node to the edge holding the bracket (1 = own edge)
 };
 
 void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> &inner,
@@ -362,7 +363,6 @@ void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> 
             }
         }
     }
-    const double eps2 = (kEpsW * g.h) * (kEpsW * g.h);
     out.resize(inner_list.size());
     auto is_in = [&](int i, int j) { return inner[static_cast<size_t>(j) * nx + i] != 0; };
     for (size_t n = 0; n < inner_list.size(); ++n) {
@@ -389,10 +389,10 @@ void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> 
             for (int e = pos - 1; e >= 0 && !found; --e) {
                 int64_t r = emax[base + e];
                 if (r >= 0) {
-                    br[dir][0] = {0, rec[r].coord, rec[r].k, rec[r].t};
+                    br[dir][0] = {0, rec[r].coord, rec[r].k, rec[r].t, pos - e};
                     found = true;
                 } else if (!node_in(e)) {
-                    br[dir][0] = {1, boundary(e + 1, e), -1, 0.0};
+                    br[dir][0] = {1, boundary(e + 1, e), -1, 0.0, pos - e};
                     found = true;
                 }
             }
@@ -401,27 +401,32 @@ void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> 
             for (int e = pos; e < nE && !found; ++e) {
                 int64_t r = emin[base + e];
                 if (r >= 0) {
-                    br[dir][1] = {0, rec[r].coord, rec[r].k, rec[r].t};
+                    br[dir][1] = {0, rec[r].coord, rec[r].k, rec[r].t, e - pos + 1};
                     found = true;
                 } else if (!node_in(e + 1)) {
-                    br[dir][1] = {1, boundary(e, e + 1), -1, 0.0};
+                    br[dir][1] = {1, boundary(e, e + 1), -1, 0.0, e - pos + 1};
                     found = true;
                 }
             }
             if (!found) fail(ADR_EINVAL, "interior grid node without a bracketing record");
             (void)coord_of;
         }
-        double W[2], cl[2], cr[2];
+        // Sec. 6: the node value is the average of the two estimates. An
+        // estimate whose bracket lies beyond the kLocalEdges nearest edges is
+        // not local (curves along a grid line); where only one estimate is
+        // local it is used alone.
+        double cl[2], cr[2];
+        bool local[2];
         for (int dir = 0; dir < 2; ++dir) {
             double p = dir == 0 ? g.x(gi) : g.y(gj);
             double dL = p - br[dir][0].coord, dR = br[dir][1].coord - p;
             double span = dL + dR;
             if (span > 0) { cl[dir] = dR / span; cr[dir] = dL / span; }
             else { cl[dir] = 0.5; cr[dir] = 0.5; }
-            W[dir] = 1.0 / (dL * dR + eps2);
+            local[dir] = br[dir][0].depth <= kLocalEdges && br[dir][1].depth <= kLocalEdges;
         }
-        double Wh = W[0] / (W[0] + W[1]);
-        double Ws[2] = {Wh, 1.0 - Wh};
+        const double Wh = local[0] == local[1] ? 0.5 : (local[0] ? 1.0 : 0.0);
+        const double Ws[2] = {Wh, 1.0 - Wh};
         Rec4 &R = out[n];
         for (int dir = 0; dir < 2; ++dir) {
             for (int side = 0; side < 2; ++side) {

@@ -68,6 +68,33 @@ def test_host_geometry_matches_oracle(maker):
     s.close()
 
 
+@pytest.mark.parametrize("maker", [lambda: W.c1(65), lambda: W.c2(129), lambda: W.data2d(31),
+                                   lambda: W.c4_instance(0, n_max=120), lambda: W.c4_instance(1, n_max=120),
+                                   lambda: W.c1(3), _axis_beta, _diag_beta])
+def test_host_scatter_matches_oracle(maker):
+    """The set-up's scatter stencils (Sec. 6 node rule, records, lerp weights)
+    equal the oracle's scatter matrix entry by entry."""
+    from oracle.method import Oracle
+    from paper_2411_11041_amd.adr import Solver
+    p = maker()
+    s = Solver(p, host_only=True)
+    o = Oracle(p)
+    for f in (0, 1):
+        node, k, ca, cb = s.export_scatter(0, f)
+        assert np.array_equal(node, o.inner_idx)
+        n_nodes = o.fams[f].n_nodes
+        dense = np.zeros((len(node), n_nodes))
+        for q in range(4):
+            ok = k[:, q] >= 0
+            r = np.nonzero(ok)[0]
+            np.add.at(dense, (r, k[ok, q]), ca[ok, q])
+            np.add.at(dense, (r, k[ok, q] + 1), cb[ok, q])
+            assert np.all(ca[~ok, q] == 0) and np.all(cb[~ok, q] == 0)
+        ref = o.P[f][o.inner_idx].toarray()
+        assert np.max(np.abs(dense - ref)) < 1e-12
+    s.close()
+
+
 def test_setup_errors():
     from paper_2411_11041_amd.adr import ADRError, Solver, ADR_EINVAL, ADR_ENONFINITE, ADR_EBETA
     p = W.c1(17)

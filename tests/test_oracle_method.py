@@ -142,3 +142,34 @@ def test_iterate_history_and_stop():
     assert rel <= 1e-8 and hist[-2] > 1e-8 and len(hist) == it
     # the returned iterate is one step past the last measured update
     assert o.rel_residual(U, 1.0, 0.05) < rel
+
+
+@pytest.mark.parametrize("mu,sigma,c", [(0.1, 1.0, 1.0), (0.02, 3.0, -0.7), (1e-3, 0.5, 2.0)])
+def test_s_guess_closed_form_grid_aligned(mu, sigma, c):
+    """eq. (11): s(u0, v) = <l, v> on the beta-curves.  With beta = (1, 0) and a
+    constant source c on the unit square the curves are the horizontal lines
+    y = (m + 1/2) h with nodes x_k = k h, and S = mu K + C + sigma M is the
+    constant-coefficient recurrence
+        (-mu/h - 1/2 + sigma h/6) v_{k-1} + (2 mu/h + 2 sigma h/3) v_k
+            + (-mu/h + 1/2 + sigma h/6) v_{k+1} = c h
+    with v_0 = v_N = 0, so v_k = c/sigma + A r1^k + B r2^k (r1, r2 the roots of
+    its characteristic polynomial).  Every curve carries the same v and the
+    vertical estimate of the scatter reads it at x_i, so u0(x_i, y_j) = v_i."""
+    n = 33
+    p = W.constant_beta(n, mu, sigma, (1.0, 0.0), f=c)
+    o = Oracle(p)
+    h = o.grid.h
+    N = n - 1
+    lo = -mu / h - 0.5 + sigma * h / 6
+    di = 2 * mu / h + 2 * sigma * h / 3
+    up = -mu / h + 0.5 + sigma * h / 6
+    r1, r2 = np.roots([up, di, lo])
+    # v_0 = 0 and v_N = 0 fix A, B
+    pc = c / sigma
+    A, B = np.linalg.solve(np.array([[1.0, 1.0], [r1 ** N, r2 ** N]]), [-pc, -pc])
+    k = np.arange(N + 1)
+    v = (pc + A * r1 ** k + B * r2 ** k).real
+    u0 = o.s_guess().reshape(n, n)
+    ref = np.tile(v, (n, 1))
+    m = o.mask
+    assert np.max(np.abs(u0[m] - ref[m])) < 1e-11 * max(1.0, np.max(np.abs(v)))

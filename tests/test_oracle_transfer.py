@@ -48,8 +48,8 @@ def _with_boundary(o, fam, v, fn):
                                    lambda: W.c4_instance(1, n_max=80)])
 def test_scatter_exact_on_bilinear(maker):
     """Every crossing value is exact for a field linear along the segment, and
-    along a grid line a bilinear field is linear: each estimate, and so any
-    weighted mean of them, reproduces the field at the node."""
+    along a grid line an affine field is linear: each estimate, and so their
+    average, reproduces the field at the node."""
     from oracle.method import Oracle
     o = Oracle(maker())
     X, Y = np.meshgrid(o.grid.x, o.grid.y, indexing="xy")
@@ -94,14 +94,15 @@ def test_round_trip_exact_on_affine_and_second_order():
     assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, errs
 
 
-def _brute_scatter(grid, dom, fam, mask):
+def _brute_scatter(grid, dom, fam, mask, local_edges=4):
     """The scatter rule written out node by node: all crossings of all segments
     with the node's horizontal and vertical grid lines, the closest one on each
     side (the boundary point of the grid line if it comes first), lerp along
-    the grid line, then the weighted mean of the two estimates."""
+    the grid line; then the plain average of the two estimates (Sec. 6), except
+    that an estimate with a bracket more than local_edges grid edges from the
+    node is dropped when the other estimate is local."""
     nx, ny = grid.nx, grid.ny
     P = np.zeros((nx * ny, fam.n_nodes))
-    eps2 = (0.1 * grid.h) ** 2
     segs = []
     for l in range(fam.n_lines):
         for k in range(fam.offsets[l], fam.offsets[l + 1] - 1):
@@ -112,6 +113,7 @@ def _brute_scatter(grid, dom, fam, mask):
                 continue
             est = []
             for axis in (0, 1):  # 0: horizontal grid line y = y_j, 1: vertical x = x_i
+                org, hh, nE, me = (grid.a, grid.hx, nx - 1, i) if axis == 0 else (grid.c, grid.hy, ny - 1, j)
                 cs = []
                 for k in segs:
                     x0, y0, x1, y1 = fam.x[k], fam.y[k], fam.x[k + 1], fam.y[k + 1]
@@ -123,6 +125,7 @@ def _brute_scatter(grid, dom, fam, mask):
                         continue
                     t = (gl - p0) / (p1 - p0)
                     cs.append((q0 + t * (q1 - q0), k, t))
+
                 # boundary points: walk node by node outward until a non-interior node
                 def walk(step):
                     ii, jj = i, j
@@ -133,23 +136,36 @@ def _brute_scatter(grid, dom, fam, mask):
                             x1, y1 = grid.x[ni], grid.y[nj]
                             t = float(dom.first_hit(np.array([x0]), np.array([y0]),
                                                     np.array([x1]), np.array([y1]))[0])
-                            return (x0 + t * (x1 - x0)) if axis == 0 else (y0 + t * (y1 - y0))
+                            crd = (x0 + t * (x1 - x0)) if axis == 0 else (y0 + t * (y1 - y0))
+                            return crd, (ni if axis == 0 else nj)
                         ii, jj = ni, nj
-                bl, br = walk(-1), walk(+1)
+                (bl, nl), (br, nr) = walk(-1), walk(+1)
                 left = [c for c in cs if bl <= c[0] < pos]
                 right = [c for c in cs if pos <= c[0] <= br]
-                L = max(left, key=lambda c: c[0]) if left else (bl, -1, 0.0)
-                R = min(right, key=lambda c: c[0]) if right else (br, -1, 0.0)
+
+                def edge(c):  # the grid edge [x_e, x_e+1] that holds coordinate c
+                    return min(max(int(np.floor((c - org) / hh)), 0), nE - 1)
+                if left:
+                    L = max(left, key=lambda c: c[0])
+                    dl = me - edge(L[0])
+                else:
+                    L, dl = (bl, -1, 0.0), me - nl
+                if right:
+                    R = min(right, key=lambda c: c[0])
+                    dr = edge(R[0]) - me + 1
+                else:
+                    R, dr = (br, -1, 0.0), nr - me
                 dL, dR = pos - L[0], R[0] - pos
                 span = dL + dR
                 cl, cr = (dR / span, dL / span) if span > 0 else (0.5, 0.5)
-                est.append((1.0 / (dL * dR + eps2), [(L, cl), (R, cr)]))
-            wsum = est[0][0] + est[1][0]
-            for w, parts in est:
+                est.append((dl <= local_edges and dr <= local_edges, [(L, cl), (R, cr)]))
+            loc = [e[0] for e in est]
+            share = [0.5, 0.5] if loc[0] == loc[1] else [float(loc[0]), float(loc[1])]
+            for w, (_, parts) in zip(share, est):
                 for (crd, k, t), c in parts:
                     if k >= 0:
-                        P[j * nx + i, k] += w / wsum * c * (1 - t)
-                        P[j * nx + i, k + 1] += w / wsum * c * t
+                        P[j * nx + i, k] += w * c * (1 - t)
+                        P[j * nx + i, k + 1] += w * c * t
     return P
 
 
@@ -184,3 +200,48 @@ def test_scatter_weights_partition_of_unity(c1_65):
         np.add.at(s, rows, coef)
         assert np.max(np.abs(s[o.inner_idx] - 1.0)) < 1e-14
         assert P.data.min() >= -1e-15
+
+
+def test_scatter_is_the_plain_average_where_local():
+    """Sec. 6: the node value is the average of the horizontal and the vertical
+    estimate.  On C1 (straight curves at an angle to the grid) every bracket is
+    local, so the scatter equals the literal rule at every node; with C2's
+    curved flow most nodes take the average and the rows of the others put all
+    their weight on one grid line."""
+    from oracle.method import Oracle
+    o = Oracle(W.c1(65))
+    for fam in (0, 1):
+        P, _ = tr.scatter_matrix(o.grid, o.dom, o.fams[fam], o.mask)
+        Pl, _ = tr.scatter_matrix(o.grid, o.dom, o.fams[fam], o.mask, literal=True)
+        assert (P != Pl).nnz == 0
+    o = Oracle(W.c2(65))
+    for fam in (0, 1):
+        P, _ = tr.scatter_matrix(o.grid, o.dom, o.fams[fam], o.mask)
+        Pl, _ = tr.scatter_matrix(o.grid, o.dom, o.fams[fam], o.mask, literal=True)
+        same = np.asarray((abs(P - Pl) > 0).sum(axis=1)).ravel()[o.inner_idx] == 0
+        assert same.mean() > 0.75
+
+
+def test_scatter_grid_aligned_curves_closed_form():
+    """beta = (1, 0): the beta-curves are the horizontal lines y = (m + 1/2) h
+    with nodes on the vertical grid lines, so no horizontal grid line is crossed
+    and the horizontal estimate would interpolate between the two ends of the
+    domain.  The vertical estimate alone is used: a line field phi(x) scatters
+    to phi(x_i) at every interior node (the literal average gives phi(x_i) / 2,
+    the zero boundary value taking the other half)."""
+    from oracle.method import Oracle
+    p = W.constant_beta(17, 0.1, 1.0, (1.0, 0.0), f=1.0)
+    o = Oracle(p)
+    F = o.fams[0]
+    h = o.grid.h
+    ys = np.sort([F.y[F.offsets[l]] for l in range(F.n_lines)])
+    assert np.allclose(ys, (np.arange(F.n_lines) + 0.5) * h, atol=1e-13)
+    assert np.allclose(F.x / h, np.round(F.x / h), atol=1e-9)
+    phi = lambda x: np.cos(3.0 * x) + x ** 3  # noqa: E731
+    v = phi(F.x)
+    X, _ = np.meshgrid(o.grid.x, o.grid.y, indexing="xy")
+    ref = phi(X).ravel()[o.inner_idx]
+    got = (o.P[0] @ v)[o.inner_idx]
+    assert np.max(np.abs(got - ref)) < 1e-12
+    Pl, _ = tr.scatter_matrix(o.grid, o.dom, F, o.mask, literal=True)
+    assert np.max(np.abs((Pl @ v)[o.inner_idx] - 0.5 * ref)) < 1e-12

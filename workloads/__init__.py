@@ -217,12 +217,3 @@ def c5_sample(seed, n=257):
     return Problem(f"c5_{seed}", n, n, (0.0, 1.0, 0.0, 1.0), DOM_BOX, (), mu, 1.0,
                    b1, b2, f, psi=psi)
 
-
-def tau_schedule(h, mu, sigma, n_tau=8):
-    """Pseudo-time steps of the defect-correction sweep, cycled: geometric from
-    h^2/(4 mu) up to 1/(sigma + 2 pi^2 mu).  A solver setting, fixed per problem."""
-    lo = h * h / (4.0 * mu)
-    hi = 1.0 / (sigma + 2.0 * math.pi ** 2 * mu)
-    if hi <= lo:
-        return np.full(n_tau, hi)
-    return np.geomspace(lo, hi, n_tau)
