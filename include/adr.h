@@ -34,7 +34,7 @@
  *
  * Errors.  Every call returns an adr_status; nothing throws or aborts.  After a
  * failure adr_last_error(ctx) gives a message (adr_last_error(NULL) gives the
- * message of the last failed adr_setup in this thread).
+ * message of the last failed adr_setup or context-free call in this thread).
  */
 #ifndef ADR_H
 #define ADR_H
@@ -240,12 +240,16 @@ adr_status adr_set_timing(adr_ctx *ctx, int32_t on);
 
 /* Kernel timing (options.timing != 0): for kernel class k (0 beta-line solve,
  * 1 gamma-line solve, 2 beta scatter, 3 gamma scatter/update, 4 norm), total
- * milliseconds and launch count of kernels of the given precision (0 FP64,
- * 1 FP32) since setup or the last reset of that precision.  ms_out and
- * count_out hold 5 entries.  reset != 0 clears that precision's counters after
- * reading.  Synchronises the stream. */
+ * milliseconds, launch count and work of kernels of the given precision (0
+ * FP64, 1 FP32) since setup or the last reset of that precision.  Work is the
+ * sum over the timed launches of what each one covered: line unknowns of the
+ * curves in its list (classes 0, 1) or interior grid nodes of its scatter
+ * blocks (classes 2, 3), over the lists compacted to the unfinished instances
+ * when a batched solve compacts them, else over all instances; 0 for the norm.
+ * ms_out, count_out and work_out hold 5 entries (each may be NULL).  reset !=
+ * 0 clears that precision's counters after reading.  Synchronises the stream. */
 adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out,
-                            int32_t reset);
+                            int64_t *work_out, int32_t reset);
 
 /* Measurement export (not part of the method): dst = src, `bytes` bytes of
  * device memory (a multiple of 16; both pointers 16-byte aligned), a plain
@@ -253,6 +257,31 @@ adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int
  * HBM bandwidth against which the kernels' rooflines are also quoted.
  * Errors: ADR_EINVAL (size or alignment), ADR_EDEVICE.  Asynchronous. */
 adr_status adr_copy_probe(const void *src, void *dst, int64_t bytes, void *stream);
+
+/* Batched tridiagonal solve on given rows: the line systems of eq. (16)-(19)
+ * (P1 elements on a curve, Dirichlet ends eliminated) with coefficients the
+ * caller supplies, solved by the partitioned scheme of the line solver (no
+ * pivoting), for systems of any length.  A test and building-block export;
+ * context free.
+ *   n_lines systems; system l has rows off[l] .. off[l+1]-1 (off: device
+ *   int64, n_lines + 1 entries, non-decreasing); n_rows = off[n_lines] -
+ *   off[0] (host; a smaller value leaves x unwritten).
+ *   Row r: lo[r] x[r-1] + di[r] x[r] + up[r] x[r+1] = rhs[r]; lo of a
+ *   system's first row and up of its last are ignored.  lo, di, up, rhs:
+ *   device FP64 (read only); x: device FP64 (written; may not alias them).
+ *   singular: device int32, n_lines (may be NULL): 1 where a pivot was not
+ *   finite or below pivot_tol times its row's scale (|di| + |l c'|); x is
+ *   then unreliable for that system.  pivot_tol <= 0: 64 * 2^-52.
+ *   Systems are cut into chunks of 32 rows; the chunks' reduced rows and the
+ *   separators' values (about 88 B per chunk + 8 B per system) live in device
+ *   scratch from the stream-ordered allocator (hipMallocAsync / hipFreeAsync
+ *   on `stream`).
+ * Asynchronous on stream (hipStream_t, NULL = default).  Errors: ADR_EINVAL
+ * (sizes, null arrays), ADR_ENOMEM, ADR_EDEVICE; messages through
+ * adr_last_error(NULL). */
+adr_status adr_line_solve(int64_t n_lines, int64_t n_rows, const int64_t *off, const double *lo, const double *di,
+                          const double *up, const double *rhs, double *x, int32_t *singular, double pivot_tol,
+                          void *stream);
 
 adr_status adr_destroy(adr_ctx *ctx);
 const char *adr_last_error(const adr_ctx *ctx);

@@ -21,7 +21,7 @@ PREC_FP64, PREC_FP32_LINES = 0, 1
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
            "adr_autotune", "adr_set_line_shapes", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_set_timing", "adr_kernel_times",
-           "adr_destroy", "adr_last_error", "adr_copy_probe")
+           "adr_destroy", "adr_last_error", "adr_copy_probe", "adr_line_solve")
 
 KERNEL_CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma", "norm")
 
@@ -79,9 +79,10 @@ def load():
     lib.adr_initial_guess.argtypes = [vp, vp]
     lib.adr_export_lines.argtypes = [vp, i32, i32, P(i64), P(i64), P(i64), P(dbl), P(dbl)]
     lib.adr_export_scatter.argtypes = [vp, i32, i32, P(i64), P(i32), P(i32), P(dbl), P(dbl)]
-    lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), i32]
+    lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), P(i64), i32]
     lib.adr_destroy.argtypes = [vp]
     lib.adr_copy_probe.argtypes = [vp, vp, i64, vp]
+    lib.adr_line_solve.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, dbl, vp]
     lib.adr_last_error.argtypes = [vp]
     lib.adr_last_error.restype = C.c_char_p
     for name in EXPORTS:
@@ -115,6 +116,32 @@ def copy_probe(src, dst, stream=None):
     code = lib.adr_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes, C.c_void_p(st))
     if code != ADR_OK:
         raise ADRError(code, "adr_copy_probe failed")
+
+
+def line_solve(off, lo, di, up, rhs, x=None, singular=None, pivot_tol=0.0, stream=None, entry="adr_line_solve"):
+    """Batched tridiagonal solve on given rows (include/adr.h adr_line_solve):
+    off int64 device tensor (n_lines + 1), lo/di/up/rhs float64 device tensors;
+    returns x (written into `x` when given), queued on torch's current stream."""
+    import torch
+    lib = load()
+    for t in (off, lo, di, up, rhs):
+        if not t.is_cuda or not t.is_contiguous():
+            raise ValueError("line_solve: contiguous device tensors")
+    if off.dtype != torch.int64 or any(t.dtype != torch.float64 for t in (lo, di, up, rhs)):
+        raise ValueError("line_solve: int64 offsets and float64 rows")
+    n_lines = off.numel() - 1
+    n_rows = rhs.numel()
+    if x is None:
+        x = torch.empty_like(rhs)
+    st = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    code = getattr(lib, entry)(n_lines, n_rows, C.c_void_p(off.data_ptr()), C.c_void_p(lo.data_ptr()),
+                               C.c_void_p(di.data_ptr()), C.c_void_p(up.data_ptr()), C.c_void_p(rhs.data_ptr()),
+                               C.c_void_p(x.data_ptr()),
+                               C.c_void_p(singular.data_ptr()) if singular is not None else None,
+                               float(pivot_tol), C.c_void_p(st))
+    if code != ADR_OK:
+        raise ADRError(code, lib.adr_last_error(None).decode())
+    return x
 
 
 class Solver:
@@ -262,11 +289,17 @@ class Solver:
                                                 k.ctypes.data_as(i32p), _dptr(ca), _dptr(cb)))
         return node, k.reshape(n, 4), ca.reshape(n, 4), cb.reshape(n, 4)
 
-    def kernel_times(self, precision="fp64", reset=True):
+    def kernel_times(self, precision="fp64", reset=True, work=False):
+        """Per kernel class: (ms, launches), or (ms, launches, work) with work=True."""
         ms = np.zeros(5)
         cnt = np.zeros(5, np.int64)
+        wk = np.zeros(5, np.int64)
+        i64p = C.POINTER(C.c_int64)
         self._check(self.lib.adr_kernel_times(self.ctx, {"fp64": 0, "fp32": 1}[precision], _dptr(ms),
-                                              cnt.ctypes.data_as(C.POINTER(C.c_int64)), int(bool(reset))))
+                                              cnt.ctypes.data_as(i64p), wk.ctypes.data_as(i64p),
+                                              int(bool(reset))))
+        if work:
+            return {k: (float(ms[i]), int(cnt[i]), int(wk[i])) for i, k in enumerate(KERNEL_CLASSES)}
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_CLASSES)}
 
     def close(self):

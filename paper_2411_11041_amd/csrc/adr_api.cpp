@@ -73,8 +73,10 @@ struct DevFam {
     float *v32 = nullptr;
     // launch-list compaction (batched stationary solves): lines of unfinished instances
     std::vector<int> inst_lines, inst_nmax;  // per instance: curves, longest curve
+    std::vector<int64_t> inst_unk;           // per instance: line unknowns
     int *lidx = nullptr;                      // compacted line list (device)
     int act = -1, act_nmax = 0;               // its length and longest curve; -1: full list
+    int64_t act_unk = 0;                      // line unknowns of the compacted list
     // length buckets: the list is ordered longest first, so bucket b is the
     // range bstart[b] .. bstart[b+1]-1 of the full list (abstart: of the
     // compacted list); bnmax: its longest curve
@@ -102,6 +104,8 @@ struct adr_ctx {
     double *Ub = nullptr;  // the state in the blocked layout during a call
     int n_blocks = 0;
     std::vector<int> inst_blocks;                      // per instance: 256-slot scatter blocks
+    std::vector<int64_t> inst_grid;                    // per instance: interior grid nodes
+    int64_t act_grid = 0;                              // interior grid nodes of the compacted blocks
     int *blist = nullptr, *cscan = nullptr, *ccount = nullptr;  // compacted block list, scan scratch, count
     int act_blocks = -1;                               // length of blist; -1: full list
     double *par = nullptr;  // [slot][fam][inst][8]
@@ -123,17 +127,18 @@ struct adr_ctx {
     // timing
     struct Tick {
         int prec, cls;
+        int64_t units;  // line unknowns (line solves) or interior grid nodes (scatters) of the launch
         hipEvent_t a, b;
     };
     std::vector<Tick> ticks;
     std::vector<hipEvent_t> ev_pool;
     double ms[2][5] = {};
-    int64_t cnt[2][5] = {};
+    int64_t cnt[2][5] = {}, units[2][5] = {};
 
     const double *par_ptr(int slot, int f) const { return par + (static_cast<size_t>(slot) * 2 + f) * n_inst * 8; }
 
     template <typename F>
-    void timed(int prec, int cls, F &&fn) {
+    void timed(int prec, int cls, int64_t work, F &&fn) {
         if (!opt.timing) {
             HIPCHK(fn());
             return;
@@ -144,7 +149,7 @@ struct adr_ctx {
             HIPCHK(hipEventCreate(&e));
             ev_pool.push_back(e);
         }
-        Tick t{prec, cls, ev_pool[2 * ticks.size()], ev_pool[2 * ticks.size() + 1]};
+        Tick t{prec, cls, work, ev_pool[2 * ticks.size()], ev_pool[2 * ticks.size() + 1]};
         HIPCHK(hipEventRecord(t.a, st));
         HIPCHK(fn());
         HIPCHK(hipEventRecord(t.b, st));
@@ -161,6 +166,7 @@ struct adr_ctx {
             HIPCHK(hipEventElapsedTime(&e, t.a, t.b));
             ms[t.prec][t.cls] += e;
             cnt[t.prec][t.cls] += 1;
+            units[t.prec][t.cls] += t.units;
         }
         ticks.clear();
     }
@@ -252,27 +258,30 @@ struct adr_ctx {
         (void)hipEventDestroy(e1);
         return ms;
     }
+    // work of a launch over the current (possibly compacted) lists
+    int64_t line_work(int f) const { return fam[f].act >= 0 ? fam[f].act_unk : fam[f].n_unknowns; }
+    int64_t grid_work() const { return act_blocks >= 0 ? act_grid : n_unknowns; }
     void line64(int f, int slot, const double *fin, const int *dn) {
-        timed(0, f, [&] { return lines<double>(f, fam[f].a64, fin, fam[f].v64, par_ptr(slot, f), dn); });
+        timed(0, f, line_work(f), [&] { return lines<double>(f, fam[f].a64, fin, fam[f].v64, par_ptr(slot, f), dn); });
     }
     void line32(int f, int slot, const float *fin, const int *dn) {
-        timed(1, f, [&] { return lines<float>(f, fam[f].a32, fin, fam[f].v32, par_ptr(slot, f), dn); });
+        timed(1, f, line_work(f), [&] { return lines<float>(f, fam[f].a32, fin, fam[f].v32, par_ptr(slot, f), dn); });
     }
 
     // One FP64 sweep of eq. (10) from U.  mode of the final scatter: 0 write U,
     // 1 write U + d32 + partial, 3 partial only (U unchanged).
     void sweep64(int slot, const double *U_in, double *U_out, int mode, const int *dn) {
         line64(0, slot, U_in, dn);
-        timed(0, 2, [&] { return adr::launch_scatter<double, double>(0, sargs(fam[0].s64), fam[0].v64, Uh64, d32, partial, dn, st); });
+        timed(0, 2, grid_work(), [&] { return adr::launch_scatter<double, double>(0, sargs(fam[0].s64), fam[0].v64, Uh64, d32, partial, dn, st); });
         line64(1, slot, Uh64, dn);
-        timed(0, 3, [&] { return adr::launch_scatter<double, double>(mode, sargs(fam[1].s64), fam[1].v64, U_out, d32, partial, dn, st); });
+        timed(0, 3, grid_work(), [&] { return adr::launch_scatter<double, double>(mode, sargs(fam[1].s64), fam[1].v64, U_out, d32, partial, dn, st); });
     }
     // One FP32 increment sweep: d32 <- T d32, U += d32.
     void sweep32(double *U, const int *dn) {
         line32(0, kSlotLin, d32, dn);
-        timed(1, 2, [&] { return adr::launch_scatter<float, float>(0, sargs(fam[0].s32), fam[0].v32, D32, nullptr, partial, dn, st); });
+        timed(1, 2, grid_work(), [&] { return adr::launch_scatter<float, float>(0, sargs(fam[0].s32), fam[0].v32, D32, nullptr, partial, dn, st); });
         line32(1, kSlotLin, D32, dn);
-        timed(1, 3, [&] { return adr::launch_scatter<float, double>(2, sargs(fam[1].s32), fam[1].v32, U, d32, partial, dn, st); });
+        timed(1, 3, grid_work(), [&] { return adr::launch_scatter<float, double>(2, sargs(fam[1].s32), fam[1].v32, U, d32, partial, dn, st); });
     }
 
     // Restricts the line and scatter launches to the instances not done (dn,
@@ -282,19 +291,26 @@ struct adr_ctx {
     // skipped as before.  A launch's workgroups then all carry work.
     void compact(const std::vector<int> &dn) {
         int nb = 0;
+        int64_t ng = 0;
         for (int i = 0; i < n_inst; ++i)
-            if (!dn[i]) nb += inst_blocks[i];
+            if (!dn[i]) {
+                nb += inst_blocks[i];
+                ng += inst_grid[i];
+            }
         if (nb == (act_blocks >= 0 ? act_blocks : n_blocks)) return;  // unchanged set
         HIPCHK(adr::launch_compact(blk_inst_d, n_blocks, done, cscan, blist, ccount, st));
         act_blocks = nb;
+        act_grid = ng;
         for (int f = 0; f < 2; ++f) {
             DevFam &F = fam[f];
             int nl = 0, nm = 0;
+            int64_t nu = 0;
             int bl[adr::kLineBuckets] = {};
             for (int b = 0; b < adr::kLineBuckets; ++b) F.abnmax[b] = 0;
             for (int i = 0; i < n_inst; ++i)
                 if (!dn[i]) {
                     nl += F.inst_lines[i];
+                    nu += F.inst_unk[i];
                     nm = std::max(nm, F.inst_nmax[i]);
                     for (int b = 0; b < adr::kLineBuckets; ++b) {
                         bl[b] += F.inst_bl[i][b];
@@ -304,6 +320,7 @@ struct adr_ctx {
             HIPCHK(adr::launch_compact(F.a64.linst, F.n_lines, done, cscan, F.lidx, ccount, st));
             F.act = nl;
             F.act_nmax = nm;
+            F.act_unk = nu;
             // the compaction keeps the list order, so the buckets stay contiguous ranges
             F.abstart[0] = 0;
             for (int b = 0; b < adr::kLineBuckets; ++b) F.abstart[b + 1] = F.abstart[b] + bl[b];
@@ -314,7 +331,7 @@ struct adr_ctx {
         fam[0].act = fam[1].act = -1;
     }
     void norm(int count, double tol, int mode) {
-        timed(0, 4, [&] {
+        timed(0, 4, 0, [&] {
             return adr::launch_norm(n_inst, partial, blk_start, cnorm, rel, done, conv_it, count, tol, mode, st);
         });
     }
@@ -570,6 +587,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             }
             C->n_unknowns += static_cast<int64_t>(G[i].inner_list.size());
         }
+        C->inst_grid.resize(n);
+        for (int i = 0; i < n; ++i) C->inst_grid[i] = static_cast<int64_t>(G[i].inner_list.size());
         C->slot_rm = upload(gidx, own, st);
         int *d_gidx = upload(gidx_b, own, st);
         C->slot_b = d_gidx;
@@ -619,6 +638,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             loff.reserve(lines.size());
             F.inst_lines.assign(n, 0);
             F.inst_nmax.assign(n, 0);
+            F.inst_unk.assign(n, 0);
             F.inst_bl.assign(n, {});
             F.inst_bnmax.assign(n, {});
             int bcount[adr::kLineBuckets] = {};
@@ -632,6 +652,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 linst.push_back(li.first);
                 F.nmax = std::max(F.nmax, cnt);
                 F.inst_lines[li.first] += 1;
+                F.inst_unk[li.first] += cnt - 2;
                 F.inst_nmax[li.first] = std::max(F.inst_nmax[li.first], cnt);
                 F.n_unknowns += cnt - 2;
                 const int b = adr::line_bucket(cnt);
@@ -1109,7 +1130,7 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     ctx->opt.fp32_sweeps = best;
     ctx->opt.adaptive = best_ad;
     if (ctx->opt.timing)
-        for (int prec = 0; prec < 2; ++prec) (void)adr_kernel_times(ctx, prec, nullptr, nullptr, 1);
+        for (int prec = 0; prec < 2; ++prec) (void)adr_kernel_times(ctx, prec, nullptr, nullptr, nullptr, 1);
     if (best_fp32_sweeps) *best_fp32_sweeps = best;
     if (best_adaptive) *best_adaptive = best_ad;
     if (best_ms) *best_ms = best_t;
@@ -1190,7 +1211,7 @@ adr_status adr_initial_guess(adr_ctx *ctx, double *u) {
     }
     try {
         ctx->line64(0, kSlotGuess, ctx->Z64, ctx->never);
-        ctx->timed(0, 2, [&] {
+        ctx->timed(0, 2, ctx->n_unknowns, [&] {
             return adr::launch_scatter<double, double>(0, ctx->fam[0].s64, ctx->fam[0].v64, ctx->Ub, ctx->d32,
                                                        ctx->partial, ctx->never, ctx->st);
         });
@@ -1242,18 +1263,21 @@ adr_status adr_set_timing(adr_ctx *ctx, int32_t on) {
     }
 }
 
-adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out, int32_t reset) {
+adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out,
+                            int64_t *work_out, int32_t reset) {
     if (!ctx || precision < 0 || precision > 1) return ADR_EINVAL;
     try {
         ctx->collect_ticks();
         for (int k = 0; k < 5; ++k) {
             if (ms_out) ms_out[k] = ctx->ms[precision][k];
             if (count_out) count_out[k] = ctx->cnt[precision][k];
+            if (work_out) work_out[k] = ctx->units[precision][k];
         }
         if (reset)
             for (int k = 0; k < 5; ++k) {
                 ctx->ms[precision][k] = 0.0;
                 ctx->cnt[precision][k] = 0;
+                ctx->units[precision][k] = 0;
             }
         return ADR_OK;
     } catch (const Error &e) {
@@ -1288,3 +1312,7 @@ const char *adr_last_error(const adr_ctx *ctx) {
 }
 
 }  // extern "C"
+
+namespace adr {
+void set_thread_error(const std::string &msg) { g_setup_error = msg; }
+}  // namespace adr

@@ -55,6 +55,10 @@ struct InstanceGeo {
     std::vector<Rec4> rec[2];          // per interior node (inner_list order)
 };
 
+// Message returned by adr_last_error(NULL) in this thread (failed set-up or
+// context-free call).
+void set_thread_error(const std::string &msg);
+
 // Builds the geometry of one instance; throws Error.
 void build_instance(const adr_problem &p, InstanceGeo &out);
 // Load vector of the beta-curves for the source of p (curves already traced).

@@ -157,3 +157,15 @@ def test_device_only_calls_reject_host_contexts():
     assert lib.adr_split_iterate_judged(s.ctx, fake, fake, 10, 1e-8, it, rel, used) == ADR_EINVAL
     assert lib.adr_split_iterate_judged(None, fake, fake, 10, 1e-8, it, rel, used) == ADR_EINVAL
     s.close()
+
+
+def test_line_solve_argument_errors():
+    """adr_line_solve checks its sizes and arrays before it touches a device."""
+    import ctypes as C
+    from paper_2411_11041_amd.adr import ADR_EINVAL, ADR_OK, load
+    lib = load()
+    fake = C.c_void_p(1)  # never dereferenced: the checks come first
+    assert lib.adr_line_solve(-1, 0, fake, fake, fake, fake, fake, fake, None, 0.0, None) == ADR_EINVAL
+    assert b"out of range" in lib.adr_last_error(None)
+    assert lib.adr_line_solve(3, 10, None, fake, fake, fake, fake, fake, None, 0.0, None) == ADR_EINVAL
+    assert lib.adr_line_solve(0, 0, None, None, None, None, None, None, None, 0.0, None) == ADR_OK

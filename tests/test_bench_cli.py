@@ -16,9 +16,37 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_roofline_byte_model():
+    """Per line unknown: gathered value, chord, |beta| (beta family), load (beta
+    family, FP64 sweeps only: the FP32 increment sweeps have no source), written
+    value; tables: cell index and two cell offsets.  Per grid node: each line
+    value read once, plus the grid traffic of the scatter mode; tables: slot
+    index, record base, three offsets and the record weights."""
     sys.path.insert(0, ROOT)
     import bench
-    # per line unknown: cell 4 + lx, ly + chord [+ |beta| + load] + gathered + written value
-    assert [bench.LINE_BYTES[k] for k in (("fp32", 0), ("fp32", 1), ("fp64", 0), ("fp64", 1))] == [32, 24, 60, 44]
-    # per grid node: FP32 write / accumulate, FP64 write / update
-    assert [bench.SCATTER_BYTES[k] for k in (("fp32", 2), ("fp32", 3), ("fp64", 2), ("fp64", 3))] == [50, 66, 118, 130]
+    assert [bench.line_bytes(*k)[0] for k in (("fp32", 0), ("fp32", 1), ("fp64", 0), ("fp64", 1))] == \
+        [16, 12, 40, 24]
+    assert [bench.line_bytes(*k)[1] for k in (("fp32", 0), ("fp64", 1))] == [12, 20]
+    counts = dict(grid_unknowns=1000, line_unknowns_b=1000, lines_b=10, line_unknowns_g=800, lines_g=20)
+    alg = [bench.scatter_bytes(p, f, counts)[0] for p, f in (("fp32", 0), ("fp32", 1), ("fp64", 0), ("fp64", 1))]
+    assert alg == [4 * 1.02 + 4, 4 * 0.84 + 20, 8 * 1.02 + 8, 8 * 0.84 + 20]
+    assert bench.scatter_bytes("fp64", 1, counts, march=True)[0] == 8 * 0.84 + 8
+    assert [bench.scatter_bytes(p, 0, counts)[1] for p in ("fp32", "fp64")] == [30, 78]
+
+
+def test_roofline_from_kernel_work():
+    """The roofline divides the algorithmic bytes of the work the library
+    counted per launch by the summed event time; the dominant class is the one
+    with the largest total time."""
+    sys.path.insert(0, ROOT)
+    import bench
+    counts = dict(grid_unknowns=1000, line_unknowns_b=1000, lines_b=10, line_unknowns_g=800, lines_g=20)
+    z = (0.0, 0, 0)
+    times = {"fp64": {"line_beta": (1.0, 2, 2000), "line_gamma": z, "scatter_beta": z, "scatter_gamma": z,
+                      "norm": z},
+             "fp32": {"line_beta": (2.0, 4, 4000), "line_gamma": z, "scatter_beta": (0.5, 4, 4000),
+                      "scatter_gamma": z, "norm": z}}
+    rf = bench.roofline(times, counts)
+    assert rf["kernel"] == "k_line<float, 0>"
+    assert abs(rf["achieved"] - 16 * 4000 / 2e-3 / 1e9) < 0.1
+    assert rf["bytes_per_launch"] == 16 * 1000
+    assert [c["cls"] for c in rf["classes"]] == ["line_beta", "line_beta", "scatter_beta"]
