@@ -283,6 +283,22 @@ adr_status adr_line_solve(int64_t n_lines, int64_t n_rows, const int64_t *off, c
                           const double *up, const double *rhs, double *x, int32_t *singular, double pivot_tol,
                           void *stream);
 
+/* adr_line_solve for callers that cannot allocate (work captured into a HIP
+ * graph, serving loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, with the scratch in a fixed device array of the library instead of
+ * the stream-ordered allocator.  The array holds 16 MiB per device (the first
+ * call on a device looks its address up; the array stays until the process
+ * ends), enough for about 6 million rows; a request above it (about 88 B per
+ * 32 rows plus 8 B per system) is refused with ADR_EINVAL before anything is
+ * queued.  Calls no allocating routine.  Every call on one device shares that
+ * device's array: calls whose work overlaps on one device (other streams,
+ * other threads) race and must be ordered by the caller.  Nothing in the
+ * array needs to start at zero.  Arguments, results and other errors as
+ * adr_line_solve. */
+adr_status adr_line_solve_noalloc(int64_t n_lines, int64_t n_rows, const int64_t *off, const double *lo,
+                                  const double *di, const double *up, const double *rhs, double *x,
+                                  int32_t *singular, double pivot_tol, void *stream);
+
 adr_status adr_destroy(adr_ctx *ctx);
 const char *adr_last_error(const adr_ctx *ctx);
 

@@ -21,7 +21,7 @@ PREC_FP64, PREC_FP32_LINES = 0, 1
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
            "adr_autotune", "adr_set_line_shapes", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_set_timing", "adr_kernel_times",
-           "adr_destroy", "adr_last_error", "adr_copy_probe", "adr_line_solve")
+           "adr_destroy", "adr_last_error", "adr_copy_probe", "adr_line_solve", "adr_line_solve_noalloc")
 
 KERNEL_CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma", "norm")
 
@@ -83,6 +83,7 @@ def load():
     lib.adr_destroy.argtypes = [vp]
     lib.adr_copy_probe.argtypes = [vp, vp, i64, vp]
     lib.adr_line_solve.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, dbl, vp]
+    lib.adr_line_solve_noalloc.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, dbl, vp]
     lib.adr_last_error.argtypes = [vp]
     lib.adr_last_error.restype = C.c_char_p
     for name in EXPORTS:
