@@ -5,7 +5,7 @@
  * for advection-diffusion-reaction model" (arXiv 2411.11041).
  *
  * Problem data follow the paper's problem statement (Sec. 2, eq. (1)-(2)):
- *   -mu Lap u + beta . grad u + sigma u = f in Omega,  u = 0 on Gamma,
+ *   -mu Lap u + beta . grad u + sigma u = f in Omega,  u = g on Gamma,
  *   (parabolic form: u_t + ... = f, u(0) = u0),
  * mu > 0, sigma > 0 constants, beta divergence free without closed integral
  * curves in the closure of Omega.  beta and f are given as nodal values on a
@@ -13,9 +13,13 @@
  * (eq. (20)).  All nodal arrays are row-major, index j*nx + i for the node
  * (a + i*hx, c + j*hy), hx = (b-a)/(nx-1), hy = (d-c)/(ny-1).
  *
- * The solver state u is a grid field with the same layout.  Entries at nodes
- * that are not strictly inside Omega hold the Dirichlet value, which is zero
- * (the paper's boundary condition); the caller keeps them at zero.
+ * The paper's boundary condition is u = 0; g (nodal Dirichlet data, read at a
+ * point of Gamma through the bilinear interpolant of eq. (22)) generalises it.
+ * The solver state u is a grid field with the same layout.  Its entries at
+ * nodes that are not strictly inside Omega are neither read nor written: the
+ * library holds g there (the curve ends take g at their boundary points, and
+ * the bilinear gather near Gamma and the boundary points of the Sec. 6
+ * interpolation read it).
  *
  * One sweep ("step") is eq. (10): the beta substep solves, on every beta-curve
  * (eq. (13)), the P1 line problem of eq. (16)-(17); the curve values are handed
@@ -55,6 +59,8 @@ enum {
     ADR_EDEVICE = -3,     /* HIP runtime error */
     ADR_EBETA = -4,       /* |beta| vanishes or a curve does not leave Omega (closed streamline) */
     ADR_ENONFINITE = -5,  /* non-finite input or residual */
+    ADR_ESINGULAR = -6,   /* a line solve met a pivot that is not finite or below options.pivot_tol
+                             times its row's scale (no pivoting); u holds the last iterate */
     ADR_ENOTCONV = 1      /* warning: max_iters reached; u holds the last iterate */
 };
 
@@ -68,9 +74,14 @@ typedef struct {
     int32_t n_dom_params;      /* number of doubles in dom_params */
     const double *dom_params;  /* DISC: cx, cy, r.  POLYGON: x0,y0,x1,y1,... counter-clockwise */
     double mu, sigma;          /* > 0 (sigma >= 0 accepted) */
-    const double *beta1;       /* nx*ny nodal beta components (host) */
+    const double *beta1;       /* nx*ny nodal beta components (host); NULL (both) to take psi */
     const double *beta2;
     const double *f;           /* nx*ny nodal source (host) */
+    const double *g;           /* nx*ny nodal Dirichlet data (host), used on and outside Gamma;
+                                  NULL: zero (the paper's case) */
+    const double *psi;         /* nx*ny nodal stream function (host), read only when beta1 and beta2
+                                  are NULL: beta = (psi_y, -psi_x) by second-order differences
+                                  (central inside, one-sided on the grid's edges) */
 } adr_problem;
 
 typedef struct {
@@ -102,6 +113,8 @@ typedef struct {
                              launches on three streams at once (the longest bucket on the
                              context's stream, the next and the rest on two streams of its
                              own, joined back by events; in turn inside a graph capture) */
+    double pivot_tol;     /* relative pivot threshold of the line solves (ADR_ESINGULAR); <= 0:
+                             64 ulp of the sweep's precision (64 * 2^-52 FP64, 64 * 2^-23 FP32) */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -196,10 +209,25 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
  * gives 0 everywhere.  Errors: ADR_EINVAL (a shape out of range). */
 adr_status adr_set_line_shapes(adr_ctx *ctx, const int32_t *shapes);
 
-/* Parabolic march (eq. (2) discretised by eq. (10)): nsteps sweeps with the
- * given theta in (0,1] and time step dt > 0, FP64, source f included.  u:
- * device FP64 packed, in: u_n, out: u_{n+nsteps}.  Asynchronous. */
-adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32_t nsteps);
+/* Parabolic march (eq. (2) discretised in time by eq. (7), split by eq. (10)).
+ * u: device FP64 packed, in: u_n, out: u_{n+nsteps}; dt > 0; source f and
+ * Dirichlet data g included.
+ *   inner_max = 0 (the paper's scheme): one splitting step of eq. (10) per time
+ *     step with the given theta in (0,1], FP64.  Asynchronous.
+ *   inner_max > 0 (splitting iterated per step): implicit Euler, theta = 1;
+ *     each step (u - u_n)/dt + A u = f is solved as the stationary problem
+ *     with reaction sigma + 1/dt and the beta-curves' load L + M (G u_n)/dt
+ *     (G the bilinear gather of eq. (22), M the P1 mass rows), by the
+ *     stationary iteration of adr_split_iterate from u_n (the context's pseudo
+ *     step, precision, schedule and launches) to rel <= inner_tol, at most
+ *     inner_max sweeps.  inner_iters (host, nsteps * n_probs, may be NULL):
+ *     sweeps of step s for instance i at [s * n_probs + i].  Returns
+ *     ADR_ENOTCONV if some step hit inner_max (the march goes on), and stops
+ *     at the first error (ADR_ESINGULAR, ADR_ENONFINITE).  Synchronises.
+ *     The context's stationary coefficients are unchanged afterwards.
+ * Errors: ADR_EINVAL (arguments; theta != 1 with inner_max > 0). */
+adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32_t nsteps, int32_t inner_max,
+                         double inner_tol, int32_t *inner_iters);
 
 /* rel_res[i] = |Phi(U) - U|_2 / |Phi(0)|_2 of the stationary sweep for the given
  * u (device FP64, unchanged), in FP64.  rel_res: host, n_probs.  Returns
@@ -224,12 +252,14 @@ adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, in
  * instance's grid); its value is sum over the 4 slots s (horizontal low,
  * horizontal high, vertical low, vertical high) of ca[4r+s] v[k] + cb[4r+s]
  * v[k+1], k = k[4r+s] a node index of the family local to the instance
- * (offsets of adr_export_lines); k = -1 marks a boundary point of Gamma (Dirichlet
- * value, weights 0).  Call with NULL arrays to get *n_rows, then with node
- * (n_rows) and k, ca, cb (4 n_rows) host buffers.  Errors: ADR_EINVAL (a
- * device context, an index out of range). */
+ * (offsets of adr_export_lines); k = -1 marks a boundary point of Gamma
+ * (weights 0); gb[r] is the Dirichlet data the row's boundary points carry
+ * (their interpolation weights times g there), added to the row's value in
+ * the sweeps of the state.  Call with NULL arrays to get *n_rows, then with
+ * node, gb (n_rows) and k, ca, cb (4 n_rows) host buffers (each may be NULL).
+ * Errors: ADR_EINVAL (a device context, an index out of range). */
 adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
-                              int32_t *node, int32_t *k, double *ca, double *cb);
+                              int32_t *node, int32_t *k, double *ca, double *cb, double *gb);
 
 /* Per-launch HIP-event timing on (1) or off (0) from now on (the set-up
  * option's initial value).  Each timed launch records two events on the

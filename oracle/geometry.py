@@ -282,6 +282,24 @@ def interior_mask(grid, dom):
 # Unit fields (Sec. 3)
 # ---------------------------------------------------------------------------
 
+def beta_from_psi(grid, psi):
+    """beta = (psi_y, -psi_x) at the nodes from a nodal stream function (Sec. 2:
+    beta divergence free): second-order differences, central inside and
+    one-sided, (-3 f0 + 4 f1 - f2) / (2 h), on the grid's edges."""
+    P = np.asarray(psi, float)
+
+    def d(axis, h):
+        out = np.empty_like(P)
+        A = np.moveaxis(P, axis, 0)
+        O = np.moveaxis(out, axis, 0)
+        O[1:-1] = (A[2:] - A[:-2]) / (2.0 * h)
+        O[0] = (-3.0 * A[0] + 4.0 * A[1] - A[2]) / (2.0 * h)
+        O[-1] = (3.0 * A[-1] - 4.0 * A[-2] + A[-3]) / (2.0 * h)
+        return out
+
+    return d(0, grid.hy), -d(1, grid.hx)
+
+
 class Flow:
     """beta from nodal values; b = beta/|beta|; p = gamma/|gamma| = (b2, -b1)."""
 

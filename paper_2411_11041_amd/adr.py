@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libadr.so")
 
 ADR_OK, ADR_EINVAL, ADR_ENOMEM, ADR_EDEVICE, ADR_EBETA, ADR_ENONFINITE, ADR_ENOTCONV = 0, -1, -2, -3, -4, -5, 1
+ADR_ESINGULAR = -6
 DOM_BOX, DOM_DISC, DOM_POLYGON = 0, 1, 2
 PREC_FP64, PREC_FP32_LINES = 0, 1
 
@@ -39,14 +40,15 @@ class Problem(C.Structure):
                 ("dom_params", C.POINTER(C.c_double)),
                 ("mu", C.c_double), ("sigma", C.c_double),
                 ("beta1", C.POINTER(C.c_double)), ("beta2", C.POINTER(C.c_double)),
-                ("f", C.POINTER(C.c_double))]
+                ("f", C.POINTER(C.c_double)), ("g", C.POINTER(C.c_double)), ("psi", C.POINTER(C.c_double))]
 
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("fp32_sweeps", C.c_int32),
                 ("theta", C.c_double), ("dt", C.c_double),
                 ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32),
-                ("graph", C.c_int32), ("adaptive", C.c_int32), ("split_lines", C.c_int32)]
+                ("graph", C.c_int32), ("adaptive", C.c_int32), ("split_lines", C.c_int32),
+                ("pivot_tol", C.c_double)]
 
 
 _lib = None
@@ -74,11 +76,11 @@ def load():
     lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32), P(i32)]
     lib.adr_set_line_shapes.argtypes = [vp, P(i32)]
     lib.adr_set_timing.argtypes = [vp, i32]
-    lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32]
+    lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32, i32, dbl, P(i32)]
     lib.adr_residual.argtypes = [vp, vp, P(dbl)]
     lib.adr_initial_guess.argtypes = [vp, vp]
     lib.adr_export_lines.argtypes = [vp, i32, i32, P(i64), P(i64), P(i64), P(dbl), P(dbl)]
-    lib.adr_export_scatter.argtypes = [vp, i32, i32, P(i64), P(i32), P(i32), P(dbl), P(dbl)]
+    lib.adr_export_scatter.argtypes = [vp, i32, i32, P(i64), P(i32), P(i32), P(dbl), P(dbl), P(dbl)]
     lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), P(i64), i32]
     lib.adr_destroy.argtypes = [vp]
     lib.adr_copy_probe.argtypes = [vp, vp, i64, vp]
@@ -149,7 +151,8 @@ class Solver:
     """One context over a batch of problems (workloads.Problem-like objects)."""
 
     def __init__(self, problems, precision="fp64", theta=1.0, dt=0.05, fp32_sweeps=3,
-                 stream=None, timing=False, host_only=False, graph=False, adaptive=False, split_lines=False):
+                 stream=None, timing=False, host_only=False, graph=False, adaptive=False, split_lines=False,
+                 pivot_tol=0.0):
         self.lib = load()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -161,7 +164,7 @@ class Solver:
         prec = {"fp64": PREC_FP64, "fp32": PREC_FP32_LINES}[precision]
         opt = Options(prec, int(fp32_sweeps), float(theta), float(dt),
                       C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)),
-                      int(bool(graph)), int(bool(adaptive)), int(split_lines))
+                      int(bool(graph)), int(bool(adaptive)), int(split_lines), float(pivot_tol))
         self.n = len(problems)
         self.ctx = C.c_void_p()
         st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))
@@ -172,16 +175,24 @@ class Solver:
 
     def _structs(self, problems):
         arr = (Problem * len(problems))()
+        def arr_or_none(v):
+            if v is None:
+                return None
+            a = np.ascontiguousarray(v, np.float64).ravel()
+            self._keep.append(a)
+            return _dptr(a)
+
         for k, p in enumerate(problems):
-            b1 = np.ascontiguousarray(p.beta1, np.float64).ravel()
-            b2 = np.ascontiguousarray(p.beta2, np.float64).ravel()
             f = np.ascontiguousarray(p.f, np.float64).ravel()
             dp = np.ascontiguousarray(np.asarray(p.dom_params, np.float64).ravel())
-            self._keep += [b1, b2, f, dp]
+            self._keep += [f, dp]
             a, b, c, d = p.box
+            # beta as given, else (both None) from the stream function psi
+            b1, b2 = arr_or_none(p.beta1), arr_or_none(p.beta2)
+            psi = arr_or_none(getattr(p, "psi", None)) if (b1 is None and b2 is None) else None
             arr[k] = Problem(p.nx, p.ny, a, b, c, d, int(p.domain), int(dp.size),
                              _dptr(dp) if dp.size else None, float(p.mu), float(p.sigma),
-                             _dptr(b1), _dptr(b2), _dptr(f))
+                             b1, b2, _dptr(f), arr_or_none(getattr(p, "g", None)), psi)
         return arr
 
     def update(self, problems):
@@ -251,8 +262,19 @@ class Solver:
         self._check(st, ok=(ADR_OK, ADR_ENOTCONV))
         return iters, rel, st, used
 
-    def time_step(self, u, theta, dt, nsteps):
-        self._check(self.lib.adr_time_step(self.ctx, _device_ptr(u), float(theta), float(dt), int(nsteps)))
+    def time_step(self, u, theta, dt, nsteps, inner_max=0, inner_tol=0.0):
+        """nsteps time steps of eq. (7)/(10) on u; with inner_max > 0 each implicit
+        Euler step is iterated to inner_tol, and the per-step sweep counts
+        (nsteps x n) and the status are returned."""
+        if inner_max <= 0:
+            self._check(self.lib.adr_time_step(self.ctx, _device_ptr(u), float(theta), float(dt), int(nsteps),
+                                               0, 0.0, None))
+            return None
+        it = np.zeros(max(int(nsteps), 0) * self.n, np.int32)
+        st = self.lib.adr_time_step(self.ctx, _device_ptr(u), float(theta), float(dt), int(nsteps),
+                                    int(inner_max), float(inner_tol), it.ctypes.data_as(C.POINTER(C.c_int32)))
+        self._check(st, ok=(ADR_OK, ADR_ENOTCONV))
+        return it.reshape(max(int(nsteps), 0), self.n), st
 
     def residual(self, u, allow_nonfinite=False):
         """Per-instance relative residual; with allow_nonfinite a non-finite
@@ -276,19 +298,21 @@ class Solver:
                                               off.ctypes.data_as(C.POINTER(C.c_int64)), _dptr(x), _dptr(y)))
         return off, x, y
 
-    def export_scatter(self, inst, family):
-        """Scatter stencil rows (host-only contexts): node, k, ca, cb."""
+    def export_scatter(self, inst, family, with_gb=False):
+        """Scatter stencil rows (host-only contexts): node, k, ca, cb [, gb]."""
         nr = C.c_int64()
-        self._check(self.lib.adr_export_scatter(self.ctx, inst, family, C.byref(nr), None, None, None, None))
+        self._check(self.lib.adr_export_scatter(self.ctx, inst, family, C.byref(nr), None, None, None, None, None))
         n = nr.value
         node = np.zeros(n, np.int32)
         k = np.zeros(4 * n, np.int32)
         ca = np.zeros(4 * n)
         cb = np.zeros(4 * n)
+        gb = np.zeros(n)
         i32p = C.POINTER(C.c_int32)
         self._check(self.lib.adr_export_scatter(self.ctx, inst, family, None, node.ctypes.data_as(i32p),
-                                                k.ctypes.data_as(i32p), _dptr(ca), _dptr(cb)))
-        return node, k.reshape(n, 4), ca.reshape(n, 4), cb.reshape(n, 4)
+                                                k.ctypes.data_as(i32p), _dptr(ca), _dptr(cb), _dptr(gb)))
+        out = (node, k.reshape(n, 4), ca.reshape(n, 4), cb.reshape(n, 4))
+        return out + (gb,) if with_gb else out
 
     def kernel_times(self, precision="fp64", reset=True, work=False):
         """Per kernel class: (ms, launches), or (ms, launches, work) with work=True."""

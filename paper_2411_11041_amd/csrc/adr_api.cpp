@@ -114,6 +114,7 @@ struct adr_ctx {
     double *rel_fb = nullptr;  // residual of a fallback start (adr_split_iterate_judged)
     float *d32 = nullptr, *D32 = nullptr;
     int *done = nullptr, *never = nullptr, *conv_it = nullptr;
+    int *sing = nullptr;  // per instance: a line solve met a bad pivot (ADR_ESINGULAR)
     double last_theta = -1, last_dt = -1;
     std::vector<double> mu, sg;
     std::string err;
@@ -123,6 +124,7 @@ struct adr_ctx {
     std::vector<adr_problem> shape;   // per instance: grid and domain (pointers cleared)
     std::vector<int64_t> noffB;       // first beta-line node of each instance
     double *L64 = nullptr;            // packed loads (mutable views of the line tables)
+    double *L64base = nullptr;        // the problem's own loads (the converged time steps shift L64)
     float *L32 = nullptr;
     // timing
     struct Tick {
@@ -330,6 +332,23 @@ struct adr_ctx {
         act_blocks = -1;
         fam[0].act = fam[1].act = -1;
     }
+    // ADR_ESINGULAR with the flagged instances named, or ADR_OK (synchronises)
+    adr_status singular_status() {
+        std::vector<int> sg_h(n_inst, 0);
+        HIPCHK(hipMemcpyAsync(sg_h.data(), sing, sizeof(int) * n_inst, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::string which;
+        int cnt = 0;
+        for (int i = 0; i < n_inst; ++i)
+            if (sg_h[i]) {
+                if (cnt < 8) which += (cnt ? ", " : "") + std::to_string(i);
+                ++cnt;
+            }
+        if (!cnt) return ADR_OK;
+        err = "a line solve met a pivot below the threshold or not finite in " + std::to_string(cnt) +
+              " instance(s): " + which + (cnt > 8 ? ", ..." : "");
+        return ADR_ESINGULAR;
+    }
     void norm(int count, double tol, int mode) {
         timed(0, 4, 0, [&] {
             return adr::launch_norm(n_inst, partial, blk_start, cnorm, rel, done, conv_it, count, tol, mode, st);
@@ -423,9 +442,12 @@ void fill_params(std::vector<double> &ph, int n_inst, int slot, const std::vecto
             double *p = ph.data() + ((static_cast<size_t>(slot) * 2 + f) * n_inst + i) * 8;
             std::fill(p, p + 8, 0.0);
             if (slot == kSlotGuess) {
-                if (f == 0) { p[0] = sg[i]; p[1] = mu[i]; p[2] = 1.0; p[6] = 1.0; }
+                if (f == 0) { p[0] = sg[i]; p[1] = mu[i]; p[2] = 1.0; p[6] = 1.0; p[7] = 1.0; }
                 continue;
             }
+            // p[7]: the sweep carries the state, so the curve ends take the
+            // Dirichlet data (the increment sweeps carry zero there)
+            p[7] = slot == kSlotLin ? 0.0 : 1.0;
             const double td = theta * dt, ed = (1.0 - theta) * dt;
             if (f == 0) {
                 p[0] = 1.0 + td * sg[i]; p[1] = td * mu[i]; p[2] = td;
@@ -475,7 +497,9 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 const adr_problem &p = probs[i];
                 std::vector<double> key = {double(p.nx), double(p.ny), p.a, p.b, p.c, p.d, double(p.domain),
                                            double(reinterpret_cast<uintptr_t>(p.beta1)),
-                                           double(reinterpret_cast<uintptr_t>(p.beta2))};
+                                           double(reinterpret_cast<uintptr_t>(p.beta2)),
+                                           double(reinterpret_cast<uintptr_t>(p.beta1 ? nullptr : p.psi)),
+                                           double(reinterpret_cast<uintptr_t>(p.g))};
                 for (int k = 0; k < p.n_dom_params && p.dom_params; ++k) key.push_back(p.dom_params[k]);
                 auto it = first.find(key);
                 if (it == first.end()) { first.emplace(key, i); rep[i] = i; }
@@ -552,6 +576,10 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         hipStream_t st = C->st;
         auto &own = C->owned;
         C->inst_bstride = upload(inst_bstride, own, st);
+        bool any_g = false;
+        for (int i = 0; i < n; ++i) any_g = any_g || probs[i].g != nullptr;
+        C->sing = dalloc<int>(n, own);
+        HIPCHK(hipMemsetAsync(C->sing, 0, sizeof(int) * n, st));
 
         // scatter slots, padded per instance to whole blocks
         std::vector<int> blk_start(n + 1, 0);
@@ -635,6 +663,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 return nx > ny;
             });
             std::vector<int> loff, lcnt, linst;
+            std::vector<double> gend;  // per list position: the Dirichlet data at the two ends
             loff.reserve(lines.size());
             F.inst_lines.assign(n, 0);
             F.inst_nmax.assign(n, 0);
@@ -650,6 +679,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 loff.push_back(static_cast<int>(noff[li.first] + fa.off[li.second]));
                 lcnt.push_back(cnt);
                 linst.push_back(li.first);
+                gend.push_back(G[li.first].gend[f][2 * li.second]);
+                gend.push_back(G[li.first].gend[f][2 * li.second + 1]);
                 F.nmax = std::max(F.nmax, cnt);
                 F.inst_lines[li.first] += 1;
                 F.inst_unk[li.first] += cnt - 2;
@@ -690,7 +721,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             const int *d_linst = upload(linst, own, st), *d_cellb = upload(cellb, own, st);
             double *dL64 = f == 0 ? upload(L, own, st) : nullptr;
             float *dL32 = f == 0 ? upload(to_type<float>(L), own, st) : nullptr;
-            if (f == 0) { C->L64 = dL64; C->L32 = dL32; }
+            if (f == 0) { C->L64 = dL64; C->L32 = dL32; C->L64base = upload(L, own, st); }
             F.a64 = adr::LineArgs<double>{d_loff, d_lcnt, d_linst, C->inst_bstride, d_cellb,
                                           upload(lx, own, st), upload(ly, own, st), upload(h, own, st),
                                           f == 0 ? upload(w, own, st) : nullptr, dL64};
@@ -698,13 +729,21 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                                          upload(to_type<float>(lx), own, st), upload(to_type<float>(ly), own, st),
                                          upload(to_type<float>(h), own, st),
                                          f == 0 ? upload(to_type<float>(w), own, st) : nullptr, dL32};
+            // Dirichlet data (FP64 state sweeps only; the FP32 sweeps carry increments)
+            F.a64.gend = any_g ? upload(gend, own, st) : nullptr;
+            F.a64.sing = C->sing;
+            F.a32.sing = C->sing;
+            F.a64.ptol = opt->pivot_tol > 0.0 ? opt->pivot_tol : 64.0 * 2.220446049250313e-16;
+            F.a32.ptol = opt->pivot_tol > 0.0 ? opt->pivot_tol : 64.0 * 1.1920928955078125e-07;
             // scatter records
             std::vector<int> rk(4 * static_cast<size_t>(npad), -1);
             std::vector<double> ra(4 * static_cast<size_t>(npad), 0.0), rb(4 * static_cast<size_t>(npad), 0.0);
+            std::vector<double> gb(any_g ? npad : 0, 0.0);
             for (int i = 0; i < n; ++i)
                 for (size_t s = 0; s < order[i].size(); ++s) {
                     const size_t slot = static_cast<size_t>(blk_start[i]) * kBlock + s;
                     const adr::Rec4 &R = G[i].rec[f][order[i][s]];
+                    if (any_g) gb[slot] = R.gb;
                     for (int r = 0; r < 4; ++r) {
                         rk[r * static_cast<size_t>(npad) + slot] = R.k[r] < 0 ? -1 : static_cast<int>(noff[i] + R.k[r]);
                         ra[r * static_cast<size_t>(npad) + slot] = R.ca[r];
@@ -738,6 +777,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             }
             F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, upload(ra, own, st),
                                              upload(rb, own, st), nullptr, npad};
+            F.s64.gb = any_g ? upload(gb, own, st) : nullptr;
             F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, nullptr, nullptr,
                                             upload(rw, own, st), npad};
             F.v64 = dalloc<double>(F.n_nodes, own);
@@ -748,19 +788,36 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         for (int i = 0; i < n; ++i) {
             C->grids.push_back(G[i].g);
             adr_problem sh = probs[i];
-            sh.beta1 = sh.beta2 = sh.f = nullptr;
+            sh.beta1 = sh.beta2 = sh.f = sh.g = sh.psi = nullptr;
             sh.dom_params = nullptr;
             C->shape.push_back(sh);
         }
-        // state scratch (zeroed: non-interior nodes must read as zero)
+        // state scratch: non-interior nodes of the state fields hold the
+        // Dirichlet data (never written later), of the increment fields zero
         C->Ub = dalloc<double>(C->n_blocked, own);
         C->Uh64 = dalloc<double>(C->n_blocked, own);
         C->Z64 = dalloc<double>(C->n_blocked, own);
         C->d32 = dalloc<float>(C->n_blocked, own);
         C->D32 = dalloc<float>(C->n_blocked, own);
-        HIPCHK(hipMemsetAsync(C->Ub, 0, sizeof(double) * C->n_blocked, st));
-        HIPCHK(hipMemsetAsync(C->Uh64, 0, sizeof(double) * C->n_blocked, st));
-        HIPCHK(hipMemsetAsync(C->Z64, 0, sizeof(double) * C->n_blocked, st));
+        if (any_g) {
+            std::vector<double> bf(C->n_blocked, 0.0);
+            for (int i = 0; i < n; ++i) {
+                if (!probs[i].g) continue;
+                const int nxi = G[i].g.nx, nyi = G[i].g.ny;
+                for (int j = 0; j < nyi; ++j)
+                    for (int x = 0; x < nxi; ++x)
+                        if (!G[i].inner[static_cast<size_t>(j) * nxi + x])
+                            bf[adr::blocked_index(x, j, static_cast<int>(boff[i]), inst_bstride[i])] =
+                                probs[i].g[static_cast<size_t>(j) * nxi + x];
+            }
+            for (double *fld : {C->Ub, C->Uh64, C->Z64})
+                HIPCHK(hipMemcpyAsync(fld, bf.data(), sizeof(double) * C->n_blocked, hipMemcpyHostToDevice, st));
+            HIPCHK(hipStreamSynchronize(st));  // bf leaves scope
+        } else {
+            HIPCHK(hipMemsetAsync(C->Ub, 0, sizeof(double) * C->n_blocked, st));
+            HIPCHK(hipMemsetAsync(C->Uh64, 0, sizeof(double) * C->n_blocked, st));
+            HIPCHK(hipMemsetAsync(C->Z64, 0, sizeof(double) * C->n_blocked, st));
+        }
         HIPCHK(hipMemsetAsync(C->d32, 0, sizeof(float) * C->n_blocked, st));
         HIPCHK(hipMemsetAsync(C->D32, 0, sizeof(float) * C->n_blocked, st));
         C->partial = dalloc<double>(std::max(nblk, 1), own);
@@ -863,6 +920,7 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs) {
         }
         HIPCHK(hipStreamSynchronize(ctx->st));
         HIPCHK(hipMemcpy(ctx->L64, L.data(), sizeof(double) * nB, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(ctx->L64base, L.data(), sizeof(double) * nB, hipMemcpyHostToDevice));
         std::vector<float> L32(L.begin(), L.end());
         HIPCHK(hipMemcpy(ctx->L32, L32.data(), sizeof(float) * nB, hipMemcpyHostToDevice));
         for (int i = 0; i < n; ++i) {
@@ -908,6 +966,7 @@ static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback,
         const int period = m + 1;
         HIPCHK(adr::launch_fill_int(ctx->done, 0, n, st));
         HIPCHK(adr::launch_fill_int(ctx->conv_it, 0, n, st));
+        HIPCHK(adr::launch_fill_int(ctx->sing, 0, n, st));
         std::vector<int> dn(n, 0);
         auto all_done = [&]() {
             HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
@@ -993,6 +1052,7 @@ static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback,
         HIPCHK(hipMemcpyAsync(ci.data(), ctx->conv_it, sizeof(int) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(rr.data(), ctx->rel, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        const adr_status sst = ctx->singular_status();
         if (use_graph) ctx->st = user;
         adr_status status = ADR_OK;
         for (int i = 0; i < n; ++i) {
@@ -1001,6 +1061,7 @@ static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback,
             if (max_iters > 0 && !std::isfinite(rr[i])) status = ADR_ENONFINITE;
             else if (!dn[i] && status == ADR_OK) status = ADR_ENOTCONV;
         }
+        if (sst != ADR_OK) return sst;
         if (status == ADR_ENONFINITE) ctx->err = "non-finite residual";
         return status;
     } catch (const Error &e) {
@@ -1156,12 +1217,75 @@ adr_status adr_set_line_shapes(adr_ctx *ctx, const int32_t *shapes) {
     return ADR_OK;
 }
 
-adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32_t nsteps) {
+// Converged implicit Euler steps: each step (u - u_n)/dt + A u = f is the
+// stationary problem with sigma + 1/dt and the beta-curves' load L + M G u_n/dt,
+// solved by the stationary iteration (the context's pseudo step, schedule and
+// launches) from u_n.  The stationary coefficients, loads and |Phi(0)| are
+// restored afterwards.
+static adr_status converged_steps(adr_ctx *ctx, double *u, double dt, int32_t nsteps, int32_t inner_max,
+                                  double inner_tol, int32_t *inner_iters) {
+    const int n = ctx->n_inst;
+    const size_t nB = static_cast<size_t>(ctx->fam[0].n_nodes);
+    auto set_sigma = [&](const std::vector<double> &sg) {
+        fill_params(ctx->par_h, n, kSlotStep, ctx->mu, sg, ctx->opt.theta, ctx->opt.dt);
+        fill_params(ctx->par_h, n, kSlotLin, ctx->mu, sg, ctx->opt.theta, ctx->opt.dt);
+        HIPCHK(hipMemcpyAsync(ctx->par, ctx->par_h.data(), sizeof(double) * 2 * 2 * n * 8, hipMemcpyHostToDevice,
+                              ctx->st));
+        HIPCHK(hipStreamSynchronize(ctx->st));  // par_h is host memory the copy reads
+    };
+    auto restore = [&]() {
+        set_sigma(ctx->sg);
+        HIPCHK(hipMemcpyAsync(ctx->L64, ctx->L64base, sizeof(double) * nB, hipMemcpyDeviceToDevice, ctx->st));
+        ctx->sweep64(kSlotStep, ctx->Z64, ctx->Z64, 3, ctx->never);
+        ctx->norm(0, 0.0, 1);
+        HIPCHK(hipStreamSynchronize(ctx->st));
+    };
+    std::vector<double> sg2(n);
+    for (int i = 0; i < n; ++i) sg2[i] = ctx->sg[i] + 1.0 / dt;
+    adr_status status = ADR_OK;
+    try {
+        set_sigma(sg2);
+        std::vector<int32_t> it(n, 0);
+        for (int s = 0; s < nsteps; ++s) {
+            ctx->to_blocked(u);  // u_n
+            HIPCHK(adr::launch_shift_load(ctx->fam[0].a64, ctx->fam[0].n_lines, ctx->fam[0].nmax, ctx->L64base,
+                                          ctx->Ub, ctx->L64, 1.0 / dt, ctx->st));
+            ctx->sweep64(kSlotStep, ctx->Z64, ctx->Z64, 3, ctx->never);  // |Phi(0)| of the step's problem
+            ctx->norm(0, 0.0, 1);
+            const adr_status st = split_iterate(ctx, u, nullptr, inner_max, inner_tol, it.data(), nullptr, nullptr);
+            if (inner_iters)
+                for (int i = 0; i < n; ++i) inner_iters[static_cast<size_t>(s) * n + i] = it[i];
+            if (st < 0) {
+                status = st;
+                break;
+            }
+            if (st == ADR_ENOTCONV) status = ADR_ENOTCONV;
+        }
+        const std::string msg = ctx->err;
+        restore();
+        ctx->err = msg;
+        return status;
+    } catch (const Error &e) {
+        try {
+            restore();
+        } catch (const Error &) {
+        }
+        return fail_ctx(ctx, e);
+    }
+}
+
+adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32_t nsteps, int32_t inner_max,
+                         double inner_tol, int32_t *inner_iters) {
     if (!ctx) return ADR_EINVAL;
-    if (!u || nsteps < 0 || !(theta > 0.0 && theta <= 1.0) || !(dt > 0.0)) {
-        ctx->err = "u, nsteps >= 0, theta in (0,1] and dt > 0 are required";
+    if (!u || nsteps < 0 || !(theta > 0.0 && theta <= 1.0) || !(dt > 0.0) || inner_max < 0) {
+        ctx->err = "u, nsteps >= 0, theta in (0,1], dt > 0 and inner_max >= 0 are required";
         return ADR_EINVAL;
     }
+    if (inner_max > 0 && theta != 1.0) {
+        ctx->err = "the converged mode (inner_max > 0) is implicit Euler: theta = 1";
+        return ADR_EINVAL;
+    }
+    if (inner_max > 0) return converged_steps(ctx, u, dt, nsteps, inner_max, inner_tol, inner_iters);
     try {
         if (theta != ctx->last_theta || dt != ctx->last_dt) {
             fill_params(ctx->par_h, ctx->n_inst, kSlotTime, ctx->mu, ctx->sg, theta, dt);
@@ -1187,11 +1311,14 @@ adr_status adr_residual(adr_ctx *ctx, const double *u, double *rel_res) {
         return ADR_EINVAL;
     }
     try {
+        HIPCHK(adr::launch_fill_int(ctx->sing, 0, ctx->n_inst, ctx->st));
         ctx->to_blocked(u);
         ctx->sweep64(kSlotStep, ctx->Ub, ctx->Ub, 3, ctx->never);
         ctx->norm(0, 0.0, 2);
         HIPCHK(hipMemcpyAsync(rel_res, ctx->rel, sizeof(double) * ctx->n_inst, hipMemcpyDeviceToHost, ctx->st));
         HIPCHK(hipStreamSynchronize(ctx->st));
+        const adr_status sst = ctx->singular_status();
+        if (sst != ADR_OK) return sst;
         for (int i = 0; i < ctx->n_inst; ++i)
             if (!std::isfinite(rel_res[i])) {
                 ctx->err = "non-finite residual";
@@ -1235,7 +1362,7 @@ adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, in
 }
 
 adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
-                              int32_t *node, int32_t *k, double *ca, double *cb) {
+                              int32_t *node, int32_t *k, double *ca, double *cb, double *gb) {
     if (!ctx || !ctx->opt.host_only || inst < 0 || inst >= ctx->n_inst || family < 0 || family > 1)
         return ADR_EINVAL;
     const adr::InstanceGeo &G = ctx->host_geo[inst];
@@ -1243,6 +1370,7 @@ adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, 
     if (n_rows) *n_rows = static_cast<int64_t>(R.size());
     for (size_t r = 0; r < R.size(); ++r) {
         if (node) node[r] = G.inner_list[r];
+        if (gb) gb[r] = R[r].gb;
         for (int q = 0; q < 4; ++q) {
             if (k) k[4 * r + q] = R[r].k[q];
             if (ca) ca[4 * r + q] = R[r].ca[q];

@@ -324,8 +324,11 @@ struct Bracket {
     int depth;     // edges from the node to the edge holding the bracket (1 = own edge)
 };
 
+// gdata: nodal Dirichlet data (NULL: zero); a boundary point's share of a node's
+// value is summed into the stencil's gb.
 void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> &inner,
-                   const std::vector<int32_t> &inner_list, const Family &F, std::vector<Rec4> &out) {
+                   const std::vector<int32_t> &inner_list, const Family &F, const double *gdata,
+                   std::vector<Rec4> &out) {
     const int nx = g.nx, ny = g.ny;
     // edges of vertical grid lines: line i, edge j (ny-1 per line); horizontal: line j, edge i
     const int64_t nvE = static_cast<int64_t>(nx) * (ny - 1), nhE = static_cast<int64_t>(ny) * (nx - 1);
@@ -428,6 +431,7 @@ void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> 
         const double Wh = local[0] == local[1] ? 0.5 : (local[0] ? 1.0 : 0.0);
         const double Ws[2] = {Wh, 1.0 - Wh};
         Rec4 &R = out[n];
+        R.gb = 0.0;
         for (int dir = 0; dir < 2; ++dir) {
             for (int side = 0; side < 2; ++side) {
                 int slot = dir * 2 + side;
@@ -437,14 +441,39 @@ void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> 
                     R.k[slot] = static_cast<int32_t>(b.k);
                     R.ca[slot] = coef * (1.0 - b.t);
                     R.cb[slot] = coef * b.t;
-                } else {  // boundary point: zero Dirichlet value
+                } else {  // boundary point: carries the Dirichlet data there
                     R.k[slot] = -1;
                     R.ca[slot] = 0.0;
                     R.cb[slot] = 0.0;
+                    if (gdata && coef != 0.0) {
+                        const double px = dir == 0 ? b.coord : g.x(gi), py = dir == 0 ? g.y(gj) : b.coord;
+                        R.gb += coef * g.interp(gdata, px, py);
+                    }
                 }
             }
         }
     }
+}
+
+// beta = (psi_y, -psi_x) at the nodes: central differences inside, the
+// second-order one-sided formula (-3 f0 + 4 f1 - f2) / (2 h) on the grid's edges.
+void beta_from_psi(const double *psi, int nx, int ny, double hx, double hy, std::vector<double> &b1,
+                   std::vector<double> &b2) {
+    b1.assign(static_cast<size_t>(nx) * ny, 0.0);
+    b2.assign(static_cast<size_t>(nx) * ny, 0.0);
+    auto P = [&](int i, int j) { return psi[static_cast<size_t>(j) * nx + i]; };
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            double dx, dy;
+            if (i == 0) dx = (-3.0 * P(0, j) + 4.0 * P(1, j) - P(2, j)) / (2.0 * hx);
+            else if (i == nx - 1) dx = (3.0 * P(nx - 1, j) - 4.0 * P(nx - 2, j) + P(nx - 3, j)) / (2.0 * hx);
+            else dx = (P(i + 1, j) - P(i - 1, j)) / (2.0 * hx);
+            if (j == 0) dy = (-3.0 * P(i, 0) + 4.0 * P(i, 1) - P(i, 2)) / (2.0 * hy);
+            else if (j == ny - 1) dy = (3.0 * P(i, ny - 1) - 4.0 * P(i, ny - 2) + P(i, ny - 3)) / (2.0 * hy);
+            else dy = (P(i, j + 1) - P(i, j - 1)) / (2.0 * hy);
+            b1[static_cast<size_t>(j) * nx + i] = dy;
+            b2[static_cast<size_t>(j) * nx + i] = -dx;
+        }
 }
 
 bool finite_all(const double *p, size_t n) {
@@ -479,11 +508,22 @@ void build_instance(const adr_problem &p, InstanceGeo &G) {
     if (!(p.b > p.a) || !(p.d > p.c)) fail(ADR_EINVAL, "empty bounding box");
     if (!(p.mu > 0.0)) fail(ADR_EINVAL, "mu must be > 0");
     if (!(p.sigma >= 0.0)) fail(ADR_EINVAL, "sigma must be >= 0");
-    if (!p.beta1 || !p.beta2 || !p.f) fail(ADR_EINVAL, "beta1, beta2 and f are required");
+    if (!p.f) fail(ADR_EINVAL, "f is required");
+    if ((!p.beta1 || !p.beta2) && !(!p.beta1 && !p.beta2 && p.psi))
+        fail(ADR_EINVAL, "give beta1 and beta2, or psi with both beta arrays NULL");
     const size_t nn = static_cast<size_t>(p.nx) * p.ny;
     if (nn > (1u << 30)) fail(ADR_EINVAL, "grid too large");
-    if (!finite_all(p.beta1, nn) || !finite_all(p.beta2, nn) || !finite_all(p.f, nn))
+    std::vector<double> b1v, b2v;
+    const double *beta1 = p.beta1, *beta2 = p.beta2;
+    if (!beta1) {
+        if (!finite_all(p.psi, nn)) fail(ADR_ENONFINITE, "non-finite psi");
+        beta_from_psi(p.psi, p.nx, p.ny, (p.b - p.a) / (p.nx - 1), (p.d - p.c) / (p.ny - 1), b1v, b2v);
+        beta1 = b1v.data();
+        beta2 = b2v.data();
+    }
+    if (!finite_all(beta1, nn) || !finite_all(beta2, nn) || !finite_all(p.f, nn))
         fail(ADR_ENONFINITE, "non-finite beta or f");
+    if (p.g && !finite_all(p.g, nn)) fail(ADR_ENONFINITE, "non-finite g");
     Grid &g = G.g;
     g.a = p.a; g.b = p.b; g.c = p.c; g.d = p.d; g.nx = p.nx; g.ny = p.ny;
     g.hx = (p.b - p.a) / (p.nx - 1);
@@ -518,7 +558,7 @@ void build_instance(const adr_problem &p, InstanceGeo &G) {
             }
         }
 
-    Flow fl{&g, p.beta1, p.beta2};
+    Flow fl{&g, beta1, beta2};
     for (int fam = 0; fam < 2; ++fam) {
         std::vector<double> sx, sy;
         make_seeds(fl, *dom, fam, g.h, sx, sy);
@@ -549,12 +589,21 @@ void build_instance(const adr_problem &p, InstanceGeo &G) {
         if (fam == 0) {
             G.wk.assign(n, 0.0);
             for (size_t k = 0; k < n; ++k) {
-                double b1 = g.interp(p.beta1, F.x[k], F.y[k]), b2 = g.interp(p.beta2, F.x[k], F.y[k]);
+                double b1 = g.interp(beta1, F.x[k], F.y[k]), b2 = g.interp(beta2, F.x[k], F.y[k]);
                 G.wk[k] = std::hypot(b1, b2);
             }
         }
-        build_scatter(g, *dom, G.inner, G.inner_list, F, G.rec[fam]);
+        build_scatter(g, *dom, G.inner, G.inner_list, F, p.g, G.rec[fam]);
+        // Dirichlet data at the curve ends (they lie on Gamma)
+        G.gend[fam].assign(2 * (F.off.size() - 1), 0.0);
+        if (p.g)
+            for (int l = 0; l < nl; ++l) {
+                const int64_t k0 = F.off[l], k1 = F.off[l + 1] - 1;
+                G.gend[fam][2 * l] = g.interp(p.g, F.x[k0], F.y[k0]);
+                G.gend[fam][2 * l + 1] = g.interp(p.g, F.x[k1], F.y[k1]);
+            }
     }
+    G.has_g = p.g != nullptr;
     compute_load(p, G);
 }
 

@@ -33,10 +33,13 @@ struct Family {
     std::vector<double> x, y;
 };
 
-// One scatter record: value = ca * v[k] + cb * v[k+1] (k = -1: unused).
+// The scatter stencil of one grid node: value = gb + sum over the 4 records of
+// ca * v[k] + cb * v[k+1] (k = -1: unused); gb = the Dirichlet data its
+// boundary points carry (0 for zero data).
 struct Rec4 {
     int32_t k[4];
     double ca[4], cb[4];
+    double gb;
 };
 
 // Everything the device needs for one instance, in local indices.
@@ -53,6 +56,8 @@ struct InstanceGeo {
     std::vector<double> wk;            // beta family: |beta| at the node
     std::vector<double> Lk;            // beta family: load int f phi_k (0 at ends)
     std::vector<Rec4> rec[2];          // per interior node (inner_list order)
+    std::vector<double> gend[2];       // per curve: Dirichlet data at its first and last node
+    bool has_g = false;                // non-zero Dirichlet data given
 };
 
 // Message returned by adr_last_error(NULL) in this thread (failed set-up or

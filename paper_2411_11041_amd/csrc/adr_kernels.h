@@ -19,6 +19,9 @@ struct LineArgs {
     const T *L;          // per node: load int f phi (beta family only)
     const int *lidx;     // optional: the line at each list position (active lines only), else line = position
     int lbase;           // list position of the launch's first workgroup (length buckets)
+    const T *gend;       // optional: per line the Dirichlet values at its two ends (2 per line); NULL: zero
+    int *sing;           // optional: per instance, set to 1 when a pivot is not finite or below ptol
+    double ptol;         // relative pivot threshold (of |diagonal| + |eliminated part|)
 };
 
 // Record indices relative to the slot's first record (ScatterArgs::rd)
@@ -43,6 +46,8 @@ struct ScatterArgs {
     int npad;
     const int *blist;     // optional: the slot block of each workgroup (active blocks only)
     int nblist;           // workgroups when blist is set
+    const double *gb;     // optional ([npad], FP64 sweeps of the state only): the boundary points'
+                          // share of the Dirichlet data in the slot's value; NULL: zero data
 };
 
 // The grid fields the sweeps use (state, half step, increments) are stored in
@@ -89,6 +94,11 @@ hipError_t launch_norm(int n_inst, const double *partial, const int *blk_start, 
                        int *it_count, int count, double tol, int mode, hipStream_t st);
 
 hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st);
+
+// Lout = Lbase + M G un / dt on the interior nodes of the beta-curves (the
+// full line list of a), ends copied: the load of an implicit Euler step.
+hipError_t launch_shift_load(const LineArgs<double> &a, int n_lines, int nmax, const double *Lbase, const double *un,
+                             double *Lout, double inv_dt, hipStream_t st);
 
 // Order-preserving compaction of the items (lines or slot blocks) whose
 // instance inst_of[i] is not done: idx receives their indices, *count (device)

@@ -80,6 +80,14 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     const double *pp = par + 8 * inst;
     const T cM = T(pp[0]), cK = T(pp[1]), cC = T(pp[2]);
     const T eM = T(pp[3]), eK = T(pp[4]), eC = T(pp[5]), eL = T(pp[6]);
+    // Dirichlet values at the curve's ends (the state sweeps; zero for increments)
+    T x0 = T(0), xn = T(0);
+    if (a.gend && pp[7] != 0.0) {
+        x0 = a.gend[2 * l];
+        xn = a.gend[2 * l + 1];
+    }
+    const T ptol = T(a.ptol);
+    bool bad = false;  // a pivot not finite or below ptol of its row's scale
 
     // chunking of the rows: thread q owns rows rs .. rs+k-1, rs = q*m (m <= MAXJ)
     const int m = (N + NT - 1) / NT;
@@ -133,7 +141,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
             const int j = tid + NT * sl;
             const T lx = lxj[sl], ly = lyj[sl];
             const T ub = (T(1) - ly) * ((T(1) - lx) * p11[t] + lx * p12[t]) + ly * ((T(1) - lx) * p21[t] + lx * p22[t]);
-            const T uj = cj[sl] >= 0 ? ub : T(0);
+            const T uj = cj[sl] >= 0 ? ub : (j == 0 ? x0 : xn);
             if (j < n) {
                 U[j] = uj;
                 if (j > 0) Hs[j] = hj[sl];
@@ -215,7 +223,9 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         for (int j = 0; j < MAXJ; ++j) {
             if (j < kin) {
                 const T ar = ra_[j];
-                const T inv = recip(rb_[j] - ar * pc);
+                const T den = rb_[j] - ar * pc;
+                bad |= !(fabs(den) > ptol * (fabs(rb_[j]) + fabs(ar * pc)));
+                const T inv = recip(den);
                 const T cp = rc_[j] * inv;
                 const T yp = (rd_[j] - ar * py) * inv;
                 const T al = (j == 0 ? -ar : -ar * pa) * inv;
@@ -265,10 +275,13 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         T ra = T(0), rc = T(0), rd = T(0);
         if (q < R) {
             const T nfy = FY[q + 1], nfa = FA[q + 1], nfg = FG[q + 1];
+            // chunk 0's left neighbour and the last chunk's right one are the
+            // curve's end nodes, whose values are known
             const T a = q > 0 ? sa * aL : T(0);
             const T b = sb + sa * gL + sc * nfa;
             const T c = q + 1 < R ? sc * nfg : T(0);
-            const T d = sd - sa * yL - sc * nfy;
+            const T d = sd - sa * yL - sc * nfy - (q == 0 ? sa * aL * x0 : T(0)) - (q + 1 == R ? sc * nfg * xn : T(0));
+            bad |= !(fabs(b) > ptol * (fabs(sb) + fabs(sa * gL) + fabs(sc * nfa)));
             const T ib = recip(b);
             ra = a * ib;
             rc = c * ib;
@@ -282,7 +295,9 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
                 T la = T(0), lc = T(0), ld = T(0), ua = T(0), uc = T(0), ud = T(0);
                 if (q - st >= 0) { la = Ai[q - st]; lc = Ci[q - st]; ld = Di[q - st]; }
                 if (q + st < R) { ua = Ai[q + st]; uc = Ci[q + st]; ud = Di[q + st]; }
-                const T ib = recip(T(1) - ra * lc - rc * ua);
+                const T den = T(1) - ra * lc - rc * ua;
+                bad |= !(fabs(den) > ptol * (T(1) + fabs(ra * lc) + fabs(rc * ua)));
+                const T ib = recip(den);
                 const T na = -(ra * la) * ib;
                 const T nc = -(rc * uc) * ib;
                 const T nd = (rd - ra * ld - rc * ud) * ib;
@@ -300,8 +315,8 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
 
     // 4. back-substitution of every chunk into X (P0)
     if (q < Q) {
-        const T SL = q > 0 ? Sv[q - 1] : T(0);
-        const T SR = q < R ? Sv[q] : T(0);
+        const T SL = q > 0 ? Sv[q - 1] : x0;
+        const T SR = q < R ? Sv[q] : xn;
         T x = T(0);
 #pragma unroll
         for (int j = MAXJ - 1; j >= 0; --j) {
@@ -316,7 +331,8 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         if (has_sep) X[rs + k - 1] = SR;
     }
     __syncthreads();
-    for (int j = tid; j < n; j += NT) vout[o + j] = (j == 0 || j == n - 1) ? T(0) : X[j - 1];
+    for (int j = tid; j < n; j += NT) vout[o + j] = j == 0 ? x0 : (j == n - 1 ? xn : X[j - 1]);
+    if (bad && a.sing) a.sing[inst] = 1;
 }
 
 // One launch for every curve of a family: curves are ordered longest first and
@@ -404,6 +420,9 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
         vb[r] = v[k + 1];
     }
     T val = T(0);
+    if constexpr (sizeof(T) == 8) {
+        if (s.gb) val = s.gb[slot];  // the Dirichlet data the boundary points carry
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r)
         if (kk[r] >= 0) val += wa[r] * va[r] + wb[r] * vb[r];
@@ -476,6 +495,42 @@ __global__ __launch_bounds__(kThreads) void k_norm(const double *__restrict__ pa
         it_count[inst] += count;  // sweeps applied since the previous measurement
         if (!(r <= tol)) return;  // NaN never converges
         done[inst] = 1;
+    }
+}
+
+// The load of an implicit Euler step solved as a stationary problem: on every
+// interior node of every beta-curve, L'_k = L_k + (M G u_n)_k / dt with G the
+// bilinear gather of eq. (22) (the curve's ends take their Dirichlet data) and
+// M the P1 mass rows.  One workgroup per curve; the gathered values go to LDS.
+__global__ __launch_bounds__(kThreads) void k_shift_load(LineArgs<double> a, const double *__restrict__ Lbase,
+                                                         const double *__restrict__ un, double *__restrict__ Lout,
+                                                         double inv_dt) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    double *su = reinterpret_cast<double *>(smem_raw);
+    const int l = static_cast<int>(blockIdx.x);
+    const int o = a.loff[l], n = a.lcnt[l], inst = a.linst[l];
+    const int nx = a.inst_nx[inst];
+    for (int j = threadIdx.x; j < n; j += kThreads) {
+        double v;
+        if (j == 0 || j == n - 1) {
+            v = a.gend ? a.gend[2 * l + (j == 0 ? 0 : 1)] : 0.0;
+        } else {
+            const int c = a.cell[o + j];
+            const int sx = (c & 7) == 7 ? 25 : 1;
+            const int cu = c + (((c >> 3) & 3) == 3 ? nx - 24 : 8);
+            const double lx = a.lx[o + j], ly = a.ly[o + j];
+            v = (1.0 - ly) * ((1.0 - lx) * un[c] + lx * un[c + sx]) + ly * ((1.0 - lx) * un[cu] + lx * un[cu + sx]);
+        }
+        su[j] = v;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += kThreads) {
+        double Lk = Lbase[o + j];
+        if (j > 0 && j < n - 1) {
+            const double hl = a.h[o + j], hr = a.h[o + j + 1];
+            Lk += inv_dt * (hl / 6.0 * su[j - 1] + (hl + hr) / 3.0 * su[j] + hr / 6.0 * su[j + 1]);
+        }
+        Lout[o + j] = Lk;
     }
 }
 
@@ -659,6 +714,15 @@ hipError_t launch_compact(const int *inst_of, int n, const int *done, int *bcnt,
     hipLaunchKernelGGL(k_count_active, dim3(nb), dim3(kThreads), 0, st, inst_of, n, done, bcnt);
     hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(kThreads), 0, st, bcnt, nb, count);
     hipLaunchKernelGGL(k_write_active, dim3(nb), dim3(kThreads), 0, st, inst_of, n, done, bcnt, idx);
+    return hipGetLastError();
+}
+
+hipError_t launch_shift_load(const LineArgs<double> &a, int n_lines, int nmax, const double *Lbase, const double *un,
+                             double *Lout, double inv_dt, hipStream_t st) {
+    if (n_lines == 0) return hipSuccess;
+    const size_t lds = sizeof(double) * static_cast<size_t>(nmax);
+    set_lds(&k_shift_load, lds);
+    hipLaunchKernelGGL(k_shift_load, dim3(n_lines), dim3(kThreads), lds, st, a, Lbase, un, Lout, inv_dt);
     return hipGetLastError();
 }
 

@@ -169,3 +169,39 @@ def test_line_solve_argument_errors():
     assert b"out of range" in lib.adr_last_error(None)
     assert lib.adr_line_solve(3, 10, None, fake, fake, fake, fake, fake, None, 0.0, None) == ADR_EINVAL
     assert lib.adr_line_solve(0, 0, None, None, None, None, None, None, None, 0.0, None) == ADR_OK
+
+
+def _psi_only(n=65):
+    p = W.c2(n)
+    p.beta1 = p.beta2 = None  # beta from the stream function
+    return p
+
+
+def _with_g(maker):
+    def make():
+        p = maker()
+        X, Y = p.coords()
+        p.g = np.sin(3 * X) + Y ** 2 - 0.5
+        return p
+    return make
+
+
+@pytest.mark.parametrize("maker", [_psi_only, _with_g(lambda: W.c1(33)),
+                                   _with_g(lambda: W.c4_instance(0, n_max=90)),
+                                   _with_g(lambda: W.c4_instance(1, n_max=90))])
+def test_host_psi_and_dirichlet_tables_match_oracle(maker):
+    """beta from psi (second-order differences), the curve ends' Dirichlet data
+    and the boundary points' share of each scatter row: the C++ set-up and
+    the oracle agree."""
+    from oracle.method import Oracle
+    from paper_2411_11041_amd.adr import Solver
+    p = maker()
+    s = Solver(p, host_only=True)
+    o = Oracle(p)
+    for f in (0, 1):
+        off, x, y = s.export_lines(0, f)
+        assert np.array_equal(off, o.fams[f].offsets)
+        assert np.max(np.abs(x - o.fams[f].x)) < 1e-12 and np.max(np.abs(y - o.fams[f].y)) < 1e-12
+        node, _, _, _, gb = s.export_scatter(0, f, with_gb=True)
+        assert np.max(np.abs(gb - o.Pb[f][node])) < 1e-12
+    s.close()

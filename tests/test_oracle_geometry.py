@@ -147,3 +147,24 @@ def test_c4_instances_cover_the_grid(i):
     p = W.c4_instance(i, n_max=90)
     o = Oracle(p)  # raises if a node has no bracketing record
     assert o.fams[0].n_lines > 0 and o.fams[1].n_lines > 0
+
+
+def test_beta_from_psi_exact_on_quadratics_and_second_order():
+    """Second-order differences (central inside, one-sided on the edges) are
+    exact for quadratic stream functions, and their error falls by about 4
+    per halving of h on a smooth one; beta = (psi_y, -psi_x) is divergence
+    free in the sense that both components come from one psi."""
+    g = geo.Grid((0.0, 2.0, -1.0, 1.0), 9, 7)
+    X, Y = np.meshgrid(g.x, g.y, indexing="xy")
+    psi = 0.3 + 1.1 * X - 0.7 * Y + 0.5 * X * X - 1.3 * X * Y + 0.9 * Y * Y
+    b1, b2 = geo.beta_from_psi(g, psi)
+    assert np.max(np.abs(b1 - (-0.7 - 1.3 * X + 1.8 * Y))) < 1e-12
+    assert np.max(np.abs(b2 + (1.1 + X - 1.3 * Y))) < 1e-12
+    errs = []
+    for n in (17, 33, 65):
+        g = geo.Grid((0.0, 1.0, 0.0, 1.0), n, n)
+        X, Y = np.meshgrid(g.x, g.y, indexing="xy")
+        psi, e1, e2 = W.curved_stream(X, Y)
+        b1, b2 = geo.beta_from_psi(g, psi)
+        errs.append(max(np.max(np.abs(b1 - e1)), np.max(np.abs(b2 - e2))))
+    assert 3.2 < errs[0] / errs[1] < 4.8 and 3.2 < errs[1] / errs[2] < 4.8, errs

@@ -173,3 +173,89 @@ def test_s_guess_closed_form_grid_aligned(mu, sigma, c):
     ref = np.tile(v, (n, 1))
     m = o.mask
     assert np.max(np.abs(u0[m] - ref[m])) < 1e-11 * max(1.0, np.max(np.abs(v)))
+
+
+def _affine_problem(kind, n, beta=(1.0, 0.5), mu=0.05, sigma=2.0):
+    """Constant beta, u = a + b x + c y, f = beta . grad u + sigma u, g = u."""
+    a, b, c = 0.7, -1.3, 0.4
+    p = W.constant_beta(n, mu, sigma, beta, f=0.0)
+    X, Y = p.coords()
+    u = a + b * X + c * Y
+    p.f = beta[0] * b + beta[1] * c + sigma * u
+    p.g = u.copy()
+    if kind == "disc":
+        p.domain, p.dom_params = W.DOM_DISC, (0.5, 0.5, 0.45)
+    elif kind == "L":
+        p.domain, p.dom_params = W.DOM_POLYGON, W.L_SHAPE
+    return p, u.ravel()
+
+
+@pytest.mark.parametrize("kind,beta", [("box", (1.0, 0.5)), ("disc", (0.6, -1.1)), ("L", (-0.8, 0.3)),
+                                       ("box", (1.0, 0.0))])
+def test_dirichlet_affine_solution_is_exact(kind, beta):
+    """Dirichlet data g: for constant beta the affine u with f = beta . grad u +
+    sigma u and g = u solves every line problem exactly (K annihilates affine
+    data, C u = |beta| u' M 1, and the load is M f), the gather and the scatter
+    reproduce affine fields, and the ends and boundary points carry g.  So one
+    step of eq. (10) maps u to itself for either theta, eq. (11) returns u, and
+    the iteration's limit from zero is u.  A wrong end value, boundary weight or
+    outside corner breaks the identity near Gamma."""
+    p, u = _affine_problem(kind, 25, beta)
+    o = Oracle(p)
+    m = o.inner_idx
+    for theta in (1.0, 0.5):
+        assert np.max(np.abs(o.step(u, theta, 0.05)[m] - u[m])) < 1e-12
+    assert np.max(np.abs(o.s_guess()[m] - u[m])) < 1e-12
+    U, it, rel, _ = o.iterate(o.zero_field(), 1.0, 0.05, 2000, 1e-13)
+    assert rel <= 1e-13 and np.max(np.abs(U[m] - u[m])) < 1e-10
+
+
+def test_dirichlet_iteration_limit_is_dense_fixed_point():
+    """With non-zero g (not affine) on a disc the iteration still converges to
+    the dense solution of (I - T) U = c, c = Phi(0) carrying g."""
+    p = W.c4_instance(0, n_max=40)
+    X, Y = p.coords()
+    p.g = np.sin(3 * X) + Y ** 2
+    o = Oracle(p)
+    Ud = dense.fixed_point(o, 1.0, 0.05)
+    U, it, rel, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-13)
+    m = o.inner_idx
+    assert np.linalg.norm(U[m] - Ud[m]) / np.linalg.norm(Ud[m]) < 1e-10
+    # g reaches the interior: the solution differs from the zero-data one
+    o0 = Oracle(W.c4_instance(0, n_max=40))
+    assert np.linalg.norm(dense.fixed_point(o0, 1.0, 0.05)[m] - Ud[m]) > 1e-2 * np.linalg.norm(Ud[m])
+
+
+def test_implicit_step_limits_and_exactness():
+    """Converged implicit Euler step: (a) for dt -> infinity it is the
+    stationary solve (sigma + 1/dt -> sigma, u_n/dt -> 0); (b) an affine u_n
+    that is the stationary solution (g = u on Gamma) is reproduced exactly,
+    since u/dt on the left balances u_n/dt on the right; (c) its limit is the
+    dense solution of the step problem's affine map."""
+    p = W.c1(25)
+    o = Oracle(p)
+    m = o.inner_idx
+    Ustat, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-13)
+    X, Y = p.coords()
+    Urand = (np.sin(5 * X) * Y).ravel()
+    U1, it, rel = o.implicit_step(Urand, 1e14, 0.05, 1e-13, 3000)
+    assert rel <= 1e-13 and np.max(np.abs(U1[m] - Ustat[m])) < 1e-9 * np.max(np.abs(Ustat[m]))
+    pa, u = _affine_problem("disc", 25, (0.6, -1.1))
+    oa = Oracle(pa)
+    ma = oa.inner_idx
+    Ua, it, rel = oa.implicit_step(u, 0.01, 0.05, 1e-14, 500)
+    assert np.max(np.abs(Ua[ma] - u[ma])) < 1e-11
+    # (c) dense: Phi_step(U) = T U + c_step with the shifted operators
+    S, L = o.step_operators(Urand, 0.02)
+    ii = o.inner_idx
+    c = o.step(o.zero_field(), 1.0, 0.05, S=S, L=L)[ii]
+    T = np.zeros((len(ii), len(ii)))
+    for col in range(len(ii)):
+        e = o.zero_field()
+        e[ii[col]] = 1.0
+        T[:, col] = o.step(e, 1.0, 0.05, S=S, L=L)[ii] - c
+    ud = np.linalg.solve(np.eye(len(ii)) - T, c)
+    Us, it, rel = o.implicit_step(Urand, 0.02, 0.05, 1e-14, 3000)
+    assert np.linalg.norm(Us[ii] - ud) / np.linalg.norm(ud) < 1e-11
+    # a reaction-dominated step converges in few sweeps
+    assert it < 60

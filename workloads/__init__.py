@@ -10,8 +10,8 @@ any solver code.
 Problem data follow the paper's problem statement (Sec. 2, eq. (1)-(2)):
 constant mu > 0 and sigma > 0, a divergence-free advection field beta
 given as nodal values of beta = (psi_y, -psi_x) for a stream function psi,
-a nodal source f, zero Dirichlet data on Gamma and, for the parabolic
-problem, an initial value u0.  All nodal arrays are float64, shape
+a nodal source f, Dirichlet data on Gamma (zero, the paper's case, unless a
+nodal field g is given) and, for the parabolic problem, an initial value u0.  All nodal arrays are float64, shape
 (ny, nx), row-major with index [j, i] for the node (x_i, y_j) of the grid
 that covers the bounding box P of eq. (20).
 """
@@ -47,6 +47,7 @@ class Problem:
     u0: np.ndarray | None = None
     psi: np.ndarray | None = None
     extra: dict = field(default_factory=dict)
+    g: np.ndarray | None = None  # nodal Dirichlet data (used on and outside Gamma); None = 0
 
     @property
     def h(self) -> float:
