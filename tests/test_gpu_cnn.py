@@ -236,3 +236,35 @@ def test_coarse_transfers_reject_bad_arguments():
     big = Net(3, 3, 1)
     with pytest.raises(ADRError):
         big.restrict(1, 5000, x)  # fine width 10001 > 8192
+
+
+def test_full_size_forward_and_gradients_match_oracle():
+    """257 x 257 images, 8 of them (2 312 tiles of 16 x 16: the persistent
+    multi-tile loops of the convolutions and of the weight gradient run), the
+    network grid the warm start uses without coarsening.  Same bars as the
+    larger case above: the device stays well inside the BF16 rounding effect."""
+    B, H, W = 8, 257, 257
+    print(f"[case] full-size network B={B} {H}x{W} vs oracle", flush=True)
+    f, s, u, mask, mu = make_batch(B, H, W, seed=7)
+    net, Wt, bt = setup_net(H, W, B, seed=8)
+    x0, tgt, sn = net.pack(B, dev(f), dev(s), dev(mask, torch.uint8), mu, dev(u))
+    xo, sno = cnn.pack_inputs(f, s, mask, mu)
+    out = net.forward(B, x0).cpu().numpy().reshape(B, H, W)
+    ref, _ = cnn.forward(xo, Wt, bt, rounding=True)
+    ref_x, _ = cnn.forward(xo, Wt, bt, rounding=False)
+    env = rel(ref_x, ref)
+    print(f"[case] forward rel {rel(out, ref):.2e} (BF16 rounding effect {env:.2e})", flush=True)
+    assert rel(out, ref) < min(1e-4, 0.25 * env)
+    g, loss = net.grads(B, x0, tgt, dev(mask, torch.uint8))
+    t = cnn.target(u, s, sno, mask)
+    L, dW, db, _ = cnn.loss_and_grads(xo, t, mask, Wt, bt, rounding=True)
+    _, dWx, _, _ = cnn.loss_and_grads(xo, t, mask, Wt, bt, rounding=False)
+    gW, gb = cnn.unflatten(g.cpu().numpy())
+    assert abs(loss - L) <= 1e-4 * L
+    for l in range(4):
+        e = rel(dWx[l], dW[l])
+        print(f"[case] layer {l}: weight gradient rel {rel(gW[l], dW[l]):.2e} (rounding effect {e:.2e}), "
+              f"bias {rel(gb[l], db[l]):.2e}", flush=True)
+        assert rel(gW[l], dW[l]) < min(2e-3, 0.25 * e)
+        assert rel(gb[l], db[l]) < 2e-3
+    net.close()

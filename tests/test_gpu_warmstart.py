@@ -101,3 +101,48 @@ def test_corrupted_network_falls_back(trained):
         assert np.all(rel <= 1e-8) and torch.isfinite(u).all()
     finally:
         net.set_params(good)
+
+
+def test_trained_network_gains_over_the_method_without_it():
+    """What the learned warm start gains, on held-out seeds at the warm-start
+    configuration's shape (257^2, the network on every 8th node): after
+    training on 8 192 method-generated solutions, the network's start is closer
+    to the fixed point than the eq. (11) iterate, and the judged solve from it
+    needs fewer sweeps on average than the solve from zero and the solve from
+    the eq. (11) iterate, all to the same fixed point."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_11041_amd import warmstart as WS
+    from paper_2411_11041_amd.adr import Net
+    print("[case] warm-start gain: 257^2, network on 33^2, train 8192 x 400, 64 held-out seeds", flush=True)
+    wl = WS.Workload(n=257, batch=128, coarsen=8)
+    net = Net(*wl.coarse_shape(), 128)
+    net.set_params(WS.he_init(0))
+    x, t = wl.generate(net, list(range(8192)), tol=1e-10)
+    WS.train(net, x, t, wl.mask_c, 8192, wl.HWc, 400, batch=32, lr=2e-3, lr_end=2e-5)
+    del x, t
+    test = list(range(20000, 20064))
+    tol = 1e-8
+    u0, it0, rel0, _ = wl.solve_batch(test, tol)
+    us, its, rels, _, _ = wl.warm_started(net, test, tol, use_net=False)
+    un, itn, reln, _, fb = wl.warm_started(net, test, tol, use_net=True)
+    # distance of the starts from the fixed point (network start vs eq. (11))
+    u_ref, _, _, _ = wl.solve_batch(test, 1e-12)
+    probs = wl.problems(test)
+    s = wl._bind(probs)
+    g = torch.zeros(len(test) * wl.HW, dtype=torch.float64, device="cuda")
+    s.initial_guess(g)
+    x0, _, sn = wl._net_inputs(net, len(test), wl.f_tensor(probs), g, [p.mu for p in probs])
+    out = net.forward(len(test), x0)
+    ustart = torch.empty_like(g)
+    net.warm_start_prolong(len(test), wl.r, g, sn, out, wl.mask, ustart)
+    e_net = float(torch.linalg.norm(ustart - u_ref) / torch.linalg.norm(u_ref))
+    e_s = float(torch.linalg.norm(g - u_ref) / torch.linalg.norm(u_ref))
+    print(f"[case] start error: eq. (11) {e_s:.3e}, network {e_net:.3e}; mean sweeps to {tol:g}: "
+          f"zero {it0.mean():.2f}, eq. (11) {its.mean():.2f}, network {itn.mean():.2f} (fallbacks {fb})",
+          flush=True)
+    assert np.all(rel0 <= tol) and np.all(rels <= tol) and np.all(reln <= tol)
+    assert e_net < e_s
+    assert itn.mean() < its.mean() < it0.mean()
+    net.close()
+    wl.solver.close()
