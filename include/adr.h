@@ -115,6 +115,14 @@ typedef struct {
                              own, joined back by events; in turn inside a graph capture) */
     double pivot_tol;     /* relative pivot threshold of the line solves (ADR_ESINGULAR); <= 0:
                              64 ulp of the sweep's precision (64 * 2^-52 FP64, 64 * 2^-23 FP32) */
+    int32_t splitting;    /* time steps of adr_time_step's paper scheme: 0 the order of eq. (10)
+                             (beta substep, then gamma substep); 1 symmetric: beta over dt/2,
+                             gamma over dt, beta over dt/2 */
+    int32_t stabilize;    /* beta-lines: 0 plain Galerkin (eq. (17)); 1 exponentially fitted
+                             (the paper's further work on singularly perturbed lines): element
+                             e's stiffness scaled by Pe coth(Pe), Pe = |beta|_e h_e / (2 mu),
+                             |beta|_e the mean of its nodal values; nodally exact for
+                             -mu u'' + |beta| u' = 0 with constant |beta| on a uniform line */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -213,7 +221,8 @@ adr_status adr_set_line_shapes(adr_ctx *ctx, const int32_t *shapes);
  * u: device FP64 packed, in: u_n, out: u_{n+nsteps}; dt > 0; source f and
  * Dirichlet data g included.
  *   inner_max = 0 (the paper's scheme): one splitting step of eq. (10) per time
- *     step with the given theta in (0,1], FP64.  Asynchronous.
+ *     step with the given theta in (0,1], FP64 (options.splitting = 1: the
+ *     symmetric step beta dt/2, gamma dt, beta dt/2).  Asynchronous.
  *   inner_max > 0 (splitting iterated per step): implicit Euler, theta = 1;
  *     each step (u - u_n)/dt + A u = f is solved as the stationary problem
  *     with reaction sigma + 1/dt and the beta-curves' load L + M (G u_n)/dt

@@ -16,6 +16,15 @@ elements are straight).  With hat functions phi_k:
   load       int f v dl, f taken as its P1 interpolant: L = M f   eq. (17)
 
 s_i = mu K + C + sigma M on beta-lines (eq. (17)); m_i = mu K on gamma-lines (eq. (19)).
+
+Stabilised beta-lines (exponential fitting, Il'in / Allen-Southwell; the
+paper's first item of further work, singularly perturbed lines): on element
+e the diffusion mu becomes mu phi(Pe_e), phi(Pe) = Pe coth(Pe), with the
+element Peclet number Pe_e = |beta|_e h_e / (2 mu) and |beta|_e the mean of
+the element's two nodal values.  phi -> 1 as Pe -> 0 (plain Galerkin) and
+phi ~ Pe for large Pe (the upwind diffusion |beta| h / 2).  For constant
+|beta| on a uniform line, -mu u'' + |beta| u' = 0 is then solved exactly at
+the nodes.
 The flow runs from z_0 to z_n (the tracing direction), which fixes the sign of C.
 
 All arrays here are "full-node" arrays over the concatenated nodes of every line
@@ -129,3 +138,23 @@ def thomas(lo, di, up, rhs):
     for k in range(n - 2, -1, -1):
         x[k] = dp[k] - cp[k] * x[k + 1]
     return x
+
+
+def fitted_stiffness(fam, wnode, mu):
+    """Stiffness of the exponentially fitted beta-lines: element e scaled by
+    phi(Pe_e) = Pe_e coth(Pe_e), Pe_e = |beta|_e h_e / (2 mu)."""
+    n = fam.n_nodes
+    inner = fam.interior()
+    h = chords(fam)
+    # per node k: phi of the element to its left, [z_{k-1}, z_k] (0 at line starts)
+    wl = np.zeros(n)
+    wl[1:] = 0.5 * (wnode[1:] + wnode[:-1])
+    pe = np.where(h > 0, wl * h / (2.0 * mu), 1.0)
+    phi = np.where(h > 0, pe / np.tanh(pe), 0.0)
+    z = np.zeros(n)
+    lo, di, up = z.copy(), z.copy(), z.copy()
+    idx = np.nonzero(inner)[0]
+    lo[idx] = -phi[idx] / h[idx]
+    up[idx] = -phi[idx + 1] / h[idx + 1]
+    di[idx] = -lo[idx] - up[idx]
+    return Tri(lo, di, up)

@@ -49,7 +49,8 @@ from . import transfer as tr
 class Oracle:
     """All operators of one problem instance (a workloads.Problem)."""
 
-    def __init__(self, prob, families=None):
+    def __init__(self, prob, families=None, stabilize=False):
+        """stabilize: exponentially fitted beta-lines (oracle.linefe)."""
         self.prob = prob
         self.grid = geo.Grid(prob.box, prob.nx, prob.ny)
         self.dom = geo.make_domain(prob.domain, prob.dom_params, prob.box)
@@ -76,6 +77,9 @@ class Oracle:
         self.bnorm = np.hypot(b1, b2)
         M, K, C = lfe.line_operators(fb, self.bnorm)
         self.MB, self.KB, self.CB = M, K, C
+        if stabilize:
+            K = lfe.fitted_stiffness(fb, self.bnorm, self.mu)
+            self.KB = K
         self.SB = K.scale(self.mu) + C + M.scale(self.sigma)
         fG = self.fams[1]
         self.MG, self.KG, _ = lfe.line_operators(fG, None)
@@ -179,10 +183,19 @@ class Oracle:
         return self.scatter(0, v)
 
     # -- time marching -------------------------------------------------------
-    def march(self, U0, theta, dt, steps):
+    def strang_step(self, U, theta, dt):
+        """Symmetric splitting of eq. (10): beta substep over dt/2, gamma substep
+        over dt, beta substep over dt/2 (each with the theta-scheme of eq. (7)
+        and values handed on through the grid)."""
+        Uh, _ = self.beta_substep(U, theta, dt / 2)
+        Ug, _ = self.gamma_substep(Uh, theta, dt)
+        Un, _ = self.beta_substep(Ug, theta, dt / 2)
+        return Un
+
+    def march(self, U0, theta, dt, steps, strang=False):
         U = self.with_boundary(U0)
         for _ in range(steps):
-            U = self.step(U, theta, dt)
+            U = self.strang_step(U, theta, dt) if strang else self.step(U, theta, dt)
         return U
 
     # -- implicit Euler steps iterated to convergence ---------------------------

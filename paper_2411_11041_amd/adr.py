@@ -48,7 +48,7 @@ class Options(C.Structure):
                 ("theta", C.c_double), ("dt", C.c_double),
                 ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32),
                 ("graph", C.c_int32), ("adaptive", C.c_int32), ("split_lines", C.c_int32),
-                ("pivot_tol", C.c_double)]
+                ("pivot_tol", C.c_double), ("splitting", C.c_int32), ("stabilize", C.c_int32)]
 
 
 _lib = None
@@ -152,7 +152,7 @@ class Solver:
 
     def __init__(self, problems, precision="fp64", theta=1.0, dt=0.05, fp32_sweeps=3,
                  stream=None, timing=False, host_only=False, graph=False, adaptive=False, split_lines=False,
-                 pivot_tol=0.0):
+                 pivot_tol=0.0, splitting="lie", stabilize=False):
         self.lib = load()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -164,7 +164,8 @@ class Solver:
         prec = {"fp64": PREC_FP64, "fp32": PREC_FP32_LINES}[precision]
         opt = Options(prec, int(fp32_sweeps), float(theta), float(dt),
                       C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)),
-                      int(bool(graph)), int(bool(adaptive)), int(split_lines), float(pivot_tol))
+                      int(bool(graph)), int(bool(adaptive)), int(split_lines), float(pivot_tol),
+                      {"lie": 0, "strang": 1}[splitting], int(bool(stabilize)))
         self.n = len(problems)
         self.ctx = C.c_void_p()
         st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))

@@ -25,7 +25,7 @@ namespace {
 
 thread_local std::string g_setup_error;
 
-constexpr int kSlotStep = 0, kSlotLin = 1, kSlotTime = 2, kSlotGuess = 3, kSlots = 4;
+constexpr int kSlotStep = 0, kSlotLin = 1, kSlotTime = 2, kSlotGuess = 3, kSlotHalf = 4, kSlots = 5;
 constexpr int kBlock = 256;
 constexpr int kTile = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
@@ -115,6 +115,7 @@ struct adr_ctx {
     float *d32 = nullptr, *D32 = nullptr;
     int *done = nullptr, *never = nullptr, *conv_it = nullptr;
     int *sing = nullptr;  // per instance: a line solve met a bad pivot (ADR_ESINGULAR)
+    double *fit = nullptr;  // per instance 1 / (2 mu) of the fitted beta-lines (options.stabilize)
     double last_theta = -1, last_dt = -1;
     std::vector<double> mu, sg;
     std::string err;
@@ -277,6 +278,20 @@ struct adr_ctx {
         timed(0, 2, grid_work(), [&] { return adr::launch_scatter<double, double>(0, sargs(fam[0].s64), fam[0].v64, Uh64, d32, partial, dn, st); });
         line64(1, slot, Uh64, dn);
         timed(0, 3, grid_work(), [&] { return adr::launch_scatter<double, double>(mode, sargs(fam[1].s64), fam[1].v64, U_out, d32, partial, dn, st); });
+    }
+    // One symmetric step of the march: beta substep over dt/2 (slot kSlotHalf),
+    // gamma substep over dt (kSlotTime), beta substep over dt/2, each writing
+    // the state in place (a line solve has gathered its input before its
+    // scatter runs).
+    void strang_step(double *U) {
+        for (int half = 0; half < 2; ++half) {
+            if (half == 1) {
+                line64(1, kSlotTime, U, never);
+                timed(0, 3, grid_work(), [&] { return adr::launch_scatter<double, double>(0, sargs(fam[1].s64), fam[1].v64, U, d32, partial, never, st); });
+            }
+            line64(0, kSlotHalf, U, never);
+            timed(0, 2, grid_work(), [&] { return adr::launch_scatter<double, double>(0, sargs(fam[0].s64), fam[0].v64, U, d32, partial, never, st); });
+        }
     }
     // One FP32 increment sweep: d32 <- T d32, U += d32.
     void sweep32(double *U, const int *dn) {
@@ -479,6 +494,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         if (!(opt->dt > 0.0) || !std::isfinite(opt->dt)) throw Error{ADR_EINVAL, "dt must be > 0"};
         if (opt->precision != ADR_PREC_FP64 && opt->precision != ADR_PREC_FP32_LINES)
             throw Error{ADR_EINVAL, "unknown precision"};
+        if (opt->splitting != 0 && opt->splitting != 1) throw Error{ADR_EINVAL, "splitting must be 0 or 1"};
+        if (opt->stabilize != 0 && opt->stabilize != 1) throw Error{ADR_EINVAL, "stabilize must be 0 or 1"};
         if (opt->fp32_sweeps < 0) throw Error{ADR_EINVAL, "fp32_sweeps must be >= 0"};
         C->opt = *opt;
         C->n_inst = n_probs;
@@ -580,6 +597,11 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         for (int i = 0; i < n; ++i) any_g = any_g || probs[i].g != nullptr;
         C->sing = dalloc<int>(n, own);
         HIPCHK(hipMemsetAsync(C->sing, 0, sizeof(int) * n, st));
+        if (opt->stabilize) {
+            std::vector<double> fit(n);
+            for (int i = 0; i < n; ++i) fit[i] = 0.5 / probs[i].mu;
+            C->fit = upload(fit, own, st);
+        }
 
         // scatter slots, padded per instance to whole blocks
         std::vector<int> blk_start(n + 1, 0);
@@ -734,6 +756,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             F.a64.sing = C->sing;
             F.a32.sing = C->sing;
             F.a64.ptol = opt->pivot_tol > 0.0 ? opt->pivot_tol : 64.0 * 2.220446049250313e-16;
+            F.a64.fit = f == 0 ? C->fit : nullptr;
+            F.a32.fit = f == 0 ? C->fit : nullptr;
             F.a32.ptol = opt->pivot_tol > 0.0 ? opt->pivot_tol : 64.0 * 1.1920928955078125e-07;
             // scatter records
             std::vector<int> rk(4 * static_cast<size_t>(npad), -1);
@@ -926,6 +950,11 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs) {
         for (int i = 0; i < n; ++i) {
             ctx->mu[i] = probs[i].mu;
             ctx->sg[i] = probs[i].sigma;
+        }
+        if (ctx->fit) {
+            std::vector<double> fit(n);
+            for (int i = 0; i < n; ++i) fit[i] = 0.5 / probs[i].mu;
+            HIPCHK(hipMemcpy(ctx->fit, fit.data(), sizeof(double) * n, hipMemcpyHostToDevice));
         }
         fill_params(ctx->par_h, n, kSlotStep, ctx->mu, ctx->sg, ctx->opt.theta, ctx->opt.dt);
         fill_params(ctx->par_h, n, kSlotLin, ctx->mu, ctx->sg, ctx->opt.theta, ctx->opt.dt);
@@ -1289,14 +1318,20 @@ adr_status adr_time_step(adr_ctx *ctx, double *u, double theta, double dt, int32
     try {
         if (theta != ctx->last_theta || dt != ctx->last_dt) {
             fill_params(ctx->par_h, ctx->n_inst, kSlotTime, ctx->mu, ctx->sg, theta, dt);
-            HIPCHK(hipMemcpy(ctx->par + static_cast<size_t>(kSlotTime) * 2 * ctx->n_inst * 8,
-                             ctx->par_h.data() + static_cast<size_t>(kSlotTime) * 2 * ctx->n_inst * 8,
-                             sizeof(double) * 2 * ctx->n_inst * 8, hipMemcpyHostToDevice));
+            fill_params(ctx->par_h, ctx->n_inst, kSlotHalf, ctx->mu, ctx->sg, theta, 0.5 * dt);
+            for (int slot : {kSlotTime, kSlotHalf})
+                HIPCHK(hipMemcpy(ctx->par + static_cast<size_t>(slot) * 2 * ctx->n_inst * 8,
+                                 ctx->par_h.data() + static_cast<size_t>(slot) * 2 * ctx->n_inst * 8,
+                                 sizeof(double) * 2 * ctx->n_inst * 8, hipMemcpyHostToDevice));
             ctx->last_theta = theta;
             ctx->last_dt = dt;
         }
         ctx->to_blocked(u);
-        for (int s = 0; s < nsteps; ++s) ctx->sweep64(kSlotTime, ctx->Ub, ctx->Ub, 0, ctx->never);
+        if (ctx->opt.splitting == 1) {
+            for (int s = 0; s < nsteps; ++s) ctx->strang_step(ctx->Ub);
+        } else {
+            for (int s = 0; s < nsteps; ++s) ctx->sweep64(kSlotTime, ctx->Ub, ctx->Ub, 0, ctx->never);
+        }
         ctx->from_blocked(u);
         return ADR_OK;
     } catch (const Error &e) {

@@ -22,6 +22,8 @@ struct LineArgs {
     const T *gend;       // optional: per line the Dirichlet values at its two ends (2 per line); NULL: zero
     int *sing;           // optional: per instance, set to 1 when a pivot is not finite or below ptol
     double ptol;         // relative pivot threshold (of |diagonal| + |eliminated part|)
+    const double *fit;   // optional (beta family): per instance 1 / (2 mu) of the exponentially
+                         // fitted stiffness; NULL: plain Galerkin rows
 };
 
 // Record indices relative to the slot's first record (ScatterArgs::rd)

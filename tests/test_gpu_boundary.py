@@ -205,3 +205,62 @@ def test_converged_time_steps_fp32_lines():
     Uo, cnt = o.march_converged(u0, 0.005, 3, 0.05, 1e-12, 500)
     assert rel_l2(u.cpu().numpy(), Uo, o.inner_idx) < 1e-5
     s.close()
+
+
+@pytest.mark.parametrize("name,theta,dt,steps", [("data2d_61", 0.5, 0.001, 30), ("c3_129", 1.0, 0.005, 10)])
+def test_strang_march_matches_oracle(name, theta, dt, steps):
+    """The symmetric splitting (beta dt/2, gamma dt, beta dt/2), FP64, step by step."""
+    print(f"[case] strang march {name} theta={theta} {steps} steps", flush=True)
+    p = W.data2d(61) if name.startswith("data2d") else with_g(W.c3(129))
+    o = Oracle(p)
+    s = solver(p, precision="fp64", splitting="strang")
+    U0 = o.s_guess() if name.startswith("data2d") else o.with_boundary(p.u0.ravel() * o.mask.ravel())
+    u = dev(U0)
+    s.time_step(u, theta, dt, steps)
+    torch.cuda.synchronize()
+    U = o.march(U0, theta, dt, steps, strang=True)
+    assert rel_l2(u.cpu().numpy(), U, o.inner_idx) < 1e-11
+    # the order-of-eq.-(10) march of the same context differs (a different scheme)
+    v = dev(U0)
+    lie = solver(p, precision="fp64")
+    lie.time_step(v, theta, dt, steps)
+    torch.cuda.synchronize()
+    assert rel_l2(v.cpu().numpy(), U, o.inner_idx) > 1e-6
+    s.close()
+    lie.close()
+
+
+def test_fitted_lines_match_oracle():
+    """Exponentially fitted beta-lines (options.stabilize): FP64 sweeps and the
+    eq. (11) s-solve of an advection-dominated batch (a coarse high-Peclet box
+    and a disc with mu ~ 1e-4), and the FP32-lines fixed point."""
+    print("[case] fitted beta-lines vs oracle", flush=True)
+    box = W.constant_beta(33, 2e-4, 1.0, (1.0, 0.4), f=1.0)
+    disc = W.c4_instance(0, n_max=70)
+    probs = [box, disc]
+    orcs = [Oracle(p, stabilize=True) for p in probs]
+    s = solver(probs, precision="fp64", theta=1.0, dt=0.05, stabilize=True)
+    off = s.layout()
+    u = dev(np.concatenate([o.zero_field() for o in orcs]))
+    s.split_iterate(u, 5, 0.0)
+    g = dev(np.concatenate([o.zero_field() for o in orcs]))
+    s.initial_guess(g)
+    torch.cuda.synchronize()
+    got, gg = u.cpu().numpy(), g.cpu().numpy()
+    for i, o in enumerate(orcs):
+        U = o.zero_field()
+        for _ in range(5):
+            U = o.step(U, 1.0, 0.05)
+        assert rel_l2(got[off[i]:off[i + 1]], U, o.inner_idx) < 1e-11, i
+        assert rel_l2(gg[off[i]:off[i + 1]], o.s_guess(), o.inner_idx) < 1e-12, i
+    assert gg[off[0]:off[1]][orcs[0].inner_idx].min() >= 0.0  # no undershoot (Galerkin: < -0.1)
+    s.close()
+    s = solver(probs, precision="fp32", fp32_sweeps=3, theta=1.0, dt=0.05, stabilize=True)
+    u = dev(np.concatenate([o.zero_field() for o in orcs]))
+    it, rel, st = s.split_iterate(u, 3000, 1e-10)
+    assert st == 0
+    got = u.cpu().numpy()
+    for i, o in enumerate(orcs):
+        Uo, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-12)
+        assert rel_l2(got[off[i]:off[i + 1]], Uo, o.inner_idx) < 1e-5, i
+    s.close()

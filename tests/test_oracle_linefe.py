@@ -11,6 +11,7 @@ from scipy.linalg import solve_banded
 
 from oracle import geometry as geo
 from oracle import linefe as lfe
+import workloads as W
 
 
 def straight_family(ls_list, direction=(0.6, 0.8), origin=(0.1, 0.2)):
@@ -182,3 +183,44 @@ def test_solve_lines_is_independent_per_line():
         ref = lfe.thomas(A.lo[a + 1:b - 1], A.di[a + 1:b - 1], A.up[a + 1:b - 1], rhs[a + 1:b - 1])
         assert np.max(np.abs(u[a + 1:b - 1] - ref)) < 1e-13
         assert u[a] == 0.0 and u[b - 1] == 0.0
+
+
+def test_exponential_fitting_is_nodally_exact():
+    """Il'in / Allen-Southwell: with mu phi(Pe) on each element, -mu u'' + c u' = 0,
+    u(0) = 0, u(1) = 1 on a uniform mesh has the nodal values of the exact
+    solution (e^{c x / mu} - 1) / (e^{c / mu} - 1), at any mesh Peclet number
+    (plain Galerkin oscillates for Pe > 1); as mu grows it tends to Galerkin."""
+    N = 20
+    ls = np.linspace(0.0, 1.0, N + 1)
+    fam = straight_family([ls])
+    for mu, c in ((0.05, 1.0), (0.004, 1.0), (0.3, 2.5)):
+        w = np.full(N + 1, c)
+        _, _, C = lfe.line_operators(fam, w)
+        K = lfe.fitted_stiffness(fam, w, mu)
+        ends = np.zeros(N + 1); ends[-1] = 1.0
+        u = lfe.solve_lines(K.scale(mu) + C, np.zeros(N + 1), fam.interior(), ends)
+        x = ls
+        ref = np.expm1(c * x / mu) / np.expm1(c / mu)
+        assert np.max(np.abs(u - ref)) < 1e-12, mu
+    # small Peclet: the fitted stiffness approaches the plain one
+    w = np.full(N + 1, 1e-6)
+    _, K0, _ = lfe.line_operators(fam, None)
+    Kf = lfe.fitted_stiffness(fam, w, 1.0)
+    inner = fam.interior()
+    assert np.max(np.abs(Kf.di[inner] - K0.di[inner])) < 1e-9 * np.max(np.abs(K0.di[inner]))
+
+
+def test_fitted_lines_keep_the_solution_free_of_undershoot():
+    """A coarse advection-dominated instance (mesh Peclet ~ 10^2) with a
+    non-negative source and zero Dirichlet data: the eq. (11) s-solve, whose
+    line systems carry no mass term, oscillates with plain Galerkin lines
+    (negative values at the outflow layers), and stays non-negative and below
+    the reaction bound f / sigma = 1 with the fitted ones."""
+    from oracle.method import Oracle
+    p = W.constant_beta(33, 2e-4, 1.0, (1.0, 0.4), f=1.0)
+    s0 = Oracle(p).s_guess()
+    o = Oracle(p, stabilize=True)
+    s1 = o.s_guess()
+    m = o.inner_idx
+    assert s0[m].min() < -0.1
+    assert s1[m].min() >= 0.0 and s1[m].max() < 1.0

@@ -259,3 +259,24 @@ def test_implicit_step_limits_and_exactness():
     assert np.linalg.norm(Us[ii] - ud) / np.linalg.norm(ud) < 1e-11
     # a reaction-dominated step converges in few sweeps
     assert it < 60
+
+
+@pytest.mark.parametrize("theta", [1.0, 0.5])
+def test_strang_step_keeps_the_affine_stationary_solution(theta):
+    """Every substep maps the affine stationary solution (g = u on Gamma) to
+    itself when its operator and its load are scaled by the same step, so
+    the symmetric step beta(dt/2) gamma(dt) beta(dt/2) does too; a half step
+    that took the full step's load (or the reverse) moves it."""
+    p, u = _affine_problem("disc", 25, (0.6, -1.1))
+    o = Oracle(p)
+    m = o.inner_idx
+    U = o.strang_step(u, theta, 0.05)
+    assert np.max(np.abs(U[m] - u[m])) < 1e-12
+    # the half step is a step of its own length: two of them are not one full step
+    Uh = o.beta_substep(u + 0.0, theta, 0.025)[0]
+    assert np.max(np.abs(Uh[m] - u[m])) < 1e-12
+    X, Y = p.coords()
+    w = o.with_boundary((np.sin(3 * X) * Y).ravel())
+    a = o.beta_substep(o.beta_substep(w, theta, 0.025)[0], theta, 0.025)[0]
+    b = o.beta_substep(w, theta, 0.05)[0]
+    assert np.max(np.abs(a[m] - b[m])) > 1e-6  # a half step is not a no-op or a full step
