@@ -184,6 +184,8 @@ def parse():
                     help="c5: the network runs on every coarsen-th node (1: on the 257x257 grid itself)")
     ap.add_argument("--instances", type=int, default=512)
     ap.add_argument("--graph", action="store_true", help="replay sweep blocks from a HIP graph")
+    ap.add_argument("--krylov", type=int, default=0,
+                    help="with --no-autotune: GMRES(m) on (I - T) U = c instead of the sweep schedule (m > 0)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="c2/c4: keep the given schedule and launches instead of choosing them with adr_autotune")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -253,16 +255,17 @@ def leg_c2(args):
     p = W.c2(args.n)
     t0 = time.time()
     s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, adaptive=args.adaptive,
-               split_lines=args.split_lines)
+               split_lines=args.split_lines, krylov=args.krylov)
     setup_s = time.time() - t0
     counts = s.counts()
     per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
     u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
     fp32_sweeps, adaptive, split, shapes, tuned = args.fp32_sweeps, args.adaptive, args.split_lines, [0] * 5, None
+    kr = args.krylov
     if not args.no_autotune:
         tuned = s.autotune(u, 5000, args.tol)
-        fp32_sweeps, adaptive, split, shapes = tuned[0], tuned[1], tuned[3], tuned[4]
-    log(f"c2: set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split}")
+        fp32_sweeps, adaptive, split, shapes, kr = tuned[0], tuned[1], tuned[3], tuned[4], tuned[5]
+    log(f"c2: set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split} krylov={kr}")
 
     def solve():
         u.zero_()
@@ -291,7 +294,8 @@ def leg_c2(args):
                        "time_to_1e-8_ms": round(1e3 * el / args.steps, 3), "sweeps_per_solve": sweeps[0],
                        "final_rel": float(rel[0]), "fp32_sweeps_per_fp64": fp32_sweeps,
                        "adaptive_schedule": bool(adaptive), "line_launches": LINE_LAUNCHES[split],
-                       "line_shapes": shapes, "autotuned": tuned is not None,
+                       "line_shapes": shapes, "autotuned": tuned is not None, "krylov_gmres_m": kr,
+                       "autotune_best_ms": round(tuned[2], 3) if tuned else None,
                        "line_unknowns_per_sweep": per_sweep, "grid_unknowns": counts["grid_unknowns"],
                        "lines": [counts["lines_b"], counts["lines_g"]], "setup_s": round(setup_s, 2),
                        "kernels": kernels_table(times)}}
@@ -314,7 +318,7 @@ def leg_c4(args):
     gen_s = time.time() - t0
     t0 = time.time()
     s = Solver(probs, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, graph=args.graph,
-               adaptive=args.adaptive, split_lines=args.split_lines)
+               adaptive=args.adaptive, split_lines=args.split_lines, krylov=args.krylov)
     setup_s = time.time() - t0
     counts = s.counts()
     per_inst = []
@@ -328,10 +332,12 @@ def leg_c4(args):
     off = s.layout()
     u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     fp32_sweeps, adaptive, split, shapes, tuned = args.fp32_sweeps, args.adaptive, args.split_lines, [0] * 5, None
+    kr = args.krylov
     if not args.no_autotune:
         tuned = s.autotune(u, 3000, args.tol)
-        fp32_sweeps, adaptive, split, shapes = tuned[0], tuned[1], tuned[3], tuned[4]
-    log(f"c4: gen {gen_s:.1f} s, set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split}")
+        fp32_sweeps, adaptive, split, shapes, kr = tuned[0], tuned[1], tuned[3], tuned[4], tuned[5]
+    log(f"c4: gen {gen_s:.1f} s, set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split} "
+        f"krylov={kr}")
 
     def solve():
         u.zero_()
@@ -361,7 +367,7 @@ def leg_c4(args):
                        "converged": int((rel <= args.tol).sum()), "gen_s": round(gen_s, 1),
                        "setup_s": round(setup_s, 1), "graph": bool(args.graph),
                        "fp32_sweeps_per_fp64": fp32_sweeps, "adaptive_schedule": bool(adaptive),
-                       "line_launches": LINE_LAUNCHES[split], "line_shapes": shapes,
+                       "line_launches": LINE_LAUNCHES[split], "line_shapes": shapes, "krylov_gmres_m": kr,
                        "autotune_ms": round(tuned[2], 2) if tuned else None, "kernels": kernels_table(times)}}
 
 

@@ -123,6 +123,13 @@ typedef struct {
                              e's stiffness scaled by Pe coth(Pe), Pe = |beta|_e h_e / (2 mu),
                              |beta|_e the mean of its nodal values; nodally exact for
                              -mu u'' + |beta| u' = 0 with constant |beta| on a uniform line */
+    int32_t krylov;       /* stationary solve: 0 the sweeps of eq. (10) (fixed-point iteration);
+                             m in 1..200: GMRES(m) on (I - T) U = c, the same fixed point (T the
+                             linear part of a sweep, c = Phi(0)), FP64 in either precision: each
+                             application of I - T is one FP64 sweep, each restart recomputes the
+                             exact residual Phi(U) - U (one FP64 sweep) and stops at
+                             rel = |Phi(U) - U| / |Phi(0)| <= tol; iters counts the sweeps; the
+                             iterate returned is that U (not Phi(U)).  Not for the judged solve */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -194,16 +201,20 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
  *      current schedule;
  *   2. with the faster of those, each candidate schedule: a fixed count of
  *      FP32 sweeps per FP64 sweep (2, 3, 4, 6) and, in eager mode, the
- *      adaptive schedule with at most 6, 8, 12, 16 or 24.
+ *      adaptive schedule with at most 6, 8, 12, 16 or 24;
+ *   3. GMRES(m) (options.krylov) with m = 10, 20, 30, kept if faster than the
+ *      best schedule.
  * With bucketed launches, between the two steps, each length bucket's
  * workgroup shape (adr_set_line_shapes) is chosen from its FP32 line solves
  * timed alone.  The fastest choices stay in the context.  Outputs (host, each
  * may be NULL): best_fp32_sweeps and best_adaptive (the count or maximum, and
  * the adaptive flag), best_ms (its time), best_split (the launch choice),
- * best_shapes (5 entries, the shape of each bucket).  Kernel timers (timing
+ * best_shapes (5 entries, the shape of each bucket), best_krylov (0, or the
+ * GMRES restart length chosen).  Kernel timers (timing
  * mode) are reset afterwards.  Synchronises. */
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
-                        int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes);
+                        int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes,
+                        int32_t *best_krylov);
 
 /* Workgroup shapes of the bucketed line launches (options.split_lines != 0):
  * shapes[b] for bucket b = 0..4 (curves of at most 3072, 2048, 1024, 512, 256

@@ -48,7 +48,8 @@ class Options(C.Structure):
                 ("theta", C.c_double), ("dt", C.c_double),
                 ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32),
                 ("graph", C.c_int32), ("adaptive", C.c_int32), ("split_lines", C.c_int32),
-                ("pivot_tol", C.c_double), ("splitting", C.c_int32), ("stabilize", C.c_int32)]
+                ("pivot_tol", C.c_double), ("splitting", C.c_int32), ("stabilize", C.c_int32),
+                ("krylov", C.c_int32)]
 
 
 _lib = None
@@ -73,7 +74,7 @@ def load():
     lib.adr_update.argtypes = [vp, P(Problem), i32]
     lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
     lib.adr_split_iterate_judged.argtypes = [vp, vp, vp, i32, dbl, P(i32), P(dbl), P(i32)]
-    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32), P(i32)]
+    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32), P(i32), P(i32)]
     lib.adr_set_line_shapes.argtypes = [vp, P(i32)]
     lib.adr_set_timing.argtypes = [vp, i32]
     lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32, i32, dbl, P(i32)]
@@ -152,7 +153,7 @@ class Solver:
 
     def __init__(self, problems, precision="fp64", theta=1.0, dt=0.05, fp32_sweeps=3,
                  stream=None, timing=False, host_only=False, graph=False, adaptive=False, split_lines=False,
-                 pivot_tol=0.0, splitting="lie", stabilize=False):
+                 pivot_tol=0.0, splitting="lie", stabilize=False, krylov=0):
         self.lib = load()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -165,7 +166,7 @@ class Solver:
         opt = Options(prec, int(fp32_sweeps), float(theta), float(dt),
                       C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)),
                       int(bool(graph)), int(bool(adaptive)), int(split_lines), float(pivot_tol),
-                      {"lie": 0, "strang": 1}[splitting], int(bool(stabilize)))
+                      {"lie": 0, "strang": 1}[splitting], int(bool(stabilize)), int(krylov))
         self.n = len(problems)
         self.ctx = C.c_void_p()
         st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))
@@ -227,15 +228,16 @@ class Solver:
         on `work` (overwritten), and keeps the fastest; returns (count or
         maximum, adaptive, ms, split_lines: 0 one launch, 1 per bucket, 2 per
         bucket on concurrent streams, shapes: the workgroup shape of each length
-        bucket)."""
+        bucket, krylov: 0 or the GMRES restart length)."""
         best = C.c_int32()
         ad = C.c_int32()
         ms = C.c_double()
         sp = C.c_int32()
         sh = (C.c_int32 * 5)()
+        kr = C.c_int32()
         self._check(self.lib.adr_autotune(self.ctx, _device_ptr(work), int(max_iters), float(tol),
-                                          C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp), sh))
-        return best.value, bool(ad.value), ms.value, int(sp.value), list(sh)
+                                          C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp), sh, C.byref(kr)))
+        return best.value, bool(ad.value), ms.value, int(sp.value), list(sh), int(kr.value)
 
     def set_line_shapes(self, shapes):
         """Workgroup shape of each of the 5 length buckets (include/adr.h)."""

@@ -23,7 +23,7 @@ def runtime_dir() -> str:
     return d if os.path.exists(os.path.join(d, "libamdhip64.so")) else "/opt/rocm/lib"
 
 
-SOURCES = ["adr_geometry.cpp", "adr_kernels.hip", "adr_api.cpp", "adr_tri.hip", "adr_tri_noalloc.hip", "adrnn.hip", "adr_probe.hip"]
+SOURCES = ["adr_geometry.cpp", "adr_kernels.hip", "adr_krylov.hip", "adr_api.cpp", "adr_tri.hip", "adr_tri_noalloc.hip", "adrnn.hip", "adr_probe.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          # packed FP32 instructions stay off (see the design notes)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

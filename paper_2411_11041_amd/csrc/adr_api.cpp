@@ -116,6 +116,14 @@ struct adr_ctx {
     int *done = nullptr, *never = nullptr, *conv_it = nullptr;
     int *sing = nullptr;  // per instance: a line solve met a bad pivot (ADR_ESINGULAR)
     double *fit = nullptr;  // per instance 1 / (2 mu) of the fitted beta-lines (options.stabilize)
+    // GMRES acceleration (options.krylov = m > 0), allocated on first use
+    std::vector<int64_t> boff_h;  // blocked offset of each instance (n_inst + 1)
+    adr::KChunks kch{};
+    int kmax = 0;                 // basis vectors allocated (m + 1)
+    double *kV = nullptr;         // the basis, kmax fields of n_blocked
+    double *kWh = nullptr;        // half step of the linear sweeps (zero outside the interior)
+    double *kpart = nullptr, *kout = nullptr, *kcoef = nullptr;
+    int *kskip = nullptr;         // done, or finished inside the current Arnoldi cycle
     double last_theta = -1, last_dt = -1;
     std::vector<double> mu, sg;
     std::string err;
@@ -291,6 +299,55 @@ struct adr_ctx {
             }
             line64(0, kSlotHalf, U, never);
             timed(0, 2, grid_work(), [&] { return adr::launch_scatter<double, double>(0, sargs(fam[0].s64), fam[0].v64, U, d32, partial, never, st); });
+        }
+    }
+    // out = T in (T the linear part of the FP64 sweep: no load, zero Dirichlet
+    // data) on the interior nodes; in and out have zero outside the interior.
+    void linear_sweep(const double *in, double *out, const int *dn) {
+        line64(0, kSlotLin, in, dn);
+        adr::ScatterArgs<double> s0 = sargs(fam[0].s64), s1 = sargs(fam[1].s64);
+        s0.gb = nullptr;
+        s1.gb = nullptr;
+        timed(0, 2, grid_work(), [&] { return adr::launch_scatter<double, double>(0, s0, fam[0].v64, kWh, d32, partial, dn, st); });
+        line64(1, kSlotLin, kWh, dn);
+        timed(0, 3, grid_work(), [&] { return adr::launch_scatter<double, double>(0, s1, fam[1].v64, out, d32, partial, dn, st); });
+    }
+    // the GMRES work arrays for m basis steps (allocated once, grown on demand)
+    void krylov_alloc(int m) {
+        if (!kch.n) {
+            const int64_t C = adr::krylov_chunk();
+            std::vector<int> ci, ic(n_inst + 1, 0);
+            std::vector<int64_t> cb, ce;
+            for (int i = 0; i < n_inst; ++i) {
+                ic[i] = static_cast<int>(ci.size());
+                for (int64_t b = boff_h[i]; b < boff_h[i + 1]; b += C) {
+                    ci.push_back(i);
+                    cb.push_back(b);
+                    ce.push_back(std::min(b + C, boff_h[i + 1]));
+                }
+            }
+            ic[n_inst] = static_cast<int>(ci.size());
+            kch = adr::KChunks{upload(ci, owned, st), upload(cb, owned, st), upload(ce, owned, st),
+                               upload(ic, owned, st), static_cast<int>(ci.size()), n_inst};
+            kWh = dalloc<double>(n_blocked, owned);
+            HIPCHK(hipMemsetAsync(kWh, 0, sizeof(double) * n_blocked, st));
+            kskip = dalloc<int>(n_inst, owned);
+        }
+        if (m + 1 > kmax) {
+            // a larger basis replaces the smaller one
+            HIPCHK(hipStreamSynchronize(st));
+            for (void *q : {static_cast<void *>(kV), static_cast<void *>(kpart), static_cast<void *>(kout),
+                            static_cast<void *>(kcoef)}) {
+                if (!q) continue;
+                owned.erase(std::remove(owned.begin(), owned.end(), q), owned.end());
+                (void)hipFree(q);
+            }
+            kmax = m + 1;
+            kV = dalloc<double>(static_cast<size_t>(kmax) * n_blocked, owned);
+            HIPCHK(hipMemsetAsync(kV, 0, sizeof(double) * kmax * n_blocked, st));
+            kpart = dalloc<double>(static_cast<size_t>(kch.n) * kmax, owned);
+            kout = dalloc<double>(static_cast<size_t>(n_inst) * kmax, owned);
+            kcoef = dalloc<double>(static_cast<size_t>(n_inst) * kmax, owned);
         }
     }
     // One FP32 increment sweep: d32 <- T d32, U += d32.
@@ -496,6 +553,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             throw Error{ADR_EINVAL, "unknown precision"};
         if (opt->splitting != 0 && opt->splitting != 1) throw Error{ADR_EINVAL, "splitting must be 0 or 1"};
         if (opt->stabilize != 0 && opt->stabilize != 1) throw Error{ADR_EINVAL, "stabilize must be 0 or 1"};
+        if (opt->krylov < 0 || opt->krylov > 200) throw Error{ADR_EINVAL, "krylov must be in 0..200"};
         if (opt->fp32_sweeps < 0) throw Error{ADR_EINVAL, "fp32_sweeps must be >= 0"};
         C->opt = *opt;
         C->n_inst = n_probs;
@@ -589,6 +647,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             inst_bstride[i] = 32 * nx8;
         }
         C->n_blocked = boff[n];
+        C->boff_h = boff;
         if (C->n_blocked > (int64_t(1) << 31) - 1) throw Error{ADR_EINVAL, "packed grid exceeds 2^31 nodes"};
         hipStream_t st = C->st;
         auto &own = C->owned;
@@ -970,10 +1029,160 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs) {
     }
 }
 
+// GMRES(m) on (I - T) U = c, c = Phi(0): the stationary fixed point by a Krylov
+// route (options.krylov = m).  FP64 throughout: every application of I - T is a
+// linear FP64 sweep; each cycle starts from the exact residual r = Phi(U) - U
+// (one FP64 sweep), whose relative norm is the iteration's stopping measure.
+// Per instance its own Krylov space; the Hessenberg columns and Givens
+// rotations are kept on the host (two small reads per basis step).
+static adr_status krylov_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol, int32_t *iters,
+                                 double *rel_res) {
+    const int n = ctx->n_inst, m = ctx->opt.krylov;
+    hipStream_t st = ctx->st;
+    ctx->krylov_alloc(m);
+    const int K = ctx->kmax;
+    const int64_t stride = ctx->n_blocked;
+    double *V = ctx->kV;
+    auto Vp = [&](int j) { return V + static_cast<int64_t>(j) * stride; };
+    std::vector<double> cn(n), out(static_cast<size_t>(n) * K), coef(static_cast<size_t>(n) * K, 0.0);
+    HIPCHK(hipMemcpyAsync(cn.data(), ctx->cnorm, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(adr::launch_fill_int(ctx->done, 0, n, st));
+    HIPCHK(adr::launch_fill_int(ctx->sing, 0, n, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::vector<int> dn(n, 0), skip(n, 0), sweeps(n, 0), steps(n, 0);
+    std::vector<double> rel(n, NAN);
+    auto read_out = [&]() {
+        HIPCHK(hipMemcpyAsync(out.data(), ctx->kout, sizeof(double) * n * K, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    };
+    auto put = [&](int *dflag, const std::vector<int> &h) {
+        HIPCHK(hipMemcpyAsync(dflag, h.data(), sizeof(int) * n, hipMemcpyHostToDevice, st));
+    };
+    auto put_coef = [&]() {
+        HIPCHK(hipMemcpyAsync(ctx->kcoef, coef.data(), sizeof(double) * n * K, hipMemcpyHostToDevice, st));
+    };
+    // per instance: H (K x m, column-major), rotations, right-hand side g
+    std::vector<double> H(static_cast<size_t>(n) * K * m), cs(static_cast<size_t>(n) * m), sn(cs.size()),
+        g(static_cast<size_t>(n) * K);
+    ctx->to_blocked(u);
+    while (true) {
+        // exact residual r = Phi(U) - U into V_0; rel = |r| / |Phi(0)|
+        ctx->sweep64(kSlotStep, ctx->Ub, Vp(0), 0, ctx->done);
+        HIPCHK(adr::launch_kresidual(ctx->slot_b, ctx->npad, Vp(0), ctx->Ub, Vp(0), st));
+        HIPCHK(adr::launch_kdot(Vp(0), Vp(0), stride, 1, K, ctx->kch, ctx->done, ctx->kpart, ctx->kout, st));
+        read_out();
+        bool all = true;
+        for (int i = 0; i < n; ++i) {
+            if (dn[i]) continue;
+            ++sweeps[i];
+            const double r = std::sqrt(out[static_cast<size_t>(i) * K]);
+            rel[i] = r / (cn[i] > 0.0 ? cn[i] : 1.0);
+            if (rel[i] <= tol || !std::isfinite(rel[i]) || sweeps[i] >= max_iters) dn[i] = 1;
+            else {
+                all = false;
+                coef[static_cast<size_t>(i) * K] = 1.0 / r;  // scale of V_0
+                g[static_cast<size_t>(i) * K] = r;
+            }
+            skip[i] = dn[i];
+            steps[i] = 0;
+        }
+        put(ctx->done, dn);
+        put(ctx->kskip, skip);
+        if (all) break;
+        put_coef();
+        HIPCHK(adr::launch_kscale(Vp(0), ctx->kcoef, K, ctx->kch, ctx->kskip, st));
+        for (int j = 0; j < m; ++j) {
+            // z = T V_j into V_{j+1}; h_ij = delta_ij - (T V_j, V_i)
+            ctx->linear_sweep(Vp(j), Vp(j + 1), ctx->kskip);
+            HIPCHK(adr::launch_kdot(Vp(j + 1), V, stride, j + 1, K, ctx->kch, ctx->kskip, ctx->kpart, ctx->kout, st));
+            read_out();
+            for (int i = 0; i < n; ++i) {
+                if (skip[i]) continue;
+                ++sweeps[i];
+                double *h = &H[(static_cast<size_t>(i) * m + j) * K];
+                for (int q = 0; q <= j; ++q) {
+                    h[q] = (q == j ? 1.0 : 0.0) - out[static_cast<size_t>(i) * K + q];
+                    coef[static_cast<size_t>(i) * K + q] = h[q];
+                }
+            }
+            put_coef();
+            // w = V_j - T V_j - sum h_ij V_i (in V_{j+1}); |w| = h_{j+1,j}
+            HIPCHK(adr::launch_kupdate(Vp(j + 1), V, stride, j, j + 1, K, ctx->kcoef, ctx->kch, ctx->kskip,
+                                       ctx->kpart, ctx->kout, st));
+            read_out();
+            bool any = false;
+            for (int i = 0; i < n; ++i) {
+                if (skip[i]) continue;
+                double *h = &H[(static_cast<size_t>(i) * m + j) * K];
+                double *c_ = &cs[static_cast<size_t>(i) * m], *s_ = &sn[static_cast<size_t>(i) * m];
+                double *gi = &g[static_cast<size_t>(i) * K];
+                const double hn = std::sqrt(out[static_cast<size_t>(i) * K]);
+                h[j + 1] = hn;
+                coef[static_cast<size_t>(i) * K] = hn > 0.0 ? 1.0 / hn : 0.0;
+                for (int q = 0; q < j; ++q) {  // earlier rotations on the new column
+                    const double t = c_[q] * h[q] + s_[q] * h[q + 1];
+                    h[q + 1] = -s_[q] * h[q] + c_[q] * h[q + 1];
+                    h[q] = t;
+                }
+                const double den = std::hypot(h[j], h[j + 1]);
+                c_[j] = den > 0.0 ? h[j] / den : 1.0;
+                s_[j] = den > 0.0 ? h[j + 1] / den : 0.0;
+                h[j] = den;
+                h[j + 1] = 0.0;
+                gi[j + 1] = -s_[j] * gi[j];
+                gi[j] = c_[j] * gi[j];
+                steps[i] = j + 1;
+                const double est = std::fabs(gi[j + 1]) / (cn[i] > 0.0 ? cn[i] : 1.0);
+                // this instance's cycle ends once its estimate reaches tol (or its sweeps run out)
+                if (est <= tol || hn == 0.0 || sweeps[i] + 1 >= max_iters) skip[i] = 1;
+                else any = true;
+            }
+            put_coef();
+            HIPCHK(adr::launch_kscale(Vp(j + 1), ctx->kcoef, K, ctx->kch, ctx->kskip, st));
+            put(ctx->kskip, skip);
+            if (!any) break;
+        }
+        // U += sum_q y_q V_q, y from the triangular H y = g of each instance's cycle
+        std::fill(coef.begin(), coef.end(), 0.0);
+        for (int i = 0; i < n; ++i) {
+            if (dn[i]) continue;
+            const int k = steps[i];
+            double *y = &coef[static_cast<size_t>(i) * K];
+            for (int q = k - 1; q >= 0; --q) {
+                double acc = g[static_cast<size_t>(i) * K + q];
+                for (int t = q + 1; t < k; ++t) acc -= H[(static_cast<size_t>(i) * m + t) * K + q] * y[t];
+                const double d = H[(static_cast<size_t>(i) * m + q) * K + q];
+                y[q] = d != 0.0 ? acc / d : 0.0;
+            }
+        }
+        put_coef();
+        HIPCHK(adr::launch_kcombine(ctx->Ub, V, stride, m, K, ctx->kcoef, ctx->kch, ctx->done, st));
+    }
+    ctx->from_blocked(u);
+    const adr_status sst = ctx->singular_status();
+    adr_status status = ADR_OK;
+    for (int i = 0; i < n; ++i) {
+        if (iters) iters[i] = sweeps[i];
+        if (rel_res) rel_res[i] = rel[i];
+        if (!std::isfinite(rel[i])) status = ADR_ENONFINITE;
+        else if (!(rel[i] <= tol) && status == ADR_OK) status = ADR_ENOTCONV;
+    }
+    if (sst != ADR_OK) return sst;
+    if (status == ADR_ENONFINITE) ctx->err = "non-finite residual";
+    return status;
+}
+
 // The stationary iteration; with a fallback start, the start u is judged by
 // the first sweep (see adr_split_iterate_judged).
 static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback, int32_t max_iters, double tol,
                                 int32_t *iters, double *rel_res, int32_t *used_fallback) {
+    if (ctx->opt.krylov > 0 && !fallback && max_iters > 0) {
+        try {
+            return krylov_iterate(ctx, u, max_iters, tol, iters, rel_res);
+        } catch (const Error &e) {
+            return fail_ctx(ctx, e);
+        }
+    }
     try {
         const int n = ctx->n_inst;
         hipStream_t user = ctx->st;
@@ -1051,7 +1260,15 @@ static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback,
                  !ctx->gexec)) {
                 ctx->drop_graph();
                 HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                ctx->block(ub, m, tol);
+                try {
+                    ctx->block(ub, m, tol);
+                } catch (...) {
+                    // leave no capture open on the context's stream
+                    hipGraph_t g = nullptr;
+                    (void)hipStreamEndCapture(st, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
                 HIPCHK(hipStreamEndCapture(st, &ctx->graph));
                 HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
                 ctx->g_u = ub;
@@ -1121,7 +1338,8 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
 }
 
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
-                        int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes) {
+                        int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes,
+                        int32_t *best_krylov) {
     if (!ctx) return ADR_EINVAL;
     if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES) {
         ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0 and FP32_LINES precision";
@@ -1130,12 +1348,16 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     // (FP32 sweeps per FP64 sweep or their maximum, adaptive)
     static const int kCand[][2] = {{2, 0}, {3, 0}, {4, 0}, {6, 0}, {6, 1}, {8, 1}, {12, 1}, {16, 1}, {24, 1}};
     const int32_t saved = ctx->opt.fp32_sweeps, saved_ad = ctx->opt.adaptive, saved_split = ctx->opt.split_lines;
+    const int32_t saved_kr = ctx->opt.krylov;
+    ctx->opt.krylov = 0;
     const bool eager = !ctx->opt.graph || ctx->opt.timing;
     const size_t nbytes = sizeof(double) * static_cast<size_t>(ctx->goff.back());
     auto restore = [&]() {
         ctx->opt.fp32_sweeps = saved;
         ctx->opt.adaptive = saved_ad;
         ctx->opt.split_lines = saved_split;
+        ctx->opt.krylov = saved_kr;
+        ctx->drop_graph();
     };
     // one timed solve from zero (the second of two runs: the first also
     // captures the graph in graph mode); ms < 0 on a device error
@@ -1196,6 +1418,7 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
             restore();
             return fail_ctx(ctx, e);
         }
+        ctx->drop_graph();  // a graph captured in step 1 holds the launches of the old shapes
     }
     // 2. the FP32/FP64 sweep schedule with those launches
     int best = saved, best_ad = saved_ad;
@@ -1219,6 +1442,22 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     }
     ctx->opt.fp32_sweeps = best;
     ctx->opt.adaptive = best_ad;
+    // 3. GMRES(m) on (I - T) U = c (FP64 sweeps) with those launches, against the best schedule
+    int best_kr = 0;
+    for (int m : {10, 20, 30}) {
+        ctx->opt.krylov = m;
+        double t;
+        const adr_status st = time_solve(t);
+        if (st != ADR_OK) {
+            restore();
+            return st;
+        }
+        if (t < best_t) {
+            best_t = t;
+            best_kr = m;
+        }
+    }
+    ctx->opt.krylov = best_kr;
     if (ctx->opt.timing)
         for (int prec = 0; prec < 2; ++prec) (void)adr_kernel_times(ctx, prec, nullptr, nullptr, nullptr, 1);
     if (best_fp32_sweeps) *best_fp32_sweeps = best;
@@ -1227,6 +1466,7 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     if (best_split) *best_split = split;
     if (best_shapes)
         for (int b = 0; b < adr::kLineBuckets; ++b) best_shapes[b] = ctx->fam[0].bshape[b];
+    if (best_krylov) *best_krylov = best_kr;
     return ADR_OK;
 }
 

@@ -97,6 +97,30 @@ hipError_t launch_norm(int n_inst, const double *partial, const int *blk_start, 
 
 hipError_t launch_fill_int(int *p, int v, int n, hipStream_t st);
 
+// ---- GMRES acceleration: per-instance vector operations on FP64 blocked fields
+// Each instance's blocked range is cut into chunks of krylov_chunk() entries.
+struct KChunks {
+    const int *inst;            // [n] instance of each chunk
+    const int64_t *begin, *end;  // [n] entry range of each chunk
+    const int *inst_chunk;      // [n_inst + 1] first chunk of each instance
+    int n, n_inst;
+};
+int krylov_chunk();
+// out[i * kmax + v] = (z, V_v) per instance i, v < nv (V_v at V + v * stride); partial: [n][kmax]
+hipError_t launch_kdot(const double *z, const double *V, int64_t stride, int nv, int kmax, const KChunks &ch,
+                       const int *done, double *partial, double *out, hipStream_t st);
+// z <- V_j - z - sum_{v < nv} coef[i * kmax + v] V_v; out[i * kmax] = |z|^2 per instance
+hipError_t launch_kupdate(double *z, const double *V, int64_t stride, int j, int nv, int kmax, const double *coef,
+                          const KChunks &ch, const int *done, double *partial, double *out, hipStream_t st);
+// x += sum_{v < nv} coef[i * kmax + v] V_v
+hipError_t launch_kcombine(double *x, const double *V, int64_t stride, int nv, int kmax, const double *coef,
+                           const KChunks &ch, const int *done, hipStream_t st);
+// v *= scale[i * kmax]
+hipError_t launch_kscale(double *v, const double *scale, int kmax, const KChunks &ch, const int *done,
+                         hipStream_t st);
+// r = phi - u on the interior nodes (gb: blocked index of each scatter slot, -1 padding)
+hipError_t launch_kresidual(const int *gb, int npad, const double *phi, const double *u, double *r, hipStream_t st);
+
 // Lout = Lbase + M G un / dt on the interior nodes of the beta-curves (the
 // full line list of a), ends copied: the load of an implicit Euler step.
 hipError_t launch_shift_load(const LineArgs<double> &a, int n_lines, int nmax, const double *Lbase, const double *un,

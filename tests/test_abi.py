@@ -205,3 +205,26 @@ def test_host_psi_and_dirichlet_tables_match_oracle(maker):
         node, _, _, _, gb = s.export_scatter(0, f, with_gb=True)
         assert np.max(np.abs(gb - o.Pb[f][node])) < 1e-12
     s.close()
+
+
+def _header_fields(struct):
+    txt = open(os.path.join(ROOT, "include", "adr.h")).read()
+    end = txt.index("} " + struct + ";")
+    body = txt[txt.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        for part in decl.split(","):
+            names.append(re.findall(r"\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*$", part.strip())[0])
+    return names
+
+
+def test_ctypes_structs_follow_the_header():
+    """The binding's Problem and Options structs list the header's fields in
+    the header's order (a mismatch would pass wrong values silently)."""
+    from paper_2411_11041_amd.adr import Options, Problem
+    assert [f[0] for f in Problem._fields_] == _header_fields("adr_problem")
+    assert [f[0] for f in Options._fields_] == _header_fields("adr_options")
