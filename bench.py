@@ -356,6 +356,23 @@ def leg_c4(args):
     rf = roofline(times, counts, split, profile="c4_512_fp32lines.md")
     rf["events_pass_ms_per_step"] = round(1e3 * el_ev / args.steps, 2)
     solved = int((its.astype(np.int64) * per_inst).sum()) * args.steps
+    # the same solves with the blocks replayed from HIP graphs (one per block
+    # length, captured in the warm-up) instead of eager launches on the lists
+    # compacted to the unfinished instances
+    s.set_graph(not args.graph)
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        its_g, rel_g, _ = solve()
+    torch.cuda.synchronize()
+    el_g = time.perf_counter() - t0
+    s.set_graph(args.graph)
+    other = {"graph_replay": not args.graph, "ms_per_step": round(1e3 * el_g / args.steps, 2),
+             "value": int((its_g.astype(np.int64) * per_inst).sum()) * args.steps / el_g,
+             "converged": int((rel_g <= args.tol).sum())}
+    log(f"c4: {'graph replay' if not args.graph else 'eager'} {other['ms_per_step']} ms")
     s.close()
     return {"value": solved / el, "unit": "line-unknowns/s", "ms_per_step": 1e3 * el / args.steps, "roofline": rf,
             "config": {"workload": f"c4: {len(probs)} stationary instances (disc/L-shape, 33..1025 per side, "
@@ -368,7 +385,8 @@ def leg_c4(args):
                        "setup_s": round(setup_s, 1), "graph": bool(args.graph),
                        "fp32_sweeps_per_fp64": fp32_sweeps, "adaptive_schedule": bool(adaptive),
                        "line_launches": LINE_LAUNCHES[split], "line_shapes": shapes, "krylov_gmres_m": kr,
-                       "autotune_ms": round(tuned[2], 2) if tuned else None, "kernels": kernels_table(times)}}
+                       "autotune_ms": round(tuned[2], 2) if tuned else None,
+                       "other_launch_mode": other, "kernels": kernels_table(times)}}
 
 
 CNN_FLOP_PER_PIXEL = 2 * 9 * (4 * 32 + 32 * 32 + 32 * 32 + 32)  # forward, 4 conv layers

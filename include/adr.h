@@ -97,15 +97,17 @@ typedef struct {
     int32_t host_only;    /* != 0: build the host geometry only, touch no device; then
                              only adr_counts, adr_export_lines, adr_export_scatter and
                              adr_destroy are valid */
-    int32_t graph;        /* != 0: adr_split_iterate replays its sweep blocks from a captured
-                             HIP graph (on a context-owned stream ordered after options.stream);
-                             ignored when timing != 0 */
-    int32_t adaptive;     /* != 0 (FP32_LINES, eager mode only: graph == 0 or timing != 0): the
-                             number of FP32 sweeps before each FP64 sweep varies from 0 to
-                             fp32_sweeps; it is chosen after each FP64 sweep so that the next
-                             one falls on the sweep where the first unfinished instance is
-                             expected to reach tol, from the geometric decay of its measured
-                             rel (at least fp32_sweeps / 2 while several instances run) */
+    int32_t graph;        /* != 0: adr_split_iterate replays its sweep blocks (m FP32 sweeps, an
+                             FP64 sweep, the norm) from HIP graphs, one per block length m,
+                             captured on first use on a context-owned stream ordered after
+                             options.stream; the replayed launches cover every instance (a
+                             finished one exits at once) where eager launches follow the lists
+                             compacted to the unfinished instances; ignored when timing != 0 */
+    int32_t adaptive;     /* != 0 (FP32_LINES): the number of FP32 sweeps before each FP64 sweep
+                             varies from 0 to fp32_sweeps; it is chosen after each FP64 sweep so
+                             that the next one falls on the sweep where the first unfinished
+                             instance is expected to reach tol, from the geometric decay of its
+                             measured rel (at least fp32_sweeps / 2 while several instances run) */
     int32_t split_lines;  /* line solves of a family: 0 one launch whose workgroups pick their
                              register footprint; 1 one launch per length bucket (curves of at
                              most 12, 8, 4, 2, 1 nodes per thread), each kernel with its
@@ -200,8 +202,8 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
  *   1. the line launches (options.split_lines 0, 1 and 2), under the context's
  *      current schedule;
  *   2. with the faster of those, each candidate schedule: a fixed count of
- *      FP32 sweeps per FP64 sweep (2, 3, 4, 6) and, in eager mode, the
- *      adaptive schedule with at most 6, 8, 12, 16 or 24;
+ *      FP32 sweeps per FP64 sweep (2, 3, 4, 6) and the adaptive schedule
+ *      with at most 6, 8, 12, 16 or 24;
  *   3. GMRES(m) (options.krylov) with m = 10, 20, 30, kept if faster than the
  *      best schedule.
  * With bucketed launches, between the two steps, each length bucket's
@@ -215,6 +217,11 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
                         int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes,
                         int32_t *best_krylov);
+
+/* Graph replay of the stationary solve's blocks on (1) or off (0) from now on
+ * (options.graph); captured graphs are dropped.  Errors: ADR_EINVAL (host-only
+ * context). */
+adr_status adr_set_graph(adr_ctx *ctx, int32_t on);
 
 /* Workgroup shapes of the bucketed line launches (options.split_lines != 0):
  * shapes[b] for bucket b = 0..4 (curves of at most 3072, 2048, 1024, 512, 256

@@ -20,7 +20,7 @@ DOM_BOX, DOM_DISC, DOM_POLYGON = 0, 1, 2
 PREC_FP64, PREC_FP32_LINES = 0, 1
 
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
-           "adr_autotune", "adr_set_line_shapes", "adr_time_step",
+           "adr_autotune", "adr_set_line_shapes", "adr_set_graph", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_set_timing", "adr_kernel_times",
            "adr_destroy", "adr_last_error", "adr_copy_probe", "adr_line_solve", "adr_line_solve_noalloc")
 
@@ -76,6 +76,7 @@ def load():
     lib.adr_split_iterate_judged.argtypes = [vp, vp, vp, i32, dbl, P(i32), P(dbl), P(i32)]
     lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32), P(i32), P(i32)]
     lib.adr_set_line_shapes.argtypes = [vp, P(i32)]
+    lib.adr_set_graph.argtypes = [vp, i32]
     lib.adr_set_timing.argtypes = [vp, i32]
     lib.adr_time_step.argtypes = [vp, vp, dbl, dbl, i32, i32, dbl, P(i32)]
     lib.adr_residual.argtypes = [vp, vp, P(dbl)]
@@ -238,6 +239,10 @@ class Solver:
         self._check(self.lib.adr_autotune(self.ctx, _device_ptr(work), int(max_iters), float(tol),
                                           C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp), sh, C.byref(kr)))
         return best.value, bool(ad.value), ms.value, int(sp.value), list(sh), int(kr.value)
+
+    def set_graph(self, on):
+        """Replay the stationary solve's blocks from HIP graphs (include/adr.h)."""
+        self._check(self.lib.adr_set_graph(self.ctx, int(bool(on))))
 
     def set_line_shapes(self, shapes):
         """Workgroup shape of each of the 5 length buckets (include/adr.h)."""

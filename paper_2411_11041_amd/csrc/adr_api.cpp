@@ -439,15 +439,16 @@ struct adr_ctx {
         norm(fp32_sweeps + 1, tol, 0);
     }
 
-    // Adaptive schedule (eager): after each FP64 sweep the per-instance rel is
+    // Adaptive schedule: after each FP64 sweep the per-instance rel is
     // read with the done flags; an unfinished instance whose rel fell from r0
     // (sweep k0) to r (sweep k) is expected to reach tol after
     // ceil(log(tol / r) / log(rho)) more sweeps, rho = (r / r0)^(1 / (k - k0)).
     // The next block ends on the earliest such sweep (at most fp32_sweeps FP32
     // sweeps; at least half of that while several instances run, so that one
     // instance about to finish does not cut every block short).
-    template <typename AllDone>
-    void adaptive_blocks(double *ub, int max_iters, double tol, std::vector<int> &dn, AllDone &&all_done) {
+    template <typename AllDone, typename Run>
+    void adaptive_blocks(double *ub, int max_iters, double tol, std::vector<int> &dn, AllDone &&all_done, Run &&run,
+                         bool may_compact) {
         const int mmax = opt.fp32_sweeps;
         std::vector<double> rel_h(n_inst, 0.0), r0(n_inst, -1.0);
         std::vector<int> k0(n_inst, 0);
@@ -460,11 +461,11 @@ struct adr_ctx {
         for (int i = 0; i < n_inst; ++i) { r0[i] = rel_h[i]; k0[i] = k; }
         int m = std::min(mmax, max_iters - k - 1);
         while (m >= 0 && k + m + 1 <= max_iters) {
-            block(ub, m, tol);
+            run(m);
             k += m + 1;
             read_rel();
             if (all_done()) return;
-            if (n_inst > 1) compact(dn);
+            if (may_compact && n_inst > 1) compact(dn);
             int target = k + mmax + 1, active = 0;
             for (int i = 0; i < n_inst; ++i) {
                 if (dn[i]) continue;
@@ -484,23 +485,60 @@ struct adr_ctx {
         }
     }
 
-    // captured graph of one block, replayed (keyed by the state pointer and tol)
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    // captured graphs of whole blocks (m FP32 sweeps, an FP64 sweep, the norm),
+    // one per block length m, captured on first use and replayed; all are
+    // dropped when the state pointer, tol or the line launches change
+    struct GBlock {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t x = nullptr;
+    };
+    std::map<int, GBlock> gblocks;
     const double *g_u = nullptr;
     double g_tol = -1.0;
-    int g_m = -1;      // FP32 sweeps per block of the captured graph
-    int g_split = -1;  // its line launches (options.split_lines)
+    int g_split = -1;  // the line launches (options.split_lines) of the captured graphs
     hipStream_t cap = nullptr;
     // concurrent bucket launches (options.split_lines == 2): two more streams of
     // the default priority, forked from and joined back into st by events
     hipStream_t side[2] = {nullptr, nullptr};
     hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
     void drop_graph() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
-        gexec = nullptr;
-        graph = nullptr;
+        for (auto &kv : gblocks) {
+            if (kv.second.x) (void)hipGraphExecDestroy(kv.second.x);
+            if (kv.second.g) (void)hipGraphDestroy(kv.second.g);
+        }
+        gblocks.clear();
+    }
+    // one block replayed from its graph (captured now if new) on st, the
+    // capture stream; the launch lists must be the full ones (not compacted)
+    void graph_block(double *ub, int m, double tol) {
+        if (g_u != ub || g_tol != tol || g_split != opt.split_lines) {
+            drop_graph();
+            g_u = ub;
+            g_tol = tol;
+            g_split = opt.split_lines;
+        }
+        auto it = gblocks.find(m);
+        if (it == gblocks.end()) {
+            GBlock b;
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            try {
+                block(ub, m, tol);
+            } catch (...) {
+                // leave no capture open on the stream
+                hipGraph_t g = nullptr;
+                (void)hipStreamEndCapture(st, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            HIPCHK(hipStreamEndCapture(st, &b.g));
+            const hipError_t e = hipGraphInstantiate(&b.x, b.g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(b.g);
+                HIPCHK(e);
+            }
+            it = gblocks.emplace(m, b).first;
+        }
+        HIPCHK(hipGraphLaunch(it->second.x, st));
     }
 
 };
@@ -1186,8 +1224,7 @@ static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback,
     try {
         const int n = ctx->n_inst;
         hipStream_t user = ctx->st;
-        const bool use_graph = ctx->opt.graph != 0 && !ctx->opt.timing &&
-                               !(ctx->opt.adaptive && ctx->opt.precision == ADR_PREC_FP32_LINES);
+        const bool use_graph = ctx->opt.graph != 0 && !ctx->opt.timing;
         if (use_graph) {
             // run on the context's own stream (capturable), ordered after the caller's work
             if (!ctx->cap) HIPCHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
@@ -1255,33 +1292,17 @@ static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback,
             }
             const int blocks = (max_iters - 1) / period;
             const int check = std::max(1, 8 / period);
-            if (use_graph && blocks > 0 &&
-                (ctx->g_u != ub || ctx->g_tol != tol || ctx->g_m != m || ctx->g_split != ctx->opt.split_lines ||
-                 !ctx->gexec)) {
-                ctx->drop_graph();
-                HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                try {
-                    ctx->block(ub, m, tol);
-                } catch (...) {
-                    // leave no capture open on the context's stream
-                    hipGraph_t g = nullptr;
-                    (void)hipStreamEndCapture(st, &g);
-                    if (g) (void)hipGraphDestroy(g);
-                    throw;
-                }
-                HIPCHK(hipStreamEndCapture(st, &ctx->graph));
-                HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
-                ctx->g_u = ub;
-                ctx->g_tol = tol;
-                ctx->g_m = m;
-                ctx->g_split = ctx->opt.split_lines;
-            }
+            // a block: replayed from its captured graph (full launch lists), or
+            // eager launches that follow the compacted lists of the active instances
+            auto run = [&](int mb) {
+                if (use_graph) ctx->graph_block(ub, mb, tol);
+                else ctx->block(ub, mb, tol);
+            };
             if (fp32 && ctx->opt.adaptive) {
-                ctx->adaptive_blocks(ub, max_iters, tol, dn, all_done);
+                ctx->adaptive_blocks(ub, max_iters, tol, dn, all_done, run, !use_graph);
             } else {
                 for (int b = 0; b < blocks; ++b) {
-                    if (use_graph) HIPCHK(hipGraphLaunch(ctx->gexec, st));
-                    else ctx->block(ub, m, tol);
+                    run(m);
                     if ((b + 1) % check == 0) {
                         if (all_done()) break;
                         // the graph's launches are fixed; eager launches follow the active set
@@ -1350,7 +1371,6 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     const int32_t saved = ctx->opt.fp32_sweeps, saved_ad = ctx->opt.adaptive, saved_split = ctx->opt.split_lines;
     const int32_t saved_kr = ctx->opt.krylov;
     ctx->opt.krylov = 0;
-    const bool eager = !ctx->opt.graph || ctx->opt.timing;
     const size_t nbytes = sizeof(double) * static_cast<size_t>(ctx->goff.back());
     auto restore = [&]() {
         ctx->opt.fp32_sweeps = saved;
@@ -1425,7 +1445,6 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     double best_t = INFINITY;
     for (const auto &cand : kCand) {
         const int c = cand[0];
-        if (cand[1] && !eager) continue;  // the adaptive schedule runs eager launches only
         ctx->opt.fp32_sweeps = c;
         ctx->opt.adaptive = cand[1];
         double t;
@@ -1467,6 +1486,13 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     if (best_shapes)
         for (int b = 0; b < adr::kLineBuckets; ++b) best_shapes[b] = ctx->fam[0].bshape[b];
     if (best_krylov) *best_krylov = best_kr;
+    return ADR_OK;
+}
+
+adr_status adr_set_graph(adr_ctx *ctx, int32_t on) {
+    if (!ctx || ctx->opt.host_only) return ADR_EINVAL;
+    ctx->opt.graph = on ? 1 : 0;
+    ctx->drop_graph();
     return ADR_OK;
 }
 

@@ -512,3 +512,36 @@ def test_copy_probe_copies():
     assert torch.equal(a, b)
     with pytest.raises(ADRError):
         copy_probe(a[:5], torch.zeros(5, dtype=torch.float32, device="cuda"))  # 20 bytes: not a multiple of 16
+
+
+def test_adaptive_schedule_graph_replay_equals_eager():
+    """The adaptive schedule replayed from per-block-length graphs (full launch
+    lists, finished instances exiting at once) gives the eager solve's result
+    (compacted lists) bitwise, with the same sweep counts, on every replay with
+    eager work in between."""
+    print("[case] adaptive schedule: graph replay vs eager, batch of 6", flush=True)
+    probs = [W.c4_instance(i, n_max=70) for i in range(6)]
+    kw = dict(precision="fp32", fp32_sweeps=8, adaptive=True, split_lines=1, theta=1.0, dt=0.05)
+    eager = solver(probs, **kw)
+    graph = solver(probs, graph=True, **kw)
+    n = int(eager.layout()[-1])
+    ref = torch.zeros(n, dtype=torch.float64, device="cuda")
+    it_e, rel_e, _ = eager.split_iterate(ref, 2000, 1e-9)
+    torch.cuda.synchronize()
+    assert len(set(int(v) for v in it_e)) > 1  # instances stop at different sweeps
+    u = torch.zeros_like(ref)
+    for rep in range(3):
+        u.zero_()
+        it_g, rel_g, _ = graph.split_iterate(u, 2000, 1e-9)
+        torch.cuda.synchronize()
+        assert np.array_equal(it_g, it_e), rep
+        assert torch.equal(u, ref), rep
+        graph.residual(u)  # eager work on the same context between replays
+    # switching the mode on a context keeps the result
+    eager.set_graph(True)
+    v = torch.zeros_like(ref)
+    eager.split_iterate(v, 2000, 1e-9)
+    torch.cuda.synchronize()
+    assert torch.equal(v, ref)
+    eager.close()
+    graph.close()
