@@ -17,6 +17,10 @@ Modules
              relative update, eq. (11) initial guess, theta-scheme time marching
   dense      the affine map Phi(U) = T U + c assembled column by column, and the
              dense LU solve of (I - T) U = c (the iteration's limit)
+  krylov     restarted GMRES(m) on (I - T) U = c: the same fixed point by a Krylov route
+  direct     the interpolation-free transfer (Sec. 8): values handed from one curve
+             family to the other at the intersections of their segments, and the
+             stationary iteration on the gamma-curve values with it
   coarse     full-weighting restriction and bilinear interpolation between the
              solver grid and the warm-start network's coarse grid
   galerkin2d own 2D P1 Galerkin solve of eq. (5)-(6) (independent reference)
