@@ -108,6 +108,7 @@ struct adr_ctx {
     int64_t act_grid = 0;                              // interior grid nodes of the compacted blocks
     int *blist = nullptr, *cscan = nullptr, *ccount = nullptr;  // compacted block list, scan scratch, count
     int act_blocks = -1;                               // length of blist; -1: full list
+    std::vector<int> act_set;                          // the flags blist was compacted from
     double *par = nullptr;  // [slot][fam][inst][8]
     std::vector<double> par_h;
     double *Uh64 = nullptr, *Z64 = nullptr, *partial = nullptr, *cnorm = nullptr, *rel = nullptr;
@@ -359,11 +360,14 @@ struct adr_ctx {
     }
 
     // Restricts the line and scatter launches to the instances not done (dn,
-    // read from the device after the stream was synchronised): the lists are
-    // compacted on the device from the same flags, their lengths counted here.
-    // The kernels still test the flags, so instances that finish later are
-    // skipped as before.  A launch's workgroups then all carry work.
-    void compact(const std::vector<int> &dn) {
+    // the host copy of the device flags `flags`, default the done flags): the
+    // lists are compacted on the device from the flags, their lengths counted
+    // here.  The kernels still test their flags, so instances that finish later
+    // are skipped as before.  A launch's workgroups then all carry work.
+    void compact(const std::vector<int> &dn, const int *flags = nullptr) {
+        if (!flags) flags = done;
+        if (act_blocks >= 0 ? dn == act_set : std::none_of(dn.begin(), dn.end(), [](int v) { return v != 0; }))
+            return;  // unchanged set
         int nb = 0;
         int64_t ng = 0;
         for (int i = 0; i < n_inst; ++i)
@@ -371,8 +375,8 @@ struct adr_ctx {
                 nb += inst_blocks[i];
                 ng += inst_grid[i];
             }
-        if (nb == (act_blocks >= 0 ? act_blocks : n_blocks)) return;  // unchanged set
-        HIPCHK(adr::launch_compact(blk_inst_d, n_blocks, done, cscan, blist, ccount, st));
+        HIPCHK(adr::launch_compact(blk_inst_d, n_blocks, flags, cscan, blist, ccount, st));
+        act_set = dn;
         act_blocks = nb;
         act_grid = ng;
         for (int f = 0; f < 2; ++f) {
@@ -391,7 +395,7 @@ struct adr_ctx {
                         F.abnmax[b] = std::max(F.abnmax[b], F.inst_bnmax[i][b]);
                     }
                 }
-            HIPCHK(adr::launch_compact(F.a64.linst, F.n_lines, done, cscan, F.lidx, ccount, st));
+            HIPCHK(adr::launch_compact(F.a64.linst, F.n_lines, flags, cscan, F.lidx, ccount, st));
             F.act = nl;
             F.act_nmax = nm;
             F.act_unk = nu;
@@ -1105,6 +1109,7 @@ static adr_status krylov_iterate(adr_ctx *ctx, double *u, int32_t max_iters, dou
     ctx->to_blocked(u);
     while (true) {
         // exact residual r = Phi(U) - U into V_0; rel = |r| / |Phi(0)|
+        if (n > 1) ctx->compact(dn);
         ctx->sweep64(kSlotStep, ctx->Ub, Vp(0), 0, ctx->done);
         HIPCHK(adr::launch_kresidual(ctx->slot_b, ctx->npad, Vp(0), ctx->Ub, Vp(0), st));
         HIPCHK(adr::launch_kdot(Vp(0), Vp(0), stride, 1, K, ctx->kch, ctx->done, ctx->kpart, ctx->kout, st));
@@ -1131,6 +1136,7 @@ static adr_status krylov_iterate(adr_ctx *ctx, double *u, int32_t max_iters, dou
         HIPCHK(adr::launch_kscale(Vp(0), ctx->kcoef, K, ctx->kch, ctx->kskip, st));
         for (int j = 0; j < m; ++j) {
             // z = T V_j into V_{j+1}; h_ij = delta_ij - (T V_j, V_i)
+            if (n > 1) ctx->compact(skip, ctx->kskip);
             ctx->linear_sweep(Vp(j), Vp(j + 1), ctx->kskip);
             HIPCHK(adr::launch_kdot(Vp(j + 1), V, stride, j + 1, K, ctx->kch, ctx->kskip, ctx->kpart, ctx->kout, st));
             read_out();
@@ -1196,6 +1202,7 @@ static adr_status krylov_iterate(adr_ctx *ctx, double *u, int32_t max_iters, dou
         put_coef();
         HIPCHK(adr::launch_kcombine(ctx->Ub, V, stride, m, K, ctx->kcoef, ctx->kch, ctx->done, st));
     }
+    ctx->uncompact();
     ctx->from_blocked(u);
     const adr_status sst = ctx->singular_status();
     adr_status status = ADR_OK;
