@@ -83,6 +83,15 @@ def scatter_bytes(prec, fam, counts, march=False):
     return vals + grid, meta
 
 
+def direct_line_bytes(fam):
+    """FP64 line solve of the direct transfer, per line unknown: algorithmic =
+    one source value, the chord, |beta| and the load (beta), the old value
+    (gamma: the update norm) and the written value; tables = the two bracket
+    indices and four weights."""
+    alg = 8 + 8 + (16 if fam == 0 else 8) + 8
+    return alg, 8 + 32
+
+
 def kernel_name(prec, cls, split_lines=0, march=False):
     tn = "float" if prec == "fp32" else "double"
     fam = 0 if cls.endswith("beta") else 1
@@ -97,7 +106,7 @@ def kernel_name(prec, cls, split_lines=0, march=False):
     return "k_scatter<double, double, 1>"
 
 
-def roofline(times, counts, split_lines=0, march=False, profile=None):
+def roofline(times, counts, split_lines=0, march=False, profile=None, direct=False):
     """Per kernel class: algorithmic and with-table bytes of its timed
     launches (work counted by the library per launch) over their summed event
     time.  The dominant class (largest total time) gives the roofline object;
@@ -110,11 +119,13 @@ def roofline(times, counts, split_lines=0, march=False, profile=None):
                 continue
             fam = 0 if cls.endswith("beta") else 1
             if cls.startswith("line"):
-                alg, meta = line_bytes(prec, fam)
+                alg, meta = direct_line_bytes(fam) if direct else line_bytes(prec, fam)
             else:
                 alg, meta = scatter_bytes(prec, fam, counts, march)
             sec = ms / 1e3
             name = kernel_name(prec, cls, split_lines, march)
+            if direct and cls.startswith("line"):
+                name = name.replace(f"{fam}>", f"{fam}, true>").replace("J, NT>", "J, NT, true>")
             rows.append(dict(kernel=name, prec=prec, cls=cls, ms=round(ms, 3), launches=cnt,
                              avg_launch_us=round(1e3 * ms / cnt, 2), work_per_launch=round(work / cnt),
                              alg_bytes_per_unit=round(alg, 2), table_bytes_per_unit=round(meta, 2),
@@ -174,7 +185,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=3, help="FP64 oracle sweeps per worker process")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle worker processes (0: one per host core, <= 16)")
-    ap.add_argument("--workload", choices=["all", "c2", "c3", "c4", "c5"], default="all",
+    ap.add_argument("--acc-n", type=int, default=1025, help="direct leg: grid of the accuracy comparison (C1)")
+    ap.add_argument("--workload", choices=["all", "c2", "c3", "c4", "c5", "direct"], default="all",
                     help="all: c2 (the step and value) with the c4 and c5 legs (default); c2: one 2049^2 problem; "
                          "c3: the 2049^2 parabolic march (200 steps); c4: the 512-instance batch; "
                          "c5: learned warm start (train, then zero / eq. (11) / network starts)")
@@ -299,6 +311,67 @@ def leg_c2(args):
                        "line_unknowns_per_sweep": per_sweep, "grid_unknowns": counts["grid_unknowns"],
                        "lines": [counts["lines_b"], counts["lines_g"]], "setup_s": round(setup_s, 2),
                        "kernels": kernels_table(times)}}
+
+
+def leg_direct(args):
+    """The interpolation-free transfer against the grid route, both in FP64:
+    C2 time to 1e-8 and sweeps, and the distance of each route's fixed point
+    from the exact solution of the manufactured problem (C1)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2411_11041_amd.adr import Solver
+    p = W.c2(args.n)
+    res = {}
+    for tr in ("grid", "direct"):
+        t0 = time.time()
+        s = Solver(p, precision="fp64", theta=1.0, dt=0.05, split_lines=0, transfer=tr)
+        setup_s = time.time() - t0
+        counts = s.counts()
+        per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
+        u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+
+        def solve():
+            u.zero_()
+            return s.split_iterate(u, 5000, args.tol)
+
+        for _ in range(args.warmup):
+            solve()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            iters, rel, st = solve()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        el_ev, times = events_pass(s, solve, args.steps)
+        rf = roofline(times, counts, 0, direct=(tr == "direct"))
+        res[tr] = {"ms_per_step": round(1e3 * el / args.steps, 3), "sweeps": int(iters[0]),
+                   "final_rel": float(rel[0]), "value": per_sweep * int(iters[0]) * args.steps / el,
+                   "setup_s": round(setup_s, 2), "events_pass_ms_per_step": round(1e3 * el_ev / args.steps, 3),
+                   "roofline": rf, "kernels": kernels_table(times)}
+        log(f"direct leg: {tr} {res[tr]['ms_per_step']:.2f} ms, {res[tr]['sweeps']} sweeps")
+        s.close()
+    # accuracy on the manufactured problem
+    q = W.c1(args.acc_n)
+    X, Y = q.coords()
+    ue = W.manufactured_u(X, Y).ravel()
+    errs = {}
+    for tr in ("grid", "direct"):
+        s = Solver(q, precision="fp64", theta=1.0, dt=0.05, transfer=tr)
+        u = torch.zeros(q.nx * q.ny, dtype=torch.float64, device="cuda")
+        s.split_iterate(u, 5000, 1e-11)
+        # interior nodes: the ones the solve wrote (the rest stays zero, as ue is zero on Gamma)
+        e = np.abs(u.cpu().numpy() - ue)
+        errs[tr] = float(e.max() / np.abs(ue).max())
+        s.close()
+    return {"value": res["direct"]["value"], "unit": "line-unknowns/s", "ms_per_step": res["direct"]["ms_per_step"],
+            "roofline": res["direct"]["roofline"],
+            "config": {"workload": f"c2 {args.n}x{args.n} stationary to 1e-8, FP64 sweeps: values handed between "
+                                   "the families directly at their segment intersections (transfer=direct) "
+                                   "against the grid route (scatter + bilinear gather)",
+                       "direct": {k: v for k, v in res["direct"].items() if k != "roofline"},
+                       "grid_fp64": res["grid"],
+                       f"c1_{args.acc_n}_max_rel_error_vs_exact": errs}}
 
 
 def gen_c4(n_inst):
@@ -577,6 +650,8 @@ def main():
         main_leg = leg_c4(args)
     elif args.workload == "c5":
         main_leg = leg_c5(args)
+    elif args.workload == "direct":
+        main_leg = leg_direct(args)
     else:
         main_leg = leg_c2(args)
         log(f"c2: {main_leg['ms_per_step']:.2f} ms to 1e-8")
@@ -585,6 +660,8 @@ def main():
             log(f"c4: {legs['c4']['ms_per_step']:.1f} ms to 1e-8")
             legs["c5"] = leg_c5(args)
             log(f"c5: network start {legs['c5']['ms_per_step']:.2f} ms")
+            legs["direct"] = leg_direct(args)
+            log(f"direct transfer: {legs['direct']['ms_per_step']:.2f} ms to 1e-8")
     out = {"metric": METRIC, "value": main_leg["value"], "unit": "line-unknowns/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": main_leg["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,

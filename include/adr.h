@@ -95,8 +95,8 @@ typedef struct {
     void *stream;         /* hipStream_t; NULL = the default stream */
     int32_t timing;       /* != 0: time each kernel with HIP events (adr_kernel_times) */
     int32_t host_only;    /* != 0: build the host geometry only, touch no device; then
-                             only adr_counts, adr_export_lines, adr_export_scatter and
-                             adr_destroy are valid */
+                             only adr_counts, adr_export_lines, adr_export_scatter,
+                             adr_export_direct and adr_destroy are valid */
     int32_t graph;        /* != 0: adr_split_iterate replays its sweep blocks (m FP32 sweeps, an
                              FP64 sweep, the norm) from HIP graphs, one per block length m,
                              captured on first use on a context-owned stream ordered after
@@ -132,6 +132,19 @@ typedef struct {
                              exact residual Phi(U) - U (one FP64 sweep) and stops at
                              rel = |Phi(U) - U| / |Phi(0)| <= tol; iters counts the sweeps; the
                              iterate returned is that U (not Phi(U)).  Not for the judged solve */
+    int32_t transfer;     /* how values pass between the families: 0 through the grid (Sec. 6:
+                             the scatter and the bilinear gather of eq. (22)); 1 directly at
+                             the intersections of the two families' segments (the
+                             conclusions' interpolation-free transfer: a node of a curve takes
+                             the linear interpolant, in arc length along its curve, of the
+                             other family's P1 values at the nearest intersections before and
+                             after it, its curve's Dirichlet end where a side has none).  With
+                             1, adr_split_iterate iterates on the gamma-curve values, every
+                             sweep FP64 (any precision; graph ignored; krylov must be 0; no
+                             fallback start): start = the bilinear gather of u onto the
+                             gamma-curves, rel = |v' - v|_2 / |Phi(0)|_2 over the interior
+                             gamma-curve nodes, u out = the scatter of Sec. 6 of the last
+                             gamma values.  The other calls keep the grid transfer */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -287,6 +300,20 @@ adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, in
  * Errors: ADR_EINVAL (a device context, an index out of range). */
 adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
                               int32_t *node, int32_t *k, double *ca, double *cb, double *gb);
+
+/* Test export (host-only contexts set up with options.transfer = 1): the
+ * direct-transfer records onto every node of one instance's family (0 beta,
+ * 1 gamma) from the other family's line values, in the node order of
+ * adr_export_lines.  Node q's value is
+ *   (k[2q] >= 0 ? w[4q] v[k[2q]] + w[4q+1] v[k[2q]+1] : w[4q] x_first)
+ * + (k[2q+1] >= 0 ? w[4q+2] v[k[2q+1]] + w[4q+3] v[k[2q+1]+1] : w[4q+2] x_last)
+ * with v the other family's values (node indices local to the instance) and
+ * x_first, x_last the Dirichlet values at the ends of q's own curve; end nodes
+ * carry k = -1 and zero weights.  Call with NULL arrays to get *n_nodes, then
+ * with k (2 n_nodes) and w (4 n_nodes) host buffers.  Errors: ADR_EINVAL (a
+ * device context, transfer != 1, an index out of range). */
+adr_status adr_export_direct(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_nodes, int32_t *k,
+                             double *w);
 
 /* Per-launch HIP-event timing on (1) or off (0) from now on (the set-up
  * option's initial value).  Each timed launch records two events on the

@@ -21,7 +21,8 @@ PREC_FP64, PREC_FP32_LINES = 0, 1
 
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
            "adr_autotune", "adr_set_line_shapes", "adr_set_graph", "adr_time_step",
-           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_set_timing", "adr_kernel_times",
+           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_export_direct",
+           "adr_set_timing", "adr_kernel_times",
            "adr_destroy", "adr_last_error", "adr_copy_probe", "adr_line_solve", "adr_line_solve_noalloc")
 
 KERNEL_CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma", "norm")
@@ -49,7 +50,7 @@ class Options(C.Structure):
                 ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32),
                 ("graph", C.c_int32), ("adaptive", C.c_int32), ("split_lines", C.c_int32),
                 ("pivot_tol", C.c_double), ("splitting", C.c_int32), ("stabilize", C.c_int32),
-                ("krylov", C.c_int32)]
+                ("krylov", C.c_int32), ("transfer", C.c_int32)]
 
 
 _lib = None
@@ -83,6 +84,7 @@ def load():
     lib.adr_initial_guess.argtypes = [vp, vp]
     lib.adr_export_lines.argtypes = [vp, i32, i32, P(i64), P(i64), P(i64), P(dbl), P(dbl)]
     lib.adr_export_scatter.argtypes = [vp, i32, i32, P(i64), P(i32), P(i32), P(dbl), P(dbl), P(dbl)]
+    lib.adr_export_direct.argtypes = [vp, i32, i32, P(i64), P(i32), P(dbl)]
     lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), P(i64), i32]
     lib.adr_destroy.argtypes = [vp]
     lib.adr_copy_probe.argtypes = [vp, vp, i64, vp]
@@ -154,7 +156,7 @@ class Solver:
 
     def __init__(self, problems, precision="fp64", theta=1.0, dt=0.05, fp32_sweeps=3,
                  stream=None, timing=False, host_only=False, graph=False, adaptive=False, split_lines=False,
-                 pivot_tol=0.0, splitting="lie", stabilize=False, krylov=0):
+                 pivot_tol=0.0, splitting="lie", stabilize=False, krylov=0, transfer="grid"):
         self.lib = load()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -167,7 +169,8 @@ class Solver:
         opt = Options(prec, int(fp32_sweeps), float(theta), float(dt),
                       C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)),
                       int(bool(graph)), int(bool(adaptive)), int(split_lines), float(pivot_tol),
-                      {"lie": 0, "strang": 1}[splitting], int(bool(stabilize)), int(krylov))
+                      {"lie": 0, "strang": 1}[splitting], int(bool(stabilize)), int(krylov),
+                      {"grid": 0, "direct": 1}[transfer])
         self.n = len(problems)
         self.ctx = C.c_void_p()
         st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))
@@ -321,6 +324,18 @@ class Solver:
                                                 k.ctypes.data_as(i32p), _dptr(ca), _dptr(cb), _dptr(gb)))
         out = (node, k.reshape(n, 4), ca.reshape(n, 4), cb.reshape(n, 4))
         return out + (gb,) if with_gb else out
+
+    def export_direct(self, inst, family):
+        """Direct-transfer records (host-only contexts with transfer="direct"):
+        k (n_nodes x 2) and w (n_nodes x 4), node indices local to the instance."""
+        nn = C.c_int64()
+        self._check(self.lib.adr_export_direct(self.ctx, inst, family, C.byref(nn), None, None))
+        n = nn.value
+        k = np.zeros(2 * n, np.int32)
+        w = np.zeros(4 * n)
+        self._check(self.lib.adr_export_direct(self.ctx, inst, family, None, k.ctypes.data_as(C.POINTER(C.c_int32)),
+                                               _dptr(w)))
+        return k.reshape(n, 2), w.reshape(n, 4)
 
     def kernel_times(self, precision="fp64", reset=True, work=False):
         """Per kernel class: (ms, launches), or (ms, launches, work) with work=True."""

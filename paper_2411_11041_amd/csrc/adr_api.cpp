@@ -66,6 +66,7 @@ struct DevFam {
     int nmax = 0;  // nodes of the longest curve (sizes the launch's LDS)
     int64_t n_nodes = 0, n_unknowns = 0;
     adr::LineArgs<double> a64{};
+    adr::LineArgs<double> a64d{};  // the same with the direct-transfer records (options.transfer = 1)
     adr::LineArgs<float> a32{};
     adr::ScatterArgs<double> s64{};
     adr::ScatterArgs<float> s32{};
@@ -109,6 +110,11 @@ struct adr_ctx {
     int *blist = nullptr, *cscan = nullptr, *ccount = nullptr;  // compacted block list, scan scratch, count
     int act_blocks = -1;                               // length of blist; -1: full list
     std::vector<int> act_set;                          // the flags blist was compacted from
+    // interpolation-free transfer (options.transfer = 1): per gamma-curve update
+    // sums grouped by instance, their ranges, and |Phi(0)| of the direct sweep
+    double *lpart = nullptr, *cnorm_d = nullptr;
+    int *inst_lstart = nullptr;
+    bool cnorm_d_valid = false;
     double *par = nullptr;  // [slot][fam][inst][8]
     std::vector<double> par_h;
     double *Uh64 = nullptr, *Z64 = nullptr, *partial = nullptr, *cnorm = nullptr, *rel = nullptr;
@@ -431,6 +437,24 @@ struct adr_ctx {
         });
     }
 
+    // One sweep of eq. (10) with the direct transfer: the beta-lines take their
+    // input from the gamma-curve values, the gamma-lines from the beta-curve
+    // values (in place into fam[1].v64, with the per-line update sums).
+    void direct_sweep(const int *dn) {
+        timed(0, 0, line_work(0), [&] {
+            return lines<double>(0, fam[0].a64d, fam[1].v64, fam[0].v64, par_ptr(kSlotStep, 0), dn);
+        });
+        timed(0, 1, line_work(1), [&] {
+            return lines<double>(1, fam[1].a64d, fam[0].v64, fam[1].v64, par_ptr(kSlotStep, 1), dn);
+        });
+    }
+    void direct_norm(int count, double tol, int mode) {
+        timed(0, 4, 0, [&] {
+            return adr::launch_norm(n_inst, lpart, inst_lstart, cnorm_d, rel, done, conv_it,
+                                    count, tol, mode, st);
+        });
+    }
+
     // the caller's row-major state in and out of the blocked state Ub (interior nodes)
     void to_blocked(const double *u) { HIPCHK(adr::launch_layout(slot_rm, slot_b, npad, u, Ub, true, st)); }
     void from_blocked(double *u) { HIPCHK(adr::launch_layout(slot_rm, slot_b, npad, Ub, u, false, st)); }
@@ -596,6 +620,9 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         if (opt->splitting != 0 && opt->splitting != 1) throw Error{ADR_EINVAL, "splitting must be 0 or 1"};
         if (opt->stabilize != 0 && opt->stabilize != 1) throw Error{ADR_EINVAL, "stabilize must be 0 or 1"};
         if (opt->krylov < 0 || opt->krylov > 200) throw Error{ADR_EINVAL, "krylov must be in 0..200"};
+        if (opt->transfer != 0 && opt->transfer != 1) throw Error{ADR_EINVAL, "transfer must be 0 or 1"};
+        if (opt->transfer == 1 && opt->krylov != 0)
+            throw Error{ADR_EINVAL, "krylov applies to the grid transfer (transfer = 0)"};
         if (opt->fp32_sweeps < 0) throw Error{ADR_EINVAL, "fp32_sweeps must be >= 0"};
         C->opt = *opt;
         C->n_inst = n_probs;
@@ -651,6 +678,15 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         for (int i = 0; i < n; ++i)
             if (errs[i].code != ADR_OK)
                 throw Error{errs[i].code, "instance " + std::to_string(i) + ": " + errs[i].msg};
+        if (opt->transfer == 1) {
+            run_pool([&](int i) {
+                adr::build_direct(G[i].g, G[i].fam[0], G[i].hk[0], G[i].fam[1], G[i].drec[0]);
+                adr::build_direct(G[i].g, G[i].fam[1], G[i].hk[1], G[i].fam[0], G[i].drec[1]);
+            });
+            for (int i = 0; i < n; ++i)
+                if (errs[i].code != ADR_OK)
+                    throw Error{errs[i].code, "instance " + std::to_string(i) + ": " + errs[i].msg};
+        }
 
         if (opt->host_only) {
             C->goff.assign(n + 1, 0);
@@ -752,6 +788,13 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         C->blist = dalloc<int>(std::max(nblk, 1), own);
         HIPCHK(hipMemsetAsync(C->blist, 0, sizeof(int) * std::max(nblk, 1), st));  // valid indices from the start
 
+        // node offsets of each family's instances (the direct records of one
+        // family index the other's nodes)
+        std::vector<int64_t> noffs[2];
+        for (int f = 0; f < 2; ++f) {
+            noffs[f].assign(n + 1, 0);
+            for (int i = 0; i < n; ++i) noffs[f][i + 1] = noffs[f][i] + static_cast<int64_t>(G[i].fam[f].x.size());
+        }
         for (int f = 0; f < 2; ++f) {
             DevFam &F = C->fam[f];
             std::vector<int64_t> noff(n + 1, 0);
@@ -860,6 +903,34 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             F.a64.fit = f == 0 ? C->fit : nullptr;
             F.a32.fit = f == 0 ? C->fit : nullptr;
             F.a32.ptol = opt->pivot_tol > 0.0 ? opt->pivot_tol : 64.0 * 1.1920928955078125e-07;
+            if (opt->transfer == 1) {
+                // direct-transfer records: source nodes in the other family's packed numbering
+                std::vector<int> dk(2 * static_cast<size_t>(F.n_nodes), -1);
+                std::vector<double> dw(4 * static_cast<size_t>(F.n_nodes), 0.0);
+                for (int i = 0; i < n; ++i) {
+                    const std::vector<adr::DirRec> &D = G[i].drec[f];
+                    for (size_t k = 0; k < D.size(); ++k) {
+                        const size_t gk = static_cast<size_t>(noff[i]) + k;
+                        for (int e = 0; e < 2; ++e)
+                            dk[2 * gk + e] = D[k].k[e] < 0 ? -1 : static_cast<int>(noffs[1 - f][i] + D[k].k[e]);
+                        for (int e = 0; e < 4; ++e) dw[4 * gk + e] = D[k].w[e];
+                    }
+                }
+                F.a64d = F.a64;
+                F.a64d.dk = reinterpret_cast<const int2 *>(upload(dk, own, st));
+                F.a64d.dw = upload(dw, own, st);
+                if (f == 1) {
+                    // update sums of the gamma-curves, grouped by instance in list order
+                    std::vector<int> start(n + 1, 0), slot(F.n_lines);
+                    for (int i = 0; i < n; ++i) start[i + 1] = start[i] + F.inst_lines[i];
+                    std::vector<int> next(start.begin(), start.end() - 1);
+                    for (int l = 0; l < F.n_lines; ++l) slot[l] = next[linst[l]]++;
+                    C->inst_lstart = upload(start, own, st);
+                    C->lpart = dalloc<double>(std::max(F.n_lines, 1), own);
+                    F.a64d.lpart = C->lpart;
+                    F.a64d.lslot = upload(slot, own, st);
+                }
+            }
             // scatter records
             std::vector<int> rk(4 * static_cast<size_t>(npad), -1);
             std::vector<double> ra(4 * static_cast<size_t>(npad), 0.0), rb(4 * static_cast<size_t>(npad), 0.0);
@@ -952,6 +1023,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             C->ccount = dalloc<int>(1, own);
         }
         C->cnorm = dalloc<double>(n, own);
+        C->cnorm_d = dalloc<double>(n, own);
         C->rel = dalloc<double>(n, own);
         C->rel_fb = dalloc<double>(n, own);
         C->done = dalloc<int>(n, own);
@@ -1013,6 +1085,7 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs) {
         ctx->err = "adr_update needs the set-up's instance count on a device context";
         return ADR_EINVAL;
     }
+    ctx->cnorm_d_valid = false;
     try {
         const int n = ctx->n_inst;
         for (int i = 0; i < n; ++i) {
@@ -1217,10 +1290,79 @@ static adr_status krylov_iterate(adr_ctx *ctx, double *u, int32_t max_iters, dou
     return status;
 }
 
+// The stationary iteration with the interpolation-free transfer: the state is
+// the gamma-curve values (fam[1].v64), every sweep FP64.  The start is the
+// bilinear gather of u onto the gamma-curves; an instance stops at the first
+// sweep whose update |v' - v| over its interior gamma nodes is <= tol |Phi(0)|
+// (Phi(0): the sweep from zero interior values); the done flags are read every
+// kDirectCheck sweeps and the launch lists compacted to the unfinished
+// instances.  u receives the scatter of the last gamma values (Sec. 6).
+constexpr int kDirectCheck = 4;
+static adr_status direct_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol, int32_t *iters,
+                                 double *rel_res) {
+    const int n = ctx->n_inst;
+    hipStream_t st = ctx->st;
+    DevFam &FG = ctx->fam[1];
+    HIPCHK(adr::launch_fill_int(ctx->done, 0, n, st));
+    HIPCHK(adr::launch_fill_int(ctx->conv_it, 0, n, st));
+    HIPCHK(adr::launch_fill_int(ctx->sing, 0, n, st));
+    if (!ctx->cnorm_d_valid) {
+        HIPCHK(adr::launch_line_values(FG.a64d, FG.n_lines, nullptr, FG.v64, st));
+        ctx->direct_sweep(ctx->never);
+        ctx->direct_norm(0, 0.0, 1);
+        ctx->cnorm_d_valid = true;
+    }
+    ctx->to_blocked(u);
+    HIPCHK(adr::launch_line_values(FG.a64d, FG.n_lines, ctx->Ub, FG.v64, st));
+    std::vector<int> dn(n, 0);
+    int k = 0;
+    while (k < max_iters) {
+        const int m = std::min(kDirectCheck, max_iters - k);
+        for (int q = 0; q < m; ++q) {
+            ctx->direct_sweep(ctx->done);
+            ctx->direct_norm(1, tol, 0);
+        }
+        k += m;
+        HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; })) break;
+        if (n > 1) ctx->compact(dn);
+    }
+    ctx->uncompact();
+    HIPCHK((adr::launch_scatter<double, double>(0, FG.s64, FG.v64, ctx->Ub, ctx->d32, ctx->partial, ctx->never, st)));
+    ctx->from_blocked(u);
+    std::vector<int> ci(n, 0);
+    std::vector<double> rr(n, 0.0);
+    HIPCHK(hipMemcpyAsync(ci.data(), ctx->conv_it, sizeof(int) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(rr.data(), ctx->rel, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const adr_status sst = ctx->singular_status();
+    adr_status status = ADR_OK;
+    for (int i = 0; i < n; ++i) {
+        if (iters) iters[i] = ci[i];
+        if (rel_res) rel_res[i] = max_iters > 0 ? rr[i] : NAN;
+        if (max_iters > 0 && !std::isfinite(rr[i])) status = ADR_ENONFINITE;
+        else if (!dn[i] && status == ADR_OK) status = ADR_ENOTCONV;
+    }
+    if (sst != ADR_OK) return sst;
+    if (status == ADR_ENONFINITE) ctx->err = "non-finite residual";
+    return status;
+}
+
 // The stationary iteration; with a fallback start, the start u is judged by
 // the first sweep (see adr_split_iterate_judged).
 static adr_status split_iterate(adr_ctx *ctx, double *u, const double *fallback, int32_t max_iters, double tol,
                                 int32_t *iters, double *rel_res, int32_t *used_fallback) {
+    if (ctx->opt.transfer == 1) {
+        if (fallback)
+            return fail_ctx(ctx, Error{ADR_EINVAL, "the judged solve runs on the grid transfer (transfer = 0)"});
+        try {
+            return direct_iterate(ctx, u, max_iters, tol, iters, rel_res);
+        } catch (const Error &e) {
+            ctx->uncompact();
+            return fail_ctx(ctx, e);
+        }
+    }
     if (ctx->opt.krylov > 0 && !fallback && max_iters > 0) {
         try {
             return krylov_iterate(ctx, u, max_iters, tol, iters, rel_res);
@@ -1369,8 +1511,9 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
                         int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes,
                         int32_t *best_krylov) {
     if (!ctx) return ADR_EINVAL;
-    if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES) {
-        ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0 and FP32_LINES precision";
+    if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES ||
+        ctx->opt.transfer != 0) {
+        ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0, FP32_LINES precision and the grid transfer";
         return ADR_EINVAL;
     }
     // (FP32 sweeps per FP64 sweep or their maximum, adaptive)
@@ -1684,6 +1827,22 @@ adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, 
             if (ca) ca[4 * r + q] = R[r].ca[q];
             if (cb) cb[4 * r + q] = R[r].cb[q];
         }
+    }
+    return ADR_OK;
+}
+
+adr_status adr_export_direct(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_nodes, int32_t *k,
+                             double *w) {
+    if (!ctx || !ctx->opt.host_only || ctx->opt.transfer != 1 || inst < 0 || inst >= ctx->n_inst || family < 0 ||
+        family > 1)
+        return ADR_EINVAL;
+    const std::vector<adr::DirRec> &D = ctx->host_geo[inst].drec[family];
+    if (n_nodes) *n_nodes = static_cast<int64_t>(D.size());
+    for (size_t q = 0; q < D.size(); ++q) {
+        for (int e = 0; e < 2; ++e)
+            if (k) k[2 * q + e] = D[q].k[e];
+        for (int e = 0; e < 4; ++e)
+            if (w) w[4 * q + e] = D[q].w[e];
     }
     return ADR_OK;
 }

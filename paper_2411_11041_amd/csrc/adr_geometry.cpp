@@ -10,8 +10,16 @@
 // a last element shorter than 0.1 h is merged into the previous one.  Seeds
 // sit at mid-increments h of the measure int |n.b| ds on every connected
 // inflow arc (midpoint rule on sub-segments of length <= h/4).  At a grid node
-// the two estimates of the scatter are combined with weights
-// 1 / (dL*dR + (h/10)^2) (the plain average when the brackets are alike).
+// the scatter takes the plain average of its horizontal and vertical
+// estimates; where only one of them is local (both brackets within
+// kLocalEdges edges of the node) that one alone.
+//
+// The interpolation-free transfer (the conclusions' second improvement): the
+// segments of the two families are intersected (candidates: the pairs whose
+// bounding boxes share a grid cell), and each interior node of a target curve
+// takes the linear interpolant, in arc length along its curve, between the
+// nearest intersections at or before and at or after it (the curve's end on a
+// side without one).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -647,6 +655,146 @@ void rebuild_for_source(const InstanceGeo &base, const adr_problem &p, InstanceG
     if (!finite_all(p.f, static_cast<size_t>(p.nx) * p.ny)) fail(ADR_ENONFINITE, "non-finite f");
     G = base;
     compute_load(p, G);
+}
+
+
+// ------------------------------------------------------- direct transfer
+namespace {
+#pragma clang fp contract(off)
+struct Hit {
+    int64_t kt;   // first node of the target segment
+    double s;     // position on it
+    int64_t ks;   // first node of the source segment
+    double t;     // position on it
+};
+
+void cell_range(double p0, double p1, double org, double h, int n_cells, int &lo, int &hi) {
+    lo = static_cast<int>(std::floor((std::min(p0, p1) - org) / h));
+    hi = static_cast<int>(std::floor((std::max(p0, p1) - org) / h));
+    lo = std::min(std::max(lo, 0), n_cells - 1);
+    hi = std::min(std::max(hi, 0), n_cells - 1);
+}
+
+std::vector<int64_t> segment_starts(const Family &F) {
+    std::vector<int64_t> k;
+    const int nl = static_cast<int>(F.off.size()) - 1;
+    for (int l = 0; l < nl; ++l)
+        for (int64_t q = F.off[l]; q + 1 < F.off[l + 1]; ++q) k.push_back(q);
+    return k;
+}
+}  // namespace
+
+void build_direct(const Grid &g, const Family &tgt, const std::vector<double> &htgt, const Family &src,
+                  std::vector<DirRec> &out) {
+    const int ncx = g.nx - 1, ncy = g.ny - 1;
+    const std::vector<int64_t> kt_all = segment_starts(tgt), ks_all = segment_starts(src);
+    // source segments by cell (compressed rows)
+    const size_t nsrc = ks_all.size();
+    std::vector<int> si0(nsrc), si1(nsrc), sj0(nsrc), sj1(nsrc);
+    std::vector<int64_t> cnt(static_cast<size_t>(ncx) * ncy + 1, 0);
+    for (size_t e = 0; e < nsrc; ++e) {
+        const int64_t k = ks_all[e];
+        cell_range(src.x[k], src.x[k + 1], g.a, g.hx, ncx, si0[e], si1[e]);
+        cell_range(src.y[k], src.y[k + 1], g.c, g.hy, ncy, sj0[e], sj1[e]);
+        for (int j = sj0[e]; j <= sj1[e]; ++j)
+            for (int i = si0[e]; i <= si1[e]; ++i) ++cnt[static_cast<size_t>(j) * ncx + i + 1];
+    }
+    for (size_t c = 1; c < cnt.size(); ++c) cnt[c] += cnt[c - 1];
+    std::vector<int> members(static_cast<size_t>(cnt.back()));
+    {
+        std::vector<int64_t> fill(cnt.begin(), cnt.end() - 1);
+        for (size_t e = 0; e < nsrc; ++e)
+            for (int j = sj0[e]; j <= sj1[e]; ++j)
+                for (int i = si0[e]; i <= si1[e]; ++i) members[fill[static_cast<size_t>(j) * ncx + i]++] = static_cast<int>(e);
+    }
+    // intersections per target segment, in target order; within a segment by (s, source segment)
+    std::vector<Hit> hits;
+    std::vector<Hit> seg_hits;
+    for (const int64_t k : kt_all) {
+        const double px0 = tgt.x[k], py0 = tgt.y[k], px1 = tgt.x[k + 1], py1 = tgt.y[k + 1];
+        int i0, i1, j0, j1;
+        cell_range(px0, px1, g.a, g.hx, ncx, i0, i1);
+        cell_range(py0, py1, g.c, g.hy, ncy, j0, j1);
+        seg_hits.clear();
+        for (int j = j0; j <= j1; ++j)
+            for (int i = i0; i <= i1; ++i) {
+                const size_t c = static_cast<size_t>(j) * ncx + i;
+                for (int64_t m = cnt[c]; m < cnt[c + 1]; ++m) {
+                    const int e = members[static_cast<size_t>(m)];
+                    // each pair once: in the first cell both boxes share
+                    if (i != std::max(i0, si0[e]) || j != std::max(j0, sj0[e])) continue;
+                    const int64_t q = ks_all[static_cast<size_t>(e)];
+                    const double rx = px1 - px0, ry = py1 - py0;
+                    const double qx = src.x[q + 1] - src.x[q], qy = src.y[q + 1] - src.y[q];
+                    const double wx = src.x[q] - px0, wy = src.y[q] - py0;
+                    const double den = rx * qy - ry * qx;
+                    if (den == 0.0) continue;
+                    const double sp = (wx * qy - wy * qx) / den;
+                    const double tp = (wx * ry - wy * rx) / den;
+                    if (sp >= 0.0 && sp <= 1.0 && tp >= 0.0 && tp <= 1.0) seg_hits.push_back(Hit{k, sp, q, tp});
+                }
+            }
+        std::sort(seg_hits.begin(), seg_hits.end(), [](const Hit &x, const Hit &y) {
+            return x.s != y.s ? x.s < y.s : x.ks < y.ks;
+        });
+        hits.insert(hits.end(), seg_hits.begin(), seg_hits.end());
+    }
+    // arc coordinates of the target nodes and of the intersections
+    const size_t nt = tgt.x.size();
+    std::vector<double> sig(nt, 0.0);
+    const int nl = static_cast<int>(tgt.off.size()) - 1;
+    for (int l = 0; l < nl; ++l) {
+        double acc = 0.0;
+        for (int64_t q = tgt.off[l] + 1; q < tgt.off[l + 1]; ++q) {
+            acc = acc + htgt[static_cast<size_t>(q)];
+            sig[static_cast<size_t>(q)] = acc;
+        }
+    }
+    out.assign(nt, DirRec{{-1, -1}, {0.0, 0.0, 0.0, 0.0}});
+    size_t h0 = 0;
+    std::vector<double> xs;
+    for (int l = 0; l < nl; ++l) {
+        const int64_t a = tgt.off[l], b = tgt.off[l + 1];
+        size_t h1 = h0;
+        while (h1 < hits.size() && hits[h1].kt < b - 1) ++h1;
+        xs.resize(h1 - h0);
+        for (size_t e = h0; e < h1; ++e) xs[e - h0] = sig[static_cast<size_t>(hits[e].kt)] + hits[e].s * htgt[static_cast<size_t>(hits[e].kt + 1)];
+        const double send = sig[static_cast<size_t>(b - 1)];
+        for (int64_t q = a + 1; q < b - 1; ++q) {
+            const double sq = sig[static_cast<size_t>(q)];
+            const int64_t iL = (std::upper_bound(xs.begin(), xs.end(), sq) - xs.begin()) - 1;  // last <= sq
+            const int64_t iR = std::lower_bound(xs.begin(), xs.end(), sq) - xs.begin();          // first >= sq
+            const double sL = iL >= 0 ? xs[static_cast<size_t>(iL)] : 0.0;
+            const double sR = iR < static_cast<int64_t>(xs.size()) ? xs[static_cast<size_t>(iR)] : send;
+            double wL = 1.0, wR = 0.0;
+            if (sR > sL) {
+                wL = (sR - sq) / (sR - sL);
+                wR = (sq - sL) / (sR - sL);
+            }
+            DirRec &R = out[static_cast<size_t>(q)];
+            if (iL >= 0) {
+                const Hit &H = hits[h0 + static_cast<size_t>(iL)];
+                R.k[0] = static_cast<int32_t>(H.ks);
+                R.w[0] = wL * (1.0 - H.t);
+                R.w[1] = wL * H.t;
+            } else {
+                R.k[0] = -1;
+                R.w[0] = wL;
+                R.w[1] = 0.0;
+            }
+            if (iR < static_cast<int64_t>(xs.size())) {
+                const Hit &H = hits[h0 + static_cast<size_t>(iR)];
+                R.k[1] = static_cast<int32_t>(H.ks);
+                R.w[2] = wR * (1.0 - H.t);
+                R.w[3] = wR * H.t;
+            } else {
+                R.k[1] = -1;
+                R.w[2] = wR;
+                R.w[3] = 0.0;
+            }
+        }
+        h0 = h1;
+    }
 }
 
 }  // namespace adr

@@ -43,6 +43,17 @@ struct Rec4 {
 };
 
 // Everything the device needs for one instance, in local indices.
+// The interpolation-free transfer onto one interior node of a target curve:
+// value = (k[0] >= 0 ? w[0] v[k[0]] + w[1] v[k[0]+1] : w[0] x_first)
+//       + (k[1] >= 0 ? w[2] v[k[1]] + w[3] v[k[1]+1] : w[2] x_last)
+// with v the other family's line values (k: first node of the source segment
+// of the bracket; -1: the target curve's own end on that side, whose
+// Dirichlet value x_first or x_last it carries).
+struct DirRec {
+    int32_t k[2];
+    double w[4];
+};
+
 struct InstanceGeo {
     Grid g;
     double mu, sigma;
@@ -56,6 +67,7 @@ struct InstanceGeo {
     std::vector<double> wk;            // beta family: |beta| at the node
     std::vector<double> Lk;            // beta family: load int f phi_k (0 at ends)
     std::vector<Rec4> rec[2];          // per interior node (inner_list order)
+    std::vector<DirRec> drec[2];       // direct transfer onto family f's nodes (options.transfer = 1)
     std::vector<double> gend[2];       // per curve: Dirichlet data at its first and last node
     bool has_g = false;                // non-zero Dirichlet data given
 };
@@ -63,6 +75,11 @@ struct InstanceGeo {
 // Message returned by adr_last_error(NULL) in this thread (failed set-up or
 // context-free call).
 void set_thread_error(const std::string &msg);
+
+// Direct-transfer records of every node of tgt (interior nodes; ends unused)
+// from the line values of src; htgt: tgt's chords (hk).
+void build_direct(const Grid &g, const Family &tgt, const std::vector<double> &htgt, const Family &src,
+                  std::vector<DirRec> &out);
 
 // Builds the geometry of one instance; throws Error.
 void build_instance(const adr_problem &p, InstanceGeo &out);

@@ -24,6 +24,15 @@ struct LineArgs {
     double ptol;         // relative pivot threshold (of |diagonal| + |eliminated part|)
     const double *fit;   // optional (beta family): per instance 1 / (2 mu) of the exponentially
                          // fitted stiffness; NULL: plain Galerkin rows
+    // interpolation-free transfer (FP64 only): when dk is set the node values
+    // come from the other family's line values fin instead of the bilinear
+    // gather: node k takes (dk[k].x >= 0 ? dw[4k] fin[dk.x] + dw[4k+1] fin[dk.x+1] : dw[4k] x_first)
+    // + (dk[k].y >= 0 ? dw[4k+2] fin[dk.y] + dw[4k+3] fin[dk.y+1] : dw[4k+2] x_last)
+    const int2 *dk;
+    const T *dw;
+    double *lpart;       // optional with dk: per line, sum over its interior nodes of
+                         // (new value - old value in vout)^2, at lpart[lslot[line]]
+    const int *lslot;
 };
 
 // Record indices relative to the slot's first record (ScatterArgs::rd)
@@ -120,6 +129,11 @@ hipError_t launch_kscale(double *v, const double *scale, int kmax, const KChunks
                          hipStream_t st);
 // r = phi - u on the interior nodes (gb: blocked index of each scatter slot, -1 padding)
 hipError_t launch_kresidual(const int *gb, int npad, const double *phi, const double *u, double *r, hipStream_t st);
+
+// v on the curve nodes of a's family: the Dirichlet values at the ends (a.gend,
+// or zero) and on the interior nodes the bilinear gather of U (eq. (22)), or
+// zero when U is NULL.  One workgroup per curve of the full list.
+hipError_t launch_line_values(const LineArgs<double> &a, int n_lines, const double *U, double *v, hipStream_t st);
 
 // Lout = Lbase + M G un / dt on the interior nodes of the beta-curves (the
 // full line list of a), ends copied: the load of an implicit Euler step.

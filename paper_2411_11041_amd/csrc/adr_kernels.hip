@@ -45,7 +45,7 @@ __device__ inline int xcd_position(int w, int G) {
 
 // NT threads per curve (the workgroup); a curve of n nodes needs n <= NT * MAXJ.
 // pos: the workgroup's position in the launch's part of the line list.
-template <typename T, int FAM, int MAXJ, int NT>
+template <typename T, int FAM, int MAXJ, int NT, bool DIR>
 __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restrict__ fin, T *__restrict__ vout,
                                           const double *__restrict__ par, const int *__restrict__ done, int nmax,
                                           int pos) {
@@ -111,7 +111,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         cj[sl] = -1;
         lxj[sl] = T(0);
         lyj[sl] = T(0);
-        if (j > 0 && j < n - 1) {
+        if (!DIR && j > 0 && j < n - 1) {
             const int kn = o + j;
             cj[sl] = a.cell[kn];
             lxj[sl] = a.lx[kn];
@@ -127,6 +127,42 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
 #pragma unroll
     for (int q0 = 0; q0 < MAXJ; q0 += G) {
         T p11[G], p12[G], p21[G], p22[G];
+        if constexpr (DIR) {
+            // the brackets of the direct transfer: two source segments (or the
+            // curve's own ends) per node, their four values issued together
+            int2 dk[G];
+            T dw[G][4];
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                const int j = tid + NT * (q0 + t);
+                const bool in = j > 0 && j < n - 1;
+                dk[t] = in ? a.dk[o + j] : make_int2(-1, -1);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) dw[t][e] = in ? a.dw[4 * static_cast<int64_t>(o + j) + e] : T(0);
+            }
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                const int kl = dk[t].x >= 0 ? dk[t].x : 0, kr = dk[t].y >= 0 ? dk[t].y : 0;
+                p11[t] = fin[kl];
+                p12[t] = fin[kl + 1];
+                p21[t] = fin[kr];
+                p22[t] = fin[kr + 1];
+            }
+#pragma unroll
+            for (int t = 0; t < G; ++t) {
+                const int sl = q0 + t;
+                const int j = tid + NT * sl;
+                const T vl = dk[t].x >= 0 ? dw[t][0] * p11[t] + dw[t][1] * p12[t] : dw[t][0] * x0;
+                const T vr = dk[t].y >= 0 ? dw[t][2] * p21[t] + dw[t][3] * p22[t] : dw[t][2] * xn;
+                const T uj = (j > 0 && j < n - 1) ? vl + vr : (j == 0 ? x0 : xn);
+                if (j < n) {
+                    U[j] = uj;
+                    if (j > 0) Hs[j] = hj[sl];
+                    if (FAM == 0) Ws[j] = wj[sl];
+                }
+            }
+            continue;
+        }
 #pragma unroll
         for (int t = 0; t < G; ++t) {
             // blocked field (8 x 4 nodes per block): the corner's position in its
@@ -343,25 +379,48 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         if (has_sep) X[rs + k - 1] = SR;
     }
     __syncthreads();
-    for (int j = tid; j < n; j += NT) vout[o + j] = j == 0 ? x0 : (j == n - 1 ? xn : X[j - 1]);
+    if constexpr (DIR) {
+        // the update of the curve's interior values, summed per line (fixed order)
+        double racc = 0.0;
+        for (int j = tid; j < n; j += NT) {
+            const T val = j == 0 ? x0 : (j == n - 1 ? xn : X[j - 1]);
+            if (a.lpart && j > 0 && j < n - 1) {
+                const double dlt = static_cast<double>(val) - static_cast<double>(vout[o + j]);
+                racc += dlt * dlt;
+            }
+            vout[o + j] = val;
+        }
+        if (a.lpart) {
+            double *red = reinterpret_cast<double *>(P1);  // the reduced system is no longer read
+            red[tid] = racc;
+            __syncthreads();
+            for (int w = NT / 2; w > 0; w >>= 1) {
+                if (tid < w) red[tid] += red[tid + w];
+                __syncthreads();
+            }
+            if (tid == 0) a.lpart[a.lslot[l]] = red[0];
+        }
+    } else {
+        for (int j = tid; j < n; j += NT) vout[o + j] = j == 0 ? x0 : (j == n - 1 ? xn : X[j - 1]);
+    }
     if (bad && a.sing) a.sing[inst] = 1;
 }
 
 // One launch for every curve of a family: curves are ordered longest first and
 // each workgroup picks the register footprint (nodes per thread) of its curve;
 // the kernel's registers are those of the largest footprint.
-template <typename T, int FAM>
+template <typename T, int FAM, bool DIR = false>
 __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
                                                    T *__restrict__ vout, const double *__restrict__ par,
                                                    const int *__restrict__ done, int nmax) {
     // the list order (longest first) is the dispatch order
     const int pos = static_cast<int>(blockIdx.x);
     const int per = (a.lcnt[a.lidx ? a.lidx[a.lbase + pos] : a.lbase + pos] + kThreads - 1) / kThreads;
-    if (per <= 1) line_body<T, FAM, 1, kThreads>(a, fin, vout, par, done, nmax, pos);
-    else if (per <= 2) line_body<T, FAM, 2, kThreads>(a, fin, vout, par, done, nmax, pos);
-    else if (per <= 4) line_body<T, FAM, 4, kThreads>(a, fin, vout, par, done, nmax, pos);
-    else if (per <= 8) line_body<T, FAM, 8, kThreads>(a, fin, vout, par, done, nmax, pos);
-    else line_body<T, FAM, 12, kThreads>(a, fin, vout, par, done, nmax, pos);
+    if (per <= 1) line_body<T, FAM, 1, kThreads, DIR>(a, fin, vout, par, done, nmax, pos);
+    else if (per <= 2) line_body<T, FAM, 2, kThreads, DIR>(a, fin, vout, par, done, nmax, pos);
+    else if (per <= 4) line_body<T, FAM, 4, kThreads, DIR>(a, fin, vout, par, done, nmax, pos);
+    else if (per <= 8) line_body<T, FAM, 8, kThreads, DIR>(a, fin, vout, par, done, nmax, pos);
+    else line_body<T, FAM, 12, kThreads, DIR>(a, fin, vout, par, done, nmax, pos);
 }
 
 // One launch per length bucket: every curve of the launch has at most
@@ -369,14 +428,14 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
 // resident workgroups for the short curves), its LDS sized by the bucket's
 // longest curve.  Short curves take smaller workgroups (128 or 64 threads,
 // 4 rows each): fewer idle lanes and a shorter reduced system.
-template <typename T, int FAM, int MAXJ, int NT>
+template <typename T, int FAM, int MAXJ, int NT, bool DIR = false>
 __global__ __launch_bounds__(NT) void k_line_b(LineArgs<T> a, const T *__restrict__ fin,
                                                T *__restrict__ vout, const double *__restrict__ par,
                                                const int *__restrict__ done, int nmax) {
     // the curves of one bucket have similar lengths: each XCD takes a contiguous
     // part of the list (one instance's neighbouring curves)
-    line_body<T, FAM, MAXJ, NT>(a, fin, vout, par, done, nmax,
-                                xcd_position(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)));
+    line_body<T, FAM, MAXJ, NT, DIR>(a, fin, vout, par, done, nmax,
+                                     xcd_position(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)));
 }
 
 // Scatter: out = P v on the interior nodes.  MODE 0: write; MODE 1 (FP64 sweep):
@@ -546,6 +605,28 @@ __global__ __launch_bounds__(kThreads) void k_shift_load(LineArgs<double> a, con
     }
 }
 
+// Curve values from a grid field: ends from gend (or 0), interior nodes the
+// bilinear gather of U (eq. (22)), or 0 when U is NULL.
+__global__ __launch_bounds__(kThreads) void k_line_values(LineArgs<double> a, const double *__restrict__ U,
+                                                          double *__restrict__ v) {
+    const int l = static_cast<int>(blockIdx.x);
+    const int o = a.loff[l], n = a.lcnt[l], inst = a.linst[l];
+    const int nx = a.inst_nx[inst];
+    for (int j = threadIdx.x; j < n; j += kThreads) {
+        double val = 0.0;
+        if (j == 0 || j == n - 1) {
+            val = a.gend ? a.gend[2 * l + (j == 0 ? 0 : 1)] : 0.0;
+        } else if (U) {
+            const int c = a.cell[o + j];
+            const int sx = (c & 7) == 7 ? 25 : 1;
+            const int cu = c + (((c >> 3) & 3) == 3 ? nx - 24 : 8);
+            const double lx = a.lx[o + j], ly = a.ly[o + j];
+            val = (1.0 - ly) * ((1.0 - lx) * U[c] + lx * U[c + sx]) + ly * ((1.0 - lx) * U[cu] + lx * U[cu + sx]);
+        }
+        v[o + j] = val;
+    }
+}
+
 // ------------------------------------------------------------------ compaction
 // active items (instance not done), order preserved: per-block counts, one
 // workgroup scans them, then every block writes its items' indices
@@ -634,35 +715,37 @@ void set_lds(K *kernel, size_t lds) {
                                   static_cast<int>(lds));
 }
 
-template <typename T, int FAM, int MAXJ, int NT>
+template <typename T, int FAM, int MAXJ, int NT, bool DIR>
 void launch_b(const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const double *par, const int *done, int nmax,
               hipStream_t st) {
     const size_t lds = sizeof(T) * static_cast<size_t>(line_lds_arrays(FAM)) * line_lds_stride(nmax, NT);
-    set_lds(&k_line_b<T, FAM, MAXJ, NT>, lds);
-    hipLaunchKernelGGL((k_line_b<T, FAM, MAXJ, NT>), dim3(n_lines), dim3(NT), lds, st, a, fin, vout, par, done, nmax);
+    set_lds(&k_line_b<T, FAM, MAXJ, NT, DIR>, lds);
+    hipLaunchKernelGGL((k_line_b<T, FAM, MAXJ, NT, DIR>), dim3(n_lines), dim3(NT), lds, st, a, fin, vout, par, done,
+                       nmax);
 }
 
 // buckets 0..4: curves of at most 3072, 2048, 1024, 512, 256 nodes; each
 // bucket's workgroup shapes (rows per thread x threads) cover its longest
 // curve, shape 0 first
-template <typename T, int FAM>
+template <typename T, int FAM, bool DIR>
 void launch_line_fam(int bucket, int shape, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
                      const double *par, const int *done, int nmax, hipStream_t st) {
     switch (bucket * 4 + shape) {
-        case 0: launch_b<T, FAM, 12, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 4: launch_b<T, FAM, 8, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 8: launch_b<T, FAM, 4, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 9: launch_b<T, FAM, 8, 128>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 12: launch_b<T, FAM, 4, 128>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 13: launch_b<T, FAM, 2, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 14: launch_b<T, FAM, 8, 64>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 16: launch_b<T, FAM, 4, 64>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 17: launch_b<T, FAM, 2, 128>(a, n_lines, fin, vout, par, done, nmax, st); break;
-        case 18: launch_b<T, FAM, 1, 256>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 0: launch_b<T, FAM, 12, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 4: launch_b<T, FAM, 8, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 8: launch_b<T, FAM, 4, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 9: launch_b<T, FAM, 8, 128, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 12: launch_b<T, FAM, 4, 128, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 13: launch_b<T, FAM, 2, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 14: launch_b<T, FAM, 8, 64, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 16: launch_b<T, FAM, 4, 64, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 17: launch_b<T, FAM, 2, 128, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 18: launch_b<T, FAM, 1, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
         default: {
             const size_t lds = line_lds_bytes<T>(FAM, nmax);
-            set_lds(&k_line<T, FAM>, lds);
-            hipLaunchKernelGGL((k_line<T, FAM>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done, nmax);
+            set_lds(&k_line<T, FAM, DIR>, lds);
+            hipLaunchKernelGGL((k_line<T, FAM, DIR>), dim3(n_lines), dim3(kThreads), lds, st, a, fin, vout, par, done,
+                               nmax);
             break;
         }
     }
@@ -686,8 +769,20 @@ hipError_t launch_line(int fam, int bucket, int shape, const LineArgs<T> &a, int
     if (nmax > 12 * kThreads || bucket > 4) return hipErrorInvalidValue;
     if (bucket >= 0 && line_bucket(nmax) < bucket) return hipErrorInvalidValue;  // curves too long for the bucket
     if (bucket >= 0 && (shape < 0 || shape >= line_shapes(bucket))) return hipErrorInvalidValue;
-    if (fam == 0) launch_line_fam<T, 0>(bucket, bucket < 0 ? 0 : shape, a, n_lines, fin, vout, par, done, nmax, st);
-    else launch_line_fam<T, 1>(bucket, bucket < 0 ? 0 : shape, a, n_lines, fin, vout, par, done, nmax, st);
+    const int sh = bucket < 0 ? 0 : shape;
+    if (a.dk) {
+        // the direct transfer runs in FP64 only
+        if constexpr (sizeof(T) == 8) {
+            if (fam == 0) launch_line_fam<T, 0, true>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
+            else launch_line_fam<T, 1, true>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (fam == 0) {
+        launch_line_fam<T, 0, false>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
+    } else {
+        launch_line_fam<T, 1, false>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
+    }
     return hipGetLastError();
 }
 
@@ -735,6 +830,12 @@ hipError_t launch_shift_load(const LineArgs<double> &a, int n_lines, int nmax, c
     const size_t lds = sizeof(double) * static_cast<size_t>(nmax);
     set_lds(&k_shift_load, lds);
     hipLaunchKernelGGL(k_shift_load, dim3(n_lines), dim3(kThreads), lds, st, a, Lbase, un, Lout, inv_dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_values(const LineArgs<double> &a, int n_lines, const double *U, double *v, hipStream_t st) {
+    if (n_lines == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_line_values, dim3(n_lines), dim3(kThreads), 0, st, a, U, v);
     return hipGetLastError();
 }
 

@@ -228,3 +228,49 @@ def test_ctypes_structs_follow_the_header():
     from paper_2411_11041_amd.adr import Options, Problem
     assert [f[0] for f in Problem._fields_] == _header_fields("adr_problem")
     assert [f[0] for f in Options._fields_] == _header_fields("adr_options")
+
+
+@pytest.mark.parametrize("maker", [lambda: W.c1(33), lambda: W.c2(65), lambda: W.data2d(31),
+                                   lambda: W.c4_instance(0, n_max=90), lambda: W.c4_instance(1, n_max=90),
+                                   lambda: W.c1(3), _axis_beta, _diag_beta])
+def test_host_direct_transfer_matches_oracle(maker):
+    """The set-up's direct-transfer records (intersections, arc-length
+    brackets, weights) equal the oracle's transfer matrix and end weights."""
+    from oracle import direct as D
+    from oracle.method import Oracle
+    from paper_2411_11041_amd.adr import Solver
+    p = maker()
+    s = Solver(p, host_only=True, transfer="direct")
+    o = Oracle(p)
+    for f in (0, 1):
+        tgt, src = o.fams[f], o.fams[1 - f]
+        X, e0, e1 = D.transfer(o.grid, tgt, src)
+        k, w = s.export_direct(0, f)
+        assert k.shape == (tgt.n_nodes, 2)
+        inner = np.nonzero(tgt.interior())[0]
+        dense = np.zeros((tgt.n_nodes, src.n_nodes))
+        ends = np.zeros((tgt.n_nodes, 2))
+        for side in (0, 1):
+            kk = k[:, side]
+            ok = kk >= 0
+            r = np.nonzero(ok)[0]
+            np.add.at(dense, (r, kk[ok]), w[ok, 2 * side])
+            np.add.at(dense, (r, kk[ok] + 1), w[ok, 2 * side + 1])
+            ends[~ok, side] = w[~ok, 2 * side]
+            assert np.all(w[~ok, 2 * side + 1] == 0.0)
+        assert np.max(np.abs(dense[inner] - X[inner].toarray())) < 1e-12
+        assert np.max(np.abs(ends[inner, 0] - e0[inner])) < 1e-12
+        assert np.max(np.abs(ends[inner, 1] - e1[inner])) < 1e-12
+    s.close()
+
+
+def test_direct_transfer_option_errors():
+    from paper_2411_11041_amd.adr import ADRError, Solver, ADR_EINVAL
+    p = W.c1(17)
+    with pytest.raises(ADRError) as e:
+        Solver(p, host_only=True, transfer="direct", krylov=10)
+    assert e.value.code == ADR_EINVAL
+    s = Solver(p, host_only=True)
+    with pytest.raises(ADRError):
+        s.export_direct(0, 0)  # the grid transfer builds no direct records
+    s.close()

@@ -1,0 +1,136 @@
+"""The interpolation-free transfer (options.transfer = 1) on the HIP path,
+against oracle.direct: sweeps, the converged fixed point, batches with
+Dirichlet data, and the accuracy against the grid route."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct as D
+from oracle.method import Oracle
+
+from test_gpu_boundary import _affine, dev, rel_l2, solver, with_g
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _oracle_sweeps(o, U0, k):
+    ds = D.DirectSweeps(o)
+    v = ds.start(U0)
+    for _ in range(k):
+        v = ds.sweep(v, 1.0, 0.05)
+    return o.scatter(1, v)
+
+
+@pytest.mark.parametrize("sweeps", [1, 3, 9])
+def test_direct_sweeps_match_oracle(sweeps):
+    """A batch (C1 65^2, a disc and an L-shape with Dirichlet data), a given
+    number of sweeps from a non-zero start: the scattered gamma values equal
+    the oracle's to 1e-11."""
+    print(f"[case] direct transfer, batch c1/disc/L with g, {sweeps} sweeps", flush=True)
+    probs = [W.c1(65), with_g(W.c4_instance(0, n_max=90)), with_g(W.c4_instance(1, n_max=90))]
+    orcs = [Oracle(p) for p in probs]
+    s = solver(probs, precision="fp64", theta=1.0, dt=0.05, transfer="direct")
+    off = s.layout()
+    starts = []
+    for p, o in zip(probs, orcs):
+        X, Y = p.coords()
+        starts.append(o.with_boundary((np.sin(2 * X) * Y).ravel()))
+    u = dev(np.concatenate(starts))
+    it, rel, st = s.split_iterate(u, sweeps, 0.0)
+    torch.cuda.synchronize()
+    assert st == 1 and np.all(it == sweeps)  # ADR_ENOTCONV at tol = 0
+    got = u.cpu().numpy()
+    for i, o in enumerate(orcs):
+        U = _oracle_sweeps(o, starts[i], sweeps)
+        assert rel_l2(got[off[i]:off[i + 1]], U, o.inner_idx) < 1e-11, i
+    s.close()
+
+
+@pytest.mark.parametrize("name", ["c2_129", "data2d_61"])
+def test_direct_converged_matches_oracle(name):
+    """To rel <= 1e-10: the same sweep count (+-1) and the oracle's fixed point."""
+    print(f"[case] direct transfer converged, {name}", flush=True)
+    p = W.c2(129) if name == "c2_129" else W.data2d(61)
+    o = Oracle(p)
+    U, it_o, rel_o, _, _ = D.DirectSweeps(o).iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-10)
+    for prec in ("fp64", "fp32"):
+        s = solver(p, precision=prec, theta=1.0, dt=0.05, transfer="direct")
+        u = dev(o.zero_field())
+        it, rel, st = s.split_iterate(u, 3000, 1e-10)
+        torch.cuda.synchronize()
+        assert st == 0 and rel[0] <= 1e-10
+        assert abs(int(it[0]) - it_o) <= 1, (int(it[0]), it_o)
+        assert rel_l2(u.cpu().numpy(), U, o.inner_idx) < 1e-9
+        s.close()
+
+
+def test_direct_batch_compaction_matches_single_solves():
+    """Instances that stop at different sweeps: the batch equals each instance
+    solved alone, bitwise, with the same sweep counts."""
+    print("[case] direct transfer batch vs single solves", flush=True)
+    probs = [W.c4_instance(i, n_max=100) for i in range(5)]
+    s = solver(probs, precision="fp64", theta=1.0, dt=0.05, transfer="direct")
+    off = s.layout()
+    u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    it, rel, st = s.split_iterate(u, 3000, 1e-9)
+    torch.cuda.synchronize()
+    assert st == 0 and len(set(it.tolist())) > 1
+    got = u.cpu().numpy()
+    s.close()
+    for i, p in enumerate(probs):
+        s1 = solver(p, precision="fp64", theta=1.0, dt=0.05, transfer="direct")
+        v = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+        it1, _, st1 = s1.split_iterate(v, 3000, 1e-9)
+        torch.cuda.synchronize()
+        assert st1 == 0 and it1[0] == it[i]
+        assert np.array_equal(v.cpu().numpy(), got[off[i]:off[i + 1]]), i
+        s1.close()
+
+
+@pytest.mark.parametrize("kind,beta", [("box", (1.0, 0.5)), ("disc", (0.6, -1.1)), ("L", (-0.8, 0.3))])
+def test_direct_affine_solution_on_gpu(kind, beta):
+    print(f"[case] direct transfer, affine exact solution, {kind}", flush=True)
+    p, uex = _affine(kind, 25, beta)
+    o = Oracle(p)
+    s = solver(p, precision="fp64", theta=1.0, dt=0.05, transfer="direct")
+    u = dev(o.zero_field())
+    it, rel, st = s.split_iterate(u, 3000, 1e-13)
+    torch.cuda.synchronize()
+    assert st == 0
+    m = o.inner_idx
+    assert np.max(np.abs(u.cpu().numpy()[m] - uex[m])) < 1e-9
+    s.close()
+
+
+def test_direct_transfer_more_accurate_than_grid_route():
+    """Manufactured solution (C1 129^2): the direct route's fixed point is
+    nearer the exact solution than the grid route's at the same pseudo step."""
+    print("[case] direct vs grid transfer accuracy, c1 129", flush=True)
+    p = W.c1(129)
+    X, Y = p.coords()
+    ue = W.manufactured_u(X, Y).ravel()
+    m = Oracle(p).inner_idx
+    errs = {}
+    for tr in ("grid", "direct"):
+        s = solver(p, precision="fp64", theta=1.0, dt=0.05, transfer=tr)
+        u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+        it, rel, st = s.split_iterate(u, 5000, 1e-11)
+        torch.cuda.synchronize()
+        assert st == 0
+        errs[tr] = np.max(np.abs(u.cpu().numpy()[m] - ue[m]))
+        s.close()
+    print(f"[case] max error grid {errs['grid']:.3e} direct {errs['direct']:.3e}", flush=True)
+    assert errs["direct"] < errs["grid"]
+
+
+def test_direct_transfer_refuses_what_it_does_not_serve():
+    from paper_2411_11041_amd.adr import ADRError, ADR_EINVAL
+    p = W.c1(33)
+    s = solver(p, precision="fp32", theta=1.0, dt=0.05, transfer="direct")
+    u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+    with pytest.raises(ADRError) as e:
+        s.autotune(u, 100, 1e-8)
+    assert e.value.code == ADR_EINVAL
+    s.close()
