@@ -83,13 +83,19 @@ def scatter_bytes(prec, fam, counts, march=False):
     return vals + grid, meta
 
 
-def direct_line_bytes(fam):
-    """FP64 line solve of the direct transfer, per line unknown: algorithmic =
-    one source value, the chord, |beta| and the load (beta), the old value
-    (gamma: the update norm) and the written value; tables = the two bracket
-    indices and four weights."""
-    alg = 8 + 8 + (16 if fam == 0 else 8) + 8
-    return alg, 8 + 32
+def direct_line_bytes(prec, fam):
+    """Line solve of the direct transfer, per line unknown (w = 4 FP32, 8
+    FP64): algorithmic = one source value, the chord, |beta| (beta), the load
+    (beta, FP64 sweeps only), the written value, and on the gamma-curves the
+    update: FP64 sweeps read the old value and write the FP32 increment, FP32
+    sweeps read and write the FP64 state; tables = the two bracket indices and
+    four weights."""
+    w = 4 if prec == "fp32" else 8
+    if fam == 0:
+        alg = w + w + w + (w if prec == "fp64" else 0) + w
+    else:
+        alg = w + w + w + (8 + 4 if prec == "fp64" else 16)
+    return alg, 8 + 4 * w
 
 
 def kernel_name(prec, cls, split_lines=0, march=False):
@@ -119,7 +125,7 @@ def roofline(times, counts, split_lines=0, march=False, profile=None, direct=Fal
                 continue
             fam = 0 if cls.endswith("beta") else 1
             if cls.startswith("line"):
-                alg, meta = direct_line_bytes(fam) if direct else line_bytes(prec, fam)
+                alg, meta = direct_line_bytes(prec, fam) if direct else line_bytes(prec, fam)
             else:
                 alg, meta = scatter_bytes(prec, fam, counts, march)
             sec = ms / 1e3
@@ -186,6 +192,8 @@ def parse():
     ap.add_argument("--cpu-sweeps", type=int, default=3, help="FP64 oracle sweeps per worker process")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle worker processes (0: one per host core, <= 16)")
     ap.add_argument("--acc-n", type=int, default=1025, help="direct leg: grid of the accuracy comparison (C1)")
+    ap.add_argument("--direct-sweeps", type=int, default=12,
+                    help="direct leg: at most this many FP32 sweeps per FP64 sweep (adaptive schedule)")
     ap.add_argument("--workload", choices=["all", "c2", "c3", "c4", "c5", "direct"], default="all",
                     help="all: c2 (the step and value) with the c4 and c5 legs (default); c2: one 2049^2 problem; "
                          "c3: the 2049^2 parabolic march (200 steps); c4: the 512-instance batch; "
@@ -314,18 +322,23 @@ def leg_c2(args):
 
 
 def leg_direct(args):
-    """The interpolation-free transfer against the grid route, both in FP64:
-    C2 time to 1e-8 and sweeps, and the distance of each route's fixed point
-    from the exact solution of the manufactured problem (C1)."""
+    """The interpolation-free transfer against the grid route: C2 time to 1e-8
+    and sweeps with every sweep in FP64 (both routes) and with FP32 increment
+    sweeps under the adaptive schedule (direct route; the grid route's is the
+    main leg), and the distance of each route's fixed point from the exact
+    solution of the manufactured problem (C1)."""
     import numpy as np
     import torch
     import workloads as W
     from paper_2411_11041_amd.adr import Solver
     p = W.c2(args.n)
     res = {}
-    for tr in ("grid", "direct"):
+    variants = (("grid_fp64", "grid", {"precision": "fp64"}),
+                ("direct_fp64", "direct", {"precision": "fp64"}),
+                ("direct_fp32", "direct", {"precision": "fp32", "fp32_sweeps": args.direct_sweeps, "adaptive": True}))
+    for name, tr, kw in variants:
         t0 = time.time()
-        s = Solver(p, precision="fp64", theta=1.0, dt=0.05, split_lines=0, transfer=tr)
+        s = Solver(p, theta=1.0, dt=0.05, split_lines=0, transfer=tr, **kw)
         setup_s = time.time() - t0
         counts = s.counts()
         per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
@@ -345,11 +358,11 @@ def leg_direct(args):
         el = time.perf_counter() - t0
         el_ev, times = events_pass(s, solve, args.steps)
         rf = roofline(times, counts, 0, direct=(tr == "direct"))
-        res[tr] = {"ms_per_step": round(1e3 * el / args.steps, 3), "sweeps": int(iters[0]),
-                   "final_rel": float(rel[0]), "value": per_sweep * int(iters[0]) * args.steps / el,
-                   "setup_s": round(setup_s, 2), "events_pass_ms_per_step": round(1e3 * el_ev / args.steps, 3),
-                   "roofline": rf, "kernels": kernels_table(times)}
-        log(f"direct leg: {tr} {res[tr]['ms_per_step']:.2f} ms, {res[tr]['sweeps']} sweeps")
+        res[name] = {"ms_per_step": round(1e3 * el / args.steps, 3), "sweeps": int(iters[0]),
+                     "final_rel": float(rel[0]), "value": per_sweep * int(iters[0]) * args.steps / el,
+                     "setup_s": round(setup_s, 2), "events_pass_ms_per_step": round(1e3 * el_ev / args.steps, 3),
+                     "roofline": rf, "kernels": kernels_table(times)}
+        log(f"direct leg: {name} {res[name]['ms_per_step']:.2f} ms, {res[name]['sweeps']} sweeps")
         s.close()
     # accuracy on the manufactured problem
     q = W.c1(args.acc_n)
@@ -360,17 +373,18 @@ def leg_direct(args):
         s = Solver(q, precision="fp64", theta=1.0, dt=0.05, transfer=tr)
         u = torch.zeros(q.nx * q.ny, dtype=torch.float64, device="cuda")
         s.split_iterate(u, 5000, 1e-11)
-        # interior nodes: the ones the solve wrote (the rest stays zero, as ue is zero on Gamma)
+        # the solve writes the interior nodes; the others stay zero, as ue is on Gamma
         e = np.abs(u.cpu().numpy() - ue)
         errs[tr] = float(e.max() / np.abs(ue).max())
         s.close()
-    return {"value": res["direct"]["value"], "unit": "line-unknowns/s", "ms_per_step": res["direct"]["ms_per_step"],
-            "roofline": res["direct"]["roofline"],
-            "config": {"workload": f"c2 {args.n}x{args.n} stationary to 1e-8, FP64 sweeps: values handed between "
-                                   "the families directly at their segment intersections (transfer=direct) "
-                                   "against the grid route (scatter + bilinear gather)",
-                       "direct": {k: v for k, v in res["direct"].items() if k != "roofline"},
-                       "grid_fp64": res["grid"],
+    best = res["direct_fp32"]
+    return {"value": best["value"], "unit": "line-unknowns/s", "ms_per_step": best["ms_per_step"],
+            "roofline": best["roofline"],
+            "config": {"workload": f"c2 {args.n}x{args.n} stationary to 1e-8: values handed between the families "
+                                   "directly at their segment intersections (transfer=direct) against the grid "
+                                   "route (scatter + bilinear gather)",
+                       "direct_fp32": {k: v for k, v in best.items() if k != "roofline"},
+                       "direct_fp64": res["direct_fp64"], "grid_fp64": res["grid_fp64"],
                        f"c1_{args.acc_n}_max_rel_error_vs_exact": errs}}
 
 

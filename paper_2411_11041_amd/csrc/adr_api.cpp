@@ -68,6 +68,7 @@ struct DevFam {
     adr::LineArgs<double> a64{};
     adr::LineArgs<double> a64d{};  // the same with the direct-transfer records (options.transfer = 1)
     adr::LineArgs<float> a32{};
+    adr::LineArgs<float> a32d{};
     adr::ScatterArgs<double> s64{};
     adr::ScatterArgs<float> s32{};
     double *v64 = nullptr;
@@ -439,13 +440,28 @@ struct adr_ctx {
 
     // One sweep of eq. (10) with the direct transfer: the beta-lines take their
     // input from the gamma-curve values, the gamma-lines from the beta-curve
-    // values (in place into fam[1].v64, with the per-line update sums).
-    void direct_sweep(const int *dn) {
+    // values (in place into fam[1].v64, with the per-line update sums; with
+    // keep_d the update also goes to fam[1].v32 as the first FP32 increment).
+    void direct_sweep(const int *dn, bool keep_d) {
         timed(0, 0, line_work(0), [&] {
             return lines<double>(0, fam[0].a64d, fam[1].v64, fam[0].v64, par_ptr(kSlotStep, 0), dn);
         });
+        adr::LineArgs<double> g = fam[1].a64d;
+        if (keep_d) g.dout = fam[1].v32;
         timed(0, 1, line_work(1), [&] {
-            return lines<double>(1, fam[1].a64d, fam[0].v64, fam[1].v64, par_ptr(kSlotStep, 1), dn);
+            return lines<double>(1, g, fam[0].v64, fam[1].v64, par_ptr(kSlotStep, 1), dn);
+        });
+    }
+    // One FP32 increment sweep with the direct transfer: d <- T d on the curve
+    // values (fam[f].v32), the gamma increments added to the FP64 state.
+    void direct_sweep32(const int *dn) {
+        timed(1, 0, line_work(0), [&] {
+            return lines<float>(0, fam[0].a32d, fam[1].v32, fam[0].v32, par_ptr(kSlotLin, 0), dn);
+        });
+        adr::LineArgs<float> g = fam[1].a32d;
+        g.vacc = fam[1].v64;
+        timed(1, 1, line_work(1), [&] {
+            return lines<float>(1, g, fam[0].v32, fam[1].v32, par_ptr(kSlotLin, 1), dn);
         });
     }
     void direct_norm(int count, double tol, int mode) {
@@ -919,6 +935,9 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 F.a64d = F.a64;
                 F.a64d.dk = reinterpret_cast<const int2 *>(upload(dk, own, st));
                 F.a64d.dw = upload(dw, own, st);
+                F.a32d = F.a32;
+                F.a32d.dk = F.a64d.dk;
+                F.a32d.dw = upload(to_type<float>(dw), own, st);
                 if (f == 1) {
                     // update sums of the gamma-curves, grouped by instance in list order
                     std::vector<int> start(n + 1, 0), slot(F.n_lines);
@@ -1291,12 +1310,16 @@ static adr_status krylov_iterate(adr_ctx *ctx, double *u, int32_t max_iters, dou
 }
 
 // The stationary iteration with the interpolation-free transfer: the state is
-// the gamma-curve values (fam[1].v64), every sweep FP64.  The start is the
-// bilinear gather of u onto the gamma-curves; an instance stops at the first
-// sweep whose update |v' - v| over its interior gamma nodes is <= tol |Phi(0)|
-// (Phi(0): the sweep from zero interior values); the done flags are read every
-// kDirectCheck sweeps and the launch lists compacted to the unfinished
-// instances.  u receives the scatter of the last gamma values (Sec. 6).
+// the gamma-curve values (fam[1].v64).  The start is the bilinear gather of u
+// onto the gamma-curves; an instance stops at the first FP64 sweep whose
+// update |v' - v| over its interior gamma nodes is <= tol |Phi(0)| (Phi(0):
+// the sweep from zero interior values).  FP64 precision: every sweep FP64, the
+// done flags read every kDirectCheck sweeps.  FP32_LINES: the FP64 sweep also
+// keeps its update as an FP32 increment d, and fp32_sweeps FP32 sweeps
+// d <- T d (each adding d to the state) precede every further FP64 sweep
+// (the block lengths chosen as in the grid route's adaptive schedule when
+// options.adaptive).  The launch lists follow the unfinished instances.  u
+// receives the scatter of the last gamma values (Sec. 6).
 constexpr int kDirectCheck = 4;
 static adr_status direct_iterate(adr_ctx *ctx, double *u, int32_t max_iters, double tol, int32_t *iters,
                                  double *rel_res) {
@@ -1308,25 +1331,54 @@ static adr_status direct_iterate(adr_ctx *ctx, double *u, int32_t max_iters, dou
     HIPCHK(adr::launch_fill_int(ctx->sing, 0, n, st));
     if (!ctx->cnorm_d_valid) {
         HIPCHK(adr::launch_line_values(FG.a64d, FG.n_lines, nullptr, FG.v64, st));
-        ctx->direct_sweep(ctx->never);
+        ctx->direct_sweep(ctx->never, false);
         ctx->direct_norm(0, 0.0, 1);
         ctx->cnorm_d_valid = true;
     }
     ctx->to_blocked(u);
     HIPCHK(adr::launch_line_values(FG.a64d, FG.n_lines, ctx->Ub, FG.v64, st));
     std::vector<int> dn(n, 0);
-    int k = 0;
-    while (k < max_iters) {
-        const int m = std::min(kDirectCheck, max_iters - k);
-        for (int q = 0; q < m; ++q) {
-            ctx->direct_sweep(ctx->done);
-            ctx->direct_norm(1, tol, 0);
-        }
-        k += m;
+    auto all_done = [&]() {
         HIPCHK(hipMemcpyAsync(dn.data(), ctx->done, sizeof(int) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        if (std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; })) break;
-        if (n > 1) ctx->compact(dn);
+        return std::all_of(dn.begin(), dn.end(), [](int v) { return v != 0; });
+    };
+    const bool fp32 = ctx->opt.precision == ADR_PREC_FP32_LINES;
+    if (!fp32) {
+        int k = 0;
+        while (k < max_iters) {
+            const int m = std::min(kDirectCheck, max_iters - k);
+            for (int q = 0; q < m; ++q) {
+                ctx->direct_sweep(ctx->done, false);
+                ctx->direct_norm(1, tol, 0);
+            }
+            k += m;
+            if (all_done()) break;
+            if (n > 1) ctx->compact(dn);
+        }
+    } else if (max_iters > 0) {
+        // a block: m FP32 increment sweeps, then the FP64 sweep and its norm
+        auto run = [&](int m) {
+            for (int q = 0; q < m; ++q) ctx->direct_sweep32(ctx->done);
+            ctx->direct_sweep(ctx->done, true);
+            ctx->direct_norm(m + 1, tol, 0);
+        };
+        run(0);
+        if (ctx->opt.adaptive) {
+            ctx->adaptive_blocks(ctx->Ub, max_iters, tol, dn, all_done, run, true);
+        } else {
+            const int m = ctx->opt.fp32_sweeps, period = m + 1;
+            const int blocks = (max_iters - 1) / period;
+            const int check = std::max(1, 8 / period);
+            for (int b = 0; b < blocks; ++b) {
+                run(m);
+                if ((b + 1) % check == 0) {
+                    if (all_done()) break;
+                    if (n > 1) ctx->compact(dn);
+                }
+            }
+        }
+        all_done();
     }
     ctx->uncompact();
     HIPCHK((adr::launch_scatter<double, double>(0, FG.s64, FG.v64, ctx->Ub, ctx->d32, ctx->partial, ctx->never, st)));

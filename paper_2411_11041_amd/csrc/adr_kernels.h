@@ -24,7 +24,7 @@ struct LineArgs {
     double ptol;         // relative pivot threshold (of |diagonal| + |eliminated part|)
     const double *fit;   // optional (beta family): per instance 1 / (2 mu) of the exponentially
                          // fitted stiffness; NULL: plain Galerkin rows
-    // interpolation-free transfer (FP64 only): when dk is set the node values
+    // interpolation-free transfer: when dk is set the node values
     // come from the other family's line values fin instead of the bilinear
     // gather: node k takes (dk[k].x >= 0 ? dw[4k] fin[dk.x] + dw[4k+1] fin[dk.x+1] : dw[4k] x_first)
     // + (dk[k].y >= 0 ? dw[4k+2] fin[dk.y] + dw[4k+3] fin[dk.y+1] : dw[4k+2] x_last)
@@ -33,6 +33,8 @@ struct LineArgs {
     double *lpart;       // optional with dk: per line, sum over its interior nodes of
                          // (new value - old value in vout)^2, at lpart[lslot[line]]
     const int *lslot;
+    float *dout;         // optional with dk: per node, new value - old value in vout (0 at the ends)
+    double *vacc;        // optional with dk: per interior node, vacc += new value
 };
 
 // Record indices relative to the slot's first record (ScatterArgs::rd)

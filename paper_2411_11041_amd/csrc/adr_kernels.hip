@@ -380,13 +380,20 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     }
     __syncthreads();
     if constexpr (DIR) {
-        // the update of the curve's interior values, summed per line (fixed order)
+        // the update of the curve's interior values (summed per line in a fixed
+        // order, and/or kept as the next increment), the state accumulation
         double racc = 0.0;
         for (int j = tid; j < n; j += NT) {
             const T val = j == 0 ? x0 : (j == n - 1 ? xn : X[j - 1]);
-            if (a.lpart && j > 0 && j < n - 1) {
-                const double dlt = static_cast<double>(val) - static_cast<double>(vout[o + j]);
-                racc += dlt * dlt;
+            if (j > 0 && j < n - 1) {
+                if (a.lpart || a.dout) {
+                    const double dlt = static_cast<double>(val) - static_cast<double>(vout[o + j]);
+                    racc += dlt * dlt;
+                    if (a.dout) a.dout[o + j] = static_cast<float>(dlt);
+                }
+                if (a.vacc) a.vacc[o + j] += static_cast<double>(val);
+            } else if (a.dout) {
+                a.dout[o + j] = 0.0f;
             }
             vout[o + j] = val;
         }
@@ -771,13 +778,8 @@ hipError_t launch_line(int fam, int bucket, int shape, const LineArgs<T> &a, int
     if (bucket >= 0 && (shape < 0 || shape >= line_shapes(bucket))) return hipErrorInvalidValue;
     const int sh = bucket < 0 ? 0 : shape;
     if (a.dk) {
-        // the direct transfer runs in FP64 only
-        if constexpr (sizeof(T) == 8) {
-            if (fam == 0) launch_line_fam<T, 0, true>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
-            else launch_line_fam<T, 1, true>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
-        } else {
-            return hipErrorInvalidValue;
-        }
+        if (fam == 0) launch_line_fam<T, 0, true>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
+        else launch_line_fam<T, 1, true>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
     } else if (fam == 0) {
         launch_line_fam<T, 0, false>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
     } else {
