@@ -59,8 +59,9 @@ def log(msg):
 # stationary solve reads and writes the FP64 state and writes the FP32
 # increment (8 + 8 + 4); in the time march the gamma scatter writes the state
 # (8).  Tables: the slot's grid index (4), the first record's line node (4),
-# three 16-bit offsets (6) and the weights of 4 records (FP16 pairs, 16, in
-# the FP32 sweeps; 2 x FP64 each, 64, in the FP64 sweeps).
+# three 16-bit offsets (6) and the weights of 4 records (in the FP32 sweeps
+# their factors: the estimates' weights and the records' positions, 12; 2 x
+# FP64 each, 64, in the FP64 sweeps).
 # --------------------------------------------------------------------------
 def line_bytes(prec, fam):
     w = 4 if prec == "fp32" else 8
@@ -79,7 +80,7 @@ def scatter_bytes(prec, fam, counts, march=False):
         grid = w
     else:
         grid = 8 if march else 8 + 8 + 4
-    meta = 4 + 4 + 6 + (16 if prec == "fp32" else 64)
+    meta = 4 + 4 + 6 + (12 if prec == "fp32" else 64)
     return vals + grid, meta
 
 
@@ -89,13 +90,13 @@ def direct_line_bytes(prec, fam):
     (beta, FP64 sweeps only), the written value, and on the gamma-curves the
     update: FP64 sweeps read the old value and write the FP32 increment, FP32
     sweeps read and write the FP64 state; tables = the two bracket indices and
-    four weights."""
+    four weights (FP16 in the FP32 sweeps)."""
     w = 4 if prec == "fp32" else 8
     if fam == 0:
         alg = w + w + w + (w if prec == "fp64" else 0) + w
     else:
         alg = w + w + w + (8 + 4 if prec == "fp64" else 16)
-    return alg, 8 + 4 * w
+    return alg, 8 + (8 if prec == "fp32" else 32)
 
 
 def kernel_name(prec, cls, split_lines=0, march=False):

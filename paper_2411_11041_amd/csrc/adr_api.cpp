@@ -935,9 +935,17 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 F.a64d = F.a64;
                 F.a64d.dk = reinterpret_cast<const int2 *>(upload(dk, own, st));
                 F.a64d.dw = upload(dw, own, st);
+                // FP32 increment sweeps: FP16 weights (relative error 2^-11, as the scatter's)
+                std::vector<unsigned> dw16(2 * static_cast<size_t>(F.n_nodes));
+                for (size_t e = 0; e < dw16.size(); ++e) {
+                    const _Float16 lo = static_cast<_Float16>(static_cast<float>(dw[2 * e]));
+                    const _Float16 hi = static_cast<_Float16>(static_cast<float>(dw[2 * e + 1]));
+                    dw16[e] = static_cast<unsigned>(__builtin_bit_cast(unsigned short, lo)) |
+                              (static_cast<unsigned>(__builtin_bit_cast(unsigned short, hi)) << 16);
+                }
                 F.a32d = F.a32;
                 F.a32d.dk = F.a64d.dk;
-                F.a32d.dw = upload(to_type<float>(dw), own, st);
+                F.a32d.dw16 = reinterpret_cast<const uint2 *>(upload(dw16, own, st));
                 if (f == 1) {
                     // update sums of the gamma-curves, grouped by instance in list order
                     std::vector<int> start(n + 1, 0), slot(F.n_lines);
@@ -954,11 +962,19 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             std::vector<int> rk(4 * static_cast<size_t>(npad), -1);
             std::vector<double> ra(4 * static_cast<size_t>(npad), 0.0), rb(4 * static_cast<size_t>(npad), 0.0);
             std::vector<double> gb(any_g ? npad : 0, 0.0);
+            // FP32 tables: the stencil's factors, quantised (weights to ~3e-5)
+            std::vector<unsigned> sw(npad, 0u), rt(2 * static_cast<size_t>(npad), 0u);
+            auto q16 = [](double v) { return static_cast<unsigned>(std::lround(std::min(std::max(v, 0.0), 1.0) * 65535.0)); };
+            auto q15 = [](double v) { return static_cast<unsigned>(std::lround(std::min(std::max(v, 0.0), 1.0) * 32767.0)); };
             for (int i = 0; i < n; ++i)
                 for (size_t s = 0; s < order[i].size(); ++s) {
                     const size_t slot = static_cast<size_t>(blk_start[i]) * kBlock + s;
                     const adr::Rec4 &R = G[i].rec[f][order[i][s]];
                     if (any_g) gb[slot] = R.gb;
+                    const unsigned wcode = R.wh == 0.0 ? 0u : (R.wh == 0.5 ? 1u : 2u);
+                    sw[slot] = wcode | (q15(R.lam[0]) << 2) | (q15(R.lam[1]) << 17);
+                    rt[slot] = q16(R.t[0]) | (q16(R.t[1]) << 16);
+                    rt[static_cast<size_t>(npad) + slot] = q16(R.t[2]) | (q16(R.t[3]) << 16);
                     for (int r = 0; r < 4; ++r) {
                         rk[r * static_cast<size_t>(npad) + slot] = R.k[r] < 0 ? -1 : static_cast<int>(noff[i] + R.k[r]);
                         ra[r * static_cast<size_t>(npad) + slot] = R.ca[r];
@@ -983,18 +999,11 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             }
             const int *d_rk0 = upload(rk0, own, st);
             const short *d_rd = upload(rd, own, st);
-            std::vector<unsigned> rw(ra.size());
-            for (size_t e = 0; e < ra.size(); ++e) {
-                const _Float16 a16 = static_cast<_Float16>(static_cast<float>(ra[e]));
-                const _Float16 b16 = static_cast<_Float16>(static_cast<float>(rb[e]));
-                rw[e] = static_cast<unsigned>(__builtin_bit_cast(unsigned short, a16)) |
-                        (static_cast<unsigned>(__builtin_bit_cast(unsigned short, b16)) << 16);
-            }
             F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, upload(ra, own, st),
-                                             upload(rb, own, st), nullptr, npad};
+                                             upload(rb, own, st), nullptr, nullptr, npad};
             F.s64.gb = any_g ? upload(gb, own, st) : nullptr;
             F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, nullptr, nullptr,
-                                            upload(rw, own, st), npad};
+                                            upload(sw, own, st), upload(rt, own, st), npad};
             F.v64 = dalloc<double>(F.n_nodes, own);
             F.v32 = dalloc<float>(F.n_nodes, own);
             for (int i = 0; i < n; ++i) C->geo[f].push_back(G[i].fam[f]);

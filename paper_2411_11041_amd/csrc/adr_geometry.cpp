@@ -440,6 +440,9 @@ void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> 
         const double Ws[2] = {Wh, 1.0 - Wh};
         Rec4 &R = out[n];
         R.gb = 0.0;
+        R.wh = Wh;
+        R.lam[0] = cl[0];
+        R.lam[1] = cl[1];
         for (int dir = 0; dir < 2; ++dir) {
             for (int side = 0; side < 2; ++side) {
                 int slot = dir * 2 + side;
@@ -449,10 +452,12 @@ void build_scatter(const Grid &g, const Domain &dom, const std::vector<uint8_t> 
                     R.k[slot] = static_cast<int32_t>(b.k);
                     R.ca[slot] = coef * (1.0 - b.t);
                     R.cb[slot] = coef * b.t;
+                    R.t[slot] = b.t;
                 } else {  // boundary point: carries the Dirichlet data there
                     R.k[slot] = -1;
                     R.ca[slot] = 0.0;
                     R.cb[slot] = 0.0;
+                    R.t[slot] = 0.0;
                     if (gdata && coef != 0.0) {
                         const double px = dir == 0 ? b.coord : g.x(gi), py = dir == 0 ? g.y(gj) : b.coord;
                         R.gb += coef * g.interp(gdata, px, py);

@@ -40,6 +40,10 @@ struct Rec4 {
     int32_t k[4];
     double ca[4], cb[4];
     double gb;
+    // the same stencil factored (records 0, 1 horizontal, 2, 3 vertical):
+    // ca[r] = W_r lam_r (1 - t[r]), cb[r] = W_r lam_r t[r] with W = (wh, wh, 1 - wh, 1 - wh)
+    // and lam = (lam[0], 1 - lam[0], lam[1], 1 - lam[1]); t = 0 at boundary points
+    double wh, lam[2], t[4];
 };
 
 // Everything the device needs for one instance, in local indices.

@@ -29,7 +29,8 @@ struct LineArgs {
     // gather: node k takes (dk[k].x >= 0 ? dw[4k] fin[dk.x] + dw[4k+1] fin[dk.x+1] : dw[4k] x_first)
     // + (dk[k].y >= 0 ? dw[4k+2] fin[dk.y] + dw[4k+3] fin[dk.y+1] : dw[4k+2] x_last)
     const int2 *dk;
-    const T *dw;
+    const T *dw;         // FP64 sweeps
+    const uint2 *dw16;   // FP32 sweeps: the four weights as FP16 (low half first)
     double *lpart;       // optional with dk: per line, sum over its interior nodes of
                          // (new value - old value in vout)^2, at lpart[lslot[line]]
     const int *lslot;
@@ -55,7 +56,10 @@ struct ScatterArgs {
     const int *rk0;       // [npad] rk[0]
     const short *rd;      // [3][npad] rk[r] - rk0 for r = 1..3, or kRecMissing / kRecEscape
     const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1] (FP64 tables)
-    const unsigned *rw;   // [4][npad] the same weights as two FP16 halves (low: v[k]); FP32 tables
+    // FP32 tables, the same weights factored: ca_r = W_r lam_r (1 - t_r), cb_r = W_r lam_r t_r
+    const unsigned *sw;   // [npad] bits 0-1: 2 W_h (W_v = 1 - W_h); 2-16: lam_h; 17-31: lam_v (15-bit
+                          // fractions; records 0, 1 take lam_h, 1 - lam_h, records 2, 3 lam_v, 1 - lam_v)
+    const unsigned *rt;   // [2][npad] t of records 0, 1 (then 2, 3) as 16-bit fractions, low half first
     int npad;
     const int *blist;     // optional: the slot block of each workgroup (active blocks only)
     int nblist;           // workgroups when blist is set

@@ -105,6 +105,11 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T hj[MAXJ], wj[MAXJ], lk[MAXJ];
     int cj[MAXJ];
     T lxj[MAXJ], lyj[MAXJ];
+    // direct transfer in the FP32 sweeps: the brackets and their FP16 weights
+    // (4 registers per slot) are loaded with the other node data
+    constexpr bool DIR16 = DIR && sizeof(T) == 4;
+    int2 dkj[DIR16 ? MAXJ : 1];
+    uint2 dwj[DIR16 ? MAXJ : 1];
 #pragma unroll
     for (int sl = 0; sl < MAXJ; ++sl) {
         const int j = tid + NT * sl;
@@ -116,6 +121,11 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
             cj[sl] = a.cell[kn];
             lxj[sl] = a.lx[kn];
             lyj[sl] = a.ly[kn];
+        }
+        if constexpr (DIR16) {
+            const bool in = j > 0 && j < n - 1;
+            dkj[sl] = in ? a.dk[o + j] : make_int2(-1, -1);
+            dwj[sl] = in ? a.dw16[o + j] : make_uint2(0u, 0u);
         }
         if (j > 0 && j < n) hj[sl] = a.h[o + j];
         if (FAM == 0 && j < n) wj[sl] = a.w[o + j];
@@ -134,11 +144,20 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
             T dw[G][4];
 #pragma unroll
             for (int t = 0; t < G; ++t) {
-                const int j = tid + NT * (q0 + t);
-                const bool in = j > 0 && j < n - 1;
-                dk[t] = in ? a.dk[o + j] : make_int2(-1, -1);
+                if constexpr (DIR16) {
+                    dk[t] = dkj[q0 + t];
+                    const uint2 h = dwj[q0 + t];
+                    dw[t][0] = static_cast<T>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h.x & 0xffffu)));
+                    dw[t][1] = static_cast<T>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h.x >> 16)));
+                    dw[t][2] = static_cast<T>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h.y & 0xffffu)));
+                    dw[t][3] = static_cast<T>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h.y >> 16)));
+                } else {
+                    const int j = tid + NT * (q0 + t);
+                    const bool in = j > 0 && j < n - 1;
+                    dk[t] = in ? a.dk[o + j] : make_int2(-1, -1);
 #pragma unroll
-                for (int e = 0; e < 4; ++e) dw[t][e] = in ? a.dw[4 * static_cast<int64_t>(o + j) + e] : T(0);
+                    for (int e = 0; e < 4; ++e) dw[t][e] = in ? a.dw[4 * static_cast<int64_t>(o + j) + e] : T(0);
+                }
             }
 #pragma unroll
             for (int t = 0; t < G; ++t) {
@@ -470,15 +489,27 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
     kk[0] = s.rk0[slot];
 #pragma unroll
     for (int r = 0; r < 3; ++r) dk[r] = s.rd[r * np + slot];
+    if constexpr (sizeof(T) == 4) {
+        // increment sweeps: the weights from their factors, 12 bytes per slot
+        // (quantised to ~3e-5; the FP64 sweeps, with FP64 weights, fix the
+        // iterate and its residual)
+        const unsigned e = s.sw[slot], t01 = s.rt[slot], t23 = s.rt[np + slot];
+        const float wh = static_cast<float>(e & 3u) * 0.5f, wv = 1.0f - wh;
+        const float lh = static_cast<float>((e >> 2) & 0x7fffu) * (1.0f / 32767.0f);
+        const float lv = static_cast<float>(e >> 17) * (1.0f / 32767.0f);
+        const float cf[4] = {wh * lh, wh - wh * lh, wv * lv, wv - wv * lv};
+        const float tt[4] = {static_cast<float>(t01 & 0xffffu) * (1.0f / 65535.0f),
+                             static_cast<float>(t01 >> 16) * (1.0f / 65535.0f),
+                             static_cast<float>(t23 & 0xffffu) * (1.0f / 65535.0f),
+                             static_cast<float>(t23 >> 16) * (1.0f / 65535.0f)};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        if constexpr (sizeof(T) == 4) {
-            // increment sweeps: FP16 weights (relative error 2^-11; the FP64
-            // sweeps, with FP64 weights, fix the iterate and its residual)
-            const unsigned w = s.rw[r * np + slot];
-            wa[r] = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w & 0xffffu)));
-            wb[r] = static_cast<float>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w >> 16)));
-        } else {
+        for (int r = 0; r < 4; ++r) {
+            wb[r] = cf[r] * tt[r];
+            wa[r] = cf[r] - wb[r];
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
             wa[r] = s.ra[r * np + slot];
             wb[r] = s.rb[r * np + slot];
         }
