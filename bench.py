@@ -99,13 +99,14 @@ def direct_line_bytes(prec, fam):
     return alg, 8 + (8 if prec == "fp32" else 32)
 
 
-def kernel_name(prec, cls, split_lines=0, march=False):
+def kernel_name(prec, cls, split_lines=0, march=False, direct=False):
     tn = "float" if prec == "fp32" else "double"
     fam = 0 if cls.endswith("beta") else 1
     if cls.startswith("line"):
+        d = "true" if direct else "false"  # the line kernels' direct-transfer flag
         if split_lines:
-            return f"k_line_b<{tn}, {fam}, J, NT> (one launch per length bucket)"
-        return f"k_line<{tn}, {fam}>"
+            return f"k_line_b<{tn}, {fam}, J, NT, {d}> (one launch per length bucket)"
+        return f"k_line<{tn}, {fam}, {d}>"
     if prec == "fp32":
         return "k_scatter<float, float, 0>" if fam == 0 else "k_scatter<float, double, 2>"
     if fam == 0 or march:
@@ -130,9 +131,7 @@ def roofline(times, counts, split_lines=0, march=False, profile=None, direct=Fal
             else:
                 alg, meta = scatter_bytes(prec, fam, counts, march)
             sec = ms / 1e3
-            name = kernel_name(prec, cls, split_lines, march)
-            if direct and cls.startswith("line"):
-                name = name.replace(f"{fam}>", f"{fam}, true>").replace("J, NT>", "J, NT, true>")
+            name = kernel_name(prec, cls, split_lines, march, direct)
             rows.append(dict(kernel=name, prec=prec, cls=cls, ms=round(ms, 3), launches=cnt,
                              avg_launch_us=round(1e3 * ms / cnt, 2), work_per_launch=round(work / cnt),
                              alg_bytes_per_unit=round(alg, 2), table_bytes_per_unit=round(meta, 2),
@@ -209,6 +208,8 @@ def parse():
                     help="with --no-autotune: GMRES(m) on (I - T) U = c instead of the sweep schedule (m > 0)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="c2/c4: keep the given schedule and launches instead of choosing them with adr_autotune")
+    ap.add_argument("--single-mode", action="store_true",
+                    help="c4: time one launch mode only (no graph-replay comparison); for profiles")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="before the timed region, run one plain elementwise copy of 256 MiB in / 256 MiB out, "
                          "the reference dispatch for scaling hardware byte counters")
@@ -267,12 +268,6 @@ def leg_c2(args):
     import torch
     import workloads as W
     from paper_2411_11041_amd.adr import Solver
-    if args.calibrate_copy:
-        a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        torch.mul(a, 1.0, out=b)
-        torch.cuda.synchronize()
-        del a, b
     p = W.c2(args.n)
     t0 = time.time()
     s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, adaptive=args.adaptive,
@@ -358,7 +353,8 @@ def leg_direct(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         el_ev, times = events_pass(s, solve, args.steps)
-        rf = roofline(times, counts, 0, direct=(tr == "direct"))
+        rf = roofline(times, counts, 0, direct=(tr == "direct"),
+                      profile="c2_2049_direct.md" if name == "direct_fp32" else None)
         res[name] = {"ms_per_step": round(1e3 * el / args.steps, 3), "sweeps": int(iters[0]),
                      "final_rel": float(rel[0]), "value": per_sweep * int(iters[0]) * args.steps / el,
                      "setup_s": round(setup_s, 2), "events_pass_ms_per_step": round(1e3 * el_ev / args.steps, 3),
@@ -447,6 +443,10 @@ def leg_c4(args):
     # the same solves with the blocks replayed from HIP graphs (one per block
     # length, captured in the warm-up) instead of eager launches on the lists
     # compacted to the unfinished instances
+    if args.single_mode:
+        s.close()
+        return c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, fp32_sweeps, adaptive,
+                         split, shapes, kr, tuned, solved, times, None)
     s.set_graph(not args.graph)
     for _ in range(args.warmup):
         solve()
@@ -462,6 +462,13 @@ def leg_c4(args):
              "converged": int((rel_g <= args.tol).sum())}
     log(f"c4: {'graph replay' if not args.graph else 'eager'} {other['ms_per_step']} ms")
     s.close()
+    return c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, fp32_sweeps, adaptive, split,
+                     shapes, kr, tuned, solved, times, other)
+
+
+def c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, fp32_sweeps, adaptive, split, shapes,
+              kr, tuned, solved, times, other):
+    import numpy as np
     return {"value": solved / el, "unit": "line-unknowns/s", "ms_per_step": 1e3 * el / args.steps, "roofline": rf,
             "config": {"workload": f"c4: {len(probs)} stationary instances (disc/L-shape, 33..1025 per side, "
                                    "mu logU[1e-4,1e-1], sigma U[0.1,10], random divergence-free beta), "
@@ -647,12 +654,25 @@ def cpu_baseline(n, sweeps, workers):
             "s_per_sweep_per_worker": round(per_sweep_s, 3)}
 
 
+def calibrate_copy():
+    """A plain 256 MiB-in / 256 MiB-out elementwise copy, whose FETCH_SIZE and
+    WRITE_SIZE give the counters' scale (read by the profile summaries)."""
+    import torch
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
     cpu = None
     if args.workload in ("all", "c2") and not args.no_cpu:
         log("cpu baseline (oracle)")

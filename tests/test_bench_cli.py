@@ -30,7 +30,12 @@ def test_roofline_byte_model():
     alg = [bench.scatter_bytes(p, f, counts)[0] for p, f in (("fp32", 0), ("fp32", 1), ("fp64", 0), ("fp64", 1))]
     assert alg == [4 * 1.02 + 4, 4 * 0.84 + 20, 8 * 1.02 + 8, 8 * 0.84 + 20]
     assert bench.scatter_bytes("fp64", 1, counts, march=True)[0] == 8 * 0.84 + 8
-    assert [bench.scatter_bytes(p, 0, counts)[1] for p in ("fp32", "fp64")] == [30, 78]
+    assert [bench.scatter_bytes(p, 0, counts)[1] for p in ("fp32", "fp64")] == [26, 78]
+    # direct transfer: source value, chord, |beta| and load (beta, FP64), written value; gamma: the
+    # update traffic (FP64: old value + FP32 increment; FP32: FP64 state read and written);
+    # tables: two bracket indices and four weights (FP16 in the FP32 sweeps)
+    assert [bench.direct_line_bytes(*k) for k in (("fp32", 0), ("fp32", 1), ("fp64", 0), ("fp64", 1))] == \
+        [(16, 16), (28, 16), (40, 40), (36, 40)]
 
 
 def test_roofline_from_kernel_work():
@@ -46,7 +51,7 @@ def test_roofline_from_kernel_work():
              "fp32": {"line_beta": (2.0, 4, 4000), "line_gamma": z, "scatter_beta": (0.5, 4, 4000),
                       "scatter_gamma": z, "norm": z}}
     rf = bench.roofline(times, counts)
-    assert rf["kernel"] == "k_line<float, 0>"
+    assert rf["kernel"] == "k_line<float, 0, false>"
     assert abs(rf["achieved"] - 16 * 4000 / 2e-3 / 1e9) < 0.1
     assert rf["bytes_per_launch"] == 16 * 1000
     assert [c["cls"] for c in rf["classes"]] == ["line_beta", "line_beta", "scatter_beta"]

@@ -162,3 +162,70 @@ def test_direct_transfer_refuses_what_it_does_not_serve():
         s.autotune(u, 100, 1e-8)
     assert e.value.code == ADR_EINVAL
     s.close()
+
+
+def test_direct_transfer_with_fitted_lines_and_update():
+    """The direct transfer with exponentially fitted beta-lines matches the
+    oracle (both built on the same options), and adr_update on a direct
+    context (new mu, sigma, f on the same curves) gives the fresh context's
+    solve."""
+    print("[case] direct transfer, fitted lines; adr_update", flush=True)
+    p = W.c4_instance(0, n_max=70)
+    o = Oracle(p, stabilize=True)
+    s = solver(p, precision="fp64", theta=1.0, dt=0.05, transfer="direct", stabilize=True)
+    u = dev(o.zero_field())
+    it, rel, st = s.split_iterate(u, 5, 0.0)
+    torch.cuda.synchronize()
+    U = _oracle_sweeps(o, o.zero_field(), 5)
+    assert rel_l2(u.cpu().numpy(), U, o.inner_idx) < 1e-11
+    s.close()
+    # update: the same grid and curves, other coefficients and source
+    a = W.c5_sample(1, n=65)
+    b = W.c5_sample(2, n=65)
+    b.beta1, b.beta2 = a.beta1, a.beta2
+    s = solver(a, precision="fp64", theta=1.0, dt=0.05, transfer="direct")
+    v = torch.zeros(a.nx * a.ny, dtype=torch.float64, device="cuda")
+    s.split_iterate(v, 3000, 1e-10)
+    s.update([b])
+    v.zero_()
+    it_u, rel_u, st_u = s.split_iterate(v, 3000, 1e-10)
+    torch.cuda.synchronize()
+    s.close()
+    f = solver(b, precision="fp64", theta=1.0, dt=0.05, transfer="direct")
+    w = torch.zeros(b.nx * b.ny, dtype=torch.float64, device="cuda")
+    it_f, rel_f, st_f = f.split_iterate(w, 3000, 1e-10)
+    torch.cuda.synchronize()
+    f.close()
+    assert st_u == 0 and st_f == 0 and abs(int(it_u[0]) - int(it_f[0])) <= 1
+    m = Oracle(b).inner_idx
+    assert rel_l2(v.cpu().numpy(), w.cpu().numpy(), m) < 1e-9
+
+
+def _axis_beta(n=33):
+    p = W.c1(n)
+    p.beta1, p.beta2 = np.ones_like(p.beta1), np.zeros_like(p.beta2)
+    return p
+
+
+def _diag_beta(n=33):
+    p = W.c1(n)
+    p.beta1, p.beta2 = np.ones_like(p.beta1), np.ones_like(p.beta2)
+    return p
+
+
+@pytest.mark.parametrize("name,maker", [("c1_3", lambda: W.c1(3)), ("c1_4", lambda: W.c1(4)),
+                                        ("axis", _axis_beta), ("diag", _diag_beta)])
+def test_direct_transfer_degenerate_cases(name, maker):
+    """One interior node (3x3), two (4x4), curves along the grid lines
+    (intersections at grid nodes and segment ends) and along the diagonals:
+    4 FP64 sweeps equal the oracle's."""
+    print(f"[case] direct transfer degenerate case {name}", flush=True)
+    p = maker()
+    o = Oracle(p)
+    s = solver(p, precision="fp64", theta=1.0, dt=0.05, transfer="direct")
+    u = dev(o.zero_field())
+    it, rel, st = s.split_iterate(u, 4, 0.0)
+    torch.cuda.synchronize()
+    U = _oracle_sweeps(o, o.zero_field(), 4)
+    assert rel_l2(u.cpu().numpy(), U, o.inner_idx) < 1e-11
+    s.close()
