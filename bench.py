@@ -208,6 +208,8 @@ def parse():
                     help="with --no-autotune: GMRES(m) on (I - T) U = c instead of the sweep schedule (m > 0)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="c2/c4: keep the given schedule and launches instead of choosing them with adr_autotune")
+    ap.add_argument("--transfer", choices=["grid", "direct"], default="grid",
+                    help="c4: values handed between the families through the grid or at their intersections")
     ap.add_argument("--single-mode", action="store_true",
                     help="c4: time one launch mode only (no graph-replay comparison); for profiles")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -402,7 +404,7 @@ def leg_c4(args):
     gen_s = time.time() - t0
     t0 = time.time()
     s = Solver(probs, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, graph=args.graph,
-               adaptive=args.adaptive, split_lines=args.split_lines, krylov=args.krylov)
+               adaptive=args.adaptive, split_lines=args.split_lines, krylov=args.krylov, transfer=args.transfer)
     setup_s = time.time() - t0
     counts = s.counts()
     per_inst = []
@@ -417,7 +419,7 @@ def leg_c4(args):
     u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     fp32_sweeps, adaptive, split, shapes, tuned = args.fp32_sweeps, args.adaptive, args.split_lines, [0] * 5, None
     kr = args.krylov
-    if not args.no_autotune:
+    if not args.no_autotune and args.transfer == "grid":
         tuned = s.autotune(u, 3000, args.tol)
         fp32_sweeps, adaptive, split, shapes, kr = tuned[0], tuned[1], tuned[3], tuned[4], tuned[5]
     log(f"c4: gen {gen_s:.1f} s, set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split} "
@@ -437,13 +439,14 @@ def leg_c4(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     el_ev, times = events_pass(s, solve, args.steps)
-    rf = roofline(times, counts, split, profile="c4_512_fp32lines.md")
+    rf = roofline(times, counts, split, profile="c4_512_fp32lines.md" if args.transfer == "grid" else None,
+                  direct=args.transfer == "direct")
     rf["events_pass_ms_per_step"] = round(1e3 * el_ev / args.steps, 2)
     solved = int((its.astype(np.int64) * per_inst).sum()) * args.steps
     # the same solves with the blocks replayed from HIP graphs (one per block
     # length, captured in the warm-up) instead of eager launches on the lists
     # compacted to the unfinished instances
-    if args.single_mode:
+    if args.single_mode or args.transfer == "direct":  # graphs serve the grid transfer only
         s.close()
         return c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, fp32_sweeps, adaptive,
                          split, shapes, kr, tuned, solved, times, None)
@@ -480,7 +483,7 @@ def c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, f
                        "setup_s": round(setup_s, 1), "graph": bool(args.graph),
                        "fp32_sweeps_per_fp64": fp32_sweeps, "adaptive_schedule": bool(adaptive),
                        "line_launches": LINE_LAUNCHES[split], "line_shapes": shapes, "krylov_gmres_m": kr,
-                       "autotune_ms": round(tuned[2], 2) if tuned else None,
+                       "autotune_ms": round(tuned[2], 2) if tuned else None, "transfer": args.transfer,
                        "other_launch_mode": other, "kernels": kernels_table(times)}}
 
 
