@@ -123,7 +123,26 @@ struct adr_ctx {
     float *d32 = nullptr, *D32 = nullptr;
     int *done = nullptr, *never = nullptr, *conv_it = nullptr;
     int *sing = nullptr;  // per instance: a line solve met a bad pivot (ADR_ESINGULAR)
-    double *fit = nullptr;  // per instance 1 / (2 mu) of the fitted beta-lines (options.stabilize)
+    // fitted beta-lines (options.stabilize): per beta node the element's |beta|_e h_e
+    // (mu-free part of its Peclet number) and phi(Pe) in FP64 and FP32
+    std::vector<double> fit_wlh;
+    double *phi64 = nullptr;
+    float *phi32 = nullptr;
+    // phi per beta node from fit_wlh and the instances' mu (0 at line starts)
+    void fill_phi(const std::vector<double> &mu_i) {
+        std::vector<double> ph(fit_wlh.size(), 0.0);
+        for (int i = 0; i < n_inst; ++i)
+            for (int64_t k = noffB[i]; k < noffB[i + 1]; ++k) {
+                const double wlh = fit_wlh[static_cast<size_t>(k)];
+                if (wlh > 0.0) {
+                    const double pe = wlh / (2.0 * mu_i[i]);
+                    ph[static_cast<size_t>(k)] = pe / std::tanh(pe);
+                }
+            }
+        std::vector<float> p32(ph.begin(), ph.end());
+        HIPCHK(hipMemcpy(phi64, ph.data(), sizeof(double) * ph.size(), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(phi32, p32.data(), sizeof(float) * p32.size(), hipMemcpyHostToDevice));
+    }
     // GMRES acceleration (options.krylov = m > 0), allocated on first use
     std::vector<int64_t> boff_h;  // blocked offset of each instance (n_inst + 1)
     adr::KChunks kch{};
@@ -750,11 +769,6 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         for (int i = 0; i < n; ++i) any_g = any_g || probs[i].g != nullptr;
         C->sing = dalloc<int>(n, own);
         HIPCHK(hipMemsetAsync(C->sing, 0, sizeof(int) * n, st));
-        if (opt->stabilize) {
-            std::vector<double> fit(n);
-            for (int i = 0; i < n; ++i) fit[i] = 0.5 / probs[i].mu;
-            C->fit = upload(fit, own, st);
-        }
 
         // scatter slots, padded per instance to whole blocks
         std::vector<int> blk_start(n + 1, 0);
@@ -916,8 +930,23 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             F.a64.sing = C->sing;
             F.a32.sing = C->sing;
             F.a64.ptol = opt->pivot_tol > 0.0 ? opt->pivot_tol : 64.0 * 2.220446049250313e-16;
-            F.a64.fit = f == 0 ? C->fit : nullptr;
-            F.a32.fit = f == 0 ? C->fit : nullptr;
+            if (f == 0 && opt->stabilize) {
+                // per node: |beta|_e h_e of the element ending there, |beta|_e the mean of its ends
+                C->fit_wlh.assign(static_cast<size_t>(F.n_nodes), 0.0);
+                for (int i = 0; i < n; ++i) {
+                    const adr::Family &fa = G[i].fam[0];
+                    for (size_t l = 0; l + 1 < fa.off.size(); ++l)
+                        for (int64_t k = fa.off[l] + 1; k < fa.off[l + 1]; ++k) {
+                            const double wl = 0.5 * (G[i].wk[static_cast<size_t>(k)] + G[i].wk[static_cast<size_t>(k - 1)]);
+                            C->fit_wlh[static_cast<size_t>(noff[i] + k)] = wl * G[i].hk[0][static_cast<size_t>(k)];
+                        }
+                }
+                C->phi64 = dalloc<double>(static_cast<size_t>(F.n_nodes), own);
+                C->phi32 = dalloc<float>(static_cast<size_t>(F.n_nodes), own);
+                C->fill_phi(mu);
+                F.a64.phi = C->phi64;
+                F.a32.phi = C->phi32;
+            }
             F.a32.ptol = opt->pivot_tol > 0.0 ? opt->pivot_tol : 64.0 * 1.1920928955078125e-07;
             if (opt->transfer == 1) {
                 // direct-transfer records: source nodes in the other family's packed numbering
@@ -1153,11 +1182,7 @@ adr_status adr_update(adr_ctx *ctx, const adr_problem *probs, int32_t n_probs) {
             ctx->mu[i] = probs[i].mu;
             ctx->sg[i] = probs[i].sigma;
         }
-        if (ctx->fit) {
-            std::vector<double> fit(n);
-            for (int i = 0; i < n; ++i) fit[i] = 0.5 / probs[i].mu;
-            HIPCHK(hipMemcpy(ctx->fit, fit.data(), sizeof(double) * n, hipMemcpyHostToDevice));
-        }
+        if (ctx->phi64) ctx->fill_phi(ctx->mu);
         fill_params(ctx->par_h, n, kSlotStep, ctx->mu, ctx->sg, ctx->opt.theta, ctx->opt.dt);
         fill_params(ctx->par_h, n, kSlotLin, ctx->mu, ctx->sg, ctx->opt.theta, ctx->opt.dt);
         fill_params(ctx->par_h, n, kSlotGuess, ctx->mu, ctx->sg, 1.0, 1.0);

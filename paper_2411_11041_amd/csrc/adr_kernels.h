@@ -22,8 +22,9 @@ struct LineArgs {
     const T *gend;       // optional: per line the Dirichlet values at its two ends (2 per line); NULL: zero
     int *sing;           // optional: per instance, set to 1 when a pivot is not finite or below ptol
     double ptol;         // relative pivot threshold (of |diagonal| + |eliminated part|)
-    const double *fit;   // optional (beta family): per instance 1 / (2 mu) of the exponentially
-                         // fitted stiffness; NULL: plain Galerkin rows
+    const T *phi;        // optional (beta family): per node, phi(Pe) = Pe coth(Pe) of the element
+                         // ending at the node, the scale of its exponentially fitted stiffness;
+                         // NULL: plain Galerkin rows
     // interpolation-free transfer: when dk is set the node values
     // come from the other family's line values fin instead of the bilinear
     // gather: node k takes (dk[k].x >= 0 ? dw[4k] fin[dk.x] + dw[4k+1] fin[dk.x+1] : dw[4k] x_first)

@@ -89,9 +89,8 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     const T ptol = T(a.ptol);
     bool bad = false;  // a pivot not finite or below ptol of its row's scale
     // exponentially fitted beta-lines: element e's stiffness scaled by
-    // phi = Pe coth(Pe), Pe = |beta|_e h_e / (2 mu), |beta|_e the element mean
-    const bool fit = FAM == 0 && a.fit != nullptr;
-    const T pes = fit ? T(a.fit[inst]) : T(0);  // 1 / (2 mu)
+    // phi = Pe coth(Pe), Pe = |beta|_e h_e / (2 mu) (precomputed per element)
+    const bool fit = FAM == 0 && a.phi != nullptr;
 
     // chunking of the rows: thread q owns rows rs .. rs+k-1, rs = q*m (m <= MAXJ)
     const int m = (N + NT - 1) / NT;
@@ -237,10 +236,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
             if (FAM == 0) {
                 wm = Ws[rs];
                 w0 = Ws[rs + 1];
-                if (fit) {
-                    const T pe = T(0.5) * (wm + w0) * hl * pes;
-                    il *= pe / tanh(pe);
-                }
+                if (fit) il *= a.phi[o + rs + 1];
             }
         }
 #pragma unroll
@@ -249,10 +245,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
                 const int r = rs + j;
                 const T up = U[r + 2], hr = Hs[r + 2];
                 T ir = recip(hr);
-                if (fit) {
-                    const T pe = T(0.5) * (w0 + Ws[r + 2]) * hr * pes;
-                    ir *= pe / tanh(pe);
-                }
+                if (fit) ir *= a.phi[o + r + 2];
                 const T mlo = hl * sixth, mdi = (hl + hr) * third, mup = hr * sixth;
                 const T klo = -il, kdi = il + ir, kup = -ir;
                 T lo = cM * mlo + cK * klo;

@@ -229,3 +229,25 @@ def test_direct_transfer_degenerate_cases(name, maker):
     U = _oracle_sweeps(o, o.zero_field(), 4)
     assert rel_l2(u.cpu().numpy(), U, o.inner_idx) < 1e-11
     s.close()
+
+
+def test_direct_batch_bucketed_fp32_reaches_the_fixed_point():
+    """The C4 launch configuration (one launch per length bucket, compacted
+    lists, FP32 increment sweeps under the adaptive schedule) with the direct
+    transfer: every instance stops at rel <= 1e-9 at its direct FP64 fixed
+    point (the oracle's) within 1e-7."""
+    print("[case] direct transfer, bucketed fp32 batch of 5 c4 instances", flush=True)
+    probs = [W.c4_instance(i, n_max=100) for i in range(5)]
+    orcs = [Oracle(p) for p in probs]
+    s = solver(probs, precision="fp32", fp32_sweeps=12, adaptive=True, split_lines=1, theta=1.0, dt=0.05,
+               transfer="direct")
+    off = s.layout()
+    u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
+    it, rel, st = s.split_iterate(u, 3000, 1e-9)
+    torch.cuda.synchronize()
+    assert st == 0 and np.all(rel <= 1e-9)
+    got = u.cpu().numpy()
+    for i, o in enumerate(orcs):
+        U, *_ = D.DirectSweeps(o).iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-12)
+        assert rel_l2(got[off[i]:off[i + 1]], U, o.inner_idx) < 1e-7, i
+    s.close()
