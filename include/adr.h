@@ -96,7 +96,8 @@ typedef struct {
     int32_t timing;       /* != 0: time each kernel with HIP events (adr_kernel_times) */
     int32_t host_only;    /* != 0: build the host geometry only, touch no device; then
                              only adr_counts, adr_export_lines, adr_export_scatter,
-                             adr_export_direct and adr_destroy are valid */
+                             adr_export_scatter_factors, adr_export_direct and adr_destroy
+                             are valid */
     int32_t graph;        /* != 0: adr_split_iterate replays its sweep blocks (m FP32 sweeps, an
                              FP64 sweep, the norm) from HIP graphs, one per block length m,
                              captured on first use on a context-owned stream ordered after
@@ -300,6 +301,17 @@ adr_status adr_export_lines(const adr_ctx *ctx, int32_t inst, int32_t family, in
  * Errors: ADR_EINVAL (a device context, an index out of range). */
 adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
                               int32_t *node, int32_t *k, double *ca, double *cb, double *gb);
+
+/* Test export (host-only contexts): the same stencil in the factored form the
+ * FP32 sweeps read (quantised on upload: wh exactly, lam to 15 and t to 16
+ * bits).  Row r's value is wh (lam_h a_0 + (1 - lam_h) a_1) + (1 - wh)
+ * (lam_v a_2 + (1 - lam_v) a_3) with a_s = (1 - t_s) v[k] + t_s v[k+1] the
+ * P1 value of slot s's record (k from adr_export_scatter; zero Dirichlet data
+ * where k = -1).  wh (n_rows) in {0, 1/2, 1}; lam (2 n_rows: horizontal,
+ * vertical); t (4 n_rows).  Errors: ADR_EINVAL (a device context, an index
+ * out of range). */
+adr_status adr_export_scatter_factors(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
+                                      double *wh, double *lam, double *t);
 
 /* Test export (host-only contexts set up with options.transfer = 1): the
  * direct-transfer records onto every node of one instance's family (0 beta,

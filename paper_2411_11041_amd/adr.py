@@ -21,7 +21,8 @@ PREC_FP64, PREC_FP32_LINES = 0, 1
 
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
            "adr_autotune", "adr_set_line_shapes", "adr_set_graph", "adr_time_step",
-           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_export_direct",
+           "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_export_scatter_factors",
+           "adr_export_direct",
            "adr_set_timing", "adr_kernel_times",
            "adr_destroy", "adr_last_error", "adr_copy_probe", "adr_line_solve", "adr_line_solve_noalloc")
 
@@ -85,6 +86,7 @@ def load():
     lib.adr_export_lines.argtypes = [vp, i32, i32, P(i64), P(i64), P(i64), P(dbl), P(dbl)]
     lib.adr_export_scatter.argtypes = [vp, i32, i32, P(i64), P(i32), P(i32), P(dbl), P(dbl), P(dbl)]
     lib.adr_export_direct.argtypes = [vp, i32, i32, P(i64), P(i32), P(dbl)]
+    lib.adr_export_scatter_factors.argtypes = [vp, i32, i32, P(i64), P(dbl), P(dbl), P(dbl)]
     lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), P(i64), i32]
     lib.adr_destroy.argtypes = [vp]
     lib.adr_copy_probe.argtypes = [vp, vp, i64, vp]
@@ -324,6 +326,17 @@ class Solver:
                                                 k.ctypes.data_as(i32p), _dptr(ca), _dptr(cb), _dptr(gb)))
         out = (node, k.reshape(n, 4), ca.reshape(n, 4), cb.reshape(n, 4))
         return out + (gb,) if with_gb else out
+
+    def export_scatter_factors(self, inst, family):
+        """The scatter stencil's factors (host-only contexts): wh (n), lam (n x 2), t (n x 4)."""
+        nr = C.c_int64()
+        self._check(self.lib.adr_export_scatter_factors(self.ctx, inst, family, C.byref(nr), None, None, None))
+        n = nr.value
+        wh = np.zeros(n)
+        lam = np.zeros(2 * n)
+        t = np.zeros(4 * n)
+        self._check(self.lib.adr_export_scatter_factors(self.ctx, inst, family, None, _dptr(wh), _dptr(lam), _dptr(t)))
+        return wh, lam.reshape(n, 2), t.reshape(n, 4)
 
     def export_direct(self, inst, family):
         """Direct-transfer records (host-only contexts with transfer="direct"):

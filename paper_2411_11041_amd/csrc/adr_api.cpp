@@ -1917,6 +1917,22 @@ adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, 
     return ADR_OK;
 }
 
+adr_status adr_export_scatter_factors(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
+                                      double *wh, double *lam, double *t) {
+    if (!ctx || !ctx->opt.host_only || inst < 0 || inst >= ctx->n_inst || family < 0 || family > 1)
+        return ADR_EINVAL;
+    const std::vector<adr::Rec4> &R = ctx->host_geo[inst].rec[family];
+    if (n_rows) *n_rows = static_cast<int64_t>(R.size());
+    for (size_t r = 0; r < R.size(); ++r) {
+        if (wh) wh[r] = R[r].wh;
+        for (int q = 0; q < 2; ++q)
+            if (lam) lam[2 * r + q] = R[r].lam[q];
+        for (int q = 0; q < 4; ++q)
+            if (t) t[4 * r + q] = R[r].t[q];
+    }
+    return ADR_OK;
+}
+
 adr_status adr_export_direct(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_nodes, int32_t *k,
                              double *w) {
     if (!ctx || !ctx->opt.host_only || ctx->opt.transfer != 1 || inst < 0 || inst >= ctx->n_inst || family < 0 ||

@@ -274,3 +274,41 @@ def test_direct_transfer_option_errors():
     with pytest.raises(ADRError):
         s.export_direct(0, 0)  # the grid transfer builds no direct records
     s.close()
+
+
+@pytest.mark.parametrize("maker", [lambda: W.c1(65), lambda: W.c2(129), lambda: W.c4_instance(0, n_max=120),
+                                   lambda: W.c4_instance(1, n_max=120), lambda: W.c1(3), _axis_beta, _diag_beta])
+def test_host_scatter_factors_rebuild_the_stencil(maker):
+    """The factored stencil the FP32 sweeps read (estimate weight, bracket
+    weights, record positions) rebuilds the oracle's scatter matrix: exactly
+    from the factors, within the quantisation (15- and 16-bit fractions) from
+    what the device receives."""
+    from oracle.method import Oracle
+    from paper_2411_11041_amd.adr import Solver
+    p = maker()
+    s = Solver(p, host_only=True)
+    o = Oracle(p)
+    for f in (0, 1):
+        node, k, _, _ = s.export_scatter(0, f)
+        wh, lam, t = s.export_scatter_factors(0, f)
+        assert set(np.unique(wh)).issubset({0.0, 0.5, 1.0})
+        n_nodes = o.fams[f].n_nodes
+        ref = o.P[f][o.inner_idx].toarray()
+        for quant in (False, True):
+            if quant:
+                whq = wh
+                lamq = np.round(np.clip(lam, 0, 1) * 32767) / 32767
+                tq = np.round(np.clip(t, 0, 1) * 65535) / 65535
+            else:
+                whq, lamq, tq = wh, lam, t
+            W_ = np.stack([whq, whq, 1 - whq, 1 - whq], 1)
+            L_ = np.stack([lamq[:, 0], 1 - lamq[:, 0], lamq[:, 1], 1 - lamq[:, 1]], 1)
+            c = W_ * L_
+            dense = np.zeros((len(node), n_nodes))
+            for q in range(4):
+                ok = k[:, q] >= 0
+                r = np.nonzero(ok)[0]
+                np.add.at(dense, (r, k[ok, q]), c[ok, q] * (1 - tq[ok, q]))
+                np.add.at(dense, (r, k[ok, q] + 1), c[ok, q] * tq[ok, q])
+            assert np.max(np.abs(dense - ref)) < (1e-4 if quant else 1e-12), (f, quant)
+    s.close()
