@@ -86,12 +86,16 @@ def segment_intersection(px0, py0, px1, py1, qx0, qy0, qx1, qy1):
     return s, t, ok
 
 
-def intersections(grid, tgt, src):
-    """Every meeting of a target segment with a source segment.
+def intersections(grid, tgt, src, lines=None):
+    """Every meeting of a target segment with a source segment (only the
+    target curves in `lines`, if given).
 
     Returns (kt, s, ks, t): first node of the target segment, position on it,
     first node of the source segment, position on it; sorted by (kt, s, ks)."""
     kt_all, ks_all = _segments(tgt), _segments(src)
+    if lines is not None:
+        line_of = np.repeat(np.arange(tgt.n_lines), np.diff(tgt.offsets))
+        kt_all = kt_all[np.isin(line_of[kt_all], np.asarray(lines))]
     ct, st_ = _cell_members(grid, tgt, kt_all)
     cs, ss_ = _cell_members(grid, src, ks_all)
     # pairs of (target, source) segments sharing a cell
@@ -126,15 +130,17 @@ def arc_coordinates(fam):
     return sig, h
 
 
-def transfer(grid, tgt, src):
-    """The direct transfer onto the target family's interior nodes.
+def transfer(grid, tgt, src, lines=None):
+    """The direct transfer onto the target family's interior nodes (of the
+    target curves in `lines` only, if given: for sampled checks on large
+    grids; the other rows stay zero).
 
     Returns (X, e0, e1): X sparse (tgt nodes x src nodes) and, per target
     node, the weights of its own line's first and last node values (the
     Dirichlet ends, brackets where a side has no intersection).  A target
     node's value is X v_src + e0 * (first end value) + e1 * (last end value);
     rows of end nodes are zero."""
-    kt, s, ks, t = intersections(grid, tgt, src)
+    kt, s, ks, t = intersections(grid, tgt, src, lines)
     sig, h = arc_coordinates(tgt)
     sx = sig[kt] + s * h[kt + 1]            # arc coordinate of each intersection
     line_of = np.repeat(np.arange(tgt.n_lines), np.diff(tgt.offsets))
@@ -143,7 +149,7 @@ def transfer(grid, tgt, src):
     e0 = np.zeros(tgt.n_nodes)
     e1 = np.zeros(tgt.n_nodes)
     inner = tgt.interior()
-    for l in range(tgt.n_lines):
+    for l in (range(tgt.n_lines) if lines is None else lines):
         a, b = tgt.offsets[l], tgt.offsets[l + 1]
         sel = np.nonzero(lx == l)[0]     # sorted by (kt, s): sigma non-decreasing
         xs = sx[sel]

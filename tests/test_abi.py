@@ -312,3 +312,43 @@ def test_host_scatter_factors_rebuild_the_stencil(maker):
                 np.add.at(dense, (r, k[ok, q] + 1), c[ok, q] * tq[ok, q])
             assert np.max(np.abs(dense - ref)) < (1e-4 if quant else 1e-12), (f, quant)
     s.close()
+
+
+def test_host_direct_transfer_full_size_sampled():
+    """The bench's direct-transfer configuration (C2 2049^2): the set-up's
+    brackets on 12 sampled curves of each family equal the oracle's transfer
+    rows for them (the oracle restricted to those curves)."""
+    import scipy.sparse as sp
+    from oracle import direct as D
+    from paper_2411_11041_amd.adr import Solver
+    p = W.c2(2049)
+    g = geo.Grid(p.box, p.nx, p.ny)
+    dom = geo.make_domain(p.domain, p.dom_params, p.box)
+    b1, b2 = (p.beta1, p.beta2) if p.beta1 is not None else geo.beta_from_psi(g, p.psi)
+    fams = geo.build_families(g, dom, geo.Flow(g, b1, b2))
+    s = Solver(p, host_only=True, transfer="direct")
+    rng = np.random.default_rng(0)
+    for f in (0, 1):
+        tgt, src = fams[f], fams[1 - f]
+        off, x, _ = s.export_lines(0, f)
+        assert np.array_equal(off, tgt.offsets) and np.max(np.abs(x - tgt.x)) < 1e-12
+        lines = np.sort(rng.choice(tgt.n_lines, 12, replace=False))
+        X, e0, e1 = D.transfer(g, tgt, src, lines=lines)
+        k, w = s.export_direct(0, f)
+        rows = np.concatenate([np.arange(tgt.offsets[l] + 1, tgt.offsets[l + 1] - 1) for l in lines])
+        ri, ci, vi = [], [], []
+        ends = np.zeros((len(rows), 2))
+        for side in (0, 1):
+            kk = k[rows, side]
+            ok = kk >= 0
+            r = np.nonzero(ok)[0]
+            ri += [r, r]
+            ci += [kk[ok], kk[ok] + 1]
+            vi += [w[rows[ok], 2 * side], w[rows[ok], 2 * side + 1]]
+            ends[~ok, side] = w[rows[~ok], 2 * side]
+        R = sp.csr_matrix((np.concatenate(vi), (np.concatenate(ri), np.concatenate(ci))),
+                          shape=(len(rows), src.n_nodes))
+        d = (R - X[rows]).tocoo()
+        assert d.nnz == 0 or np.max(np.abs(d.data)) < 1e-12
+        assert np.max(np.abs(ends[:, 0] - e0[rows])) < 1e-12 and np.max(np.abs(ends[:, 1] - e1[rows])) < 1e-12
+    s.close()
