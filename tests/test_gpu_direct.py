@@ -251,3 +251,25 @@ def test_direct_batch_bucketed_fp32_reaches_the_fixed_point():
         U, *_ = D.DirectSweeps(o).iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-12)
         assert rel_l2(got[off[i]:off[i + 1]], U, o.inner_idx) < 1e-7, i
     s.close()
+
+
+def test_direct_context_keeps_the_grid_route_elsewhere():
+    """A context set up with the direct transfer serves the other calls (the
+    march, eq. (11), the residual) on the grid transfer, bitwise as a grid
+    context does."""
+    print("[case] direct context: time_step, initial_guess, residual on the grid route", flush=True)
+    p = with_g(W.c3(65))
+    o = Oracle(p)
+    out = []
+    for tr in ("grid", "direct"):
+        s = solver(p, precision="fp64", theta=1.0, dt=0.05, transfer=tr)
+        u = dev(o.with_boundary(p.u0.ravel() * o.mask.ravel()))
+        s.time_step(u, 1.0, 0.005, 4)
+        g = dev(o.zero_field())
+        s.initial_guess(g)
+        r = s.residual(g)
+        torch.cuda.synchronize()
+        out.append((u.cpu().numpy(), g.cpu().numpy(), np.asarray(r)))
+        s.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
