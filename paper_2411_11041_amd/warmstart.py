@@ -29,7 +29,8 @@ from .adr import Net, Solver
 
 
 class Workload:
-    def __init__(self, n=257, batch=128, precision="fp32", fp32_sweeps=3, dt=0.05, graph=True, coarsen=1):
+    def __init__(self, n=257, batch=128, precision="fp32", fp32_sweeps=3, dt=0.05, graph=True, coarsen=1,
+                 adaptive=False, split_lines=0):
         import torch
         if coarsen < 1 or (n - 1) % coarsen:
             raise ValueError(f"coarsening factor {coarsen} does not divide {n - 1}")
@@ -49,7 +50,8 @@ class Workload:
         mc = np.zeros((self.nc, self.nc), np.uint8)
         mc[1:-1, 1:-1] = 1
         self.mask_c = torch.from_numpy(mc.ravel()).cuda()
-        self.kw = dict(precision=precision, fp32_sweeps=fp32_sweeps, theta=1.0, dt=dt, graph=graph)
+        self.kw = dict(precision=precision, fp32_sweeps=fp32_sweeps, theta=1.0, dt=dt, graph=graph,
+                       adaptive=adaptive, split_lines=split_lines)
         self.solver = None
 
     def problems(self, seeds):
@@ -68,6 +70,16 @@ class Workload:
         else:
             self.solver.update(probs)
         return self.solver
+
+    def tune(self, seeds, tol, max_iters=2000):
+        """adr_autotune on the batch of these seeds (from zero): the context
+        bound to them keeps the fastest line launches, shapes and schedule.
+        Returns the autotuner's choice."""
+        import torch
+        probs = self.problems(seeds)
+        s = self._bind(probs)
+        work = torch.zeros(len(probs) * self.HW, dtype=torch.float64, device="cuda")
+        return s.autotune(work, max_iters, tol)
 
     def solve_batch(self, seeds, tol, max_iters=2000, start=None):
         """Returns u (device, B*HW), iters, rel, seconds.  start: None (zero) or a tensor."""
