@@ -146,6 +146,19 @@ typedef struct {
                              gamma-curves, rel = |v' - v|_2 / |Phi(0)|_2 over the interior
                              gamma-curve nodes, u out = the scatter of Sec. 6 of the last
                              gamma values.  The other calls keep the grid transfer */
+    int32_t increments;   /* FP32_LINES mode with transfer = 0: 0 the FP32 increment sweeps use
+                             the grid transfer, the linear part of the FP64 sweeps themselves; 1
+                             they use the direct transfer of `transfer` (the same linear map
+                             up to the difference of the two transfers, an approximation that
+                             is cheaper: two line kernels per sweep and no scatter): each
+                             block gathers the FP64 sweep's update onto the gamma-curves, runs
+                             its FP32 sweeps on the curve values, and adds their sum to the
+                             state by one scatter.  The FP64 sweeps, and with them the
+                             iterate's fixed point, the residual and the stop, are the grid
+                             route's in either case; only the sweep count may differ.  Set-up
+                             builds the direct-transfer records (adr_autotune then also times
+                             both kinds of increment sweeps).  No effect with transfer = 1,
+                             whose increments are direct already; another value: ADR_EINVAL */
 } adr_options;
 
 /* Builds the curve families of every instance (host, FP64) and uploads the
@@ -217,7 +230,9 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
  *      current schedule;
  *   2. with the faster of those, each candidate schedule: a fixed count of
  *      FP32 sweeps per FP64 sweep (2, 3, 4, 6) and the adaptive schedule
- *      with at most 6, 8, 12, 16 or 24;
+ *      with at most 6, 8, 12, 16 or 24; each with both kinds of increment
+ *      sweeps (options.increments) when the context has the direct-transfer
+ *      records (set up with increments = 1);
  *   3. GMRES(m) (options.krylov) with m = 10, 20, 30, kept if faster than the
  *      best schedule.
  * With bucketed launches, between the two steps, each length bucket's
@@ -226,11 +241,12 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
  * may be NULL): best_fp32_sweeps and best_adaptive (the count or maximum, and
  * the adaptive flag), best_ms (its time), best_split (the launch choice),
  * best_shapes (5 entries, the shape of each bucket), best_krylov (0, or the
- * GMRES restart length chosen).  Kernel timers (timing
+ * GMRES restart length chosen), best_increments (options.increments chosen).
+ * Kernel timers (timing
  * mode) are reset afterwards.  Synchronises. */
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
                         int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes,
-                        int32_t *best_krylov);
+                        int32_t *best_krylov, int32_t *best_increments);
 
 /* Graph replay of the stationary solve's blocks on (1) or off (0) from now on
  * (options.graph); captured graphs are dropped.  Errors: ADR_EINVAL (host-only
@@ -313,8 +329,8 @@ adr_status adr_export_scatter(const adr_ctx *ctx, int32_t inst, int32_t family, 
 adr_status adr_export_scatter_factors(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_rows,
                                       double *wh, double *lam, double *t);
 
-/* Test export (host-only contexts set up with options.transfer = 1): the
- * direct-transfer records onto every node of one instance's family (0 beta,
+/* Test export (host-only contexts set up with options.transfer = 1 or
+ * options.increments = 1): the direct-transfer records onto every node of one instance's family (0 beta,
  * 1 gamma) from the other family's line values, in the node order of
  * adr_export_lines.  Node q's value is
  *   (k[2q] >= 0 ? w[4q] v[k[2q]] + w[4q+1] v[k[2q]+1] : w[4q] x_first)
@@ -323,7 +339,7 @@ adr_status adr_export_scatter_factors(const adr_ctx *ctx, int32_t inst, int32_t 
  * x_first, x_last the Dirichlet values at the ends of q's own curve; end nodes
  * carry k = -1 and zero weights.  Call with NULL arrays to get *n_nodes, then
  * with k (2 n_nodes) and w (4 n_nodes) host buffers.  Errors: ADR_EINVAL (a
- * device context, transfer != 1, an index out of range). */
+ * device context, a context without the records, an index out of range). */
 adr_status adr_export_direct(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_nodes, int32_t *k,
                              double *w);
 
@@ -342,6 +358,9 @@ adr_status adr_set_timing(adr_ctx *ctx, int32_t on);
  * curves in its list (classes 0, 1) or interior grid nodes of its scatter
  * blocks (classes 2, 3), over the lists compacted to the unfinished instances
  * when a batched solve compacts them, else over all instances; 0 for the norm.
+ * With direct increments (options.increments = 1) the FP32 classes 2 and 3
+ * time each block's gather of the update onto the gamma-curves (work: gamma
+ * line unknowns) and its closing scatter.
  * ms_out, count_out and work_out hold 5 entries (each may be NULL).  reset !=
  * 0 clears that precision's counters after reading.  Synchronises the stream. */
 adr_status adr_kernel_times(adr_ctx *ctx, int32_t precision, double *ms_out, int64_t *count_out,

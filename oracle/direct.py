@@ -230,6 +230,19 @@ class DirectSweeps:
         rhs = o.MG.apply(u) - (1.0 - theta) * dt * o.mu * o.KG.apply(u)
         return lfe.solve_lines(A, rhs, o.inner[1], o.gend[1])
 
+    def linear_sweep(self, vG, theta, dt):
+        """The linear part of sweep: zero load and zero Dirichlet values at every
+        curve end (the map that carries an update of v_G to the next one)."""
+        o = self.o
+        u = self.to_beta(vG, bc=False)
+        A = o.MB + o.SB.scale(theta * dt)
+        rhs = o.MB.apply(u) - (1.0 - theta) * dt * o.SB.apply(u)
+        vB = lfe.solve_lines(A, rhs, o.inner[0], np.zeros(o.fams[0].n_nodes))
+        u = self.to_gamma(vB, bc=False)
+        A = o.MG + o.KG.scale(theta * dt * o.mu)
+        rhs = o.MG.apply(u) - (1.0 - theta) * dt * o.mu * o.KG.apply(u)
+        return lfe.solve_lines(A, rhs, o.inner[1], np.zeros(o.fams[1].n_nodes))
+
     def zero_state(self):
         o = self.o
         v = np.zeros(o.fams[1].n_nodes)
@@ -258,3 +271,38 @@ class DirectSweeps:
             if rel <= tol or not np.isfinite(rel):
                 break
         return self.o.scatter(1, v), it, rel, (hist if history else None), v
+
+
+def hybrid_iterate(o, ds, U0, theta, dt, m, max_iters, tol):
+    """The stationary iteration of eq. (10) on the grid (o.step, the grid
+    transfer) whose extra sweeps between two full sweeps are taken with the
+    direct transfer: after a full sweep U -> U' with update d = U' - U, the
+    next m updates are approximated on the gamma-curves, v_1 = T_d G_G d,
+    v_{k+1} = T_d v_k (T_d = ds.linear_sweep, G_G the bilinear gather with
+    zero ends), and U' + P_G (v_1 + ... + v_m) starts the next full sweep
+    (P_G the gamma scatter's linear part).  Only the full sweeps measure
+    rel = |U' - U| / |Phi(0)| and stop the iteration, so its limit is the
+    grid route's fixed point; the direct sweeps count as sweeps.  Blocks of m
+    fixed; m = 0 is o.iterate.  Returns (U, sweeps, rel)."""
+    cn = o.c_norm(theta, dt)
+    U = o.with_boundary(U0)
+    k, rel = 0, np.inf
+    inner = o.inner[1]
+    while k < max_iters:
+        Un = o.step(U, theta, dt)
+        d = Un - U
+        rel = o.norm(d) / cn
+        U = Un
+        k += 1
+        if rel <= tol or not np.isfinite(rel) or k + m + 1 > max_iters:
+            break
+        if m:
+            v = o.G[1] @ d
+            v[~inner] = 0.0
+            S = np.zeros_like(v)
+            for _ in range(m):
+                v = ds.linear_sweep(v, theta, dt)
+                S += v
+            U = U + o.P[1] @ S
+            k += m
+    return U, k, rel

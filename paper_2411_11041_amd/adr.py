@@ -51,7 +51,7 @@ class Options(C.Structure):
                 ("stream", C.c_void_p), ("timing", C.c_int32), ("host_only", C.c_int32),
                 ("graph", C.c_int32), ("adaptive", C.c_int32), ("split_lines", C.c_int32),
                 ("pivot_tol", C.c_double), ("splitting", C.c_int32), ("stabilize", C.c_int32),
-                ("krylov", C.c_int32), ("transfer", C.c_int32)]
+                ("krylov", C.c_int32), ("transfer", C.c_int32), ("increments", C.c_int32)]
 
 
 _lib = None
@@ -76,7 +76,7 @@ def load():
     lib.adr_update.argtypes = [vp, P(Problem), i32]
     lib.adr_split_iterate.argtypes = [vp, vp, i32, dbl, P(i32), P(dbl)]
     lib.adr_split_iterate_judged.argtypes = [vp, vp, vp, i32, dbl, P(i32), P(dbl), P(i32)]
-    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32), P(i32), P(i32)]
+    lib.adr_autotune.argtypes = [vp, vp, i32, dbl, P(i32), P(i32), P(dbl), P(i32), P(i32), P(i32), P(i32)]
     lib.adr_set_line_shapes.argtypes = [vp, P(i32)]
     lib.adr_set_graph.argtypes = [vp, i32]
     lib.adr_set_timing.argtypes = [vp, i32]
@@ -153,12 +153,17 @@ def line_solve(off, lo, di, up, rhs, x=None, singular=None, pivot_tol=0.0, strea
     return x
 
 
+def _kind(v):
+    """options.transfer / options.increments from "grid", "direct" (or the raw value)."""
+    return {"grid": 0, "direct": 1}[v] if isinstance(v, str) else int(v)
+
+
 class Solver:
     """One context over a batch of problems (workloads.Problem-like objects)."""
 
     def __init__(self, problems, precision="fp64", theta=1.0, dt=0.05, fp32_sweeps=3,
                  stream=None, timing=False, host_only=False, graph=False, adaptive=False, split_lines=False,
-                 pivot_tol=0.0, splitting="lie", stabilize=False, krylov=0, transfer="grid"):
+                 pivot_tol=0.0, splitting="lie", stabilize=False, krylov=0, transfer="grid", increments="grid"):
         self.lib = load()
         if not isinstance(problems, (list, tuple)):
             problems = [problems]
@@ -172,7 +177,7 @@ class Solver:
                       C.c_void_p(stream) if stream else None, int(bool(timing)), int(bool(host_only)),
                       int(bool(graph)), int(bool(adaptive)), int(split_lines), float(pivot_tol),
                       {"lie": 0, "strang": 1}[splitting], int(bool(stabilize)), int(krylov),
-                      {"grid": 0, "direct": 1}[transfer])
+                      _kind(transfer), _kind(increments))
         self.n = len(problems)
         self.ctx = C.c_void_p()
         st = self.lib.adr_setup(arr, self.n, C.byref(opt), C.byref(self.ctx))
@@ -234,16 +239,19 @@ class Solver:
         on `work` (overwritten), and keeps the fastest; returns (count or
         maximum, adaptive, ms, split_lines: 0 one launch, 1 per bucket, 2 per
         bucket on concurrent streams, shapes: the workgroup shape of each length
-        bucket, krylov: 0 or the GMRES restart length)."""
+        bucket, krylov: 0 or the GMRES restart length, increments: 0 grid, 1
+        direct-transfer increment sweeps)."""
         best = C.c_int32()
         ad = C.c_int32()
         ms = C.c_double()
         sp = C.c_int32()
         sh = (C.c_int32 * 5)()
         kr = C.c_int32()
+        inc = C.c_int32()
         self._check(self.lib.adr_autotune(self.ctx, _device_ptr(work), int(max_iters), float(tol),
-                                          C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp), sh, C.byref(kr)))
-        return best.value, bool(ad.value), ms.value, int(sp.value), list(sh), int(kr.value)
+                                          C.byref(best), C.byref(ad), C.byref(ms), C.byref(sp), sh, C.byref(kr),
+                                          C.byref(inc)))
+        return best.value, bool(ad.value), ms.value, int(sp.value), list(sh), int(kr.value), int(inc.value)
 
     def set_graph(self, on):
         """Replay the stationary solve's blocks from HIP graphs (include/adr.h)."""

@@ -116,6 +116,9 @@ struct adr_ctx {
     double *lpart = nullptr, *cnorm_d = nullptr;
     int *inst_lstart = nullptr;
     bool cnorm_d_valid = false;
+    // direct increments on the grid route (options.increments = 1): the FP32
+    // sum of a block's gamma-curve increments
+    float *hsum = nullptr;
     double *par = nullptr;  // [slot][fam][inst][8]
     std::vector<double> par_h;
     double *Uh64 = nullptr, *Z64 = nullptr, *partial = nullptr, *cnorm = nullptr, *rel = nullptr;
@@ -472,13 +475,15 @@ struct adr_ctx {
         });
     }
     // One FP32 increment sweep with the direct transfer: d <- T d on the curve
-    // values (fam[f].v32), the gamma increments added to the FP64 state.
-    void direct_sweep32(const int *dn) {
+    // values (fam[f].v32), the gamma increments added to the FP64 state (or,
+    // with sum32, to the FP32 sum of the grid route's direct increments).
+    void direct_sweep32(const int *dn, float *sum32 = nullptr) {
         timed(1, 0, line_work(0), [&] {
             return lines<float>(0, fam[0].a32d, fam[1].v32, fam[0].v32, par_ptr(kSlotLin, 0), dn);
         });
         adr::LineArgs<float> g = fam[1].a32d;
-        g.vacc = fam[1].v64;
+        if (sum32) g.vacc32 = sum32;
+        else g.vacc = fam[1].v64;
         timed(1, 1, line_work(1), [&] {
             return lines<float>(1, g, fam[0].v32, fam[1].v32, par_ptr(kSlotLin, 1), dn);
         });
@@ -497,9 +502,31 @@ struct adr_ctx {
     // one block of the stationary iteration: FP32 increment sweeps, then an FP64
     // sweep with the update norm (the first block has no FP32 sweeps)
     void block(double *u, int fp32_sweeps, double tol) {
-        for (int k = 0; k < fp32_sweeps; ++k) sweep32(u, done);
+        if (hsum && opt.increments == 1 && fp32_sweeps > 0) {
+            hybrid_increments(u, fp32_sweeps);
+        } else {
+            for (int k = 0; k < fp32_sweeps; ++k) sweep32(u, done);
+        }
         sweep64(kSlotStep, u, u, 1, done);
         norm(fp32_sweeps + 1, tol, 0);
+    }
+    // The block's m FP32 increments with the direct transfer (options.increments
+    // = 1): the last FP64 update d (d32) gathered onto the gamma-curves, m direct
+    // increment sweeps v <- T v summed into S (FP32, zero at the curve ends),
+    // then one scatter U += P_G S (the FP32 increment scatter).  The increments
+    // only steer the iterate: the FP64 grid-route sweeps fix the limit and
+    // measure the residual.  Timed as FP32 classes 2 (the gather) and 3 (the
+    // scatter).
+    void hybrid_increments(double *u, int m) {
+        DevFam &G = fam[1];
+        adr::LineArgs<float> a = largs(G, G.a32);
+        a.gend = nullptr;
+        const int nl = G.act >= 0 ? G.act : G.n_lines;
+        timed(1, 2, line_work(1), [&] { return adr::launch_line_values32(a, nl, d32, G.v32, hsum, st); });
+        for (int q = 0; q < m; ++q) direct_sweep32(done, hsum);
+        timed(1, 3, grid_work(), [&] {
+            return adr::launch_scatter<float, double>(2, sargs(G.s32), hsum, u, d32, partial, done, st);
+        });
     }
 
     // Adaptive schedule: after each FP64 sweep the per-instance rel is
@@ -559,6 +586,7 @@ struct adr_ctx {
     const double *g_u = nullptr;
     double g_tol = -1.0;
     int g_split = -1;  // the line launches (options.split_lines) of the captured graphs
+    int g_inc = -1;    // and their increment sweeps (options.increments)
     hipStream_t cap = nullptr;
     // concurrent bucket launches (options.split_lines == 2): two more streams of
     // the default priority, forked from and joined back into st by events
@@ -574,11 +602,12 @@ struct adr_ctx {
     // one block replayed from its graph (captured now if new) on st, the
     // capture stream; the launch lists must be the full ones (not compacted)
     void graph_block(double *ub, int m, double tol) {
-        if (g_u != ub || g_tol != tol || g_split != opt.split_lines) {
+        if (g_u != ub || g_tol != tol || g_split != opt.split_lines || g_inc != opt.increments) {
             drop_graph();
             g_u = ub;
             g_tol = tol;
             g_split = opt.split_lines;
+            g_inc = opt.increments;
         }
         auto it = gblocks.find(m);
         if (it == gblocks.end()) {
@@ -658,6 +687,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         if (opt->transfer != 0 && opt->transfer != 1) throw Error{ADR_EINVAL, "transfer must be 0 or 1"};
         if (opt->transfer == 1 && opt->krylov != 0)
             throw Error{ADR_EINVAL, "krylov applies to the grid transfer (transfer = 0)"};
+        if (opt->increments != 0 && opt->increments != 1) throw Error{ADR_EINVAL, "increments must be 0 or 1"};
         if (opt->fp32_sweeps < 0) throw Error{ADR_EINVAL, "fp32_sweeps must be >= 0"};
         C->opt = *opt;
         C->n_inst = n_probs;
@@ -713,7 +743,8 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
         for (int i = 0; i < n; ++i)
             if (errs[i].code != ADR_OK)
                 throw Error{errs[i].code, "instance " + std::to_string(i) + ": " + errs[i].msg};
-        if (opt->transfer == 1) {
+        const bool direct_recs = opt->transfer == 1 || opt->increments == 1;
+        if (direct_recs) {
             run_pool([&](int i) {
                 adr::build_direct(G[i].g, G[i].fam[0], G[i].hk[0], G[i].fam[1], G[i].drec[0]);
                 adr::build_direct(G[i].g, G[i].fam[1], G[i].hk[1], G[i].fam[0], G[i].drec[1]);
@@ -948,7 +979,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 F.a32.phi = C->phi32;
             }
             F.a32.ptol = opt->pivot_tol > 0.0 ? opt->pivot_tol : 64.0 * 1.1920928955078125e-07;
-            if (opt->transfer == 1) {
+            if (direct_recs) {
                 // direct-transfer records: source nodes in the other family's packed numbering
                 std::vector<int> dk(2 * static_cast<size_t>(F.n_nodes), -1);
                 std::vector<double> dw(4 * static_cast<size_t>(F.n_nodes), 0.0);
@@ -1035,6 +1066,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                                             upload(sw, own, st), upload(rt, own, st), npad};
             F.v64 = dalloc<double>(F.n_nodes, own);
             F.v32 = dalloc<float>(F.n_nodes, own);
+            if (f == 1 && opt->increments == 1 && opt->transfer == 0) C->hsum = dalloc<float>(F.n_nodes, own);
             for (int i = 0; i < n; ++i) C->geo[f].push_back(G[i].fam[f]);
         }
 
@@ -1595,7 +1627,7 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
 
 adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double tol, int32_t *best_fp32_sweeps,
                         int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes,
-                        int32_t *best_krylov) {
+                        int32_t *best_krylov, int32_t *best_increments) {
     if (!ctx) return ADR_EINVAL;
     if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES ||
         ctx->opt.transfer != 0) {
@@ -1605,14 +1637,18 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     // (FP32 sweeps per FP64 sweep or their maximum, adaptive)
     static const int kCand[][2] = {{2, 0}, {3, 0}, {4, 0}, {6, 0}, {6, 1}, {8, 1}, {12, 1}, {16, 1}, {24, 1}};
     const int32_t saved = ctx->opt.fp32_sweeps, saved_ad = ctx->opt.adaptive, saved_split = ctx->opt.split_lines;
-    const int32_t saved_kr = ctx->opt.krylov;
+    const int32_t saved_kr = ctx->opt.krylov, saved_inc = ctx->opt.increments;
     ctx->opt.krylov = 0;
+    // the increment kinds to try: the grid route's, and the direct transfer's
+    // when the context holds its records (set up with increments = 1)
+    const int n_inc = ctx->hsum ? 2 : 1;
     const size_t nbytes = sizeof(double) * static_cast<size_t>(ctx->goff.back());
     auto restore = [&]() {
         ctx->opt.fp32_sweeps = saved;
         ctx->opt.adaptive = saved_ad;
         ctx->opt.split_lines = saved_split;
         ctx->opt.krylov = saved_kr;
+        ctx->opt.increments = saved_inc;
         ctx->drop_graph();
     };
     // one timed solve from zero (the second of two runs: the first also
@@ -1676,27 +1712,31 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
         }
         ctx->drop_graph();  // a graph captured in step 1 holds the launches of the old shapes
     }
-    // 2. the FP32/FP64 sweep schedule with those launches
-    int best = saved, best_ad = saved_ad;
+    // 2. the FP32/FP64 sweep schedule and the kind of increments with those launches
+    int best = saved, best_ad = saved_ad, best_inc = 0;
     double best_t = INFINITY;
-    for (const auto &cand : kCand) {
-        const int c = cand[0];
-        ctx->opt.fp32_sweeps = c;
-        ctx->opt.adaptive = cand[1];
-        double t;
-        const adr_status st = time_solve(t);
-        if (st != ADR_OK) {
-            restore();
-            return st;
+    for (int inc = 0; inc < n_inc; ++inc)
+        for (const auto &cand : kCand) {
+            const int c = cand[0];
+            ctx->opt.fp32_sweeps = c;
+            ctx->opt.adaptive = cand[1];
+            ctx->opt.increments = inc;
+            double t;
+            const adr_status st = time_solve(t);
+            if (st != ADR_OK) {
+                restore();
+                return st;
+            }
+            if (t < best_t) {
+                best_t = t;
+                best = c;
+                best_ad = cand[1];
+                best_inc = inc;
+            }
         }
-        if (t < best_t) {
-            best_t = t;
-            best = c;
-            best_ad = cand[1];
-        }
-    }
     ctx->opt.fp32_sweeps = best;
     ctx->opt.adaptive = best_ad;
+    ctx->opt.increments = best_inc;
     // 3. GMRES(m) on (I - T) U = c (FP64 sweeps) with those launches, against the best schedule
     int best_kr = 0;
     for (int m : {10, 20, 30}) {
@@ -1722,6 +1762,7 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     if (best_shapes)
         for (int b = 0; b < adr::kLineBuckets; ++b) best_shapes[b] = ctx->fam[0].bshape[b];
     if (best_krylov) *best_krylov = best_kr;
+    if (best_increments) *best_increments = best_inc;
     return ADR_OK;
 }
 
@@ -1935,7 +1976,7 @@ adr_status adr_export_scatter_factors(const adr_ctx *ctx, int32_t inst, int32_t 
 
 adr_status adr_export_direct(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_nodes, int32_t *k,
                              double *w) {
-    if (!ctx || !ctx->opt.host_only || ctx->opt.transfer != 1 || inst < 0 || inst >= ctx->n_inst || family < 0 ||
+    if (!ctx || !ctx->opt.host_only || (ctx->opt.transfer != 1 && ctx->opt.increments != 1) || inst < 0 || inst >= ctx->n_inst || family < 0 ||
         family > 1)
         return ADR_EINVAL;
     const std::vector<adr::DirRec> &D = ctx->host_geo[inst].drec[family];

@@ -37,6 +37,7 @@ struct LineArgs {
     const int *lslot;
     float *dout;         // optional with dk: per node, new value - old value in vout (0 at the ends)
     double *vacc;        // optional with dk: per interior node, vacc += new value
+    float *vacc32;       // optional with dk: the same into an FP32 sum
 };
 
 // Record indices relative to the slot's first record (ScatterArgs::rd)
@@ -141,6 +142,11 @@ hipError_t launch_kresidual(const int *gb, int npad, const double *phi, const do
 // or zero) and on the interior nodes the bilinear gather of U (eq. (22)), or
 // zero when U is NULL.  One workgroup per curve of the full list.
 hipError_t launch_line_values(const LineArgs<double> &a, int n_lines, const double *U, double *v, hipStream_t st);
+// the same from an FP32 blocked field into FP32 curve values (ends from a.gend,
+// NULL for increments), clearing zacc (when set) on the same nodes; the lines
+// are a.lidx[0 .. n_lines) when a.lidx is set
+hipError_t launch_line_values32(const LineArgs<float> &a, int n_lines, const float *U, float *v, float *zacc,
+                                hipStream_t st);
 
 // Lout = Lbase + M G un / dt on the interior nodes of the beta-curves (the
 // full line list of a), ends copied: the load of an implicit Euler step.

@@ -404,6 +404,7 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
                     if (a.dout) a.dout[o + j] = static_cast<float>(dlt);
                 }
                 if (a.vacc) a.vacc[o + j] += static_cast<double>(val);
+                if (a.vacc32) a.vacc32[o + j] += static_cast<float>(val);
             } else if (a.dout) {
                 a.dout[o + j] = 0.0f;
             }
@@ -637,24 +638,28 @@ __global__ __launch_bounds__(kThreads) void k_shift_load(LineArgs<double> a, con
 }
 
 // Curve values from a grid field: ends from gend (or 0), interior nodes the
-// bilinear gather of U (eq. (22)), or 0 when U is NULL.
-__global__ __launch_bounds__(kThreads) void k_line_values(LineArgs<double> a, const double *__restrict__ U,
-                                                          double *__restrict__ v) {
-    const int l = static_cast<int>(blockIdx.x);
+// bilinear gather of U (eq. (22)), or 0 when U is NULL; zacc, when set, is
+// cleared on the same nodes (an accumulator of later curve values).  One
+// workgroup per line of the list (a.lidx when set).
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_line_values(LineArgs<T> a, const T *__restrict__ U,
+                                                          T *__restrict__ v, T *__restrict__ zacc) {
+    const int l = a.lidx ? a.lidx[blockIdx.x] : static_cast<int>(blockIdx.x);
     const int o = a.loff[l], n = a.lcnt[l], inst = a.linst[l];
     const int nx = a.inst_nx[inst];
     for (int j = threadIdx.x; j < n; j += kThreads) {
-        double val = 0.0;
+        T val = T(0);
         if (j == 0 || j == n - 1) {
-            val = a.gend ? a.gend[2 * l + (j == 0 ? 0 : 1)] : 0.0;
+            val = a.gend ? a.gend[2 * l + (j == 0 ? 0 : 1)] : T(0);
         } else if (U) {
             const int c = a.cell[o + j];
             const int sx = (c & 7) == 7 ? 25 : 1;
             const int cu = c + (((c >> 3) & 3) == 3 ? nx - 24 : 8);
-            const double lx = a.lx[o + j], ly = a.ly[o + j];
-            val = (1.0 - ly) * ((1.0 - lx) * U[c] + lx * U[c + sx]) + ly * ((1.0 - lx) * U[cu] + lx * U[cu + sx]);
+            const T lx = a.lx[o + j], ly = a.ly[o + j];
+            val = (T(1) - ly) * ((T(1) - lx) * U[c] + lx * U[c + sx]) + ly * ((T(1) - lx) * U[cu] + lx * U[cu + sx]);
         }
         v[o + j] = val;
+        if (zacc) zacc[o + j] = T(0);
     }
 }
 
@@ -861,7 +866,14 @@ hipError_t launch_shift_load(const LineArgs<double> &a, int n_lines, int nmax, c
 
 hipError_t launch_line_values(const LineArgs<double> &a, int n_lines, const double *U, double *v, hipStream_t st) {
     if (n_lines == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_line_values, dim3(n_lines), dim3(kThreads), 0, st, a, U, v);
+    hipLaunchKernelGGL(k_line_values<double>, dim3(n_lines), dim3(kThreads), 0, st, a, U, v, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_line_values32(const LineArgs<float> &a, int n_lines, const float *U, float *v, float *zacc,
+                                hipStream_t st) {
+    if (n_lines == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_line_values<float>, dim3(n_lines), dim3(kThreads), 0, st, a, U, v, zacc);
     return hipGetLastError();
 }
 

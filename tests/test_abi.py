@@ -274,6 +274,25 @@ def test_direct_transfer_option_errors():
     with pytest.raises(ADRError):
         s.export_direct(0, 0)  # the grid transfer builds no direct records
     s.close()
+    for bad in (dict(increments=2), dict(increments=-1), dict(transfer=2)):
+        with pytest.raises(ADRError) as e:
+            Solver(p, host_only=True, **bad)
+        assert e.value.code == ADR_EINVAL, bad
+
+
+def test_direct_increments_build_the_direct_records():
+    """options.increments = 1 on the grid transfer builds the same direct
+    records as options.transfer = 1 (the increment sweeps read them)."""
+    from paper_2411_11041_amd.adr import Solver
+    p = W.c2(65)
+    a = Solver(p, host_only=True, increments="direct")
+    b = Solver(p, host_only=True, transfer="direct")
+    for f in (0, 1):
+        ka, wa = a.export_direct(0, f)
+        kb, wb = b.export_direct(0, f)
+        assert np.array_equal(ka, kb) and np.array_equal(wa, wb)
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("maker", [lambda: W.c1(65), lambda: W.c2(129), lambda: W.c4_instance(0, n_max=120),

@@ -246,7 +246,7 @@ def test_autotune_keeps_a_candidate_and_the_fixed_point():
     p = W.c2(129)
     s = solver(p, precision="fp32", fp32_sweeps=3)
     work = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
-    best, adaptive, ms, split, shapes, kr = s.autotune(work, 2000, 1e-10)
+    best, adaptive, ms, split, shapes, kr, inc = s.autotune(work, 2000, 1e-10)
     assert ((best in (2, 3, 4, 6) and not adaptive) or (best in (6, 8, 12, 16, 24) and adaptive)) and ms > 0
     assert split in (0, 1, 2)
     assert all(0 <= v < n for v, n in zip(shapes, (1, 1, 2, 3, 3)))

@@ -199,3 +199,79 @@ def test_direct_transfer_is_closer_to_the_exact_solution_than_the_grid_route():
         ue = W.manufactured_u(X, Y).ravel()
         m = o.inner_idx
         assert np.max(np.abs(U[m] - ue[m])) < 0.75 * np.max(np.abs(Ug[m] - ue[m]))
+
+
+@pytest.mark.parametrize("maker", [lambda: W.c1(17), lambda: W.c2(17), lambda: W.c4_instance(1, n_max=40)])
+def test_linear_sweep_is_the_sweep_without_load_and_end_values(maker):
+    """The direct sweep is affine in the interior gamma values: with z the
+    state carrying the end values and zero inside, sweep(z + v) - sweep(z) is
+    the linear part for every v with zero ends, and the linear part maps 0 to 0."""
+    p = maker()
+    X, Y = p.coords()
+    p.g = np.sin(3 * X) + Y ** 2
+    o = Oracle(p)
+    ds = D.DirectSweeps(o)
+    z = ds.zero_state()
+    inner = o.inner[1]
+    rng = np.random.default_rng(5)
+    v = np.where(inner, rng.standard_normal(z.size), 0.0)
+    ref = ds.sweep(z + v, 1.0, 0.05) - ds.sweep(z, 1.0, 0.05)
+    got = ds.linear_sweep(v, 1.0, 0.05)
+    assert np.max(np.abs(got - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+    assert np.all(got[~inner] == 0.0)
+    assert np.all(ds.linear_sweep(np.zeros_like(v), 1.0, 0.05) == 0.0)
+
+
+def test_hybrid_without_direct_sweeps_is_the_grid_iteration():
+    p = W.c2(17)
+    o = Oracle(p)
+    U, k, rel = D.hybrid_iterate(o, D.DirectSweeps(o), o.zero_field(), 1.0, 0.05, 0, 9, 0.0)
+    Ug, it, relg, _ = o.iterate(o.zero_field(), 1.0, 0.05, 9, 0.0)
+    assert k == it == 9 and rel == relg and np.array_equal(U, Ug)
+
+
+@pytest.mark.parametrize("maker", [lambda: W.c1(13), lambda: W.c2(17), lambda: W.c4_instance(0, n_max=40)])
+@pytest.mark.parametrize("m", [3, 8])
+def test_hybrid_limit_is_the_dense_grid_fixed_point(maker, m):
+    """The grid sweep is affine, U -> T U + c on the interior nodes; whatever
+    the direct sweeps between two grid sweeps contribute, the hybrid
+    iteration stops on a grid sweep whose update is below tol, so its limit
+    solves (I - T) U = c (dense LU)."""
+    p = maker()
+    X, Y = p.coords()
+    p.g = np.cos(2 * X) * (1 + Y)
+    o = Oracle(p)
+    idx = o.inner_idx
+    z = o.zero_field()
+    c = o.step(z, 1.0, 0.05)
+    T = np.zeros((len(idx), len(idx)))
+    for col, q in enumerate(idx):
+        e = z.copy()
+        e[q] += 1.0
+        T[:, col] = (o.step(e, 1.0, 0.05) - c)[idx]
+    Ud = np.linalg.solve(np.eye(len(idx)) - T, c[idx])
+    U, k, rel = D.hybrid_iterate(o, D.DirectSweeps(o), z, 1.0, 0.05, m, 5000, 1e-13)
+    assert rel <= 1e-13
+    assert np.linalg.norm(U[idx] - Ud) / np.linalg.norm(Ud) < 1e-10
+    assert (k - 1) % (m + 1) == 0  # ends on a grid sweep
+
+
+def test_hybrid_excess_sweeps_fall_as_the_grid_is_refined():
+    """Measured finding (C2, blocks of 12 direct sweeps): the direct sweeps
+    approximate the grid sweep's linear part up to the difference of the two
+    transfers, which shrinks with h, so the sweeps the hybrid needs beyond
+    the grid iteration's fall as the grid is refined; on the straight C1
+    families (where both transfers are exact on affine data) fewer than one
+    block more."""
+    excess = []
+    for n in (33, 65, 129):
+        o = Oracle(W.c2(n))
+        _, k, rel = D.hybrid_iterate(o, D.DirectSweeps(o), o.zero_field(), 1.0, 0.05, 12, 3000, 1e-8)
+        _, it, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-8)
+        assert rel <= 1e-8
+        excess.append(k - it)
+    assert excess[0] > excess[1] > excess[2] > 0, excess
+    o = Oracle(W.c1(33))
+    _, k, _ = D.hybrid_iterate(o, D.DirectSweeps(o), o.zero_field(), 1.0, 0.05, 12, 3000, 1e-8)
+    _, it, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-8)
+    assert k <= it + 13
