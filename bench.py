@@ -6,9 +6,12 @@ learned warm start as two more legs of the same line.
 
 Step = one stationary solve (eq. (10) sweeps to the fixed point, Sec. 2 limit)
 of the 2049 x 2049 problem from zero to a relative fixed-point residual of
-1e-8: FP32 line solves (FP16 scatter weights in the FP32 increment sweeps), FP64
-state, residual and convergence test.  value = line unknowns solved per second
-(every sweep solves one tridiagonal system per curve of both families);
+1e-8: FP64 sweeps (state, residual, convergence test) with FP32 increment
+sweeps between them, whose transfer between the families is the grid's or the
+direct one at the curves' intersections, as the autotuner picks (quantised
+transfer weights either way); the FP64 sweeps fix the limit.  value = line
+unknowns solved per second (every sweep solves one tridiagonal system per
+curve of both families);
 ms_per_step is the time to the 1e-8 residual.  Inputs are resident in device
 memory before the timed region; set-up (curve tracing, tables, upload) and the
 autotuner are outside it.
@@ -34,7 +37,7 @@ sys.path.insert(0, ROOT)
 METRIC = "line-unknowns/s + time-to-1e-8 residual: plain vs batched/warm-start, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma")
-DTYPE = ("f32 line solves with f16 scatter weights (increment sweeps), "
+DTYPE = ("f32 line solves with f16 transfer weights (increment sweeps), "
          "f64 line solves, state, residual and convergence test (every FP64 sweep)")
 
 
@@ -84,24 +87,39 @@ def scatter_bytes(prec, fam, counts, march=False):
     return vals + grid, meta
 
 
-def direct_line_bytes(prec, fam):
+def direct_line_bytes(prec, fam, hybrid=False):
     """Line solve of the direct transfer, per line unknown (w = 4 FP32, 8
     FP64): algorithmic = one source value, the chord, |beta| (beta), the load
     (beta, FP64 sweeps only), the written value, and on the gamma-curves the
     update: FP64 sweeps read the old value and write the FP32 increment, FP32
-    sweeps read and write the FP64 state; tables = the two bracket indices and
-    four weights (FP16 in the FP32 sweeps)."""
+    sweeps read and write the FP64 state (the FP32 sum of the block's
+    increments when they steer the grid route, hybrid); tables = the two
+    bracket indices and four weights (FP16 in the FP32 sweeps)."""
     w = 4 if prec == "fp32" else 8
     if fam == 0:
         alg = w + w + w + (w if prec == "fp64" else 0) + w
     else:
-        alg = w + w + w + (8 + 4 if prec == "fp64" else 16)
+        alg = w + w + w + (8 + 4 if prec == "fp64" else (8 if hybrid else 16))
     return alg, 8 + (8 if prec == "fp32" else 32)
 
 
-def kernel_name(prec, cls, split_lines=0, march=False, direct=False):
+def hybrid_gather_bytes():
+    """The block's gather of the FP64 sweep's FP32 update onto the gamma-curves
+    (direct increments on the grid route), per gamma line unknown:
+    algorithmic = one grid value, the written curve value and the cleared sum
+    (4 + 4 + 4); tables = the bilinear stencil (cell index and two offsets)."""
+    return 12.0, 12.0
+
+
+def kernel_name(prec, cls, split_lines=0, march=False, direct=False, hybrid=False):
     tn = "float" if prec == "fp32" else "double"
     fam = 0 if cls.endswith("beta") else 1
+    if hybrid and prec == "fp32":
+        # direct increments on the grid route: the FP32 classes are the direct
+        # line solves, the block's gather (class 2) and its closing scatter (3)
+        direct = True
+        if cls == "scatter_beta":
+            return "k_line_values<float>"
     if cls.startswith("line"):
         d = "true" if direct else "false"  # the line kernels' direct-transfer flag
         if split_lines:
@@ -114,11 +132,12 @@ def kernel_name(prec, cls, split_lines=0, march=False, direct=False):
     return "k_scatter<double, double, 1>"
 
 
-def roofline(times, counts, split_lines=0, march=False, profile=None, direct=False):
+def roofline(times, counts, split_lines=0, march=False, profile=None, direct=False, hybrid=False):
     """Per kernel class: algorithmic and with-table bytes of its timed
     launches (work counted by the library per launch) over their summed event
     time.  The dominant class (largest total time) gives the roofline object;
-    `classes` lists every class."""
+    `classes` lists every class.  hybrid: the FP32 classes are the direct
+    increments of the grid route (options.increments = 1)."""
     rows = []
     for prec in ("fp64", "fp32"):
         for cls in CLASSES:
@@ -126,12 +145,15 @@ def roofline(times, counts, split_lines=0, march=False, profile=None, direct=Fal
             if cnt == 0 or ms <= 0:
                 continue
             fam = 0 if cls.endswith("beta") else 1
+            hyb = hybrid and prec == "fp32"
             if cls.startswith("line"):
-                alg, meta = direct_line_bytes(prec, fam) if direct else line_bytes(prec, fam)
+                alg, meta = (direct_line_bytes(prec, fam, hyb) if (direct or hyb) else line_bytes(prec, fam))
+            elif hyb and cls == "scatter_beta":
+                alg, meta = hybrid_gather_bytes()
             else:
                 alg, meta = scatter_bytes(prec, fam, counts, march)
             sec = ms / 1e3
-            name = kernel_name(prec, cls, split_lines, march, direct)
+            name = kernel_name(prec, cls, split_lines, march, direct, hybrid)
             rows.append(dict(kernel=name, prec=prec, cls=cls, ms=round(ms, 3), launches=cnt,
                              avg_launch_us=round(1e3 * ms / cnt, 2), work_per_launch=round(work / cnt),
                              alg_bytes_per_unit=round(alg, 2), table_bytes_per_unit=round(meta, 2),
@@ -208,6 +230,9 @@ def parse():
                     help="with --no-autotune: GMRES(m) on (I - T) U = c instead of the sweep schedule (m > 0)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="c2/c4: keep the given schedule and launches instead of choosing them with adr_autotune")
+    ap.add_argument("--increments", choices=["auto", "grid", "direct"], default="auto",
+                    help="c2/c4: the FP32 increment sweeps' transfer on the grid route (auto: the autotuner's "
+                         "choice of the two; grid with --no-autotune)")
     ap.add_argument("--transfer", choices=["grid", "direct"], default="grid",
                     help="c4: values handed between the families through the grid or at their intersections")
     ap.add_argument("--single-mode", action="store_true",
@@ -272,18 +297,24 @@ def leg_c2(args):
     from paper_2411_11041_amd.adr import Solver
     p = W.c2(args.n)
     t0 = time.time()
+    # increments "auto": the direct-transfer records are built and the
+    # autotuner times both kinds of increment sweeps
+    inc = args.increments if args.increments != "auto" else ("grid" if args.no_autotune else "direct")
     s = Solver(p, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, adaptive=args.adaptive,
-               split_lines=args.split_lines, krylov=args.krylov)
+               split_lines=args.split_lines, krylov=args.krylov, increments=inc)
     setup_s = time.time() - t0
     counts = s.counts()
     per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
     u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
     fp32_sweeps, adaptive, split, shapes, tuned = args.fp32_sweeps, args.adaptive, args.split_lines, [0] * 5, None
     kr = args.krylov
+    hybrid = inc == "direct"
     if not args.no_autotune:
         tuned = s.autotune(u, 5000, args.tol)
         fp32_sweeps, adaptive, split, shapes, kr = tuned[0], tuned[1], tuned[3], tuned[4], tuned[5]
-    log(f"c2: set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split} krylov={kr}")
+        hybrid = tuned[6] == 1
+    log(f"c2: set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split} krylov={kr} "
+        f"increments={'direct' if hybrid else 'grid'}")
 
     def solve():
         u.zero_()
@@ -300,7 +331,7 @@ def leg_c2(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     el_ev, times = events_pass(s, solve, args.steps)
-    rf = roofline(times, counts, split, profile="c2_2049_fp32lines.md")
+    rf = roofline(times, counts, split, profile="c2_2049_fp32lines.md", hybrid=hybrid)
     rf["copy_measured"] = round(copy_bandwidth_gbs(), 1)
     rf["frac_of_copy"] = round(rf["achieved"] / rf["copy_measured"], 4)
     rf["events_pass_ms_per_step"] = round(1e3 * el_ev / args.steps, 3)
@@ -313,6 +344,7 @@ def leg_c2(args):
                        "final_rel": float(rel[0]), "fp32_sweeps_per_fp64": fp32_sweeps,
                        "adaptive_schedule": bool(adaptive), "line_launches": LINE_LAUNCHES[split],
                        "line_shapes": shapes, "autotuned": tuned is not None, "krylov_gmres_m": kr,
+                       "increment_sweeps": "direct transfer" if hybrid else "grid transfer",
                        "autotune_best_ms": round(tuned[2], 3) if tuned else None,
                        "line_unknowns_per_sweep": per_sweep, "grid_unknowns": counts["grid_unknowns"],
                        "lines": [counts["lines_b"], counts["lines_g"]], "setup_s": round(setup_s, 2),
@@ -403,8 +435,13 @@ def leg_c4(args):
     probs = gen_c4(args.instances)
     gen_s = time.time() - t0
     t0 = time.time()
+    # increments "auto" on the grid transfer: both kinds of increment sweeps
+    # for the autotuner (the direct transfer's increments are direct already)
+    inc = args.increments if args.increments != "auto" else (
+        "direct" if (args.transfer == "grid" and not args.no_autotune) else "grid")
     s = Solver(probs, precision="fp32", fp32_sweeps=args.fp32_sweeps, theta=1.0, dt=0.05, graph=args.graph,
-               adaptive=args.adaptive, split_lines=args.split_lines, krylov=args.krylov, transfer=args.transfer)
+               adaptive=args.adaptive, split_lines=args.split_lines, krylov=args.krylov, transfer=args.transfer,
+               increments=inc)
     setup_s = time.time() - t0
     counts = s.counts()
     per_inst = []
@@ -419,11 +456,13 @@ def leg_c4(args):
     u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     fp32_sweeps, adaptive, split, shapes, tuned = args.fp32_sweeps, args.adaptive, args.split_lines, [0] * 5, None
     kr = args.krylov
+    hybrid = inc == "direct" and args.transfer == "grid"
     if not args.no_autotune and args.transfer == "grid":
         tuned = s.autotune(u, 3000, args.tol)
         fp32_sweeps, adaptive, split, shapes, kr = tuned[0], tuned[1], tuned[3], tuned[4], tuned[5]
+        hybrid = tuned[6] == 1
     log(f"c4: gen {gen_s:.1f} s, set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split} "
-        f"krylov={kr}")
+        f"krylov={kr} increments={'direct' if hybrid else 'grid'}")
 
     def solve():
         u.zero_()
@@ -440,7 +479,8 @@ def leg_c4(args):
     el = time.perf_counter() - t0
     el_ev, times = events_pass(s, solve, args.steps)
     rf = roofline(times, counts, split, profile="c4_512_fp32lines.md" if args.transfer == "grid" else None,
-                  direct=args.transfer == "direct")
+                  direct=args.transfer == "direct", hybrid=hybrid)
+    inc_kind = "direct transfer" if (hybrid or args.transfer == "direct") else "grid transfer"
     rf["events_pass_ms_per_step"] = round(1e3 * el_ev / args.steps, 2)
     solved = int((its.astype(np.int64) * per_inst).sum()) * args.steps
     # the same solves with the blocks replayed from HIP graphs (one per block
@@ -449,7 +489,7 @@ def leg_c4(args):
     if args.single_mode or args.transfer == "direct":  # graphs serve the grid transfer only
         s.close()
         return c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, fp32_sweeps, adaptive,
-                         split, shapes, kr, tuned, solved, times, None)
+                         split, shapes, kr, tuned, solved, times, None, inc_kind)
     s.set_graph(not args.graph)
     for _ in range(args.warmup):
         solve()
@@ -466,11 +506,11 @@ def leg_c4(args):
     log(f"c4: {'graph replay' if not args.graph else 'eager'} {other['ms_per_step']} ms")
     s.close()
     return c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, fp32_sweeps, adaptive, split,
-                     shapes, kr, tuned, solved, times, other)
+                     shapes, kr, tuned, solved, times, other, inc_kind)
 
 
 def c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, fp32_sweeps, adaptive, split, shapes,
-              kr, tuned, solved, times, other):
+              kr, tuned, solved, times, other, inc_kind):
     import numpy as np
     return {"value": solved / el, "unit": "line-unknowns/s", "ms_per_step": 1e3 * el / args.steps, "roofline": rf,
             "config": {"workload": f"c4: {len(probs)} stationary instances (disc/L-shape, 33..1025 per side, "
@@ -484,6 +524,7 @@ def c4_result(args, probs, counts, per_inst, its, rel, el, rf, gen_s, setup_s, f
                        "fp32_sweeps_per_fp64": fp32_sweeps, "adaptive_schedule": bool(adaptive),
                        "line_launches": LINE_LAUNCHES[split], "line_shapes": shapes, "krylov_gmres_m": kr,
                        "autotune_ms": round(tuned[2], 2) if tuned else None, "transfer": args.transfer,
+                       "increment_sweeps": inc_kind,
                        "other_launch_mode": other, "kernels": kernels_table(times)}}
 
 

@@ -256,8 +256,9 @@ adr_status adr_set_graph(adr_ctx *ctx, int32_t on);
 /* Workgroup shapes of the bucketed line launches (options.split_lines != 0):
  * shapes[b] for bucket b = 0..4 (curves of at most 3072, 2048, 1024, 512, 256
  * nodes) selects rows per thread x threads per curve:
- *   bucket 0: 0 = 12 x 256            bucket 1: 0 = 8 x 256
- *   bucket 2: 0 = 4 x 256, 1 = 8 x 128
+ *   bucket 0: 0 = 12 x 256, 1 = 6 x 512
+ *   bucket 1: 0 = 8 x 256,  1 = 4 x 512
+ *   bucket 2: 0 = 4 x 256, 1 = 8 x 128, 2 = 2 x 512
  *   bucket 3: 0 = 4 x 128, 1 = 2 x 256, 2 = 8 x 64
  *   bucket 4: 0 = 4 x 64,  1 = 2 x 128, 2 = 1 x 256
  * Every shape solves the same systems (the partition of a curve's rows among

@@ -131,8 +131,10 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     }
     // gathers in groups of (up to) 4 slots: the 16 corner loads of a group are
     // issued together (cell 0 stands in for the end nodes, whose value is
-    // dropped), then the group's values go to LDS
-    constexpr int G = MAXJ < 4 ? MAXJ : 4;
+    // dropped), then the group's values go to LDS; G divides MAXJ, so every
+    // group's slots exist
+    constexpr int G = MAXJ % 4 == 0 ? 4 : MAXJ % 3 == 0 ? 3 : MAXJ % 2 == 0 ? 2 : 1;
+    static_assert(MAXJ % G == 0, "gather groups must tile the slots");
 #pragma unroll
     for (int q0 = 0; q0 < MAXJ; q0 += G) {
         T p11[G], p12[G], p21[G], p22[G];
@@ -768,9 +770,12 @@ void launch_line_fam(int bucket, int shape, const LineArgs<T> &a, int n_lines, c
                      const double *par, const int *done, int nmax, hipStream_t st) {
     switch (bucket * 4 + shape) {
         case 0: launch_b<T, FAM, 12, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 1: launch_b<T, FAM, 6, 512, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
         case 4: launch_b<T, FAM, 8, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 5: launch_b<T, FAM, 4, 512, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
         case 8: launch_b<T, FAM, 4, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
         case 9: launch_b<T, FAM, 8, 128, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
+        case 10: launch_b<T, FAM, 2, 512, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
         case 12: launch_b<T, FAM, 4, 128, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
         case 13: launch_b<T, FAM, 2, 256, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
         case 14: launch_b<T, FAM, 8, 64, DIR>(a, n_lines, fin, vout, par, done, nmax, st); break;
@@ -794,7 +799,7 @@ int line_bucket(int nodes) {
 }
 
 int line_shapes(int bucket) {
-    static const int kShapes[kLineBuckets] = {1, 1, 2, 3, 3};
+    static const int kShapes[kLineBuckets] = {2, 2, 3, 3, 3};
     return bucket >= 0 && bucket < kLineBuckets ? kShapes[bucket] : 1;
 }
 

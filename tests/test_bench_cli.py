@@ -55,3 +55,33 @@ def test_roofline_from_kernel_work():
     assert abs(rf["achieved"] - 16 * 4000 / 2e-3 / 1e9) < 0.1
     assert rf["bytes_per_launch"] == 16 * 1000
     assert [c["cls"] for c in rf["classes"]] == ["line_beta", "line_beta", "scatter_beta"]
+
+
+def test_roofline_of_the_direct_increments_on_the_grid_route():
+    """Direct increments steering the grid route: the FP32 line classes are
+    the direct line kernels (the gamma one adds to an FP32 sum, 4 B read and
+    written), class scatter_beta is the block's gather onto the gamma-curves
+    (grid value, curve value, cleared sum; bilinear stencil as tables) and
+    scatter_gamma the FP32 increment scatter; the FP64 classes are unchanged."""
+    sys.path.insert(0, ROOT)
+    import bench
+    assert bench.direct_line_bytes("fp32", 1, hybrid=True) == (20, 16)
+    assert bench.hybrid_gather_bytes() == (12.0, 12.0)
+    counts = dict(grid_unknowns=1000, line_unknowns_b=1000, lines_b=10, line_unknowns_g=800, lines_g=20)
+    z = (0.0, 0, 0)
+    times = {"fp64": {"line_beta": (0.5, 1, 1000), "line_gamma": z, "scatter_beta": z,
+                      "scatter_gamma": (0.4, 1, 1000), "norm": z},
+             "fp32": {"line_beta": (2.0, 4, 4000), "line_gamma": (1.5, 4, 3200), "scatter_beta": (0.2, 1, 800),
+                      "scatter_gamma": (0.3, 1, 1000), "norm": z}}
+    rf = bench.roofline(times, counts, hybrid=True)
+    names = {(c["prec"], c["cls"]): c["kernel"] for c in rf["classes"]}
+    assert names[("fp32", "line_beta")] == "k_line<float, 0, true>"
+    assert names[("fp32", "line_gamma")] == "k_line<float, 1, true>"
+    assert names[("fp32", "scatter_beta")] == "k_line_values<float>"
+    assert names[("fp32", "scatter_gamma")] == "k_scatter<float, double, 2>"
+    assert names[("fp64", "line_beta")] == "k_line<double, 0, false>"
+    assert names[("fp64", "scatter_gamma")] == "k_scatter<double, double, 1>"
+    row = {(c["prec"], c["cls"]): c for c in rf["classes"]}
+    assert row[("fp32", "line_gamma")]["alg_bytes_per_unit"] == 20
+    assert row[("fp32", "scatter_beta")]["alg_bytes_per_unit"] == 12
+    assert rf["kernel"] == "k_line<float, 0, true>"

@@ -126,12 +126,12 @@ def test_data2d_paper_experiment():
 
 
 @pytest.mark.parametrize("split,shapes", [(0, None), (1, None), (2, None), (1, (0, 0, 1, 1, 1)),
-                                          (1, (0, 0, 0, 2, 2))])
+                                          (1, (0, 0, 0, 2, 2)), (1, (1, 1, 2, 1, 1))])
 def test_batched_instances_match_oracle(split, shapes):
     """Disc and L-shape instances of uneven sizes in one context (one launch per
     kernel for all of them, or one per length bucket: curves of up to 256
-    nodes on 64-thread workgroups, up to 512 on 128): every instance matches
-    its own oracle."""
+    nodes on 64-thread workgroups, up to 512 on 128, up to 1024 on 512):
+    every instance matches its own oracle."""
     print(f"[case] batched c4 x4 fp64 8 sweeps, line launches {split}, shapes {shapes}", flush=True)
     probs = [W.c4_instance(i, n_max=140) for i in range(3)] + [W.c4_instance(7, n_max=600)]
     s = solver(probs, precision="fp64", theta=1.0, dt=0.05, split_lines=split)
@@ -249,7 +249,7 @@ def test_autotune_keeps_a_candidate_and_the_fixed_point():
     best, adaptive, ms, split, shapes, kr, inc = s.autotune(work, 2000, 1e-10)
     assert ((best in (2, 3, 4, 6) and not adaptive) or (best in (6, 8, 12, 16, 24) and adaptive)) and ms > 0
     assert split in (0, 1, 2)
-    assert all(0 <= v < n for v, n in zip(shapes, (1, 1, 2, 3, 3)))
+    assert all(0 <= v < n for v, n in zip(shapes, (2, 2, 3, 3, 3)))
     u = torch.zeros_like(work)
     iters, rel, st = s.split_iterate(u, 2000, 1e-10)
     assert st == 0 and rel[0] <= 1e-10
@@ -495,7 +495,17 @@ def test_split_line_launches_equal_the_single_launch(precision):
         torch.cuda.synchronize()
         assert st4 == 0 and np.array_equal(it4, it2)
         assert torch.equal(u4, u2), rep
-    for s in (one, spl, spl_g, conc):
+    # the 512-thread shapes of the buckets of long curves (6, 4 and 2 rows per thread)
+    wide = solver(probs, split_lines=True, **kw)
+    wide.set_line_shapes((1, 1, 2, 0, 0))
+    u5 = torch.zeros_like(u1)
+    it5, _, st5 = wide.split_iterate(u5, 3000, tol)
+    torch.cuda.synchronize()
+    d5 = float(torch.max(torch.abs(u5 - u2)) / torch.max(torch.abs(u2)))
+    print(f"[case] 512-thread shapes: max relative difference {d5:.2e}", flush=True)
+    assert st5 == 0 and np.all(np.abs(it5.astype(int) - it2.astype(int)) <= 1)
+    assert d5 <= (1e-11 if precision == "fp64" else 1e-6)
+    for s in (one, spl, spl_g, conc, wide):
         s.close()
 
 
