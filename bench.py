@@ -215,7 +215,8 @@ def parse():
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle worker processes (0: one per host core, <= 16)")
     ap.add_argument("--acc-n", type=int, default=1025, help="direct leg: grid of the accuracy comparison (C1)")
     ap.add_argument("--direct-sweeps", type=int, default=12,
-                    help="direct leg: at most this many FP32 sweeps per FP64 sweep (adaptive schedule)")
+                    help="direct leg with --no-autotune: at most this many FP32 sweeps per FP64 sweep "
+                         "(adaptive schedule)")
     ap.add_argument("--workload", choices=["all", "c2", "c3", "c4", "c5", "direct"], default="all",
                     help="all: c2 (the step and value) with the c4 and c5 legs (default); c2: one 2049^2 problem; "
                          "c3: the 2049^2 parabolic march (200 steps); c4: the 512-instance batch; "
@@ -354,9 +355,10 @@ def leg_c2(args):
 def leg_direct(args):
     """The interpolation-free transfer against the grid route: C2 time to 1e-8
     and sweeps with every sweep in FP64 (both routes) and with FP32 increment
-    sweeps under the adaptive schedule (direct route; the grid route's is the
-    main leg), and the distance of each route's fixed point from the exact
-    solution of the manufactured problem (C1)."""
+    sweeps (direct route, its launches and schedule from adr_autotune, or the
+    adaptive schedule of --direct-sweeps with --no-autotune; the grid route's
+    is the main leg), and the distance of each route's fixed point from the
+    exact solution of the manufactured problem (C1)."""
     import numpy as np
     import torch
     import workloads as W
@@ -373,6 +375,13 @@ def leg_direct(args):
         counts = s.counts()
         per_sweep = counts["line_unknowns_b"] + counts["line_unknowns_g"]
         u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+        tuned = None
+        if kw["precision"] == "fp32" and not args.no_autotune:
+            # the direct route's own launches and schedule (the grid route's
+            # FP32 solve is the main leg)
+            tuned = s.autotune(u, 5000, args.tol)
+            log(f"direct leg: {name} autotuned schedule {tuned[0]} adaptive={tuned[1]} lines={tuned[3]} "
+                f"shapes={tuned[4]}")
 
         def solve():
             u.zero_()
@@ -387,11 +396,14 @@ def leg_direct(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         el_ev, times = events_pass(s, solve, args.steps)
-        rf = roofline(times, counts, 0, direct=(tr == "direct"),
+        rf = roofline(times, counts, tuned[3] if tuned else 0, direct=(tr == "direct"),
                       profile="c2_2049_direct.md" if name == "direct_fp32" else None)
         res[name] = {"ms_per_step": round(1e3 * el / args.steps, 3), "sweeps": int(iters[0]),
                      "final_rel": float(rel[0]), "value": per_sweep * int(iters[0]) * args.steps / el,
                      "setup_s": round(setup_s, 2), "events_pass_ms_per_step": round(1e3 * el_ev / args.steps, 3),
+                     "autotuned": None if tuned is None else {
+                         "fp32_sweeps_per_fp64": tuned[0], "adaptive_schedule": bool(tuned[1]),
+                         "line_launches": LINE_LAUNCHES[tuned[3]], "line_shapes": list(tuned[4])},
                      "roofline": rf, "kernels": kernels_table(times)}
         log(f"direct leg: {name} {res[name]['ms_per_step']:.2f} ms, {res[name]['sweeps']} sweeps")
         s.close()
@@ -457,10 +469,10 @@ def leg_c4(args):
     fp32_sweeps, adaptive, split, shapes, tuned = args.fp32_sweeps, args.adaptive, args.split_lines, [0] * 5, None
     kr = args.krylov
     hybrid = inc == "direct" and args.transfer == "grid"
-    if not args.no_autotune and args.transfer == "grid":
+    if not args.no_autotune:
         tuned = s.autotune(u, 3000, args.tol)
         fp32_sweeps, adaptive, split, shapes, kr = tuned[0], tuned[1], tuned[3], tuned[4], tuned[5]
-        hybrid = tuned[6] == 1
+        hybrid = tuned[6] == 1 and args.transfer == "grid"
     log(f"c4: gen {gen_s:.1f} s, set-up {setup_s:.1f} s, schedule {fp32_sweeps} adaptive={adaptive} lines={split} "
         f"krylov={kr} increments={'direct' if hybrid else 'grid'}")
 

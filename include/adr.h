@@ -225,7 +225,7 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
 /* Autotuner of the batched stationary solve (FP32_LINES precision only).  Each
  * trial runs the stationary solve from zero twice on `work` (device FP64,
  * packed layout, overwritten) and times the second run on the host clock (the
- * first also captures the graph in graph mode).  It tunes in two steps:
+ * first also captures the graph in graph mode).  It tunes in three steps:
  *   1. the line launches (options.split_lines 0, 1 and 2), under the context's
  *      current schedule;
  *   2. with the faster of those, each candidate schedule: a fixed count of
@@ -234,10 +234,11 @@ adr_status adr_split_iterate_judged(adr_ctx *ctx, double *u, const double *fallb
  *      sweeps (options.increments) when the context has the direct-transfer
  *      records (set up with increments = 1);
  *   3. GMRES(m) (options.krylov) with m = 10, 20, 30, kept if faster than the
- *      best schedule.
- * With bucketed launches, between the two steps, each length bucket's
+ *      best schedule (grid transfer only).
+ * With bucketed launches, between steps 1 and 2, each length bucket's
  * workgroup shape (adr_set_line_shapes) is chosen from its FP32 line solves
- * timed alone.  The fastest choices stay in the context.  Outputs (host, each
+ * timed alone.  A context with the direct transfer (options.transfer = 1) is
+ * tuned the same way on its own sweeps and line solves, without step 3.  The fastest choices stay in the context.  Outputs (host, each
  * may be NULL): best_fp32_sweeps and best_adaptive (the count or maximum, and
  * the adaptive flag), best_ms (its time), best_split (the launch choice),
  * best_shapes (5 entries, the shape of each bucket), best_krylov (0, or the

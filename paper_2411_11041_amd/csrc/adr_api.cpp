@@ -273,19 +273,22 @@ struct adr_ctx {
         return hipSuccess;
     }
     // milliseconds of `reps` FP32 line solves of bucket b (both families, full
-    // lists) with workgroup shape `shape`, after one untimed run
+    // lists) with workgroup shape `shape`, after one untimed run (the direct
+    // transfer's line solves in a direct context)
     double time_bucket(int b, int shape, int reps) {
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
+        const bool dir = opt.transfer == 1;
         auto run = [&]() {
             for (int f = 0; f < 2; ++f) {
                 const DevFam &F = fam[f];
-                adr::LineArgs<float> a = F.a32;
+                adr::LineArgs<float> a = dir ? F.a32d : F.a32;
                 a.lidx = nullptr;
                 a.lbase = F.bstart[b];
-                HIPCHK(adr::launch_line<float>(f, b, shape, a, F.bstart[b + 1] - F.bstart[b], d32, F.v32,
-                                               par_ptr(kSlotLin, f), never, F.bnmax[b], st));
+                HIPCHK(adr::launch_line<float>(f, b, shape, a, F.bstart[b + 1] - F.bstart[b],
+                                               dir ? fam[1 - f].v32 : d32, F.v32, par_ptr(kSlotLin, f), never,
+                                               F.bnmax[b], st));
             }
         };
         run();
@@ -1629,9 +1632,8 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
                         int32_t *best_adaptive, double *best_ms, int32_t *best_split, int32_t *best_shapes,
                         int32_t *best_krylov, int32_t *best_increments) {
     if (!ctx) return ADR_EINVAL;
-    if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES ||
-        ctx->opt.transfer != 0) {
-        ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0, FP32_LINES precision and the grid transfer";
+    if (!work || max_iters < 1 || !(tol >= 0.0) || ctx->opt.precision != ADR_PREC_FP32_LINES) {
+        ctx->err = "adr_autotune needs work, max_iters >= 1, tol >= 0 and FP32_LINES precision";
         return ADR_EINVAL;
     }
     // (FP32 sweeps per FP64 sweep or their maximum, adaptive)
@@ -1737,9 +1739,11 @@ adr_status adr_autotune(adr_ctx *ctx, double *work, int32_t max_iters, double to
     ctx->opt.fp32_sweeps = best;
     ctx->opt.adaptive = best_ad;
     ctx->opt.increments = best_inc;
-    // 3. GMRES(m) on (I - T) U = c (FP64 sweeps) with those launches, against the best schedule
+    // 3. GMRES(m) on (I - T) U = c (FP64 sweeps) with those launches, against the best
+    //    schedule (the grid transfer only)
     int best_kr = 0;
     for (int m : {10, 20, 30}) {
+        if (ctx->opt.transfer != 0) break;
         ctx->opt.krylov = m;
         double t;
         const adr_status st = time_solve(t);

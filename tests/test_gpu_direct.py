@@ -154,13 +154,36 @@ def test_direct_transfer_more_accurate_than_grid_route():
 
 
 def test_direct_transfer_refuses_what_it_does_not_serve():
+    """The judged solve (a start against a fallback) runs on the grid route."""
     from paper_2411_11041_amd.adr import ADRError, ADR_EINVAL
     p = W.c1(33)
     s = solver(p, precision="fp32", theta=1.0, dt=0.05, transfer="direct")
     u = torch.zeros(p.nx * p.ny, dtype=torch.float64, device="cuda")
+    fb = torch.zeros_like(u)
     with pytest.raises(ADRError) as e:
-        s.autotune(u, 100, 1e-8)
+        s.split_iterate_judged(u, fb, 100, 1e-8)
     assert e.value.code == ADR_EINVAL
+    s.close()
+
+
+def test_direct_transfer_autotune_keeps_the_fixed_point():
+    """adr_autotune on a direct context tunes its own launches, bucket shapes
+    and schedule (no GMRES, no second kind of increments); the tuned solve
+    reaches the direct oracle's fixed point (FP32-increment bar 1e-8)."""
+    print("[case] direct transfer autotune (c2 129)", flush=True)
+    p = W.c2(129)
+    o = Oracle(p)
+    U, _, _, _, _ = D.DirectSweeps(o).iterate(o.zero_field(), 1.0, 0.05, 3000, 1e-10)
+    s = solver(p, precision="fp32", theta=1.0, dt=0.05, transfer="direct")
+    work = dev(o.zero_field())
+    best, adaptive, ms, split, shapes, kr, inc = s.autotune(work, 2000, 1e-10)
+    print(f"[case] autotuned: sweeps {best} adaptive {adaptive} split {split} shapes {shapes} {ms:.2f} ms", flush=True)
+    assert kr == 0 and inc == 0 and ms > 0
+    u = dev(o.zero_field())
+    it, rel, st = s.split_iterate(u, 3000, 1e-10)
+    torch.cuda.synchronize()
+    assert st == 0 and rel[0] <= 1e-10
+    assert rel_l2(u.cpu().numpy(), U, o.inner_idx) < 1e-8
     s.close()
 
 
