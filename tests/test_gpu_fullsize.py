@@ -46,16 +46,21 @@ def test_c2_full_fp64_three_sweeps(golden, problem):
     s.close()
 
 
-@pytest.mark.parametrize("schedule", ["fixed3", "bench"])
+@pytest.mark.parametrize("schedule", ["fixed3", "grid12", "bench"])
 def test_c2_full_fp32_lines_bench_configuration(golden, problem, schedule):
     """FP32 line solves to tol 1e-8: the converged iterate matches the oracle's
     fixed point within 1e-5 relative L2.  fixed3: 3 FP32 sweeps per FP64 sweep;
-    bench: the configuration the benchmark's autotuner picks on the MI355X (one
-    line launch per family, adaptive schedule with at most 12 FP32 sweeps per
-    FP64 sweep, the factored 12-byte scatter weights in the FP32 sweeps)."""
+    grid12: one line launch per family, adaptive schedule with at most 12 FP32
+    sweeps per FP64 sweep, the factored 12-byte scatter weights in the FP32
+    sweeps; bench: the configuration the benchmark's autotuner picks on the
+    MI355X (one line launch per family, adaptive schedule with at most 16 FP32
+    sweeps per FP64 sweep, the increments through the direct transfer)."""
     print(f"[case] c2 2049 fp32 lines ({schedule}) to 1e-8 vs stored oracle fixed point", flush=True)
     from paper_2411_11041_amd.adr import Solver
     if schedule == "bench":
+        s = Solver(problem, precision="fp32", fp32_sweeps=16, adaptive=True, split_lines=0, theta=1.0, dt=0.05,
+                   increments="direct")
+    elif schedule == "grid12":
         s = Solver(problem, precision="fp32", fp32_sweeps=12, adaptive=True, split_lines=0, theta=1.0, dt=0.05)
     else:
         s = Solver(problem, precision="fp32", fp32_sweeps=3, theta=1.0, dt=0.05)
