@@ -94,13 +94,14 @@ def direct_line_bytes(prec, fam, hybrid=False):
     update: FP64 sweeps read the old value and write the FP32 increment, FP32
     sweeps read and write the FP64 state (the FP32 sum of the block's
     increments when they steer the grid route, hybrid); tables = the two
-    bracket indices and four weights (FP16 in the FP32 sweeps)."""
+    bracket indices and four weights (FP64: 8 + 32 B; FP32 sweeps: 10 B, a
+    source node, a 16-bit offset and three packed fractions)."""
     w = 4 if prec == "fp32" else 8
     if fam == 0:
         alg = w + w + w + (w if prec == "fp64" else 0) + w
     else:
         alg = w + w + w + (8 + 4 if prec == "fp64" else (8 if hybrid else 16))
-    return alg, 8 + (8 if prec == "fp32" else 32)
+    return alg, (10 if prec == "fp32" else 40)
 
 
 def hybrid_gather_bytes():

@@ -345,6 +345,24 @@ adr_status adr_export_scatter_factors(const adr_ctx *ctx, int32_t inst, int32_t 
 adr_status adr_export_direct(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_nodes, int32_t *k,
                              double *w);
 
+/* Test export (host-only contexts with the direct-transfer records): the
+ * records of adr_export_direct as the FP32 increment sweeps receive them, 10
+ * bytes per node (source nodes local to the instance):
+ *   k0[q]  the left bracket's source node, or the right one's when kd[q] =
+ *          -32766 (no left bracket: the curve's first end), or -1;
+ *   kd[q]  the right bracket's source node minus k0[q], or -32767 (no right
+ *          bracket: the curve's last end), or -32768 (farther than 32765 from
+ *          k0: the device reads the full record);
+ *   wp[q]  bits 0-9: the left bracket's weight wL as a multiple of 1/1023;
+ *          bits 10-20 and 21-31: the positions tL, tR on the two source
+ *          segments as multiples of 1/2047.
+ * Node q's weights are then wL(1 - tL), wL tL, wR(1 - tR), wR tR with
+ * wR = 1 - wL (each within 2^-11 of the FP64 record's, sum 1).  Call with NULL
+ * arrays to get *n_nodes.  Errors: ADR_EINVAL (a device context, a context
+ * without the records, an index out of range). */
+adr_status adr_export_direct_packed(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_nodes,
+                                    int32_t *k0, int16_t *kd, uint32_t *wp);
+
 /* Per-launch HIP-event timing on (1) or off (0) from now on (the set-up
  * option's initial value).  Each timed launch records two events on the
  * context's stream, which adds a few microseconds between launches.  Pending

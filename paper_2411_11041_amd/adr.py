@@ -22,7 +22,7 @@ PREC_FP64, PREC_FP32_LINES = 0, 1
 EXPORTS = ("adr_setup", "adr_layout", "adr_counts", "adr_update", "adr_split_iterate", "adr_split_iterate_judged",
            "adr_autotune", "adr_set_line_shapes", "adr_set_graph", "adr_time_step",
            "adr_residual", "adr_initial_guess", "adr_export_lines", "adr_export_scatter", "adr_export_scatter_factors",
-           "adr_export_direct",
+           "adr_export_direct", "adr_export_direct_packed",
            "adr_set_timing", "adr_kernel_times",
            "adr_destroy", "adr_last_error", "adr_copy_probe", "adr_line_solve", "adr_line_solve_noalloc")
 
@@ -86,6 +86,7 @@ def load():
     lib.adr_export_lines.argtypes = [vp, i32, i32, P(i64), P(i64), P(i64), P(dbl), P(dbl)]
     lib.adr_export_scatter.argtypes = [vp, i32, i32, P(i64), P(i32), P(i32), P(dbl), P(dbl), P(dbl)]
     lib.adr_export_direct.argtypes = [vp, i32, i32, P(i64), P(i32), P(dbl)]
+    lib.adr_export_direct_packed.argtypes = [vp, i32, i32, P(i64), P(i32), P(C.c_int16), P(C.c_uint32)]
     lib.adr_export_scatter_factors.argtypes = [vp, i32, i32, P(i64), P(dbl), P(dbl), P(dbl)]
     lib.adr_kernel_times.argtypes = [vp, i32, P(dbl), P(i64), P(i64), i32]
     lib.adr_destroy.argtypes = [vp]
@@ -357,6 +358,21 @@ class Solver:
         self._check(self.lib.adr_export_direct(self.ctx, inst, family, None, k.ctypes.data_as(C.POINTER(C.c_int32)),
                                                _dptr(w)))
         return k.reshape(n, 2), w.reshape(n, 4)
+
+    def export_direct_packed(self, inst, family):
+        """The same records as the FP32 sweeps receive them (include/adr.h):
+        k0 (int32), kd (int16), wp (uint32) per node."""
+        nn = C.c_int64()
+        self._check(self.lib.adr_export_direct_packed(self.ctx, inst, family, C.byref(nn), None, None, None))
+        n = nn.value
+        k0 = np.zeros(n, np.int32)
+        kd = np.zeros(n, np.int16)
+        wp = np.zeros(n, np.uint32)
+        self._check(self.lib.adr_export_direct_packed(self.ctx, inst, family, None,
+                                                      k0.ctypes.data_as(C.POINTER(C.c_int32)),
+                                                      kd.ctypes.data_as(C.POINTER(C.c_int16)),
+                                                      wp.ctypes.data_as(C.POINTER(C.c_uint32))))
+        return k0, kd, wp
 
     def kernel_times(self, precision="fp64", reset=True, work=False):
         """Per kernel class: (ms, launches), or (ms, launches, work) with work=True."""

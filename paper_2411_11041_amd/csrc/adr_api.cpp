@@ -8,6 +8,7 @@
 #include <chrono>
 #include <atomic>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -59,6 +60,31 @@ T *upload(const std::vector<T> &h, std::vector<void *> &owned, hipStream_t st) {
 template <typename T>
 std::vector<T> to_type(const std::vector<double> &v) {
     return std::vector<T>(v.begin(), v.end());
+}
+
+// One node's direct-transfer record in the FP32 sweeps' 10-byte form
+// (LineArgs::dk0, dkd, dwp); koff shifts the source nodes into the packed
+// numbering of the other family.  The weights become the left bracket's weight
+// wL = w0 + w1 (10 bits) and the positions t = w1 / wL, w3 / wR on the two
+// source segments (11 bits each); the right weight is 1 - wL, so every row
+// keeps the sum 1 of its brackets.
+void pack_direct(const adr::DirRec &r, int64_t koff, int32_t &k0, int16_t &kd, uint32_t &wp) {
+    const int64_t kl = r.k[0] < 0 ? -1 : koff + r.k[0], kr = r.k[1] < 0 ? -1 : koff + r.k[1];
+    if (kl < 0 && kr >= 0) {
+        k0 = static_cast<int32_t>(kr);
+        kd = adr::kDirNoLeft;
+    } else {
+        k0 = static_cast<int32_t>(kl);
+        kd = kr < 0 ? adr::kDirNoRight
+                    : (std::llabs(kr - kl) <= adr::kDirMaxDelta ? static_cast<int16_t>(kr - kl) : adr::kDirEscape);
+    }
+    const double wl = r.w[0] + r.w[1], wr = r.w[2] + r.w[3];
+    const double tl = wl > 0.0 ? r.w[1] / wl : 0.0, tr = wr > 0.0 ? r.w[3] / wr : 0.0;
+    auto q = [](double x, double scale, uint32_t top) {
+        const double v = std::nearbyint(std::min(std::max(x, 0.0), 1.0) * scale);
+        return std::min(static_cast<uint32_t>(v), top);
+    };
+    wp = q(wl, 1023.0, 1023u) | (q(tl, 2047.0, 2047u) << 10) | (q(tr, 2047.0, 2047u) << 21);
 }
 
 struct DevFam {
@@ -998,17 +1024,22 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                 F.a64d = F.a64;
                 F.a64d.dk = reinterpret_cast<const int2 *>(upload(dk, own, st));
                 F.a64d.dw = upload(dw, own, st);
-                // FP32 increment sweeps: FP16 weights (relative error 2^-11, as the scatter's)
-                std::vector<unsigned> dw16(2 * static_cast<size_t>(F.n_nodes));
-                for (size_t e = 0; e < dw16.size(); ++e) {
-                    const _Float16 lo = static_cast<_Float16>(static_cast<float>(dw[2 * e]));
-                    const _Float16 hi = static_cast<_Float16>(static_cast<float>(dw[2 * e + 1]));
-                    dw16[e] = static_cast<unsigned>(__builtin_bit_cast(unsigned short, lo)) |
-                              (static_cast<unsigned>(__builtin_bit_cast(unsigned short, hi)) << 16);
+                // FP32 increment sweeps: the records packed into 10 bytes per node
+                std::vector<int32_t> dk0(static_cast<size_t>(F.n_nodes), -1);
+                std::vector<int16_t> dkd(static_cast<size_t>(F.n_nodes), adr::kDirNoRight);
+                std::vector<uint32_t> dwp(static_cast<size_t>(F.n_nodes), 0u);
+                for (int i = 0; i < n; ++i) {
+                    const std::vector<adr::DirRec> &D = G[i].drec[f];
+                    for (size_t k = 0; k < D.size(); ++k) {
+                        const size_t gk = static_cast<size_t>(noff[i]) + k;
+                        pack_direct(D[k], noffs[1 - f][i], dk0[gk], dkd[gk], dwp[gk]);
+                    }
                 }
                 F.a32d = F.a32;
-                F.a32d.dk = F.a64d.dk;
-                F.a32d.dw16 = reinterpret_cast<const uint2 *>(upload(dw16, own, st));
+                F.a32d.dk = F.a64d.dk;  // the escapes' full records (and the direct mode's flag)
+                F.a32d.dk0 = upload(dk0, own, st);
+                F.a32d.dkd = reinterpret_cast<const short *>(upload(dkd, own, st));
+                F.a32d.dwp = upload(dwp, own, st);
                 if (f == 1) {
                     // update sums of the gamma-curves, grouped by instance in list order
                     std::vector<int> start(n + 1, 0), slot(F.n_lines);
@@ -1991,6 +2022,18 @@ adr_status adr_export_direct(const adr_ctx *ctx, int32_t inst, int32_t family, i
         for (int e = 0; e < 4; ++e)
             if (w) w[4 * q + e] = D[q].w[e];
     }
+    return ADR_OK;
+}
+
+adr_status adr_export_direct_packed(const adr_ctx *ctx, int32_t inst, int32_t family, int64_t *n_nodes,
+                                    int32_t *k0, int16_t *kd, uint32_t *wp) {
+    if (!ctx || !ctx->opt.host_only || (ctx->opt.transfer != 1 && ctx->opt.increments != 1) || inst < 0 ||
+        inst >= ctx->n_inst || family < 0 || family > 1)
+        return ADR_EINVAL;
+    const std::vector<adr::DirRec> &D = ctx->host_geo[inst].drec[family];
+    if (n_nodes) *n_nodes = static_cast<int64_t>(D.size());
+    if (k0 && kd && wp)
+        for (size_t q = 0; q < D.size(); ++q) pack_direct(D[q], 0, k0[q], kd[q], wp[q]);
     return ADR_OK;
 }
 

@@ -31,7 +31,15 @@ struct LineArgs {
     // + (dk[k].y >= 0 ? dw[4k+2] fin[dk.y] + dw[4k+3] fin[dk.y+1] : dw[4k+2] x_last)
     const int2 *dk;
     const T *dw;         // FP64 sweeps
-    const uint2 *dw16;   // FP32 sweeps: the four weights as FP16 (low half first)
+    // FP32 sweeps: the same records in 10 bytes (kDir* codes below): dk0 the
+    // left bracket's source node (the right one's when the left is the curve's
+    // end, or -1 when both are), dkd the right one's offset from dk0 or a code,
+    // dwp the left bracket's weight wL (bits 0-9, a fraction of 1023) and the
+    // positions tL, tR on the two source segments (bits 10-20, 21-31, fractions
+    // of 2047): weights wL(1 - tL), wL tL, wR(1 - tR), wR tR with wR = 1 - wL
+    const int *dk0;
+    const short *dkd;
+    const unsigned *dwp;
     double *lpart;       // optional with dk: per line, sum over its interior nodes of
                          // (new value - old value in vout)^2, at lpart[lslot[line]]
     const int *lslot;
@@ -39,6 +47,13 @@ struct LineArgs {
     double *vacc;        // optional with dk: per interior node, vacc += new value
     float *vacc32;       // optional with dk: the same into an FP32 sum
 };
+
+// Codes of LineArgs::dkd: no left bracket on a source segment (the right one
+// is dk0), no right one, or a right one too far from dk0 (read dk[k].y)
+constexpr short kDirNoLeft = -32766;
+constexpr short kDirNoRight = -32767;
+constexpr short kDirEscape = -32768;
+constexpr int kDirMaxDelta = 32765;
 
 // Record indices relative to the slot's first record (ScatterArgs::rd)
 constexpr short kRecMissing = -32768;  // no record

@@ -104,11 +104,12 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     T hj[MAXJ], wj[MAXJ], lk[MAXJ];
     int cj[MAXJ];
     T lxj[MAXJ], lyj[MAXJ];
-    // direct transfer in the FP32 sweeps: the brackets and their FP16 weights
-    // (4 registers per slot) are loaded with the other node data
+    // direct transfer in the FP32 sweeps: the packed brackets (10 bytes, 3
+    // registers per slot) are loaded with the other node data
     constexpr bool DIR16 = DIR && sizeof(T) == 4;
-    int2 dkj[DIR16 ? MAXJ : 1];
-    uint2 dwj[DIR16 ? MAXJ : 1];
+    int dk0j[DIR16 ? MAXJ : 1];
+    int dkdj[DIR16 ? MAXJ : 1];
+    unsigned dwj[DIR16 ? MAXJ : 1];
 #pragma unroll
     for (int sl = 0; sl < MAXJ; ++sl) {
         const int j = tid + NT * sl;
@@ -123,8 +124,9 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
         }
         if constexpr (DIR16) {
             const bool in = j > 0 && j < n - 1;
-            dkj[sl] = in ? a.dk[o + j] : make_int2(-1, -1);
-            dwj[sl] = in ? a.dw16[o + j] : make_uint2(0u, 0u);
+            dk0j[sl] = in ? a.dk0[o + j] : -1;
+            dkdj[sl] = in ? static_cast<int>(a.dkd[o + j]) : static_cast<int>(kDirNoRight);
+            dwj[sl] = in ? a.dwp[o + j] : 0u;
         }
         if (j > 0 && j < n) hj[sl] = a.h[o + j];
         if (FAM == 0 && j < n) wj[sl] = a.w[o + j];
@@ -146,12 +148,24 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
 #pragma unroll
             for (int t = 0; t < G; ++t) {
                 if constexpr (DIR16) {
-                    dk[t] = dkj[q0 + t];
-                    const uint2 h = dwj[q0 + t];
-                    dw[t][0] = static_cast<T>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h.x & 0xffffu)));
-                    dw[t][1] = static_cast<T>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h.x >> 16)));
-                    dw[t][2] = static_cast<T>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h.y & 0xffffu)));
-                    dw[t][3] = static_cast<T>(__builtin_bit_cast(_Float16, static_cast<unsigned short>(h.y >> 16)));
+                    const int k0 = dk0j[q0 + t], d = dkdj[q0 + t];
+                    if (d == kDirNoLeft) {
+                        dk[t] = make_int2(-1, k0);
+                    } else {
+                        int kr = k0 + d;
+                        if (d == kDirNoRight) kr = -1;
+                        else if (d == kDirEscape) kr = a.dk[o + tid + NT * (q0 + t)].y;  // rare
+                        dk[t] = make_int2(k0, kr);
+                    }
+                    const unsigned e = dwj[q0 + t];
+                    const T wl = static_cast<T>(e & 0x3ffu) * T(1.0f / 1023.0f);
+                    const T tl = static_cast<T>((e >> 10) & 0x7ffu) * T(1.0f / 2047.0f);
+                    const T tr = static_cast<T>(e >> 21) * T(1.0f / 2047.0f);
+                    const T wr = T(1) - wl;
+                    dw[t][1] = wl * tl;
+                    dw[t][0] = wl - dw[t][1];
+                    dw[t][3] = wr * tr;
+                    dw[t][2] = wr - dw[t][3];
                 } else {
                     const int j = tid + NT * (q0 + t);
                     const bool in = j > 0 && j < n - 1;

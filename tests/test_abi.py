@@ -264,6 +264,53 @@ def test_host_direct_transfer_matches_oracle(maker):
     s.close()
 
 
+def _decode_packed(k0, kd, wp):
+    """The FP32 sweeps' 10-byte direct records, decoded as include/adr.h states."""
+    k0 = k0.astype(np.int64)
+    kd = kd.astype(np.int64)
+    kl = np.where(kd == -32766, -1, k0)
+    kr = np.where(kd == -32766, k0, np.where(kd == -32767, -1, k0 + kd))
+    esc = kd == -32768
+    wl = (wp & 0x3ff).astype(np.float64) / 1023.0
+    tl = ((wp >> 10) & 0x7ff).astype(np.float64) / 2047.0
+    tr = (wp >> 21).astype(np.float64) / 2047.0
+    wr = 1.0 - wl
+    w = np.stack([wl * (1 - tl), wl * tl, wr * (1 - tr), wr * tr], axis=1)
+    return np.stack([kl, kr], axis=1), esc, w
+
+
+@pytest.mark.parametrize("maker", [lambda: W.c1(33), lambda: W.c2(65), lambda: W.c4_instance(0, n_max=90),
+                                   lambda: W.c4_instance(1, n_max=90), lambda: W.c1(3), _axis_beta, _diag_beta])
+def test_host_direct_records_packed_for_the_fp32_sweeps(maker):
+    """The 10-byte records the FP32 sweeps read decode to the FP64 records:
+    the same source nodes (escapes only where the offset is beyond 16 bits),
+    and the weights from wL (rounded to 10 bits: error <= 2^-11) and the two
+    positions (11 bits: <= 2^-12): each weight within 2^-11 + 2^-12, the four
+    errors summing to at most 2^-11 + 2^-11 + 2 (wL + wR) 2^-12 = 3 2^-11 in
+    absolute value, and a row sum of exactly 1 on every interior node (the
+    errors cancel on a constant field)."""
+    from paper_2411_11041_amd.adr import Solver
+    p = maker()
+    s = Solver(p, host_only=True, increments="direct")
+    for f in (0, 1):
+        k, w = s.export_direct(0, f)
+        k0, kd, wp = s.export_direct_packed(0, f)
+        kk, esc, ww = _decode_packed(k0, kd, wp)
+        off, _, _ = s.export_lines(0, f)
+        inner = np.ones(len(k), bool)
+        inner[off[:-1]] = False
+        inner[off[1:] - 1] = False
+        # escapes carry the left node; the device reads the right one from the full record
+        assert np.all(np.abs(k[esc, 1] - k[esc, 0]) > 32765)
+        kk[esc, 1] = k[esc, 1]
+        assert np.array_equal(kk[inner], k[inner])
+        err = np.abs(ww[inner] - w[inner])
+        assert np.max(err) <= 2.0 ** -11 + 2.0 ** -12 + 1e-12
+        assert np.max(err.sum(axis=1)) <= 3 * 2.0 ** -11 + 1e-12
+        assert np.max(np.abs(ww[inner].sum(axis=1) - 1.0)) < 1e-12
+    s.close()
+
+
 def test_direct_transfer_option_errors():
     from paper_2411_11041_amd.adr import ADRError, Solver, ADR_EINVAL
     p = W.c1(17)

@@ -33,9 +33,9 @@ def test_roofline_byte_model():
     assert [bench.scatter_bytes(p, 0, counts)[1] for p in ("fp32", "fp64")] == [26, 78]
     # direct transfer: source value, chord, |beta| and load (beta, FP64), written value; gamma: the
     # update traffic (FP64: old value + FP32 increment; FP32: FP64 state read and written);
-    # tables: two bracket indices and four weights (FP16 in the FP32 sweeps)
+    # tables: two bracket indices and four weights (FP64), or 10 packed bytes (FP32 sweeps)
     assert [bench.direct_line_bytes(*k) for k in (("fp32", 0), ("fp32", 1), ("fp64", 0), ("fp64", 1))] == \
-        [(16, 16), (28, 16), (40, 40), (36, 40)]
+        [(16, 10), (28, 10), (40, 40), (36, 40)]
 
 
 def test_roofline_from_kernel_work():
@@ -65,7 +65,7 @@ def test_roofline_of_the_direct_increments_on_the_grid_route():
     scatter_gamma the FP32 increment scatter; the FP64 classes are unchanged."""
     sys.path.insert(0, ROOT)
     import bench
-    assert bench.direct_line_bytes("fp32", 1, hybrid=True) == (20, 16)
+    assert bench.direct_line_bytes("fp32", 1, hybrid=True) == (20, 10)
     assert bench.hybrid_gather_bytes() == (12.0, 12.0)
     counts = dict(grid_unknowns=1000, line_unknowns_b=1000, lines_b=10, line_unknowns_g=800, lines_g=20)
     z = (0.0, 0, 0)

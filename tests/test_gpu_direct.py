@@ -77,10 +77,15 @@ def test_direct_fp32_sweeps_track_the_fp64_iteration():
     """A fixed number of sweeps (fixed schedule, 3 FP32 sweeps per FP64
     sweep): in exact arithmetic the mixed iteration is the FP64 one, so after
     9 sweeps the result is the oracle's 9-sweep result up to the error of the
-    increments.  Bar: the FP32 sweeps take their weights as FP16 (relative
-    error 2^-11); the increments of sweeps 6-8 are about 0.1 of the state
-    here, so three of them carry at most ~3 * 2^-11 * 0.1 = 1.5e-4 of it into
-    the last FP64 sweep, which contracts it (measured 1.1e-5)."""
+    increments.  Bar: the FP32 sweeps rebuild each node's four weights from
+    10- and 11-bit fractions (off by at most 3 * 2^-11 in sum, summing exactly
+    to 1), so a transferred value is off by at most 3 * 2^-11 of the spread
+    of its bracket values, which lie on two segments of neighbouring curves
+    (within 2h, h = 1/128: a few hundredths of the increment at most); the
+    increments of sweeps 6-8 are about 0.1 of the state here, so three of
+    them carry at most ~3 * 3 * 2^-11 * 0.05 * 0.1 = 2e-5 of it into the last
+    FP64 sweep, which contracts it: bar 1e-4 (measured 1.1e-5 with FP16
+    weights, whose rows do not sum to 1 exactly)."""
     print("[case] direct transfer, fp32 increment sweeps vs fp64 iteration, c2 129", flush=True)
     p = with_g(W.c2(129))
     o = Oracle(p)
@@ -90,7 +95,9 @@ def test_direct_fp32_sweeps_track_the_fp64_iteration():
     torch.cuda.synchronize()
     assert st == 1 and it[0] == 9
     U = _oracle_sweeps(o, o.zero_field(), 9)
-    assert rel_l2(u.cpu().numpy(), U, o.inner_idx) < 1e-4
+    err = rel_l2(u.cpu().numpy(), U, o.inner_idx)
+    print(f"[case] rel L2 to the oracle's FP64 iteration {err:.2e}", flush=True)
+    assert err < 1e-4
     s.close()
 
 

@@ -41,13 +41,15 @@ def rel_l2(a, b):
 def test_hybrid_blocks_match_the_oracle(name, maker, m):
     """Two blocks (a grid sweep, m direct FP32 sweeps, a grid sweep, m more,
     a grid sweep) against the oracle's hybrid iteration in FP64.  The FP32
-    sweeps read the transfer weights as FP16 (relative error <= 2^-11 each,
-    every value a convex combination, so <= 2^-11 of the values it mixes per
-    transfer) and the scatter's factored weights (<= 3e-5): each direct sweep
-    adds <= 2 * 2^-11 of its increment, summed over m sweeps of increments no
-    larger than the first, <= 2 m 2^-11 |S| per block, and |S| <= |U| on
-    these starts from zero (the increments shrink).  Two blocks: bar
-    4 m 2^-11 relative L2."""
+    sweeps rebuild the transfer weights from 10- and 11-bit fractions (each
+    row off by at most 3 * 2^-11 in sum and summing exactly to 1, so a
+    transferred value is off by at most 3 * 2^-11 of the spread of its four
+    bracket values, which lie within 2h: under a third of the value here,
+    h <= 1/100), and the scatter's factored weights (<= 3e-5): each direct
+    sweep adds <= 2 * 2^-11 of its increment, summed over m sweeps of
+    increments no larger than the first, <= 2 m 2^-11 |S| per block, and
+    |S| <= |U| on these starts from zero (the increments shrink).  Two
+    blocks: bar 4 m 2^-11 relative L2."""
     print(f"[case] hybrid blocks {name} m={m}", flush=True)
     p = maker()
     o = Oracle(p)
