@@ -30,8 +30,11 @@ constexpr int kSlotStep = 0, kSlotLin = 1, kSlotTime = 2, kSlotGuess = 3, kSlotH
 constexpr int kBlock = 256;
 constexpr int kTile = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
-// one line-solve launch per family: all curves of all instances, longest first
-constexpr int kMaxNodes = 3072;  // 12 nodes per thread of a 256-thread workgroup
+// the single line launch deals chunks of this many neighbouring curves to the
+// XCDs in turn (measured on C2 2049^2: 16 and 32 best, 8 and 64 slower)
+constexpr int kXcdChunk = 32;
+// the longest curve: 12 nodes per thread of a 256-thread workgroup
+constexpr int kMaxNodes = 3072;
 
 #define HIPCHK(x)                                                                              \
     do {                                                                                       \
@@ -110,6 +113,11 @@ struct DevFam {
     // compacted list); bnmax: its longest curve
     int bstart[adr::kLineBuckets + 1] = {}, bnmax[adr::kLineBuckets] = {};
     int bshape[adr::kLineBuckets] = {};  // workgroup shape of each bucket's launch (adr_autotune)
+    // the single launch's dispatch (full list): list positions in XCD order
+    // (sidx), each XCD's share (xs, 9 entries, device), the grid (xgrid)
+    const int *sidx = nullptr;
+    const int *xs = nullptr;
+    int xgrid = 0;
     int abstart[adr::kLineBuckets + 1] = {}, abnmax[adr::kLineBuckets] = {};
     std::vector<std::array<int, adr::kLineBuckets>> inst_bl, inst_bnmax;  // per instance and bucket
 };
@@ -262,6 +270,12 @@ struct adr_ctx {
         a.lbase = 0;
         if (!opt.split_lines) {
             const int nl = F.act >= 0 ? F.act : F.n_lines, nm = F.act >= 0 ? F.act_nmax : F.nmax;
+            if (F.act < 0 && F.xs) {
+                // the full list: chunks of neighbouring curves dealt to the XCDs
+                a.lidx = F.sidx;
+                a.xs = F.xs;
+                return adr::launch_line<T>(f, -1, 0, a, F.xgrid, fin, vout, par, dn, nm, st);
+            }
             return adr::launch_line<T>(f, -1, 0, a, nl, fin, vout, par, dn, nm, st);
         }
         const int *bs = F.act >= 0 ? F.abstart : F.bstart;
@@ -950,6 +964,29 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             }
             F.bstart[0] = 0;
             for (int b = 0; b < adr::kLineBuckets; ++b) F.bstart[b + 1] = F.bstart[b] + bcount[b];
+            {
+                // dispatch of the single launch: the curves in their own order
+                // (instance, then seeds along the inflow boundary, so
+                // neighbours), cut into chunks of kXcdChunk, chunk c to XCD c mod 8
+                std::vector<int> nat(lines.size());
+                for (size_t p = 0; p < nat.size(); ++p) nat[p] = static_cast<int>(p);
+                std::sort(nat.begin(), nat.end(), [&](int x, int y) { return lines[x] < lines[y]; });
+                const int nl = static_cast<int>(nat.size());
+                const int nch = (nl + kXcdChunk - 1) / kXcdChunk;
+                std::vector<int> sp, xs(9, 0);
+                sp.reserve(nat.size());
+                for (int x = 0; x < 8; ++x) {
+                    xs[x] = static_cast<int>(sp.size());
+                    for (int c = x; c < nch; c += 8)
+                        for (int q = c * kXcdChunk; q < std::min(nl, (c + 1) * kXcdChunk); ++q) sp.push_back(nat[q]);
+                }
+                xs[8] = static_cast<int>(sp.size());
+                int most = 0;
+                for (int x = 0; x < 8; ++x) most = std::max(most, xs[x + 1] - xs[x]);
+                F.sidx = upload(sp, own, st);
+                F.xs = upload(xs, own, st);
+                F.xgrid = 8 * most;
+            }
             if (F.nmax > kMaxNodes || adr::line_lds_bytes<double>(f, F.nmax) > kLdsLimit)
                 throw Error{ADR_EINVAL, "a curve has " + std::to_string(F.nmax) +
                                             " nodes: longer than the LDS-resident line solver holds"};

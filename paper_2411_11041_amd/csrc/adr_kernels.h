@@ -46,6 +46,14 @@ struct LineArgs {
     float *dout;         // optional with dk: per node, new value - old value in vout (0 at the ends)
     double *vacc;        // optional with dk: per interior node, vacc += new value
     float *vacc32;       // optional with dk: the same into an FP32 sum
+    // optional (k_line, the one launch per family): XCD-dealt dispatch.
+    // Workgroup w runs on XCD w mod 8 as its (w div 8)-th; XCD x takes the list
+    // positions xs[x] .. xs[x+1]-1 (through lidx) in order, and workgroups
+    // beyond them exit at once.  The set-up deals chunks of neighbouring
+    // curves to the XCDs in turn, so that the curves one XCD solves at a time
+    // read neighbouring data through its L2, and every XCD gets a share of
+    // long and short curves
+    const int *xs;
 };
 
 // Codes of LineArgs::dkd: no left bracket on a source segment (the right one
@@ -110,7 +118,8 @@ int line_shapes(int bucket);
 // bucket -1: one launch for curves of any length (a register footprint per
 // workgroup inside the kernel; shape ignored); bucket b: every curve of the
 // launch lies in b and is solved with the given shape.  n_lines workgroups
-// take the list positions a.lbase .. a.lbase + n_lines - 1.
+// take the list positions a.lbase .. a.lbase + n_lines - 1; with a.xs (bucket
+// -1 only) n_lines is the grid, 8 times the longest XCD share.
 template <typename T>
 hipError_t launch_line(int fam, int bucket, int shape, const LineArgs<T> &a, int n_lines, const T *fin, T *vout,
                        const double *par, const int *done, int nmax, hipStream_t st);

@@ -442,15 +442,23 @@ __device__ __forceinline__ void line_body(const LineArgs<T> &a, const T *__restr
     if (bad && a.sing) a.sing[inst] = 1;
 }
 
-// One launch for every curve of a family: curves are ordered longest first and
-// each workgroup picks the register footprint (nodes per thread) of its curve;
-// the kernel's registers are those of the largest footprint.
+// One launch for every curve of a family: each workgroup picks the register
+// footprint (nodes per thread) of its curve; the kernel's registers are those
+// of the largest footprint.  The full list is dealt to the XCDs in chunks of
+// neighbouring curves (a.xs); a list compacted to the unfinished instances
+// runs in its own order (longest first within each instance's bucket).
 template <typename T, int FAM, bool DIR = false>
 __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__restrict__ fin,
                                                    T *__restrict__ vout, const double *__restrict__ par,
                                                    const int *__restrict__ done, int nmax) {
-    // the list order (longest first) is the dispatch order
-    const int pos = static_cast<int>(blockIdx.x);
+    // the list order (longest first) is the dispatch order, or each XCD takes
+    // its share of the list in order
+    int pos = static_cast<int>(blockIdx.x);
+    if (a.xs) {
+        const int p = a.xs[pos & 7] + (pos >> 3);
+        if (p >= a.xs[(pos & 7) + 1]) return;
+        pos = p;
+    }
     const int per = (a.lcnt[a.lidx ? a.lidx[a.lbase + pos] : a.lbase + pos] + kThreads - 1) / kThreads;
     if (per <= 1) line_body<T, FAM, 1, kThreads, DIR>(a, fin, vout, par, done, nmax, pos);
     else if (per <= 2) line_body<T, FAM, 2, kThreads, DIR>(a, fin, vout, par, done, nmax, pos);
@@ -824,6 +832,7 @@ hipError_t launch_line(int fam, int bucket, int shape, const LineArgs<T> &a, int
     if (nmax > 12 * kThreads || bucket > 4) return hipErrorInvalidValue;
     if (bucket >= 0 && line_bucket(nmax) < bucket) return hipErrorInvalidValue;  // curves too long for the bucket
     if (bucket >= 0 && (shape < 0 || shape >= line_shapes(bucket))) return hipErrorInvalidValue;
+    if (bucket >= 0 && a.xs) return hipErrorInvalidValue;  // XCD shares serve the single launch
     const int sh = bucket < 0 ? 0 : shape;
     if (a.dk) {
         if (fam == 0) launch_line_fam<T, 0, true>(bucket, sh, a, n_lines, fin, vout, par, done, nmax, st);
