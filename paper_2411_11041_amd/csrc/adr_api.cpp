@@ -30,9 +30,6 @@ constexpr int kSlotStep = 0, kSlotLin = 1, kSlotTime = 2, kSlotGuess = 3, kSlotH
 constexpr int kBlock = 256;
 constexpr int kTile = 16;
 constexpr size_t kLdsLimit = 160 * 1024;
-// the single line launch deals chunks of this many neighbouring curves to the
-// XCDs in turn (measured on C2 2049^2: 16 and 32 best, 8 and 64 slower)
-constexpr int kXcdChunk = 32;
 // the longest curve: 12 nodes per thread of a 256-thread workgroup
 constexpr int kMaxNodes = 3072;
 
@@ -919,10 +916,11 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                                                 std::to_string(kMaxNodes)};
             }
             // list order: length bucket (longest first), then instance, then curve
-            // length (longest first).  With one instance this is longest first, so
-            // that no long curve is left for the end of a launch; in a batch each
-            // bucket holds the instances one after another, so that the workgroups
-            // of one XCD gather from one instance's grid at a time (see k_line_b)
+            // length (longest first): the order of the bucketed launches and of
+            // lists compacted to the unfinished instances.  In a batch each bucket
+            // holds the instances one after another, so that a chunk of
+            // neighbouring positions (one XCD's, see k_line_b) holds one
+            // instance's curves
             std::stable_sort(lines.begin(), lines.end(), [&](const std::pair<int, int> &x, const std::pair<int, int> &y) {
                 const adr::Family &fx = G[x.first].fam[f], &fy = G[y.first].fam[f];
                 const int nx = static_cast<int>(fx.off[x.second + 1] - fx.off[x.second]);
@@ -967,18 +965,18 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             {
                 // dispatch of the single launch: the curves in their own order
                 // (instance, then seeds along the inflow boundary, so
-                // neighbours), cut into chunks of kXcdChunk, chunk c to XCD c mod 8
+                // neighbours), cut into chunks of adr::kXcdChunk, chunk c to XCD c mod 8
                 std::vector<int> nat(lines.size());
                 for (size_t p = 0; p < nat.size(); ++p) nat[p] = static_cast<int>(p);
                 std::sort(nat.begin(), nat.end(), [&](int x, int y) { return lines[x] < lines[y]; });
                 const int nl = static_cast<int>(nat.size());
-                const int nch = (nl + kXcdChunk - 1) / kXcdChunk;
+                const int nch = (nl + adr::kXcdChunk - 1) / adr::kXcdChunk;
                 std::vector<int> sp, xs(9, 0);
                 sp.reserve(nat.size());
                 for (int x = 0; x < 8; ++x) {
                     xs[x] = static_cast<int>(sp.size());
                     for (int c = x; c < nch; c += 8)
-                        for (int q = c * kXcdChunk; q < std::min(nl, (c + 1) * kXcdChunk); ++q) sp.push_back(nat[q]);
+                        for (int q = c * adr::kXcdChunk; q < std::min(nl, (c + 1) * adr::kXcdChunk); ++q) sp.push_back(nat[q]);
                 }
                 xs[8] = static_cast<int>(sp.size());
                 int most = 0;

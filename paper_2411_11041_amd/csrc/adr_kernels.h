@@ -56,6 +56,11 @@ struct LineArgs {
     const int *xs;
 };
 
+// Line launches deal their list to the 8 XCDs in chunks of this many
+// neighbouring curves, chunk c to XCD c mod 8 (measured on C2 2049^2: 16 and
+// 32 best, 8 and 64 slower)
+constexpr int kXcdChunk = 32;
+
 // Codes of LineArgs::dkd: no left bracket on a source segment (the right one
 // is dk0), no right one, or a right one too far from dk0 (read dk[k].y)
 constexpr short kDirNoLeft = -32766;

@@ -33,14 +33,20 @@ __host__ __device__ inline int line_lds_arrays(int fam) { return fam == 0 ? 3 : 
 __device__ inline double recip(double x) { return 1.0 / x; }
 __device__ inline float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// List position of workgroup w of G when each XCD is to take a contiguous
-// part of the list: workgroups are dispatched to the 8 XCDs in turn (w mod 8),
-// so XCD x receives positions x*floor(G/8) + min(x, G mod 8) onwards, in order
-// (a bijection of 0..G-1).  Neighbouring curves of one instance then share
-// one XCD's L2 for their bilinear gathers.
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup w to XCD w mod 8,
+// as its (w div 8)-th).  The bucketed launches deal the list to them in chunks
+// of kXcdChunk positions: chunk c goes to XCD c mod 8, so the curves one XCD
+// solves at a time are neighbours (their gathers share its L2) and every XCD
+// gets a share of the whole list.  List position of workgroup w, or -1 past
+// the end of a list of G (the grid is line_grid(G), a whole number of rounds).
 __device__ inline int xcd_position(int w, int G) {
-    const int x = w & 7, i = w >> 3, base = G >> 3, rem = G & 7;
-    return x * base + (x < rem ? x : rem) + i;
+    const int x = w & 7, i = w >> 3;
+    const int p = ((i / kXcdChunk) * 8 + x) * kXcdChunk + i % kXcdChunk;
+    return p < G ? p : -1;
+}
+inline int line_grid(int G) {
+    const int chunks = (G + kXcdChunk - 1) / kXcdChunk;
+    return 8 * ((chunks + 7) / 8) * kXcdChunk;
 }
 
 // NT threads per curve (the workgroup); a curve of n nodes needs n <= NT * MAXJ.
@@ -475,11 +481,11 @@ __global__ __launch_bounds__(kThreads) void k_line(LineArgs<T> a, const T *__res
 template <typename T, int FAM, int MAXJ, int NT, bool DIR = false>
 __global__ __launch_bounds__(NT) void k_line_b(LineArgs<T> a, const T *__restrict__ fin,
                                                T *__restrict__ vout, const double *__restrict__ par,
-                                               const int *__restrict__ done, int nmax) {
-    // the curves of one bucket have similar lengths: each XCD takes a contiguous
-    // part of the list (one instance's neighbouring curves)
-    line_body<T, FAM, MAXJ, NT, DIR>(a, fin, vout, par, done, nmax,
-                                     xcd_position(static_cast<int>(blockIdx.x), static_cast<int>(gridDim.x)));
+                                               const int *__restrict__ done, int nmax, int nlist) {
+    // the curves of one bucket, dealt to the XCDs in chunks of neighbours
+    const int p = xcd_position(static_cast<int>(blockIdx.x), nlist);
+    if (p < 0) return;
+    line_body<T, FAM, MAXJ, NT, DIR>(a, fin, vout, par, done, nmax, p);
 }
 
 // Scatter: out = P v on the interior nodes.  MODE 0: write; MODE 1 (FP64 sweep):
@@ -780,8 +786,8 @@ void launch_b(const LineArgs<T> &a, int n_lines, const T *fin, T *vout, const do
               hipStream_t st) {
     const size_t lds = sizeof(T) * static_cast<size_t>(line_lds_arrays(FAM)) * line_lds_stride(nmax, NT);
     set_lds(&k_line_b<T, FAM, MAXJ, NT, DIR>, lds);
-    hipLaunchKernelGGL((k_line_b<T, FAM, MAXJ, NT, DIR>), dim3(n_lines), dim3(NT), lds, st, a, fin, vout, par, done,
-                       nmax);
+    hipLaunchKernelGGL((k_line_b<T, FAM, MAXJ, NT, DIR>), dim3(line_grid(n_lines)), dim3(NT), lds, st, a, fin, vout,
+                       par, done, nmax, n_lines);
 }
 
 // buckets 0..4: curves of at most 3072, 2048, 1024, 512, 256 nodes; each
