@@ -179,7 +179,9 @@ def roofline(times, counts, split_lines=0, march=False, profile=None, direct=Fal
 def measured_traffic(kernel, profile):
     """HBM bytes per launch of `kernel` from the committed counter summary
     (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the
-    summary is missing or was taken on other kernel sources."""
+    summary is missing or was taken on other kernel sources.  A bucketed line
+    class (one dispatch per length bucket and family per sweep) sums the
+    dispatches of its kernels, one per bucket shape."""
     import hashlib
     path = os.path.join(ROOT, "profiles", profile)
     if not os.path.exists(path):
@@ -191,11 +193,21 @@ def measured_traffic(kernel, profile):
     text = open(path).read()
     if f"Kernel source sha256[:16] = {h.hexdigest()[:16]}" not in text:
         return None
+    bucketed = kernel.startswith("k_line_b<")
+    head, tail = (kernel.split(", J, NT, ")[0] + ", ", ", " + kernel.split(", J, NT, ")[1].split(">")[0] + ">") \
+        if bucketed else (None, None)
+    total, found = 0.0, False
     for line in text.splitlines():
         cells = [c.strip() for c in line.strip().strip("|").split("|")]
-        if len(cells) == 4 and cells[0] == "adr::" + kernel:
+        if len(cells) != 4:
+            continue
+        name = cells[0]
+        if not bucketed and name == "adr::" + kernel:
             return float(cells[3])
-    return None
+        if bucketed and name.startswith("adr::" + head) and name.endswith(tail):
+            total += float(cells[3])
+            found = True
+    return total if found else None
 
 
 def parse():
@@ -211,6 +223,8 @@ def parse():
     ap.add_argument("--split-lines", type=int, choices=[0, 1, 2], default=0,
                     help="with --no-autotune (and c3): line-solve launches, 0 one per family, 1 one per "
                          "length bucket, 2 one per length bucket on concurrent streams")
+    ap.add_argument("--line-shapes", type=str, default=None,
+                    help="c4 with --no-autotune: the five bucket shapes, comma-separated (adr_set_line_shapes)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sweeps", type=int, default=3, help="FP64 oracle sweeps per worker process")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle worker processes (0: one per host core, <= 16)")
@@ -470,6 +484,9 @@ def leg_c4(args):
     fp32_sweeps, adaptive, split, shapes, tuned = args.fp32_sweeps, args.adaptive, args.split_lines, [0] * 5, None
     kr = args.krylov
     hybrid = inc == "direct" and args.transfer == "grid"
+    if args.no_autotune and args.line_shapes:
+        shapes = [int(v) for v in args.line_shapes.split(",")]
+        s.set_line_shapes(shapes)
     if not args.no_autotune:
         tuned = s.autotune(u, 3000, args.tol)
         fp32_sweeps, adaptive, split, shapes, kr = tuned[0], tuned[1], tuned[3], tuned[4], tuned[5]

@@ -85,3 +85,34 @@ def test_roofline_of_the_direct_increments_on_the_grid_route():
     assert row[("fp32", "line_gamma")]["alg_bytes_per_unit"] == 20
     assert row[("fp32", "scatter_beta")]["alg_bytes_per_unit"] == 12
     assert rf["kernel"] == "k_line<float, 0, true>"
+
+
+def test_measured_traffic_of_a_bucketed_class(tmp_path, monkeypatch):
+    """A bucketed line class sums its kernels' rows (one dispatch per bucket
+    shape) from a summary taken on the current kernel sources; other sources
+    give None."""
+    import hashlib
+    sys.path.insert(0, ROOT)
+    import bench
+    h = hashlib.sha256()
+    for f in ("adr_kernels.hip", "adr_kernels.h"):
+        with open(os.path.join(ROOT, "paper_2411_11041_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    rows = ["| adr::k_line_b<float, 1, 4, 256, true> | 1 | 2 | 3.0e+06 |",
+            "| adr::k_line_b<float, 1, 8, 64, true> | 1 | 2 | 1.5e+06 |",
+            "| adr::k_line_b<float, 0, 4, 256, true> | 1 | 2 | 9.0e+06 |",
+            "| adr::k_line_b<float, 1, 4, 256, false> | 1 | 2 | 7.0e+06 |",
+            "| adr::k_line<float, 1, true> | 1 | 2 | 2.0e+06 |"]
+    (prof / "x.md").write_text(f"Kernel source sha256[:16] = {h.hexdigest()[:16]}\n" + "\n".join(rows) + "\n")
+    (prof / "old.md").write_text("Kernel source sha256[:16] = 0000000000000000\n" + "\n".join(rows) + "\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    # the kernel sources are read from ROOT too: point them at the real tree
+    real = os.path.join(ROOT, "paper_2411_11041_amd")
+    os.symlink(real, tmp_path / "paper_2411_11041_amd")
+    name = bench.kernel_name("fp32", "line_gamma", 1, direct=True)
+    assert bench.measured_traffic(name, "x.md") == 4.5e6
+    assert bench.measured_traffic("k_line<float, 1, true>", "x.md") == 2.0e6
+    assert bench.measured_traffic(name, "old.md") is None
+    assert bench.measured_traffic(name, "missing.md") is None
