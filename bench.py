@@ -62,9 +62,9 @@ def log(msg):
 # stationary solve reads and writes the FP64 state and writes the FP32
 # increment (8 + 8 + 4); in the time march the gamma scatter writes the state
 # (8).  Tables: the slot's grid index (4), the first record's line node (4),
-# three 16-bit offsets (6) and the weights of 4 records (in the FP32 sweeps
-# their factors: the estimates' weights and the records' positions, 12; 2 x
-# FP64 each, 64, in the FP64 sweeps).
+# three 16-bit offsets (6) and the weights of 4 records as their factors: the
+# estimates' weight code and bracket weights and the records' positions (12 in
+# the FP32 sweeps, quantised; 4 + 6 x 8 = 52 in FP64).
 # --------------------------------------------------------------------------
 def line_bytes(prec, fam):
     w = 4 if prec == "fp32" else 8
@@ -83,7 +83,7 @@ def scatter_bytes(prec, fam, counts, march=False):
         grid = w
     else:
         grid = 8 if march else 8 + 8 + 4
-    meta = 4 + 4 + 6 + (12 if prec == "fp32" else 64)
+    meta = 4 + 4 + 6 + (12 if prec == "fp32" else 52)
     return vals + grid, meta
 
 

@@ -1089,7 +1089,7 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             }
             // scatter records
             std::vector<int> rk(4 * static_cast<size_t>(npad), -1);
-            std::vector<double> ra(4 * static_cast<size_t>(npad), 0.0), rb(4 * static_cast<size_t>(npad), 0.0);
+            std::vector<double> rf(6 * static_cast<size_t>(npad), 0.0);  // FP64 factors
             std::vector<double> gb(any_g ? npad : 0, 0.0);
             // FP32 tables: the stencil's factors, quantised (weights to ~3e-5)
             std::vector<unsigned> sw(npad, 0u), rt(2 * static_cast<size_t>(npad), 0u);
@@ -1104,10 +1104,11 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
                     sw[slot] = wcode | (q15(R.lam[0]) << 2) | (q15(R.lam[1]) << 17);
                     rt[slot] = q16(R.t[0]) | (q16(R.t[1]) << 16);
                     rt[static_cast<size_t>(npad) + slot] = q16(R.t[2]) | (q16(R.t[3]) << 16);
+                    rf[slot] = R.lam[0];
+                    rf[static_cast<size_t>(npad) + slot] = R.lam[1];
                     for (int r = 0; r < 4; ++r) {
                         rk[r * static_cast<size_t>(npad) + slot] = R.k[r] < 0 ? -1 : static_cast<int>(noff[i] + R.k[r]);
-                        ra[r * static_cast<size_t>(npad) + slot] = R.ca[r];
-                        rb[r * static_cast<size_t>(npad) + slot] = R.cb[r];
+                        rf[(2 + r) * static_cast<size_t>(npad) + slot] = R.t[r];
                     }
                 }
             const int *d_rk = upload(rk, own, st);
@@ -1128,11 +1129,12 @@ adr_status adr_setup(const adr_problem *probs, int32_t n_probs, const adr_option
             }
             const int *d_rk0 = upload(rk0, own, st);
             const short *d_rd = upload(rd, own, st);
-            F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, upload(ra, own, st),
-                                             upload(rb, own, st), nullptr, nullptr, npad};
+            const unsigned *d_sw = upload(sw, own, st);
+            F.s64 = adr::ScatterArgs<double>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, d_sw, nullptr,
+                                             upload(rf, own, st), npad};
             F.s64.gb = any_g ? upload(gb, own, st) : nullptr;
-            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, nullptr, nullptr,
-                                            upload(sw, own, st), upload(rt, own, st), npad};
+            F.s32 = adr::ScatterArgs<float>{d_gidx, d_blk_inst, d_rk, d_rk0, d_rd, d_sw, upload(rt, own, st),
+                                            nullptr, npad};
             F.v64 = dalloc<double>(F.n_nodes, own);
             F.v32 = dalloc<float>(F.n_nodes, own);
             if (f == 1 && opt->increments == 1 && opt->transfer == 0) C->hsum = dalloc<float>(F.n_nodes, own);

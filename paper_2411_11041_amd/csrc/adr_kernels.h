@@ -85,11 +85,13 @@ struct ScatterArgs {
     const int *rk;        // [4][npad] first node of the record's segment, -1 unused (escapes only)
     const int *rk0;       // [npad] rk[0]
     const short *rd;      // [3][npad] rk[r] - rk0 for r = 1..3, or kRecMissing / kRecEscape
-    const T *ra, *rb;     // [4][npad] weights of v[k] and v[k+1] (FP64 tables)
-    // FP32 tables, the same weights factored: ca_r = W_r lam_r (1 - t_r), cb_r = W_r lam_r t_r
-    const unsigned *sw;   // [npad] bits 0-1: 2 W_h (W_v = 1 - W_h); 2-16: lam_h; 17-31: lam_v (15-bit
-                          // fractions; records 0, 1 take lam_h, 1 - lam_h, records 2, 3 lam_v, 1 - lam_v)
-    const unsigned *rt;   // [2][npad] t of records 0, 1 (then 2, 3) as 16-bit fractions, low half first
+    // the weights of v[k] and v[k+1] factored: ca_r = W_r lam_r (1 - t_r), cb_r = W_r lam_r t_r
+    // (records 0, 1 take W_h and lam_h, 1 - lam_h; records 2, 3 W_v = 1 - W_h and lam_v, 1 - lam_v)
+    const unsigned *sw;   // [npad] bits 0-1: 2 W_h; FP32 sweeps: bits 2-16 lam_h, 17-31 lam_v (15-bit
+                          // fractions)
+    const unsigned *rt;   // FP32 sweeps: [2][npad] t of records 0, 1 (then 2, 3) as 16-bit fractions,
+                          // low half first
+    const double *rf;     // FP64 sweeps: [6][npad] lam_h, lam_v, t_0 .. t_3
     int npad;
     const int *blist;     // optional: the slot block of each workgroup (active blocks only)
     int nblist;           // workgroups when blist is set

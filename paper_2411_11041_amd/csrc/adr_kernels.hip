@@ -532,10 +532,15 @@ __global__ __launch_bounds__(kThreads) void k_scatter(ScatterArgs<T> s, const T 
             wa[r] = cf[r] - wb[r];
         }
     } else {
+        // state sweeps: the same factors in FP64 (48 bytes and the weight code)
+        const unsigned e = s.sw[slot];
+        const double wh = static_cast<double>(e & 3u) * 0.5, wv = 1.0 - wh;
+        const double lh = s.rf[slot], lv = s.rf[np + slot];
+        const double cf[4] = {wh * lh, wh - wh * lh, wv * lv, wv - wv * lv};
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            wa[r] = s.ra[r * np + slot];
-            wb[r] = s.rb[r * np + slot];
+            wb[r] = cf[r] * s.rf[(2 + r) * np + slot];
+            wa[r] = cf[r] - wb[r];
         }
     }
 #pragma unroll

@@ -30,7 +30,7 @@ def test_roofline_byte_model():
     alg = [bench.scatter_bytes(p, f, counts)[0] for p, f in (("fp32", 0), ("fp32", 1), ("fp64", 0), ("fp64", 1))]
     assert alg == [4 * 1.02 + 4, 4 * 0.84 + 20, 8 * 1.02 + 8, 8 * 0.84 + 20]
     assert bench.scatter_bytes("fp64", 1, counts, march=True)[0] == 8 * 0.84 + 8
-    assert [bench.scatter_bytes(p, 0, counts)[1] for p in ("fp32", "fp64")] == [26, 78]
+    assert [bench.scatter_bytes(p, 0, counts)[1] for p in ("fp32", "fp64")] == [26, 66]
     # direct transfer: source value, chord, |beta| and load (beta, FP64), written value; gamma: the
     # update traffic (FP64: old value + FP32 increment; FP32: FP64 state read and written);
     # tables: two bracket indices and four weights (FP64), or 10 packed bytes (FP32 sweeps)
