@@ -247,8 +247,8 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true",
                     help="c2/c4: keep the given schedule and launches instead of choosing them with adr_autotune")
     ap.add_argument("--increments", choices=["auto", "grid", "direct"], default="auto",
-                    help="c2/c4: the FP32 increment sweeps' transfer on the grid route (auto: the autotuner's "
-                         "choice of the two; grid with --no-autotune)")
+                    help="c2/c4/c5: the FP32 increment sweeps' transfer on the grid route (auto: the "
+                         "autotuner's choice of the two; grid with --no-autotune)")
     ap.add_argument("--transfer", choices=["grid", "direct"], default="grid",
                     help="c4: values handed between the families through the grid or at their intersections")
     ap.add_argument("--single-mode", action="store_true",
@@ -574,7 +574,7 @@ def leg_c5(args):
     # the batch configuration of C4 (short curves: one launch per length bucket,
     # adaptive schedule, eager launches on the compacted lists) for the dataset
     wl = WS.Workload(n=n, batch=128, coarsen=args.coarsen, fp32_sweeps=12, adaptive=True, split_lines=1,
-                     graph=False)
+                     graph=False, increments="direct" if args.increments != "grid" else "grid")
     Hc, Wc = wl.coarse_shape()
     net = Net(Hc, Wc, 128)
     net.set_params(WS.he_init(0))
@@ -593,7 +593,7 @@ def leg_c5(args):
     # the test batch's context, autotuned once (not timed); all three starts use it
     tuned = wl.tune(test, args.tol)
     log(f"c5: autotuned schedule {tuned[0]} adaptive={tuned[1]} lines={tuned[3]} shapes={tuned[4]} "
-        f"krylov={tuned[5]}")
+        f"krylov={tuned[5]} increments={'direct' if tuned[6] == 1 else 'grid'}")
     res = {}
     for name in ("zero", "eq11", "network"):
         for _ in range(args.warmup + 1):
@@ -639,7 +639,8 @@ def leg_c5(args):
                        "network_grid": f"{Hc}x{Wc} (every {args.coarsen}th node)",
                        "solver": {"fp32_sweeps_per_fp64": tuned[0], "adaptive_schedule": bool(tuned[1]),
                                   "line_launches": LINE_LAUNCHES[tuned[3]], "line_shapes": list(tuned[4]),
-                                  "krylov_gmres_m": tuned[5], "autotune_ms": round(tuned[2], 2)},
+                                  "krylov_gmres_m": tuned[5], "autotune_ms": round(tuned[2], 2),
+                                  "increment_sweeps": "direct transfer" if tuned[6] == 1 else "grid transfer"},
                        "train_samples": args.train, "epochs": args.epochs,
                        "final_train_loss": losses[-1], "gen_s": round(gen_s, 1), "train_s": round(train_s, 1),
                        "train_samples_per_s": round(args.train * args.epochs / train_s, 1),

@@ -30,7 +30,7 @@ from .adr import Net, Solver
 
 class Workload:
     def __init__(self, n=257, batch=128, precision="fp32", fp32_sweeps=3, dt=0.05, graph=True, coarsen=1,
-                 adaptive=False, split_lines=0):
+                 adaptive=False, split_lines=0, increments="grid"):
         import torch
         if coarsen < 1 or (n - 1) % coarsen:
             raise ValueError(f"coarsening factor {coarsen} does not divide {n - 1}")
@@ -50,8 +50,10 @@ class Workload:
         mc = np.zeros((self.nc, self.nc), np.uint8)
         mc[1:-1, 1:-1] = 1
         self.mask_c = torch.from_numpy(mc.ravel()).cuda()
+        # increments="direct": the contexts also hold the direct-transfer records, so
+        # that tune() times both kinds of increment sweeps
         self.kw = dict(precision=precision, fp32_sweeps=fp32_sweeps, theta=1.0, dt=dt, graph=graph,
-                       adaptive=adaptive, split_lines=split_lines)
+                       adaptive=adaptive, split_lines=split_lines, increments=increments)
         self.solver = None
 
     def problems(self, seeds):
