@@ -136,9 +136,11 @@ def test_c3_full_parabolic_march():
 
 def test_c4_full_batch_bench_configuration():
     """The 512-instance batch in the benchmark's configuration (launch shape,
-    bucket shapes and sweep schedule chosen by adr_autotune): every instance
-    stops at rel <= 1e-8, and sampled instances (the four smallest grids, discs
-    and L-shapes) match their own oracle fixed points to the FP32-lines bar."""
+    bucket shapes, sweep schedule and kind of increments chosen by
+    adr_autotune on a context holding the direct-transfer records): every
+    instance stops at rel <= 1e-8, and sampled instances (the four smallest
+    grids, discs and L-shapes, where direct increments differ most from the
+    grid's) match their own oracle fixed points to the FP32-lines bar."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     print("[case] c4 512 instances, autotuned, to 1e-8; sampled instances vs oracle", flush=True)
@@ -148,7 +150,7 @@ def test_c4_full_batch_bench_configuration():
     from paper_2411_11041_amd.adr import Solver
     with ThreadPoolExecutor(max_workers=8) as ex:
         probs = list(ex.map(W.c4_instance, range(512)))
-    s = Solver(probs, precision="fp32", fp32_sweeps=3, theta=1.0, dt=0.05)
+    s = Solver(probs, precision="fp32", fp32_sweeps=3, theta=1.0, dt=0.05, increments="direct")
     off = s.layout()
     u = torch.zeros(int(off[-1]), dtype=torch.float64, device="cuda")
     tuned = s.autotune(u, 3000, 1e-8)
@@ -183,7 +185,9 @@ def test_c5_full_size_warm_start():
     print("[case] c5 257^2, network on 33^2: train 512 x 20, judged solve of 16 seeds", flush=True)
     from paper_2411_11041_amd import warmstart as WS
     from paper_2411_11041_amd.adr import Net
-    wl = WS.Workload(n=257, batch=128, coarsen=8)
+    # the benchmark's solver configuration (its autotuner picks direct increments)
+    wl = WS.Workload(n=257, batch=128, coarsen=8, fp32_sweeps=12, adaptive=True, split_lines=1, graph=False,
+                     increments="direct")
     net = Net(*wl.coarse_shape(), 128)
     net.set_params(WS.he_init(0))
     x, t = wl.generate(net, list(range(512)), tol=1e-10)
