@@ -37,7 +37,7 @@ sys.path.insert(0, ROOT)
 METRIC = "line-unknowns/s + time-to-1e-8 residual: plain vs batched/warm-start, 1 GPU"
 HBM_PEAK_GBS = 8000.0
 CLASSES = ("line_beta", "line_gamma", "scatter_beta", "scatter_gamma")
-DTYPE = ("f32 line solves with f16 transfer weights (increment sweeps), "
+DTYPE = ("f32 line solves with quantised transfer weights (increment sweeps), "
          "f64 line solves, state, residual and convergence test (every FP64 sweep)")
 
 

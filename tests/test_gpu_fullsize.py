@@ -78,7 +78,7 @@ def test_c2_full_fp32_lines_bench_configuration(golden, problem, schedule):
 
 def test_c2_full_direct_transfer_bench_configuration(problem):
     """The direct leg's configuration (C2 2049^2, FP32 increment sweeps with
-    FP16 bracket weights, adaptive schedule with at most 12, one line launch
+    packed 10-byte bracket records, adaptive schedule with at most 12, one line launch
     per family) to 1e-8 reaches the direct FP64 iteration's fixed point
     (to 1e-11) within 1e-6 relative L2 (the set-up's brackets are checked
     against the oracle on sampled curves at this size on the CPU), in a sweep
