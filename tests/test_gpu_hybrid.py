@@ -166,3 +166,53 @@ def test_hybrid_autotune_keeps_a_candidate_and_the_fixed_point():
     Uo, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 2000, 1e-12)
     assert rel_l2(u.cpu().numpy(), Uo) < 1e-5
     s.close()
+
+
+def _with_g(p):
+    X, Y = p.coords()
+    p.g = np.sin(3 * X) + Y ** 2 - 0.5
+    return p
+
+
+@pytest.mark.parametrize("case", ["dirichlet", "fitted", "concurrent", "judged", "update"])
+def test_hybrid_with_the_other_options(case):
+    """Direct increments combined with the context's other options, each to
+    the oracle's grid fixed point (FP32-lines bar): Dirichlet data on the
+    boundary (the increments carry none), exponentially fitted beta-lines
+    (the direct line kernels take the same fitting factors), bucketed line
+    launches on concurrent streams, the judged start, and adr_update (new
+    coefficients and source on the same curves, the direct records kept)."""
+    print(f"[case] hybrid with {case}", flush=True)
+    tol = 1e-10
+    kw = dict(precision="fp32", fp32_sweeps=8, adaptive=True, increments="direct")
+    if case == "fitted":
+        p = W.c4_instance(0, n_max=90)
+        o = Oracle(p, stabilize=True)
+        kw["stabilize"] = True
+    elif case == "update":
+        a = W.c5_sample(1, n=97)
+        p = W.c5_sample(2, n=97)
+        p.beta1, p.beta2 = a.beta1, a.beta2
+        o = Oracle(p)
+    else:
+        p = _with_g(W.c2(129)) if case != "concurrent" else W.c4_instance(3, n_max=160)
+        o = Oracle(p)
+    if case == "concurrent":
+        kw["split_lines"] = 2
+    s = solver(a if case == "update" else p, **kw)
+    if case == "update":
+        s.update([p])
+    u = torch.from_numpy(o.zero_field()).cuda()
+    if case == "judged":
+        fb = torch.from_numpy(o.zero_field()).cuda()
+        u = torch.from_numpy(o.with_boundary(0.5 * o.step(o.zero_field(), 1.0, 0.05))).cuda()
+        it, rel, st, used = s.split_iterate_judged(u, fb, 3000, tol)
+    else:
+        it, rel, st = s.split_iterate(u, 3000, tol)
+    torch.cuda.synchronize()
+    assert st == 0 and rel[0] <= tol
+    Uo, _, _, _ = o.iterate(o.zero_field(), 1.0, 0.05, 4000, 1e-12)
+    err = rel_l2(u.cpu().numpy(), Uo)
+    print(f"[case] {int(it[0])} sweeps, rel L2 to the oracle's fixed point {err:.2e}", flush=True)
+    assert err < 1e-5
+    s.close()
